@@ -1,0 +1,225 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+closed forms (BKW, collisionless slab), invariants (mass conservation, symmetry,
+equilibrium), an independent physical-space quadrature, and brute-force limits."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cell, collision as C, maxwellian as MX, physical as PH, sweep as SW
+from oracle.grid import Spec, velocity_nodes
+
+
+# ------------------------------------------------------------------ Maxwellian
+def test_discrete_maxwellian_moments_and_idempotence():
+    sp = Spec(d=3, N=16, L=8.0)
+    f = synth.mixture_batch(1, 16, 8.0, seed=11)[0]
+    M, th = MX.discrete_maxwellian(sp, f, return_theta=True)
+    m_f, m_M = MX.moments(sp, f), MX.moments(sp, M)
+    assert np.max(np.abs(m_f - m_M) / np.abs(m_f).max()) < 1e-13
+    M2 = MX.discrete_maxwellian(sp, M)
+    assert np.max(np.abs(M2 - M)) < 1e-13 * M.max()
+
+
+def test_gaussian_input_returns_its_parameters():
+    sp = Spec(d=3, N=16, L=8.0)
+    th = MX.theta_from_macro(sp, 1.3, np.array([0.3, -0.2, 0.1]), 1.2)
+    th[0] += 0.01  # any Gaussian of this form is its own discrete Maxwellian
+    G = MX.gaussian(sp, th)
+    _, th2 = MX.discrete_maxwellian(sp, G, return_theta=True)
+    assert np.max(np.abs(th2 - th)) < 1e-12
+
+
+def test_resolved_maxwellian_matches_continuous_parameters():
+    # a well-resolved continuous Maxwellian sampled on the grid: the discrete
+    # parameters approach the continuous ones (eq. maxwellian)
+    sp = Spec(d=3, N=32, L=8.0)
+    rho, U, T = 0.9, np.array([0.2, 0.1, -0.3]), 1.1
+    f = synth.maxwellian_mixture([(rho, U, T)], 32, 8.0)
+    _, th = MX.discrete_maxwellian(sp, f, return_theta=True)
+    assert np.max(np.abs(th - MX.theta_from_macro(sp, rho, U, T))) < 1e-8
+
+
+# ------------------------------------------------------------------ collision
+def _narrow(N, L, seed=3):
+    return synth.mixture_batch(1, N, L, seed=seed, T=(0.15, 0.25), speed=(0.0, 0.3))[0]
+
+
+def test_sigma_exact_sum_conserves_mass():
+    sp = Spec(d=3, N=8, L=4.0)
+    f = _narrow(8, 4.0)
+    D = C.q_direct(sp, f)
+    g, l = C.q_direct(sp, f, parts=True)
+    assert abs(MX.moments(sp, D)[0]) < 1e-13 * sp.w * np.abs(l).sum()
+
+
+def test_fast_form_converges_to_sigma_exact_sum():
+    f = _narrow(8, 4.0)
+    D = C.q_direct(Spec(d=3, N=8, L=4.0), f)
+    errs = []
+    for nt in (4, 8, 16):
+        sp = Spec(d=3, N=8, L=4.0, n_theta=nt, n_phi=2 * nt, n_rho=nt)
+        errs.append(np.abs(C.q_fsm(sp, f) - D).max() / np.abs(D).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-11
+
+
+@pytest.mark.slow
+def test_fast_form_matches_physical_space_quadrature():
+    # independent pin of the whole Fourier derivation: direct quadrature of the
+    # truncated integral for an analytic mixture, at nodes with |v| + R_g <= L
+    N, L = 32, 8.0
+    sp = Spec(d=3, N=N, L=L, n_theta=8, n_phi=16, n_rho=16)
+    rng = np.random.default_rng([5, 0])
+    params = synth.mixture_params(rng, T=(0.8, 1.2), speed=(0.0, 0.5))
+    f = synth.maxwellian_mixture(params, N, L)
+    g, l = C.q_fsm(sp, f, parts=True)
+    v = velocity_nodes(sp)
+    idx = [i for i in range(len(v)) if np.linalg.norm(v[i]) < 1.9][::331][:2]
+    gp, lp = PH.q_physical(params, v[idx], 3, sp.R_g, n_rho=32, n_sph=12)
+    scale = np.abs(l).max()
+    assert np.max(np.abs(g[idx] - gp)) < 1e-7 * scale
+    assert np.max(np.abs(l[idx] - lp)) < 1e-7 * scale
+
+
+def test_bkw_closed_form():
+    # Bobylev-Krook-Wu solution for Maxwell molecules (3D, kernel normalised to
+    # one over the sphere): Q[f] = df/dt; with B = 1 the operator is 4 pi times that.
+    errs = []
+    for N, nt, nr in [(16, 8, 8), (24, 8, 12)]:
+        sp = Spec(d=3, N=N, L=8.0, n_theta=nt, n_phi=2 * nt, n_rho=nr)
+        v = velocity_nodes(sp)
+        v2 = (v * v).sum(1)
+        t = 6.5
+        K = 1 - np.exp(-t / 6)
+        dK = np.exp(-t / 6) / 6
+
+        def fb(K):
+            return np.exp(-v2 / (2 * K)) / (2 * (2 * np.pi * K) ** 1.5) * ((5 * K - 3) / K + (1 - K) / K ** 2 * v2)
+
+        dfb = (np.exp(-v2 / (2 * K)) / (2 * (2 * np.pi * K) ** 1.5)
+               * (v2 / (2 * K * K) * ((5 * K - 3) / K + (1 - K) / K ** 2 * v2)
+                  - 1.5 / K * ((5 * K - 3) / K + (1 - K) / K ** 2 * v2)
+                  + 3 / K ** 2 + (K - 2) / K ** 3 * v2)) * dK
+        Q = C.q_fsm(sp, fb(K))
+        errs.append(np.abs(Q - 4 * np.pi * dfb).max() / np.abs(4 * np.pi * dfb).max())
+    assert errs[1] < 0.2 * errs[0]
+    assert errs[1] < 1e-2
+
+
+def test_maxwellian_is_near_equilibrium_and_corrected_form_exact():
+    sp = Spec(d=3, N=32, L=8.0, n_theta=4, n_phi=8, n_rho=8)
+    f = synth.mixture_batch(1, 32, 8.0, seed=2, T=(0.8, 1.2), speed=(0.0, 0.3))[0]
+    M = MX.discrete_maxwellian(sp, f)
+    g, l = C.q_fsm(sp, M, parts=True)
+    assert np.abs(g - l).max() < 1e-6 * np.abs(l).max()  # spectral accuracy
+    assert np.abs(C.q_corrected(sp, M, M)).max() == 0.0  # eq. discrete_Q
+
+
+def test_symmetries_reflection_swap_translation():
+    sp = Spec(d=3, N=8, L=4.0, n_theta=4, n_phi=8, n_rho=4)
+    f = _narrow(8, 4.0, seed=7).reshape(8, 8, 8)
+    Q = C.q_fsm(sp, f.reshape(-1)).reshape(8, 8, 8)
+    # swapping the two azimuthal axes maps the sigma rule onto itself (n_phi % 4 == 0)
+    Qs = C.q_fsm(sp, f.transpose(0, 2, 1).reshape(-1)).reshape(8, 8, 8)
+    assert np.abs(Qs - Q.transpose(0, 2, 1)).max() < 1e-13 * np.abs(Q).max()
+    # reflection v -> -v on the periodic grid: index j -> N-2-j (mod N), on the polar axis
+    ref = (8 - 2 - np.arange(8)) % 8
+    Qr = C.q_fsm(sp, f[ref].reshape(-1)).reshape(8, 8, 8)
+    assert np.abs(Qr - Q[ref]).max() < 1e-13 * np.abs(Q).max()
+    # translation by one node along axis 2 (the operator is translation invariant)
+    Qt = C.q_fsm(sp, np.roll(f, 1, axis=2).reshape(-1)).reshape(8, 8, 8)
+    assert np.abs(Qt - np.roll(Q, 1, axis=2)).max() < 1e-13 * np.abs(Q).max()
+
+
+# ------------------------------------------------------------------ cell solve
+def _cell_case(i=0, N=8, L=6.0, dx=1 / 32):
+    sp = Spec(d=3, N=N, L=L, n_theta=2, n_phi=4, n_rho=4)
+    fo, fl, fr, _ = synth.cell_inflow_batch(i + 1, N, L, dx)
+    v1 = velocity_nodes(sp)[:, 0]
+    r = (-np.maximum(v1, 0) * fl[i] + np.minimum(v1, 0) * fr[i]) / dx
+    return sp, r, C.nu_of(sp, fo[i]), fo[i], dx
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.01])
+def test_fp_and_pfp_reach_the_theta_newton_fixed_point(eps):
+    sp, r, nu, g0, dx = _cell_case()
+    gs, _ = cell.theta_solve(sp, r, nu, eps, dx)
+    scale = np.abs(gs).max()
+    assert cell.inner_residual(sp, gs, r, nu, eps, dx) < 1e-10 * (nu / eps) * scale
+    g1, s1 = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", tol=1e-11)
+    g2, s2 = cell.solve(sp, r, nu, eps, dx, g0, mode="fp", tol=1e-11, max_iter=5000)
+    assert not s1.fallback
+    assert np.abs(g1 - gs).max() < 1e-8 * scale
+    assert np.abs(g2 - gs).max() < 1e-5 * scale  # FP converges slowly at small eps
+    # eq. macro holds at the fixed point (conservation of the discrete Maxwellian)
+    c = cell.transport_coef(sp, dx)
+    macro = MX.moments(sp, c * gs + r)
+    assert np.max(np.abs(macro)) < 1e-9 * np.max(np.abs(MX.moments(sp, np.abs(c * gs) + np.abs(r))))
+    # the preconditioned iteration does not slow down as eps -> 0 (Section 3.2)
+    assert s1.iterations < s2.iterations
+
+
+def test_pfp_falls_back_when_existence_fails():
+    sp, r, nu, g0, dx = _cell_case()
+    # shift r by a constant so that s_0 = sum w (c (M[g0] - g0) - r) < 0: eq. existence fails
+    c = cell.transport_coef(sp, dx)
+    s0 = sp.w * np.sum(c * (MX.discrete_maxwellian(sp, g0) - g0) - r)
+    r_bad = r + (s0 + 1e-3 * abs(s0)) / (sp.w * sp.K)
+    _, st = cell.solve(sp, r_bad, nu, 0.01, dx, g0, mode="pfp", fixed_iters=2)
+    assert st.fallback
+    _, st = cell.solve(sp, r, nu, 0.01, dx, g0, mode="pfp", fixed_iters=2)
+    assert not st.fallback
+
+
+def test_large_eps_limit():
+    # eps -> infinity: (|v_1|/dx) g = -r wherever v_1 != 0
+    sp, r, nu, g0, dx = _cell_case()
+    gs, _ = cell.theta_solve(sp, r, nu, 1e12, dx)
+    c = cell.transport_coef(sp, dx)
+    m = c > 0
+    assert np.abs(gs[m] + r[m] / c[m]).max() < 1e-8 * np.abs(r[m] / c[m]).max()
+
+
+# ------------------------------------------------------------------ sweep
+def test_collisionless_slab_closed_form():
+    # eps huge, BGK (P == 0): right-movers carry the left wall Maxwellian, left-movers
+    # the right one; the discrete zero-flux condition fixes rho_L/rho_R, the mass C the scale
+    sp = Spec(d=3, N=8, L=6.0)
+    prob = SW.Slab(spec=sp, nx=6, eps=1e12, collision="bgk", T_L=1.0, T_R=2.0, mass=1.3)
+    f, hist = SW.solve_sgs(prob, SW.initial_state(prob), tol=1e-12, max_iter=20)
+    v1 = velocity_nodes(sp)[:, 0]
+    ML, MR = SW.wall_maxwellian(sp, 1.0, (0, 0, 0)), SW.wall_maxwellian(sp, 2.0, (0, 0, 0))
+    a = np.sum(np.where(v1 > 0, v1, 0) * ML)
+    b = np.sum(np.where(v1 < 0, -v1, 0) * MR)
+    # rho_L a = rho_R b (no net flux), and mass: dx w sum_j (rho_L sum_{v1>0} ML + rho_R sum_{v1<0} MR) = C
+    rho_L = b / a  # with rho_R = 1
+    unit = np.where(v1 > 0, rho_L * ML, 0.0) + np.where(v1 < 0, MR, 0.0)
+    # nodes with v_1 = 0 are not transported (g = M[g] there), so the total mass fixes
+    # only a common scale: f / unit must be one constant over every cell and node
+    m = (v1 != 0) & (unit > 1e-6 * unit.max())
+    ratio = f[:, m] / unit[None, m]
+    assert hist[-1] < 1e-10
+    assert np.ptp(ratio) < 1e-10 * ratio.mean()
+
+
+def test_sgs_fp_and_pfp_reach_the_same_state():
+    sp = Spec(d=3, N=8, L=6.0)
+    out = []
+    for inner in ("pfp", "fp"):
+        prob = SW.Slab(spec=sp, nx=4, eps=0.1, collision="bgk", inner=inner, tol_inner=1e-11, max_inner=5000)
+        f, hist = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-9, max_iter=200)
+        out.append(f)
+    assert np.abs(out[0] - out[1]).max() < 1e-8 * out[0].max()
+
+
+def test_multigrid_reaches_the_sgs_state():
+    sp = Spec(d=3, N=8, L=6.0)
+    prob = SW.Slab(spec=sp, nx=8, eps=0.1, collision="bgk")
+    f_sgs, _ = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-9, max_iter=300)
+    prob2 = SW.Slab(spec=sp, nx=8, eps=0.1, collision="bgk")
+    f_mg, hist = SW.solve_mg(prob2, SW.initial_state(prob2, T=1.5), coarsest=2, tol=1e-9)
+    assert hist[-1] < 1e-9
+    assert np.abs(f_mg - f_sgs).max() < 1e-7 * f_sgs.max()
+    # a converged state is a fixed point of the V-cycle
+    f_again = SW.vcycle(prob2, f_mg, None, 2, 1, 1, 0.0)
+    assert np.abs(f_again - f_mg).max() < 1e-7 * f_mg.max()
