@@ -1,0 +1,234 @@
+/*
+ * bz.h - C ABI of the MI355X (gfx950) steady-state Boltzmann hot path.
+ *
+ * Method: Cai, Dong, Hu, "Symmetric Gauss-Seidel Method with a Preconditioned
+ * Fixed-Point Iteration for the Steady-State Boltzmann Equation".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Velocity grid (Section 2.2): d = 3, N points per axis, nodes k*dv with
+ *    k = -N/2+1 .. N/2 and dv = 2L/N, periodic box [-L, L)^3, equal weights
+ *    w = dv^3.  A distribution of one cell is K = N^3 doubles in C order
+ *    [i1][i2][i3]; velocity axis i1 is v_1, the transport direction.
+ *  - Field buffers are caller-owned DEVICE pointers (hipMalloc / torch), FP64,
+ *    contiguous: a batch of B cells is [B][K].  The library never frees or
+ *    reallocates caller memory.  The context owns its tables and workspace.
+ *  - All work is asynchronous and stream-ordered on `stream` (a hipStream_t,
+ *    NULL = the default stream).  Results are valid once the stream is
+ *    synchronised.  A context is not thread-safe: one context per host thread.
+ *  - Argument and shape errors are detected synchronously and returned as a
+ *    bz_status; nothing is launched then.  No C++ exception crosses the ABI.
+ *    bz_last_error() gives the message of the last failure on a context.
+ *  - Numerical events (existence test failed and the fixed-point fallback was
+ *    taken, Newton not converged, non-finite values) never fail a call; they
+ *    are reported per cell in device-side statistics.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BZ_OK = 0,
+  BZ_EINVAL = 1,       /* bad argument or shape */
+  BZ_ENOMEM = 2,       /* device allocation of workspace failed */
+  BZ_EHIP = 3,         /* a HIP runtime call failed */
+  BZ_EUNSUPPORTED = 4  /* valid request this build does not implement */
+} bz_status;
+
+typedef enum { BZ_FP64 = 0, BZ_FP32 = 1 } bz_precision;
+
+typedef struct bz_ctx bz_ctx;
+
+/* Discretisation of one velocity cell.
+ *   N        points per axis: 8, 16 or 32
+ *   L        half-width of the periodic velocity box (> 0)
+ *   gamma    VHS exponent of B = |v - v_*|^gamma (0: Maxwell molecules, B = 1;
+ *            1: hard spheres), Section 4.2 and eq. collision
+ *   n_theta  Gauss-Legendre nodes in cos(theta) of the sphere rule (even >= 2)
+ *   n_phi    uniform azimuth nodes (even >= 2); M = n_theta * n_phi directions
+ *   n_rho    Gauss-Legendre nodes of the radial rule for |g| in [0, 2R]
+ *   R        support radius; <= 0 selects L = (3 sqrt 2 + 1) R / 2 (Section 4.2)
+ *   precision  arithmetic of the spectral stage (FFTs, shifted products and
+ *            their accumulation).  Moments, Newton solves, the steady-state
+ *            correction, the cell solve and residuals are always FP64.
+ *   device   HIP device ordinal the context works on. */
+typedef struct {
+  int N;
+  double L;
+  double gamma;
+  int n_theta;
+  int n_phi;
+  int n_rho;
+  double R;
+  int precision;
+  int device;
+} bz_params;
+
+/* Create / destroy a context: host-built quadrature, phase and weight tables
+ * are uploaded to the device.  Returns BZ_EINVAL for unsupported N or rule
+ * sizes, BZ_EHIP / BZ_ENOMEM on runtime failures.  *out is NULL on error. */
+bz_status bz_create(const bz_params* p, bz_ctx** out);
+void bz_destroy(bz_ctx* ctx);
+
+const char* bz_status_str(bz_status s);
+/* Copies the last error message of ctx (NUL-terminated, truncated to n). */
+bz_status bz_last_error(bz_ctx* ctx, char* buf, size_t n);
+/* Workspace bytes the context currently holds on the device. */
+size_t bz_workspace_bytes(bz_ctx* ctx);
+
+/* ---------------------------------------------------------------- collision
+ * bz_eval_Q: collision term of `batch` independent cells.
+ *   f  [batch][K] FP64 device, read only;  Q  [batch][K] FP64 device, written.
+ *   flags & BZ_Q_CORRECTED: the steady-state preserving form of eq. discrete_Q,
+ *       Q = Q^FSM[f,f] - Q^FSM[M[f], M[f]], with M[f] the discrete Maxwellian of
+ *       eqs. discrete_conservation / discrete_Gaussian.  It is evaluated as
+ *       the symmetric bilinear form Q_s(f - M, f + M), which is equal up to
+ *       rounding and avoids cancellation.
+ *   otherwise Q = Q^FSM[f,f]: the Fourier spectral operator (Section 2.2,
+ *       eq. collision truncated to |v - v_*| <= 2R on the periodic box) with an
+ *       M-direction sphere rule and an n_rho-node radial rule.
+ *   theta (nullable, BZ_Q_CORRECTED only) receives [batch][5] parameters
+ *       (alpha, beta_1..3, gamma) of M[f] = exp(alpha + beta.v - gamma |v|^2).
+ * Returns BZ_EINVAL for batch < 0 or NULL buffers with batch > 0. */
+#define BZ_Q_CORRECTED 1u
+bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
+                    double* theta, void* stream);
+
+/* bz_maxwellian: discrete Maxwellian of each cell (eqs. discrete_conservation,
+ * discrete_Gaussian; Newton's method, Section 2.2).
+ *   f [batch][K] in;  theta [batch][5] out (alpha, beta, gamma);
+ *   M [batch][K] out, nullable;  newton_iters [batch] int32 out, nullable
+ *   (negative when Newton did not converge). */
+bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* newton_iters,
+                        int64_t batch, void* stream);
+
+/* ---------------------------------------------------------------- cell solve
+ * Inner problem of one cell visit, eq. inner_eqn:
+ *     (|v_1|/dx) g + r = (nu/eps) (M[g] - g).
+ * mode BZ_SOLVE_PFP: preconditioned fixed point, eqs. step1 / step2, with the
+ *     existence test of eq. existence; on failure (or when the step-1 Newton
+ *     does not converge) the visit continues with the plain iteration.
+ * mode BZ_SOLVE_FP: plain fixed point, eq. fix_point.
+ * The residual |(|v_1|/dx) g + r - (nu/eps)(M[g] - g)|_{L2(R^3)} is evaluated
+ * after every update; iteration stops when it is <= tol or after max_iter
+ * updates.  fixed_iters > 0 makes exactly that many updates (for one-to-one
+ * comparisons of iterates). */
+typedef enum { BZ_SOLVE_PFP = 0, BZ_SOLVE_FP = 1 } bz_solve_mode;
+
+typedef struct {
+  int mode;        /* bz_solve_mode */
+  double tol;      /* inner residual tolerance (1e-8 in Section 4) */
+  int max_iter;    /* cap on updates per visit */
+  int fixed_iters; /* > 0: exactly this many updates */
+} bz_solve_opts;
+
+/* Per-cell statistics (device memory, written by the solve). */
+typedef struct {
+  int32_t iterations;  /* updates made */
+  int32_t fallback;    /* 1 if the visit fell back to the plain iteration */
+  int32_t newton_fail; /* Newton failures met during the visit */
+  int32_t status;      /* 0 ok, 1 residual not below tol, 2 non-finite */
+  double residual;     /* last inner residual */
+} bz_cell_stats;
+
+/* bz_cell_solve: `batch` independent inner problems.
+ *   r  [batch][K] right-hand sides;  g0 [batch][K] initial guesses (may equal g);
+ *   nu, eps [batch] per-cell collision frequency and Knudsen number (device);
+ *   dx > 0 cell width;  g [batch][K] out;  stats [batch] device, nullable. */
+bz_status bz_cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx,
+                        const double* g0, double* g, int64_t batch, const bz_solve_opts* opts,
+                        bz_cell_stats* stats, void* stream);
+
+/* bz_cell_fixed_point: the data-parallel cell update of the SGS scan with the
+ * binary collision operator (Section 3.3, eq. SGS): from the previous iterate
+ * f_old of each cell it computes Q[f_old] (BZ_Q_CORRECTED form), nu = 4 pi rho,
+ * the BGK-penalty part P = Q - nu (M[f_old] - f_old) (eq. Pf), the right-hand
+ * side r = inflow_r - P / eps, and solves eq. inner_eqn from g0 = f_old.
+ *   f_old, inflow_r [batch][K];  eps [batch];  g [batch][K] out;
+ *   inflow_r is the transport part of eq. r (neighbour and slope terms). */
+bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* inflow_r, const double* eps,
+                              double dx, double* g, int64_t batch, const bz_solve_opts* opts,
+                              bz_cell_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- 1D slabs
+ * A set of independent 1D slab problems (instances) on x in [xL, xR] with
+ * nx cells each, diffuse walls (eq. boundary) at both ends, Knudsen number
+ * eps, and the total-mass constraint of eq. mass_conserv.  Instances may
+ * have different cell counts; their cells are stored back to back in the
+ * caller's field buffer f [sum_i nx_i][K] (borrowed for the slab lifetime).
+ * collision: BZ_COLL_BINARY (Q of eq. discrete_Q, nu = 4 pi rho) or
+ * BZ_COLL_BGK (P == 0, nu = bgk_nu if > 0 else 4 pi rho). */
+typedef enum { BZ_COLL_BINARY = 0, BZ_COLL_BGK = 1 } bz_collision;
+
+typedef struct {
+  double xL, xR;
+  int nx;
+  double eps;
+  double T_L, T_R;      /* wall temperatures */
+  double U_L[3], U_R[3];/* wall velocities (tangential: U[0] must be 0) */
+  double mass;          /* C in eq. mass_conserv */
+} bz_slab_instance;
+
+typedef struct {
+  int n_instances;
+  const bz_slab_instance* instances; /* host array [n_instances] */
+  int collision;                     /* bz_collision */
+  double bgk_nu;                     /* BGK only; <= 0: 4 pi rho */
+  bz_solve_opts inner;               /* inner solve options */
+  double* f;                         /* device [sum nx][K], borrowed */
+} bz_slab_desc;
+
+typedef struct bz_slab bz_slab;
+
+bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* desc, bz_slab** out);
+void bz_slab_destroy(bz_slab* slab);
+
+/* Statistics of the last sweep / V-cycle call (host memory, filled on return;
+ * these calls synchronise the stream once at the end). */
+typedef struct {
+  int n_iters;           /* SGS iterations (or V-cycles) made */
+  int64_t inner_iters;   /* total inner updates over all visits */
+  int64_t visits;        /* cell visits */
+  int64_t fallbacks;     /* visits that fell back to the plain iteration */
+} bz_sweep_stats;
+
+/* bz_sgs_sweep: n_iters full SGS iterations (forward then backward scan,
+ * eq. SGS; first-order upwind), each followed by the uniform mass rescale of
+ * Section 4.  P and nu of every cell are computed in one batched collision
+ * evaluation before each scan (P is explicit); the cells of a scan are
+ * then visited in order, one visit per instance at a time.
+ * residual_out (host, nullable) [n_instances] receives each instance's outer
+ * residual AFTER the last iteration. */
+bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* slab, int n_iters, double* residual_out, bz_sweep_stats* stats,
+                       void* stream);
+
+/* bz_outer_residual: sqrt(sum_j dx sum_k w (v.grad f - Q/eps)^2) per instance
+ * (Section 4 stopping rule), into residual_out (host) [n_instances]. */
+bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* slab, double* residual_out, void* stream);
+
+/* bz_multigrid_vcycle: n_cycles nonlinear multigrid V-cycles (eq. coarse,
+ * H = 2h) with SGS-PFP smoothing (nu1 pre-, nu2 post-steps, tab. mg), a
+ * coarsest level of `coarsest` cells smoothed until its residual falls 10x or
+ * coarse_iters iterations pass, and a mass rescale after each cycle.  Every
+ * instance's cell count must be coarsest * 2^k.  A cycle stops descending
+ * once a level's residual is below `tol`. */
+typedef struct {
+  int coarsest;
+  int nu1, nu2;
+  int coarse_iters;
+  double tol;
+} bz_mg_opts;
+
+bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int n_cycles,
+                              double* residual_out, bz_sweep_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BZ_H */

@@ -1,0 +1,239 @@
+"""Python binding of libbz, the MI355X (gfx950) steady-state Boltzmann hot path.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are torch CUDA (HIP) tensors on the context's device;
+their raw pointers and the current HIP stream are handed to the C ABI
+declared in ``include/bz.h``.  If ``libbz.so`` is missing, importing the
+collision entry points raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbz.so")
+
+BZ_FP64, BZ_FP32 = 0, 1
+BZ_Q_CORRECTED = 1
+BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
+BZ_COLL_BINARY, BZ_COLL_BGK = 0, 1
+
+# every symbol include/bz.h declares
+EXPORTED = [
+    "bz_create", "bz_destroy", "bz_status_str", "bz_last_error", "bz_workspace_bytes",
+    "bz_eval_Q", "bz_maxwellian", "bz_cell_solve", "bz_cell_fixed_point",
+    "bz_slab_create", "bz_slab_destroy", "bz_sgs_sweep", "bz_outer_residual", "bz_multigrid_vcycle",
+]
+
+
+class bz_params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_rho", ctypes.c_int),
+                ("R", ctypes.c_double), ("precision", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class bz_solve_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("fixed_iters", ctypes.c_int)]
+
+
+class bz_cell_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("fallback", ctypes.c_int32), ("newton_fail", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("residual", ctypes.c_double)]
+
+
+class bz_slab_instance(ctypes.Structure):
+    _fields_ = [("xL", ctypes.c_double), ("xR", ctypes.c_double), ("nx", ctypes.c_int), ("eps", ctypes.c_double),
+                ("T_L", ctypes.c_double), ("T_R", ctypes.c_double), ("U_L", ctypes.c_double * 3),
+                ("U_R", ctypes.c_double * 3), ("mass", ctypes.c_double)]
+
+
+class bz_slab_desc(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int), ("instances", ctypes.POINTER(bz_slab_instance)),
+                ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double), ("inner", bz_solve_opts),
+                ("f", ctypes.c_void_p)]
+
+
+class bz_sweep_stats(ctypes.Structure):
+    _fields_ = [("n_iters", ctypes.c_int), ("inner_iters", ctypes.c_int64), ("visits", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64)]
+
+
+class bz_mg_opts(ctypes.Structure):
+    _fields_ = [("coarsest", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("coarse_iters", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+CELL_STATS_DTYPE_FIELDS = [("iterations", "<i4"), ("fallback", "<i4"), ("newton_fail", "<i4"), ("status", "<i4"),
+                           ("residual", "<f8")]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libbz.so and declare argument types.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libbz.so not built at {path}: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I64, D, U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
+    lib.bz_create.argtypes = [ctypes.POINTER(bz_params), ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_destroy.argtypes = [P]
+    lib.bz_destroy.restype = None
+    lib.bz_status_str.argtypes = [ctypes.c_int]
+    lib.bz_status_str.restype = ctypes.c_char_p
+    lib.bz_last_error.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+    lib.bz_workspace_bytes.argtypes = [P]
+    lib.bz_workspace_bytes.restype = ctypes.c_size_t
+    lib.bz_eval_Q.argtypes = [P, P, P, I64, U32, P, P]
+    lib.bz_maxwellian.argtypes = [P, P, P, P, P, I64, P]
+    lib.bz_cell_solve.argtypes = [P, P, P, P, D, P, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
+    lib.bz_cell_fixed_point.argtypes = [P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
+    lib.bz_slab_create.argtypes = [P, ctypes.POINTER(bz_slab_desc), ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_slab_destroy.argtypes = [P]
+    lib.bz_slab_destroy.restype = None
+    lib.bz_sgs_sweep.argtypes = [P, P, ctypes.c_int, P, ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_outer_residual.argtypes = [P, P, P, P]
+    lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
+                                        ctypes.POINTER(bz_sweep_stats), P]
+    for name in EXPORTED:
+        if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class BZError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Params:
+    N: int = 32
+    L: float = 8.0
+    gamma: float = 0.0
+    n_theta: int = 8
+    n_phi: int = 16
+    n_rho: int = 16
+    R: float = 0.0
+    precision: int = BZ_FP64
+    device: int = 0
+
+
+class Context:
+    """Owns a bz_ctx.  Tensors passed to it must be float64, contiguous, on cuda:device."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        self.lib = load_library()
+        self.params = params or Params(**kw)
+        p = bz_params(self.params.N, self.params.L, self.params.gamma, self.params.n_theta, self.params.n_phi,
+                      self.params.n_rho, self.params.R, self.params.precision, self.params.device)
+        h = ctypes.c_void_p()
+        st = self.lib.bz_create(ctypes.byref(p), ctypes.byref(h))
+        if st != 0:
+            raise BZError(f"bz_create: {self.lib.bz_status_str(st).decode()}")
+        self.h = h
+        self.K = self.params.N ** 3
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bz_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            buf = ctypes.create_string_buffer(512)
+            self.lib.bz_last_error(self.h, buf, 512)
+            raise BZError(f"{what}: {self.lib.bz_status_str(st).decode()}: {buf.value.decode()}")
+
+    def _field(self, t, name):
+        import torch
+
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise BZError(f"{name} must be a contiguous float64 device tensor")
+        if t.numel() % self.K:
+            raise BZError(f"{name}: size not a multiple of K = {self.K}")
+        return t.numel() // self.K
+
+    def eval_Q(self, f, corrected: bool = True, out=None, theta=None):
+        import torch
+
+        B = self._field(f, "f")
+        Q = torch.empty_like(f) if out is None else out
+        st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, BZ_Q_CORRECTED if corrected else 0, _ptr(theta),
+                                _stream())
+        self._check(st, "bz_eval_Q")
+        return Q
+
+    def maxwellian(self, f, want_M: bool = True):
+        import torch
+
+        B = self._field(f, "f")
+        theta = torch.empty((B, 5), dtype=torch.float64, device=f.device)
+        M = torch.empty_like(f) if want_M else None
+        it = torch.empty(B, dtype=torch.int32, device=f.device)
+        st = self.lib.bz_maxwellian(self.h, _ptr(f), _ptr(theta), _ptr(M), _ptr(it), B, _stream())
+        self._check(st, "bz_maxwellian")
+        return theta, M, it
+
+    @staticmethod
+    def _opts(mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0):
+        return bz_solve_opts(BZ_SOLVE_PFP if mode == "pfp" else BZ_SOLVE_FP, tol, max_iter, fixed_iters)
+
+    @staticmethod
+    def _stats_tensor(B, device):
+        import torch
+
+        return torch.zeros((B, 3), dtype=torch.float64, device=device)  # 24 bytes per cell
+
+    @staticmethod
+    def decode_stats(t):
+        import numpy as np
+
+        raw = t.detach().cpu().numpy().tobytes()
+        return np.frombuffer(raw, dtype=np.dtype(CELL_STATS_DTYPE_FIELDS))
+
+    def cell_solve(self, r, nu, eps, dx, g0, mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, out=None):
+        import torch
+
+        B = self._field(r, "r")
+        g = torch.empty_like(r) if out is None else out
+        stats = self._stats_tensor(B, r.device)
+        o = self._opts(mode, tol, max_iter, fixed_iters)
+        st = self.lib.bz_cell_solve(self.h, _ptr(r), _ptr(nu), _ptr(eps), float(dx), _ptr(g0), _ptr(g), B,
+                                    ctypes.byref(o), _ptr(stats), _stream())
+        self._check(st, "bz_cell_solve")
+        return g, stats
+
+    def cell_fixed_point(self, f_old, inflow_r, eps, dx, mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0,
+                         out=None):
+        import torch
+
+        B = self._field(f_old, "f_old")
+        g = torch.empty_like(f_old) if out is None else out
+        stats = self._stats_tensor(B, f_old.device)
+        o = self._opts(mode, tol, max_iter, fixed_iters)
+        st = self.lib.bz_cell_fixed_point(self.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx), _ptr(g), B,
+                                          ctypes.byref(o), _ptr(stats), _stream())
+        self._check(st, "bz_cell_fixed_point")
+        return g, stats

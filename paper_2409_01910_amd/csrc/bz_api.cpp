@@ -1,0 +1,179 @@
+// C ABI entry points: validation, context lifetime, workspace.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "bz_internal.hpp"
+
+namespace bz {
+
+bz_status set_err(bz_ctx* c, bz_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+bz_status hip_err(bz_ctx* c, hipError_t e, const char* what) {
+  return set_err(c, e == hipErrorOutOfMemory ? BZ_ENOMEM : BZ_EHIP,
+                 std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bz_status ensure_ws(bz_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return BZ_OK;
+  if (ctx->ws) {
+    // the workspace may still be in use by queued work on any stream
+    BZ_HIP(hipDeviceSynchronize());
+    BZ_HIP(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  BZ_HIP(hipMalloc(&ctx->ws, bytes));
+  ctx->ws_bytes = bytes;
+  return BZ_OK;
+}
+
+}  // namespace bz
+
+using bz::set_err;
+
+extern "C" {
+
+const char* bz_status_str(bz_status s) {
+  switch (s) {
+    case BZ_OK: return "ok";
+    case BZ_EINVAL: return "invalid argument";
+    case BZ_ENOMEM: return "out of device memory";
+    case BZ_EHIP: return "HIP runtime error";
+    case BZ_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+bz_status bz_last_error(bz_ctx* ctx, char* buf, size_t n) {
+  if (!ctx || !buf || n == 0) return BZ_EINVAL;
+  std::strncpy(buf, ctx->err.c_str(), n - 1);
+  buf[n - 1] = '\0';
+  return BZ_OK;
+}
+
+size_t bz_workspace_bytes(bz_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+bz_status bz_create(const bz_params* p, bz_ctx** out) {
+  if (!out) return BZ_EINVAL;
+  *out = nullptr;
+  if (!p) return BZ_EINVAL;
+  if (!(p->N == 8 || p->N == 16 || p->N == 32)) return BZ_EINVAL;
+  if (!(p->L > 0) || !std::isfinite(p->L)) return BZ_EINVAL;
+  if (p->n_theta < 2 || p->n_theta % 2 || p->n_theta > 64) return BZ_EINVAL;
+  if (p->n_phi < 2 || p->n_phi % 2 || p->n_phi > 256) return BZ_EINVAL;
+  if (p->n_rho < 1 || p->n_rho > 256) return BZ_EINVAL;
+  if (p->precision != BZ_FP64 && p->precision != BZ_FP32) return BZ_EINVAL;
+  if (!(p->gamma > -3.0) || p->gamma > 2.0) return BZ_EINVAL;
+  bz_ctx* ctx = new bz_ctx();
+  ctx->p = *p;
+  ctx->N = p->N;
+  ctx->K = p->N * p->N * p->N;
+  ctx->n_theta = p->n_theta;
+  ctx->n_phi = p->n_phi;
+  ctx->n_rho = p->n_rho;
+  ctx->dv = 2.0 * p->L / p->N;
+  ctx->w = ctx->dv * ctx->dv * ctx->dv;
+  ctx->R = p->R > 0 ? p->R : 2.0 * p->L / (3.0 * std::sqrt(2.0) + 1.0);
+  ctx->Rg = 2.0 * ctx->R;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return BZ_EHIP;
+  }
+  bz_status s = bz::build_tables(ctx);
+  if (s != BZ_OK) {
+    bz::free_tables(ctx);
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return BZ_OK;
+}
+
+void bz_destroy(bz_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->p.device);
+  (void)hipDeviceSynchronize();
+  bz::free_tables(ctx);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  delete ctx;
+}
+
+bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags, double* theta,
+                    void* stream) {
+  if (!ctx) return BZ_EINVAL;
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  if (batch > 0 && (!f || !Q)) return set_err(ctx, BZ_EINVAL, "NULL field buffer");
+  if (flags & ~BZ_Q_CORRECTED) return set_err(ctx, BZ_EINVAL, "unknown flag");
+  if (theta && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "theta requires BZ_Q_CORRECTED");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, (hipStream_t)stream);
+}
+
+bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* newton_iters, int64_t batch,
+                        void* stream) {
+  if (!ctx) return BZ_EINVAL;
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  if (batch > 0 && (!f || !theta)) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return bz::maxwellian(ctx, f, theta, M, newton_iters, batch, (hipStream_t)stream);
+}
+
+static bz_status check_opts(bz_ctx* ctx, const bz_solve_opts* o) {
+  if (!o) return set_err(ctx, BZ_EINVAL, "NULL solve options");
+  if (o->mode != BZ_SOLVE_PFP && o->mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad solve mode");
+  if (o->fixed_iters < 0 || o->fixed_iters > 100000) return set_err(ctx, BZ_EINVAL, "bad fixed_iters");
+  if (o->fixed_iters == 0 && (o->max_iter < 1 || o->max_iter > 100000))
+    return set_err(ctx, BZ_EINVAL, "max_iter must be in [1, 100000]");
+  if (!(o->tol >= 0) || !std::isfinite(o->tol)) return set_err(ctx, BZ_EINVAL, "bad tol");
+  return BZ_OK;
+}
+
+bz_status bz_cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
+                        double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, void* stream) {
+  if (!ctx) return BZ_EINVAL;
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  bz_status s = check_opts(ctx, opts);
+  if (s != BZ_OK) return s;
+  if (!(dx > 0) || !std::isfinite(dx)) return set_err(ctx, BZ_EINVAL, "dx must be > 0");
+  if (batch > 0 && (!r || !nu || !eps || !g0 || !g)) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return bz::cell_solve(ctx, r, nu, eps, dx, g0, g, batch, opts, stats, (hipStream_t)stream);
+}
+
+bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* inflow_r, const double* eps, double dx,
+                              double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats,
+                              void* stream) {
+  if (!ctx) return BZ_EINVAL;
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  bz_status s = check_opts(ctx, opts);
+  if (s != BZ_OK) return s;
+  if (!(dx > 0) || !std::isfinite(dx)) return set_err(ctx, BZ_EINVAL, "dx must be > 0");
+  if (batch == 0) return BZ_OK;
+  if (!f_old || !inflow_r || !eps || !g) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (g == f_old) return set_err(ctx, BZ_EINVAL, "g must not alias f_old");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  // scratch: Q, r [batch][K], theta [batch][5], nu [batch] (separate from the
+  // collision workspace, which eval_q sizes itself)
+  const size_t K = (size_t)ctx->K;
+  double* buf = nullptr;
+  const size_t bytes = (size_t)batch * (2 * K + 6) * sizeof(double);
+  hipError_t e = hipMallocAsync((void**)&buf, bytes, st);
+  if (e != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
+  double* Q = buf;
+  double* r = Q + batch * K;
+  double* theta = r + batch * K;
+  double* nu = theta + batch * 5;
+  s = bz::eval_q(ctx, f_old, Q, batch, true, theta, st);
+  if (s == BZ_OK) s = bz::penalty_rhs(ctx, f_old, Q, theta, inflow_r, eps, r, nu, batch, st);
+  if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, f_old, g, batch, opts, stats, st);
+  (void)hipFreeAsync(buf, st);
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Shared device helpers of the bz HIP library (gfx950, wave64).
+//
+// * compile-time twiddle tables (cos/sin of 2 pi j / n evaluated by constexpr
+//   Taylor series after exact octant reduction),
+// * an in-register radix-2 FFT of N points per lane (N = 8, 16, 32),
+// * wave and block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bz {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    s += t;
+  }
+  return s;
+}
+constexpr double sin_turn(double x);
+// cos(2 pi x) for x in [0, 1), reduced exactly to |2 pi x| <= pi/4
+constexpr double cos_turn(double x) {
+  return x > 0.5 ? cos_turn(1.0 - x)
+         : x > 0.25 ? -cos_turn(0.5 - x)
+         : x > 0.125 ? sin_turn(0.25 - x)
+                     : taylor_cos(2.0 * kPi * x);
+}
+constexpr double sin_turn(double x) {
+  return x > 0.5 ? -sin_turn(1.0 - x)
+         : x > 0.25 ? sin_turn(0.5 - x)
+         : x > 0.125 ? cos_turn(0.25 - x)
+                     : taylor_sin(2.0 * kPi * x);
+}
+
+template <int N>
+struct Twiddle {
+  double c[N];
+  double s[N];
+  constexpr Twiddle() : c(), s() {
+    for (int k = 0; k < N; ++k) {
+      c[k] = cos_turn(double(k) / N);
+      s[k] = sin_turn(double(k) / N);
+    }
+  }
+};
+
+template <int N>
+constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < N; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of N points held by one lane:
+//   X_l = sum_j x_j exp(SIGN * 2 pi i l j / N)   (SIGN = -1 forward, +1 inverse,
+// no normalisation).  Radix-2 decimation in time; all indices are compile-time
+// constants after unrolling, so re[] / im[] stay in VGPRs and twiddles fold
+// into immediates.
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void fft_reg(T* re, T* im) {
+  constexpr Twiddle<N> tw{};
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int j = bitrev<N>(i);
+    if (j > i) {
+      T t = re[i];
+      re[i] = re[j];
+      re[j] = t;
+      t = im[i];
+      im[i] = im[j];
+      im[j] = t;
+    }
+  }
+#pragma unroll
+  for (int half = 1; half < N; half <<= 1) {
+#pragma unroll
+    for (int k = 0; k < half; ++k) {
+      const int idx = k * (N / (2 * half));
+      const T c = T(tw.c[idx]);
+      const T s = T(SIGN * tw.s[idx]);
+#pragma unroll
+      for (int i = k; i < N; i += 2 * half) {
+        const int j = i + half;
+        T xr, xi;
+        if (k == 0) {
+          xr = re[j];
+          xi = im[j];
+        } else if (4 * k == 2 * half) {  // w = SIGN * i
+          xr = -T(SIGN) * im[j];
+          xi = T(SIGN) * re[j];
+        } else {
+          xr = re[j] * c - im[j] * s;
+          xi = re[j] * s + im[j] * c;
+        }
+        re[j] = re[i] - xr;
+        im[j] = im[i] - xi;
+        re[i] += xr;
+        im[i] += xi;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum of NV values per thread; result valid in all threads.
+// scratch must hold NV * (blockDim.x / 64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) scratch[q * nw + wid] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += scratch[q * nw + w];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
+}  // namespace bz

@@ -1,0 +1,75 @@
+// Internal declarations of the bz library: context, tables, workspace and
+// the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bz.h"
+
+struct bz_ctx {
+  bz_params p{};
+  int N = 0, K = 0;
+  int n_theta = 0, n_phi = 0, n_rho = 0, n_pairs = 0;
+  double dv = 0, w = 0, R = 0, Rg = 0;
+  std::string err;
+
+  // host copies of the tables (FP64)
+  std::vector<double> h_nodes;  // [N] axis node coordinates
+  std::vector<double> h_pair_w; // [n_pairs] weight of one direction of each antipodal pair
+
+  // device tables (FP64 masters; FP32 copies where the FP32 path reads them)
+  double* d_nodes = nullptr;   // [N]
+  double* d_ph1 = nullptr;     // [n_rho][n_theta][N] complex: exp(i xi_l rho c_t / 2)
+  double* d_ph23 = nullptr;    // [n_rho][n_pairs][2][N] complex: exp(i xi_l s_2), exp(i xi_l s_3)
+  double* d_pairw = nullptr;   // [n_pairs]
+  double* d_W = nullptr;       // [n_rho][K] gain radial weights / K
+  double* d_Gm = nullptr;      // [K] loss weight
+  float* d_ph1_f = nullptr;
+  float* d_ph23_f = nullptr;
+  float* d_pairw_f = nullptr;
+  float* d_W_f = nullptr;
+  float* d_Gm_f = nullptr;
+
+  // workspace (grown on demand, never shrunk until destroy)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace bz {
+
+bz_status set_err(bz_ctx* c, bz_status s, const std::string& msg);
+bz_status hip_err(bz_ctx* c, hipError_t e, const char* what);
+bz_status ensure_ws(bz_ctx* c, size_t bytes);
+
+#define BZ_HIP(call)                                         \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return bz::hip_err(ctx, e_, #call); \
+  } while (0)
+
+// host tables (bz_tables.cpp)
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+bz_status build_tables(bz_ctx* ctx);
+void free_tables(bz_ctx* ctx);
+
+// collision pipeline (bz_q.hip).  Writes Q (FP64).  When rho_out / theta_out are
+// non-null (corrected mode), the discrete Maxwellian parameters and density of
+// each cell are returned too.
+bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
+                 hipStream_t st);
+size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected);
+
+// cell kernels (bz_cell.hip)
+bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,
+                     hipStream_t st);
+bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
+                     double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st);
+// r = inflow - (Q - nu (M_theta - f)) / eps, nu = 4 pi rho(theta); writes nu
+bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const double* theta, const double* inflow,
+                      const double* eps, double* r, double* nu, int64_t batch, hipStream_t st);
+
+}  // namespace bz

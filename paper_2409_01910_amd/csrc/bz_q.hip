@@ -1,0 +1,527 @@
+// Batched Fourier-spectral collision operator on gfx950.
+//
+// Pipeline for a chunk of cells (T = double or float for the spectral stage):
+//   prep      moments + discrete Maxwellian (FP64 Newton) ; fields g = f - M,
+//             h = f + M (corrected form) or f (plain form)
+//   fft3      forward transform of the fields, 1/K scaling, Nyquist modes zeroed
+//   loss      L[u] = IDFT(Gm * DFT u)                   (loss term of the operator)
+//   per radial node r:
+//     zstage  axis-0 inverse transform with the phase exp(i xi_1 s_1) for every
+//             polar node: shared by all azimuths of that node
+//     pairs   for every antipodal direction pair (sigma, -sigma): axis-1/axis-2
+//             inverse transforms with the remaining phases, giving
+//             c = A(v + s) + i B(v - s) in one complex transform; accumulate
+//             w Re(c) Im(c) in physical space; then 2D forward transform of the
+//             accumulated plane
+//     colw    axis-0 forward transform, multiply by W_r(|xi|), add into Qh+
+//   final     inverse transform of Qh+, Q = Q+ - loss (FP64 combine)
+// The corrected form (eq. discrete_Q) is evaluated as the symmetric bilinear
+// form Q_s(g, h): gain pairs are g(v+s) h(v-s) + g(v-s) h(v+s), loss is
+// (g L[h] + h L[g]) / 2.  This equals Q^FSM[f,f] - Q^FSM[M,M] up to rounding.
+#include "bz_common.hpp"
+#include "bz_internal.hpp"
+#include "bz_newton.hpp"
+
+namespace bz {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+
+constexpr int kPrepThreads = 256;
+
+// ------------------------------------------------------------------ prep
+template <typename T, int N>
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict__ f, double* __restrict__ GH,
+                                                       typename V2<T>::type* __restrict__ Fc,
+                                                       double* __restrict__ theta_out, const double* __restrict__ nodes,
+                                                       double w, int corrected) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N;
+  const int b = blockIdx.x;
+  const double* fb = f + (size_t)b * K;
+  __shared__ double s_red[5 * (kPrepThreads / 64)];
+  __shared__ double s_nodes[N];
+  __shared__ double s_E[3][N];
+  __shared__ double s_th[5];
+  if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
+  __syncthreads();
+  if (!corrected) {
+    C* out = Fc + (size_t)b * K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) out[k] = C{T(fb[k]), T(0)};
+    return;
+  }
+  double m[5] = {0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = s_nodes[k / (N * N)], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
+    const double fk = fb[k];
+    m[0] += fk;
+    m[1] += fk * v0;
+    m[2] += fk * v1;
+    m[3] += fk * v2;
+    m[4] += fk * (v0 * v0 + v1 * v1 + v2 * v2);
+  }
+  block_sum<5>(m, s_red);
+  if (threadIdx.x < 64) {
+    double tgt[5], th[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) tgt[i] = w * m[i];
+    theta_from_moments(tgt, w, th);
+    AxisW aw{W_ONE, 0.0, 0.0};
+    newton_gauss(s_nodes, N, w, tgt, th, aw, 1e-13, 60);
+    if (threadIdx.x < 5) s_th[threadIdx.x] = th[threadIdx.x];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 * N) {
+    const int a = threadIdx.x / N, i = threadIdx.x % N;
+    const double x = s_nodes[i];
+    s_E[a][i] = exp(s_th[1 + a] * x - s_th[4] * x * x);
+  }
+  if (theta_out && threadIdx.x < 5) theta_out[(size_t)b * 5 + threadIdx.x] = s_th[threadIdx.x];
+  __syncthreads();
+  const double ea = exp(s_th[0]);
+  double* g = GH + (size_t)b * 2 * K;
+  double* h = g + K;
+  C* Fg = Fc + (size_t)b * 2 * K;
+  C* Fh = Fg + K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+    const double gk = fb[k] - M, hk = fb[k] + M;
+    g[k] = gk;
+    h[k] = hk;
+    Fg[k] = C{T(gk), T(0)};
+    Fh[k] = C{T(hk), T(0)};
+  }
+}
+
+// ------------------------------------------------------------------ plane FFT (axes 1, 2)
+template <typename T, int N>
+constexpr int plane_ppb() {
+  return (N >= 32) ? (sizeof(T) == 8 ? 4 : 8) : (N == 16 ? 8 : 16);
+}
+
+template <typename T, int N, int SIGN>
+__global__ __launch_bounds__((N * plane_ppb<T, N>())) void k_plane(const typename V2<T>::type* __restrict__ in,
+                                                                typename V2<T>::type* __restrict__ out,
+                                                                int64_t nplanes) {
+  using C = typename V2<T>::type;
+  constexpr int PPB = plane_ppb<T, N>();
+  constexpr int NT = N * PPB;
+  constexpr int LD = N + 1;
+  __shared__ C s[PPB * N * LD];
+  const int64_t p0 = (int64_t)blockIdx.x * PPB;
+  const int np = (int)((nplanes - p0) < PPB ? (nplanes - p0) : PPB);
+  const C* src = in + p0 * N * N;
+  for (int e = threadIdx.x; e < np * N * N; e += NT) {
+    const int p = e / (N * N), rr = (e / N) % N, cc = e % N;
+    s[(p * N + rr) * LD + cc] = src[e];
+  }
+  __syncthreads();
+  const int p = threadIdx.x / N, q = threadIdx.x % N;
+  T re[N], im[N];
+  if (p < np) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C v = s[(p * N + q) * LD + j];
+      re[j] = v.x;
+      im[j] = v.y;
+    }
+    fft_reg<T, N, SIGN>(re, im);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[(p * N + q) * LD + j] = C{re[j], im[j]};
+  }
+  __syncthreads();
+  if (p < np) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C v = s[(p * N + j) * LD + q];
+      re[j] = v.x;
+      im[j] = v.y;
+    }
+    fft_reg<T, N, SIGN>(re, im);
+    C* dst = out + (p0 + p) * N * N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) dst[j * N + q] = C{re[j], im[j]};
+  }
+}
+
+// ------------------------------------------------------------------ column FFT (axis 0)
+enum ColMode { COL_PLAIN = 0, COL_FWD_NYQ = 1, COL_PREMUL = 2 };
+
+template <typename T, int N, int SIGN, int MODE>
+__global__ __launch_bounds__(256) void k_col(const typename V2<T>::type* __restrict__ in,
+                                             typename V2<T>::type* __restrict__ out, int64_t nvol,
+                                             const T* __restrict__ wt) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nvol * NN) return;
+  const int64_t vol = gid / NN;
+  const int c = (int)(gid % NN);
+  const C* src = in + vol * K + c;
+  T re[N], im[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    C v = src[(size_t)l * NN];
+    if (MODE == COL_PREMUL) {
+      const T g = wt[(size_t)l * NN + c];
+      v.x *= g;
+      v.y *= g;
+    }
+    re[l] = v.x;
+    im[l] = v.y;
+  }
+  fft_reg<T, N, SIGN>(re, im);
+  C* dst = out + vol * K + c;
+  if (MODE == COL_FWD_NYQ) {
+    const T sc = T(1.0 / K);
+    const bool zero_all = (c / N == N / 2) || (c % N == N / 2);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const bool z = zero_all || l == N / 2;
+      dst[(size_t)l * NN] = z ? C{T(0), T(0)} : C{re[l] * sc, im[l] * sc};
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < N; ++l) dst[(size_t)l * NN] = C{re[l], im[l]};
+  }
+}
+
+// ------------------------------------------------------------------ z-stage
+// Z[b][fld][t][i1][l2][l3] = sum_l1 F[b][fld][l1][l2][l3] exp(i xi_l1 s1_t) e^{2 pi i l1 i1 / N}
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_zstage(const typename V2<T>::type* __restrict__ F,
+                                                typename V2<T>::type* __restrict__ Z, int64_t nvol, int n_theta,
+                                                const typename V2<T>::type* __restrict__ ph1) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nvol * NN) return;
+  const int64_t vol = gid / NN;  // vol = b * nf + fld
+  const int c = (int)(gid % NN);
+  T xr[N], xi[N];
+  const C* src = F + vol * K + c;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const C v = src[(size_t)l * NN];
+    xr[l] = v.x;
+    xi[l] = v.y;
+  }
+  for (int t = 0; t < n_theta; ++t) {
+    T re[N], im[N];
+    const C* ph = ph1 + (size_t)t * N;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const C p = ph[l];
+      re[l] = xr[l] * p.x - xi[l] * p.y;
+      im[l] = xr[l] * p.y + xi[l] * p.x;
+    }
+    fft_reg<T, N, +1>(re, im);
+    C* dst = Z + (vol * n_theta + t) * K + c;
+#pragma unroll
+    for (int l = 0; l < N; ++l) dst[(size_t)l * NN] = C{re[l], im[l]};
+  }
+}
+
+// ------------------------------------------------------------------ direction pairs (hot loop)
+constexpr int kPairWaves = 4;
+
+template <typename T, int N>
+constexpr size_t pairs_lds_bytes() {
+  return (size_t)kPairWaves * (64 / N) * N * (N + 1) * sizeof(typename V2<T>::type) + (size_t)N * N * sizeof(T);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int N, int NF>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>::type* __restrict__ Z,
+                                                           typename V2<T>::type* __restrict__ Acc, int n_theta,
+                                                           int n_phi, const typename V2<T>::type* __restrict__ ph23,
+                                                           const T* __restrict__ pairw) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N, SPW = 64 / N, LD = N + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* trans = reinterpret_cast<C*>(smem);
+  T* red = reinterpret_cast<T*>(smem + (size_t)kPairWaves * SPW * N * LD * sizeof(C));
+  const int b = blockIdx.x / N, i1 = blockIdx.x % N;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int s = ln / N, q = ln % N;
+  C* tw = trans + (size_t)(wv * SPW + s) * N * LD;
+  T acc[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) acc[j] = T(0);
+  const int half = n_theta / 2;
+  const int J = NF * n_phi;
+  const int rounds = (J + SPW - 1) / SPW;
+  const int v = s % NF;
+  for (int tp = wv; tp < half; tp += kPairWaves) {
+    const int tA = half + tp, tB = half - 1 - tp;
+    // A(v + s) and B(v - s): plain form uses f for both; corrected variant 0 is
+    // g(v + s), h(v - s), variant 1 is g(v - s), h(v + s).
+    const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
+    const int fA = 0, fB = NF - 1;
+    const C* za = Z + (((size_t)b * NF + fA) * n_theta + thA) * K + (size_t)i1 * NN + q;
+    const C* zb = Z + (((size_t)b * NF + fB) * n_theta + thB) * K + (size_t)i1 * NN + q;
+    T ar[N], ai[N], br[N], bi[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const C x = za[(size_t)l * N], y = zb[(size_t)l * N];
+      ar[l] = x.x;
+      ai[l] = x.y;
+      br[l] = y.x;
+      bi[l] = y.y;
+    }
+    const T sA = (v == 0) ? T(1) : T(-1);  // A uses P (v = 0) or conj(P) (v = 1)
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int j = rd * SPW + s;
+      const bool active = j < J;
+      const int pq = tp * n_phi + (active ? j / NF : 0);
+      T re[N], im[N];
+      if (active) {
+        const C* p2 = ph23 + (size_t)pq * 2 * N;
+        const C p3 = p2[N + q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          const C a2 = p2[l];
+          const T Pr = a2.x * p3.x - a2.y * p3.y;
+          const T Pi = sA * (a2.x * p3.y + a2.y * p3.x);
+          // a = A * P_A, bb = B * conj(P_A), C = a + i bb
+          const T a_r = ar[l] * Pr - ai[l] * Pi, a_i = ar[l] * Pi + ai[l] * Pr;
+          const T b_r = br[l] * Pr + bi[l] * Pi, b_i = bi[l] * Pr - br[l] * Pi;
+          re[l] = a_r - b_i;
+          im[l] = a_i + b_r;
+        }
+        fft_reg<T, N, +1>(re, im);  // along axis 1
+#pragma unroll
+        for (int l = 0; l < N; ++l) tw[l * LD + q] = C{re[l], im[l]};
+      }
+      wave_sync();
+      if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          const C x = tw[q * LD + l];
+          re[l] = x.x;
+          im[l] = x.y;
+        }
+        fft_reg<T, N, +1>(re, im);  // along axis 2
+        const T wgt = pairw[pq] * T(NF == 1 ? 2 : 1);
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc[l] += wgt * re[l] * im[l];
+      }
+      wave_sync();
+    }
+  }
+  // sum slots of the wave: lanes q, q + N, ... hold partial rows of row q
+#pragma unroll
+  for (int off = N; off < 64; off <<= 1)
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc[l] += __shfl_xor(acc[l], off, 64);
+  for (int w2 = 0; w2 < kPairWaves; ++w2) {
+    if (wv == w2 && ln < N) {
+#pragma unroll
+      for (int l = 0; l < N; ++l) red[q * N + l] = (w2 == 0 ? T(0) : red[q * N + l]) + acc[l];
+    }
+    __syncthreads();
+  }
+  // forward 2D transform of the accumulated real plane (axes 1 and 2)
+  if (threadIdx.x < N) {
+    const int row = threadIdx.x;
+    T re[N], im[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      re[l] = red[row * N + l];
+      im[l] = T(0);
+    }
+    fft_reg<T, N, -1>(re, im);
+#pragma unroll
+    for (int l = 0; l < N; ++l) trans[row * LD + l] = C{re[l], im[l]};
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int col = threadIdx.x;
+    T re[N], im[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const C x = trans[l * LD + col];
+      re[l] = x.x;
+      im[l] = x.y;
+    }
+    fft_reg<T, N, -1>(re, im);
+    C* dst = Acc + (size_t)b * K + (size_t)i1 * NN + col;
+#pragma unroll
+    for (int l = 0; l < N; ++l) dst[(size_t)l * N] = C{re[l], im[l]};
+  }
+}
+
+// ------------------------------------------------------------------ axis-0 forward + radial weight
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __restrict__ Acc,
+                                              typename V2<T>::type* __restrict__ Qh, int64_t nvol,
+                                              const T* __restrict__ Wr, int first) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nvol * NN) return;
+  const int64_t vol = gid / NN;
+  const int c = (int)(gid % NN);
+  T re[N], im[N];
+  const C* src = Acc + vol * K + c;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const C v = src[(size_t)l * NN];
+    re[l] = v.x;
+    im[l] = v.y;
+  }
+  fft_reg<T, N, -1>(re, im);
+  C* dst = Qh + vol * K + c;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const T g = Wr[(size_t)l * NN + c];
+    C o = first ? C{T(0), T(0)} : dst[(size_t)l * NN];
+    o.x += g * re[l];
+    o.y += g * im[l];
+    dst[(size_t)l * NN] = o;
+  }
+}
+
+// ------------------------------------------------------------------ combine
+template <typename T, int N, int NF>
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, const double* __restrict__ GH,
+                                                 const typename V2<T>::type* __restrict__ Qp,
+                                                 const typename V2<T>::type* __restrict__ Lc, double* __restrict__ Q,
+                                                 int64_t n) {
+  constexpr int K = N * N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n) return;
+  const int64_t b = gid / K;
+  const int k = (int)(gid % K);
+  const double gain = double(Qp[gid].x);
+  double loss;
+  if (NF == 1) {
+    loss = f[gid] * double(Lc[gid].x);
+  } else {
+    const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
+    const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
+    loss = 0.5 * (g * Lh + h * Lg);
+  }
+  Q[gid] = gain - loss;
+}
+
+// ------------------------------------------------------------------ host driver
+template <typename T>
+static size_t ws_per_cell(int N, int n_theta, int nf) {
+  const size_t K = (size_t)N * N * N, cs = 2 * sizeof(T);
+  return K * (nf * cs /*Fc*/ + nf * cs /*Lc*/ + nf * 8 /*GH*/ + (size_t)nf * n_theta * cs /*Z*/ + cs /*Acc*/ +
+              cs /*Qh*/);
+}
+
+template <typename T, int N>
+static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
+                             hipStream_t st) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N;
+  const int nf = corrected ? 2 : 1;
+  const int nt = ctx->n_theta;
+  const size_t per = ws_per_cell<T>(N, nt, nf);
+  const size_t budget = (size_t)2 << 30;
+  int64_t chunk = (int64_t)(budget / per);
+  if (chunk < 1) chunk = 1;
+  if (chunk > batch) chunk = batch;
+  bz_status s = ensure_ws(ctx, per * chunk);
+  if (s != BZ_OK) return s;
+  unsigned char* base = (unsigned char*)ctx->ws;
+  C* Fc = (C*)base;
+  C* Lc = Fc + (size_t)chunk * nf * K;
+  double* GH = (double*)(Lc + (size_t)chunk * nf * K);
+  C* Z = (C*)(GH + (size_t)chunk * nf * K);
+  C* Acc = Z + (size_t)chunk * nf * nt * K;
+  C* Qh = Acc + (size_t)chunk * K;
+  const bool f64 = sizeof(T) == 8;
+  const C* ph1 = (const C*)(f64 ? (const void*)ctx->d_ph1 : (const void*)ctx->d_ph1_f);
+  const C* ph23 = (const C*)(f64 ? (const void*)ctx->d_ph23 : (const void*)ctx->d_ph23_f);
+  const T* pairw = (const T*)(f64 ? (const void*)ctx->d_pairw : (const void*)ctx->d_pairw_f);
+  const T* W = (const T*)(f64 ? (const void*)ctx->d_W : (const void*)ctx->d_W_f);
+  const T* Gm = (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
+  constexpr int PPB = plane_ppb<T, N>();
+  const size_t lds = pairs_lds_bytes<T, N>();
+  if (corrected) {
+    BZ_HIP(hipFuncSetAttribute((const void*)k_pairs<T, N, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  } else {
+    BZ_HIP(hipFuncSetAttribute((const void*)k_pairs<T, N, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
+    const int64_t B = (batch - c0) < chunk ? (batch - c0) : chunk;
+    const double* fb = f + c0 * K;
+    const int64_t nvol = B * nf;
+    hipLaunchKernelGGL((k_prep<T, N>), dim3((unsigned)B), dim3(kPrepThreads), 0, st, fb, GH, Fc,
+                       theta_out ? theta_out + c0 * 5 : nullptr, ctx->d_nodes, ctx->w, corrected ? 1 : 0);
+    const unsigned gcol = (unsigned)((nvol * NN + 255) / 256);
+    const unsigned gpl = (unsigned)((nvol * N + PPB - 1) / PPB);
+    hipLaunchKernelGGL((k_plane<T, N, -1>), dim3(gpl), dim3(N * PPB), 0, st, Fc, Fc, nvol * N);
+    hipLaunchKernelGGL((k_col<T, N, -1, COL_FWD_NYQ>), dim3(gcol), dim3(256), 0, st, Fc, Fc, nvol, (const T*)nullptr);
+    // loss: L[u] = IDFT(Gm * uhat)
+    hipLaunchKernelGGL((k_col<T, N, +1, COL_PREMUL>), dim3(gcol), dim3(256), 0, st, Fc, Lc, nvol, Gm);
+    hipLaunchKernelGGL((k_plane<T, N, +1>), dim3(gpl), dim3(N * PPB), 0, st, Lc, Lc, nvol * N);
+    for (int r = 0; r < ctx->n_rho; ++r) {
+      hipLaunchKernelGGL((k_zstage<T, N>), dim3(gcol), dim3(256), 0, st, Fc, Z, nvol, nt, ph1 + (size_t)r * nt * N);
+      const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
+      if (corrected)
+        hipLaunchKernelGGL((k_pairs<T, N, 2>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
+                           ctx->n_phi, ph23r, pairw);
+      else
+        hipLaunchKernelGGL((k_pairs<T, N, 1>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
+                           ctx->n_phi, ph23r, pairw);
+      const unsigned gq = (unsigned)((B * NN + 255) / 256);
+      hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r * K, r == 0 ? 1 : 0);
+    }
+    const unsigned gq = (unsigned)((B * NN + 255) / 256);
+    hipLaunchKernelGGL((k_col<T, N, +1, COL_PLAIN>), dim3(gq), dim3(256), 0, st, Qh, Qh, B, (const T*)nullptr);
+    hipLaunchKernelGGL((k_plane<T, N, +1>), dim3((unsigned)((B * N + PPB - 1) / PPB)), dim3(N * PPB), 0, st, Qh, Qh,
+                       B * N);
+    const unsigned ge = (unsigned)((B * K + 255) / 256);
+    if (corrected)
+      hipLaunchKernelGGL((k_combine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+    else
+      hipLaunchKernelGGL((k_combine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+    BZ_HIP(hipGetLastError());
+  }
+  return BZ_OK;
+}
+
+size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected) {
+  const int nf = corrected ? 2 : 1;
+  return ctx->p.precision == BZ_FP32 ? ws_per_cell<float>(ctx->N, ctx->n_theta, nf)
+                                     : ws_per_cell<double>(ctx->N, ctx->n_theta, nf);
+}
+
+bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
+                 hipStream_t st) {
+  if (batch == 0) return BZ_OK;
+  const bool fp32 = ctx->p.precision == BZ_FP32;
+  switch (ctx->N) {
+    case 8:
+      return fp32 ? run_chunked<float, 8>(ctx, f, Q, batch, corrected, theta_out, st)
+                  : run_chunked<double, 8>(ctx, f, Q, batch, corrected, theta_out, st);
+    case 16:
+      return fp32 ? run_chunked<float, 16>(ctx, f, Q, batch, corrected, theta_out, st)
+                  : run_chunked<double, 16>(ctx, f, Q, batch, corrected, theta_out, st);
+    case 32:
+      return fp32 ? run_chunked<float, 32>(ctx, f, Q, batch, corrected, theta_out, st)
+                  : run_chunked<double, 32>(ctx, f, Q, batch, corrected, theta_out, st);
+    default:
+      return set_err(ctx, BZ_EUNSUPPORTED, "N must be 8, 16 or 32");
+  }
+}
+
+}  // namespace bz

@@ -1,0 +1,163 @@
+// Host-built quadrature, phase and spectral weight tables (FP64), uploaded
+// once per context.
+//
+// Fourier spectral collision operator (Section 2.2, eq. collision with the
+// relative speed truncated at R_g = 2R, Section 4.2): with f periodic on
+// [-L, L)^3, f(v) = sum_l fh_l exp(i xi_l.v), xi_l = pi l / L, and B = |g|^gamma,
+//   gain  Qh+_k = sum_r W_r(|xi_k|) DFT_k[ sum_sigma w_sigma f(v + s) f(v - s) ],
+//         s = rho_r sigma / 2,  W_r(z) = w_r rho_r^{gamma+2} 4 pi sinc(rho_r z / 2),
+//   loss  Q- = f * IDFT[ Gm(|xi|) fh ],  Gm(z) = 4 pi sum_r w_r rho_r^{gamma+2} 4 pi sinc(rho_r z),
+// with a Gauss-Legendre x uniform-azimuth sphere rule and a Gauss-Legendre
+// radial rule on [0, R_g].  The shift f(v + s) is a phase exp(i xi.s) on fh;
+// it separates over the three axes, which the kernels exploit.
+#include <cmath>
+#include <vector>
+
+#include "bz_internal.hpp"
+
+namespace bz {
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  // Newton's method on P_n from the Tricomi-type initial guess; nodes ascending.
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  // enforce exact antipodal symmetry of the rule
+  for (int i = 0; i < n / 2; ++i) {
+    const double a = 0.5 * (x[n - 1 - i] - x[i]);
+    const double b = 0.5 * (w[n - 1 - i] + w[i]);
+    x[i] = -a;
+    x[n - 1 - i] = a;
+    w[i] = w[n - 1 - i] = b;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+static double sinc(double z) { return z == 0.0 ? 1.0 : std::sin(z) / z; }
+
+template <typename D, typename S>
+static bz_status upload(bz_ctx* ctx, D** dst, const std::vector<S>& src) {
+  std::vector<D> tmp(src.begin(), src.end());
+  BZ_HIP(hipMalloc((void**)dst, tmp.size() * sizeof(D)));
+  BZ_HIP(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(D), hipMemcpyHostToDevice));
+  return BZ_OK;
+}
+
+bz_status build_tables(bz_ctx* ctx) {
+  const int N = ctx->N, K = ctx->K, nt = ctx->n_theta, np = ctx->n_phi, nr = ctx->n_rho;
+  const double L = ctx->p.L, gam = ctx->p.gamma;
+  std::vector<double> ct, wt, rr, wr;
+  gauss_legendre(nt, ct, wt);
+  gauss_legendre(nr, rr, wr);
+  for (int i = 0; i < nr; ++i) {  // map [-1, 1] -> [0, R_g]
+    rr[i] = 0.5 * ctx->Rg * (rr[i] + 1.0);
+    wr[i] = 0.5 * ctx->Rg * wr[i];
+  }
+  std::vector<double> xi(N);
+  for (int l = 0; l < N; ++l) xi[l] = M_PI * (l < N / 2 ? l : l - N) / L;
+  ctx->h_nodes.resize(N);
+  for (int i = 0; i < N; ++i) ctx->h_nodes[i] = (i - N / 2 + 1) * ctx->dv;
+
+  // z-stage phases exp(i xi_l rho_r c_t / 2)
+  std::vector<double> ph1((size_t)nr * nt * N * 2);
+  for (int r = 0; r < nr; ++r)
+    for (int t = 0; t < nt; ++t)
+      for (int l = 0; l < N; ++l) {
+        const double a = xi[l] * rr[r] * ct[t] / 2.0;
+        const size_t o = (((size_t)r * nt + t) * N + l) * 2;
+        ph1[o] = std::cos(a);
+        ph1[o + 1] = std::sin(a);
+      }
+  // pair q = tp * n_phi + j: theta node t = nt/2 + tp (c_t > 0), azimuth 2 pi j / n_phi;
+  // its antipode is (nt - 1 - t, j + n_phi / 2).
+  const int npairs = (nt / 2) * np;
+  ctx->h_pair_w.resize(npairs);
+  std::vector<double> ph23((size_t)nr * npairs * 2 * N * 2);
+  for (int tp = 0; tp < nt / 2; ++tp) {
+    const int t = nt / 2 + tp;
+    const double st = std::sqrt(std::max(0.0, 1.0 - ct[t] * ct[t]));
+    for (int j = 0; j < np; ++j) {
+      const int q = tp * np + j;
+      const double ph = 2.0 * M_PI * j / np;
+      ctx->h_pair_w[q] = wt[t] * 2.0 * M_PI / np;
+      const double s2 = st * std::cos(ph), s3 = st * std::sin(ph);
+      for (int r = 0; r < nr; ++r)
+        for (int l = 0; l < N; ++l) {
+          const double a2 = xi[l] * rr[r] * s2 / 2.0, a3 = xi[l] * rr[r] * s3 / 2.0;
+          const size_t o = ((((size_t)r * npairs + q) * 2 + 0) * N + l) * 2;
+          const size_t o3 = ((((size_t)r * npairs + q) * 2 + 1) * N + l) * 2;
+          ph23[o] = std::cos(a2);
+          ph23[o + 1] = std::sin(a2);
+          ph23[o3] = std::cos(a3);
+          ph23[o3 + 1] = std::sin(a3);
+        }
+    }
+  }
+  // radial gain weights (with the 1/K of the forward transform) and loss weight
+  std::vector<double> W((size_t)nr * K), Gm(K, 0.0);
+  for (int l1 = 0; l1 < N; ++l1)
+    for (int l2 = 0; l2 < N; ++l2)
+      for (int l3 = 0; l3 < N; ++l3) {
+        const size_t k = ((size_t)l1 * N + l2) * N + l3;
+        const double z = std::sqrt(xi[l1] * xi[l1] + xi[l2] * xi[l2] + xi[l3] * xi[l3]);
+        double g = 0.0;
+        for (int r = 0; r < nr; ++r) {
+          const double rad = wr[r] * std::pow(rr[r], gam + 2.0);
+          W[(size_t)r * K + k] = rad * 4.0 * M_PI * sinc(rr[r] * z / 2.0) / K;
+          g += rad * 4.0 * M_PI * sinc(rr[r] * z);
+        }
+        Gm[k] = 4.0 * M_PI * g;
+      }
+  bz_status s;
+  if ((s = upload(ctx, &ctx->d_nodes, ctx->h_nodes)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_ph1, ph1)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_ph23, ph23)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_pairw, ctx->h_pair_w)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_W, W)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_Gm, Gm)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_ph1_f, ph1)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_ph23_f, ph23)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_pairw_f, ctx->h_pair_w)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_W_f, W)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_Gm_f, Gm)) != BZ_OK) return s;
+  ctx->n_pairs = npairs;
+  return BZ_OK;
+}
+
+void free_tables(bz_ctx* ctx) {
+  void* ptrs[] = {ctx->d_nodes, ctx->d_ph1, ctx->d_ph23, ctx->d_pairw, ctx->d_W, ctx->d_Gm,
+                  ctx->d_ph1_f, ctx->d_ph23_f, ctx->d_pairw_f, ctx->d_W_f, ctx->d_Gm_f};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+}  // namespace bz

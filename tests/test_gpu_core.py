@@ -1,0 +1,157 @@
+"""GPU parity of the collision operator, the discrete Maxwellian and the cell
+solve against the FP64 CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cell as OC, collision as OQ, maxwellian as OM
+from oracle.grid import Spec, velocity_nodes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_01910_amd as bz
+
+    bz.load_library()
+    return torch.device("cuda:0")
+
+
+def _ctx(N, L, nt, nph, nr, gamma=0.0, prec=0):
+    import paper_2409_01910_amd as bz
+
+    return bz.Context(N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr, gamma=gamma, precision=prec)
+
+
+def _spec(N, L, nt, nph, nr, gamma=0.0):
+    return Spec(d=3, N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr, gamma=gamma)
+
+
+def _rel(gpu, ref, scale):
+    return float(np.max(np.abs(gpu - ref)) / scale)
+
+
+# (N, L, n_theta, n_phi, n_rho, batch): several tiles, ragged batch counts
+CASES = [(8, 4.0, 2, 4, 3, 3), (8, 6.0, 4, 8, 4, 5), (16, 8.0, 4, 8, 8, 3)]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("corrected", [False, True])
+@pytest.mark.parametrize("gamma", [0.0, 1.0])
+def test_eval_q_fp64_matches_oracle(dev, case, corrected, gamma):
+    N, L, nt, nph, nr, B = case
+    print(f"eval_Q N={N} M={nt}x{nph} n_rho={nr} B={B} corrected={corrected} gamma={gamma}", flush=True)
+    sp = _spec(N, L, nt, nph, nr, gamma)
+    f = synth.mixture_batch(B, N, L, seed=21)
+    ctx = _ctx(N, L, nt, nph, nr, gamma)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=corrected).cpu().numpy()
+    for i in range(B):
+        if corrected:
+            ref = OQ.q_corrected(sp, f[i])
+            _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        else:
+            gain, loss = OQ.q_fsm(sp, f[i], parts=True)
+            ref = gain - loss
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
+
+
+def test_eval_q_fp32_error_bound(dev):
+    N, L, nt, nph, nr, B = 16, 8.0, 4, 8, 8, 3
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=22)
+    ctx = _ctx(N, L, nt, nph, nr, prec=1)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True).cpu().numpy()
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i])
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        err = _rel(Qg[i], ref, scale)
+        print("fp32 rel err", err)
+        assert err < 2e-6
+
+
+def test_eval_q_empty_batch(dev):
+    ctx = _ctx(8, 4.0, 2, 4, 2)
+    f = torch.empty((0, 512), dtype=torch.float64, device=dev)
+    assert ctx.eval_Q(f).numel() == 0
+
+
+def test_maxwellian_matches_oracle(dev):
+    N, L = 16, 8.0
+    sp = _spec(N, L, 2, 4, 2)
+    f = synth.mixture_batch(4, N, L, seed=23)
+    ctx = _ctx(N, L, 2, 4, 2)
+    th, M, it = ctx.maxwellian(torch.from_numpy(f).to(dev))
+    th, M, it = th.cpu().numpy(), M.cpu().numpy(), it.cpu().numpy()
+    for i in range(4):
+        Mo, tho = OM.discrete_maxwellian(sp, f[i], return_theta=True)
+        assert it[i] >= 0
+        assert np.max(np.abs(th[i] - tho)) < 1e-11 * (1 + np.abs(tho).max())
+        assert np.max(np.abs(M[i] - Mo)) < 1e-12 * Mo.max()
+
+
+def _cell_inputs(N, L, dx, B, seed=31):
+    sp = _spec(N, L, 2, 4, 2)
+    fo, fl, fr, eps = synth.cell_inflow_batch(B, N, L, dx, seed=seed)
+    v1 = velocity_nodes(sp)[:, 0]
+    r = (-np.maximum(v1, 0) * fl + np.minimum(v1, 0) * fr) / dx
+    nu = np.array([OQ.nu_of(sp, fo[i]) for i in range(B)])
+    return sp, r, nu, eps, fo, (fl, fr)
+
+
+@pytest.mark.parametrize("mode", ["pfp", "fp"])
+def test_cell_solve_fixed_iterations_match_oracle(dev, mode):
+    N, L, dx, B = 8, 6.0, 1 / 32, 6
+    sp, r, nu, eps, g0, _ = _cell_inputs(N, L, dx, B)
+    ctx = _ctx(N, L, 2, 4, 2)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    for n_it in (1, 3):
+        g, st = ctx.cell_solve(T(r), T(nu), T(eps), dx, T(g0), mode=mode, fixed_iters=n_it)
+        g = g.cpu().numpy()
+        stats = ctx.decode_stats(st)
+        for i in range(B):
+            go, so = OC.solve(sp, r[i], nu[i], eps[i], dx, g0[i], mode=mode, fixed_iters=n_it)
+            scale = np.abs(go).max()
+            assert np.max(np.abs(g[i] - go)) < 1e-11 * scale, (i, n_it)
+            assert stats["iterations"][i] == n_it
+            if mode == "pfp":
+                assert bool(stats["fallback"][i]) == bool(so.fallback)
+            assert abs(stats["residual"][i] - so.residual) <= 1e-9 * max(so.residual, 1e-300) + 1e-12 * (nu[i] / eps[i]) * scale
+
+
+def test_cell_solve_converges_to_theta_fixed_point(dev):
+    N, L, dx, B = 8, 6.0, 1 / 32, 4
+    sp, r, nu, eps, g0, _ = _cell_inputs(N, L, dx, B, seed=32)
+    ctx = _ctx(N, L, 2, 4, 2)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g, st = ctx.cell_solve(T(r), T(nu), T(eps), dx, T(g0), mode="pfp", tol=1e-10, max_iter=200)
+    g = g.cpu().numpy()
+    stats = ctx.decode_stats(st)
+    for i in range(B):
+        gs, _ = OC.theta_solve(sp, r[i], nu[i], eps[i], dx)
+        assert stats["status"][i] == 0
+        assert np.max(np.abs(g[i] - gs)) < 1e-8 * np.abs(gs).max()
+
+
+def test_cell_fixed_point_matches_oracle_composition(dev):
+    # Q, P = Q - nu (M - f), r = inflow - P / eps, then the PFP solve from f_old
+    N, L, nt, nph, nr, dx, B = 8, 6.0, 2, 4, 3, 1 / 16, 3
+    sp = _spec(N, L, nt, nph, nr)
+    fo, fl, fr, eps = synth.cell_inflow_batch(B, N, L, dx, seed=33)
+    v1 = velocity_nodes(sp)[:, 0]
+    inflow = (-np.maximum(v1, 0) * fl + np.minimum(v1, 0) * fr) / dx
+    ctx = _ctx(N, L, nt, nph, nr)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g, st = ctx.cell_fixed_point(T(fo), T(inflow), T(eps), dx, fixed_iters=2)
+    g = g.cpu().numpy()
+    for i in range(B):
+        P = OQ.penalty(sp, fo[i])
+        r = inflow[i] - P / eps[i]
+        go, _ = OC.solve(sp, r, OQ.nu_of(sp, fo[i]), eps[i], dx, fo[i], mode="pfp", fixed_iters=2)
+        assert np.max(np.abs(g[i] - go)) < 1e-10 * np.abs(go).max()
