@@ -1,0 +1,162 @@
+"""Benchmark of the hot path on one MI355X.
+
+Workload (the batched collision evaluation it is quoted on): 4096 independent
+cells, 32^3 velocity grid on [-8, 8]^3, M = 128 directions (8 polar x 16
+azimuth nodes), 16 radial nodes, Maxwell molecules (gamma = 0; --gamma 1 for
+hard spheres); every cell a seeded sum of 2-4 Maxwellians with
+rho ~ U(0.5, 2), |u| ~ U(0, 1.5) in a random direction, T ~ U(0.5, 2).
+
+One step = one pass of the whole hot path over the batch: the steady-state
+corrected collision term Q[f] (moments, discrete Maxwellian, spectral
+operator), the BGK-penalty source P, the right-hand side r of every cell
+(transport inflow from its neighbours in the batch, dx = 40/128) and the
+preconditioned fixed-point cell solve to residual 1e-8 - i.e. one
+bz_cell_fixed_point call on 4096 cells.  value = cells per second = Q evals/s.
+
+Prints one JSON line.  Options: --precision fp64|fp32, --batch, --gamma,
+--no-cpu-baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, L, N_THETA, N_PHI, N_RHO = 32, 8.0, 8, 16, 16
+DX = 40.0 / 128
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector peaks (vendor)
+
+
+def make_inputs(batch, seed=0):
+    import numpy as np
+
+    import synth
+
+    f = synth.mixture_batch(batch, N, L, seed=seed)
+    rng = np.random.default_rng([seed, 10 ** 6])
+    eps = np.exp(rng.uniform(np.log(0.005), np.log(1.0), size=batch))
+    return f, eps
+
+
+def cpu_baseline(f_np, eps_np, n_cells=2):
+    """The oracle, as it stands, on the same step for a bounded sample of cells."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cell as OC, collision as OQ
+    from oracle.grid import Spec, velocity_nodes
+
+    sp = Spec(d=3, N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO)
+    v1 = velocity_nodes(sp)[:, 0]
+    B = f_np.shape[0]
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        for i in range(n_cells):
+            fl, fr = f_np[(i - 1) % B], f_np[(i + 1) % B]
+            inflow = (-np.maximum(v1, 0) * fl + np.minimum(v1, 0) * fr) / DX
+            P = OQ.penalty(sp, f_np[i])
+            r = inflow - P / eps_np[i]
+            OC.solve(sp, r, OQ.nu_of(sp, f_np[i]), eps_np[i], DX, f_np[i], mode="pfp", tol=1e-8, max_iter=100)
+    dt = time.perf_counter() - t0
+    return {"value": n_cells / dt, "unit": "Q evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cells} cells of the same workload (corrected Q + penalty + PFP solve), "
+                      f"numpy FP64, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--gamma", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+
+    dev = torch.device("cuda:0")
+    prec = bz.BZ_FP64 if args.precision == "fp64" else bz.BZ_FP32
+    ctx = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=args.gamma, precision=prec)
+    print(f"# generating {args.batch} cells", file=sys.stderr, flush=True)
+    f_np, eps_np = make_inputs(args.batch)
+    f = torch.from_numpy(f_np).to(dev)
+    eps = torch.from_numpy(eps_np).to(dev)
+    # transport inflow from the neighbouring cells of the batch (input preparation)
+    v1 = torch.tensor(((np.arange(N) - N // 2 + 1) * (2 * L / N)), dtype=torch.float64, device=dev)
+    v1 = v1.view(N, 1, 1).expand(N, N, N).reshape(-1)
+    fl, fr = torch.roll(f, 1, 0), torch.roll(f, -1, 0)
+    inflow = ((-torch.clamp(v1, min=0) * fl + torch.clamp(v1, max=0) * fr) / DX).contiguous()
+    del fl, fr
+    g = torch.empty_like(f)
+    torch.cuda.synchronize()
+
+    def step():
+        return ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for i in range(args.steps):
+        _, stats = step()
+        torch.cuda.synchronize()
+        print(f"# step {i} done {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_get()
+    ctx.profile_enable(False)
+    st = ctx.decode_stats(stats)
+    value = args.steps * args.batch / elapsed
+    dt = "f64" if prec == bz.BZ_FP64 else "f32"
+    achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
+    line = {
+        "metric": "Q evals/s at 32^3 velocity grid; time-to-residual 1e-8, learned+FP32 vs plain",
+        "value": value,
+        "unit": "Q evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic",
+        "config": {"workload": f"batched corrected collision term + PFP cell update, {args.batch} cells, "
+                               f"32^3 velocities on [-8,8]^3, M=128 (8x16), 16 radial nodes, gamma={args.gamma}",
+                   "cells": args.batch, "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "gamma": args.gamma,
+                   "spectral_precision": args.precision},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                     "frac": achieved / VALU_PEAK_TFLOPS[dt], "traffic": None,
+                     "kernel": "k_pairs (direction-pair transforms)", "launches": prof["launches"],
+                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
+                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed},
+        "inner": {"mean_iterations": float(st["iterations"].mean()), "max_iterations": int(st["iterations"].max()),
+                  "fallbacks": int(st["fallback"].sum()), "unconverged": int((st["status"] != 0).sum())},
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(f_np, eps_np)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

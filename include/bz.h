@@ -228,6 +228,25 @@ typedef struct {
 bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int n_cycles,
                               double* residual_out, bz_sweep_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------- profiling
+ * bz_profile_enable(ctx, 1) makes the library record a pair of HIP events
+ * around every launch of the direction-pair kernel (the dominant kernel of
+ * bz_eval_Q), on the stream it is launched on; 0 disables and clears.
+ * bz_profile_get synchronises the device and returns, since enabling, the
+ * number of launches, their summed duration (ms) and the algorithmic FLOPs
+ * they performed: per launch, cells * N * pairs * fields *
+ * (10 N^2 log2 N + 17 N^2) - one N x N complex inverse transform per
+ * (plane, pair, field combination), the two phase products, the combination
+ * into one complex field and the weighted product accumulation. */
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double flops;
+} bz_profile_info;
+
+bz_status bz_profile_enable(bz_ctx* ctx, int enable);
+bz_status bz_profile_get(bz_ctx* ctx, bz_profile_info* out);
+
 #ifdef __cplusplus
 }
 #endif

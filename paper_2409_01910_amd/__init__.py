@@ -25,6 +25,7 @@ EXPORTED = [
     "bz_create", "bz_destroy", "bz_status_str", "bz_last_error", "bz_workspace_bytes",
     "bz_eval_Q", "bz_maxwellian", "bz_cell_solve", "bz_cell_fixed_point",
     "bz_slab_create", "bz_slab_destroy", "bz_sgs_sweep", "bz_outer_residual", "bz_multigrid_vcycle",
+    "bz_profile_enable", "bz_profile_get",
 ]
 
 
@@ -66,6 +67,10 @@ class bz_mg_opts(ctypes.Structure):
                 ("coarse_iters", ctypes.c_int), ("tol", ctypes.c_double)]
 
 
+class bz_profile_info(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
 CELL_STATS_DTYPE_FIELDS = [("iterations", "<i4"), ("fallback", "<i4"), ("newton_fail", "<i4"), ("status", "<i4"),
                            ("residual", "<f8")]
 
@@ -100,6 +105,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_outer_residual.argtypes = [P, P, P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_profile_enable.argtypes = [P, ctypes.c_int]
+    lib.bz_profile_get.argtypes = [P, ctypes.POINTER(bz_profile_info)]
     for name in EXPORTED:
         if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
@@ -237,3 +244,11 @@ class Context:
                                           ctypes.byref(o), _ptr(stats), _stream())
         self._check(st, "bz_cell_fixed_point")
         return g, stats
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.bz_profile_enable(self.h, 1 if on else 0), "bz_profile_enable")
+
+    def profile_get(self):
+        info = bz_profile_info()
+        self._check(self.lib.bz_profile_get(self.h, ctypes.byref(info)), "bz_profile_get")
+        return {"launches": info.launches, "total_ms": info.total_ms, "flops": info.flops}

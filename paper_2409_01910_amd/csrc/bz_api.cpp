@@ -31,6 +31,18 @@ bz_status ensure_ws(bz_ctx* ctx, size_t bytes) {
   return BZ_OK;
 }
 
+bz_status prof_mark(bz_ctx* ctx, hipStream_t st, bool stop, double flops) {
+  if (!ctx->prof) return BZ_OK;
+  if (ctx->prof_used == ctx->prof_ev.size()) {
+    hipEvent_t e;
+    BZ_HIP(hipEventCreate(&e));
+    ctx->prof_ev.push_back(e);
+  }
+  BZ_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used++], st));
+  if (stop) ctx->prof_flops += flops;
+  return BZ_OK;
+}
+
 }  // namespace bz
 
 using bz::set_err;
@@ -100,7 +112,33 @@ void bz_destroy(bz_ctx* ctx) {
   (void)hipDeviceSynchronize();
   bz::free_tables(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   delete ctx;
+}
+
+bz_status bz_profile_enable(bz_ctx* ctx, int enable) {
+  if (!ctx) return BZ_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(ctx, BZ_EHIP, "hipDeviceSynchronize");
+  ctx->prof = enable != 0;
+  ctx->prof_used = 0;
+  ctx->prof_flops = 0.0;
+  return BZ_OK;
+}
+
+bz_status bz_profile_get(bz_ctx* ctx, bz_profile_info* out) {
+  if (!ctx || !out) return BZ_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(ctx, BZ_EHIP, "hipDeviceSynchronize");
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < ctx->prof_used; i += 2) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ctx->prof_ev[i], ctx->prof_ev[i + 1]) != hipSuccess)
+      return set_err(ctx, BZ_EHIP, "hipEventElapsedTime");
+    ms += t;
+  }
+  out->launches = (int64_t)(ctx->prof_used / 2);
+  out->total_ms = ms;
+  out->flops = ctx->prof_flops;
+  return BZ_OK;
 }
 
 bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags, double* theta,

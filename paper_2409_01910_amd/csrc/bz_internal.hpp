@@ -34,6 +34,12 @@ struct bz_ctx {
   float* d_W_f = nullptr;
   float* d_Gm_f = nullptr;
 
+  // profiling of the direction-pair kernel (events recorded around launches)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+  size_t prof_used = 0;             // events used
+  double prof_flops = 0.0;
+
   // workspace (grown on demand, never shrunk until destroy)
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -44,6 +50,8 @@ namespace bz {
 bz_status set_err(bz_ctx* c, bz_status s, const std::string& msg);
 bz_status hip_err(bz_ctx* c, hipError_t e, const char* what);
 bz_status ensure_ws(bz_ctx* c, size_t bytes);
+// record the start (stop = false) or stop event of a profiled launch
+bz_status prof_mark(bz_ctx* c, hipStream_t st, bool stop, double flops);
 
 #define BZ_HIP(call)                                         \
   do {                                                       \

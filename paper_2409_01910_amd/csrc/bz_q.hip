@@ -476,12 +476,15 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
     for (int r = 0; r < ctx->n_rho; ++r) {
       hipLaunchKernelGGL((k_zstage<T, N>), dim3(gcol), dim3(256), 0, st, Fc, Z, nvol, nt, ph1 + (size_t)r * nt * N);
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
+      const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
+      if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
       if (corrected)
         hipLaunchKernelGGL((k_pairs<T, N, 2>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
                            ctx->n_phi, ph23r, pairw);
       else
         hipLaunchKernelGGL((k_pairs<T, N, 1>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
                            ctx->n_phi, ph23r, pairw);
+      if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nf * job_flops)) != BZ_OK) return s;
       const unsigned gq = (unsigned)((B * NN + 255) / 256);
       hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r * K, r == 0 ? 1 : 0);
     }

@@ -35,11 +35,15 @@ def maxwellian_mixture(params, N: int, L: float, d: int = 3) -> np.ndarray:
     grid nodes; returns a C-ordered array of shape (N,)*d flattened to N^d.
     ``params`` is a list of (rho, u[d], T)."""
     x = grid_nodes(N, L)
-    axes = np.meshgrid(*([x] * d), indexing="ij")
     f = np.zeros((N,) * d)
     for rho, u, T in params:
-        r2 = sum((axes[a] - u[a]) ** 2 for a in range(d))
-        f += rho * (2.0 * np.pi * T) ** (-d / 2.0) * np.exp(-r2 / (2.0 * T))
+        # each component factorises over the axes
+        comp = rho * (2.0 * np.pi * T) ** (-d / 2.0)
+        fac = [np.exp(-((x - u[a]) ** 2) / (2.0 * T)) for a in range(d)]
+        prod = fac[0]
+        for a in range(1, d):
+            prod = np.multiply.outer(prod, fac[a])
+        f += comp * prod
     return f.reshape(-1)
 
 
