@@ -252,3 +252,72 @@ class Context:
         info = bz_profile_info()
         self._check(self.lib.bz_profile_get(self.h, ctypes.byref(info)), "bz_profile_get")
         return {"launches": info.launches, "total_ms": info.total_ms, "flops": info.flops}
+
+
+class Slab:
+    """A set of 1D slab instances sharing one context (bz_slab).
+
+    ``instances`` is a list of dicts with keys xL, xR, nx, eps, T_L, T_R, U_L, U_R,
+    mass.  ``f`` is a float64 device tensor [sum nx, K] that the slab reads and
+    updates in place (borrowed for the slab's lifetime)."""
+
+    def __init__(self, ctx: Context, instances, f, collision: str = "binary", bgk_nu: float = 0.0,
+                 mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0):
+        self.ctx = ctx
+        self.f = f
+        n = len(instances)
+        arr = (bz_slab_instance * n)()
+        for i, d in enumerate(instances):
+            arr[i].xL, arr[i].xR, arr[i].nx, arr[i].eps = d.get("xL", 0.0), d.get("xR", 1.0), d["nx"], d["eps"]
+            arr[i].T_L, arr[i].T_R, arr[i].mass = d.get("T_L", 1.0), d.get("T_R", 2.0), d.get("mass", 1.0)
+            for a in range(3):
+                arr[i].U_L[a] = d.get("U_L", (0.0, 0.0, 0.0))[a]
+                arr[i].U_R[a] = d.get("U_R", (0.0, 0.0, 0.0))[a]
+        total = sum(d["nx"] for d in instances)
+        ctx._field(f, "f")
+        if f.numel() != total * ctx.K:
+            raise BZError("f must hold sum(nx) cells")
+        self._arr = arr
+        desc = bz_slab_desc(n, arr, BZ_COLL_BINARY if collision == "binary" else BZ_COLL_BGK, bgk_nu,
+                            Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()))
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.bz_slab_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_slab_create")
+        self.h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.bz_slab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stats(st):
+        return {"n_iters": st.n_iters, "inner_iters": st.inner_iters, "visits": st.visits, "fallbacks": st.fallbacks}
+
+    def sweep(self, n_iters: int = 1):
+        """n_iters SGS iterations; returns (residuals per instance, stats)."""
+        res = (ctypes.c_double * self.n)()
+        st = bz_sweep_stats()
+        self.ctx._check(self.ctx.lib.bz_sgs_sweep(self.ctx.h, self.h, n_iters, res, ctypes.byref(st), _stream()),
+                        "bz_sgs_sweep")
+        return list(res), self._stats(st)
+
+    def residual(self):
+        res = (ctypes.c_double * self.n)()
+        self.ctx._check(self.ctx.lib.bz_outer_residual(self.ctx.h, self.h, res, _stream()), "bz_outer_residual")
+        return list(res)
+
+    def vcycle(self, n_cycles: int = 1, coarsest: int = 4, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
+               tol: float = 1e-5):
+        o = bz_mg_opts(coarsest, nu1, nu2, coarse_iters, tol)
+        res = (ctypes.c_double * self.n)()
+        st = bz_sweep_stats()
+        self.ctx._check(self.ctx.lib.bz_multigrid_vcycle(self.ctx.h, self.h, ctypes.byref(o), n_cycles, res,
+                                                         ctypes.byref(st), _stream()), "bz_multigrid_vcycle")
+        return list(res), self._stats(st)

@@ -1,22 +1,715 @@
-// 1D slab sweeps (placeholder until the SGS driver lands).
+// Symmetric Gauss-Seidel scans, outer residual, mass constraint and the FAS
+// multigrid V-cycle on 1D slabs (Sections 3.1, 3.3 and 4), first-order upwind.
+//
+// One scan of eq. SGS on every instance:
+//   batched   Q, M[f], nu of every cell from the iterate before the scan
+//             (P = Q - nu (M - f) is explicit, eq. Pf), the wall densities from
+//             the zero-mass-flux condition (eq. boundary), and the static part
+//             of the right-hand side r_j (eq. r): the not-yet-updated neighbour,
+//             the ghost terms, -P_j/eps and the FAS source -b_j;
+//   sequential one work-group per instance visits its cells in scan order;
+//             each visit adds the freshly updated upwind neighbour to r and
+//             solves eq. inner_eqn (solve_cell_block).
+// After the backward scan every instance is rescaled uniformly to its total
+// mass C (eq. mass_conserv).  Readings where the paper is silent: the wall
+// density uses the discrete flux balance on the grid; ghost values use the
+// latest value of the wall-adjacent cell; the inner solve starts from the
+// cell's current value; the mass rescale happens after each SGS iteration on
+// the finest level (after each V-cycle under multigrid), never inside coarse
+// smoothing; restriction averages two children, prolongation injects the
+// coarse correction; the coarsest level is smoothed until its residual falls
+// 10x or coarse_iters iterations pass; a V-cycle stops descending once the
+// level residual (max over instances) is below tol.
+#include <cmath>
+#include <vector>
+
+#include "bz_cellsolve.hpp"
+#include "bz_common.hpp"
 #include "bz_internal.hpp"
 
-extern "C" {
-struct bz_slab {
-  int dummy;
+namespace bz {
+
+struct InstDev {
+  int off;
+  int nx;
+  double dx;
+  double eps;
+  double mass;
 };
-bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc*, bz_slab** out) {
-  if (out) *out = nullptr;
-  return bz::set_err(ctx, BZ_EUNSUPPORTED, "slab sweeps not built yet");
+
+struct WallDev {
+  double T[2];
+  double U[2][3];
+};
+
+struct Level {
+  int ncell = 0;
+  std::vector<InstDev> h_inst;
+  InstDev* d_inst = nullptr;
+  int* d_cell_inst = nullptr;
+  double* f = nullptr;
+  bool own_f = false;
+  double* b = nullptr;  // FAS right-hand side (nullptr on the finest level)
+  double* Q = nullptr;
+  double* theta = nullptr;
+  double* nu = nullptr;
+  double* rs = nullptr;
+  double* R = nullptr;  // residual field (transport - Q/eps), multigrid only
+  double* fc0 = nullptr;  // restricted fine iterate (coarse levels)
+  double* cellsum = nullptr;
+  double* ghost = nullptr;  // [n_inst][2] wall densities
+  bool q_valid = false;
+};
+
+}  // namespace bz
+
+struct bz_slab {
+  bz_ctx* ctx = nullptr;
+  int n_inst = 0;
+  std::vector<bz_slab_instance> inst;
+  int collision = 0;
+  double bgk_nu = 0.0;
+  bz_solve_opts inner{};
+  double* wallM = nullptr;    // [n_inst][2][K] unit-density wall Maxwellians
+  double* wall_in = nullptr;  // [n_inst][2] incoming discrete flux of the unit wall Maxwellian
+  unsigned long long* d_stats = nullptr;  // inner iterations, visits, fallbacks
+  std::vector<bz::Level> levels;
+  bool mg_built = false;
+};
+
+namespace bz {
+
+// ------------------------------------------------------------------ kernels
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_wall_init(const WallDev* __restrict__ walls, double* __restrict__ wallM,
+                                                            double* __restrict__ wall_in,
+                                                            const double* __restrict__ nodes, double w) {
+  constexpr int K = N * N * N;
+  const int i = blockIdx.x / 2, side = blockIdx.x % 2;
+  const WallDev wd = walls[i];
+  const double T = wd.T[side];
+  const double* U = wd.U[side];
+  double* M = wallM + ((size_t)i * 2 + side) * K;
+  __shared__ double s_red[kCellThreads / 64];
+  double acc[1] = {0.0};
+  const double norm = pow(2.0 * kPi * T, -1.5);
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = nodes[k / (N * N)], v1 = nodes[(k / N) % N], v2 = nodes[k % N];
+    const double d0 = v0 - U[0], d1 = v1 - U[1], d2 = v2 - U[2];
+    const double m = norm * exp(-(d0 * d0 + d1 * d1 + d2 * d2) / (2.0 * T));
+    M[k] = m;
+    // incoming half-space: v_1 > 0 at the left wall, v_1 < 0 at the right wall
+    if (side == 0 ? v0 > 0.0 : v0 < 0.0) acc[0] += fabs(v0) * m;
+  }
+  block_sum<1>(acc, s_red);
+  if (threadIdx.x == 0) wall_in[i * 2 + side] = w * acc[0];
 }
-void bz_slab_destroy(bz_slab*) {}
-bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab*, int, double*, bz_sweep_stats*, void*) {
-  return bz::set_err(ctx, BZ_EUNSUPPORTED, "slab sweeps not built yet");
+
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __restrict__ f, const InstDev* __restrict__ inst,
+                                                            const double* __restrict__ wall_in,
+                                                            double* __restrict__ ghost, const double* __restrict__ nodes,
+                                                            double w) {
+  constexpr int K = N * N * N;
+  const int i = blockIdx.x / 2, side = blockIdx.x % 2;
+  const InstDev id = inst[i];
+  const double* fc = f + (size_t)(id.off + (side == 0 ? 0 : id.nx - 1)) * K;
+  __shared__ double s_red[kCellThreads / 64];
+  double acc[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = nodes[k / (N * N)];
+    // outgoing half-space of the wall-adjacent cell
+    if (side == 0 ? v0 < 0.0 : v0 > 0.0) acc[0] += fabs(v0) * fc[k];
+  }
+  block_sum<1>(acc, s_red);
+  if (threadIdx.x == 0) ghost[i * 2 + side] = w * acc[0] / wall_in[i * 2 + side];
 }
-bz_status bz_outer_residual(bz_ctx* ctx, bz_slab*, double*, void*) {
-  return bz::set_err(ctx, BZ_EUNSUPPORTED, "slab sweeps not built yet");
+
+// theta -> (axis factors, e^alpha); returns 4 pi rho of the Gaussian in s_nu
+template <int N>
+__device__ __forceinline__ void gauss_tables(const double* th, const double* nodes, double w, double (*s_E)[N],
+                                             double* s_rho) {
+  if (threadIdx.x < 3 * N) {
+    const int a = threadIdx.x / N, i = threadIdx.x % N;
+    const double x = nodes[i];
+    s_E[a][i] = exp(th[1 + a] * x - th[4] * x * x);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < N; ++i) s[a] += s_E[a][i];
+    *s_rho = w * exp(th[0]) * s[0] * s[1] * s[2];
+  }
+  __syncthreads();
 }
-bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab*, const bz_mg_opts*, int, double*, bz_sweep_stats*, void*) {
-  return bz::set_err(ctx, BZ_EUNSUPPORTED, "slab sweeps not built yet");
+
+// static right-hand side of one scan for every cell; also nu of every cell
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_static_rhs(
+    const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
+    const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ nu_out,
+    const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
+    const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const int i = cell_inst[c];
+  const InstDev id = inst[i];
+  const int j = c - id.off;
+  __shared__ double s_E[3][N];
+  __shared__ double s_rho;
+  gauss_tables<N>(theta + (size_t)c * 5, nodes, w, s_E, &s_rho);
+  const double nu = (bgk && bgk_nu > 0.0) ? bgk_nu : 4.0 * kPi * s_rho;
+  if (threadIdx.x == 0) nu_out[c] = nu;
+  const double ea = exp(theta[(size_t)c * 5]);
+  const double ie = 1.0 / id.eps, idx = 1.0 / id.dx;
+  const double* fc = f + (size_t)c * K;
+  const double* fR = (j < id.nx - 1) ? f + (size_t)(c + 1) * K : nullptr;
+  const double* fL = (j > 0) ? f + (size_t)(c - 1) * K : nullptr;
+  const double gL = ghost[i * 2], gR = ghost[i * 2 + 1];
+  const double* ML = wallM + (size_t)i * 2 * K;
+  const double* MR = ML + K;
+  double* out = rs + (size_t)c * K;
+  const double* bc = bsrc ? bsrc + (size_t)c * K : nullptr;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = nodes[k / (N * N)];
+    const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
+    double r = 0.0;
+    if (!bgk) {
+      const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+      r -= (Q[(size_t)c * K + k] - nu * (M - fc[k])) * ie;  // -P / eps
+    }
+    if (bc) r -= bc[k];
+    if (forward) {
+      r += vm * (fR ? fR[k] : gR * MR[k]) * idx;   // old downstream neighbour (or right wall)
+      if (j == 0) r -= vp * gL * ML[k] * idx;      // left wall ghost
+    } else {
+      r -= vp * (fL ? fL[k] : gL * ML[k]) * idx;   // neighbour from the forward scan (or left wall)
+      if (j == id.nx - 1) r += vm * gR * MR[k] * idx;  // right wall ghost
+    }
+    out[k] = r;
+  }
 }
+
+template <int N>
+struct RChain {
+  const double* rs;
+  const double* fn;  // freshly updated upwind neighbour, or nullptr
+  const double* nodes;
+  double idx;
+  int forward;
+  __device__ __forceinline__ double operator()(int k) const {
+    double r = rs[k];
+    if (fn) {
+      const double v0 = nodes[k / (N * N)];
+      r += forward ? -fmax(v0, 0.0) * idx * fn[k] : fmin(v0, 0.0) * idx * fn[k];
+    }
+    return r;
+  }
+};
+
+// one work-group per instance: the cells of the scan in order
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_chain(double* f, const double* __restrict__ rs,
+                                                        const double* __restrict__ nu, const InstDev* __restrict__ inst,
+                                                        int forward, SolveArgs opt,
+                                                        unsigned long long* __restrict__ stats,
+                                                        const double* __restrict__ nodes, double w) {
+  constexpr int K = N * N * N;
+  const InstDev id = inst[blockIdx.x];
+  unsigned long long it_sum = 0, fb_sum = 0;
+  for (int step = 0; step < id.nx; ++step) {
+    const int j = forward ? step : id.nx - 1 - step;
+    const int c = id.off + j;
+    const double* fn = forward ? (j > 0 ? f + (size_t)(c - 1) * K : nullptr)
+                               : (j < id.nx - 1 ? f + (size_t)(c + 1) * K : nullptr);
+    RChain<N> rf{rs + (size_t)c * K, fn, nodes, 1.0 / id.dx, forward};
+    double* fc = f + (size_t)c * K;
+    const SolveOut o = solve_cell_block<N>(rf, fc, fc, nu[c] / id.eps, id.dx, opt, nodes, w);
+    it_sum += o.iterations;
+    fb_sum += o.fallback;
+    __syncthreads();  // f_j written before it is read as the next upwind neighbour
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&stats[0], it_sum);
+    atomicAdd(&stats[1], (unsigned long long)id.nx);
+    atomicAdd(&stats[2], fb_sum);
+  }
 }
+
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_cell_sum(const double* __restrict__ f, double* __restrict__ out) {
+  constexpr int K = N * N * N;
+  __shared__ double s_red[kCellThreads / 64];
+  double acc[1] = {0.0};
+  const double* fc = f + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) acc[0] += fc[k];
+  block_sum<1>(acc, s_red);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
+}
+
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_rescale(double* f, const double* __restrict__ cellsum,
+                                                          const InstDev* __restrict__ inst,
+                                                          const int* __restrict__ cell_inst, double w) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const InstDev id = inst[cell_inst[c]];
+  double tot = 0.0;
+  for (int j = 0; j < id.nx; ++j) tot += cellsum[id.off + j];
+  const double scale = id.mass / (id.dx * w * tot);
+  double* fc = f + (size_t)c * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) fc[k] *= scale;
+}
+
+// residual field T = transport(f) - Q/eps; per-cell sum of w (T - b)^2
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_residual(
+    const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
+    const double* __restrict__ bsrc, double* __restrict__ Rout, double* __restrict__ cellres,
+    const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
+    const double* __restrict__ wallM, int bgk, double bgk_nu, const double* __restrict__ nodes, double w) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const int i = cell_inst[c];
+  const InstDev id = inst[i];
+  const int j = c - id.off;
+  __shared__ double s_E[3][N];
+  __shared__ double s_rho;
+  __shared__ double s_red[kCellThreads / 64];
+  gauss_tables<N>(theta + (size_t)c * 5, nodes, w, s_E, &s_rho);
+  const double nu = (bgk_nu > 0.0) ? bgk_nu : 4.0 * kPi * s_rho;
+  const double ea = exp(theta[(size_t)c * 5]);
+  const double ie = 1.0 / id.eps, idx = 1.0 / id.dx;
+  const double* fc = f + (size_t)c * K;
+  const double* fR = (j < id.nx - 1) ? fc + K : nullptr;
+  const double* fL = (j > 0) ? fc - K : nullptr;
+  const double gL = ghost[i * 2], gR = ghost[i * 2 + 1];
+  const double* ML = wallM + (size_t)i * 2 * K;
+  const double* MR = ML + K;
+  double acc[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = nodes[k / (N * N)];
+    const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
+    const double left = fL ? fL[k] : gL * ML[k];
+    const double right = fR ? fR[k] : gR * MR[k];
+    double q;
+    if (bgk) {
+      const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+      q = nu * (M - fc[k]);
+    } else {
+      q = Q[(size_t)c * K + k];
+    }
+    const double T = (vp * (fc[k] - left) + vm * (right - fc[k])) * idx - q * ie;
+    if (Rout) Rout[(size_t)c * K + k] = T;
+    const double d = bsrc ? T - bsrc[(size_t)c * K + k] : T;
+    acc[0] += d * d;
+  }
+  block_sum<1>(acc, s_red);
+  if (threadIdx.x == 0) cellres[c] = w * acc[0];
+}
+
+// coarse[J] = (a[2J] + a[2J+1]) / 2 - (b ? (b[2J] + b[2J+1]) / 2 : 0), K values per cell
+__global__ void k_restrict(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                           int64_t ncoarse, int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ncoarse * K) return;
+  const int64_t J = g / K, k = g % K;
+  const double* a0 = a + (2 * J) * K + k;
+  double v = 0.5 * (a0[0] + a0[K]);
+  if (b) {
+    const double* b0 = b + (2 * J) * K + k;
+    v -= 0.5 * (b0[0] + b0[K]);
+  }
+  out[g] = v;
+}
+
+// out = x + sign * y (elementwise)
+__global__ void k_axpy(double* out, const double* __restrict__ x, const double* __restrict__ y, double sign, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) out[g] = x[g] + sign * y[g];
+}
+
+// f_fine[2J + s] += fc[J] - fc0[J]
+__global__ void k_prolong_add(double* f, const double* __restrict__ fc, const double* __restrict__ fc0, int64_t nfine,
+                              int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nfine * K) return;
+  const int64_t jf = g / K, k = g % K;
+  const int64_t J = jf / 2;
+  f[g] += fc[J * K + k] - fc0[J * K + k];
+}
+
+// ------------------------------------------------------------------ host side
+#define BZ_SLAB_N(NV, CALL)                                         \
+  switch (NV) {                                                     \
+    case 8: {                                                       \
+      constexpr int NN_ = 8;                                        \
+      CALL;                                                         \
+    } break;                                                        \
+    case 16: {                                                      \
+      constexpr int NN_ = 16;                                       \
+      CALL;                                                         \
+    } break;                                                        \
+    case 32: {                                                      \
+      constexpr int NN_ = 32;                                       \
+      CALL;                                                         \
+    } break;                                                        \
+    default:                                                        \
+      return set_err(ctx, BZ_EUNSUPPORTED, "N must be 8, 16 or 32"); \
+  }
+
+static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg) {
+  const size_t K = ctx->K;
+  BZ_HIP(hipMalloc((void**)&L.d_inst, sizeof(InstDev) * L.h_inst.size()));
+  BZ_HIP(hipMemcpy(L.d_inst, L.h_inst.data(), sizeof(InstDev) * L.h_inst.size(), hipMemcpyHostToDevice));
+  std::vector<int> ci(L.ncell);
+  for (size_t i = 0; i < L.h_inst.size(); ++i)
+    for (int j = 0; j < L.h_inst[i].nx; ++j) ci[L.h_inst[i].off + j] = (int)i;
+  BZ_HIP(hipMalloc((void**)&L.d_cell_inst, sizeof(int) * L.ncell));
+  BZ_HIP(hipMemcpy(L.d_cell_inst, ci.data(), sizeof(int) * L.ncell, hipMemcpyHostToDevice));
+  BZ_HIP(hipMalloc((void**)&L.Q, sizeof(double) * K * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.rs, sizeof(double) * K * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.theta, sizeof(double) * 5 * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.nu, sizeof(double) * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.cellsum, sizeof(double) * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.ghost, sizeof(double) * 2 * n_inst));
+  if (with_mg) BZ_HIP(hipMalloc((void**)&L.R, sizeof(double) * K * L.ncell));
+  return BZ_OK;
+}
+
+static void level_free(Level& L) {
+  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (L.own_f && L.f) (void)hipFree(L.f);
+  L = Level();
+}
+
+static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
+  if (L.q_valid) return BZ_OK;
+  bz_status e;
+  if (s->collision == BZ_COLL_BINARY)
+    e = eval_q(ctx, L.f, L.Q, L.ncell, true, L.theta, st);
+  else
+    e = maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st);
+  if (e == BZ_OK) L.q_valid = true;
+  return e;
+}
+
+static bz_status ghosts(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_ghost_rho<NN_>), dim3(2 * s->n_inst), dim3(kCellThreads), 0, st, L.f,
+                                       L.d_inst, s->wall_in, L.ghost, ctx->d_nodes, ctx->w));
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream_t st) {
+  bz_status e = collide(ctx, s, L, st);
+  if (e != BZ_OK) return e;
+  if ((e = ghosts(ctx, s, L, st)) != BZ_OK) return e;
+  const int bgk = s->collision == BZ_COLL_BGK;
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_static_rhs<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
+                                       L.theta, L.b, L.rs, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
+                                       forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w));
+  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters};
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kCellThreads), 0, st, L.f, L.rs, L.nu,
+                                       L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
+  BZ_HIP(hipGetLastError());
+  L.q_valid = false;
+  return BZ_OK;
+}
+
+static bz_status rescale(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
+  (void)s;
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_cell_sum<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.cellsum));
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_rescale<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.cellsum,
+                                       L.d_inst, L.d_cell_inst, ctx->w));
+  BZ_HIP(hipGetLastError());
+  L.q_valid = false;
+  return BZ_OK;
+}
+
+static bz_status sgs_iter(bz_ctx* ctx, bz_slab* s, Level& L, bool do_rescale, hipStream_t st) {
+  bz_status e;
+  if ((e = scan(ctx, s, L, true, st)) != BZ_OK) return e;
+  if ((e = scan(ctx, s, L, false, st)) != BZ_OK) return e;
+  if (do_rescale) return rescale(ctx, s, L, st);
+  return BZ_OK;
+}
+
+// per-instance residual norms |T - b| (host vector); optionally keeps the field T in L.R
+static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, std::vector<double>& out,
+                          hipStream_t st) {
+  bz_status e = collide(ctx, s, L, st);
+  if (e != BZ_OK) return e;
+  if ((e = ghosts(ctx, s, L, st)) != BZ_OK) return e;
+  const int bgk = s->collision == BZ_COLL_BGK;
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_residual<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
+                                       L.theta, L.b, keep_field ? L.R : nullptr, L.cellsum, L.d_inst, L.d_cell_inst,
+                                       L.ghost, s->wallM, bgk, bgk ? s->bgk_nu : 0.0, ctx->d_nodes, ctx->w));
+  BZ_HIP(hipGetLastError());
+  std::vector<double> cs(L.ncell);
+  BZ_HIP(hipMemcpyAsync(cs.data(), L.cellsum, sizeof(double) * L.ncell, hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipStreamSynchronize(st));
+  out.assign(L.h_inst.size(), 0.0);
+  for (size_t i = 0; i < L.h_inst.size(); ++i) {
+    double t = 0.0;
+    for (int j = 0; j < L.h_inst[i].nx; ++j) t += cs[L.h_inst[i].off + j];
+    out[i] = std::sqrt(L.h_inst[i].dx * t);
+  }
+  return BZ_OK;
+}
+
+static double vmax(const std::vector<double>& v) {
+  double m = 0.0;
+  for (double x : v) m = std::fmax(m, x);
+  return m;
+}
+
+static bz_status build_mg(bz_ctx* ctx, bz_slab* s, int coarsest) {
+  if (s->mg_built) return BZ_OK;
+  const int nx = s->inst[0].nx;
+  for (const auto& in : s->inst)
+    if (in.nx != nx) return set_err(ctx, BZ_EINVAL, "multigrid needs equal cell counts in every instance");
+  int n = nx;
+  while (n > coarsest && n % 2 == 0) n /= 2;
+  if (n != coarsest) return set_err(ctx, BZ_EINVAL, "cell count must be coarsest * 2^k");
+  const size_t K = ctx->K;
+  // the finest level gets a residual field
+  BZ_HIP(hipMalloc((void**)&s->levels[0].R, sizeof(double) * K * s->levels[0].ncell));
+  int lev_nx = nx / 2;
+  while (lev_nx >= coarsest) {
+    Level L;
+    const Level& F = s->levels.back();
+    L.ncell = F.ncell / 2;
+    for (const InstDev& fi : F.h_inst) L.h_inst.push_back(InstDev{fi.off / 2, fi.nx / 2, fi.dx * 2.0, fi.eps, fi.mass});
+    bz_status e = level_alloc(ctx, L, s->n_inst, true);
+    if (e != BZ_OK) return e;
+    BZ_HIP(hipMalloc((void**)&L.f, sizeof(double) * K * L.ncell));
+    L.own_f = true;
+    BZ_HIP(hipMalloc((void**)&L.b, sizeof(double) * K * L.ncell));
+    BZ_HIP(hipMalloc((void**)&L.fc0, sizeof(double) * K * L.ncell));
+    s->levels.push_back(L);
+    if (lev_nx == coarsest) break;
+    lev_nx /= 2;
+  }
+  s->mg_built = true;
+  return BZ_OK;
+}
+
+static bz_status vcycle(bz_ctx* ctx, bz_slab* s, size_t l, const bz_mg_opts* o, hipStream_t st) {
+  Level& L = s->levels[l];
+  bz_status e;
+  std::vector<double> rn;
+  for (int i = 0; i < o->nu1; ++i)
+    if ((e = sgs_iter(ctx, s, L, false, st)) != BZ_OK) return e;
+  if (l + 1 == s->levels.size()) {
+    if ((e = residual(ctx, s, L, false, rn, st)) != BZ_OK) return e;
+    const double r0 = vmax(rn);
+    for (int it = 0; it < o->coarse_iters; ++it) {
+      if (it > 0) {
+        if ((e = residual(ctx, s, L, false, rn, st)) != BZ_OK) return e;
+      }
+      if (vmax(rn) <= 0.1 * r0) break;
+      if ((e = sgs_iter(ctx, s, L, false, st)) != BZ_OK) return e;
+    }
+    return BZ_OK;
+  }
+  if ((e = residual(ctx, s, L, true, rn, st)) != BZ_OK) return e;  // L.R = R_h(f)
+  if (vmax(rn) < o->tol) return BZ_OK;
+  Level& C = s->levels[l + 1];
+  const size_t K = ctx->K;
+  const unsigned gc = (unsigned)(((int64_t)C.ncell * K + 255) / 256);
+  // f_H = I f_h ; fc0 = f_H ; res_h = b_h - R_h(f_h) (b_h = 0 on the finest level)
+  hipLaunchKernelGGL(k_restrict, dim3(gc), dim3(256), 0, st, L.f, (const double*)nullptr, C.f, (int64_t)C.ncell, (int)K);
+  BZ_HIP(hipMemcpyAsync(C.fc0, C.f, sizeof(double) * K * C.ncell, hipMemcpyDeviceToDevice, st));
+  C.q_valid = false;
+  // b_H = R_H(f_H) + I (b_h - R_h(f_h)): first R_H(f_H) into C.R (C.b not yet used)
+  std::vector<double> tmp;
+  double* saved_b = C.b;
+  C.b = nullptr;
+  e = residual(ctx, s, C, true, tmp, st);
+  C.b = saved_b;
+  if (e != BZ_OK) return e;
+  // C.b = I(b_h - R_h) computed as I(b_h) - I(R_h), then += R_H(f_H)
+  if (L.b)
+    hipLaunchKernelGGL(k_restrict, dim3(gc), dim3(256), 0, st, L.b, L.R, C.b, (int64_t)C.ncell, (int)K);
+  else {
+    hipLaunchKernelGGL(k_restrict, dim3(gc), dim3(256), 0, st, L.R, (const double*)nullptr, C.b, (int64_t)C.ncell,
+                       (int)K);
+    hipLaunchKernelGGL(k_axpy, dim3(gc), dim3(256), 0, st, C.b, (const double*)C.R, (const double*)C.b, -1.0,
+                       (int64_t)C.ncell * K);
+  }
+  if (L.b) hipLaunchKernelGGL(k_axpy, dim3(gc), dim3(256), 0, st, C.b, (const double*)C.b, (const double*)C.R, 1.0,
+                              (int64_t)C.ncell * K);
+  BZ_HIP(hipGetLastError());
+  if ((e = vcycle(ctx, s, l + 1, o, st)) != BZ_OK) return e;
+  const unsigned gf = (unsigned)(((int64_t)L.ncell * K + 255) / 256);
+  hipLaunchKernelGGL(k_prolong_add, dim3(gf), dim3(256), 0, st, L.f, (const double*)C.f, (const double*)C.fc0,
+                     (int64_t)L.ncell, (int)K);
+  BZ_HIP(hipGetLastError());
+  L.q_valid = false;
+  for (int i = 0; i < o->nu2; ++i)
+    if ((e = sgs_iter(ctx, s, L, false, st)) != BZ_OK) return e;
+  return BZ_OK;
+}
+
+static bz_status read_stats(bz_ctx* ctx, bz_slab* s, bz_sweep_stats* stats, int n_iters, hipStream_t st) {
+  unsigned long long h[3] = {0, 0, 0};
+  BZ_HIP(hipMemcpyAsync(h, s->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    stats->n_iters = n_iters;
+    stats->inner_iters = (int64_t)h[0];
+    stats->visits = (int64_t)h[1];
+    stats->fallbacks = (int64_t)h[2];
+  }
+  return BZ_OK;
+}
+
+}  // namespace bz
+
+using bz::set_err;
+
+extern "C" {
+
+bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
+  if (!ctx || !out) return BZ_EINVAL;
+  *out = nullptr;
+  if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
+  if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK) return set_err(ctx, BZ_EINVAL, "bad collision");
+  const bz_solve_opts& o = d->inner;
+  if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad inner mode");
+  if (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0))
+    return set_err(ctx, BZ_EINVAL, "bad inner options");
+  int off = 0;
+  std::vector<bz::InstDev> hi;
+  std::vector<bz::WallDev> walls;
+  for (int i = 0; i < d->n_instances; ++i) {
+    const bz_slab_instance& in = d->instances[i];
+    if (in.nx < 1 || !(in.xR > in.xL) || !(in.eps > 0) || !(in.T_L > 0) || !(in.T_R > 0) || !(in.mass > 0))
+      return set_err(ctx, BZ_EINVAL, "bad slab instance");
+    if (in.U_L[0] != 0.0 || in.U_R[0] != 0.0) return set_err(ctx, BZ_EINVAL, "wall velocity must be tangential");
+    hi.push_back(bz::InstDev{off, in.nx, (in.xR - in.xL) / in.nx, in.eps, in.mass});
+    bz::WallDev wd{};
+    wd.T[0] = in.T_L;
+    wd.T[1] = in.T_R;
+    for (int a = 0; a < 3; ++a) {
+      wd.U[0][a] = in.U_L[a];
+      wd.U[1][a] = in.U_R[a];
+    }
+    walls.push_back(wd);
+    off += in.nx;
+  }
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  bz_slab* s = new bz_slab();
+  s->ctx = ctx;
+  s->n_inst = d->n_instances;
+  s->inst.assign(d->instances, d->instances + d->n_instances);
+  s->collision = d->collision;
+  s->bgk_nu = d->bgk_nu;
+  s->inner = d->inner;
+  bz::Level L0;
+  L0.ncell = off;
+  L0.h_inst = hi;
+  L0.f = d->f;
+  bz_status e = bz::level_alloc(ctx, L0, s->n_inst, false);
+  s->levels.push_back(L0);
+  auto fail = [&](bz_status st) {
+    bz_slab_destroy(s);
+    return st;
+  };
+  if (e != BZ_OK) return fail(e);
+  const size_t K = ctx->K;
+  bz::WallDev* d_walls = nullptr;
+  if (hipMalloc((void**)&s->wallM, sizeof(double) * 2 * K * s->n_inst) != hipSuccess ||
+      hipMalloc((void**)&s->wall_in, sizeof(double) * 2 * s->n_inst) != hipSuccess ||
+      hipMalloc((void**)&s->d_stats, sizeof(unsigned long long) * 3) != hipSuccess ||
+      hipMalloc((void**)&d_walls, sizeof(bz::WallDev) * s->n_inst) != hipSuccess)
+    return fail(set_err(ctx, BZ_ENOMEM, "slab allocation"));
+  if (hipMemcpy(d_walls, walls.data(), sizeof(bz::WallDev) * s->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(s->d_stats, 0, sizeof(unsigned long long) * 3) != hipSuccess)
+    return fail(set_err(ctx, BZ_EHIP, "slab upload"));
+  switch (ctx->N) {
+    case 8: hipLaunchKernelGGL((bz::k_wall_init<8>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
+    case 16: hipLaunchKernelGGL((bz::k_wall_init<16>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
+    case 32: hipLaunchKernelGGL((bz::k_wall_init<32>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(set_err(ctx, BZ_EHIP, "wall init"));
+  (void)hipFree(d_walls);
+  *out = s;
+  return BZ_OK;
+}
+
+void bz_slab_destroy(bz_slab* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  for (auto& L : s->levels) bz::level_free(L);
+  if (s->wallM) (void)hipFree(s->wallM);
+  if (s->wall_in) (void)hipFree(s->wall_in);
+  if (s->d_stats) (void)hipFree(s->d_stats);
+  delete s;
+}
+
+bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_out, bz_sweep_stats* stats,
+                       void* stream) {
+  if (!ctx || !s || s->ctx != ctx) return BZ_EINVAL;
+  if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 3, st) != hipSuccess)
+    return set_err(ctx, BZ_EHIP, "stats reset");
+  bz::Level& L = s->levels[0];
+  L.q_valid = false;  // the caller may have changed f
+  for (int it = 0; it < n_iters; ++it) {
+    bz_status e = bz::sgs_iter(ctx, s, L, true, st);
+    if (e != BZ_OK) return e;
+  }
+  if (residual_out) {
+    std::vector<double> rn;
+    bz_status e = bz::residual(ctx, s, L, false, rn, st);
+    if (e != BZ_OK) return e;
+    for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
+  }
+  return bz::read_stats(ctx, s, stats, n_iters, st);
+}
+
+bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* s, double* residual_out, void* stream) {
+  if (!ctx || !s || s->ctx != ctx || !residual_out) return BZ_EINVAL;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  bz::Level& L = s->levels[0];
+  L.q_valid = false;
+  std::vector<double> rn;
+  bz_status e = bz::residual(ctx, s, L, false, rn, (hipStream_t)stream);
+  if (e != BZ_OK) return e;
+  for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
+  return BZ_OK;
+}
+
+bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int n_cycles, double* residual_out,
+                              bz_sweep_stats* stats, void* stream) {
+  if (!ctx || !s || s->ctx != ctx || !o) return BZ_EINVAL;
+  if (n_cycles < 0 || o->coarsest < 1 || o->nu1 < 0 || o->nu2 < 0 || o->coarse_iters < 0 || !(o->tol >= 0))
+    return set_err(ctx, BZ_EINVAL, "bad multigrid options");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  bz_status e = bz::build_mg(ctx, s, o->coarsest);
+  if (e != BZ_OK) return e;
+  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 3, st) != hipSuccess)
+    return set_err(ctx, BZ_EHIP, "stats reset");
+  bz::Level& L = s->levels[0];
+  L.q_valid = false;
+  for (int c = 0; c < n_cycles; ++c) {
+    if ((e = bz::vcycle(ctx, s, 0, o, st)) != BZ_OK) return e;
+    if ((e = bz::rescale(ctx, s, L, st)) != BZ_OK) return e;
+  }
+  if (residual_out) {
+    std::vector<double> rn;
+    if ((e = bz::residual(ctx, s, L, false, rn, st)) != BZ_OK) return e;
+    for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
+  }
+  return bz::read_stats(ctx, s, stats, n_cycles, st);
+}
+
+}  // extern "C"
