@@ -364,6 +364,167 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
   }
 }
 
+// ------------------------------------------------------------------ direction pairs, N = 32
+// Same computation as k_pairs, with each 32-point column split over two
+// adjacent lanes (lane = 2 q + h holds entries 16 h .. 16 h + 15 of column q).
+// One radix-2 decimation-in-frequency step, with the partner's half taken by
+// a lane-pair exchange, leaves two independent 16-point transforms: lane h
+// produces the outputs of parity h.  Halving the per-lane state lets two waves
+// share a SIMD.  A wave owns one (polar pair, variant) item - for the plain
+// form the second index splits the azimuths by parity instead - and runs all
+// of its azimuths with the A/B columns kept in registers.
+constexpr int kPair32Waves = 8;
+
+template <typename T>
+constexpr size_t pairs32_lds_bytes() {
+  return (size_t)kPair32Waves * 32 * 33 * sizeof(typename V2<T>::type) + (size_t)32 * 32 * sizeof(T);
+}
+
+// y <- first DIF step of a 32-point inverse DFT whose entries 16h+m live in
+// lane h of a lane pair; afterwards lane h holds the 16-point input whose
+// inverse DFT gives outputs 2k + h.
+// value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]
+__device__ __forceinline__ float swap_pair(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// y <- first DIF step of a 32-point inverse DFT whose entries 16h+m live in
+// lane h of a lane pair; afterwards lane h holds the 16-point input whose
+// inverse DFT gives outputs 2k + h.  With sg = 1 - 2h and hh = h:
+//   y = (partner + sg * own) * W^(h m),  W = e^{2 pi i / 32},
+// i.e. C(m) + C(m+16) on lane 0 and (C(m) - C(m+16)) W^m on lane 1.
+template <typename T>
+__device__ __forceinline__ void dif32_pair(T* re, T* im, int h) {
+  constexpr Twiddle<32> tw{};
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
+    const T sr = re[m] + pr, si = im[m] + pi;
+    const T dr = pr - re[m], di = pi - im[m];
+    const T c = T(tw.c[m]), s = T(tw.s[m]);
+    const T tr = dr * c - di * s, ti = dr * s + di * c;
+    re[m] = h ? tr : sr;
+    im[m] = h ? ti : si;
+  }
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2<T>::type* __restrict__ Z,
+                                                               typename V2<T>::type* __restrict__ Acc, int n_theta,
+                                                               int n_phi, const typename V2<T>::type* __restrict__ ph23,
+                                                               const T* __restrict__ pairw) {
+  using C = typename V2<T>::type;
+  constexpr int N = 32, K = N * N * N, NN = N * N, LD = N + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* trans = reinterpret_cast<C*>(smem);
+  T* red = reinterpret_cast<T*>(smem + (size_t)kPair32Waves * N * LD * sizeof(C));
+  const int b = blockIdx.x / N, i1 = blockIdx.x % N;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int q = ln >> 1, h = ln & 1;
+  C* tw = trans + (size_t)wv * N * LD;
+  T acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = T(0);
+  const int half = n_theta / 2;
+  const int items = half * 2;
+  for (int it = wv; it < items; it += kPair32Waves) {
+    const int tp = it >> 1, v = (NF == 2) ? (it & 1) : 0;
+    const int tA = half + tp, tB = half - 1 - tp;
+    const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
+    const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
+    const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
+    T ar[16], ai[16], br[16], bi[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const C x = za[(size_t)m * N], y = zb[(size_t)m * N];
+      ar[m] = x.x;
+      ai[m] = x.y;
+      br[m] = y.x;
+      bi[m] = y.y;
+    }
+    const T sA = (v == 0) ? T(1) : T(-1);
+    const int phi0 = (NF == 2) ? 0 : (it & 1);
+    const int phi_step = (NF == 2) ? 1 : 2;
+    for (int jj = phi0; jj < n_phi; jj += phi_step) {
+      const int pq = tp * n_phi + jj;
+      const C* p2 = ph23 + (size_t)pq * 2 * N;
+      const C p3 = p2[N + q];
+      T re[16], im[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const C a2 = p2[16 * h + m];
+        const T Pr = a2.x * p3.x - a2.y * p3.y;
+        const T Pi = sA * (a2.x * p3.y + a2.y * p3.x);
+        const T a_r = ar[m] * Pr - ai[m] * Pi, a_i = ar[m] * Pi + ai[m] * Pr;
+        const T b_r = br[m] * Pr + bi[m] * Pi, b_i = bi[m] * Pr - br[m] * Pi;
+        re[m] = a_r - b_i;
+        im[m] = a_i + b_r;
+      }
+      dif32_pair<T>(re, im, h);
+      fft_reg<T, 16, +1>(re, im);  // lane h: rows i2 = 2k + h of column q
+#pragma unroll
+      for (int k = 0; k < 16; ++k) tw[(2 * k + h) * LD + q] = C{re[k], im[k]};
+      wave_sync();
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const C x = tw[q * LD + 16 * h + m];  // row i2 = q, entries l3 = 16h + m
+        re[m] = x.x;
+        im[m] = x.y;
+      }
+      dif32_pair<T>(re, im, h);
+      fft_reg<T, 16, +1>(re, im);  // lane h: c(q, i3 = 2k + h)
+      const T wgt = pairw[pq] * T(NF == 1 ? 2 : 1);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[k] += wgt * re[k] * im[k];
+      wave_sync();
+    }
+  }
+  for (int w2 = 0; w2 < kPair32Waves; ++w2) {
+    if (wv == w2) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        T* dst = red + q * N + 2 * k + h;
+        *dst = (w2 == 0 ? T(0) : *dst) + acc[k];
+      }
+    }
+    __syncthreads();
+  }
+  // forward 2D transform of the accumulated real plane (axes 1 and 2)
+  if (threadIdx.x < N) {
+    const int row = threadIdx.x;
+    T re[N], im[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      re[l] = red[row * N + l];
+      im[l] = T(0);
+    }
+    fft_reg<T, N, -1>(re, im);
+#pragma unroll
+    for (int l = 0; l < N; ++l) trans[row * LD + l] = C{re[l], im[l]};
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int col = threadIdx.x;
+    T re[N], im[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const C x = trans[l * LD + col];
+      re[l] = x.x;
+      im[l] = x.y;
+    }
+    fft_reg<T, N, -1>(re, im);
+    C* dst = Acc + (size_t)b * K + (size_t)i1 * NN + col;
+#pragma unroll
+    for (int l = 0; l < N; ++l) dst[(size_t)l * N] = C{re[l], im[l]};
+  }
+}
+
 // ------------------------------------------------------------------ axis-0 forward + radial weight
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __restrict__ Acc,
@@ -454,12 +615,11 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   const T* W = (const T*)(f64 ? (const void*)ctx->d_W : (const void*)ctx->d_W_f);
   const T* Gm = (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
   constexpr int PPB = plane_ppb<T, N>();
-  const size_t lds = pairs_lds_bytes<T, N>();
-  if (corrected) {
-    BZ_HIP(hipFuncSetAttribute((const void*)k_pairs<T, N, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  } else {
-    BZ_HIP(hipFuncSetAttribute((const void*)k_pairs<T, N, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  }
+  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>() : pairs_lds_bytes<T, N>();
+  const void* kp = (N == 32) ? (corrected ? (const void*)k_pairs32<T, 2> : (const void*)k_pairs32<T, 1>)
+                             : (corrected ? (const void*)k_pairs<T, N, 2> : (const void*)k_pairs<T, N, 1>);
+  BZ_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int pair_threads = (N == 32) ? 64 * kPair32Waves : 64 * kPairWaves;
   for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
     const int64_t B = (batch - c0) < chunk ? (batch - c0) : chunk;
     const double* fb = f + c0 * K;
@@ -478,12 +638,10 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
       if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
-      if (corrected)
-        hipLaunchKernelGGL((k_pairs<T, N, 2>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
-                           ctx->n_phi, ph23r, pairw);
-      else
-        hipLaunchKernelGGL((k_pairs<T, N, 1>), dim3((unsigned)(B * N)), dim3(64 * kPairWaves), lds, st, Z, Acc, nt,
-                           ctx->n_phi, ph23r, pairw);
+      {
+        void* args[] = {(void*)&Z, (void*)&Acc, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pairw};
+        BZ_HIP(hipLaunchKernel(kp, dim3((unsigned)(B * N)), dim3(pair_threads), args, lds, st));
+      }
       if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nf * job_flops)) != BZ_OK) return s;
       const unsigned gq = (unsigned)((B * NN + 255) / 256);
       hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r * K, r == 0 ? 1 : 0);

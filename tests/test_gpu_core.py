@@ -155,3 +155,45 @@ def test_cell_fixed_point_matches_oracle_composition(dev):
         r = inflow[i] - P / eps[i]
         go, _ = OC.solve(sp, r, OQ.nu_of(sp, fo[i]), eps[i], dx, fo[i], mode="pfp", fixed_iters=2)
         assert np.max(np.abs(g[i] - go)) < 1e-10 * np.abs(go).max()
+
+
+# N = 32 uses the lane-pair kernel; cover every wave/item mapping: polar pairs
+# 1, 2, 4 (idle and busy waves), odd azimuth counts per parity, both forms.
+N32_CASES = [(2, 4, 2), (4, 6, 2), (8, 4, 1)]
+
+
+@pytest.mark.parametrize("rule", N32_CASES)
+@pytest.mark.parametrize("corrected", [False, True])
+def test_eval_q_n32_matches_oracle(dev, rule, corrected):
+    nt, nph, nr = rule
+    N, L, B = 32, 8.0, 2
+    print(f"eval_Q N=32 M={nt}x{nph} n_rho={nr} corrected={corrected}", flush=True)
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=24)
+    ctx = _ctx(N, L, nt, nph, nr)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=corrected).cpu().numpy()
+    for i in range(B):
+        gain, loss = OQ.q_fsm(sp, f[i], parts=True)
+        ref = OQ.q_corrected(sp, f[i]) if corrected else gain - loss
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qg[i], ref, scale) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_eval_q_full_workload_sampled(dev, prec, tol):
+    # the benchmark's workload and launch configuration: 4096 cells, 32^3,
+    # M = 128 (8 x 16), 16 radial nodes; two cells checked against the oracle
+    N, L, B = 32, 8.0, 4096
+    print(f"full workload precision={prec}", flush=True)
+    f = synth.mixture_batch(B, N, L, seed=0)
+    ctx = _ctx(N, L, 8, 16, 16, prec=prec)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True)
+    assert torch.isfinite(Qg).all().item()
+    sp = _spec(N, L, 8, 16, 16)
+    for i in (0, 4095):
+        ref = OQ.q_corrected(sp, f[i])
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        err = _rel(Qg[i].cpu().numpy(), ref, scale)
+        print(f"cell {i} rel err {err:.3e}", flush=True)
+        assert err < tol
