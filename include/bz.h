@@ -135,6 +135,8 @@ typedef struct {
   int32_t newton_fail; /* Newton failures met during the visit */
   int32_t status;      /* 0 ok, 1 residual not below tol, 2 non-finite */
   double residual;     /* last inner residual */
+  int32_t learned;     /* 1 if the learned initial guess was kept (learned path) */
+  int32_t reserved;
 } bz_cell_stats;
 
 /* bz_cell_solve: `batch` independent inner problems.
@@ -155,6 +157,49 @@ bz_status bz_cell_solve(bz_ctx* ctx, const double* r, const double* nu, const do
 bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* inflow_r, const double* eps,
                               double dx, double* g, int64_t batch, const bz_solve_opts* opts,
                               bz_cell_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- learned warm start
+ * A three-layer MLP  y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3  that
+ * predicts the correction g^0 - M[f_old] of a cell's initial guess (not part of
+ * the paper's method: an addition whose only effect is the starting point of
+ * the inner iteration, which still converges to the same fixed point).
+ * Parameters are FP32 on the device; flat layout W1 [in][H], b1 [H],
+ * W2 [H][H], b2 [H], W3 [H][out], b3 [out], row-major.  Inference uses BF16
+ * matrix-core products with FP32 accumulation, training FP32 products.
+ * bz_mlp_create: Glorot-uniform weights from `seed`, zero biases.
+ * bz_mlp_forward: X [batch][in] FP32 device -> Y [batch][out] FP32 device;
+ *   bf16 != 0 rounds X and the weights to BF16 for the products.
+ * bz_mlp_grad: loss = mean((y - T)^2) (returned on the host when loss != NULL,
+ *   which synchronises) and its gradient [num_params] FP32 device (nullable).
+ * bz_mlp_train_step: one Adam step (beta 0.9 / 0.999, eps 1e-8) on that loss.
+ * bz_mlp_features: the model input of each cell, width K + 6: inflow_r * dx
+ *   (K values), rho, U_1..3, T of the Maxwellian theta, log10(eps).
+ * bz_mlp_set_output_scale: y is multiplied by this before it is added to
+ *   M[f_old]. */
+typedef struct bz_mlp bz_mlp;
+
+bz_status bz_mlp_create(bz_ctx* ctx, int n_in, int hidden, int n_out, uint64_t seed, bz_mlp** out);
+void bz_mlp_destroy(bz_mlp* mlp);
+int64_t bz_mlp_num_params(bz_mlp* mlp);
+bz_status bz_mlp_get_params(bz_mlp* mlp, float* host, int64_t n);
+bz_status bz_mlp_set_params(bz_mlp* mlp, const float* host, int64_t n);
+bz_status bz_mlp_set_output_scale(bz_mlp* mlp, double y_scale);
+bz_status bz_mlp_forward(bz_mlp* mlp, const float* X, float* Y, int64_t batch, int bf16, void* stream);
+bz_status bz_mlp_grad(bz_mlp* mlp, const float* X, const float* T, int64_t batch, float* grad, double* loss,
+                      void* stream);
+bz_status bz_mlp_train_step(bz_mlp* mlp, const float* X, const float* T, int64_t batch, double lr, double* loss,
+                            void* stream);
+bz_status bz_mlp_features(bz_ctx* ctx, const double* inflow_r, const double* theta, const double* eps, double dx,
+                          float* X, int64_t batch, void* stream);
+
+/* bz_cell_fixed_point_learned: bz_cell_fixed_point with a second candidate
+ * initial guess g^0 = M[f_old] + scale * MLP(features) (BF16 inference); each
+ * cell keeps the candidate (f_old or learned) with the smaller initial residual
+ * of eq. inner_eqn, recorded in stats.learned.  mlp must have n_in = K + 6 and
+ * n_out = K. */
+bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_old, const double* inflow_r,
+                                      const double* eps, double dx, double* g, int64_t batch,
+                                      const bz_solve_opts* opts, bz_cell_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------- 1D slabs
  * A set of independent 1D slab problems (instances) on x in [xL, xR] with

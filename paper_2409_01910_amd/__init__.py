@@ -26,6 +26,9 @@ EXPORTED = [
     "bz_eval_Q", "bz_maxwellian", "bz_cell_solve", "bz_cell_fixed_point",
     "bz_slab_create", "bz_slab_destroy", "bz_sgs_sweep", "bz_outer_residual", "bz_multigrid_vcycle",
     "bz_profile_enable", "bz_profile_get",
+    "bz_mlp_create", "bz_mlp_destroy", "bz_mlp_num_params", "bz_mlp_get_params", "bz_mlp_set_params",
+    "bz_mlp_set_output_scale", "bz_mlp_forward", "bz_mlp_grad", "bz_mlp_train_step", "bz_mlp_features",
+    "bz_cell_fixed_point_learned",
 ]
 
 
@@ -42,7 +45,8 @@ class bz_solve_opts(ctypes.Structure):
 
 class bz_cell_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("fallback", ctypes.c_int32), ("newton_fail", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("residual", ctypes.c_double)]
+                ("status", ctypes.c_int32), ("residual", ctypes.c_double), ("learned", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class bz_slab_instance(ctypes.Structure):
@@ -72,7 +76,7 @@ class bz_profile_info(ctypes.Structure):
 
 
 CELL_STATS_DTYPE_FIELDS = [("iterations", "<i4"), ("fallback", "<i4"), ("newton_fail", "<i4"), ("status", "<i4"),
-                           ("residual", "<f8")]
+                           ("residual", "<f8"), ("learned", "<i4"), ("reserved", "<i4")]
 
 _lib = None
 
@@ -105,10 +109,25 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_outer_residual.argtypes = [P, P, P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_mlp_create.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_mlp_destroy.argtypes = [P]
+    lib.bz_mlp_destroy.restype = None
+    lib.bz_mlp_num_params.argtypes = [P]
+    lib.bz_mlp_num_params.restype = ctypes.c_int64
+    lib.bz_mlp_get_params.argtypes = [P, P, I64]
+    lib.bz_mlp_set_params.argtypes = [P, P, I64]
+    lib.bz_mlp_set_output_scale.argtypes = [P, D]
+    lib.bz_mlp_forward.argtypes = [P, P, P, I64, ctypes.c_int, P]
+    lib.bz_mlp_grad.argtypes = [P, P, P, I64, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.bz_mlp_train_step.argtypes = [P, P, P, I64, D, ctypes.POINTER(ctypes.c_double), P]
+    lib.bz_mlp_features.argtypes = [P, P, P, P, D, P, I64, P]
+    lib.bz_cell_fixed_point_learned.argtypes = [P, P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
     lib.bz_profile_enable.argtypes = [P, ctypes.c_int]
     lib.bz_profile_get.argtypes = [P, ctypes.POINTER(bz_profile_info)]
     for name in EXPORTED:
-        if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes"):
+        if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes", "bz_mlp_destroy",
+                        "bz_mlp_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,7 +230,7 @@ class Context:
     def _stats_tensor(B, device):
         import torch
 
-        return torch.zeros((B, 3), dtype=torch.float64, device=device)  # 24 bytes per cell
+        return torch.zeros((B, 4), dtype=torch.float64, device=device)  # 32 bytes per cell
 
     @staticmethod
     def decode_stats(t):
@@ -244,6 +263,28 @@ class Context:
                                           ctypes.byref(o), _ptr(stats), _stream())
         self._check(st, "bz_cell_fixed_point")
         return g, stats
+
+    def cell_fixed_point_learned(self, mlp, f_old, inflow_r, eps, dx, mode="pfp", tol=1e-8, max_iter=100,
+                                 fixed_iters=0, out=None):
+        import torch
+
+        B = self._field(f_old, "f_old")
+        g = torch.empty_like(f_old) if out is None else out
+        stats = self._stats_tensor(B, f_old.device)
+        o = self._opts(mode, tol, max_iter, fixed_iters)
+        st = self.lib.bz_cell_fixed_point_learned(self.h, mlp.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx),
+                                                  _ptr(g), B, ctypes.byref(o), _ptr(stats), _stream())
+        self._check(st, "bz_cell_fixed_point_learned")
+        return g, stats
+
+    def features(self, inflow_r, theta, eps, dx):
+        import torch
+
+        B = self._field(inflow_r, "inflow_r")
+        X = torch.empty((B, self.K + 6), dtype=torch.float32, device=inflow_r.device)
+        self._check(self.lib.bz_mlp_features(self.h, _ptr(inflow_r), _ptr(theta), _ptr(eps), float(dx), _ptr(X), B,
+                                             _stream()), "bz_mlp_features")
+        return X
 
     def profile_enable(self, on: bool = True):
         self._check(self.lib.bz_profile_enable(self.h, 1 if on else 0), "bz_profile_enable")
@@ -321,3 +362,67 @@ class Slab:
         self.ctx._check(self.ctx.lib.bz_multigrid_vcycle(self.ctx.h, self.h, ctypes.byref(o), n_cycles, res,
                                                          ctypes.byref(st), _stream()), "bz_multigrid_vcycle")
         return list(res), self._stats(st)
+
+
+class MLP:
+    """The warm-start network (bz_mlp): FP32 parameters on the device."""
+
+    def __init__(self, ctx: Context, n_in: int, hidden: int, n_out: int, seed: int = 0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.bz_mlp_create(ctx.h, n_in, hidden, n_out, seed, ctypes.byref(h)), "bz_mlp_create")
+        self.h = h
+        self.n_in, self.hidden, self.n_out = n_in, hidden, n_out
+        self.n_params = int(ctx.lib.bz_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.bz_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+
+        buf = np.empty(self.n_params, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.bz_mlp_get_params(self.h, buf.ctypes.data, self.n_params), "bz_mlp_get_params")
+        return buf
+
+    def set_params(self, p):
+        import numpy as np
+
+        buf = np.ascontiguousarray(p, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.bz_mlp_set_params(self.h, buf.ctypes.data, self.n_params), "bz_mlp_set_params")
+
+    def set_output_scale(self, s: float):
+        self.ctx._check(self.ctx.lib.bz_mlp_set_output_scale(self.h, float(s)), "bz_mlp_set_output_scale")
+
+    def forward(self, X, bf16: bool = False):
+        import torch
+
+        B = X.shape[0]
+        Y = torch.empty((B, self.n_out), dtype=torch.float32, device=X.device)
+        self.ctx._check(self.ctx.lib.bz_mlp_forward(self.h, _ptr(X), _ptr(Y), B, 1 if bf16 else 0, _stream()),
+                        "bz_mlp_forward")
+        return Y
+
+    def grad(self, X, T):
+        import torch
+
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx.lib.bz_mlp_grad(self.h, _ptr(X), _ptr(T), X.shape[0], _ptr(g), ctypes.byref(loss),
+                                                 _stream()), "bz_mlp_grad")
+        return loss.value, g
+
+    def train_step(self, X, T, lr: float, want_loss: bool = False):
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx.lib.bz_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], float(lr),
+                                                       ctypes.byref(loss) if want_loss else None, _stream()),
+                        "bz_mlp_train_step")
+        return loss.value if want_loss else None

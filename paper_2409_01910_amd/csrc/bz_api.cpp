@@ -214,4 +214,35 @@ bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* in
   return s;
 }
 
+bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_old, const double* inflow_r,
+                                      const double* eps, double dx, double* g, int64_t batch,
+                                      const bz_solve_opts* opts, bz_cell_stats* stats, void* stream) {
+  if (!ctx || !mlp) return BZ_EINVAL;
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  bz_status s = check_opts(ctx, opts);
+  if (s != BZ_OK) return s;
+  if (!(dx > 0) || !std::isfinite(dx)) return set_err(ctx, BZ_EINVAL, "dx must be > 0");
+  if (batch == 0) return BZ_OK;
+  if (!f_old || !inflow_r || !eps || !g) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (g == f_old) return set_err(ctx, BZ_EINVAL, "g must not alias f_old");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t K = (size_t)ctx->K;
+  double* buf = nullptr;
+  const size_t bytes = (size_t)batch * (3 * K + 6) * sizeof(double);
+  hipError_t e = hipMallocAsync((void**)&buf, bytes, st);
+  if (e != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
+  double* Q = buf;
+  double* r = Q + batch * K;
+  double* g0l = r + batch * K;
+  double* theta = g0l + batch * K;
+  double* nu = theta + batch * 5;
+  s = bz::eval_q(ctx, f_old, Q, batch, true, theta, st);
+  if (s == BZ_OK) s = bz::penalty_rhs(ctx, f_old, Q, theta, inflow_r, eps, r, nu, batch, st);
+  if (s == BZ_OK) s = bz::learned_guess(ctx, mlp, inflow_r, theta, eps, dx, g0l, batch, st);
+  if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, f_old, g, batch, opts, stats, st, g0l);
+  (void)hipFreeAsync(buf, st);
+  return s;
+}
+
 }  // extern "C"

@@ -77,11 +77,13 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
                                                              const double* __restrict__ eps, double dx,
                                                              const double* g0, double* g, SolveArgs opt,
                                                              bz_cell_stats* __restrict__ stats,
-                                                             const double* __restrict__ nodes, double w) {
+                                                             const double* __restrict__ nodes, double w,
+                                                             const double* __restrict__ g0b) {
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
   RPlain rf{r + (size_t)b * K};
-  const SolveOut o = solve_cell_block<N>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dx, opt, nodes, w);
+  const SolveOut o = solve_cell_block<N>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dx, opt, nodes, w,
+                                         g0b ? g0b + (size_t)b * K : nullptr);
   if (stats && threadIdx.x == 0) {
     bz_cell_stats st;
     st.iterations = o.iterations;
@@ -89,6 +91,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
     st.newton_fail = o.newton_fail;
     st.status = o.status;
     st.residual = o.residual;
+    st.learned = o.used_b;
+    st.reserved = 0;
     stats[b] = st;
   }
 }
@@ -157,11 +161,12 @@ bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int
 }
 
 bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
-                     double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st) {
+                     double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
+                     const double* g0b) {
   if (batch == 0) return BZ_OK;
   SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters};
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_cell_solve<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, r,
-                                           nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w));
+                                           nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

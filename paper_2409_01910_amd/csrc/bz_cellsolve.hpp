@@ -27,6 +27,7 @@ struct SolveArgs {
 };
 
 struct SolveOut {
+  int used_b;  // 1 if the second initial guess was kept
   int iterations;
   int fallback;
   int newton_fail;
@@ -35,13 +36,18 @@ struct SolveOut {
 };
 
 // Block of kCellThreads threads.  rf(k) returns r at node k; g0 and g may alias
-// (g0 is read in the first pass only, before the final write).
+// (g0 is read in the first passes only, before the final write).  With g0b
+// non-null the visit keeps whichever of g0 and g0b has the smaller initial
+// residual of eq. inner_eqn (used by the learned warm start).
 template <int N, typename RF>
 __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double* g0, double* g, double lam, double dx,
-                                                     const SolveArgs& opt, const double* nodes, double w) {
+                                                     const SolveArgs& opt, const double* nodes, double w,
+                                                     const double* g0b = nullptr) {
   constexpr int K = N * N * N;
   const double inv_dx = 1.0 / dx;
-  __shared__ double s_red[25 * (kCellThreads / 64)];
+  __shared__ double s_red[35 * (kCellThreads / 64)];
+  __shared__ double s_Ea[3][N], s_Eb[3][N];  // axis factors of M[g0], M[g0b]
+  __shared__ double s_ea[2];
   __shared__ double s_nodes[N];
   __shared__ double s_Et[3][N], s_Ee[3][N];  // axis factors of M_theta and M_eta
   __shared__ double s_th[5], s_eta[5];
@@ -50,16 +56,17 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
   if (threadIdx.x < 4) s_flags[threadIdx.x] = 0;
   __syncthreads();
-  // pass 1: fixed moment vectors of r and the moments of g0
-  double acc[25];
+  // pass 1: fixed moment vectors of r and the moments of g0 (and g0b)
+  double acc[35];
 #pragma unroll
-  for (int i = 0; i < 25; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 35; ++i) acc[i] = 0.0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double v0 = s_nodes[k / (N * N)], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
     const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
     const double c = fabs(v0) * inv_dx, Dinv = 1.0 / (c + lam);
     const double rk = rf(k), gk = g0[k];
     const double t0 = rk, t1 = rk * Dinv, t2 = c * rk * Dinv, t3 = gk, t4 = c * gk;
+    const double gb = g0b ? g0b[k] : 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       acc[i] += phi[i] * t0;
@@ -67,9 +74,15 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
       acc[10 + i] += phi[i] * t2;
       acc[15 + i] += phi[i] * t3;
       acc[20 + i] += phi[i] * t4;
+      acc[25 + i] += phi[i] * gb;
+      acc[30 + i] += phi[i] * c * gb;
     }
   }
-  block_sum<25>(acc, s_red);
+  if (g0b) {
+    block_sum<35>(acc, s_red);
+  } else {
+    block_sum<25>(*reinterpret_cast<double(*)[25]>(acc), s_red);
+  }
   double R0[5], R1[5], R2[5], cg[5], th[5], eta[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -80,6 +93,8 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   }
   bool fallback = opt.mode == 1;
   int newton_fail = 0;
+  int used_b = 0;
+  double eta_b[5];
   if (threadIdx.x < 64) {
     double mg[5];
 #pragma unroll
@@ -87,6 +102,53 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
     theta_from_moments(mg, w, eta);
     AxisW aw{W_ONE, inv_dx, lam};
     if (newton_gauss(s_nodes, N, w, mg, eta, aw, 1e-13, 60) < 0) newton_fail++;
+    if (g0b) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) mg[i] = w * acc[25 + i];
+      theta_from_moments(mg, w, eta_b);
+      if (newton_gauss(s_nodes, N, w, mg, eta_b, aw, 1e-13, 60) < 0) newton_fail++;
+      const int lane = threadIdx.x;
+      if (lane < N) {
+        const double x = s_nodes[lane];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          s_Ea[a][lane] = exp(eta[1 + a] * x - eta[4] * x * x);
+          s_Eb[a][lane] = exp(eta_b[1 + a] * x - eta_b[4] * x * x);
+        }
+      }
+      if (lane == 0) {
+        s_ea[0] = exp(eta[0]);
+        s_ea[1] = exp(eta_b[0]);
+      }
+    }
+  }
+  if (g0b) {
+    // pass 2: initial residuals |c g + r - lambda (M[g] - g)| of both guesses
+    __syncthreads();
+    double part[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+      const double c = fabs(s_nodes[a0]) * inv_dx;
+      const double rk = rf(k), ga = g0[k], gb = g0b[k];
+      const double Ma = s_ea[0] * s_Ea[0][a0] * s_Ea[1][a1] * s_Ea[2][a2];
+      const double Mb = s_ea[1] * s_Eb[0][a0] * s_Eb[1][a1] * s_Eb[2][a2];
+      const double ra = c * ga + rk - lam * (Ma - ga), rb = c * gb + rk - lam * (Mb - gb);
+      part[0] += ra * ra;
+      part[1] += rb * rb;
+    }
+    block_sum<2>(part, s_red);
+    if (part[1] < part[0]) {
+      used_b = 1;
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          eta[i] = eta_b[i];
+          cg[i] = w * acc[30 + i];
+        }
+      }
+    }
+  }
+  if (threadIdx.x < 64) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) th[i] = eta[i];
   }
@@ -182,6 +244,7 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   if (bad) s_flags[2] = 1;
   __syncthreads();
   SolveOut out;
+  out.used_b = used_b;
   out.iterations = k_done;
   out.fallback = s_flags[0];
   out.newton_fail = s_flags[1];

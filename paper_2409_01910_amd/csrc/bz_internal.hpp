@@ -75,7 +75,11 @@ size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected);
 bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,
                      hipStream_t st);
 bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
-                     double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st);
+                     double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
+                     const double* g0b = nullptr);
+// learned initial guesses g0 [batch][K] (bz_mlp.hip)
+bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const double* theta, const double* eps,
+                        double dx, double* g0, int64_t batch, hipStream_t st);
 // r = inflow - (Q - nu (M_theta - f)) / eps, nu = 4 pi rho(theta); writes nu
 bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const double* theta, const double* inflow,
                       const double* eps, double* r, double* nu, int64_t batch, hipStream_t st);

@@ -100,3 +100,58 @@ def RH_states(mach: float, gas_gamma: float = 5.0 / 3.0):
     T_ratio = (2.0 * g * m2 - (g - 1.0)) * ((g - 1.0) * m2 + 2.0) / ((g + 1.0) ** 2 * m2)
     u1 = mach * np.sqrt(g)
     return (1.0, u1, 1.0), (rho_ratio, u1 / rho_ratio, T_ratio)
+
+
+def _maxw_grid(rho, u0, T, N, L, d=3):
+    x = grid_nodes(N, L)
+    fac = [np.exp(-((x - (u0 if a == 0 else 0.0)) ** 2) / (2.0 * T)) for a in range(d)]
+    prod = fac[0]
+    for a in range(1, d):
+        prod = np.multiply.outer(prod, fac[a])
+    return (rho * (2.0 * np.pi * T) ** (-d / 2.0) * prod).reshape(-1)
+
+
+def warmstart_cells(n_inst: int, cells_per_inst: int, N: int, L: float, seed: int = 7, start: int = 0):
+    """Cell states of the two families used to train and test the learned warm
+    start: normal-shock profiles (Mach ~ U(2, 4), Rankine-Hugoniot end states,
+    velocities centred on the mean of the two bulk speeds, a smooth blend of
+    the two Maxwellians across a width delta ~ U(0.5, 2)) for even instance
+    indices, and heat-slab profiles (T_L = 1, T_R ~ U(1.5, 2.5), rho ~ 1/T, a
+    heat-flux perturbation of amplitude ~ eps) for odd ones.  eps is
+    log-uniform in [0.005, 1] per instance.  Returns (f_left, f_old, f_right,
+    eps) with shapes [n_inst * cells_per_inst, N^3] and [n_inst * cells_per_inst]."""
+    K = N ** 3
+    n = n_inst * cells_per_inst
+    fl, fo, fr = np.empty((n, K)), np.empty((n, K)), np.empty((n, K))
+    eps = np.empty(n)
+    x = grid_nodes(N, L)
+    v1 = np.repeat(x, N * N)
+    v2 = (np.add.outer(np.add.outer(x * x, x * x), x * x)).reshape(-1)
+    for i in range(n_inst):
+        rng = np.random.default_rng([seed, start + i])
+        e = float(np.exp(rng.uniform(np.log(0.005), np.log(1.0))))
+        if (start + i) % 2 == 0:
+            mach = float(rng.uniform(2.0, 4.0))
+            (r1, u1, T1), (r2, u2, T2) = RH_states(mach)
+            ub = 0.5 * (u1 + u2)
+            delta = float(rng.uniform(0.5, 2.0))
+            M1 = _maxw_grid(r1, u1 - ub, T1, N, L)
+            M2 = _maxw_grid(r2, u2 - ub, T2, N, L)
+            h = delta / 4.0
+            for c in range(cells_per_inst):
+                xc = float(rng.uniform(-3.0 * delta, 3.0 * delta))
+                for arr, xx in ((fl, xc - h), (fo, xc), (fr, xc + h)):
+                    wgt = 1.0 / (1.0 + np.exp(-xx / delta))
+                    arr[i * cells_per_inst + c] = (1.0 - wgt) * M1 + wgt * M2
+        else:
+            TR = float(rng.uniform(1.5, 2.5))
+            a = min(e, 0.3) * (TR - 1.0) * 0.5
+            for c in range(cells_per_inst):
+                xc = float(rng.uniform(0.05, 0.95))
+                for arr, xx in ((fl, xc - 1.0 / 32), (fo, xc), (fr, xc + 1.0 / 32)):
+                    T = 1.0 + (TR - 1.0) * xx
+                    M = _maxw_grid(1.0 / T, 0.0, T, N, L)
+                    pert = 1.0 + a * (v1 / np.sqrt(T)) * (v2 / (2.0 * T) - 2.5)
+                    arr[i * cells_per_inst + c] = np.maximum(M * pert, 0.0)
+        eps[i * cells_per_inst:(i + 1) * cells_per_inst] = e
+    return fl, fo, fr, eps
