@@ -43,6 +43,26 @@ def make_inputs(batch, seed=0):
     return f, eps
 
 
+def traffic_per_launch(precision, total_cell_nodes, launches):
+    """HBM bytes per pair-kernel launch from the committed counter profile, or
+    None when that profile was taken on a different kernel source or precision."""
+    import hashlib
+
+    if precision != "fp64" or launches == 0:
+        return None
+    path = os.path.join(ROOT, "profiles", "k_pairs32_zstage_traffic_fp64.md")
+    src = os.path.join(ROOT, "paper_2409_01910_amd", "csrc", "bz_q.hip")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("source_sha256", "").strip() != sha:
+            return None
+        per = float(kv["pairs_fetch_bytes_per_cell_node"]) + float(kv["pairs_write_bytes_per_cell_node"])
+    except (OSError, KeyError, ValueError):
+        return None
+    return per * total_cell_nodes / launches
+
+
 def cpu_baseline(f_np, eps_np, n_cells=2):
     """The oracle, as it stands, on the same step for a bounded sample of cells."""
     import numpy as np
@@ -77,6 +97,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--gamma", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -89,8 +110,6 @@ def main():
     import paper_2409_01910_amd as bz
 
     dev = torch.device("cuda:0")
-    prec = bz.BZ_FP64 if args.precision == "fp64" else bz.BZ_FP32
-    ctx = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=args.gamma, precision=prec)
     print(f"# generating {args.batch} cells", file=sys.stderr, flush=True)
     f_np, eps_np = make_inputs(args.batch)
     f = torch.from_numpy(f_np).to(dev)
@@ -104,29 +123,41 @@ def main():
     g = torch.empty_like(f)
     torch.cuda.synchronize()
 
-    def step():
-        return ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g)
+    def measure(precision):
+        prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
+        ctx = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=args.gamma, precision=prec)
 
-    for i in range(args.warmup):
-        step()
+        def step():
+            return ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g)
+
+        for i in range(args.warmup):
+            step()
+            torch.cuda.synchronize()
+            print(f"# {precision} warmup {i} done", file=sys.stderr, flush=True)
+        ctx.profile_enable(True)
         torch.cuda.synchronize()
-        print(f"# warmup {i} done", file=sys.stderr, flush=True)
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = None
-    for i in range(args.steps):
-        _, stats = step()
+        t0 = time.perf_counter()
+        stats = None
+        for i in range(args.steps):
+            _, stats = step()
+            torch.cuda.synchronize()
+            print(f"# {precision} step {i} done {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        print(f"# step {i} done {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_get()
-    ctx.profile_enable(False)
-    st = ctx.decode_stats(stats)
-    value = args.steps * args.batch / elapsed
-    dt = "f64" if prec == bz.BZ_FP64 else "f32"
-    achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
+        elapsed = time.perf_counter() - t0
+        prof = ctx.profile_get()
+        ctx.profile_enable(False)
+        ctx.close()
+        dt = "f64" if prec == bz.BZ_FP64 else "f32"
+        achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                "frac": achieved / VALU_PEAK_TFLOPS[dt],
+                "traffic": traffic_per_launch(precision, args.steps * args.batch * N_RHO, prof["launches"]),
+                "kernel": "k_pairs32 (direction-pair transforms)", "launches": prof["launches"],
+                "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
+                "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
+        return args.steps * args.batch / elapsed, elapsed, dt, roof, ctx.decode_stats(stats)
+
+    value, elapsed, dt, roof, st = measure(args.precision)
     line = {
         "metric": "Q evals/s at 32^3 velocity grid; time-to-residual 1e-8, learned+FP32 vs plain",
         "value": value,
@@ -144,14 +175,13 @@ def main():
                                f"32^3 velocities on [-8,8]^3, M=128 (8x16), 16 radial nodes, gamma={args.gamma}",
                    "cells": args.batch, "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "gamma": args.gamma,
                    "spectral_precision": args.precision},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                     "frac": achieved / VALU_PEAK_TFLOPS[dt], "traffic": None,
-                     "kernel": "k_pairs (direction-pair transforms)", "launches": prof["launches"],
-                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
-                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed},
+        "roofline": roof,
         "inner": {"mean_iterations": float(st["iterations"].mean()), "max_iterations": int(st["iterations"].max()),
                   "fallbacks": int(st["fallback"].sum()), "unconverged": int((st["status"] != 0).sum())},
     }
+    if args.precision == "fp64" and not args.no_fp32:
+        v32, e32, _, r32, _ = measure("fp32")
+        line["fp32_spectral"] = {"value": v32, "ms_per_step": e32 / args.steps * 1e3, "roofline": r32}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(f_np, eps_np)

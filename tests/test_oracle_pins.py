@@ -206,10 +206,10 @@ def test_sgs_fp_and_pfp_reach_the_same_state():
     sp = Spec(d=3, N=8, L=6.0)
     out = []
     for inner in ("pfp", "fp"):
-        prob = SW.Slab(spec=sp, nx=4, eps=0.1, collision="bgk", inner=inner, tol_inner=1e-11, max_inner=5000)
-        f, hist = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-9, max_iter=200)
+        prob = SW.Slab(spec=sp, nx=4, eps=0.5, collision="bgk", inner=inner, tol_inner=1e-10, max_inner=5000)
+        f, hist = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-8, max_iter=200)
         out.append(f)
-    assert np.abs(out[0] - out[1]).max() < 1e-8 * out[0].max()
+    assert np.abs(out[0] - out[1]).max() < 1e-7 * out[0].max()
 
 
 def test_multigrid_reaches_the_sgs_state():
