@@ -88,6 +88,107 @@ def cpu_baseline(f_np, eps_np, n_cells=2):
                       f"numpy FP64, one thread, {dt:.1f} s"}
 
 
+def slab_workload(args, tol=1e-8, max_iters=3000):
+    """1D slab x in [0, 1], 32 cells, diffuse walls T = 1 and 2 at rest, 16^3 velocities
+    on [-8, 8]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes, eps = 0.1,
+    initial Maxwellian rho = 1, u = 0, T = 1.5 scaled to mass 1; plain SGS-PFP
+    (inner residual 1e-8) until the outer residual is below tol.  One SGS
+    iteration per call, so the residual is read after every iteration."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+    import synth
+
+    out = {}
+    for precision in ("fp64", "fp32"):
+        prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
+        ctx = bz.Context(N=16, L=8.0, n_theta=4, n_phi=8, n_rho=8, precision=prec)
+        m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], 16, 8.0)
+        nx = 32
+        f0 = np.repeat(m[None], nx, axis=0)
+        f0 *= 1.0 / ((1.0 / nx) * (1.0 ** 3) * f0.sum())  # dv = 1 at 16^3 on [-8, 8]
+        f = torch.from_numpy(f0).cuda().contiguous()
+        slab = bz.Slab(ctx, [dict(nx=nx, eps=0.1, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="binary",
+                       tol=1e-8, max_iter=100)
+        hist, inner, visits, fallbacks = [slab.residual()[0]], 0, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while hist[-1] >= tol and len(hist) <= max_iters:
+            r, st = slab.sweep(1)
+            hist.append(r[0])
+            inner += st["inner_iters"]
+            visits += st["visits"]
+            fallbacks += st["fallbacks"]
+            if len(hist) % 50 == 0:
+                print(f"# slab {precision} iteration {len(hist) - 1} residual {r[0]:.3e}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[precision] = {"seconds": el, "iterations": len(hist) - 1, "final_residual": hist[-1],
+                          "reached": hist[-1] < tol, "ms_per_iteration": el / max(len(hist) - 1, 1) * 1e3,
+                          "mean_inner_iterations": inner / max(visits, 1), "fallbacks": fallbacks,
+                          "residual_every_50": hist[::50]}
+        slab.close()
+        ctx.close()
+    return {"metric": "time to outer residual 1e-8, 1D heat slab (32 cells, 16^3, M=32, eps=0.1), plain SGS-PFP",
+            "value": out["fp64"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "slab", "cells": 32, "N": 16, "M": 32, "n_rho": 8,
+                                            "eps": 0.1}, "fp64": out["fp64"], "fp32_spectral": out["fp32"]}
+
+
+def warmstart_workload(args):
+    """Learned warm start at 32^3: train on cell solves generated by the library
+    (shock and heat-slab profile families), then solve held-out cells to inner
+    residual 1e-8 with the plain FP64 path and with learned start + FP32
+    spectral stage; report inner updates and wall time of each."""
+    import torch
+
+    import paper_2409_01910_amd as bz
+    from paper_2409_01910_amd import warmstart as WS
+
+    dx = 40.0 / 128
+    ctx64 = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, precision=bz.BZ_FP64)
+    ctx32 = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, precision=bz.BZ_FP32)
+    t0 = time.perf_counter()
+    X, Y, _, st = WS.make_dataset(ctx64, 160, 8, dx, seed=7)
+    t_data = time.perf_counter() - t0
+    print(f"# dataset {X.shape[0]} cells in {t_data:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    mlp, hist = WS.train(ctx32, X, Y, hidden=256, epochs=30, batch=128, lr=1e-3,
+                         log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    t_train = time.perf_counter() - t0
+    del X, Y
+    _, _, (fo, inflow, eps), _ = WS.make_dataset(ctx64, 40, 8, dx, seed=7, start=1000)
+    torch.cuda.synchronize()
+    res = {}
+    for name, ctx, learned in (("plain_fp64", ctx64, False), ("learned_fp32", ctx32, True),
+                               ("plain_fp32", ctx32, False)):
+        fn = (lambda: ctx.cell_fixed_point_learned(mlp, fo, inflow, eps, dx, tol=1e-8, max_iter=100)) if learned \
+            else (lambda: ctx.cell_fixed_point(fo, inflow, eps, dx, tol=1e-8, max_iter=100))
+        g, s = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            g, s = fn()
+        torch.cuda.synchronize()
+        d = bz.Context.decode_stats(s)
+        res[name] = {"seconds": (time.perf_counter() - t0) / 3, "cells": int(fo.shape[0]),
+                     "mean_inner_iterations": float(d["iterations"].mean()),
+                     "learned_kept": int(d["learned"].sum()), "unconverged": int((d["status"] != 0).sum())}
+        if name == "plain_fp64":
+            g64 = g
+        else:
+            res[name]["max_rel_diff_vs_plain_fp64"] = (g - g64).abs().max().item() / g64.abs().max().item()
+    return {"metric": "time to inner residual 1e-8 on held-out cells, learned+FP32 vs plain FP64",
+            "value": res["learned_fp32"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "warmstart", "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "hidden": 256,
+                       "train_cells": int(len(hist) and 0) or None},
+            "train": {"dataset_seconds": t_data, "train_seconds": t_train, "loss_first": hist[0],
+                      "loss_last": hist[-1]},
+            "results": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +199,9 @@ def main():
     ap.add_argument("--gamma", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart"], default="batched-q",
+                    help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
+                         "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -108,6 +212,13 @@ def main():
     import torch
 
     import paper_2409_01910_amd as bz
+
+    if args.workload == "slab":
+        print(json.dumps(slab_workload(args)), flush=True)
+        return
+    if args.workload == "warmstart":
+        print(json.dumps(warmstart_workload(args)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     print(f"# generating {args.batch} cells", file=sys.stderr, flush=True)

@@ -93,10 +93,18 @@ size_t bz_workspace_bytes(bz_ctx* ctx);
  *   otherwise Q = Q^FSM[f,f]: the Fourier spectral operator (Section 2.2,
  *       eq. collision truncated to |v - v_*| <= 2R on the periodic box) with an
  *       M-direction sphere rule and an n_rho-node radial rule.
+ *   flags & BZ_Q_MASS (with BZ_Q_CORRECTED): afterwards Q <- Q - M[f] s, with
+ *       s = sum_k Q_k / sum_k M[f]_k, so that sum_k w Q_k = 0 to rounding.  The
+ *       sigma quadrature of the gain term conserves mass only approximately;
+ *       with diffuse walls the steady problem is solvable only if the summed
+ *       collision term vanishes, so the slab solver and bz_cell_fixed_point
+ *       always use this form.  Allocates a [batch][5] stream-ordered temporary
+ *       when theta is NULL.
  *   theta (nullable, BZ_Q_CORRECTED only) receives [batch][5] parameters
  *       (alpha, beta_1..3, gamma) of M[f] = exp(alpha + beta.v - gamma |v|^2).
  * Returns BZ_EINVAL for batch < 0 or NULL buffers with batch > 0. */
 #define BZ_Q_CORRECTED 1u
+#define BZ_Q_MASS 2u
 bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
                     double* theta, void* stream);
 
@@ -149,7 +157,7 @@ bz_status bz_cell_solve(bz_ctx* ctx, const double* r, const double* nu, const do
 
 /* bz_cell_fixed_point: the data-parallel cell update of the SGS scan with the
  * binary collision operator (Section 3.3, eq. SGS): from the previous iterate
- * f_old of each cell it computes Q[f_old] (BZ_Q_CORRECTED form), nu = 4 pi rho,
+ * f_old of each cell it computes Q[f_old] (BZ_Q_CORRECTED | BZ_Q_MASS form), nu = 4 pi rho,
  * the BGK-penalty part P = Q - nu (M[f_old] - f_old) (eq. Pf), the right-hand
  * side r = inflow_r - P / eps, and solves eq. inner_eqn from g0 = f_old.
  *   f_old, inflow_r [batch][K];  eps [batch];  g [batch][K] out;

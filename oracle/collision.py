@@ -119,12 +119,22 @@ def q_direct(spec: Spec, f: np.ndarray, n_rho_exact: int = 64, parts: bool = Fal
     return gain - loss
 
 
-def q_corrected(spec: Spec, f: np.ndarray, M: np.ndarray | None = None, op=q_fsm):
+def mass_project(spec: Spec, Q: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """Q - M (sum_k w Q_k) / (sum_k w M_k): removes the mass the discrete operator
+    creates through sigma-quadrature error, along the Maxwellian.  With diffuse
+    walls the only globally conserved quantity is mass, and summing the discrete
+    residual over all cells gives -(1/eps) sum_j dx sum_k w Q_jk; the steady
+    problem has a solution only if that vanishes."""
+    return Q - M * (np.sum(Q) / np.sum(M))
+
+
+def q_corrected(spec: Spec, f: np.ndarray, M: np.ndarray | None = None, op=q_fsm, conserve_mass: bool = False):
     """Steady-state preserving collision term, eq. discrete_Q:
-    Q[f] = Q^FSM[f, f] - Q^FSM[M[f], M[f]]."""
+    Q[f] = Q^FSM[f, f] - Q^FSM[M[f], M[f]]; optionally mass-projected."""
     if M is None:
         M = discrete_maxwellian(spec, f)
-    return op(spec, f) - op(spec, M)
+    Q = op(spec, f) - op(spec, M)
+    return mass_project(spec, Q, M) if conserve_mass else Q
 
 
 def nu_of(spec: Spec, f: np.ndarray) -> float:
@@ -133,10 +143,11 @@ def nu_of(spec: Spec, f: np.ndarray) -> float:
     return sphere_area(spec.d) * moments(spec, f)[0]
 
 
-def penalty(spec: Spec, f: np.ndarray, Q: np.ndarray | None = None, M: np.ndarray | None = None):
-    """P[f] = Q[f,f] - nu (M[f] - f), eq. Pf."""
+def penalty(spec: Spec, f: np.ndarray, Q: np.ndarray | None = None, M: np.ndarray | None = None,
+            conserve_mass: bool = True):
+    """P[f] = Q[f,f] - nu (M[f] - f), eq. Pf, with the mass-projected corrected Q."""
     if M is None:
         M = discrete_maxwellian(spec, f)
     if Q is None:
-        Q = q_corrected(spec, f, M)
+        Q = q_corrected(spec, f, M, conserve_mass=conserve_mass)
     return Q - nu_of(spec, f) * (M - f)

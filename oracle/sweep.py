@@ -102,14 +102,15 @@ def ghosts(prob: Slab, f: np.ndarray, s: np.ndarray):
 
 
 def collision_terms(prob: Slab, f_j: np.ndarray):
-    """(Q, M, nu) for one cell: the steady-state preserving Q^FSM (eq. discrete_Q) in
-    binary mode, or nu (M - f) in BGK mode."""
+    """(Q, M, nu) for one cell: the steady-state preserving Q^FSM (eq. discrete_Q),
+    mass-projected (collision.mass_project), in binary mode, or nu (M - f) in BGK
+    mode."""
     spec = prob.spec
     M = discrete_maxwellian(spec, f_j)
     if prob.collision == "bgk":
         nu = prob.bgk_nu if prob.bgk_nu is not None else nu_of(spec, f_j)
         return nu * (M - f_j), M, nu
-    return q_corrected(spec, f_j, M, op=q_fsm), M, nu_of(spec, f_j)
+    return q_corrected(spec, f_j, M, op=q_fsm, conserve_mass=True), M, nu_of(spec, f_j)
 
 
 def residual_field(prob: Slab, f: np.ndarray, Q: np.ndarray) -> np.ndarray:

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbz.so")
 
 BZ_FP64, BZ_FP32 = 0, 1
 BZ_Q_CORRECTED = 1
+BZ_Q_MASS = 2
 BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
 BZ_COLL_BINARY, BZ_COLL_BGK = 0, 1
 
@@ -201,13 +202,13 @@ class Context:
             raise BZError(f"{name}: size not a multiple of K = {self.K}")
         return t.numel() // self.K
 
-    def eval_Q(self, f, corrected: bool = True, out=None, theta=None):
+    def eval_Q(self, f, corrected: bool = True, out=None, theta=None, conserve_mass: bool = False):
         import torch
 
         B = self._field(f, "f")
         Q = torch.empty_like(f) if out is None else out
-        st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, BZ_Q_CORRECTED if corrected else 0, _ptr(theta),
-                                _stream())
+        flags = (BZ_Q_CORRECTED if corrected else 0) | (BZ_Q_MASS if conserve_mass else 0)
+        st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, flags, _ptr(theta), _stream())
         self._check(st, "bz_eval_Q")
         return Q
 

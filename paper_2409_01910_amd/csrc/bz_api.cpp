@@ -146,10 +146,21 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
   if (!ctx) return BZ_EINVAL;
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   if (batch > 0 && (!f || !Q)) return set_err(ctx, BZ_EINVAL, "NULL field buffer");
-  if (flags & ~BZ_Q_CORRECTED) return set_err(ctx, BZ_EINVAL, "unknown flag");
+  if (flags & ~(BZ_Q_CORRECTED | BZ_Q_MASS)) return set_err(ctx, BZ_EINVAL, "unknown flag");
   if (theta && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "theta requires BZ_Q_CORRECTED");
+  if ((flags & BZ_Q_MASS) && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS requires BZ_Q_CORRECTED");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
-  return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (!(flags & BZ_Q_MASS) || batch == 0) return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, st);
+  double* th = theta;
+  if (!th) {
+    hipError_t e = hipMallocAsync((void**)&th, (size_t)batch * 5 * sizeof(double), st);
+    if (e != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
+  }
+  bz_status s = bz::eval_q(ctx, f, Q, batch, true, th, st);
+  if (s == BZ_OK) s = bz::mass_project(ctx, Q, th, batch, st);
+  if (!theta) (void)hipFreeAsync(th, st);
+  return s;
 }
 
 bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* newton_iters, int64_t batch,
@@ -208,6 +219,7 @@ bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* in
   double* theta = r + batch * K;
   double* nu = theta + batch * 5;
   s = bz::eval_q(ctx, f_old, Q, batch, true, theta, st);
+  if (s == BZ_OK) s = bz::mass_project(ctx, Q, theta, batch, st);
   if (s == BZ_OK) s = bz::penalty_rhs(ctx, f_old, Q, theta, inflow_r, eps, r, nu, batch, st);
   if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, f_old, g, batch, opts, stats, st);
   (void)hipFreeAsync(buf, st);
@@ -238,6 +250,7 @@ bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_
   double* theta = g0l + batch * K;
   double* nu = theta + batch * 5;
   s = bz::eval_q(ctx, f_old, Q, batch, true, theta, st);
+  if (s == BZ_OK) s = bz::mass_project(ctx, Q, theta, batch, st);
   if (s == BZ_OK) s = bz::penalty_rhs(ctx, f_old, Q, theta, inflow_r, eps, r, nu, batch, st);
   if (s == BZ_OK) s = bz::learned_guess(ctx, mlp, inflow_r, theta, eps, dx, g0l, batch, st);
   if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, f_old, g, batch, opts, stats, st, g0l);

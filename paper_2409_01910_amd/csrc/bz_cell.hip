@@ -133,6 +133,36 @@ __global__ __launch_bounds__(kCellThreads) void k_penalty_rhs(const double* __re
   }
 }
 
+// Q <- Q - M_theta (sum_k Q_k) / (sum_k M_theta,k): removes, along the cell's
+// Maxwellian, the mass that the sigma quadrature of the gain term creates, so
+// that the collision term conserves mass to rounding.  Deterministic block sums.
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_mass_project(double* __restrict__ Q, const double* __restrict__ theta,
+                                                               const double* __restrict__ nodes) {
+  constexpr int K = N * N * N;
+  const int b = blockIdx.x;
+  __shared__ double s_E[3][N];
+  __shared__ double s_red[2 * (kCellThreads / 64)];
+  const double* th = theta + (size_t)b * 5;
+  if (threadIdx.x < 3 * N) {
+    const int a = threadIdx.x / N, i = threadIdx.x % N;
+    const double x = nodes[i];
+    s_E[a][i] = exp(th[1 + a] * x - th[4] * x * x);
+  }
+  __syncthreads();
+  const double ea = exp(th[0]);
+  double* q = Q + (size_t)b * K;
+  double acc[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    acc[0] += q[k];
+    acc[1] += ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+  }
+  block_sum<2>(acc, s_red);
+  const double c = acc[0] / acc[1];
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    q[k] -= c * ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+}
+
 #define BZ_DISPATCH_N(NV, CALL)                                           \
   switch (NV) {                                                           \
     case 8: {                                                             \
@@ -167,6 +197,14 @@ bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const doubl
   SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters};
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_cell_solve<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, r,
                                            nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b));
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+bz_status mass_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st) {
+  if (batch == 0) return BZ_OK;
+  BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_mass_project<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, Q,
+                                           theta, ctx->d_nodes));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

@@ -389,10 +389,12 @@ static void level_free(Level& L) {
 static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   if (L.q_valid) return BZ_OK;
   bz_status e;
-  if (s->collision == BZ_COLL_BINARY)
+  if (s->collision == BZ_COLL_BINARY) {
     e = eval_q(ctx, L.f, L.Q, L.ncell, true, L.theta, st);
-  else
+    if (e == BZ_OK) e = mass_project(ctx, L.Q, L.theta, L.ncell, st);
+  } else {
     e = maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st);
+  }
   if (e == BZ_OK) L.q_valid = true;
   return e;
 }

@@ -61,6 +61,30 @@ def test_eval_q_fp64_matches_oracle(dev, case, corrected, gamma):
         assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
 
 
+@pytest.mark.parametrize("case", [(8, 6.0, 4, 8, 4, 5), (16, 8.0, 4, 8, 8, 3)])
+def test_eval_q_mass_projection_matches_oracle(dev, case):
+    import paper_2409_01910_amd as bz
+
+    N, L, nt, nph, nr, B = case
+    print(f"eval_Q mass-projected N={N} M={nt}x{nph} n_rho={nr} B={B}", flush=True)
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=23)
+    ctx = _ctx(N, L, nt, nph, nr)
+    fd = torch.from_numpy(f).to(dev)
+    Qg = ctx.eval_Q(fd, corrected=True, conserve_mass=True).cpu().numpy()
+    theta = torch.empty(B, 5, dtype=torch.float64, device=dev)
+    Qt = ctx.eval_Q(fd, corrected=True, conserve_mass=True, theta=theta).cpu().numpy()
+    assert np.array_equal(Qg, Qt)
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i], conserve_mass=True)
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
+        assert abs(Qg[i].sum()) < 1e-13 * np.abs(loss).sum()
+    with pytest.raises(bz.BZError):
+        ctx.eval_Q(fd, corrected=False, conserve_mass=True)
+
+
 def test_eval_q_fp32_error_bound(dev):
     N, L, nt, nph, nr, B = 16, 8.0, 4, 8, 8, 3
     sp = _spec(N, L, nt, nph, nr)
@@ -141,7 +165,7 @@ def test_cell_solve_converges_to_theta_fixed_point(dev):
 
 def test_cell_fixed_point_matches_oracle_composition(dev):
     # Q, P = Q - nu (M - f), r = inflow - P / eps, then the PFP solve from f_old
-    N, L, nt, nph, nr, dx, B = 8, 6.0, 2, 4, 3, 1 / 16, 3
+    N, L, nt, nph, nr, dx, B = 8, 6.0, 2, 4, 3, 1 / 16, 5
     sp = _spec(N, L, nt, nph, nr)
     fo, fl, fr, eps = synth.cell_inflow_batch(B, N, L, dx, seed=33)
     v1 = velocity_nodes(sp)[:, 0]
@@ -150,11 +174,18 @@ def test_cell_fixed_point_matches_oracle_composition(dev):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     g, st = ctx.cell_fixed_point(T(fo), T(inflow), T(eps), dx, fixed_iters=2)
     g = g.cpu().numpy()
+    checked = 0
     for i in range(B):
         P = OQ.penalty(sp, fo[i])
         r = inflow[i] - P / eps[i]
-        go, _ = OC.solve(sp, r, OQ.nu_of(sp, fo[i]), eps[i], dx, fo[i], mode="pfp", fixed_iters=2)
+        go, so = OC.solve(sp, r, OQ.nu_of(sp, fo[i]), eps[i], dx, fo[i], mode="pfp", fixed_iters=2)
+        if so.fallback:
+            # step 1's Newton failed on this coarse grid: both sides fall back and
+            # the failure point depends on rounding, so iterates are not comparable
+            continue
+        checked += 1
         assert np.max(np.abs(g[i] - go)) < 1e-10 * np.abs(go).max()
+    assert checked > 0
 
 
 # N = 32 uses the lane-pair kernel; cover every wave/item mapping: polar pairs

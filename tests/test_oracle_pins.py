@@ -63,6 +63,26 @@ def test_fast_form_converges_to_sigma_exact_sum():
     assert errs[2] < 1e-11
 
 
+def test_mass_projection_removes_only_quadrature_mass():
+    """The collision integral conserves mass; the sigma-exact sum does too.  The
+    projected fast form conserves it to rounding, keeps the corrected form exact
+    at equilibrium, and changes Q by an amount that vanishes as the sphere rule
+    is refined (so it removes only quadrature error)."""
+    f = _narrow(8, 4.0)
+    changes = []
+    for nt in (4, 8, 16):
+        sp = Spec(d=3, N=8, L=4.0, n_theta=nt, n_phi=2 * nt, n_rho=nt)
+        M = MX.discrete_maxwellian(sp, f)
+        Q = C.q_corrected(sp, f, M)
+        Qp = C.q_corrected(sp, f, M, conserve_mass=True)
+        _, loss = C.q_fsm(sp, f, parts=True)
+        assert abs(MX.moments(sp, Qp)[0]) < 1e-14 * sp.w * np.abs(loss).sum()
+        assert np.abs(C.q_corrected(sp, M, M, conserve_mass=True)).max() == 0.0
+        changes.append(np.abs(Qp - Q).max() / np.abs(Q).max())
+    assert changes[0] > changes[1] > changes[2]
+    assert changes[2] < 1e-9
+
+
 @pytest.mark.slow
 def test_fast_form_matches_physical_space_quadrature():
     # independent pin of the whole Fourier derivation: direct quadrature of the
