@@ -88,52 +88,83 @@ def cpu_baseline(f_np, eps_np, n_cells=2):
                       f"numpy FP64, one thread, {dt:.1f} s"}
 
 
-def slab_workload(args, tol=1e-8, max_iters=3000):
-    """1D slab x in [0, 1], 32 cells, diffuse walls T = 1 and 2 at rest, 16^3 velocities
-    on [-8, 8]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes, eps = 0.1,
-    initial Maxwellian rho = 1, u = 0, T = 1.5 scaled to mass 1; plain SGS-PFP
-    (inner residual 1e-8) until the outer residual is below tol.  One SGS
-    iteration per call, so the residual is read after every iteration."""
+def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs"):
+    """Heat slab x in [0, 1], nx cells, diffuse walls T = 1 and 2 at rest, n^3
+    velocities on [-l, l]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes,
+    initial Maxwellian u = 0, T = 1.5 of total mass 1; SGS-PFP with inner
+    residual 1e-8, one SGS iteration (method "sgs") or one V-cycle (method "mg":
+    coarsest 4 cells, one pre- and one post-smoothing step) per call so that
+    the outer residual is read after every iteration.  plan = [(precision, switch_residual), ...]: run in
+    each precision until the residual is below its switch value (or stalls for
+    50 iterations), then continue from the same f in the next one."""
     import numpy as np
     import torch
 
     import paper_2409_01910_amd as bz
     import synth
 
-    out = {}
-    for precision in ("fp64", "fp32"):
+    m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+    f0 = np.repeat(m[None], nx, axis=0)
+    f0 *= 1.0 / ((1.0 / nx) * (2.0 * l / n) ** 3 * f0.sum())
+    f = torch.from_numpy(f0).cuda().contiguous()
+    hist, inner, visits, fallbacks, legs = [], 0, 0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for precision, switch in plan:
         prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
-        ctx = bz.Context(N=16, L=8.0, n_theta=4, n_phi=8, n_rho=8, precision=prec)
-        m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], 16, 8.0)
-        nx = 32
-        f0 = np.repeat(m[None], nx, axis=0)
-        f0 *= 1.0 / ((1.0 / nx) * (1.0 ** 3) * f0.sum())  # dv = 1 at 16^3 on [-8, 8]
-        f = torch.from_numpy(f0).cuda().contiguous()
-        slab = bz.Slab(ctx, [dict(nx=nx, eps=0.1, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="binary",
+        ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8, precision=prec)
+        slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="binary",
                        tol=1e-8, max_iter=100)
-        hist, inner, visits, fallbacks = [slab.residual()[0]], 0, 0, 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while hist[-1] >= tol and len(hist) <= max_iters:
-            r, st = slab.sweep(1)
+        if not hist:
+            hist.append(slab.residual()[0])
+        start = len(hist)
+        best, best_at = hist[-1], len(hist)
+        while hist[-1] >= switch and len(hist) <= max_iters and time.perf_counter() - t0 < max_seconds:
+            r, st = slab.sweep(1) if method == "sgs" else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
             hist.append(r[0])
             inner += st["inner_iters"]
             visits += st["visits"]
             fallbacks += st["fallbacks"]
+            if r[0] < 0.9 * best:
+                best, best_at = r[0], len(hist)
             if len(hist) % 50 == 0:
-                print(f"# slab {precision} iteration {len(hist) - 1} residual {r[0]:.3e}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[precision] = {"seconds": el, "iterations": len(hist) - 1, "final_residual": hist[-1],
-                          "reached": hist[-1] < tol, "ms_per_iteration": el / max(len(hist) - 1, 1) * 1e3,
-                          "mean_inner_iterations": inner / max(visits, 1), "fallbacks": fallbacks,
-                          "residual_every_50": hist[::50]}
+                print(f"# slab {nx} cells {n}^3 {method} {precision} iteration {len(hist) - 1} residual {r[0]:.3e}", file=sys.stderr,
+                      flush=True)
+            if switch > tol and len(hist) - best_at > 50:
+                break
+            if not np.isfinite(r[0]):
+                break
+        legs.append({"precision": precision, "iterations": len(hist) - start, "residual_at_end": hist[-1]})
         slab.close()
         ctx.close()
-    return {"metric": "time to outer residual 1e-8, 1D heat slab (32 cells, 16^3, M=32, eps=0.1), plain SGS-PFP",
-            "value": out["fp64"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
-            "data": "synthetic", "config": {"workload": "slab", "cells": 32, "N": 16, "M": 32, "n_rho": 8,
-                                            "eps": 0.1}, "fp64": out["fp64"], "fp32_spectral": out["fp32"]}
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"seconds": el, "iterations": len(hist) - 1, "final_residual": hist[-1], "reached": hist[-1] < tol,
+            "ms_per_iteration": el / max(len(hist) - 1, 1) * 1e3, "mean_inner_iterations": inner / max(visits, 1),
+            "fallbacks": fallbacks, "legs": legs, "residual_every_50": hist[::50]}
+
+
+def slab_workload(args, tol=1e-8):
+    """Time to outer residual 1e-8 on the heat slab: 16^3 velocities (dv = 1, the
+    small configuration) and 32^3 (dv = 0.5); plain FP64, and FP32 spectral
+    stage followed by FP64 once the FP32 residual stops falling."""
+    cases = {
+        "n16_fp64": lambda: _slab_run(16, 8.0, [("fp64", tol)], tol, 3000, 60.0),
+        "n32_fp64": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0),
+        "n32_fp32_then_fp64": lambda: _slab_run(32, 8.0, [("fp32", 1e-5), ("fp64", tol)], tol, 3000, 90.0),
+        "n32_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, method="mg"),
+        "n32_128cells_fp64": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0, nx=128),
+        "n32_128cells_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, nx=128, method="mg"),
+    }
+    names = list(cases) if args.slab_case == "all" else [args.slab_case]
+    out = {k: cases[k]() for k in names}
+    if "n32_fp64" not in out:
+        return {"workload": "slab", "runs": out}
+    return {"metric": "time to outer residual 1e-8, 1D heat slab (32 cells, 32^3 on [-8,8]^3, M=32, eps=0.1), "
+                      "plain SGS-PFP FP64",
+            "value": out["n32_fp64"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "slab", "cells": 32, "N": 32, "M": 32, "n_rho": 8,
+                                            "eps": 0.1}, "runs": out}
 
 
 def warmstart_workload(args):
@@ -199,6 +230,9 @@ def main():
     ap.add_argument("--gamma", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
+    ap.add_argument("--slab-case", default="all",
+                    choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_mg", "n32_128cells_fp64",
+                             "n32_128cells_mg"], help="with --workload slab: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8")
