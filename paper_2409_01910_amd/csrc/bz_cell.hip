@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
   RPlain rf{r + (size_t)b * K};
-  const SolveOut o = solve_cell_block<N>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dx, opt, nodes, w,
+  const SolveOut o = solve_cell_block<N, kCellThreads>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dx, opt, nodes, w,
                                          g0b ? g0b + (size_t)b * K : nullptr);
   if (stats && threadIdx.x == 0) {
     bz_cell_stats st;

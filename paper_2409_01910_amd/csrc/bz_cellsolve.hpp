@@ -9,7 +9,12 @@
 //   sum w phi c g^{k+1}        = lambda sum w phi c D^{-1} M_theta - R2,
 // with R0 = sum w phi r, R1 = sum w phi r / D, R2 = sum w phi c r / D fixed per
 // visit (c = |v_1|/dx).  The residual of eq. inner_eqn at g^{k+1} is
-// lambda |M_theta - M[g^{k+1}]|_{L2}, evaluated pointwise without memory traffic.
+// lambda |M_theta - M[g^{k+1}]|_{L2}; both Gaussians factorise over the axes, so
+// its square is a short sum of products of 1D sums (gauss_diff_norm2), and each
+// update costs O(N) work in one wave.  That sum can cancel when the two
+// parameter sets differ more than the sampled Gaussians do (coarse grids), so
+// whenever its rounding bound straddles the tolerance, and in fixed-count mode,
+// the block evaluates the norm pointwise instead.
 #pragma once
 
 #include "bz_common.hpp"
@@ -17,7 +22,66 @@
 
 namespace bz {
 
-constexpr int kCellThreads = 256;
+constexpr int kCellThreads = 256;   // batched cell solve: one work-group per cell
+constexpr int kChainThreads = 256;  // sequential scan (one wave per SIMD: the update loop needs > 256 registers)
+
+// |e^a E_0 E_1 E_2 - e^a' E'_0 E'_1 E'_2|^2 summed over the grid (no weight), for
+// E_a(x) = exp(th[1+a] x - th[4] x^2) and E'_a from et.  The difference is
+// telescoped into four separable terms,
+//   (e^a - e^a') E0 E1 E2 + e^a' (E0 - E0') E1 E2 + e^a' E0' (E1 - E1') E2
+//   + e^a' E0' E1' (E2 - E2'),
+// with the differences formed through expm1, so that no term cancels against
+// another when the two Gaussians are close.  Their 16 inner products are
+// products of three 1D sums of pairwise products of {E, E', E - E'}.
+// Returns the squared norm and, in bound, the sum of the magnitudes of the 16
+// products (the scale of its rounding error).
+// One wave; lane i < N holds node i; results in every lane.
+__device__ __forceinline__ double gauss_diff_norm2(const double* nodes, int N, const double th[5], const double et[5],
+                                                   double& bound) {
+  const int lane = threadIdx.x & 63;
+  double v[3][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[a][q] = 0.0;
+  if (lane < N) {
+    const double x = nodes[lane];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double ep = exp(et[1 + a] * x - et[4] * x * x);
+      const double e = exp(th[1 + a] * x - th[4] * x * x);
+      const double d = ep * expm1((th[1 + a] - et[1 + a]) * x - (th[4] - et[4]) * x * x);
+      // pairs: 0 EE, 1 EE', 2 Ed, 3 E'E', 4 E'd, 5 dd
+      v[a][0] = e * e;
+      v[a][1] = e * ep;
+      v[a][2] = e * d;
+      v[a][3] = ep * ep;
+      v[a][4] = ep * d;
+      v[a][5] = d * d;
+    }
+  }
+  double S[3][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[a][q] = wave_sum(v[a][q]);
+  // factor of term i on axis a: 0 = E, 1 = E', 2 = d
+  constexpr int F[4][3] = {{0, 0, 0}, {2, 0, 0}, {1, 2, 0}, {1, 1, 2}};
+  constexpr int P[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  const double ce = exp(et[0]);
+  const double c[4] = {ce * expm1(th[0] - et[0]), ce, ce, ce};
+  double n2 = 0.0, b = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double t = c[i] * c[j] * S[0][P[F[i][0]][F[j][0]]] * S[1][P[F[i][1]][F[j][1]]] * S[2][P[F[i][2]][F[j][2]]];
+      n2 += t;
+      b += fabs(t);
+    }
+  bound = b;
+  return fmax(n2, 0.0);
+}
 
 struct SolveArgs {
   int mode;
@@ -35,22 +99,24 @@ struct SolveOut {
   double residual;
 };
 
-// Block of kCellThreads threads.  rf(k) returns r at node k; g0 and g may alias
+// Block of NT threads.  rf(k) returns r at node k; g0 and g may alias
 // (g0 is read in the first passes only, before the final write).  With g0b
 // non-null the visit keeps whichever of g0 and g0b has the smaller initial
 // residual of eq. inner_eqn (used by the learned warm start).
-template <int N, typename RF>
+template <int N, int NT, typename RF>
 __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double* g0, double* g, double lam, double dx,
                                                      const SolveArgs& opt, const double* nodes, double w,
                                                      const double* g0b = nullptr) {
   constexpr int K = N * N * N;
   const double inv_dx = 1.0 / dx;
-  __shared__ double s_red[35 * (kCellThreads / 64)];
+  static_assert(NT % 64 == 0 && K % NT == 0, "block size must divide the grid");
+  __shared__ double s_red[35 * (NT / 64)];
   __shared__ double s_Ea[3][N], s_Eb[3][N];  // axis factors of M[g0], M[g0b]
   __shared__ double s_ea[2];
   __shared__ double s_nodes[N];
   __shared__ double s_Et[3][N], s_Ee[3][N];  // axis factors of M_theta and M_eta
-  __shared__ double s_th[5], s_eta[5];
+  __shared__ double s_th[5], s_eta[5], s_res[2];
+  __shared__ int s_chk[2];
   __shared__ int s_flags[4];  // fallback, newton_fail, nonfinite
   __syncthreads();  // the block may be reused across calls (sequential scans)
   if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
@@ -60,7 +126,8 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   double acc[35];
 #pragma unroll
   for (int i = 0; i < 35; ++i) acc[i] = 0.0;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += NT) {
     const double v0 = s_nodes[k / (N * N)], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
     const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
     const double c = fabs(v0) * inv_dx, Dinv = 1.0 / (c + lam);
@@ -126,7 +193,7 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
     // pass 2: initial residuals |c g + r - lambda (M[g] - g)| of both guesses
     __syncthreads();
     double part[2] = {0.0, 0.0};
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    for (int k = threadIdx.x; k < K; k += NT) {
       const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
       const double c = fabs(s_nodes[a0]) * inv_dx;
       const double rk = rf(k), ga = g0[k], gb = g0b[k];
@@ -148,14 +215,17 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
       }
     }
   }
+  // the update loop: wave 0 iterates in theta-space, the block joins only for a
+  // pointwise residual when the separable one cannot decide
+  const int n_upd = opt.fixed_iters > 0 ? opt.fixed_iters : opt.max_iter;
+  int k_done = 0;
+  double res = INFINITY;
   if (threadIdx.x < 64) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) th[i] = eta[i];
   }
-  const int n_upd = opt.fixed_iters > 0 ? opt.fixed_iters : opt.max_iter;
-  int k_done = 0;
-  double res = INFINITY;
   for (int k = 0; k < n_upd; ++k) {
+    const int slot = k & 1;  // double-buffered so that the next write cannot race this read
     if (threadIdx.x < 64) {
       double S[3][5], mom[5];
       if (!fallback) {
@@ -199,8 +269,13 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
       for (int i = 0; i < 5; ++i) cg[i] = lam * mom[i] - R2[i];
       AxisW aw1{W_ONE, inv_dx, lam};
       if (newton_gauss(s_nodes, N, w, mg, eta, aw1, 1e-13, 60) < 0) newton_fail++;
+      // residual lambda |M_theta - M[g^{k+1}]|_{L2}, separable form with its rounding bound
+      double bnd;
+      const double n2 = gauss_diff_norm2(s_nodes, N, th, eta, bnd);
+      const double rs = lam * sqrt(w * n2), fl = lam * sqrt(w * 1e-14 * bnd);
+      const int chk = opt.fixed_iters > 0 || !isfinite(rs) || !(fabs(rs - opt.tol) > fl);
       const int lane = threadIdx.x;
-      if (lane < N) {
+      if (chk && lane < N) {
         const double x = s_nodes[lane];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -213,28 +288,44 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
         s_eta[lane] = eta[lane];
       }
       if (lane == 0) {
+        s_res[slot] = rs;
+        s_chk[slot] = chk;
         s_flags[0] = fallback ? 1 : 0;
         s_flags[1] = newton_fail;
       }
     }
     __syncthreads();
-    // residual lambda |M_theta - M[g^{k+1}]|_{L2}, pointwise
-    const double ea = exp(s_th[0]), ee = exp(s_eta[0]);
-    double part[1] = {0.0};
-    for (int kk = threadIdx.x; kk < K; kk += blockDim.x) {
-      const int a0 = kk / (N * N), a1 = (kk / N) % N, a2 = kk % N;
-      const double d = ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - ee * s_Ee[0][a0] * s_Ee[1][a1] * s_Ee[2][a2];
-      part[0] += d * d;
+    if (s_chk[slot]) {
+      const double ea = exp(s_th[0]), ee = exp(s_eta[0]);
+      double part[1] = {0.0};
+      for (int kk = threadIdx.x; kk < K; kk += NT) {
+        const int a0 = kk / (N * N), a1 = (kk / N) % N, a2 = kk % N;
+        const double d = ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - ee * s_Ee[0][a0] * s_Ee[1][a1] * s_Ee[2][a2];
+        part[0] += d * d;
+      }
+      block_sum<1>(part, s_red);
+      res = lam * sqrt(w * part[0]);
+    } else {
+      res = s_res[slot];
     }
-    block_sum<1>(part, s_red);
-    res = lam * sqrt(w * part[0]);
     k_done = k + 1;
     if (opt.fixed_iters <= 0 && res <= opt.tol) break;
   }
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane < N) {
+      const double x = s_nodes[lane];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s_Et[a][lane] = exp(th[1 + a] * x - th[4] * x * x);
+    }
+    if (lane < 5) s_th[lane] = th[lane];
+  }
+  __syncthreads();
   // final write g = D^{-1}(lambda M_theta - r)
   const double ea = exp(s_th[0]);
   bool bad = false;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += NT) {
     const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
     const double c = fabs(s_nodes[a0]) * inv_dx;
     const double val = (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rf(k)) / (c + lam);

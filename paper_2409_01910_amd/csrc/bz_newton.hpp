@@ -187,12 +187,13 @@ __device__ __forceinline__ int newton_gauss(const double* nodes, int N, double w
 #pragma unroll
     for (int i = 0; i < 5; ++i) rhs[i] = -r[i];
     solve5(J, rhs, step);
-    double t = 1.0, thn[5], n_new = INFINITY, mn[5], Jn[5][5];
+    // J was consumed by solve5; it is rebuilt from the accepted point's 1D sums
+    double t = 1.0, thn[5], n_new = INFINITY, mn[5];
     while (true) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) thn[i] = th[i] + t * step[i];
       axis_sums(nodes, N, thn, aw, S);
-      gauss_moments(S, w * exp(thn[0]), mn, Jn);
+      gauss_moments(S, w * exp(thn[0]), mn, nullptr);
       n_new = 0.0;
 #pragma unroll
       for (int i = 0; i < 5; ++i) n_new = fmax(n_new, fabs(mn[i] - target[i]));
@@ -211,9 +212,8 @@ __device__ __forceinline__ int newton_gauss(const double* nodes, int N, double w
     for (int i = 0; i < 5; ++i) {
       th[i] = thn[i];
       r[i] = mn[i] - target[i];
-#pragma unroll
-      for (int j = 0; j < 5; ++j) J[i][j] = Jn[i][j];
     }
+    gauss_moments(S, w * exp(th[0]), mn, J);
     nrm = n_new;
     if (dmax <= 1e-15 * (1.0 + tmax)) return nrm <= 1e-10 * scale ? it + 1 : -(it + 2);
   }

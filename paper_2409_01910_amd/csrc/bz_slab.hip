@@ -210,7 +210,7 @@ struct RChain {
 
 // one work-group per instance: the cells of the scan in order
 template <int N>
-__global__ __launch_bounds__(kCellThreads) void k_chain(double* f, const double* __restrict__ rs,
+__global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double* __restrict__ rs,
                                                         const double* __restrict__ nu, const InstDev* __restrict__ inst,
                                                         int forward, SolveArgs opt,
                                                         unsigned long long* __restrict__ stats,
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kCellThreads) void k_chain(double* f, const double*
                                : (j < id.nx - 1 ? f + (size_t)(c + 1) * K : nullptr);
     RChain<N> rf{rs + (size_t)c * K, fn, nodes, 1.0 / id.dx, forward};
     double* fc = f + (size_t)c * K;
-    const SolveOut o = solve_cell_block<N>(rf, fc, fc, nu[c] / id.eps, id.dx, opt, nodes, w);
+    const SolveOut o = solve_cell_block<N, kChainThreads>(rf, fc, fc, nu[c] / id.eps, id.dx, opt, nodes, w);
     it_sum += o.iterations;
     fb_sum += o.fallback;
     __syncthreads();  // f_j written before it is read as the next upwind neighbour
@@ -415,7 +415,7 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
                                        L.theta, L.b, L.rs, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w));
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters};
-  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kCellThreads), 0, st, L.f, L.rs, L.nu,
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
   L.q_valid = false;
