@@ -30,41 +30,38 @@ constexpr int kChainThreads = 256;  // sequential scan (one wave per SIMD: the u
 // telescoped into four separable terms,
 //   (e^a - e^a') E0 E1 E2 + e^a' (E0 - E0') E1 E2 + e^a' E0' (E1 - E1') E2
 //   + e^a' E0' E1' (E2 - E2'),
-// with the differences formed through expm1, so that no term cancels against
-// another when the two Gaussians are close.  Their 16 inner products are
-// products of three 1D sums of pairwise products of {E, E', E - E'}.
-// Returns the squared norm and, in bound, the sum of the magnitudes of the 16
-// products (the scale of its rounding error).
-// One wave; lane i < N holds node i; results in every lane.
+// with the differences formed through expm1, so that each term is accurate when
+// the two Gaussians are close (the terms can still cancel one another where
+// the grid samples the Gaussians coarsely; the caller checks the bound).  Their
+// 16 inner products are products of three 1D sums of pairwise products of
+// {E, E', E - E'}.  Returns the squared norm and, in bound, the sum of the
+// magnitudes of the 16 products (the scale of its rounding error).
+// One full wave, N <= 32; results in every lane.
 __device__ __forceinline__ double gauss_diff_norm2(const double* nodes, int N, const double th[5], const double et[5],
                                                    double& bound) {
-  const int lane = threadIdx.x & 63;
-  double v[3][6];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int q = 0; q < 6; ++q) v[a][q] = 0.0;
-  if (lane < N) {
-    const double x = nodes[lane];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double ep = exp(et[1 + a] * x - et[4] * x * x);
-      const double e = exp(th[1 + a] * x - th[4] * x * x);
-      const double d = ep * expm1((th[1 + a] - et[1 + a]) * x - (th[4] - et[4]) * x * x);
-      // pairs: 0 EE, 1 EE', 2 Ed, 3 E'E', 4 E'd, 5 dd
-      v[a][0] = e * e;
-      v[a][1] = e * ep;
-      v[a][2] = e * d;
-      v[a][3] = ep * ep;
-      v[a][4] = ep * d;
-      v[a][5] = d * d;
-    }
-  }
-  double S[3][6];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int q = 0; q < 6; ++q) S[a][q] = wave_sum(v[a][q]);
+  // lanes 0..31: axis 0 (first set) and axis 2 (second set); lanes 32..63: axis 1.
+  // Branch-free, so that the lanes the DPP moves read hold defined values.
+  const int lane = threadIdx.x & 63, ix = lane & 31, h = lane >> 5;
+  const bool act = ix < N;
+  const double x = nodes[act ? ix : 0], x2 = x * x;
+  double va[6], vb[6];
+  auto pairs = [&](int a, bool on, double (&v)[6]) {
+    const double ep = exp(et[1 + a] * x - et[4] * x2);
+    const double e = exp(th[1 + a] * x - th[4] * x2);
+    const double d = ep * expm1((th[1 + a] - et[1 + a]) * x - (th[4] - et[4]) * x2);
+    // pairs: 0 EE, 1 EE', 2 Ed, 3 E'E', 4 E'd, 5 dd
+    v[0] = on ? e * e : 0.0;
+    v[1] = on ? e * ep : 0.0;
+    v[2] = on ? e * d : 0.0;
+    v[3] = on ? ep * ep : 0.0;
+    v[4] = on ? ep * d : 0.0;
+    v[5] = on ? d * d : 0.0;
+  };
+  pairs(h, act, va);
+  pairs(2, act && h == 0, vb);
+  double S[3][6], unused[6];
+  half_wave_sums<6>(va, S[0], S[1]);
+  half_wave_sums<6>(vb, S[2], unused);
   // factor of term i on axis a: 0 = E, 1 = E', 2 = d
   constexpr int F[4][3] = {{0, 0, 0}, {2, 0, 0}, {1, 2, 0}, {1, 1, 2}};
   constexpr int P[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
@@ -99,131 +96,51 @@ struct SolveOut {
   double residual;
 };
 
-// Block of NT threads.  rf(k) returns r at node k; g0 and g may alias
-// (g0 is read in the first passes only, before the final write).  With g0b
-// non-null the visit keeps whichever of g0 and g0b has the smaller initial
-// residual of eq. inner_eqn (used by the learned warm start).
+// Per-visit inputs of the theta-space iteration, all multiplied by w and held by
+// wave 0: R0 = sum phi r, R1 = sum phi r / D, R2 = sum phi c r / D, the moments
+// mg = sum phi g^0 and cg = sum phi c g^0 of the initial guess, and eta, the
+// parameters of M[g^0].
+struct VisitMoments {
+  double R0[5], R1[5], R2[5], mg[5], cg[5];
+};
+
+// Optional by-product of the final write for a sequential scan: the
+// neighbour part of the next visit's R0, R1, R2, i.e. the sums of phi t,
+// phi t / D', phi c t / D' with t = coef(v_1) g, where g is this visit's result
+// (the next cell's fresh upwind neighbour) and D' the next cell's D.  coef and
+// dinv are LDS tables over the v_1 index; coef == nullptr disables it.
+struct NextMoments {
+  const double* coef;
+  const double* dinv;
+  double out[15];
+};
+
+// Block of NT threads, after VisitMoments and eta are known (wave 0): the
+// update loop in theta-space and the final write g = D^{-1}(lambda M_theta - r).
+// rf(k) returns r at node k; g may alias the initial guess (read before).
+// s_nodes, s_c, s_dinv are LDS tables over an axis index: nodes, c = |v_1|/dx
+// and 1 / (c + lambda).
 template <int N, int NT, typename RF>
-__device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double* g0, double* g, double lam, double dx,
-                                                     const SolveArgs& opt, const double* nodes, double w,
-                                                     const double* g0b = nullptr) {
+__device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double lam, double inv_dx,
+                                               const SolveArgs& opt, const double* s_nodes, const double* s_c,
+                                               const double* s_dinv, double w, VisitMoments& vm, double (&eta)[5],
+                                               int newton_fail, bool fallback, int used_b, NextMoments* nx) {
   constexpr int K = N * N * N;
-  const double inv_dx = 1.0 / dx;
-  static_assert(NT % 64 == 0 && K % NT == 0, "block size must divide the grid");
-  __shared__ double s_red[35 * (NT / 64)];
-  __shared__ double s_Ea[3][N], s_Eb[3][N];  // axis factors of M[g0], M[g0b]
-  __shared__ double s_ea[2];
-  __shared__ double s_nodes[N];
+  __shared__ double s_red[15 * (NT / 64)];
   __shared__ double s_Et[3][N], s_Ee[3][N];  // axis factors of M_theta and M_eta
   __shared__ double s_th[5], s_eta[5], s_res[2];
   __shared__ int s_chk[2];
   __shared__ int s_flags[4];  // fallback, newton_fail, nonfinite
-  __syncthreads();  // the block may be reused across calls (sequential scans)
-  if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
   if (threadIdx.x < 4) s_flags[threadIdx.x] = 0;
   __syncthreads();
-  // pass 1: fixed moment vectors of r and the moments of g0 (and g0b)
-  double acc[35];
-#pragma unroll
-  for (int i = 0; i < 35; ++i) acc[i] = 0.0;
-#pragma unroll 4
-  for (int k = threadIdx.x; k < K; k += NT) {
-    const double v0 = s_nodes[k / (N * N)], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
-    const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
-    const double c = fabs(v0) * inv_dx, Dinv = 1.0 / (c + lam);
-    const double rk = rf(k), gk = g0[k];
-    const double t0 = rk, t1 = rk * Dinv, t2 = c * rk * Dinv, t3 = gk, t4 = c * gk;
-    const double gb = g0b ? g0b[k] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      acc[i] += phi[i] * t0;
-      acc[5 + i] += phi[i] * t1;
-      acc[10 + i] += phi[i] * t2;
-      acc[15 + i] += phi[i] * t3;
-      acc[20 + i] += phi[i] * t4;
-      acc[25 + i] += phi[i] * gb;
-      acc[30 + i] += phi[i] * c * gb;
-    }
-  }
-  if (g0b) {
-    block_sum<35>(acc, s_red);
-  } else {
-    block_sum<25>(*reinterpret_cast<double(*)[25]>(acc), s_red);
-  }
-  double R0[5], R1[5], R2[5], cg[5], th[5], eta[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    R0[i] = w * acc[i];
-    R1[i] = w * acc[5 + i];
-    R2[i] = w * acc[10 + i];
-    cg[i] = w * acc[20 + i];
-  }
-  bool fallback = opt.mode == 1;
-  int newton_fail = 0;
-  int used_b = 0;
-  double eta_b[5];
-  if (threadIdx.x < 64) {
-    double mg[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) mg[i] = w * acc[15 + i];
-    theta_from_moments(mg, w, eta);
-    AxisW aw{W_ONE, inv_dx, lam};
-    if (newton_gauss(s_nodes, N, w, mg, eta, aw, 1e-13, 60) < 0) newton_fail++;
-    if (g0b) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i) mg[i] = w * acc[25 + i];
-      theta_from_moments(mg, w, eta_b);
-      if (newton_gauss(s_nodes, N, w, mg, eta_b, aw, 1e-13, 60) < 0) newton_fail++;
-      const int lane = threadIdx.x;
-      if (lane < N) {
-        const double x = s_nodes[lane];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          s_Ea[a][lane] = exp(eta[1 + a] * x - eta[4] * x * x);
-          s_Eb[a][lane] = exp(eta_b[1 + a] * x - eta_b[4] * x * x);
-        }
-      }
-      if (lane == 0) {
-        s_ea[0] = exp(eta[0]);
-        s_ea[1] = exp(eta_b[0]);
-      }
-    }
-  }
-  if (g0b) {
-    // pass 2: initial residuals |c g + r - lambda (M[g] - g)| of both guesses
-    __syncthreads();
-    double part[2] = {0.0, 0.0};
-    for (int k = threadIdx.x; k < K; k += NT) {
-      const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
-      const double c = fabs(s_nodes[a0]) * inv_dx;
-      const double rk = rf(k), ga = g0[k], gb = g0b[k];
-      const double Ma = s_ea[0] * s_Ea[0][a0] * s_Ea[1][a1] * s_Ea[2][a2];
-      const double Mb = s_ea[1] * s_Eb[0][a0] * s_Eb[1][a1] * s_Eb[2][a2];
-      const double ra = c * ga + rk - lam * (Ma - ga), rb = c * gb + rk - lam * (Mb - gb);
-      part[0] += ra * ra;
-      part[1] += rb * rb;
-    }
-    block_sum<2>(part, s_red);
-    if (part[1] < part[0]) {
-      used_b = 1;
-      if (threadIdx.x < 64) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          eta[i] = eta_b[i];
-          cg[i] = w * acc[30 + i];
-        }
-      }
-    }
-  }
   // the update loop: wave 0 iterates in theta-space, the block joins only for a
   // pointwise residual when the separable one cannot decide
   const int n_upd = opt.fixed_iters > 0 ? opt.fixed_iters : opt.max_iter;
   int k_done = 0;
   double res = INFINITY;
-  if (threadIdx.x < 64) {
+  double th[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) th[i] = eta[i];
-  }
+  for (int i = 0; i < 5; ++i) th[i] = eta[i];
   for (int k = 0; k < n_upd; ++k) {
     const int slot = k & 1;  // double-buffered so that the next write cannot race this read
     if (threadIdx.x < 64) {
@@ -232,10 +149,10 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
         // step 1 (eq. step1): sum w phi c M' = sum w phi (c (M[g^k] - g^k) - r)
         AxisW awc{W_C, inv_dx, lam};
         axis_sums(s_nodes, N, eta, awc, S);
-        gauss_moments(S, w * exp(eta[0]), mom, nullptr);
+        gauss_moments(S, w * exp(eta[0]), mom);
         double sv[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) sv[i] = mom[i] - cg[i] - R0[i];
+        for (int i = 0; i < 5; ++i) sv[i] = mom[i] - vm.cg[i] - vm.R0[i];
         // eq. existence
         bool ok = sv[0] > 0.0 && sv[0] * sv[4] > sv[1] * sv[1] + sv[2] * sv[2] + sv[3] * sv[3];
         double tt[5];
@@ -259,14 +176,14 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
       // moments of g^{k+1} = D^{-1}(lambda M_theta - r)
       AxisW awd{W_DINV, inv_dx, lam}, awcd{W_CDINV, inv_dx, lam};
       axis_sums(s_nodes, N, th, awd, S);
-      gauss_moments(S, w * exp(th[0]), mom, nullptr);
+      gauss_moments(S, w * exp(th[0]), mom);
       double mg[5];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) mg[i] = lam * mom[i] - R1[i];
+      for (int i = 0; i < 5; ++i) mg[i] = lam * mom[i] - vm.R1[i];
       axis_sums(s_nodes, N, th, awcd, S);
-      gauss_moments(S, w * exp(th[0]), mom, nullptr);
+      gauss_moments(S, w * exp(th[0]), mom);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) cg[i] = lam * mom[i] - R2[i];
+      for (int i = 0; i < 5; ++i) vm.cg[i] = lam * mom[i] - vm.R2[i];
       AxisW aw1{W_ONE, inv_dx, lam};
       if (newton_gauss(s_nodes, N, w, mg, eta, aw1, 1e-13, 60) < 0) newton_fail++;
       // residual lambda |M_theta - M[g^{k+1}]|_{L2}, separable form with its rounding bound
@@ -321,18 +238,48 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
     if (lane < 5) s_th[lane] = th[lane];
   }
   __syncthreads();
-  // final write g = D^{-1}(lambda M_theta - r)
+  // final write g = D^{-1}(lambda M_theta - r).  g may alias the initial guess
+  // and nothing proves it does not alias r's sources, so the loads of a batch
+  // of U points are staged in registers before any store, keeping U loads in
+  // flight.
   const double ea = exp(s_th[0]);
+  const bool want_next = nx && nx->coef;
+  double acc[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) acc[i] = 0.0;
   bool bad = false;
-#pragma unroll 4
-  for (int k = threadIdx.x; k < K; k += NT) {
-    const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
-    const double c = fabs(s_nodes[a0]) * inv_dx;
-    const double val = (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rf(k)) / (c + lam);
-    bad |= !isfinite(val);
-    g[k] = val;
+  constexpr int U = (K / NT) < 16 ? (K / NT) : 16;
+  static_assert((K / NT) % U == 0, "unroll must divide the per-thread count");
+  for (int k0 = threadIdx.x; k0 < K; k0 += U * NT) {
+    double rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rv[u] = rf(k0 + u * NT);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * NT;
+      const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+      const double val = (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rv[u]) * s_dinv[a0];
+      bad |= !isfinite(val);
+      g[k] = val;
+      if (want_next) {
+        const double v0 = s_nodes[a0], v1 = s_nodes[a1], v2 = s_nodes[a2];
+        const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+        const double t = nx->coef[a0] * val, td = t * nx->dinv[a0], tcd = s_c[a0] * td;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          acc[i] += phi[i] * t;
+          acc[5 + i] += phi[i] * td;
+          acc[10 + i] += phi[i] * tcd;
+        }
+      }
+    }
   }
   if (bad) s_flags[2] = 1;
+  if (want_next) {
+    block_sum<15>(acc, s_red);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) nx->out[i] = w * acc[i];
+  }
   __syncthreads();
   SolveOut out;
   out.used_b = used_b;
@@ -342,6 +289,139 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   out.residual = res;
   out.status = (s_flags[2] || !isfinite(res)) ? 2 : ((opt.fixed_iters > 0 || res <= opt.tol) ? 0 : 1);
   return out;
+}
+
+// Tables over the v_1 index for a cell: nodes, c = |v_1|/dx, 1/(c + lambda).
+template <int N>
+__device__ __forceinline__ void axis_tables(const double* nodes, double inv_dx, double lam, double* s_nodes,
+                                            double* s_c, double* s_dinv) {
+  if (threadIdx.x < N) {
+    const double x = nodes[threadIdx.x], c = fabs(x) * inv_dx;
+    s_nodes[threadIdx.x] = x;
+    s_c[threadIdx.x] = c;
+    s_dinv[threadIdx.x] = 1.0 / (c + lam);
+  }
+}
+
+// Initial Maxwellian parameters from the moments of g^0 (wave 0).
+template <int N>
+__device__ __forceinline__ int initial_eta(const double* s_nodes, double w, const double mg[5], double inv_dx,
+                                           double lam, double (&eta)[5]) {
+  theta_from_moments(mg, w, eta);
+  AxisW aw{W_ONE, inv_dx, lam};
+  return newton_gauss(s_nodes, N, w, mg, eta, aw, 1e-13, 60) < 0 ? 1 : 0;
+}
+
+// Full visit of one cell by a block of NT threads: a pass over memory for the
+// fixed moment vectors of r and the moments of g^0, then solve_core.  g0 and g
+// may alias.  With g0b non-null the visit keeps whichever of g0 and g0b has
+// the smaller initial residual of eq. inner_eqn (used by the learned warm start).
+template <int N, int NT, typename RF>
+__device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double* g0, double* g, double lam, double dx,
+                                                     const SolveArgs& opt, const double* nodes, double w,
+                                                     const double* g0b = nullptr) {
+  constexpr int K = N * N * N;
+  const double inv_dx = 1.0 / dx;
+  static_assert(NT % 64 == 0 && K % NT == 0, "block size must divide the grid");
+  __shared__ double s_red[35 * (NT / 64)];
+  __shared__ double s_Ea[3][N], s_Eb[3][N];  // axis factors of M[g0], M[g0b]
+  __shared__ double s_ea[2];
+  __shared__ double s_nodes[N], s_c[N], s_dinv[N];
+  __syncthreads();  // the block may be reused across calls
+  axis_tables<N>(nodes, inv_dx, lam, s_nodes, s_c, s_dinv);
+  __syncthreads();
+  // pass 1: fixed moment vectors of r and the moments of g0 (and g0b)
+  double acc[35];
+#pragma unroll
+  for (int i = 0; i < 35; ++i) acc[i] = 0.0;
+#pragma unroll 8
+  for (int k = threadIdx.x; k < K; k += NT) {
+    const int a0 = k / (N * N);
+    const double v0 = s_nodes[a0], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
+    const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+    const double c = s_c[a0], Dinv = s_dinv[a0];
+    const double rk = rf(k), gk = g0[k];
+    const double t0 = rk, t1 = rk * Dinv, t2 = c * rk * Dinv, t3 = gk, t4 = c * gk;
+    const double gb = g0b ? g0b[k] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      acc[i] += phi[i] * t0;
+      acc[5 + i] += phi[i] * t1;
+      acc[10 + i] += phi[i] * t2;
+      acc[15 + i] += phi[i] * t3;
+      acc[20 + i] += phi[i] * t4;
+      acc[25 + i] += phi[i] * gb;
+      acc[30 + i] += phi[i] * c * gb;
+    }
+  }
+  if (g0b) {
+    block_sum<35>(acc, s_red);
+  } else {
+    block_sum<25>(*reinterpret_cast<double(*)[25]>(acc), s_red);
+  }
+  VisitMoments vm;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    vm.R0[i] = w * acc[i];
+    vm.R1[i] = w * acc[5 + i];
+    vm.R2[i] = w * acc[10 + i];
+    vm.mg[i] = w * acc[15 + i];
+    vm.cg[i] = w * acc[20 + i];
+  }
+  const bool fallback = opt.mode == 1;
+  int newton_fail = 0;
+  int used_b = 0;
+  double eta[5], eta_b[5];
+  if (threadIdx.x < 64) {
+    newton_fail += initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta);
+    if (g0b) {
+      double mgb[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) mgb[i] = w * acc[25 + i];
+      newton_fail += initial_eta<N>(s_nodes, w, mgb, inv_dx, lam, eta_b);
+      const int lane = threadIdx.x;
+      if (lane < N) {
+        const double x = s_nodes[lane];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          s_Ea[a][lane] = exp(eta[1 + a] * x - eta[4] * x * x);
+          s_Eb[a][lane] = exp(eta_b[1 + a] * x - eta_b[4] * x * x);
+        }
+      }
+      if (lane == 0) {
+        s_ea[0] = exp(eta[0]);
+        s_ea[1] = exp(eta_b[0]);
+      }
+    }
+  }
+  if (g0b) {
+    // pass 2: initial residuals |c g + r - lambda (M[g] - g)| of both guesses
+    __syncthreads();
+    double part[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < K; k += NT) {
+      const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+      const double c = s_c[a0];
+      const double rk = rf(k), ga = g0[k], gb = g0b[k];
+      const double Ma = s_ea[0] * s_Ea[0][a0] * s_Ea[1][a1] * s_Ea[2][a2];
+      const double Mb = s_ea[1] * s_Eb[0][a0] * s_Eb[1][a1] * s_Eb[2][a2];
+      const double ra = c * ga + rk - lam * (Ma - ga), rb = c * gb + rk - lam * (Mb - gb);
+      part[0] += ra * ra;
+      part[1] += rb * rb;
+    }
+    block_sum<2>(part, s_red);
+    if (part[1] < part[0]) {
+      used_b = 1;
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          eta[i] = eta_b[i];
+          vm.cg[i] = w * acc[30 + i];
+        }
+      }
+    }
+  }
+  return solve_core<N, NT>(rf, g, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta, newton_fail, fallback, used_b,
+                           nullptr);
 }
 
 }  // namespace bz

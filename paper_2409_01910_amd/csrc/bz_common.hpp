@@ -128,6 +128,45 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// DPP lane move of a double (both 32-bit halves); lanes the row mask leaves
+// out, and lanes whose source is out of range, receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sums of NV values over each 32-lane half of the wave, with DPP row moves
+// instead of LDS permutes: quad exchanges, two row rotations (16-lane row
+// sums), then row 0 into row 1 and row 2 into row 3.  lo[q] = sum over lanes
+// 0..31, hi[q] = sum over lanes 32..63, both in every lane.
+template <int NV>
+__device__ __forceinline__ void half_wave_sums(double (&v)[NV], double (&lo)[NV], double (&hi)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0xB1>(v[q]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x4E>(v[q]);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x124>(v[q]);  // row_ror:4
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x128>(v[q]);  // row_ror:8
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x142, 0xA>(v[q]);  // row_bcast:15 into rows 1, 3
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    lo[q] = read_lane(v[q], 31);
+    hi[q] = read_lane(v[q], 63);
+  }
+}
+
 // Deterministic block sum of NV values per thread; result valid in all threads.
 // scratch must hold NV * (blockDim.x / 64) doubles.
 template <int NV>

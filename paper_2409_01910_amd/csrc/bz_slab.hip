@@ -54,6 +54,7 @@ struct Level {
   double* theta = nullptr;
   double* nu = nullptr;
   double* rs = nullptr;
+  double* pre = nullptr;  // [cells][25] static moments of rs and f for the scan (see k_static_rhs)
   double* R = nullptr;  // residual field (transport - Q/eps), multigrid only
   double* fc0 = nullptr;  // restricted fine iterate (coarse levels)
   double* cellsum = nullptr;
@@ -148,7 +149,7 @@ __device__ __forceinline__ void gauss_tables(const double* th, const double* nod
 template <int N>
 __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
-    const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ nu_out,
+    const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ pre, double* __restrict__ nu_out,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
     const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w) {
   constexpr int K = N * N * N;
@@ -171,12 +172,27 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
   const double* MR = ML + K;
   double* out = rs + (size_t)c * K;
   const double* bc = bsrc ? bsrc + (size_t)c * K : nullptr;
+  // the scan visit needs, besides r = rs + (fresh upwind neighbour term), the
+  // moments sum phi {1, 1/D, c/D} rs and sum phi {1, c} f of this cell; they are
+  // summed here, in parallel over cells, instead of in the sequential scan
+  __shared__ double s_c[N], s_dinv[N];
+  __shared__ double s_red[25 * (kCellThreads / 64)];
+  if (threadIdx.x < N) {
+    const double cc = fabs(nodes[threadIdx.x]) * idx;
+    s_c[threadIdx.x] = cc;
+    s_dinv[threadIdx.x] = 1.0 / (cc + nu * ie);
+  }
+  __syncthreads();
+  double acc[25];
+#pragma unroll
+  for (int q = 0; q < 25; ++q) acc[q] = 0.0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double v0 = nodes[k / (N * N)];
+    const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+    const double v0 = nodes[a0], v1 = nodes[a1], v2 = nodes[a2];
     const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
     double r = 0.0;
     if (!bgk) {
-      const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+      const double M = ea * s_E[0][a0] * s_E[1][a1] * s_E[2][a2];
       r -= (Q[(size_t)c * K + k] - nu * (M - fc[k])) * ie;  // -P / eps
     }
     if (bc) r -= bc[k];
@@ -188,7 +204,19 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
       if (j == id.nx - 1) r += vm * gR * MR[k] * idx;  // right wall ghost
     }
     out[k] = r;
+    const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+    const double cc = s_c[a0], rd = r * s_dinv[a0], fk = fc[k];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      acc[q] += phi[q] * r;
+      acc[5 + q] += phi[q] * rd;
+      acc[10 + q] += phi[q] * cc * rd;
+      acc[15 + q] += phi[q] * fk;
+      acc[20 + q] += phi[q] * cc * fk;
+    }
   }
+  block_sum<25>(acc, s_red);
+  if (threadIdx.x < 25) pre[(size_t)c * 25 + threadIdx.x] = w * acc[threadIdx.x];
 }
 
 template <int N>
@@ -208,27 +236,65 @@ struct RChain {
   }
 };
 
-// one work-group per instance: the cells of the scan in order
+// one work-group per instance: the cells of the scan in order.  A visit takes
+// its fixed moments from pre (summed by k_static_rhs) plus the neighbour part
+// accumulated by the previous visit's final write, so it touches memory only
+// in that final write.
 template <int N>
 __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double* __restrict__ rs,
+                                                        const double* __restrict__ pre,
                                                         const double* __restrict__ nu, const InstDev* __restrict__ inst,
                                                         int forward, SolveArgs opt,
                                                         unsigned long long* __restrict__ stats,
                                                         const double* __restrict__ nodes, double w) {
   constexpr int K = N * N * N;
   const InstDev id = inst[blockIdx.x];
+  __shared__ double s_nodes[N], s_c[N], s_dinv[N], s_coef[N], s_dinv_next[N];
+  const double inv_dx = 1.0 / id.dx;
   unsigned long long it_sum = 0, fb_sum = 0;
+  double nb[15];  // neighbour part of this visit's R0, R1, R2
+#pragma unroll
+  for (int q = 0; q < 15; ++q) nb[q] = 0.0;
   for (int step = 0; step < id.nx; ++step) {
     const int j = forward ? step : id.nx - 1 - step;
     const int c = id.off + j;
+    const int jn = forward ? j + 1 : j - 1;
+    const bool has_next = jn >= 0 && jn < id.nx;
+    const double lam = nu[c] / id.eps;
+    __syncthreads();  // the previous visit is done with the tables
+    axis_tables<N>(nodes, inv_dx, lam, s_nodes, s_c, s_dinv);
+    if (threadIdx.x < N) {
+      const double x = nodes[threadIdx.x];
+      s_coef[threadIdx.x] = forward ? -fmax(x, 0.0) * inv_dx : fmin(x, 0.0) * inv_dx;
+      s_dinv_next[threadIdx.x] = has_next ? 1.0 / (fabs(x) * inv_dx + nu[id.off + jn] / id.eps) : 0.0;
+    }
+    __syncthreads();
     const double* fn = forward ? (j > 0 ? f + (size_t)(c - 1) * K : nullptr)
                                : (j < id.nx - 1 ? f + (size_t)(c + 1) * K : nullptr);
-    RChain<N> rf{rs + (size_t)c * K, fn, nodes, 1.0 / id.dx, forward};
+    RChain<N> rf{rs + (size_t)c * K, fn, nodes, inv_dx, forward};
     double* fc = f + (size_t)c * K;
-    const SolveOut o = solve_cell_block<N, kChainThreads>(rf, fc, fc, nu[c] / id.eps, id.dx, opt, nodes, w);
+    VisitMoments vm;
+    double eta[5];
+    int nfail = 0;
+    if (threadIdx.x < 64) {
+      const double* p = pre + (size_t)c * 25;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        vm.R0[q] = p[q] + nb[q];
+        vm.R1[q] = p[5 + q] + nb[5 + q];
+        vm.R2[q] = p[10 + q] + nb[10 + q];
+        vm.mg[q] = p[15 + q];
+        vm.cg[q] = p[20 + q];
+      }
+      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta);
+    }
+    NextMoments nx{has_next ? s_coef : nullptr, s_dinv_next, {}};
+    const SolveOut o = solve_core<N, kChainThreads>(rf, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
+                                                    nfail, opt.mode == 1, 0, &nx);
+#pragma unroll
+    for (int q = 0; q < 15; ++q) nb[q] = has_next ? nx.out[q] : 0.0;
     it_sum += o.iterations;
     fb_sum += o.fallback;
-    __syncthreads();  // f_j written before it is read as the next upwind neighbour
   }
   if (threadIdx.x == 0) {
     atomicAdd(&stats[0], it_sum);
@@ -370,6 +436,7 @@ static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg) {
   BZ_HIP(hipMemcpy(L.d_cell_inst, ci.data(), sizeof(int) * L.ncell, hipMemcpyHostToDevice));
   BZ_HIP(hipMalloc((void**)&L.Q, sizeof(double) * K * L.ncell));
   BZ_HIP(hipMalloc((void**)&L.rs, sizeof(double) * K * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.pre, sizeof(double) * 25 * L.ncell));
   BZ_HIP(hipMalloc((void**)&L.theta, sizeof(double) * 5 * L.ncell));
   BZ_HIP(hipMalloc((void**)&L.nu, sizeof(double) * L.ncell));
   BZ_HIP(hipMalloc((void**)&L.cellsum, sizeof(double) * L.ncell));
@@ -379,7 +446,7 @@ static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg) {
 }
 
 static void level_free(Level& L) {
-  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0};
+  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.pre, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (L.own_f && L.f) (void)hipFree(L.f);
@@ -412,10 +479,10 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
   if ((e = ghosts(ctx, s, L, st)) != BZ_OK) return e;
   const int bgk = s->collision == BZ_COLL_BGK;
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_static_rhs<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
-                                       L.theta, L.b, L.rs, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
+                                       L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w));
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters};
-  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.nu,
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
   L.q_valid = false;
