@@ -396,21 +396,53 @@ __device__ __forceinline__ double swap_pair(double x) {
 
 // y <- first DIF step of a 32-point inverse DFT whose entries 16h+m live in
 // lane h of a lane pair; afterwards lane h holds the 16-point input whose
-// inverse DFT gives outputs 2k + h.  With sg = 1 - 2h and hh = h:
-//   y = (partner + sg * own) * W^(h m),  W = e^{2 pi i / 32},
-// i.e. C(m) + C(m+16) on lane 0 and (C(m) - C(m+16)) W^m on lane 1.
+// inverse DFT gives outputs 2k + h:
+//   y = (partner + sg * own) * t_h(m),  sg = 1 - 2h,  t_0 = 1,  t_1 = W^m,
+// W = e^{2 pi i / 32}, i.e. C(m) + C(m+16) on lane 0 and (C(m) - C(m+16)) W^m on
+// lane 1.  In FP64 the per-lane twiddle is formed from the lane bit hd = h as
+// t_h = (1 + hd (cos - 1), hd sin), so the step is branch-free: two FMAs for the
+// butterfly, two for the twiddle and one complex product per entry (a select
+// of a double costs two instructions).  In FP32 a select per value is cheaper.
 template <typename T>
-__device__ __forceinline__ void dif32_pair(T* re, T* im, int h) {
+struct PairTwiddle {
+  T sg, hd;
+  __device__ __forceinline__ explicit PairTwiddle(int h) : sg(h ? T(-1) : T(1)), hd(h ? T(1) : T(0)) {}
+};
+
+template <typename T>
+__device__ __forceinline__ void dif32_pair(T* re, T* im, const PairTwiddle<T>& pt) {
   constexpr Twiddle<32> tw{};
+  if constexpr (sizeof(T) == 8) {
+    // keep the 30 twiddle values from being hoisted out of the pair loop (they
+    // would hold 60 registers for the whole kernel); an empty asm makes hd opaque
+    T hd = pt.hd;
+    asm volatile("" : "+v"(hd));
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
-    const T sr = re[m] + pr, si = im[m] + pi;
-    const T dr = pr - re[m], di = pi - im[m];
-    const T c = T(tw.c[m]), s = T(tw.s[m]);
-    const T tr = dr * c - di * s, ti = dr * s + di * c;
-    re[m] = h ? tr : sr;
-    im[m] = h ? ti : si;
+    for (int m = 0; m < 16; ++m) {
+      const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
+      const T tr = fma(pt.sg, re[m], pr), ti = fma(pt.sg, im[m], pi);
+      if (m == 0) {  // t_h = 1 on both lanes
+        re[m] = tr;
+        im[m] = ti;
+      } else {
+        const T c = fma(hd, T(tw.c[m] - 1.0), T(1)), sn = hd * T(tw.s[m]);
+        re[m] = tr * c - ti * sn;
+        im[m] = tr * sn + ti * c;
+      }
+    }
+  } else {
+    // FP32: both branch results, then one select per value
+    const bool odd = pt.hd != T(0);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
+      const T sr = re[m] + pr, si = im[m] + pi;
+      const T dr = pr - re[m], di = pi - im[m];
+      const T c = T(tw.c[m]), sn = T(tw.s[m]);
+      const T tr = dr * c - di * sn, ti = dr * sn + di * c;
+      re[m] = odd ? tr : sr;
+      im[m] = odd ? ti : si;
+    }
   }
 }
 
@@ -428,6 +460,7 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int q = ln >> 1, h = ln & 1;
   C* tw = trans + (size_t)wv * N * LD;
+  const PairTwiddle<T> ptw(h);
   T acc[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = T(0);
@@ -466,7 +499,7 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
         re[m] = a_r - b_i;
         im[m] = a_i + b_r;
       }
-      dif32_pair<T>(re, im, h);
+      dif32_pair<T>(re, im, ptw);
       fft_reg<T, 16, +1>(re, im);  // lane h: rows i2 = 2k + h of column q
 #pragma unroll
       for (int k = 0; k < 16; ++k) tw[(2 * k + h) * LD + q] = C{re[k], im[k]};
@@ -477,7 +510,7 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
         re[m] = x.x;
         im[m] = x.y;
       }
-      dif32_pair<T>(re, im, h);
+      dif32_pair<T>(re, im, ptw);
       fft_reg<T, 16, +1>(re, im);  // lane h: c(q, i3 = 2k + h)
       const T wgt = pairw[pq] * T(NF == 1 ? 2 : 1);
 #pragma unroll
