@@ -57,7 +57,12 @@ typedef struct bz_ctx bz_ctx;
  *   precision  arithmetic of the spectral stage (FFTs, shifted products and
  *            their accumulation).  Moments, Newton solves, the steady-state
  *            correction, the cell solve and residuals are always FP64.
- *   device   HIP device ordinal the context works on. */
+ *   device   HIP device ordinal the context works on.
+ *   v1_shift physical v_1 of the grid origin: the nodes sample v' = v - v1_shift e_1.
+ *            Fields, moments, Maxwellian parameters (theta) and the collision
+ *            operator (translation invariant) are all in v'; transport uses the
+ *            physical v_1 = v'_1 + v1_shift (c = |v_1|/dx, upwind split, wall
+ *            fluxes).  0 for a grid centred on rest. */
 typedef struct {
   int N;
   double L;
@@ -68,6 +73,7 @@ typedef struct {
   double R;
   int precision;
   int device;
+  double v1_shift;
 } bz_params;
 
 /* Create / destroy a context: host-built quadrature, phase and weight tables
@@ -211,21 +217,28 @@ bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_
 
 /* ---------------------------------------------------------------- 1D slabs
  * A set of independent 1D slab problems (instances) on x in [xL, xR] with
- * nx cells each, diffuse walls (eq. boundary) at both ends, Knudsen number
- * eps, and the total-mass constraint of eq. mass_conserv.  Instances may
+ * nx cells each, a diffuse wall (eq. boundary) or an inflow boundary at each
+ * end, Knudsen number eps, and the total-mass constraint of eq. mass_conserv
+ * (which also fixes the position of a shock between two inflow states).  Instances may
  * have different cell counts; their cells are stored back to back in the
  * caller's field buffer f [sum_i nx_i][K] (borrowed for the slab lifetime).
  * collision: BZ_COLL_BINARY (Q of eq. discrete_Q, nu = 4 pi rho) or
  * BZ_COLL_BGK (P == 0, nu = bgk_nu if > 0 else 4 pi rho). */
 typedef enum { BZ_COLL_BINARY = 0, BZ_COLL_BGK = 1 } bz_collision;
 
+typedef enum { BZ_BC_WALL = 0, BZ_BC_INFLOW = 1 } bz_boundary;
+
 typedef struct {
   double xL, xR;
   int nx;
   double eps;
-  double T_L, T_R;      /* wall temperatures */
-  double U_L[3], U_R[3];/* wall velocities (tangential: U[0] must be 0) */
+  double T_L, T_R;      /* wall / inflow temperatures */
+  double U_L[3], U_R[3];/* physical velocities: of a wall (tangential, U[0] = 0)
+                           or the bulk velocity of an inflow Maxwellian */
   double mass;          /* C in eq. mass_conserv */
+  int bc_L, bc_R;       /* bz_boundary: BZ_BC_WALL, or BZ_BC_INFLOW for a ghost
+                           cell holding rho M(T, U) on the incoming half-space */
+  double rho_L, rho_R;  /* inflow densities (> 0; unused at walls) */
 } bz_slab_instance;
 
 typedef struct {

@@ -20,13 +20,13 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .grid import Spec, phi_vectors, velocity_nodes
+from .grid import Spec, phi_vectors, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, gaussian, moments, solve_weighted_gaussian, theta_from_macro
 
 
 def transport_coef(spec: Spec, dx: float) -> np.ndarray:
-    """c_k = |v_{k,1}| / dx; v_1 is velocity axis 0 (the slowest array axis)."""
-    return np.abs(velocity_nodes(spec)[:, 0]) / dx
+    """c_k = |v_{k,1}| / dx with the physical v_1 (velocity axis 0, the slowest array axis)."""
+    return np.abs(transport_v1(spec)) / dx
 
 
 def inner_residual(spec: Spec, g, r, nu, eps, dx, Mg=None) -> float:

@@ -25,6 +25,9 @@ class Spec:
     n_phi    3D: uniform azimuth nodes;  2D: number of circle directions
     n_rho    Gauss-Legendre nodes of the radial |g| rule on [0, R_g]
     R        support radius; default from L = (3 sqrt 2 + 1) R / 2
+    v1_shift physical v_1 of the grid's origin: the grid samples v' = v - v1_shift e_1.
+             The collision operator and the discrete Maxwellian are translation
+             invariant and work in v'; transport uses the physical v_1 = v'_1 + v1_shift.
     """
 
     d: int = 3
@@ -35,6 +38,7 @@ class Spec:
     n_phi: int = 8
     n_rho: int = 8
     R: float | None = None
+    v1_shift: float = 0.0
     _cache: dict = field(default_factory=dict, repr=False, compare=False)
 
     @property
@@ -76,6 +80,11 @@ def velocity_nodes(spec: Spec) -> np.ndarray:
     x = axis_nodes(spec)
     axes = np.meshgrid(*([x] * spec.d), indexing="ij")
     return np.stack([a.reshape(-1) for a in axes], axis=1)
+
+
+def transport_v1(spec: Spec) -> np.ndarray:
+    """Physical v_1 = v'_1 + v1_shift at every node (the advection speed along x)."""
+    return velocity_nodes(spec)[:, 0] + spec.v1_shift
 
 
 def phi_vectors(spec: Spec) -> np.ndarray:

@@ -31,7 +31,7 @@ import numpy as np
 
 from . import cell as cellmod
 from .collision import nu_of, q_corrected, q_fsm
-from .grid import Spec, sphere_area, velocity_nodes
+from .grid import Spec, sphere_area, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, moments
 
 
@@ -47,6 +47,10 @@ class Slab:
     U_R: tuple = (0.0, 0.0, 0.0)
     eps: float = 0.1
     mass: float = 1.0
+    bc_L: str = "wall"  # "wall": diffuse wall (eq. boundary); "inflow": given Maxwellian rho_L M(T_L, U_L)
+    bc_R: str = "wall"
+    rho_L: float = 1.0  # inflow densities (unused at walls)
+    rho_R: float = 1.0
     order: int = 1
     collision: str = "binary"  # "binary" (Q^FSM with eq. discrete_Q) or "bgk" (P == 0)
     bgk_nu: float | None = None  # constant nu for "bgk"; None -> |S^{d-1}| rho
@@ -67,8 +71,9 @@ class Slab:
 
 
 def wall_maxwellian(spec: Spec, T: float, U) -> np.ndarray:
-    """Unit-density Maxwellian of eq. boundary at the grid nodes."""
-    v = velocity_nodes(spec)
+    """Unit-density Maxwellian of eq. boundary at the grid nodes, U in physical velocity."""
+    v = velocity_nodes(spec).copy()
+    v[:, 0] += spec.v1_shift
     d = spec.d
     r2 = ((v - np.asarray(U[:d])) ** 2).sum(1)
     return (2.0 * np.pi * T) ** (-d / 2.0) * np.exp(-r2 / (2.0 * T))
@@ -86,19 +91,24 @@ def slopes(prob: Slab, f: np.ndarray) -> np.ndarray:
 
 
 def ghosts(prob: Slab, f: np.ndarray, s: np.ndarray):
-    """Left/right ghost distributions rho_w * M_w from the zero-mass-flux condition
-    of eq. boundary, with the discrete flux balance on the grid."""
+    """Left/right ghost distributions.  At a diffuse wall rho_w M_w, with rho_w
+    from the zero-mass-flux condition of eq. boundary (discrete flux balance on
+    the grid, physical v_1); at an inflow boundary the given rho M(T, U)."""
     spec = prob.spec
-    v1 = velocity_nodes(spec)[:, 0]
+    v1 = transport_v1(spec)
     ML = wall_maxwellian(spec, prob.T_L, prob.U_L)
     MR = wall_maxwellian(spec, prob.T_R, prob.U_R)
-    face_L = f[0] - 0.5 * s[0]
-    face_R = f[-1] + 0.5 * s[-1]
-    out_L = np.sum(np.where(v1 < 0, -v1, 0.0) * face_L)
-    in_L = np.sum(np.where(v1 > 0, v1, 0.0) * ML)
-    out_R = np.sum(np.where(v1 > 0, v1, 0.0) * face_R)
-    in_R = np.sum(np.where(v1 < 0, -v1, 0.0) * MR)
-    return (out_L / in_L) * ML, (out_R / in_R) * MR
+    if prob.bc_L == "inflow":
+        rho_L = prob.rho_L
+    else:
+        face_L = f[0] - 0.5 * s[0]
+        rho_L = np.sum(np.where(v1 < 0, -v1, 0.0) * face_L) / np.sum(np.where(v1 > 0, v1, 0.0) * ML)
+    if prob.bc_R == "inflow":
+        rho_R = prob.rho_R
+    else:
+        face_R = f[-1] + 0.5 * s[-1]
+        rho_R = np.sum(np.where(v1 > 0, v1, 0.0) * face_R) / np.sum(np.where(v1 < 0, -v1, 0.0) * MR)
+    return rho_L * ML, rho_R * MR
 
 
 def collision_terms(prob: Slab, f_j: np.ndarray):
@@ -116,7 +126,7 @@ def collision_terms(prob: Slab, f_j: np.ndarray):
 def residual_field(prob: Slab, f: np.ndarray, Q: np.ndarray) -> np.ndarray:
     """Discrete v.grad f - Q/eps per cell (eq. fully_discrete rearranged)."""
     spec = prob.spec
-    v1 = velocity_nodes(spec)[:, 0]
+    v1 = transport_v1(spec)
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
     s = slopes(prob, f)
     gl, gr = ghosts(prob, f, s)
@@ -148,7 +158,7 @@ def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) 
     """One SGS scan (the first or second line of eq. SGS): P and nu from the iterate
     before the scan, slopes from the previous scan, cells visited in order."""
     spec = prob.spec
-    v1 = velocity_nodes(spec)[:, 0]
+    v1 = transport_v1(spec)
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
     dx, eps = prob.dx, prob.eps
     Q, M, nu = all_collision(prob, f)

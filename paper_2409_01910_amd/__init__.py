@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbz.so")
 BZ_FP64, BZ_FP32 = 0, 1
 BZ_Q_CORRECTED = 1
 BZ_Q_MASS = 2
+BZ_BC_WALL, BZ_BC_INFLOW = 0, 1
 BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
 BZ_COLL_BINARY, BZ_COLL_BGK = 0, 1
 
@@ -36,7 +37,8 @@ EXPORTED = [
 class bz_params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_rho", ctypes.c_int),
-                ("R", ctypes.c_double), ("precision", ctypes.c_int), ("device", ctypes.c_int)]
+                ("R", ctypes.c_double), ("precision", ctypes.c_int), ("device", ctypes.c_int),
+                ("v1_shift", ctypes.c_double)]
 
 
 class bz_solve_opts(ctypes.Structure):
@@ -53,7 +55,8 @@ class bz_cell_stats(ctypes.Structure):
 class bz_slab_instance(ctypes.Structure):
     _fields_ = [("xL", ctypes.c_double), ("xR", ctypes.c_double), ("nx", ctypes.c_int), ("eps", ctypes.c_double),
                 ("T_L", ctypes.c_double), ("T_R", ctypes.c_double), ("U_L", ctypes.c_double * 3),
-                ("U_R", ctypes.c_double * 3), ("mass", ctypes.c_double)]
+                ("U_R", ctypes.c_double * 3), ("mass", ctypes.c_double), ("bc_L", ctypes.c_int),
+                ("bc_R", ctypes.c_int), ("rho_L", ctypes.c_double), ("rho_R", ctypes.c_double)]
 
 
 class bz_slab_desc(ctypes.Structure):
@@ -159,6 +162,7 @@ class Params:
     R: float = 0.0
     precision: int = BZ_FP64
     device: int = 0
+    v1_shift: float = 0.0  # physical v_1 of the grid origin (transport uses node + v1_shift)
 
 
 class Context:
@@ -168,7 +172,8 @@ class Context:
         self.lib = load_library()
         self.params = params or Params(**kw)
         p = bz_params(self.params.N, self.params.L, self.params.gamma, self.params.n_theta, self.params.n_phi,
-                      self.params.n_rho, self.params.R, self.params.precision, self.params.device)
+                      self.params.n_rho, self.params.R, self.params.precision, self.params.device,
+                      self.params.v1_shift)
         h = ctypes.c_void_p()
         st = self.lib.bz_create(ctypes.byref(p), ctypes.byref(h))
         if st != 0:
@@ -300,7 +305,7 @@ class Slab:
     """A set of 1D slab instances sharing one context (bz_slab).
 
     ``instances`` is a list of dicts with keys xL, xR, nx, eps, T_L, T_R, U_L, U_R,
-    mass.  ``f`` is a float64 device tensor [sum nx, K] that the slab reads and
+    mass, and optionally bc_L / bc_R ("wall" or "inflow") with rho_L / rho_R.  ``f`` is a float64 device tensor [sum nx, K] that the slab reads and
     updates in place (borrowed for the slab's lifetime)."""
 
     def __init__(self, ctx: Context, instances, f, collision: str = "binary", bgk_nu: float = 0.0,
@@ -315,6 +320,9 @@ class Slab:
             for a in range(3):
                 arr[i].U_L[a] = d.get("U_L", (0.0, 0.0, 0.0))[a]
                 arr[i].U_R[a] = d.get("U_R", (0.0, 0.0, 0.0))[a]
+            kinds = {"wall": BZ_BC_WALL, "inflow": BZ_BC_INFLOW}
+            arr[i].bc_L, arr[i].bc_R = kinds[d.get("bc_L", "wall")], kinds[d.get("bc_R", "wall")]
+            arr[i].rho_L, arr[i].rho_R = d.get("rho_L", 1.0), d.get("rho_R", 1.0)
         total = sum(d["nx"] for d in instances)
         ctx._field(f, "f")
         if f.numel() != total * ctx.K:

@@ -80,6 +80,7 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   if (p->n_rho < 1 || p->n_rho > 256) return BZ_EINVAL;
   if (p->precision != BZ_FP64 && p->precision != BZ_FP32) return BZ_EINVAL;
   if (!(p->gamma > -3.0) || p->gamma > 2.0) return BZ_EINVAL;
+  if (!std::isfinite(p->v1_shift) || std::fabs(p->v1_shift) > 1e6) return BZ_EINVAL;
   bz_ctx* ctx = new bz_ctx();
   ctx->p = *p;
   ctx->N = p->N;

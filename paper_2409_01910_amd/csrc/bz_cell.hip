@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kCellThreads) void k_maxwellian(const double* __res
 #pragma unroll
     for (int i = 0; i < 5; ++i) tgt[i] = w * m[i];
     theta_from_moments(tgt, w, th);
-    AxisW aw{W_ONE, 0.0, 0.0};
+    AxisW aw{W_ONE, 0.0, 0.0, 0.0};
     const int it = newton_gauss(s_nodes, N, w, tgt, th, aw, 1e-13, 60);
     if (threadIdx.x < 5) s_th[threadIdx.x] = th[threadIdx.x];
     if (threadIdx.x == 0 && iters) iters[b] = it;
@@ -194,7 +194,7 @@ bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const doubl
                      double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
                      const double* g0b) {
   if (batch == 0) return BZ_OK;
-  SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters};
+  SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters, ctx->p.v1_shift};
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_cell_solve<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, r,
                                            nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b));
   BZ_HIP(hipGetLastError());

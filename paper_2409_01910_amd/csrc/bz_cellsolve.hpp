@@ -85,6 +85,7 @@ struct SolveArgs {
   double tol;
   int max_iter;
   int fixed_iters;
+  double u0;  // grid v_1 shift: physical v_1 = node + u0
 };
 
 struct SolveOut {
@@ -147,7 +148,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
       double S[3][5], mom[5];
       if (!fallback) {
         // step 1 (eq. step1): sum w phi c M' = sum w phi (c (M[g^k] - g^k) - r)
-        AxisW awc{W_C, inv_dx, lam};
+        AxisW awc{W_C, inv_dx, lam, opt.u0};
         axis_sums(s_nodes, N, eta, awc, S);
         gauss_moments(S, w * exp(eta[0]), mom);
         double sv[5];
@@ -174,7 +175,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
         for (int i = 0; i < 5; ++i) th[i] = eta[i];
       }
       // moments of g^{k+1} = D^{-1}(lambda M_theta - r)
-      AxisW awd{W_DINV, inv_dx, lam}, awcd{W_CDINV, inv_dx, lam};
+      AxisW awd{W_DINV, inv_dx, lam, opt.u0}, awcd{W_CDINV, inv_dx, lam, opt.u0};
       axis_sums(s_nodes, N, th, awd, S);
       gauss_moments(S, w * exp(th[0]), mom);
       double mg[5];
@@ -184,7 +185,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
       gauss_moments(S, w * exp(th[0]), mom);
 #pragma unroll
       for (int i = 0; i < 5; ++i) vm.cg[i] = lam * mom[i] - vm.R2[i];
-      AxisW aw1{W_ONE, inv_dx, lam};
+      AxisW aw1{W_ONE, inv_dx, lam, opt.u0};
       if (newton_gauss(s_nodes, N, w, mg, eta, aw1, 1e-13, 60) < 0) newton_fail++;
       // residual lambda |M_theta - M[g^{k+1}]|_{L2}, separable form with its rounding bound
       double bnd;
@@ -291,12 +292,12 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
   return out;
 }
 
-// Tables over the v_1 index for a cell: nodes, c = |v_1|/dx, 1/(c + lambda).
+// Tables over the v_1 index for a cell: nodes, c = |x + u0|/dx, 1/(c + lambda).
 template <int N>
-__device__ __forceinline__ void axis_tables(const double* nodes, double inv_dx, double lam, double* s_nodes,
-                                            double* s_c, double* s_dinv) {
+__device__ __forceinline__ void axis_tables(const double* nodes, double inv_dx, double lam, double u0,
+                                            double* s_nodes, double* s_c, double* s_dinv) {
   if (threadIdx.x < N) {
-    const double x = nodes[threadIdx.x], c = fabs(x) * inv_dx;
+    const double x = nodes[threadIdx.x], c = fabs(x + u0) * inv_dx;
     s_nodes[threadIdx.x] = x;
     s_c[threadIdx.x] = c;
     s_dinv[threadIdx.x] = 1.0 / (c + lam);
@@ -308,7 +309,7 @@ template <int N>
 __device__ __forceinline__ int initial_eta(const double* s_nodes, double w, const double mg[5], double inv_dx,
                                            double lam, double (&eta)[5]) {
   theta_from_moments(mg, w, eta);
-  AxisW aw{W_ONE, inv_dx, lam};
+  AxisW aw{W_ONE, inv_dx, lam, 0.0};
   return newton_gauss(s_nodes, N, w, mg, eta, aw, 1e-13, 60) < 0 ? 1 : 0;
 }
 
@@ -328,7 +329,7 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   __shared__ double s_ea[2];
   __shared__ double s_nodes[N], s_c[N], s_dinv[N];
   __syncthreads();  // the block may be reused across calls
-  axis_tables<N>(nodes, inv_dx, lam, s_nodes, s_c, s_dinv);
+  axis_tables<N>(nodes, inv_dx, lam, opt.u0, s_nodes, s_c, s_dinv);
   __syncthreads();
   // pass 1: fixed moment vectors of r and the moments of g0 (and g0b)
   double acc[35];

@@ -14,17 +14,19 @@
 
 namespace bz {
 
-// weight applied on velocity axis 0 (v_1): c = |v_1| / dx, D = c + lambda
+// weight applied on velocity axis 0: c = |x + u0| / dx with u0 the grid's v_1
+// shift (physical v_1 = x + u0), D = c + lambda
 enum AxisWeight { W_ONE = 0, W_C = 1, W_DINV = 2, W_CDINV = 3 };
 
 struct AxisW {
   int kind;
   double inv_dx;
   double lam;
+  double u0;
 };
 
 __device__ __forceinline__ double axis0_weight(const AxisW& aw, double x) {
-  const double c = fabs(x) * aw.inv_dx;
+  const double c = fabs(x + aw.u0) * aw.inv_dx;
   switch (aw.kind) {
     case W_C: return c;
     case W_DINV: return 1.0 / (c + aw.lam);

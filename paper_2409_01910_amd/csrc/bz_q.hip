@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
 #pragma unroll
     for (int i = 0; i < 5; ++i) tgt[i] = w * m[i];
     theta_from_moments(tgt, w, th);
-    AxisW aw{W_ONE, 0.0, 0.0};
+    AxisW aw{W_ONE, 0.0, 0.0, 0.0};
     newton_gauss(s_nodes, N, w, tgt, th, aw, 1e-13, 60);
     if (threadIdx.x < 5) s_th[threadIdx.x] = th[threadIdx.x];
   }

@@ -39,7 +39,9 @@ struct InstDev {
 
 struct WallDev {
   double T[2];
-  double U[2][3];
+  double U[2][3];  // physical velocities
+  int kind[2];     // bz_boundary
+  double rho[2];   // inflow densities
 };
 
 struct Level {
@@ -73,6 +75,7 @@ struct bz_slab {
   bz_solve_opts inner{};
   double* wallM = nullptr;    // [n_inst][2][K] unit-density wall Maxwellians
   double* wall_in = nullptr;  // [n_inst][2] incoming discrete flux of the unit wall Maxwellian
+  double* bc_fixed = nullptr;  // [n_inst][2] inflow density, or 0 at a diffuse wall
   unsigned long long* d_stats = nullptr;  // inner iterations, visits, fallbacks
   std::vector<bz::Level> levels;
   bool mg_built = false;
@@ -83,8 +86,8 @@ namespace bz {
 // ------------------------------------------------------------------ kernels
 template <int N>
 __global__ __launch_bounds__(kCellThreads) void k_wall_init(const WallDev* __restrict__ walls, double* __restrict__ wallM,
-                                                            double* __restrict__ wall_in,
-                                                            const double* __restrict__ nodes, double w) {
+                                                            double* __restrict__ wall_in, double* __restrict__ bc_fixed,
+                                                            const double* __restrict__ nodes, double w, double u0) {
   constexpr int K = N * N * N;
   const int i = blockIdx.x / 2, side = blockIdx.x % 2;
   const WallDev wd = walls[i];
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(kCellThreads) void k_wall_init(const WallDev* __res
   double acc[1] = {0.0};
   const double norm = pow(2.0 * kPi * T, -1.5);
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double v0 = nodes[k / (N * N)], v1 = nodes[(k / N) % N], v2 = nodes[k % N];
+    const double v0 = nodes[k / (N * N)] + u0, v1 = nodes[(k / N) % N], v2 = nodes[k % N];  // physical
     const double d0 = v0 - U[0], d1 = v1 - U[1], d2 = v2 - U[2];
     const double m = norm * exp(-(d0 * d0 + d1 * d1 + d2 * d2) / (2.0 * T));
     M[k] = m;
@@ -103,22 +106,30 @@ __global__ __launch_bounds__(kCellThreads) void k_wall_init(const WallDev* __res
     if (side == 0 ? v0 > 0.0 : v0 < 0.0) acc[0] += fabs(v0) * m;
   }
   block_sum<1>(acc, s_red);
-  if (threadIdx.x == 0) wall_in[i * 2 + side] = w * acc[0];
+  if (threadIdx.x == 0) {
+    wall_in[i * 2 + side] = w * acc[0];
+    bc_fixed[i * 2 + side] = wd.kind[side] == BZ_BC_INFLOW ? wd.rho[side] : 0.0;
+  }
 }
 
 template <int N>
 __global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __restrict__ f, const InstDev* __restrict__ inst,
                                                             const double* __restrict__ wall_in,
+                                                            const double* __restrict__ bc_fixed,
                                                             double* __restrict__ ghost, const double* __restrict__ nodes,
-                                                            double w) {
+                                                            double w, double u0) {
   constexpr int K = N * N * N;
   const int i = blockIdx.x / 2, side = blockIdx.x % 2;
+  if (bc_fixed[i * 2 + side] > 0.0) {  // inflow: the given density
+    if (threadIdx.x == 0) ghost[i * 2 + side] = bc_fixed[i * 2 + side];
+    return;
+  }
   const InstDev id = inst[i];
   const double* fc = f + (size_t)(id.off + (side == 0 ? 0 : id.nx - 1)) * K;
   __shared__ double s_red[kCellThreads / 64];
   double acc[1] = {0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double v0 = nodes[k / (N * N)];
+    const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
     // outgoing half-space of the wall-adjacent cell
     if (side == 0 ? v0 < 0.0 : v0 > 0.0) acc[0] += fabs(v0) * fc[k];
   }
@@ -151,7 +162,8 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
     const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ pre, double* __restrict__ nu_out,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
-    const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w) {
+    const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w,
+    double u0) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const int i = cell_inst[c];
@@ -178,7 +190,7 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
   __shared__ double s_c[N], s_dinv[N];
   __shared__ double s_red[25 * (kCellThreads / 64)];
   if (threadIdx.x < N) {
-    const double cc = fabs(nodes[threadIdx.x]) * idx;
+    const double cc = fabs(nodes[threadIdx.x] + u0) * idx;
     s_c[threadIdx.x] = cc;
     s_dinv[threadIdx.x] = 1.0 / (cc + nu * ie);
   }
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
     const double v0 = nodes[a0], v1 = nodes[a1], v2 = nodes[a2];
-    const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
+    const double vp = fmax(v0 + u0, 0.0), vm = fmin(v0 + u0, 0.0);  // physical v_1
     double r = 0.0;
     if (!bgk) {
       const double M = ea * s_E[0][a0] * s_E[1][a1] * s_E[2][a2];
@@ -226,10 +238,11 @@ struct RChain {
   const double* nodes;
   double idx;
   int forward;
+  double u0;
   __device__ __forceinline__ double operator()(int k) const {
     double r = rs[k];
     if (fn) {
-      const double v0 = nodes[k / (N * N)];
+      const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
       r += forward ? -fmax(v0, 0.0) * idx * fn[k] : fmin(v0, 0.0) * idx * fn[k];
     }
     return r;
@@ -262,16 +275,16 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
     const bool has_next = jn >= 0 && jn < id.nx;
     const double lam = nu[c] / id.eps;
     __syncthreads();  // the previous visit is done with the tables
-    axis_tables<N>(nodes, inv_dx, lam, s_nodes, s_c, s_dinv);
+    axis_tables<N>(nodes, inv_dx, lam, opt.u0, s_nodes, s_c, s_dinv);
     if (threadIdx.x < N) {
-      const double x = nodes[threadIdx.x];
+      const double x = nodes[threadIdx.x] + opt.u0;  // physical v_1
       s_coef[threadIdx.x] = forward ? -fmax(x, 0.0) * inv_dx : fmin(x, 0.0) * inv_dx;
       s_dinv_next[threadIdx.x] = has_next ? 1.0 / (fabs(x) * inv_dx + nu[id.off + jn] / id.eps) : 0.0;
     }
     __syncthreads();
     const double* fn = forward ? (j > 0 ? f + (size_t)(c - 1) * K : nullptr)
                                : (j < id.nx - 1 ? f + (size_t)(c + 1) * K : nullptr);
-    RChain<N> rf{rs + (size_t)c * K, fn, nodes, inv_dx, forward};
+    RChain<N> rf{rs + (size_t)c * K, fn, nodes, inv_dx, forward, opt.u0};
     double* fc = f + (size_t)c * K;
     VisitMoments vm;
     double eta[5];
@@ -334,7 +347,7 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
     const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
     const double* __restrict__ bsrc, double* __restrict__ Rout, double* __restrict__ cellres,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
-    const double* __restrict__ wallM, int bgk, double bgk_nu, const double* __restrict__ nodes, double w) {
+    const double* __restrict__ wallM, int bgk, double bgk_nu, const double* __restrict__ nodes, double w, double u0) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const int i = cell_inst[c];
@@ -355,7 +368,7 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
   const double* MR = ML + K;
   double acc[1] = {0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double v0 = nodes[k / (N * N)];
+    const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
     const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
     const double left = fL ? fL[k] : gL * ML[k];
     const double right = fR ? fR[k] : gR * MR[k];
@@ -468,7 +481,8 @@ static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
 
 static bz_status ghosts(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_ghost_rho<NN_>), dim3(2 * s->n_inst), dim3(kCellThreads), 0, st, L.f,
-                                       L.d_inst, s->wall_in, L.ghost, ctx->d_nodes, ctx->w));
+                                       L.d_inst, s->wall_in, s->bc_fixed, L.ghost, ctx->d_nodes, ctx->w,
+                                       ctx->p.v1_shift));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
@@ -480,8 +494,8 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
   const int bgk = s->collision == BZ_COLL_BGK;
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_static_rhs<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
-                                       forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w));
-  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters};
+                                       forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift));
+  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift};
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
@@ -516,7 +530,8 @@ static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, st
   const int bgk = s->collision == BZ_COLL_BGK;
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_residual<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
                                        L.theta, L.b, keep_field ? L.R : nullptr, L.cellsum, L.d_inst, L.d_cell_inst,
-                                       L.ghost, s->wallM, bgk, bgk ? s->bgk_nu : 0.0, ctx->d_nodes, ctx->w));
+                                       L.ghost, s->wallM, bgk, bgk ? s->bgk_nu : 0.0, ctx->d_nodes, ctx->w,
+                                       ctx->p.v1_shift));
   BZ_HIP(hipGetLastError());
   std::vector<double> cs(L.ncell);
   BZ_HIP(hipMemcpyAsync(cs.data(), L.cellsum, sizeof(double) * L.ncell, hipMemcpyDeviceToHost, st));
@@ -659,7 +674,12 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
     const bz_slab_instance& in = d->instances[i];
     if (in.nx < 1 || !(in.xR > in.xL) || !(in.eps > 0) || !(in.T_L > 0) || !(in.T_R > 0) || !(in.mass > 0))
       return set_err(ctx, BZ_EINVAL, "bad slab instance");
-    if (in.U_L[0] != 0.0 || in.U_R[0] != 0.0) return set_err(ctx, BZ_EINVAL, "wall velocity must be tangential");
+    if ((in.bc_L != BZ_BC_WALL && in.bc_L != BZ_BC_INFLOW) || (in.bc_R != BZ_BC_WALL && in.bc_R != BZ_BC_INFLOW))
+      return set_err(ctx, BZ_EINVAL, "bad boundary kind");
+    if ((in.bc_L == BZ_BC_WALL && in.U_L[0] != 0.0) || (in.bc_R == BZ_BC_WALL && in.U_R[0] != 0.0))
+      return set_err(ctx, BZ_EINVAL, "wall velocity must be tangential");
+    if ((in.bc_L == BZ_BC_INFLOW && !(in.rho_L > 0)) || (in.bc_R == BZ_BC_INFLOW && !(in.rho_R > 0)))
+      return set_err(ctx, BZ_EINVAL, "inflow density must be > 0");
     hi.push_back(bz::InstDev{off, in.nx, (in.xR - in.xL) / in.nx, in.eps, in.mass});
     bz::WallDev wd{};
     wd.T[0] = in.T_L;
@@ -668,6 +688,10 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
       wd.U[0][a] = in.U_L[a];
       wd.U[1][a] = in.U_R[a];
     }
+    wd.kind[0] = in.bc_L;
+    wd.kind[1] = in.bc_R;
+    wd.rho[0] = in.rho_L;
+    wd.rho[1] = in.rho_R;
     walls.push_back(wd);
     off += in.nx;
   }
@@ -694,6 +718,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   bz::WallDev* d_walls = nullptr;
   if (hipMalloc((void**)&s->wallM, sizeof(double) * 2 * K * s->n_inst) != hipSuccess ||
       hipMalloc((void**)&s->wall_in, sizeof(double) * 2 * s->n_inst) != hipSuccess ||
+      hipMalloc((void**)&s->bc_fixed, sizeof(double) * 2 * s->n_inst) != hipSuccess ||
       hipMalloc((void**)&s->d_stats, sizeof(unsigned long long) * 3) != hipSuccess ||
       hipMalloc((void**)&d_walls, sizeof(bz::WallDev) * s->n_inst) != hipSuccess)
     return fail(set_err(ctx, BZ_ENOMEM, "slab allocation"));
@@ -701,9 +726,9 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
       hipMemset(s->d_stats, 0, sizeof(unsigned long long) * 3) != hipSuccess)
     return fail(set_err(ctx, BZ_EHIP, "slab upload"));
   switch (ctx->N) {
-    case 8: hipLaunchKernelGGL((bz::k_wall_init<8>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
-    case 16: hipLaunchKernelGGL((bz::k_wall_init<16>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
-    case 32: hipLaunchKernelGGL((bz::k_wall_init<32>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, ctx->d_nodes, ctx->w); break;
+    case 8: hipLaunchKernelGGL((bz::k_wall_init<8>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, s->bc_fixed, ctx->d_nodes, ctx->w, ctx->p.v1_shift); break;
+    case 16: hipLaunchKernelGGL((bz::k_wall_init<16>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, s->bc_fixed, ctx->d_nodes, ctx->w, ctx->p.v1_shift); break;
+    case 32: hipLaunchKernelGGL((bz::k_wall_init<32>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, s->bc_fixed, ctx->d_nodes, ctx->w, ctx->p.v1_shift); break;
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(set_err(ctx, BZ_EHIP, "wall init"));
   (void)hipFree(d_walls);
@@ -717,6 +742,7 @@ void bz_slab_destroy(bz_slab* s) {
   for (auto& L : s->levels) bz::level_free(L);
   if (s->wallM) (void)hipFree(s->wallM);
   if (s->wall_in) (void)hipFree(s->wall_in);
+  if (s->bc_fixed) (void)hipFree(s->bc_fixed);
   if (s->d_stats) (void)hipFree(s->d_stats);
   delete s;
 }

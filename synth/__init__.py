@@ -102,9 +102,11 @@ def RH_states(mach: float, gas_gamma: float = 5.0 / 3.0):
     return (1.0, u1, 1.0), (rho_ratio, u1 / rho_ratio, T_ratio)
 
 
-def _maxw_grid(rho, u0, T, N, L, d=3):
+def _maxw_grid(rho, u0, T, N, L, d=3, v1_shift=0.0):
+    """rho M(u0 e_1, T) at the nodes of a grid whose axis 0 is shifted by v1_shift."""
     x = grid_nodes(N, L)
-    fac = [np.exp(-((x - (u0 if a == 0 else 0.0)) ** 2) / (2.0 * T)) for a in range(d)]
+    fac = [np.exp(-((x + (v1_shift if a == 0 else 0.0) - (u0 if a == 0 else 0.0)) ** 2) / (2.0 * T))
+           for a in range(d)]
     prod = fac[0]
     for a in range(1, d):
         prod = np.multiply.outer(prod, fac[a])
@@ -155,3 +157,23 @@ def warmstart_cells(n_inst: int, cells_per_inst: int, N: int, L: float, seed: in
                     arr[i * cells_per_inst + c] = np.maximum(M * pert, 0.0)
         eps[i * cells_per_inst:(i + 1) * cells_per_inst] = e
     return fl, fo, fr, eps
+
+
+def shock_step(mach: float, nx: int, N: int, L: float, xL: float = -20.0, xR: float = 20.0, v1_shift: float = 0.0):
+    """Initial state of the normal-shock problem: the upstream Rankine-Hugoniot
+    Maxwellian in the cells left of x = 0 and the downstream one right of it, on
+    a velocity grid whose axis 0 is shifted by v1_shift.  Returns (f [nx, N^3],
+    upstream (rho, u, T), downstream (rho, u, T))."""
+    up, down = RH_states(mach)
+    dx = (xR - xL) / nx
+    xc = xL + (np.arange(nx) + 0.5) * dx
+    fu = _maxw_grid(up[0], up[1], up[2], N, L, v1_shift=v1_shift)
+    fd = _maxw_grid(down[0], down[1], down[2], N, L, v1_shift=v1_shift)
+    f = np.where((xc < 0.0)[:, None], fu[None, :], fd[None, :])
+    return np.ascontiguousarray(f), up, down
+
+
+def shock_instances(n: int = 16, mach=(2.0, 4.0), eps_cycle=(1.0, 0.1, 0.01)):
+    """Batched shock workload: Mach numbers linspace(mach), eps cycling through eps_cycle."""
+    machs = np.linspace(mach[0], mach[1], n)
+    return [(float(machs[i]), float(eps_cycle[i % len(eps_cycle)])) for i in range(n)]

@@ -149,6 +149,23 @@ def test_cell_solve_fixed_iterations_match_oracle(dev, mode):
             assert abs(stats["residual"][i] - so.residual) <= 1e-9 * max(so.residual, 1e-300) + 1e-12 * (nu[i] / eps[i]) * scale
 
 
+@pytest.mark.parametrize("mode", ["pfp", "fp"])
+def test_cell_solve_on_shifted_grid_matches_oracle(dev, mode):
+    # the grid origin at physical v_1 = 0.75: c = |v'_1 + 0.75| / dx in the solve
+    import paper_2409_01910_amd as bz
+
+    N, L, dx, B, shift = 8, 6.0, 1 / 32, 5, 0.75
+    _, r, nu, eps, g0, _ = _cell_inputs(N, L, dx, B, seed=35)
+    sp = Spec(d=3, N=N, L=L, n_theta=2, n_phi=4, n_rho=2, v1_shift=shift)
+    ctx = bz.Context(N=N, L=L, n_theta=2, n_phi=4, n_rho=2, v1_shift=shift)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g, st = ctx.cell_solve(T(r), T(nu), T(eps), dx, T(g0), mode=mode, fixed_iters=3)
+    g = g.cpu().numpy()
+    for i in range(B):
+        go, so = OC.solve(sp, r[i], nu[i], eps[i], dx, g0[i], mode=mode, fixed_iters=3)
+        assert np.max(np.abs(g[i] - go)) < 1e-11 * np.abs(go).max(), i
+
+
 def test_cell_solve_converges_to_theta_fixed_point(dev):
     N, L, dx, B = 8, 6.0, 1 / 32, 4
     sp, r, nu, eps, g0, _ = _cell_inputs(N, L, dx, B, seed=32)

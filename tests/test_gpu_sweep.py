@@ -100,3 +100,71 @@ def test_sgs_converges_and_conserves_mass(dev):
     assert hist[-1] < 1e-6 * hist[0] or hist[-1] < 1e-8
     mass = probs[0].dx * sp.w * fg.sum().item()
     assert abs(mass - 1.0) < 1e-12
+
+
+def _inflow_setup(dev, shift, instances, collision, fixed_inner):
+    import paper_2409_01910_amd as bz
+
+    N, L, nt, nph, nr = 8, 6.0, 2, 4, 3
+    sp = Spec(d=3, N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr, v1_shift=shift)
+    probs, f0 = [], []
+    for d in instances:
+        p = SW.Slab(spec=sp, nx=d["nx"], xL=d.get("xL", 0.0), xR=d.get("xR", 1.0), T_L=d["T_L"], T_R=d["T_R"],
+                    U_L=d.get("U_L", (0.0, 0.0, 0.0)), U_R=d.get("U_R", (0.0, 0.0, 0.0)), eps=d["eps"],
+                    collision=collision, fixed_inner=fixed_inner, bc_L=d.get("bc_L", "wall"),
+                    bc_R=d.get("bc_R", "wall"), rho_L=d.get("rho_L", 1.0), rho_R=d.get("rho_R", 1.0))
+        # step initial state: left state in the left half, right state in the right half
+        ML = SW.wall_maxwellian(sp, d["T_L"], d.get("U_L", (0.0, 0.0, 0.0))) * d.get("rho_L", 1.0)
+        MR = SW.wall_maxwellian(sp, d["T_R"], d.get("U_R", (0.0, 0.0, 0.0))) * d.get("rho_R", 1.0)
+        f = np.stack([ML if j < d["nx"] // 2 else MR for j in range(d["nx"])])
+        p.mass = SW.total_mass(p, f)
+        d["mass"] = p.mass
+        probs.append(p)
+        f0.append(f)
+    ctx = bz.Context(N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr, v1_shift=shift)
+    fg = torch.from_numpy(np.concatenate(f0)).to(dev).contiguous()
+    slab = bz.Slab(ctx, instances, fg, collision=collision, fixed_iters=fixed_inner)
+    return probs, f0, ctx, slab, fg
+
+
+SHOCKISH = [dict(nx=6, eps=0.1, xL=-1.0, xR=1.0, bc_L="inflow", bc_R="inflow", rho_L=1.0, rho_R=1.6,
+                 T_L=1.0, T_R=1.4, U_L=(1.5, 0.0, 0.0), U_R=(0.9, 0.0, 0.0)),
+            dict(nx=4, eps=0.5, T_L=1.0, T_R=1.5)]  # walls on the shifted grid
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_inflow_and_shifted_grid_match_oracle(dev, collision):
+    print(f"inflow/shift {collision}", flush=True)
+    inst = [dict(d) for d in SHOCKISH]
+    probs, f0, ctx, slab, fg = _inflow_setup(dev, 1.25, inst, collision, fixed_inner=3)
+    res, st = slab.sweep(2)
+    got = _split(fg, inst)
+    for i in range(len(inst)):
+        f = f0[i]
+        for _ in range(2):
+            f = SW.sgs_iteration(probs[i], f)
+        assert np.max(np.abs(got[i] - f)) < 1e-10 * f.max(), i
+        assert abs(res[i] - SW.outer_residual(probs[i], f)) < 1e-9 * res[i], i
+
+
+def test_inflow_vcycle_matches_oracle(dev):
+    print("inflow vcycle", flush=True)
+    inst = [dict(SHOCKISH[0], nx=8)]
+    probs, f0, ctx, slab, fg = _inflow_setup(dev, 1.25, inst, "binary", fixed_inner=2)
+    res, _ = slab.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
+    ref = SW.vcycle(probs[0], f0[0], None, coarsest=2, nu1=1, nu2=1, tol=0.0, coarse_iters=3)
+    ref = ref * (probs[0].mass / SW.total_mass(probs[0], ref))
+    got = _split(fg, inst)[0]
+    assert np.max(np.abs(got - ref)) < 1e-9 * ref.max()
+    assert abs(res[0] - SW.outer_residual(probs[0], ref)) < 1e-8 * res[0]
+
+
+def test_bad_boundary_arguments_are_rejected(dev):
+    import paper_2409_01910_amd as bz
+
+    ctx = bz.Context(N=8, L=6.0, n_theta=2, n_phi=4, n_rho=3)
+    f = torch.zeros(3 * ctx.K, dtype=torch.float64, device=dev)
+    with pytest.raises(bz.BZError):
+        bz.Slab(ctx, [dict(nx=3, eps=0.1, bc_L="inflow", rho_L=0.0)], f)
+    with pytest.raises(bz.BZError):
+        bz.Slab(ctx, [dict(nx=3, eps=0.1, U_L=(1.0, 0.0, 0.0))], f)  # a wall moving along x

@@ -243,3 +243,40 @@ def test_multigrid_reaches_the_sgs_state():
     # a converged state is a fixed point of the V-cycle
     f_again = SW.vcycle(prob2, f_mg, None, 2, 1, 1, 0.0)
     assert np.abs(f_again - f_mg).max() < 1e-7 * f_mg.max()
+
+
+def test_inflow_equilibrium_is_a_steady_state_on_a_shifted_grid():
+    # Equal inflow Maxwellians on both sides and the same Maxwellian in every cell:
+    # transport vanishes cell by cell and the corrected collision term of a sampled
+    # Gaussian is exactly zero, so the outer residual is zero to rounding and one
+    # SGS iteration leaves the state unchanged; the grid is shifted along v_1 and
+    # the bulk velocity is not a node, so the physical v_1 enters every upwind split
+    sp = Spec(d=3, N=8, L=6.0, n_theta=2, n_phi=4, n_rho=3, v1_shift=1.25)
+    U = (2.0, 0.3, 0.0)
+    M = SW.wall_maxwellian(sp, 1.3, U) * 0.7
+    prob = SW.Slab(spec=sp, nx=5, eps=0.1, bc_L="inflow", bc_R="inflow", rho_L=0.7, rho_R=0.7,
+                   T_L=1.3, T_R=1.3, U_L=U, U_R=U, xL=-1.0, xR=1.0)
+    f0 = np.repeat(M[None], 5, axis=0)
+    prob.mass = SW.total_mass(prob, f0)
+    scale = np.abs(cell.transport_coef(sp, prob.dx) * M).max()
+    assert SW.outer_residual(prob, f0) < 1e-12 * scale
+    f1 = SW.sgs_iteration(prob, f0)
+    assert np.abs(f1 - f0).max() < 1e-12 * M.max()
+
+
+def test_collisionless_inflow_closed_form_on_a_shifted_grid():
+    # eps -> infinity, BGK: physical right-movers carry the left inflow Maxwellian,
+    # left-movers the right one, in every cell; no physical v_1 is zero on this grid
+    sp = Spec(d=3, N=8, L=6.0, v1_shift=1.0)
+    v1 = sp.v1_shift + velocity_nodes(sp)[:, 0]
+    assert np.all(v1 != 0.0)
+    ML = SW.wall_maxwellian(sp, 1.0, (2.0, 0.0, 0.0)) * 1.0
+    MR = SW.wall_maxwellian(sp, 1.8, (0.8, 0.0, 0.0)) * 2.2
+    exact = np.where(v1 > 0, ML, MR)
+    prob = SW.Slab(spec=sp, nx=6, eps=1e12, collision="bgk", bc_L="inflow", bc_R="inflow", rho_L=1.0, rho_R=2.2,
+                   T_L=1.0, T_R=1.8, U_L=(2.0, 0.0, 0.0), U_R=(0.8, 0.0, 0.0))
+    prob.mass = SW.total_mass(prob, np.repeat(exact[None], 6, axis=0))
+    f = SW.initial_state(prob)
+    for _ in range(3):
+        f = SW.sgs_iteration(prob, f)
+    assert np.abs(f - exact[None]).max() < 1e-10 * exact.max()
