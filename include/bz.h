@@ -104,13 +104,21 @@ size_t bz_workspace_bytes(bz_ctx* ctx);
  *       sigma quadrature of the gain term conserves mass only approximately;
  *       with diffuse walls the steady problem is solvable only if the summed
  *       collision term vanishes, so the slab solver and bz_cell_fixed_point
- *       always use this form.  Allocates a [batch][5] stream-ordered temporary
- *       when theta is NULL.
+ *       use this form by default.  Allocates a [batch][5] stream-ordered
+ *       temporary when theta is NULL.
+ *   flags & BZ_Q_CONSERVE (with BZ_Q_CORRECTED, not with BZ_Q_MASS): afterwards
+ *       Q <- Q - M[f] (a . phi), phi = (1, v, |v|^2), with a from the 5x5 system
+ *       sum_k phi_i M phi_j a_j = sum_k phi_i Q_k, so that mass, momentum and
+ *       energy are conserved to rounding (the least change in sum dQ^2 / M).
+ *       The spectral operator conserves momentum and energy only up to its
+ *       truncation error; problems with inflow at both ends of a slab need all
+ *       five invariants balanced (BZ_COLL_BINARY_CONSERVE).
  *   theta (nullable, BZ_Q_CORRECTED only) receives [batch][5] parameters
  *       (alpha, beta_1..3, gamma) of M[f] = exp(alpha + beta.v - gamma |v|^2).
  * Returns BZ_EINVAL for batch < 0 or NULL buffers with batch > 0. */
 #define BZ_Q_CORRECTED 1u
 #define BZ_Q_MASS 2u
+#define BZ_Q_CONSERVE 4u
 bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
                     double* theta, void* stream);
 
@@ -222,9 +230,10 @@ bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_
  * (which also fixes the position of a shock between two inflow states).  Instances may
  * have different cell counts; their cells are stored back to back in the
  * caller's field buffer f [sum_i nx_i][K] (borrowed for the slab lifetime).
- * collision: BZ_COLL_BINARY (Q of eq. discrete_Q, nu = 4 pi rho) or
- * BZ_COLL_BGK (P == 0, nu = bgk_nu if > 0 else 4 pi rho). */
-typedef enum { BZ_COLL_BINARY = 0, BZ_COLL_BGK = 1 } bz_collision;
+ * collision: BZ_COLL_BINARY (Q of eq. discrete_Q with the BZ_Q_MASS projection,
+ * nu = 4 pi rho), BZ_COLL_BINARY_CONSERVE (the same with the BZ_Q_CONSERVE
+ * projection instead), or BZ_COLL_BGK (P == 0, nu = bgk_nu if > 0 else 4 pi rho). */
+typedef enum { BZ_COLL_BINARY = 0, BZ_COLL_BGK = 1, BZ_COLL_BINARY_CONSERVE = 2 } bz_collision;
 
 typedef enum { BZ_BC_WALL = 0, BZ_BC_INFLOW = 1 } bz_boundary;
 

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .grid import Spec, S_d, frequencies, nyquist_mask, radial_rule, sphere_area, sphere_rule, xi_grids
+from .grid import Spec, S_d, frequencies, nyquist_mask, phi_vectors, radial_rule, sphere_area, sphere_rule, xi_grids
 from .maxwellian import discrete_maxwellian, moments
 
 
@@ -120,21 +120,42 @@ def q_direct(spec: Spec, f: np.ndarray, n_rho_exact: int = 64, parts: bool = Fal
 
 
 def mass_project(spec: Spec, Q: np.ndarray, M: np.ndarray) -> np.ndarray:
-    """Q - M (sum_k w Q_k) / (sum_k w M_k): removes the mass the discrete operator
-    creates through sigma-quadrature error, along the Maxwellian.  With diffuse
-    walls the only globally conserved quantity is mass, and summing the discrete
-    residual over all cells gives -(1/eps) sum_j dx sum_k w Q_jk; the steady
-    problem has a solution only if that vanishes."""
+    """Q - M (sum_k Q_k) / (sum_k M_k): removes, along the Maxwellian, the mass the
+    sigma quadrature of the gain term creates.  With diffuse walls the only
+    globally conserved quantity is mass: summing the discrete residual over all
+    cells gives -(1/eps) sum_j dx sum_k w Q_jk, so a steady state exists only if
+    that vanishes."""
     return Q - M * (np.sum(Q) / np.sum(M))
 
 
-def q_corrected(spec: Spec, f: np.ndarray, M: np.ndarray | None = None, op=q_fsm, conserve_mass: bool = False):
+def conserve_project(spec: Spec, Q: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """Q - M (phi . a) with sum_k phi_i M phi_j a_j = sum_k phi_i Q_k, phi = (1, v, |v|^2):
+    removes, along M times the collision invariants, the mass, momentum and
+    energy that the discrete operator creates (sigma quadrature, truncation and
+    periodisation of the spectral method), so that it conserves all five to
+    rounding, as the collision integral does.  It is the change of least
+    sum_k dQ_k^2 / M_k.  Summing the discrete residual over all cells leaves
+    -(1/eps) sum_j dx sum_k w phi Q_jk plus the boundary fluxes; with inflow at
+    both ends every invariant is balanced, so a steady state exists only if this
+    sum vanishes."""
+    phi = phi_vectors(spec)
+    G = (phi * M[:, None]).T @ phi
+    a = np.linalg.solve(G, phi.T @ Q)
+    return Q - M * (phi @ a)
+
+
+def q_corrected(spec: Spec, f: np.ndarray, M: np.ndarray | None = None, op=q_fsm, conserve: str | None = None):
     """Steady-state preserving collision term, eq. discrete_Q:
-    Q[f] = Q^FSM[f, f] - Q^FSM[M[f], M[f]]; optionally mass-projected."""
+    Q[f] = Q^FSM[f, f] - Q^FSM[M[f], M[f]]; then, with conserve = "mass" or "all",
+    mass_project or conserve_project."""
     if M is None:
         M = discrete_maxwellian(spec, f)
     Q = op(spec, f) - op(spec, M)
-    return mass_project(spec, Q, M) if conserve_mass else Q
+    if conserve == "mass":
+        return mass_project(spec, Q, M)
+    if conserve == "all":
+        return conserve_project(spec, Q, M)
+    return Q
 
 
 def nu_of(spec: Spec, f: np.ndarray) -> float:
@@ -144,10 +165,10 @@ def nu_of(spec: Spec, f: np.ndarray) -> float:
 
 
 def penalty(spec: Spec, f: np.ndarray, Q: np.ndarray | None = None, M: np.ndarray | None = None,
-            conserve_mass: bool = True):
+            conserve: str | None = "mass"):
     """P[f] = Q[f,f] - nu (M[f] - f), eq. Pf, with the mass-projected corrected Q."""
     if M is None:
         M = discrete_maxwellian(spec, f)
     if Q is None:
-        Q = q_corrected(spec, f, M, conserve_mass=conserve_mass)
+        Q = q_corrected(spec, f, M, conserve=conserve)
     return Q - nu_of(spec, f) * (M - f)

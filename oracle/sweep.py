@@ -53,6 +53,7 @@ class Slab:
     rho_R: float = 1.0
     order: int = 1
     collision: str = "binary"  # "binary" (Q^FSM with eq. discrete_Q) or "bgk" (P == 0)
+    conserve: str = "mass"  # binary: project Q onto zero mass ("mass") or all five invariants ("all")
     bgk_nu: float | None = None  # constant nu for "bgk"; None -> |S^{d-1}| rho
     inner: str = "pfp"
     tol_inner: float = 1e-8
@@ -113,14 +114,15 @@ def ghosts(prob: Slab, f: np.ndarray, s: np.ndarray):
 
 def collision_terms(prob: Slab, f_j: np.ndarray):
     """(Q, M, nu) for one cell: the steady-state preserving Q^FSM (eq. discrete_Q),
-    mass-projected (collision.mass_project), in binary mode, or nu (M - f) in BGK
+    projected (collision.mass_project, or conserve_project for conserve="all"), in
+    binary mode, or nu (M - f) in BGK
     mode."""
     spec = prob.spec
     M = discrete_maxwellian(spec, f_j)
     if prob.collision == "bgk":
         nu = prob.bgk_nu if prob.bgk_nu is not None else nu_of(spec, f_j)
         return nu * (M - f_j), M, nu
-    return q_corrected(spec, f_j, M, op=q_fsm, conserve_mass=True), M, nu_of(spec, f_j)
+    return q_corrected(spec, f_j, M, op=q_fsm, conserve=prob.conserve), M, nu_of(spec, f_j)
 
 
 def residual_field(prob: Slab, f: np.ndarray, Q: np.ndarray) -> np.ndarray:

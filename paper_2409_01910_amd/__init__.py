@@ -18,9 +18,11 @@ LIB_PATH = os.path.join(HERE, "libbz.so")
 BZ_FP64, BZ_FP32 = 0, 1
 BZ_Q_CORRECTED = 1
 BZ_Q_MASS = 2
+BZ_Q_CONSERVE = 4
 BZ_BC_WALL, BZ_BC_INFLOW = 0, 1
 BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
-BZ_COLL_BINARY, BZ_COLL_BGK = 0, 1
+BZ_COLL_BINARY, BZ_COLL_BGK, BZ_COLL_BINARY_CONSERVE = 0, 1, 2
+_COLLISIONS = {"binary": BZ_COLL_BINARY, "bgk": BZ_COLL_BGK, "binary_conserve": BZ_COLL_BINARY_CONSERVE}
 
 # every symbol include/bz.h declares
 EXPORTED = [
@@ -207,12 +209,13 @@ class Context:
             raise BZError(f"{name}: size not a multiple of K = {self.K}")
         return t.numel() // self.K
 
-    def eval_Q(self, f, corrected: bool = True, out=None, theta=None, conserve_mass: bool = False):
+    def eval_Q(self, f, corrected: bool = True, out=None, theta=None, conserve: str | None = None):
+        """conserve: None, "mass" (BZ_Q_MASS) or "all" (BZ_Q_CONSERVE)."""
         import torch
 
         B = self._field(f, "f")
         Q = torch.empty_like(f) if out is None else out
-        flags = (BZ_Q_CORRECTED if corrected else 0) | (BZ_Q_MASS if conserve_mass else 0)
+        flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
         st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, flags, _ptr(theta), _stream())
         self._check(st, "bz_eval_Q")
         return Q
@@ -328,7 +331,7 @@ class Slab:
         if f.numel() != total * ctx.K:
             raise BZError("f must hold sum(nx) cells")
         self._arr = arr
-        desc = bz_slab_desc(n, arr, BZ_COLL_BINARY if collision == "binary" else BZ_COLL_BGK, bgk_nu,
+        desc = bz_slab_desc(n, arr, _COLLISIONS[collision], bgk_nu,
                             Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()))
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_slab_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_slab_create")

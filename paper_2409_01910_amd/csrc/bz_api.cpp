@@ -147,19 +147,24 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
   if (!ctx) return BZ_EINVAL;
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   if (batch > 0 && (!f || !Q)) return set_err(ctx, BZ_EINVAL, "NULL field buffer");
-  if (flags & ~(BZ_Q_CORRECTED | BZ_Q_MASS)) return set_err(ctx, BZ_EINVAL, "unknown flag");
+  if (flags & ~(BZ_Q_CORRECTED | BZ_Q_MASS | BZ_Q_CONSERVE)) return set_err(ctx, BZ_EINVAL, "unknown flag");
+  if ((flags & BZ_Q_MASS) && (flags & BZ_Q_CONSERVE)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS with BZ_Q_CONSERVE");
+  if ((flags & BZ_Q_CONSERVE) && !(flags & BZ_Q_CORRECTED))
+    return set_err(ctx, BZ_EINVAL, "BZ_Q_CONSERVE requires BZ_Q_CORRECTED");
   if (theta && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "theta requires BZ_Q_CORRECTED");
   if ((flags & BZ_Q_MASS) && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS requires BZ_Q_CORRECTED");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if (!(flags & BZ_Q_MASS) || batch == 0) return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, st);
+  if (!(flags & (BZ_Q_MASS | BZ_Q_CONSERVE)) || batch == 0)
+    return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, st);
   double* th = theta;
   if (!th) {
     hipError_t e = hipMallocAsync((void**)&th, (size_t)batch * 5 * sizeof(double), st);
     if (e != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
   }
   bz_status s = bz::eval_q(ctx, f, Q, batch, true, th, st);
-  if (s == BZ_OK) s = bz::mass_project(ctx, Q, th, batch, st);
+  if (s == BZ_OK)
+    s = (flags & BZ_Q_CONSERVE) ? bz::conserve_project(ctx, Q, th, batch, st) : bz::mass_project(ctx, Q, th, batch, st);
   if (!theta) (void)hipFreeAsync(th, st);
   return s;
 }

@@ -163,6 +163,68 @@ __global__ __launch_bounds__(kCellThreads) void k_mass_project(double* __restric
     q[k] -= c * ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
 }
 
+// Q <- Q - M_theta (a . phi), phi = (1, v, |v|^2), with G a = sum_k phi Q_k and
+// G = sum_k phi phi^T M_theta: mass, momentum and energy conserved to rounding.
+// G is separable (1D sums of x^p E_a(x)), so one thread builds and solves it.
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_conserve_project(double* __restrict__ Q,
+                                                                   const double* __restrict__ theta,
+                                                                   const double* __restrict__ nodes) {
+  constexpr int K = N * N * N;
+  const int b = blockIdx.x;
+  __shared__ double s_E[3][N];
+  __shared__ double s_nodes[N];
+  __shared__ double s_red[5 * (kCellThreads / 64)];
+  __shared__ double s_a[5];
+  const double* th = theta + (size_t)b * 5;
+  if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
+  if (threadIdx.x < 3 * N) {
+    const int a = threadIdx.x / N, i = threadIdx.x % N;
+    const double x = nodes[i];
+    s_E[a][i] = exp(th[1 + a] * x - th[4] * x * x);
+  }
+  __syncthreads();
+  double* q = Q + (size_t)b * K;
+  double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double v0 = s_nodes[k / (N * N)], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
+    const double qk = q[k];
+    m[0] += qk;
+    m[1] += qk * v0;
+    m[2] += qk * v1;
+    m[3] += qk * v2;
+    m[4] += qk * (v0 * v0 + v1 * v1 + v2 * v2);
+  }
+  block_sum<5>(m, s_red);
+  const double ea = exp(th[0]);
+  if (threadIdx.x == 0) {
+    double S[3][5], G[5][5], a[5];
+    for (int ax = 0; ax < 3; ++ax)
+      for (int p = 0; p < 5; ++p) S[ax][p] = 0.0;
+    for (int ax = 0; ax < 3; ++ax)
+      for (int i = 0; i < N; ++i) {
+        double t = s_E[ax][i];
+        for (int p = 0; p < 5; ++p) {
+          S[ax][p] += t;
+          t *= s_nodes[i];
+        }
+      }
+    gauss_gram(S, G);
+    double rhs[5];
+    for (int i = 0; i < 5; ++i) rhs[i] = m[i] / ea;
+    solve_spd5(G, rhs, a);
+    for (int i = 0; i < 5; ++i) s_a[i] = a[i];
+  }
+  __syncthreads();
+  const double a0 = s_a[0], a1 = s_a[1], a2 = s_a[2], a3 = s_a[3], a4 = s_a[4];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int i0 = k / (N * N), i1 = (k / N) % N, i2 = k % N;
+    const double v0 = s_nodes[i0], v1 = s_nodes[i1], v2 = s_nodes[i2];
+    const double M = ea * s_E[0][i0] * s_E[1][i1] * s_E[2][i2];
+    q[k] -= M * (a0 + a1 * v0 + a2 * v1 + a3 * v2 + a4 * (v0 * v0 + v1 * v1 + v2 * v2));
+  }
+}
+
 #define BZ_DISPATCH_N(NV, CALL)                                           \
   switch (NV) {                                                           \
     case 8: {                                                             \
@@ -205,6 +267,14 @@ bz_status mass_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batc
   if (batch == 0) return BZ_OK;
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_mass_project<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, Q,
                                            theta, ctx->d_nodes));
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+bz_status conserve_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st) {
+  if (batch == 0) return BZ_OK;
+  BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_conserve_project<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st,
+                                           Q, theta, ctx->d_nodes));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

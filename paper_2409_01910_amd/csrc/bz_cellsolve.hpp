@@ -118,11 +118,14 @@ struct NextMoments {
 
 // Block of NT threads, after VisitMoments and eta are known (wave 0): the
 // update loop in theta-space and the final write g = D^{-1}(lambda M_theta - r).
-// rf(k) returns r at node k; g may alias the initial guess (read before).
+// rf(k) returns r at node k; g0 is the initial guess, which g may alias.  A
+// visit whose final theta or residual is not finite (a diverged plain
+// iteration) keeps g0 and reports status 2, so one failed cell does not turn
+// the whole field non-finite.
 // s_nodes, s_c, s_dinv are LDS tables over an axis index: nodes, c = |v_1|/dx
 // and 1 / (c + lambda).
 template <int N, int NT, typename RF>
-__device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double lam, double inv_dx,
+__device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, double* g, double lam, double inv_dx,
                                                const SolveArgs& opt, const double* s_nodes, const double* s_c,
                                                const double* s_dinv, double w, VisitMoments& vm, double (&eta)[5],
                                                int newton_fail, bool fallback, int used_b, NextMoments* nx) {
@@ -131,7 +134,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
   __shared__ double s_Et[3][N], s_Ee[3][N];  // axis factors of M_theta and M_eta
   __shared__ double s_th[5], s_eta[5], s_res[2];
   __shared__ int s_chk[2];
-  __shared__ int s_flags[4];  // fallback, newton_fail, nonfinite
+  __shared__ int s_flags[4];  // fallback, newton_fail, nonfinite, keep g0
   if (threadIdx.x < 4) s_flags[threadIdx.x] = 0;
   __syncthreads();
   // the update loop: wave 0 iterates in theta-space, the block joins only for a
@@ -237,8 +240,16 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
       for (int a = 0; a < 3; ++a) s_Et[a][lane] = exp(th[1 + a] * x - th[4] * x * x);
     }
     if (lane < 5) s_th[lane] = th[lane];
+    bool finite = isfinite(res);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) finite = finite && isfinite(th[i]);
+    if (lane == 0 && !finite) {
+      s_flags[2] = 1;
+      s_flags[3] = 1;
+    }
   }
   __syncthreads();
+  const bool keep = s_flags[3] != 0;
   // final write g = D^{-1}(lambda M_theta - r).  g may alias the initial guess
   // and nothing proves it does not alias r's sources, so the loads of a batch
   // of U points are staged in registers before any store, keeping U loads in
@@ -254,12 +265,12 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, double* g, double l
   for (int k0 = threadIdx.x; k0 < K; k0 += U * NT) {
     double rv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) rv[u] = rf(k0 + u * NT);
+    for (int u = 0; u < U; ++u) rv[u] = keep ? g0[k0 + u * NT] : rf(k0 + u * NT);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * NT;
       const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
-      const double val = (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rv[u]) * s_dinv[a0];
+      const double val = keep ? rv[u] : (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rv[u]) * s_dinv[a0];
       bad |= !isfinite(val);
       g[k] = val;
       if (want_next) {
@@ -421,7 +432,7 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
       }
     }
   }
-  return solve_core<N, NT>(rf, g, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta, newton_fail, fallback, used_b,
+  return solve_core<N, NT>(rf, g0, g, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta, newton_fail, fallback, used_b,
                            nullptr);
 }
 

@@ -82,6 +82,8 @@ bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const d
                         double dx, double* g0, int64_t batch, hipStream_t st);
 // Q <- Q - M_theta sum(Q) / sum(M_theta) per cell (mass-conserving projection)
 bz_status mass_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st);
+// Q <- Q - M_theta (a . phi): mass, momentum and energy conserved per cell
+bz_status conserve_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st);
 // r = inflow - (Q - nu (M_theta - f)) / eps, nu = 4 pi rho(theta); writes nu
 bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const double* theta, const double* inflow,
                       const double* eps, double* r, double* nu, int64_t batch, hipStream_t st);

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
       nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta);
     }
     NextMoments nx{has_next ? s_coef : nullptr, s_dinv_next, {}};
-    const SolveOut o = solve_core<N, kChainThreads>(rf, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
+    const SolveOut o = solve_core<N, kChainThreads>(rf, fc, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
                                                     nfail, opt.mode == 1, 0, &nx);
 #pragma unroll
     for (int q = 0; q < 15; ++q) nb[q] = has_next ? nx.out[q] : 0.0;
@@ -469,9 +469,11 @@ static void level_free(Level& L) {
 static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   if (L.q_valid) return BZ_OK;
   bz_status e;
-  if (s->collision == BZ_COLL_BINARY) {
+  if (s->collision != BZ_COLL_BGK) {
     e = eval_q(ctx, L.f, L.Q, L.ncell, true, L.theta, st);
-    if (e == BZ_OK) e = mass_project(ctx, L.Q, L.theta, L.ncell, st);
+    if (e == BZ_OK)
+      e = s->collision == BZ_COLL_BINARY_CONSERVE ? conserve_project(ctx, L.Q, L.theta, L.ncell, st)
+                                                  : mass_project(ctx, L.Q, L.theta, L.ncell, st);
   } else {
     e = maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st);
   }
@@ -662,7 +664,8 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (!ctx || !out) return BZ_EINVAL;
   *out = nullptr;
   if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
-  if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK) return set_err(ctx, BZ_EINVAL, "bad collision");
+  if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK && d->collision != BZ_COLL_BINARY_CONSERVE)
+    return set_err(ctx, BZ_EINVAL, "bad collision");
   const bz_solve_opts& o = d->inner;
   if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad inner mode");
   if (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0))

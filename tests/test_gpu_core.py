@@ -62,6 +62,27 @@ def test_eval_q_fp64_matches_oracle(dev, case, corrected, gamma):
 
 
 @pytest.mark.parametrize("case", [(8, 6.0, 4, 8, 4, 5), (16, 8.0, 4, 8, 8, 3)])
+def test_eval_q_conservation_projection_matches_oracle(dev, case):
+    import paper_2409_01910_amd as bz
+    from oracle import maxwellian as MXo
+
+    N, L, nt, nph, nr, B = case
+    print(f"eval_Q conservation-projected N={N} B={B}", flush=True)
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=24)
+    ctx = _ctx(N, L, nt, nph, nr)
+    fd = torch.from_numpy(f).to(dev)
+    Qg = ctx.eval_Q(fd, corrected=True, conserve="all").cpu().numpy()
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i], conserve="all")
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
+        m = MXo.moments(sp, Qg[i])
+        assert np.all(np.abs(m) < 1e-13 * sp.w * np.abs(loss).sum() * np.array([1, L, L, L, L * L])), m
+
+
+@pytest.mark.parametrize("case", [(8, 6.0, 4, 8, 4, 5), (16, 8.0, 4, 8, 8, 3)])
 def test_eval_q_mass_projection_matches_oracle(dev, case):
     import paper_2409_01910_amd as bz
 
@@ -71,18 +92,18 @@ def test_eval_q_mass_projection_matches_oracle(dev, case):
     f = synth.mixture_batch(B, N, L, seed=23)
     ctx = _ctx(N, L, nt, nph, nr)
     fd = torch.from_numpy(f).to(dev)
-    Qg = ctx.eval_Q(fd, corrected=True, conserve_mass=True).cpu().numpy()
+    Qg = ctx.eval_Q(fd, corrected=True, conserve="mass").cpu().numpy()
     theta = torch.empty(B, 5, dtype=torch.float64, device=dev)
-    Qt = ctx.eval_Q(fd, corrected=True, conserve_mass=True, theta=theta).cpu().numpy()
+    Qt = ctx.eval_Q(fd, corrected=True, conserve="mass", theta=theta).cpu().numpy()
     assert np.array_equal(Qg, Qt)
     for i in range(B):
-        ref = OQ.q_corrected(sp, f[i], conserve_mass=True)
+        ref = OQ.q_corrected(sp, f[i], conserve="mass")
         _, loss = OQ.q_fsm(sp, f[i], parts=True)
         scale = max(np.abs(ref).max(), np.abs(loss).max())
         assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
         assert abs(Qg[i].sum()) < 1e-13 * np.abs(loss).sum()
     with pytest.raises(bz.BZError):
-        ctx.eval_Q(fd, corrected=False, conserve_mass=True)
+        ctx.eval_Q(fd, corrected=False, conserve="mass")
 
 
 def test_eval_q_fp32_error_bound(dev):

@@ -111,7 +111,9 @@ def _inflow_setup(dev, shift, instances, collision, fixed_inner):
     for d in instances:
         p = SW.Slab(spec=sp, nx=d["nx"], xL=d.get("xL", 0.0), xR=d.get("xR", 1.0), T_L=d["T_L"], T_R=d["T_R"],
                     U_L=d.get("U_L", (0.0, 0.0, 0.0)), U_R=d.get("U_R", (0.0, 0.0, 0.0)), eps=d["eps"],
-                    collision=collision, fixed_inner=fixed_inner, bc_L=d.get("bc_L", "wall"),
+                    collision="binary" if collision == "binary_conserve" else collision,
+                    conserve="all" if collision == "binary_conserve" else "mass",
+                    fixed_inner=fixed_inner, bc_L=d.get("bc_L", "wall"),
                     bc_R=d.get("bc_R", "wall"), rho_L=d.get("rho_L", 1.0), rho_R=d.get("rho_R", 1.0))
         # step initial state: left state in the left half, right state in the right half
         ML = SW.wall_maxwellian(sp, d["T_L"], d.get("U_L", (0.0, 0.0, 0.0))) * d.get("rho_L", 1.0)
@@ -132,7 +134,7 @@ SHOCKISH = [dict(nx=6, eps=0.1, xL=-1.0, xR=1.0, bc_L="inflow", bc_R="inflow", r
             dict(nx=4, eps=0.5, T_L=1.0, T_R=1.5)]  # walls on the shifted grid
 
 
-@pytest.mark.parametrize("collision", ["bgk", "binary"])
+@pytest.mark.parametrize("collision", ["bgk", "binary", "binary_conserve"])
 def test_inflow_and_shifted_grid_match_oracle(dev, collision):
     print(f"inflow/shift {collision}", flush=True)
     inst = [dict(d) for d in SHOCKISH]
@@ -150,7 +152,7 @@ def test_inflow_and_shifted_grid_match_oracle(dev, collision):
 def test_inflow_vcycle_matches_oracle(dev):
     print("inflow vcycle", flush=True)
     inst = [dict(SHOCKISH[0], nx=8)]
-    probs, f0, ctx, slab, fg = _inflow_setup(dev, 1.25, inst, "binary", fixed_inner=2)
+    probs, f0, ctx, slab, fg = _inflow_setup(dev, 1.25, inst, "binary_conserve", fixed_inner=2)
     res, _ = slab.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
     ref = SW.vcycle(probs[0], f0[0], None, coarsest=2, nu1=1, nu2=1, tol=0.0, coarse_iters=3)
     ref = ref * (probs[0].mass / SW.total_mass(probs[0], ref))

@@ -64,23 +64,47 @@ def test_fast_form_converges_to_sigma_exact_sum():
 
 
 def test_mass_projection_removes_only_quadrature_mass():
-    """The collision integral conserves mass; the sigma-exact sum does too.  The
-    projected fast form conserves it to rounding, keeps the corrected form exact
-    at equilibrium, and changes Q by an amount that vanishes as the sphere rule
-    is refined (so it removes only quadrature error)."""
+    """The collision integral conserves mass, and so does the sigma-exact sum.  The
+    mass-projected fast form conserves it to rounding, keeps the corrected form
+    exact at equilibrium, and changes Q by an amount that vanishes as the sphere
+    rule is refined (so it removes only quadrature error)."""
     f = _narrow(8, 4.0)
     changes = []
     for nt in (4, 8, 16):
         sp = Spec(d=3, N=8, L=4.0, n_theta=nt, n_phi=2 * nt, n_rho=nt)
         M = MX.discrete_maxwellian(sp, f)
         Q = C.q_corrected(sp, f, M)
-        Qp = C.q_corrected(sp, f, M, conserve_mass=True)
+        Qp = C.q_corrected(sp, f, M, conserve="mass")
         _, loss = C.q_fsm(sp, f, parts=True)
         assert abs(MX.moments(sp, Qp)[0]) < 1e-14 * sp.w * np.abs(loss).sum()
-        assert np.abs(C.q_corrected(sp, M, M, conserve_mass=True)).max() == 0.0
+        assert np.abs(C.q_corrected(sp, M, M, conserve="mass")).max() == 0.0
         changes.append(np.abs(Qp - Q).max() / np.abs(Q).max())
     assert changes[0] > changes[1] > changes[2]
     assert changes[2] < 1e-9
+
+
+def test_conservation_projection_is_the_least_change_that_conserves():
+    """conserve_project: zero mass, momentum and energy to rounding; a projection
+    (idempotent); exact at equilibrium; and no other change with those moments is
+    smaller in the sum of dQ^2 / M (checked against random admissible changes)."""
+    sp = Spec(d=3, N=8, L=6.0, n_theta=4, n_phi=8, n_rho=4)
+    f = synth.mixture_batch(1, 8, 6.0, seed=4, T=(0.8, 1.2), speed=(0.0, 0.3))[0]
+    M = MX.discrete_maxwellian(sp, f)
+    Q = C.q_corrected(sp, f, M)
+    Qp = C.q_corrected(sp, f, M, conserve="all")
+    m = MX.moments(sp, Qp)
+    scale = sp.w * np.abs(Q).sum() * np.array([1.0, sp.L, sp.L, sp.L, sp.L ** 2])
+    assert np.all(np.abs(m) < 1e-13 * scale), m
+    assert np.abs(C.conserve_project(sp, Qp, M) - Qp).max() < 1e-13 * np.abs(Qp).max()
+    assert np.abs(C.q_corrected(sp, M, M, conserve="all")).max() == 0.0
+    dQ = Qp - Q
+    base = np.sum(dQ * dQ / M)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        h = rng.normal(size=sp.K) * M  # an arbitrary direction, made admissible below
+        h = C.conserve_project(sp, h, M)  # zero invariant moments
+        other = dQ + 1e-3 * np.abs(dQ).max() * h / np.abs(h).max()
+        assert np.sum(other * other / M) > base
 
 
 @pytest.mark.slow
