@@ -167,6 +167,79 @@ def slab_workload(args, tol=1e-8):
                                             "eps": 0.1}, "runs": out}
 
 
+def shock_workload(args, tol=1e-8):
+    """Normal shocks between Rankine-Hugoniot inflow states, x in [-20, 20], 128
+    cells, 32^3 velocities on [-8, 8]^3 shifted along v_1 to the mean of the two
+    bulk speeds, Maxwell molecules, collision term projected onto zero mass,
+    momentum and energy, plain SGS-PFP (inner residual 1e-8), total mass held at
+    the initial step's.  single: Mach 1.5, eps 0.1, M = 32, n_rho = 8, to outer
+    residual tol.  batch16: 16 instances, Mach = linspace(1.5, 2.5), eps cycling
+    1, 0.1, 0.01, M = 128, n_rho = 16, in one slab (one work-group per instance
+    in each scan), for a bounded time."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+    import synth
+
+    def build(machs_eps, nt, nph, nr):
+        ups = [synth.RH_states(m) for m, _ in machs_eps]
+        shift = float(np.mean([0.5 * (u[1] + d[1]) for u, d in ups]))
+        ctx = bz.Context(N=32, L=8.0, n_theta=nt, n_phi=nph, n_rho=nr, v1_shift=shift)
+        fs, inst = [], []
+        dx = 40.0 / 128
+        for (mach, eps) in machs_eps:
+            f0, up, down = synth.shock_step(mach, 128, 32, 8.0, v1_shift=shift)
+            fs.append(f0)
+            inst.append(dict(nx=128, eps=eps, xL=-20.0, xR=20.0, bc_L="inflow", bc_R="inflow", rho_L=up[0],
+                             rho_R=down[0], T_L=up[2], T_R=down[2], U_L=(up[1], 0, 0), U_R=(down[1], 0, 0),
+                             mass=dx * 0.5 ** 3 * f0.sum()))
+        f = torch.from_numpy(np.concatenate(fs)).cuda().contiguous()
+        slab = bz.Slab(ctx, inst, f, collision="binary_conserve", tol=1e-8, max_iter=100)
+        return ctx, slab, shift
+
+    def run(slab, max_seconds, label):
+        hist = [slab.residual()]
+        inner = visits = fallbacks = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while max(hist[-1]) >= tol and time.perf_counter() - t0 < max_seconds:
+            r, st = slab.sweep(1)
+            hist.append(r)
+            inner += st["inner_iters"]
+            visits += st["visits"]
+            fallbacks += st["fallbacks"]
+            if len(hist) % 20 == 0:
+                print(f"# shock {label} iteration {len(hist) - 1} max residual {max(r):.3e}", file=sys.stderr,
+                      flush=True)
+            if not all(np.isfinite(r)):
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n = len(hist) - 1
+        return {"seconds": el, "iterations": n, "ms_per_iteration": el / max(n, 1) * 1e3,
+                "final_residuals": hist[-1], "reached": max(hist[-1]) < tol,
+                "mean_inner_iterations": inner / max(visits, 1), "fallbacks": fallbacks,
+                "max_residual_every_20": [max(h) for h in hist[::20]]}
+
+    out = {}
+    ctx, slab, shift = build([(1.5, 0.1)], 4, 8, 8)
+    out["single_mach1.5_eps0.1_M32"] = dict(run(slab, 60.0, "single"), v1_shift=shift)
+    slab.close()
+    ctx.close()
+    batch = synth.shock_instances(16, mach=(1.5, 2.5))
+    ctx, slab, shift = build(batch, 8, 16, 16)
+    r = run(slab, 90.0, "batch16")
+    r["cell_visits_per_second"] = 2 * 16 * 128 * r["iterations"] / r["seconds"]
+    out["batch16_M128"] = dict(r, v1_shift=shift, instances=[{"mach": m, "eps": e} for m, e in batch])
+    slab.close()
+    ctx.close()
+    return {"metric": "time to outer residual 1e-8, normal shock (128 cells, 32^3, inflow both ends), plain SGS-PFP",
+            "value": out["single_mach1.5_eps0.1_M32"]["seconds"], "unit": "s", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "shock", "cells": 128, "N": 32, "mach": 1.5, "eps": 0.1}, "runs": out}
+
+
 def warmstart_workload(args):
     """Learned warm start at 32^3: train on cell solves generated by the library
     (shock and heat-slab profile families), then solve held-out cells to inner
@@ -233,9 +306,10 @@ def main():
     ap.add_argument("--slab-case", default="all",
                     choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_mg", "n32_128cells_fp64",
                              "n32_128cells_mg"], help="with --workload slab: run one case only")
-    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart"], default="batched-q",
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
-                         "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8")
+                         "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
+                         "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -252,6 +326,9 @@ def main():
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_workload(args)), flush=True)
+        return
+    if args.workload == "shock":
+        print(json.dumps(shock_workload(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")

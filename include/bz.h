@@ -303,6 +303,27 @@ typedef struct {
 bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int n_cycles,
                               double* residual_out, bz_sweep_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------- graph replay
+ * For callers that run many SGS iterations and want one host synchronisation
+ * per segment instead of one per iteration (launch-bound small slabs, serving
+ * loops): bz_graph_capture_sweeps records iters_per_replay SGS iterations of
+ * bz_sgs_sweep (two scans and the mass rescale each), and with with_residual
+ * != 0 the outer residual of the result, into a HIP graph; bz_graph_launch
+ * replays it on `stream` and, when requested, returns the per-instance
+ * residuals (host, [n_instances], needs with_residual) and the statistics of
+ * the replay, synchronising once.  Capture needs a non-default stream; the
+ * collision workspace is sized before the capture, and the graph holds no
+ * allocation and no memset node.  The graph borrows the slab and its field f:
+ * replays read and update f in place, and the slab must outlive the graph.
+ * Graphs of one slab must not be replayed concurrently.  Returns BZ_EINVAL for
+ * iters_per_replay < 1, a NULL stream, or a residual request on a graph
+ * captured without it. */
+typedef struct bz_graph bz_graph;
+bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* slab, int iters_per_replay, int with_residual,
+                                  void* stream, bz_graph** out);
+bz_status bz_graph_launch(bz_graph* graph, double* residual_out, bz_sweep_stats* stats, void* stream);
+void bz_graph_destroy(bz_graph* graph);
+
 /* ---------------------------------------------------------------- profiling
  * bz_profile_enable(ctx, 1) makes the library record a pair of HIP events
  * around every launch of the direction-pair kernel (the dominant kernel of

@@ -33,6 +33,7 @@ EXPORTED = [
     "bz_mlp_create", "bz_mlp_destroy", "bz_mlp_num_params", "bz_mlp_get_params", "bz_mlp_set_params",
     "bz_mlp_set_output_scale", "bz_mlp_forward", "bz_mlp_grad", "bz_mlp_train_step", "bz_mlp_features",
     "bz_cell_fixed_point_learned",
+    "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
 ]
 
 
@@ -131,8 +132,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_cell_fixed_point_learned.argtypes = [P, P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
     lib.bz_profile_enable.argtypes = [P, ctypes.c_int]
     lib.bz_profile_get.argtypes = [P, ctypes.POINTER(bz_profile_info)]
+    lib.bz_graph_capture_sweeps.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_graph_launch.argtypes = [P, P, ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_graph_destroy.argtypes = [P]
+    lib.bz_graph_destroy.restype = None
     for name in EXPORTED:
         if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes", "bz_mlp_destroy",
+                        "bz_graph_destroy",
                         "bz_mlp_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -374,6 +380,54 @@ class Slab:
         self.ctx._check(self.ctx.lib.bz_multigrid_vcycle(self.ctx.h, self.h, ctypes.byref(o), n_cycles, res,
                                                          ctypes.byref(st), _stream()), "bz_multigrid_vcycle")
         return list(res), self._stats(st)
+
+    def capture(self, iters: int, with_residual: bool = True) -> "SweepGraph":
+        """Capture iters SGS iterations into a replayable HIP graph."""
+        return SweepGraph(self, iters, with_residual)
+
+
+class SweepGraph:
+    """iters SGS iterations (and optionally the outer residual) of a Slab captured
+    into a HIP graph (bz_graph_capture_sweeps), replayed on a dedicated stream of
+    default priority that is ordered after the caller's current stream."""
+
+    def __init__(self, slab: "Slab", iters: int, with_residual: bool = True):
+        import torch
+
+        self.slab = slab
+        self.ctx = slab.ctx
+        self.iters = iters
+        self.with_residual = with_residual
+        self.stream = torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        h = ctypes.c_void_p()
+        self.ctx._check(self.ctx.lib.bz_graph_capture_sweeps(self.ctx.h, slab.h, iters, 1 if with_residual else 0,
+                                                             ctypes.c_void_p(self.stream.cuda_stream),
+                                                             ctypes.byref(h)), "bz_graph_capture_sweeps")
+        self.h = h
+
+    def launch(self):
+        """One replay; returns (per-instance residuals or None, stats)."""
+        import torch
+
+        self.stream.wait_stream(torch.cuda.current_stream())
+        res = (ctypes.c_double * self.slab.n)() if self.with_residual else None
+        st = bz_sweep_stats()
+        self.ctx._check(self.ctx.lib.bz_graph_launch(self.h, res, ctypes.byref(st),
+                                                     ctypes.c_void_p(self.stream.cuda_stream)), "bz_graph_launch")
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return (list(res) if res is not None else None), self.slab._stats(st)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.bz_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:

@@ -70,6 +70,9 @@ void free_tables(bz_ctx* ctx);
 bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
                  hipStream_t st);
 size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected);
+// sizes the workspace and sets kernel attributes for eval_q on `batch` cells,
+// so that a later eval_q makes no allocation (needed under stream capture)
+bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected);
 
 // cell kernels (bz_cell.hip)
 bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,

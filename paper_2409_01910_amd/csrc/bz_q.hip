@@ -620,6 +620,29 @@ static size_t ws_per_cell(int N, int n_theta, int nf) {
               cs /*Qh*/);
 }
 
+// cells per chunk of the collision workspace (2 GiB budget)
+template <typename T, int N>
+static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected) {
+  const size_t per = ws_per_cell<T>(N, ctx->n_theta, corrected ? 2 : 1);
+  int64_t chunk = (int64_t)(((size_t)2 << 30) / per);
+  if (chunk < 1) chunk = 1;
+  if (chunk > batch) chunk = batch;
+  return chunk;
+}
+
+template <typename T, int N>
+static bz_status prepare_chunked(bz_ctx* ctx, int64_t batch, bool corrected) {
+  if (batch == 0) return BZ_OK;
+  const size_t per = ws_per_cell<T>(N, ctx->n_theta, corrected ? 2 : 1);
+  bz_status s = ensure_ws(ctx, per * chunk_cells<T, N>(ctx, batch, corrected));
+  if (s != BZ_OK) return s;
+  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>() : pairs_lds_bytes<T, N>();
+  const void* kp = (N == 32) ? (corrected ? (const void*)k_pairs32<T, 2> : (const void*)k_pairs32<T, 1>)
+                             : (corrected ? (const void*)k_pairs<T, N, 2> : (const void*)k_pairs<T, N, 1>);
+  BZ_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return BZ_OK;
+}
+
 template <typename T, int N>
 static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
                              hipStream_t st) {
@@ -628,10 +651,7 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   const int nf = corrected ? 2 : 1;
   const int nt = ctx->n_theta;
   const size_t per = ws_per_cell<T>(N, nt, nf);
-  const size_t budget = (size_t)2 << 30;
-  int64_t chunk = (int64_t)(budget / per);
-  if (chunk < 1) chunk = 1;
-  if (chunk > batch) chunk = batch;
+  const int64_t chunk = chunk_cells<T, N>(ctx, batch, corrected);
   bz_status s = ensure_ws(ctx, per * chunk);
   if (s != BZ_OK) return s;
   unsigned char* base = (unsigned char*)ctx->ws;
@@ -697,6 +717,21 @@ size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected) {
   const int nf = corrected ? 2 : 1;
   return ctx->p.precision == BZ_FP32 ? ws_per_cell<float>(ctx->N, ctx->n_theta, nf)
                                      : ws_per_cell<double>(ctx->N, ctx->n_theta, nf);
+}
+
+bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected) {
+  const bool fp32 = ctx->p.precision == BZ_FP32;
+  switch (ctx->N) {
+    case 8:
+      return fp32 ? prepare_chunked<float, 8>(ctx, batch, corrected) : prepare_chunked<double, 8>(ctx, batch, corrected);
+    case 16:
+      return fp32 ? prepare_chunked<float, 16>(ctx, batch, corrected)
+                  : prepare_chunked<double, 16>(ctx, batch, corrected);
+    case 32:
+      return fp32 ? prepare_chunked<float, 32>(ctx, batch, corrected)
+                  : prepare_chunked<double, 32>(ctx, batch, corrected);
+  }
+  return set_err(ctx, BZ_EUNSUPPORTED, "N must be 8, 16 or 32");
 }
 
 bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,

@@ -523,9 +523,9 @@ static bz_status sgs_iter(bz_ctx* ctx, bz_slab* s, Level& L, bool do_rescale, hi
   return BZ_OK;
 }
 
-// per-instance residual norms |T - b| (host vector); optionally keeps the field T in L.R
-static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, std::vector<double>& out,
-                          hipStream_t st) {
+// per-cell squared residual sums |T - b|^2 into L.cellsum (device work only);
+// optionally keeps the field T in L.R
+static bz_status residual_launch(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, hipStream_t st) {
   bz_status e = collide(ctx, s, L, st);
   if (e != BZ_OK) return e;
   if ((e = ghosts(ctx, s, L, st)) != BZ_OK) return e;
@@ -535,6 +535,11 @@ static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, st
                                        L.ghost, s->wallM, bgk, bgk ? s->bgk_nu : 0.0, ctx->d_nodes, ctx->w,
                                        ctx->p.v1_shift));
   BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// per-instance norms from L.cellsum (one host synchronisation)
+static bz_status residual_read(bz_ctx* ctx, Level& L, std::vector<double>& out, hipStream_t st) {
   std::vector<double> cs(L.ncell);
   BZ_HIP(hipMemcpyAsync(cs.data(), L.cellsum, sizeof(double) * L.ncell, hipMemcpyDeviceToHost, st));
   BZ_HIP(hipStreamSynchronize(st));
@@ -545,6 +550,18 @@ static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, st
     out[i] = std::sqrt(L.h_inst[i].dx * t);
   }
   return BZ_OK;
+}
+
+// per-instance residual norms |T - b| (host vector); optionally keeps the field T in L.R
+static bz_status residual(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_field, std::vector<double>& out,
+                          hipStream_t st) {
+  bz_status e = residual_launch(ctx, s, L, keep_field, st);
+  if (e != BZ_OK) return e;
+  return residual_read(ctx, L, out, st);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 static double vmax(const std::vector<double>& v) {
@@ -808,6 +825,94 @@ bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int 
     for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
   }
   return bz::read_stats(ctx, s, stats, n_cycles, st);
+}
+
+}  // extern "C"
+
+/* ------------------------------------------------------------ graph replay */
+struct bz_graph {
+  bz_ctx* ctx = nullptr;
+  bz_slab* slab = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int iters = 0;
+  bool with_residual = false;
+};
+
+extern "C" {
+
+bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay, int with_residual, void* stream,
+                                  bz_graph** out) {
+  if (!out) return BZ_EINVAL;
+  *out = nullptr;
+  if (!ctx || !s || s->ctx != ctx) return BZ_EINVAL;
+  if (iters_per_replay < 1) return set_err(ctx, BZ_EINVAL, "iters_per_replay < 1");
+  if (!stream) return set_err(ctx, BZ_EINVAL, "capture needs a non-default stream");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  bz::Level& L = s->levels[0];
+  // everything that allocates or sets attributes happens before the capture
+  if (s->collision != BZ_COLL_BGK) {
+    bz_status e = bz::eval_q_prepare(ctx, L.ncell, true);
+    if (e != BZ_OK) return e;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipStreamSynchronize");
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    ctx->prof = prof;
+    return set_err(ctx, BZ_EHIP, "hipStreamBeginCapture");
+  }
+  bz_status e = BZ_OK;
+  hipLaunchKernelGGL(bz::k_zero_u64, dim3(1), dim3(64), 0, st, s->d_stats, 3);  // a kernel, not a memset node
+  L.q_valid = false;
+  for (int it = 0; it < iters_per_replay && e == BZ_OK; ++it) e = bz::sgs_iter(ctx, s, L, true, st);
+  if (e == BZ_OK && with_residual) e = bz::residual_launch(ctx, s, L, false, st);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(st, &g);
+  ctx->prof = prof;
+  L.q_valid = false;
+  if (e != BZ_OK || ce != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return e != BZ_OK ? e : set_err(ctx, BZ_EHIP, "hipStreamEndCapture");
+  }
+  bz_graph* gr = new bz_graph();
+  gr->ctx = ctx;
+  gr->slab = s;
+  gr->graph = g;
+  gr->iters = iters_per_replay;
+  gr->with_residual = with_residual != 0;
+  if (hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    bz_graph_destroy(gr);
+    return set_err(ctx, BZ_EHIP, "hipGraphInstantiate");
+  }
+  *out = gr;
+  return BZ_OK;
+}
+
+bz_status bz_graph_launch(bz_graph* g, double* residual_out, bz_sweep_stats* stats, void* stream) {
+  if (!g || !g->exec) return BZ_EINVAL;
+  bz_ctx* ctx = g->ctx;
+  if (residual_out && !g->with_residual) return set_err(ctx, BZ_EINVAL, "graph captured without the residual");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipGraphLaunch(g->exec, st) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipGraphLaunch");
+  bz::Level& L = g->slab->levels[0];
+  L.q_valid = false;
+  if (residual_out) {
+    std::vector<double> rn;
+    bz_status e = bz::residual_read(ctx, L, rn, st);
+    if (e != BZ_OK) return e;
+    for (int i = 0; i < g->slab->n_inst; ++i) residual_out[i] = rn[i];
+  }
+  return bz::read_stats(ctx, g->slab, stats, g->iters, st);
+}
+
+void bz_graph_destroy(bz_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

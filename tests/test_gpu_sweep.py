@@ -170,3 +170,32 @@ def test_bad_boundary_arguments_are_rejected(dev):
         bz.Slab(ctx, [dict(nx=3, eps=0.1, bc_L="inflow", rho_L=0.0)], f)
     with pytest.raises(bz.BZError):
         bz.Slab(ctx, [dict(nx=3, eps=0.1, U_L=(1.0, 0.0, 0.0))], f)  # a wall moving along x
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_graph_replays_match_eager_sweeps(dev, collision):
+    # the same initial state in two slabs: eager sweeps of 2 iterations in one,
+    # replays of a captured 2-iteration graph in the other, with eager work and
+    # synchronisations between the replays; every replay must match
+    print(f"graph replay {collision}", flush=True)
+    inst = [dict(nx=6, eps=0.1, mass=1.0), dict(nx=4, eps=0.5, T_L=1.2, T_R=1.8, mass=0.9)]
+    sp, probs, f0, ctx, slab_e, fg_e = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=0)
+    import paper_2409_01910_amd as bz
+
+    fg_g = fg_e.clone()
+    slab_g = bz.Slab(ctx, inst, fg_g, collision=collision)
+    graph = slab_g.capture(2)
+    start = fg_g.clone()
+    for rep in range(3):
+        res_e, st_e = slab_e.sweep(2)
+        res_g, st_g = graph.launch()
+        torch.cuda.synchronize()
+        _ = (fg_g * 2.0).sum().item()  # eager work between replays
+        scale = fg_e.abs().max().item()
+        assert (fg_g - fg_e).abs().max().item() <= 1e-13 * scale, rep
+        for a, b in zip(res_e, res_g):
+            assert abs(a - b) <= 1e-12 * a, rep
+        assert st_e["visits"] == st_g["visits"] and st_e["inner_iters"] == st_g["inner_iters"], rep
+    assert (fg_g - start).abs().max().item() > 1e-6 * start.abs().max().item()
+    graph.close()
+    slab_g.close()
