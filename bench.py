@@ -88,13 +88,15 @@ def cpu_baseline(f_np, eps_np, n_cells=2):
                       f"numpy FP64, one thread, {dt:.1f} s"}
 
 
-def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs"):
+def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0):
     """Heat slab x in [0, 1], nx cells, diffuse walls T = 1 and 2 at rest, n^3
     velocities on [-l, l]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes,
     initial Maxwellian u = 0, T = 1.5 of total mass 1; SGS-PFP with inner
     residual 1e-8, one SGS iteration (method "sgs") or one V-cycle (method "mg":
     coarsest 4 cells, one pre- and one post-smoothing step) per call so that
-    the outer residual is read after every iteration.  plan = [(precision, switch_residual), ...]: run in
+    the outer residual is read after every iteration; with graph_iters > 0 the
+    SGS iterations run as replays of a captured graph of that many iterations
+    (residual read once per replay).  plan = [(precision, switch_residual), ...]: run in
     each precision until the residual is below its switch value (or stalls for
     50 iterations), then continue from the same f in the next one."""
     import numpy as np
@@ -119,8 +121,13 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
             hist.append(slab.residual()[0])
         start = len(hist)
         best, best_at = hist[-1], len(hist)
+        graph = slab.capture(graph_iters) if graph_iters > 0 else None
         while hist[-1] >= switch and len(hist) <= max_iters and time.perf_counter() - t0 < max_seconds:
-            r, st = slab.sweep(1) if method == "sgs" else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
+            if graph is not None:
+                r, st = graph.launch()
+                hist.extend([None] * (graph_iters - 1))  # residual read once per replay
+            else:
+                r, st = slab.sweep(1) if method == "sgs" else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
             hist.append(r[0])
             inner += st["inner_iters"]
             visits += st["visits"]
@@ -135,6 +142,8 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
             if not np.isfinite(r[0]):
                 break
         legs.append({"precision": precision, "iterations": len(hist) - start, "residual_at_end": hist[-1]})
+        if graph is not None:
+            graph.close()
         slab.close()
         ctx.close()
     torch.cuda.synchronize()
@@ -152,6 +161,7 @@ def slab_workload(args, tol=1e-8):
         "n16_fp64": lambda: _slab_run(16, 8.0, [("fp64", tol)], tol, 3000, 60.0),
         "n32_fp64": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0),
         "n32_fp32_then_fp64": lambda: _slab_run(32, 8.0, [("fp32", 1e-5), ("fp64", tol)], tol, 3000, 90.0),
+        "n32_graph10": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0, graph_iters=10),
         "n32_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, method="mg"),
         "n32_128cells_fp64": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0, nx=128),
         "n32_128cells_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, nx=128, method="mg"),
@@ -304,7 +314,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
     ap.add_argument("--slab-case", default="all",
-                    choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_mg", "n32_128cells_fp64",
+                    choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_graph10", "n32_mg",
+                             "n32_128cells_fp64",
                              "n32_128cells_mg"], help="with --workload slab: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
