@@ -413,21 +413,21 @@ template <typename T>
 __device__ __forceinline__ void dif32_pair(T* re, T* im, const PairTwiddle<T>& pt) {
   constexpr Twiddle<32> tw{};
   if constexpr (sizeof(T) == 8) {
-    // keep the 30 twiddle values from being hoisted out of the pair loop (they
-    // would hold 60 registers for the whole kernel); an empty asm makes hd opaque
-    T hd = pt.hd;
-    asm volatile("" : "+v"(hd));
+    // FMA butterfly (one instruction per component), the lane-1 twiddle product
+    // with constant factors, then a select per component
+    const bool odd = pt.hd != T(0);
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
       const T tr = fma(pt.sg, re[m], pr), ti = fma(pt.sg, im[m], pi);
-      if (m == 0) {  // t_h = 1 on both lanes
+      if (m == 0) {
         re[m] = tr;
         im[m] = ti;
       } else {
-        const T c = fma(hd, T(tw.c[m] - 1.0), T(1)), sn = hd * T(tw.s[m]);
-        re[m] = tr * c - ti * sn;
-        im[m] = tr * sn + ti * c;
+        const T c = T(tw.c[m]), sn = T(tw.s[m]);
+        const T xr = tr * c - ti * sn, xi = tr * sn + ti * c;
+        re[m] = odd ? xr : tr;
+        im[m] = odd ? xi : ti;
       }
     }
   } else {
