@@ -265,7 +265,11 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
   const int J = NF * n_phi;
   const int rounds = (J + SPW - 1) / SPW;
   const int v = s % NF;
-  for (int tp = wv; tp < half; tp += kPairWaves) {
+  // with fewer polar pairs than waves, the rounds of a polar pair are split over
+  // S waves; the per-wave accumulators are summed below
+  const int S = half < kPairWaves ? kPairWaves / half : 1;
+  for (int u = wv; u < half * S; u += kPairWaves) {
+    const int tp = u / S, sub = u % S;
     const int tA = half + tp, tB = half - 1 - tp;
     // A(v + s) and B(v - s): plain form uses f for both; corrected variant 0 is
     // g(v + s), h(v - s), variant 1 is g(v - s), h(v + s).
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
       bi[l] = y.y;
     }
     const T sA = (v == 0) ? T(1) : T(-1);  // A uses P (v = 0) or conj(P) (v = 1)
-    for (int rd = 0; rd < rounds; ++rd) {
+    for (int rd = sub; rd < rounds; rd += S) {
       const int j = rd * SPW + s;
       const bool active = j < J;
       const int pq = tp * n_phi + (active ? j / NF : 0);
@@ -466,7 +470,11 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
   for (int j = 0; j < 16; ++j) acc[j] = T(0);
   const int half = n_theta / 2;
   const int items = half * 2;
-  for (int it = wv; it < items; it += kPair32Waves) {
+  // with fewer items than waves (small sphere rules), the azimuth loop of an
+  // item is split over S waves; the per-wave accumulators are summed below
+  const int S = items < kPair32Waves ? kPair32Waves / items : 1;
+  for (int u = wv; u < items * S; u += kPair32Waves) {
+    const int it = u / S, sub = u % S;
     const int tp = it >> 1, v = (NF == 2) ? (it & 1) : 0;
     const int tA = half + tp, tB = half - 1 - tp;
     const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
@@ -482,9 +490,9 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
       bi[m] = y.y;
     }
     const T sA = (v == 0) ? T(1) : T(-1);
-    const int phi0 = (NF == 2) ? 0 : (it & 1);
     const int phi_step = (NF == 2) ? 1 : 2;
-    for (int jj = phi0; jj < n_phi; jj += phi_step) {
+    const int phi0 = ((NF == 2) ? 0 : (it & 1)) + sub * phi_step;
+    for (int jj = phi0; jj < n_phi; jj += phi_step * S) {
       const int pq = tp * n_phi + jj;
       const C* p2 = ph23 + (size_t)pq * 2 * N;
       const C p3 = p2[N + q];
