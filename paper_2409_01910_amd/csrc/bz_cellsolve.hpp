@@ -80,6 +80,11 @@ __device__ __forceinline__ double gauss_diff_norm2(const double* nodes, int N, c
   return fmax(n2, 0.0);
 }
 
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
 struct SolveArgs {
   int mode;
   double tol;
@@ -260,31 +265,99 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
 #pragma unroll
   for (int i = 0; i < 15; ++i) acc[i] = 0.0;
   bool bad = false;
-  constexpr int U = (K / NT) < 16 ? (K / NT) : 16;
-  static_assert((K / NT) % U == 0, "unroll must divide the per-thread count");
-  for (int k0 = threadIdx.x; k0 < K; k0 += U * NT) {
-    double rv[U];
+  // one instantiation per case, so that every load of a batch is unconditional
+  // and can be issued before the first use
+  auto final_pass = [&](auto keep_tag) {
+    constexpr bool KEEP = decltype(keep_tag)::value;
+    auto load = [&](int k) -> double {
+      if constexpr (KEEP) {
+        return g0[k];
+      } else {
+        return rf(k);
+      }
+    };
+    if constexpr ((N * N) % NT == 0) {
+      // plane by plane: the last-axis index is constant per thread (NT is a
+      // multiple of N), the first-axis factors are read once per plane, and the
+      // next visit's moments are summed per plane over (v_2, v_3) and weighted
+      // by the plane's constants afterwards (4 FMAs per point instead of 15)
+      constexpr int NN = N * N, PP = NN / NT, PB = (16 / PP) > 0 ? 16 / PP : 1;
+      static_assert(N % PB == 0, "planes per batch must divide N");
+      const int a2 = threadIdx.x % N;
+      const double E2 = s_Et[2][a2], v2 = s_nodes[a2];
+      for (int p0 = 0; p0 < N; p0 += PB) {
+        double rv[PB * PP];
 #pragma unroll
-    for (int u = 0; u < U; ++u) rv[u] = keep ? g0[k0 + u * NT] : rf(k0 + u * NT);
+        for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * NT;
-      const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
-      const double val = keep ? rv[u] : (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rv[u]) * s_dinv[a0];
-      bad |= !isfinite(val);
-      g[k] = val;
-      if (want_next) {
-        const double v0 = s_nodes[a0], v1 = s_nodes[a1], v2 = s_nodes[a2];
-        const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
-        const double t = nx->coef[a0] * val, td = t * nx->dinv[a0], tcd = s_c[a0] * td;
+          for (int j = 0; j < PP; ++j) rv[pb * PP + j] = load((p0 + pb) * NN + j * NT + threadIdx.x);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          acc[i] += phi[i] * t;
-          acc[5 + i] += phi[i] * td;
-          acc[10 + i] += phi[i] * tcd;
+        for (int pb = 0; pb < PB; ++pb) {
+          const int a0 = p0 + pb;
+          const double E0 = lam * ea * s_Et[0][a0], di = s_dinv[a0];
+          double sg[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int j = 0; j < PP; ++j) {
+            const int kk = j * NT + threadIdx.x, k = a0 * NN + kk, a1 = kk / N;
+            const double val = KEEP ? rv[pb * PP + j] : (E0 * s_Et[1][a1] * E2 - rv[pb * PP + j]) * di;
+            bad |= !isfinite(val);
+            g[k] = val;
+            if (want_next) {
+              const double v1 = s_nodes[a1];
+              sg[0] += val;
+              sg[1] += val * v1;
+              sg[2] += val * v2;
+              sg[3] += val * (v1 * v1 + v2 * v2);
+            }
+          }
+          if (want_next) {
+            const double v0 = s_nodes[a0], c0 = nx->coef[a0];
+            const double sc[3] = {c0, c0 * nx->dinv[a0], s_c[a0] * c0 * nx->dinv[a0]};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              acc[5 * q + 0] += sc[q] * sg[0];
+              acc[5 * q + 1] += sc[q] * v0 * sg[0];
+              acc[5 * q + 2] += sc[q] * sg[1];
+              acc[5 * q + 3] += sc[q] * sg[2];
+              acc[5 * q + 4] += sc[q] * (v0 * v0 * sg[0] + sg[3]);
+            }
+          }
+        }
+      }
+    } else {
+      constexpr int U = (K / NT) < 16 ? (K / NT) : 16;
+      static_assert((K / NT) % U == 0, "unroll must divide the per-thread count");
+      for (int k0 = threadIdx.x; k0 < K; k0 += U * NT) {
+        double rv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rv[u] = load(k0 + u * NT);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * NT;
+          const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+          const double val =
+              KEEP ? rv[u] : (lam * ea * s_Et[0][a0] * s_Et[1][a1] * s_Et[2][a2] - rv[u]) * s_dinv[a0];
+          bad |= !isfinite(val);
+          g[k] = val;
+          if (want_next) {
+            const double v0 = s_nodes[a0], v1 = s_nodes[a1], v2 = s_nodes[a2];
+            const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+            const double t = nx->coef[a0] * val, td = t * nx->dinv[a0], tcd = s_c[a0] * td;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+              acc[i] += phi[i] * t;
+              acc[5 + i] += phi[i] * td;
+              acc[10 + i] += phi[i] * tcd;
+            }
+          }
         }
       }
     }
+  };
+  if (keep) {
+    final_pass(BoolTag<true>{});
+  } else {
+    final_pass(BoolTag<false>{});
   }
   if (bad) s_flags[2] = 1;
   if (want_next) {
@@ -342,29 +415,43 @@ __device__ __forceinline__ SolveOut solve_cell_block(const RF& rf, const double*
   __syncthreads();  // the block may be reused across calls
   axis_tables<N>(nodes, inv_dx, lam, opt.u0, s_nodes, s_c, s_dinv);
   __syncthreads();
-  // pass 1: fixed moment vectors of r and the moments of g0 (and g0b)
+  // pass 1: fixed moment vectors of r and the moments of g0 (and g0b); one
+  // instantiation per case so that the loads are unconditional
   double acc[35];
 #pragma unroll
   for (int i = 0; i < 35; ++i) acc[i] = 0.0;
+  auto pass1 = [&](auto with_b) {
+    constexpr bool WB = decltype(with_b)::value;
 #pragma unroll 8
-  for (int k = threadIdx.x; k < K; k += NT) {
-    const int a0 = k / (N * N);
-    const double v0 = s_nodes[a0], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
-    const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
-    const double c = s_c[a0], Dinv = s_dinv[a0];
-    const double rk = rf(k), gk = g0[k];
-    const double t0 = rk, t1 = rk * Dinv, t2 = c * rk * Dinv, t3 = gk, t4 = c * gk;
-    const double gb = g0b ? g0b[k] : 0.0;
+    for (int k = threadIdx.x; k < K; k += NT) {
+      const int a0 = k / (N * N);
+      const double v0 = s_nodes[a0], v1 = s_nodes[(k / N) % N], v2 = s_nodes[k % N];
+      const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+      const double c = s_c[a0], Dinv = s_dinv[a0];
+      const double rk = rf(k), gk = g0[k];
+      const double t0 = rk, t1 = rk * Dinv, t2 = c * rk * Dinv, t3 = gk, t4 = c * gk;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      acc[i] += phi[i] * t0;
-      acc[5 + i] += phi[i] * t1;
-      acc[10 + i] += phi[i] * t2;
-      acc[15 + i] += phi[i] * t3;
-      acc[20 + i] += phi[i] * t4;
-      acc[25 + i] += phi[i] * gb;
-      acc[30 + i] += phi[i] * c * gb;
+      for (int i = 0; i < 5; ++i) {
+        acc[i] += phi[i] * t0;
+        acc[5 + i] += phi[i] * t1;
+        acc[10 + i] += phi[i] * t2;
+        acc[15 + i] += phi[i] * t3;
+        acc[20 + i] += phi[i] * t4;
+      }
+      if constexpr (WB) {
+        const double gb = g0b[k];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          acc[25 + i] += phi[i] * gb;
+          acc[30 + i] += phi[i] * c * gb;
+        }
+      }
     }
+  };
+  if (g0b) {
+    pass1(BoolTag<true>{});
+  } else {
+    pass1(BoolTag<false>{});
   }
   if (g0b) {
     block_sum<35>(acc, s_red);

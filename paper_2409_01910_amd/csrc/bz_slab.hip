@@ -234,18 +234,16 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
 template <int N>
 struct RChain {
   const double* rs;
-  const double* fn;  // freshly updated upwind neighbour, or nullptr
-  const double* nodes;
-  double idx;
+  const double* fn;     // freshly updated upwind neighbour (any valid array when idx == 0)
+  const double* nodes;  // axis nodes (an LDS table in the scan kernel)
+  double idx;           // 1/dx, or 0 for the first cell of the scan (no neighbour term)
   int forward;
   double u0;
+  // branch-free, so that a batch of loads can be issued together
   __device__ __forceinline__ double operator()(int k) const {
-    double r = rs[k];
-    if (fn) {
-      const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
-      r += forward ? -fmax(v0, 0.0) * idx * fn[k] : fmin(v0, 0.0) * idx * fn[k];
-    }
-    return r;
+    const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
+    const double coef = forward ? -fmax(v0, 0.0) : fmin(v0, 0.0);
+    return rs[k] + coef * idx * fn[k];
   }
 };
 
@@ -284,7 +282,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
     __syncthreads();
     const double* fn = forward ? (j > 0 ? f + (size_t)(c - 1) * K : nullptr)
                                : (j < id.nx - 1 ? f + (size_t)(c + 1) * K : nullptr);
-    RChain<N> rf{rs + (size_t)c * K, fn, nodes, inv_dx, forward, opt.u0};
+    const double* rsc = rs + (size_t)c * K;
+    RChain<N> rf{rsc, fn ? fn : rsc, s_nodes, fn ? inv_dx : 0.0, forward, opt.u0};  // nodes from LDS
     double* fc = f + (size_t)c * K;
     VisitMoments vm;
     double eta[5];
