@@ -195,29 +195,47 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     s_dinv[threadIdx.x] = 1.0 / (cc + nu * ie);
   }
   __syncthreads();
+  // every source is read unconditionally (a valid pointer with weight 0 when a
+  // term is absent), so that the loads of several points are in flight together:
+  //   r = -wq (Q - nu (M - f)) - wb b + idx (v- sA A - v+ sB B)
+  // forward scan: A = old downstream neighbour (or the right ghost), B = the
+  // left ghost on the first cell; backward: B = the upstream neighbour from the
+  // forward scan (or the left ghost), A = the right ghost on the last cell
+  const double wq = bgk ? 0.0 : ie;
+  const double* Qc = bgk ? fc : Q + (size_t)c * K;
+  const double wb = bc ? 1.0 : 0.0;
+  const double* bp = bc ? bc : fc;
+  const double* A;
+  const double* B;
+  double sA, sB;
+  if (forward) {
+    A = fR ? fR : MR;
+    sA = fR ? 1.0 : gR;
+    B = ML;
+    sB = (j == 0) ? gL : 0.0;
+  } else {
+    B = fL ? fL : ML;
+    sB = fL ? 1.0 : gL;
+    A = MR;
+    sA = (j == id.nx - 1) ? gR : 0.0;
+  }
+  __shared__ double s_nodes[N];
+  if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
+  __syncthreads();
   double acc[25];
 #pragma unroll
   for (int q = 0; q < 25; ++q) acc[q] = 0.0;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += kCellThreads) {
     const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
-    const double v0 = nodes[a0], v1 = nodes[a1], v2 = nodes[a2];
+    const double v0 = s_nodes[a0], v1 = s_nodes[a1], v2 = s_nodes[a2];
     const double vp = fmax(v0 + u0, 0.0), vm = fmin(v0 + u0, 0.0);  // physical v_1
-    double r = 0.0;
-    if (!bgk) {
-      const double M = ea * s_E[0][a0] * s_E[1][a1] * s_E[2][a2];
-      r -= (Q[(size_t)c * K + k] - nu * (M - fc[k])) * ie;  // -P / eps
-    }
-    if (bc) r -= bc[k];
-    if (forward) {
-      r += vm * (fR ? fR[k] : gR * MR[k]) * idx;   // old downstream neighbour (or right wall)
-      if (j == 0) r -= vp * gL * ML[k] * idx;      // left wall ghost
-    } else {
-      r -= vp * (fL ? fL[k] : gL * ML[k]) * idx;   // neighbour from the forward scan (or left wall)
-      if (j == id.nx - 1) r += vm * gR * MR[k] * idx;  // right wall ghost
-    }
+    const double M = ea * s_E[0][a0] * s_E[1][a1] * s_E[2][a2];
+    const double fk = fc[k];
+    const double r = -wq * (Qc[k] - nu * (M - fk)) - wb * bp[k] + idx * (vm * sA * A[k] - vp * sB * B[k]);
     out[k] = r;
     const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
-    const double cc = s_c[a0], rd = r * s_dinv[a0], fk = fc[k];
+    const double cc = s_c[a0], rd = r * s_dinv[a0];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       acc[q] += phi[q] * r;
@@ -365,22 +383,27 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
   const double gL = ghost[i * 2], gR = ghost[i * 2 + 1];
   const double* ML = wallM + (size_t)i * 2 * K;
   const double* MR = ML + K;
+  // unconditional reads (valid pointers with weights), as in k_static_rhs
+  const double* Lp = fL ? fL : ML;
+  const double sL = fL ? 1.0 : gL;
+  const double* Rp = fR ? fR : MR;
+  const double sR = fR ? 1.0 : gR;
+  const double* Qc = bgk ? fc : Q + (size_t)c * K;
+  const double wq = bgk ? 0.0 : 1.0, wm = bgk ? 1.0 : 0.0;
+  const double* bp = bsrc ? bsrc + (size_t)c * K : fc;
+  const double wb = bsrc ? 1.0 : 0.0;
   double acc[1] = {0.0};
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += kCellThreads) {
     const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
     const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
-    const double left = fL ? fL[k] : gL * ML[k];
-    const double right = fR ? fR[k] : gR * MR[k];
-    double q;
-    if (bgk) {
-      const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
-      q = nu * (M - fc[k]);
-    } else {
-      q = Q[(size_t)c * K + k];
-    }
-    const double T = (vp * (fc[k] - left) + vm * (right - fc[k])) * idx - q * ie;
+    const double fk = fc[k];
+    const double left = sL * Lp[k], right = sR * Rp[k];
+    const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+    const double q = wq * Qc[k] + wm * nu * (M - fk);
+    const double T = (vp * (fk - left) + vm * (right - fk)) * idx - q * ie;
     if (Rout) Rout[(size_t)c * K + k] = T;
-    const double d = bsrc ? T - bsrc[(size_t)c * K + k] : T;
+    const double d = T - wb * bp[k];
     acc[0] += d * d;
   }
   block_sum<1>(acc, s_red);
