@@ -194,6 +194,11 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
 #pragma unroll
       for (int i = 0; i < 5; ++i) vm.cg[i] = lam * mom[i] - vm.R2[i];
       AxisW aw1{W_ONE, inv_dx, lam, opt.u0};
+      // start from M_theta: at the fixed point M[g] = M_theta
+      if (!fallback) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) eta[i] = th[i];
+      }
       if (newton_gauss(s_nodes, N, w, mg, eta, aw1, 1e-13, 60) < 0) newton_fail++;
       // residual lambda |M_theta - M[g^{k+1}]|_{L2}, separable form with its rounding bound
       double bnd;
@@ -388,11 +393,17 @@ __device__ __forceinline__ void axis_tables(const double* nodes, double inv_dx, 
   }
 }
 
-// Initial Maxwellian parameters from the moments of g^0 (wave 0).
+// Initial Maxwellian parameters from the moments of g^0 (wave 0); with guess
+// non-null Newton starts there (the parameters of M[g^0] if already known).
 template <int N>
 __device__ __forceinline__ int initial_eta(const double* s_nodes, double w, const double mg[5], double inv_dx,
-                                           double lam, double (&eta)[5]) {
-  theta_from_moments(mg, w, eta);
+                                           double lam, double (&eta)[5], const double* guess = nullptr) {
+  if (guess) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) eta[i] = guess[i];
+  } else {
+    theta_from_moments(mg, w, eta);
+  }
   AxisW aw{W_ONE, inv_dx, lam, 0.0};
   return newton_gauss(s_nodes, N, w, mg, eta, aw, 1e-13, 60) < 0 ? 1 : 0;
 }

@@ -167,13 +167,35 @@ __device__ __forceinline__ void half_wave_sums(double (&v)[NV], double (&lo)[NV]
   }
 }
 
+// Sums of NV values over the whole wave with DPP row moves: quad exchanges and
+// two row rotations give 16-lane row sums, row 0 is added into row 1 and row 2
+// into row 3, then lane 31 into rows 2 and 3; lane 63 holds the total.  Full
+// wave only.
+template <int NV>
+__device__ __forceinline__ void wave_sums_dpp(double (&v)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0xB1>(v[q]);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x4E>(v[q]);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x124>(v[q]);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x128>(v[q]);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x142, 0xA>(v[q]);  // row_bcast:15 into rows 1, 3
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] += dpp_move<0x143, 0xC>(v[q]);  // row_bcast:31 into rows 2, 3
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = read_lane(v[q], 63);
+}
+
 // Deterministic block sum of NV values per thread; result valid in all threads.
-// scratch must hold NV * (blockDim.x / 64) doubles.
+// scratch must hold NV * (blockDim.x / 64) doubles.  Every thread of the block
+// must take part.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  wave_sums_dpp<NV>(v);
   __syncthreads();
   if (lane == 0) {
 #pragma unroll

@@ -272,6 +272,7 @@ struct RChain {
 template <int N>
 __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double* __restrict__ rs,
                                                         const double* __restrict__ pre,
+                                                        const double* __restrict__ theta,
                                                         const double* __restrict__ nu, const InstDev* __restrict__ inst,
                                                         int forward, SolveArgs opt,
                                                         unsigned long long* __restrict__ stats,
@@ -316,7 +317,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
         vm.mg[q] = p[15 + q];
         vm.cg[q] = p[20 + q];
       }
-      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta);
+      // theta[c] holds the parameters of M[f_c] computed at the start of the
+      // scan, and f_c is still unchanged: Newton only confirms them
+      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta, theta + (size_t)c * 5);
     }
     NextMoments nx{has_next ? s_coef : nullptr, s_dinv_next, {}};
     const SolveOut o = solve_core<N, kChainThreads>(rf, fc, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
@@ -520,7 +523,8 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift));
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift};
-  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.nu,
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.theta,
+                                       L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
   L.q_valid = false;
