@@ -277,14 +277,16 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
     const int fA = 0, fB = NF - 1;
     const C* za = Z + (((size_t)b * NF + fA) * n_theta + thA) * K + (size_t)i1 * NN + q;
     const C* zb = Z + (((size_t)b * NF + fB) * n_theta + thB) * K + (size_t)i1 * NN + q;
-    T ar[N], ai[N], br[N], bi[N];
+    // a + i b with a = A P, b = B conj(P) (P carrying the sign sA) is
+    // Re = Pr (Ar - Bi) + Pi (Br - Ai), Im = Pr (Ai + Br) + Pi (Ar + Bi)
+    T u1[N], u2[N], u3[N], u4[N];
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       const C x = za[(size_t)l * N], y = zb[(size_t)l * N];
-      ar[l] = x.x;
-      ai[l] = x.y;
-      br[l] = y.x;
-      bi[l] = y.y;
+      u1[l] = x.x - y.y;
+      u2[l] = y.x - x.y;
+      u3[l] = x.y + y.x;
+      u4[l] = x.x + y.y;
     }
     const T sA = (v == 0) ? T(1) : T(-1);  // A uses P (v = 0) or conj(P) (v = 1)
     for (int rd = sub; rd < rounds; rd += S) {
@@ -295,16 +297,14 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
       if (active) {
         const C* p2 = ph23 + (size_t)pq * 2 * N;
         const C p3 = p2[N + q];
+        const T sp3x = sA * p3.x, sp3y = sA * p3.y;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
           const C a2 = p2[l];
           const T Pr = a2.x * p3.x - a2.y * p3.y;
-          const T Pi = sA * (a2.x * p3.y + a2.y * p3.x);
-          // a = A * P_A, bb = B * conj(P_A), C = a + i bb
-          const T a_r = ar[l] * Pr - ai[l] * Pi, a_i = ar[l] * Pi + ai[l] * Pr;
-          const T b_r = br[l] * Pr + bi[l] * Pi, b_i = bi[l] * Pr - br[l] * Pi;
-          re[l] = a_r - b_i;
-          im[l] = a_i + b_r;
+          const T Pi = a2.x * sp3y + a2.y * sp3x;
+          re[l] = Pr * u1[l] + Pi * u2[l];
+          im[l] = Pr * u3[l] + Pi * u4[l];
         }
         fft_reg<T, N, +1>(re, im);  // along axis 1
 #pragma unroll
@@ -480,14 +480,19 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
     const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
     const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
     const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
-    T ar[16], ai[16], br[16], bi[16];
+    // with P = Pr + i Pi (Pi carrying the sign sA), a = A P and b = B conj(P),
+    // the combined field a + i b is
+    //   Re = Pr (Ar - Bi) + Pi (Br - Ai),   Im = Pr (Ai + Br) + Pi (Ar + Bi),
+    // so the four sums are formed once per item and each azimuth costs two
+    // FMA pairs per entry
+    T u1[16], u2[16], u3[16], u4[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const C x = za[(size_t)m * N], y = zb[(size_t)m * N];
-      ar[m] = x.x;
-      ai[m] = x.y;
-      br[m] = y.x;
-      bi[m] = y.y;
+      u1[m] = x.x - y.y;
+      u2[m] = y.x - x.y;
+      u3[m] = x.y + y.x;
+      u4[m] = x.x + y.y;
     }
     const T sA = (v == 0) ? T(1) : T(-1);
     const int phi_step = (NF == 2) ? 1 : 2;
@@ -496,16 +501,15 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
       const int pq = tp * n_phi + jj;
       const C* p2 = ph23 + (size_t)pq * 2 * N;
       const C p3 = p2[N + q];
+      const T p3x = p3.x, p3y = p3.y, sp3x = sA * p3.x, sp3y = sA * p3.y;
       T re[16], im[16];
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const C a2 = p2[16 * h + m];
-        const T Pr = a2.x * p3.x - a2.y * p3.y;
-        const T Pi = sA * (a2.x * p3.y + a2.y * p3.x);
-        const T a_r = ar[m] * Pr - ai[m] * Pi, a_i = ar[m] * Pi + ai[m] * Pr;
-        const T b_r = br[m] * Pr + bi[m] * Pi, b_i = bi[m] * Pr - br[m] * Pi;
-        re[m] = a_r - b_i;
-        im[m] = a_i + b_r;
+        const T Pr = a2.x * p3x - a2.y * p3y;
+        const T Pi = a2.x * sp3y + a2.y * sp3x;
+        re[m] = Pr * u1[m] + Pi * u2[m];
+        im[m] = Pr * u3[m] + Pi * u4[m];
       }
       dif32_pair<T>(re, im, ptw);
       fft_reg<T, 16, +1>(re, im);  // lane h: rows i2 = 2k + h of column q
