@@ -72,8 +72,10 @@ def solve_weighted_gaussian(spec: Spec, target: np.ndarray, weight: np.ndarray |
     scale = np.abs(target[0]) + np.abs(target[-1]) + 1e-300
 
     def F(th):
-        g = np.exp(th[0] + v @ th[1 : 1 + spec.d] - th[-1] * (v * v).sum(1))
-        return spec.w * phi.T @ (c * g) - target, g
+        # a trial step may overflow; the backtracking below rejects non-finite residuals
+        with np.errstate(over="ignore", invalid="ignore"):
+            g = np.exp(th[0] + v @ th[1 : 1 + spec.d] - th[-1] * (v * v).sum(1))
+            return spec.w * phi.T @ (c * g) - target, g
 
     r, g = F(theta)
     nrm = np.max(np.abs(r))
@@ -81,7 +83,13 @@ def solve_weighted_gaussian(spec: Spec, target: np.ndarray, weight: np.ndarray |
         if nrm <= tol * scale:
             return theta, it, True
         J = spec.w * (phi * (c * g)[:, None]).T @ pt
-        step = np.linalg.solve(J, -r)
+        if not np.isfinite(J).all():
+            return theta, it, False
+        try:
+            step = np.linalg.solve(J, -r)
+        except np.linalg.LinAlgError:
+            # a singular Jacobian is a Newton failure, not an error of the caller
+            return theta, it, False
         t = 1.0
         while True:
             th_new = theta + t * step
