@@ -369,85 +369,48 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
 }
 
 // ------------------------------------------------------------------ direction pairs, N = 32
-// Same computation as k_pairs, with each 32-point column split over two
-// adjacent lanes (lane = 2 q + h holds entries 16 h .. 16 h + 15 of column q).
-// One radix-2 decimation-in-frequency step, with the partner's half taken by
-// a lane-pair exchange, leaves two independent 16-point transforms: lane h
-// produces the outputs of parity h.  Halving the per-lane state lets two waves
-// share a SIMD.  A wave owns one (polar pair, variant) item - for the plain
-// form the second index splits the azimuths by parity instead - and runs all
-// of its azimuths with the A/B columns kept in registers.
+// Same computation as k_pairs.  A wave owns one (polar pair, variant) item -
+// for the plain form the second index splits the azimuths by parity instead -
+// keeps the item's four per-entry sums in registers and runs its azimuths.
+// The 32x32 inverse transform of one azimuth is done in three register stages
+// of 16 values per lane, joined by two exchanges through the wave's LDS tile:
+//   stage 1, lane (q, h): column i3 = q, entries i2 = 2m + h.  Phase products,
+//            then the 16-point transform over m: the even (h = 0) or odd
+//            (h = 1) half of a radix-2 decimation in time along axis 2.
+//   stage 2, lane (k, c): the radix-2 step of axis 2, E + W^k O and
+//            E - W^k O for rows k and k + 16, at columns i3 = c + 4j; then
+//            8-point transforms over j (axis 3 split as 4 x 8 in time).
+//   stage 3, lane (rg, k'): rows i2 = rg + 8g; the twiddles W^(c k') and
+//            4-point transforms over c give columns i3 = k' + 8t.
+// No stage moves data between lanes by lane permutes, and no lane computes a
+// twiddle it does not use.
 constexpr int kPair32Waves = 8;
 
 template <typename T>
 constexpr size_t pairs32_lds_bytes() {
-  return (size_t)kPair32Waves * 32 * 33 * sizeof(typename V2<T>::type) + (size_t)32 * 32 * sizeof(T);
+  return (size_t)(kPair32Waves * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)32 * 32 * sizeof(T);
 }
 
-// y <- first DIF step of a 32-point inverse DFT whose entries 16h+m live in
-// lane h of a lane pair; afterwards lane h holds the 16-point input whose
-// inverse DFT gives outputs 2k + h.
-// value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]
-__device__ __forceinline__ float swap_pair(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double swap_pair(double x) {
-  const long long u = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0xB1, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
+// e^{2 pi i n / 32}, n = 0..31, for the per-lane twiddles of stages 2 and 3
+constexpr Twiddle<32> kTw32{};
 
-// y <- first DIF step of a 32-point inverse DFT whose entries 16h+m live in
-// lane h of a lane pair; afterwards lane h holds the 16-point input whose
-// inverse DFT gives outputs 2k + h:
-//   y = (partner + sg * own) * t_h(m),  sg = 1 - 2h,  t_0 = 1,  t_1 = W^m,
-// W = e^{2 pi i / 32}, i.e. C(m) + C(m+16) on lane 0 and (C(m) - C(m+16)) W^m on
-// lane 1.  In FP64 the per-lane twiddle is formed from the lane bit hd = h as
-// t_h = (1 + hd (cos - 1), hd sin), so the step is branch-free: two FMAs for the
-// butterfly, two for the twiddle and one complex product per entry (a select
-// of a double costs two instructions).  In FP32 a select per value is cheaper.
-template <typename T>
-struct PairTwiddle {
-  T sg, hd;
-  __device__ __forceinline__ explicit PairTwiddle(int h) : sg(h ? T(-1) : T(1)), hd(h ? T(1) : T(0)) {}
-};
+// Slots of the wave's tile, 33 slots per row.  Every slot is a lane base plus
+// a compile-time offset, so a stage's 16 accesses share one address register.
+// With the lane roles of the kernel, each access pattern (a stage's writes,
+// the next stage's reads) touches distinct slots modulo 8 in every 8
+// consecutive lanes and modulo 16 in every 16, so 16-byte accesses spread
+// over all LDS banks (checked by enumeration over all patterns).
+// stage-1 output: half h, frequency k, column q
+__device__ __forceinline__ int s1_slot(int h, int k, int q) { return h * 528 + k * 33 + q; }
+// stage-2 output: row r, column c + 4 kp
+__device__ __forceinline__ int s2_slot(int r, int c, int kp) { return r * 33 + c + 4 * kp; }
+constexpr int kPair32Tile = 1056;
 
 template <typename T>
-__device__ __forceinline__ void dif32_pair(T* re, T* im, const PairTwiddle<T>& pt) {
-  constexpr Twiddle<32> tw{};
-  if constexpr (sizeof(T) == 8) {
-    // FMA butterfly (one instruction per component), the lane-1 twiddle product
-    // with constant factors, then a select per component
-    const bool odd = pt.hd != T(0);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
-      const T tr = fma(pt.sg, re[m], pr), ti = fma(pt.sg, im[m], pi);
-      if (m == 0) {
-        re[m] = tr;
-        im[m] = ti;
-      } else {
-        const T c = T(tw.c[m]), sn = T(tw.s[m]);
-        const T xr = tr * c - ti * sn, xi = tr * sn + ti * c;
-        re[m] = odd ? xr : tr;
-        im[m] = odd ? xi : ti;
-      }
-    }
-  } else {
-    // FP32: both branch results, then one select per value
-    const bool odd = pt.hd != T(0);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const T pr = swap_pair(re[m]), pi = swap_pair(im[m]);
-      const T sr = re[m] + pr, si = im[m] + pi;
-      const T dr = pr - re[m], di = pi - im[m];
-      const T c = T(tw.c[m]), sn = T(tw.s[m]);
-      const T tr = dr * c - di * sn, ti = dr * sn + di * c;
-      re[m] = odd ? tr : sr;
-      im[m] = odd ? ti : si;
-    }
-  }
+__device__ __forceinline__ void cmul(T& xr, T& xi, T wr, T wi) {
+  const T r = xr * wr - xi * wi;
+  xi = xr * wi + xi * wr;
+  xr = r;
 }
 
 template <typename T, int NF>
@@ -458,13 +421,19 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
   using C = typename V2<T>::type;
   constexpr int N = 32, K = N * N * N, NN = N * N, LD = N + 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  C* trans = reinterpret_cast<C*>(smem);
-  T* red = reinterpret_cast<T*>(smem + (size_t)kPair32Waves * N * LD * sizeof(C));
+  C* tiles = reinterpret_cast<C*>(smem);
+  C* twl = tiles + (size_t)kPair32Waves * kPair32Tile;  // e^{2 pi i n / 32}
+  T* red = reinterpret_cast<T*>(twl + 32);
   const int b = blockIdx.x / N, i1 = blockIdx.x % N;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const int q = ln >> 1, h = ln & 1;
-  C* tw = trans + (size_t)wv * N * LD;
-  const PairTwiddle<T> ptw(h);
+  // wave index made uniform, so that per-item and per-azimuth values load once
+  // per wave through the scalar unit
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
+  const int q = ln & 31, h = ln >> 5;     // stage 1
+  const int k2 = ln & 15, c2 = ln >> 4;   // stage 2
+  const int kp = (ln & 1) | ((ln >> 2) & 6), rg = ((ln >> 1) & 3) | ((ln >> 3) & 4);  // stage 3
+  C* tile = tiles + (size_t)wv * kPair32Tile;
+  if (threadIdx.x < 32) twl[threadIdx.x] = C{T(kTw32.c[threadIdx.x]), T(kTw32.s[threadIdx.x])};
+  __syncthreads();
   T acc[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = T(0);
@@ -478,52 +447,111 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
     const int tp = it >> 1, v = (NF == 2) ? (it & 1) : 0;
     const int tA = half + tp, tB = half - 1 - tp;
     const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
-    const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
-    const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * K + (size_t)i1 * NN + (size_t)(16 * h) * N + q;
-    // with P = Pr + i Pi (Pi carrying the sign sA), a = A P and b = B conj(P),
-    // the combined field a + i b is
-    //   Re = Pr (Ar - Bi) + Pi (Br - Ai),   Im = Pr (Ai + Br) + Pi (Ar + Bi),
+    const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * K + (size_t)i1 * NN + (size_t)h * N + q;
+    const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * K + (size_t)i1 * NN + (size_t)h * N + q;
+    // with the phase P = Pr + i Pi, the sign sA of the item, a = A P' and
+    // b = B conj(P'), P' = Pr + i sA Pi, the combined field a + i b is
+    //   Re = Pr (Ar - Bi) + Pi sA (Br - Ai),   Im = Pr (Ai + Br) + Pi sA (Ar + Bi),
     // so the four sums are formed once per item and each azimuth costs two
     // FMA pairs per entry
+    const T sA = (v == 0) ? T(1) : T(-1);
     T u1[16], u2[16], u3[16], u4[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const C x = za[(size_t)m * N], y = zb[(size_t)m * N];
+      const C x = za[(size_t)(2 * m) * N], y = zb[(size_t)(2 * m) * N];
       u1[m] = x.x - y.y;
-      u2[m] = y.x - x.y;
+      u2[m] = sA * (y.x - x.y);
       u3[m] = x.y + y.x;
-      u4[m] = x.x + y.y;
+      u4[m] = sA * (x.x + y.y);
     }
-    const T sA = (v == 0) ? T(1) : T(-1);
     const int phi_step = (NF == 2) ? 1 : 2;
     const int phi0 = ((NF == 2) ? 0 : (it & 1)) + sub * phi_step;
     for (int jj = phi0; jj < n_phi; jj += phi_step * S) {
       const int pq = tp * n_phi + jj;
       const C* p2 = ph23 + (size_t)pq * 2 * N;
       const C p3 = p2[N + q];
-      const T p3x = p3.x, p3y = p3.y, sp3x = sA * p3.x, sp3y = sA * p3.y;
       T re[16], im[16];
+      // stage 1
+      if constexpr (sizeof(T) == 8) {
+        // The row phase of row i2 is z^l, l its signed frequency and z = p2[1]
+        // (the table entry of frequency 1), so the phases of rows 2m + h follow
+        // from P(h) and P(16 + h) by two chains of products with z^2 (error
+        // growth of a few ulp over seven steps).  This replaces sixteen table
+        // loads per azimuth, which the register budget would serialise.
+        const C zz = p2[2];
+        const C a0 = p2[h], a8 = p2[16 + h];
+        T ar = a0.x * p3.x - a0.y * p3.y, ai = a0.x * p3.y + a0.y * p3.x;
+        T br = a8.x * p3.x - a8.y * p3.y, bi = a8.x * p3.y + a8.y * p3.x;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const C a2 = p2[16 * h + m];
-        const T Pr = a2.x * p3x - a2.y * p3y;
-        const T Pi = a2.x * sp3y + a2.y * sp3x;
-        re[m] = Pr * u1[m] + Pi * u2[m];
-        im[m] = Pr * u3[m] + Pi * u4[m];
+        for (int m = 0; m < 8; ++m) {
+          re[m] = ar * u1[m] + ai * u2[m];
+          im[m] = ar * u3[m] + ai * u4[m];
+          re[8 + m] = br * u1[8 + m] + bi * u2[8 + m];
+          im[8 + m] = br * u3[8 + m] + bi * u4[8 + m];
+          if (m < 7) {
+            cmul(ar, ai, zz.x, zz.y);
+            cmul(br, bi, zz.x, zz.y);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const C a2 = p2[2 * m + h];
+          const T Pr = a2.x * p3.x - a2.y * p3.y;
+          const T Pi = a2.x * p3.y + a2.y * p3.x;
+          re[m] = Pr * u1[m] + Pi * u2[m];
+          im[m] = Pr * u3[m] + Pi * u4[m];
+        }
       }
-      dif32_pair<T>(re, im, ptw);
-      fft_reg<T, 16, +1>(re, im);  // lane h: rows i2 = 2k + h of column q
+      fft_reg<T, 16, +1>(re, im);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) tw[(2 * k + h) * LD + q] = C{re[k], im[k]};
+      for (int k = 0; k < 16; ++k) tile[s1_slot(h, k, q)] = C{re[k], im[k]};
+      wave_sync();
+      // stage 2: re/im[j] row k2, re/im[8 + j] row k2 + 16, column c2 + 4j
+      // (the per-lane twiddles are read from LDS each time: kept in registers
+      // across the loop they would cost spills in FP64)
+      const C wk = twl[k2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const C e = tile[s1_slot(0, k2, c2 + 4 * j)], o = tile[s1_slot(1, k2, c2 + 4 * j)];
+        T tr = o.x, ti = o.y;
+        cmul(tr, ti, wk.x, wk.y);
+        re[j] = e.x + tr;
+        im[j] = e.y + ti;
+        re[8 + j] = e.x - tr;
+        im[8 + j] = e.y - ti;
+      }
+      fft_reg<T, 8, +1>(re, im);
+      fft_reg<T, 8, +1>(re + 8, im + 8);
       wave_sync();
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const C x = tw[q * LD + 16 * h + m];  // row i2 = q, entries l3 = 16h + m
-        re[m] = x.x;
-        im[m] = x.y;
+      for (int j = 0; j < 8; ++j) {
+        tile[s2_slot(k2, c2, j)] = C{re[j], im[j]};
+        tile[s2_slot(k2 + 16, c2, j)] = C{re[8 + j], im[8 + j]};
       }
-      dif32_pair<T>(re, im, ptw);
-      fft_reg<T, 16, +1>(re, im);  // lane h: c(q, i3 = 2k + h)
+      wave_sync();
+      // stage 3: row rg + 8g, column kp + 8t in entry 4g + t
+      const C w1 = twl[kp], w2 = twl[2 * kp], w3 = twl[3 * kp];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int r = rg + 8 * g;
+        const C z0 = tile[s2_slot(r, 0, kp)], z1 = tile[s2_slot(r, 1, kp)];
+        const C z2 = tile[s2_slot(r, 2, kp)], z3 = tile[s2_slot(r, 3, kp)];
+        T x1r = z1.x, x1i = z1.y, x2r = z2.x, x2i = z2.y, x3r = z3.x, x3i = z3.y;
+        cmul(x1r, x1i, w1.x, w1.y);
+        cmul(x2r, x2i, w2.x, w2.y);
+        cmul(x3r, x3i, w3.x, w3.y);
+        const T ar = z0.x + x2r, ai = z0.y + x2i, br = z0.x - x2r, bi = z0.y - x2i;
+        const T cr = x1r + x3r, ci = x1i + x3i, dr = x1r - x3r, di = x1i - x3i;
+        re[4 * g + 0] = ar + cr;
+        im[4 * g + 0] = ai + ci;
+        re[4 * g + 2] = ar - cr;
+        im[4 * g + 2] = ai - ci;
+        re[4 * g + 1] = br - di;  // b + i d
+        im[4 * g + 1] = bi + dr;
+        re[4 * g + 3] = br + di;  // b - i d
+        im[4 * g + 3] = bi - dr;
+      }
       const T wgt = pairw[pq] * T(NF == 1 ? 2 : 1);
 #pragma unroll
       for (int k = 0; k < 16; ++k) acc[k] += wgt * re[k] * im[k];
@@ -533,14 +561,17 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
   for (int w2 = 0; w2 < kPair32Waves; ++w2) {
     if (wv == w2) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        T* dst = red + q * N + 2 * k + h;
-        *dst = (w2 == 0 ? T(0) : *dst) + acc[k];
-      }
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          T* dst = red + (rg + 8 * g) * N + kp + 8 * t;
+          *dst = (w2 == 0 ? T(0) : *dst) + acc[4 * g + t];
+        }
     }
     __syncthreads();
   }
   // forward 2D transform of the accumulated real plane (axes 1 and 2)
+  C* trans = tiles;
   if (threadIdx.x < N) {
     const int row = threadIdx.x;
     T re[N], im[N];
