@@ -26,11 +26,13 @@ struct bz_ctx {
   double* d_ph1 = nullptr;     // [n_rho][n_theta][N] complex: exp(i xi_l rho c_t / 2)
   double* d_ph23 = nullptr;    // [n_rho][n_pairs][2][N] complex: exp(i xi_l s_2), exp(i xi_l s_3)
   double* d_pairw = nullptr;   // [n_pairs]
+  double* d_pairsw = nullptr;  // [n_pairs] sqrt of d_pairw
   double* d_W = nullptr;       // [n_rho][K] gain radial weights / K
   double* d_Gm = nullptr;      // [K] loss weight
   float* d_ph1_f = nullptr;
   float* d_ph23_f = nullptr;
   float* d_pairw_f = nullptr;
+  float* d_pairsw_f = nullptr;
   float* d_W_f = nullptr;
   float* d_Gm_f = nullptr;
 

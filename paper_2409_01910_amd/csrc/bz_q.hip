@@ -388,7 +388,7 @@ constexpr int kPair32Waves = 8;
 
 template <typename T>
 constexpr size_t pairs32_lds_bytes() {
-  return (size_t)(kPair32Waves * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)32 * 32 * sizeof(T);
+  return (size_t)(kPair32Waves * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)kPair32Waves * 64 * 6 * sizeof(T);
 }
 
 // e^{2 pi i n / 32}, n = 0..31, for the per-lane twiddles of stages 2 and 3
@@ -417,13 +417,18 @@ template <typename T, int NF>
 __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2<T>::type* __restrict__ Z,
                                                                typename V2<T>::type* __restrict__ Acc, int n_theta,
                                                                int n_phi, const typename V2<T>::type* __restrict__ ph23,
-                                                               const T* __restrict__ pairw) {
+                                                               const T* __restrict__ pairsw) {
   using C = typename V2<T>::type;
   constexpr int N = 32, K = N * N * N, NN = N * N, LD = N + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   C* tiles = reinterpret_cast<C*>(smem);
   C* twl = tiles + (size_t)kPair32Waves * kPair32Tile;  // e^{2 pi i n / 32}
-  T* red = reinterpret_cast<T*>(twl + 32);
+  // part of the per-item sums live in LDS instead of registers (FP64 has no
+  // register left for them): [wave][u1 u2 (m = 15) | u3 u4 (m = 15) | u1 u2
+  // (m = 14)][lane], 16-byte pairs
+  C* ulast = twl + 32;
+  // the accumulated plane reuses the wave tiles once every wave is done
+  T* red = reinterpret_cast<T*>(tiles);
   const int b = blockIdx.x / N, i1 = blockIdx.x % N;
   // wave index made uniform, so that per-item and per-azimuth values load once
   // per wave through the scalar unit
@@ -455,21 +460,42 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
     // so the four sums are formed once per item and each azimuth costs two
     // FMA pairs per entry
     const T sA = (v == 0) ? T(1) : T(-1);
-    T u1[16], u2[16], u3[16], u4[16];
+    T u1[16], u2[16], u3[16], u4[16];  // entries 14 (u1, u2) and 15 unused
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < 15; ++m) {
       const C x = za[(size_t)(2 * m) * N], y = zb[(size_t)(2 * m) * N];
-      u1[m] = x.x - y.y;
-      u2[m] = sA * (y.x - x.y);
+      if (m < 14) {
+        u1[m] = x.x - y.y;
+        u2[m] = sA * (y.x - x.y);
+      }
       u3[m] = x.y + y.x;
       u4[m] = sA * (x.x + y.y);
     }
+    C* ul = ulast + (size_t)wv * 192 + ln;
+    {
+      const C x = za[(size_t)30 * N], y = zb[(size_t)30 * N];
+      ul[0] = C{x.x - y.y, sA * (y.x - x.y)};
+      ul[64] = C{x.y + y.x, sA * (x.x + y.y)};
+      const C x14 = za[(size_t)28 * N], y14 = zb[(size_t)28 * N];
+      ul[128] = C{x14.x - y14.y, sA * (y14.x - x14.y)};
+    }
     const int phi_step = (NF == 2) ? 1 : 2;
     const int phi0 = ((NF == 2) ? 0 : (it & 1)) + sub * phi_step;
-    for (int jj = phi0; jj < n_phi; jj += phi_step * S) {
+    const int jstep = phi_step * S;
+    // the column phase of the next azimuth is loaded one azimuth ahead (the
+    // index is clamped, so the last load repeats a valid entry)
+    C p3n = ph23[((size_t)(tp * n_phi + (phi0 < n_phi ? phi0 : 0)) * 2 + 1) * N + q];
+    for (int jj = phi0; jj < n_phi; jj += jstep) {
       const int pq = tp * n_phi + jj;
       const C* p2 = ph23 + (size_t)pq * 2 * N;
-      const C p3 = p2[N + q];
+      // the pair weight w enters as sqrt(w) on the field, so that the
+      // accumulation is one FMA per entry
+      const T sw = pairsw[pq] * T(NF == 1 ? 1.4142135623730950488 : 1.0);
+      const T p3x = p3n.x * sw, p3y = p3n.y * sw;
+      {
+        const int jn = (jj + jstep < n_phi) ? jj + jstep : jj;
+        p3n = ph23[((size_t)(tp * n_phi + jn) * 2 + 1) * N + q];
+      }
       T re[16], im[16];
       // stage 1
       if constexpr (sizeof(T) == 8) {
@@ -477,30 +503,50 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
         // (the table entry of frequency 1), so the phases of rows 2m + h follow
         // from P(h) and P(16 + h) by two chains of products with z^2 (error
         // growth of a few ulp over seven steps).  This replaces sixteen table
-        // loads per azimuth, which the register budget would serialise.
-        const C zz = p2[2];
-        const C a0 = p2[h], a8 = p2[16 + h];
-        T ar = a0.x * p3.x - a0.y * p3.y, ai = a0.x * p3.y + a0.y * p3.x;
-        T br = a8.x * p3.x - a8.y * p3.y, bi = a8.x * p3.y + a8.y * p3.x;
+        // loads per azimuth, which the register budget would serialise.  All
+        // four table entries used are the same for the whole wave.
+        const C z1 = p2[1], zz = p2[2], c16 = p2[16], c17 = p2[17];
+        const T a0x = h ? z1.x : T(1), a0y = h ? z1.y : T(0);  // p2[0] = 1
+        const T a8x = h ? c17.x : c16.x, a8y = h ? c17.y : c16.y;
+        T ar = a0x * p3x - a0y * p3y, ai = a0x * p3y + a0y * p3x;
+        T br = a8x * p3x - a8y * p3y, bi = a8x * p3y + a8y * p3x;
+        const C v12 = ul[0], v34 = ul[64], w12 = ul[128];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
           re[m] = ar * u1[m] + ai * u2[m];
           im[m] = ar * u3[m] + ai * u4[m];
-          re[8 + m] = br * u1[8 + m] + bi * u2[8 + m];
-          im[8 + m] = br * u3[8 + m] + bi * u4[8 + m];
+          if (m < 6) {
+            re[8 + m] = br * u1[8 + m] + bi * u2[8 + m];
+            im[8 + m] = br * u3[8 + m] + bi * u4[8 + m];
+          } else if (m == 6) {
+            re[14] = br * w12.x + bi * w12.y;
+            im[14] = br * u3[14] + bi * u4[14];
+          } else {
+            re[15] = br * v12.x + bi * v12.y;
+            im[15] = br * v34.x + bi * v34.y;
+          }
           if (m < 7) {
             cmul(ar, ai, zz.x, zz.y);
             cmul(br, bi, zz.x, zz.y);
           }
         }
       } else {
+        const C v12 = ul[0], v34 = ul[64], w12 = ul[128];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
           const C a2 = p2[2 * m + h];
-          const T Pr = a2.x * p3.x - a2.y * p3.y;
-          const T Pi = a2.x * p3.y + a2.y * p3.x;
-          re[m] = Pr * u1[m] + Pi * u2[m];
-          im[m] = Pr * u3[m] + Pi * u4[m];
+          const T Pr = a2.x * p3x - a2.y * p3y;
+          const T Pi = a2.x * p3y + a2.y * p3x;
+          if (m < 14) {
+            re[m] = Pr * u1[m] + Pi * u2[m];
+            im[m] = Pr * u3[m] + Pi * u4[m];
+          } else if (m == 14) {
+            re[14] = Pr * w12.x + Pi * w12.y;
+            im[14] = Pr * u3[14] + Pi * u4[14];
+          } else {
+            re[15] = Pr * v12.x + Pi * v12.y;
+            im[15] = Pr * v34.x + Pi * v34.y;
+          }
         }
       }
       fft_reg<T, 16, +1>(re, im);
@@ -552,12 +598,12 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
         re[4 * g + 3] = br + di;  // b - i d
         im[4 * g + 3] = bi - dr;
       }
-      const T wgt = pairw[pq] * T(NF == 1 ? 2 : 1);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc[k] += wgt * re[k] * im[k];
+      for (int k = 0; k < 16; ++k) acc[k] += re[k] * im[k];
       wave_sync();
     }
   }
+  __syncthreads();  // every wave is done with its tile before red overwrites them
   for (int w2 = 0; w2 < kPair32Waves; ++w2) {
     if (wv == w2) {
 #pragma unroll
@@ -570,8 +616,9 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
     }
     __syncthreads();
   }
-  // forward 2D transform of the accumulated real plane (axes 1 and 2)
-  C* trans = tiles;
+  // forward 2D transform of the accumulated real plane (axes 1 and 2), through
+  // a transpose buffer placed after red
+  C* trans = tiles + NN / 2;
   if (threadIdx.x < N) {
     const int row = threadIdx.x;
     T re[N], im[N];
@@ -708,6 +755,9 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   const C* ph1 = (const C*)(f64 ? (const void*)ctx->d_ph1 : (const void*)ctx->d_ph1_f);
   const C* ph23 = (const C*)(f64 ? (const void*)ctx->d_ph23 : (const void*)ctx->d_ph23_f);
   const T* pairw = (const T*)(f64 ? (const void*)ctx->d_pairw : (const void*)ctx->d_pairw_f);
+  const T* pairsw = (const T*)(f64 ? (const void*)ctx->d_pairsw : (const void*)ctx->d_pairsw_f);
+  // the N = 32 kernel takes sqrt of the pair weights, the general one the weights
+  const T* pw = (N == 32) ? pairsw : pairw;
   const T* W = (const T*)(f64 ? (const void*)ctx->d_W : (const void*)ctx->d_W_f);
   const T* Gm = (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
   constexpr int PPB = plane_ppb<T, N>();
@@ -735,7 +785,7 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
       if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
       {
-        void* args[] = {(void*)&Z, (void*)&Acc, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pairw};
+        void* args[] = {(void*)&Z, (void*)&Acc, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pw};
         BZ_HIP(hipLaunchKernel(kp, dim3((unsigned)(B * N)), dim3(pair_threads), args, lds, st));
       }
       if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nf * job_flops)) != BZ_OK) return s;

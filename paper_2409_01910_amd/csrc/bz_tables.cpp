@@ -142,11 +142,15 @@ bz_status build_tables(bz_ctx* ctx) {
   if ((s = upload(ctx, &ctx->d_ph1, ph1)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_ph23, ph23)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_pairw, ctx->h_pair_w)) != BZ_OK) return s;
+  std::vector<double> pair_sw(npairs);
+  for (int q = 0; q < npairs; ++q) pair_sw[q] = std::sqrt(ctx->h_pair_w[q]);
+  if ((s = upload(ctx, &ctx->d_pairsw, pair_sw)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_W, W)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_Gm, Gm)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_ph1_f, ph1)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_ph23_f, ph23)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_pairw_f, ctx->h_pair_w)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_pairsw_f, pair_sw)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_W_f, W)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_Gm_f, Gm)) != BZ_OK) return s;
   ctx->n_pairs = npairs;
@@ -154,8 +158,9 @@ bz_status build_tables(bz_ctx* ctx) {
 }
 
 void free_tables(bz_ctx* ctx) {
-  void* ptrs[] = {ctx->d_nodes, ctx->d_ph1, ctx->d_ph23, ctx->d_pairw, ctx->d_W, ctx->d_Gm,
-                  ctx->d_ph1_f, ctx->d_ph23_f, ctx->d_pairw_f, ctx->d_W_f, ctx->d_Gm_f};
+  void* ptrs[] = {ctx->d_nodes,  ctx->d_ph1,   ctx->d_ph23,     ctx->d_pairw,      ctx->d_pairsw, ctx->d_W,
+                  ctx->d_Gm,     ctx->d_ph1_f, ctx->d_ph23_f,   ctx->d_pairw_f,    ctx->d_pairsw_f,
+                  ctx->d_W_f,    ctx->d_Gm_f};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
