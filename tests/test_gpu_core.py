@@ -226,8 +226,9 @@ def test_cell_fixed_point_matches_oracle_composition(dev):
     assert checked > 0
 
 
-# N = 32 uses the lane-pair kernel; cover every wave/item mapping: polar pairs
-# 1, 2, 4 (idle and busy waves), odd azimuth counts per parity, both forms.
+# N = 32 uses the three-stage pair kernel; cover every wave/item mapping:
+# polar pairs 1, 2, 4 (azimuths of an item split over several waves, idle and
+# busy waves), odd azimuth counts per parity, both forms.
 N32_CASES = [(2, 4, 2), (4, 6, 2), (8, 4, 1)]
 
 
@@ -246,6 +247,26 @@ def test_eval_q_n32_matches_oracle(dev, rule, corrected):
         ref = OQ.q_corrected(sp, f[i]) if corrected else gain - loss
         scale = max(np.abs(ref).max(), np.abs(loss).max())
         assert _rel(Qg[i], ref, scale) < 1e-12
+
+
+@pytest.mark.parametrize("rule", N32_CASES)
+@pytest.mark.parametrize("corrected", [False, True])
+def test_eval_q_n32_fp32_error_bound(dev, rule, corrected):
+    # the FP32 build of the same kernel reads its row phases from the table
+    nt, nph, nr = rule
+    N, L, B = 32, 8.0, 2
+    print(f"eval_Q FP32 N=32 M={nt}x{nph} n_rho={nr} corrected={corrected}", flush=True)
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=25)
+    ctx = _ctx(N, L, nt, nph, nr, prec=1)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=corrected).cpu().numpy()
+    for i in range(B):
+        gain, loss = OQ.q_fsm(sp, f[i], parts=True)
+        ref = OQ.q_corrected(sp, f[i]) if corrected else gain - loss
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        err = _rel(Qg[i], ref, scale)
+        print("fp32 rel err", err, flush=True)
+        assert err < 2e-6
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])

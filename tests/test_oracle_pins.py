@@ -215,6 +215,19 @@ def test_pfp_falls_back_when_existence_fails():
     assert not st.fallback
 
 
+def test_weighted_newton_reports_a_singular_jacobian_as_failure():
+    # Step 1 with a weight that leaves fewer than d + 2 nodes has a singular
+    # Jacobian; that is a Newton failure, after which the visit falls back
+    # (Section 3.2), not an error
+    sp = Spec(d=3, N=8, L=6.0, n_theta=2, n_phi=4, n_rho=2)
+    target = MX.moments(sp, MX.gaussian(sp, MX.theta_from_macro(sp, 1.0, np.zeros(3), 1.0)))
+    for keep in (0, 1):
+        c = np.zeros(sp.K)
+        c[:keep] = 1.0
+        _, _, ok = MX.solve_weighted_gaussian(sp, target, weight=c)
+        assert not ok
+
+
 def test_large_eps_limit():
     # eps -> infinity: (|v_1|/dx) g = -r wherever v_1 != 0
     sp, r, nu, g0, dx = _cell_case()
