@@ -62,7 +62,26 @@ typedef struct bz_ctx bz_ctx;
  *            Fields, moments, Maxwellian parameters (theta) and the collision
  *            operator (translation invariant) are all in v'; transport uses the
  *            physical v_1 = v'_1 + v1_shift (c = |v_1|/dx, upwind split, wall
- *            fluxes).  0 for a grid centred on rest. */
+ *            fluxes).  0 for a grid centred on rest.
+ *   method   evaluation of the Fourier spectral operator:
+ *            BZ_METHOD_SIGMA: the sigma form described at bz_eval_Q (any gamma).
+ *            BZ_METHOD_CARLEMAN: the fast form for kernels that separate in the
+ *            Carleman representation (Section 2.2 cites this family of fast
+ *            spectral methods); here hard spheres in 3D, gamma = 1, whose
+ *            Carleman kernel is the constant 4.  With x, y truncated to the ball
+ *            of radius 2R, the spectral weight separates per direction e of the
+ *            half sphere into psi1(xi.e) Phi2(|P_e xi|),
+ *              psi1(s) = 2 int_0^{2R} rho cos(rho s) drho,
+ *              Phi2(t) = 2 pi (2R) J1(2R t) / t,
+ *            P_e the projection perpendicular to e.  The M/2 directions of the
+ *            sphere rule with cos(theta) > 0 give the gain
+ *              Q+ = sum_p IDFT(A_p fh) IDFT(B_p fh),
+ *              A_p = 4 w_p psi1(xi.e_p),  B_p = Phi2(|P_{e_p} xi|),
+ *            and the loss f IDFT(beta fh) with beta = sum_p A_p B_p, so the
+ *            plain form conserves mass exactly.  n_rho is not used.  A context
+ *            with this method and gamma != 1 is refused (BZ_EUNSUPPORTED). */
+typedef enum { BZ_METHOD_SIGMA = 0, BZ_METHOD_CARLEMAN = 1 } bz_method;
+
 typedef struct {
   int N;
   double L;
@@ -74,6 +93,7 @@ typedef struct {
   int precision;
   int device;
   double v1_shift;
+  int method;
 } bz_params;
 
 /* Create / destroy a context: host-built quadrature, phase and weight tables

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbz.so")
 
 BZ_FP64, BZ_FP32 = 0, 1
+BZ_METHOD_SIGMA, BZ_METHOD_CARLEMAN = 0, 1
 BZ_Q_CORRECTED = 1
 BZ_Q_MASS = 2
 BZ_Q_CONSERVE = 4
@@ -41,7 +42,7 @@ class bz_params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_rho", ctypes.c_int),
                 ("R", ctypes.c_double), ("precision", ctypes.c_int), ("device", ctypes.c_int),
-                ("v1_shift", ctypes.c_double)]
+                ("v1_shift", ctypes.c_double), ("method", ctypes.c_int)]
 
 
 class bz_solve_opts(ctypes.Structure):
@@ -171,6 +172,7 @@ class Params:
     precision: int = BZ_FP64
     device: int = 0
     v1_shift: float = 0.0  # physical v_1 of the grid origin (transport uses node + v1_shift)
+    method: int = 0  # BZ_METHOD_SIGMA, or BZ_METHOD_CARLEMAN (hard spheres, gamma = 1)
 
 
 class Context:
@@ -181,7 +183,7 @@ class Context:
         self.params = params or Params(**kw)
         p = bz_params(self.params.N, self.params.L, self.params.gamma, self.params.n_theta, self.params.n_phi,
                       self.params.n_rho, self.params.R, self.params.precision, self.params.device,
-                      self.params.v1_shift)
+                      self.params.v1_shift, self.params.method)
         h = ctypes.c_void_p()
         st = self.lib.bz_create(ctypes.byref(p), ctypes.byref(h))
         if st != 0:

@@ -29,12 +29,18 @@ struct bz_ctx {
   double* d_pairsw = nullptr;  // [n_pairs] sqrt of d_pairw
   double* d_W = nullptr;       // [n_rho][K] gain radial weights / K
   double* d_Gm = nullptr;      // [K] loss weight
+  // Carleman form (BZ_METHOD_CARLEMAN): n_dir half-sphere directions
+  int n_dir = 0;
+  double* d_cw = nullptr;      // [n_dir][2][K] A_p, B_p on the spectrum grid
+  double* d_cbeta = nullptr;   // [K] loss weight sum_p A_p B_p
   float* d_ph1_f = nullptr;
   float* d_ph23_f = nullptr;
   float* d_pairw_f = nullptr;
   float* d_pairsw_f = nullptr;
   float* d_W_f = nullptr;
   float* d_Gm_f = nullptr;
+  float* d_cw_f = nullptr;
+  float* d_cbeta_f = nullptr;
 
   // profiling of the direction-pair kernel (events recorded around launches)
   bool prof = false;

@@ -648,6 +648,148 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
   }
 }
 
+// ------------------------------------------------------------------ Carleman form (hard spheres)
+// Direction p of the half sphere, with the tables A_p, B_p of the context:
+//   NF = 1: c = (A_p + i B_p) fh, so IDFT(c) = a_p + i b_p (A_p, B_p real and
+//           even, f real: a_p and b_p are real) and the gain adds a_p b_p;
+//   NF = 2: z = gh + i hh (spectra of g = f - M and h = f + M), c_A = A_p z and
+//           c_B = B_p z, so IDFT(c_A) = a[g] + i a[h] and IDFT(c_B) = b[g] + i b[h];
+//           the symmetric bilinear gain (a[g] b[h] + a[h] b[g]) / 2 is
+//           Im(IDFT(c_A) IDFT(c_B)) / 2.
+// k_ccol premultiplies and makes the axis-0 inverse transform, one thread per
+// (cell, field, column); D is [cell][i1][NF][N][N], so the NF planes of one
+// (cell, i1) are adjacent for k_cplane.
+template <typename T, int N, int NF>
+__global__ __launch_bounds__(256) void k_ccol(const typename V2<T>::type* __restrict__ Fc,
+                                              typename V2<T>::type* __restrict__ D, int64_t ncells,
+                                              const T* __restrict__ tab) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ncells * NF * NN) return;
+  const int col = (int)(gid % NN);
+  const int which = (int)((gid / NN) % NF);
+  const int64_t b = gid / ((int64_t)NN * NF);
+  const C* fb = Fc + (size_t)b * NF * K + col;
+  const T* ta = tab + col;
+  const T* tb = tab + K + col;
+  T re[N], im[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    if (NF == 1) {
+      const C x = fb[(size_t)l * NN];
+      const T A = ta[(size_t)l * NN], B = tb[(size_t)l * NN];
+      re[l] = A * x.x - B * x.y;
+      im[l] = A * x.y + B * x.x;
+    } else {
+      const C g = fb[(size_t)l * NN], h = fb[(size_t)K + (size_t)l * NN];
+      const T wgt = which ? tb[(size_t)l * NN] : ta[(size_t)l * NN];
+      re[l] = wgt * (g.x - h.y);
+      im[l] = wgt * (g.y + h.x);
+    }
+  }
+  fft_reg<T, N, +1>(re, im);
+  C* dst = D + ((size_t)b * N * NF + which) * NN + col;
+#pragma unroll
+  for (int l = 0; l < N; ++l) dst[(size_t)l * NF * NN] = C{re[l], im[l]};
+}
+
+// Axes-1/2 inverse transform of the planes of D and accumulation of the
+// direction's gain into gain [cell][K] (overwritten when first != 0).  A block
+// holds PPB planes (PPB even, so the two fields of one (cell, i1) stay
+// together when NF = 2).
+template <typename T, int N, int NF>
+__global__ __launch_bounds__((N * plane_ppb<T, N>())) void k_cplane(const typename V2<T>::type* __restrict__ D,
+                                                                 T* __restrict__ gain, int64_t nplanes,
+                                                                 int first) {
+  using C = typename V2<T>::type;
+  constexpr int PPB = plane_ppb<T, N>();
+  static_assert(PPB % 2 == 0, "plane pairs must not straddle blocks");
+  constexpr int NT = N * PPB;
+  constexpr int LD = N + 1;
+  __shared__ C s[PPB * N * LD];
+  const int64_t p0 = (int64_t)blockIdx.x * PPB;
+  const int np = (int)((nplanes - p0) < PPB ? (nplanes - p0) : PPB);
+  const C* src = D + p0 * N * N;
+  for (int e = threadIdx.x; e < np * N * N; e += NT) {
+    const int p = e / (N * N), rr = (e / N) % N, cc = e % N;
+    s[(p * N + rr) * LD + cc] = src[e];
+  }
+  __syncthreads();
+  const int p = threadIdx.x / N, q = threadIdx.x % N;
+  T re[N], im[N];
+  if (p < np) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C v = s[(p * N + q) * LD + j];
+      re[j] = v.x;
+      im[j] = v.y;
+    }
+    fft_reg<T, N, +1>(re, im);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[(p * N + q) * LD + j] = C{re[j], im[j]};
+  }
+  __syncthreads();
+  if (p < np) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C v = s[(p * N + j) * LD + q];
+      re[j] = v.x;
+      im[j] = v.y;
+    }
+    fft_reg<T, N, +1>(re, im);
+  }
+  const int64_t pos = (p0 + p) / NF;  // (cell, i1) of this plane
+  if (NF == 1) {
+    if (p < np) {
+      T* dst = gain + pos * N * N;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const T v = re[j] * im[j];
+        dst[j * N + q] = first ? v : dst[j * N + q] + v;
+      }
+    }
+  } else {
+    __syncthreads();
+    if (p < np) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) s[(p * N + j) * LD + q] = C{re[j], im[j]};
+    }
+    __syncthreads();
+    if (p < np && (p & 1) == 0) {
+      T* dst = gain + pos * N * N;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const C cb = s[((p + 1) * N + j) * LD + q];
+        const T v = T(0.5) * (re[j] * cb.y + im[j] * cb.x);
+        dst[j * N + q] = first ? v : dst[j * N + q] + v;
+      }
+    }
+  }
+}
+
+// Q = gain - loss, with the gain already in physical space (real).
+template <typename T, int N, int NF>
+__global__ __launch_bounds__(256) void k_ccombine(const double* __restrict__ f, const double* __restrict__ GH,
+                                                  const T* __restrict__ gain,
+                                                  const typename V2<T>::type* __restrict__ Lc, double* __restrict__ Q,
+                                                  int64_t n) {
+  constexpr int K = N * N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n) return;
+  const int64_t b = gid / K;
+  const int k = (int)(gid % K);
+  double loss;
+  if (NF == 1) {
+    loss = f[gid] * double(Lc[gid].x);
+  } else {
+    const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
+    const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
+    loss = 0.5 * (g * Lh + h * Lg);
+  }
+  Q[gid] = double(gain[gid]) - loss;
+}
+
 // ------------------------------------------------------------------ axis-0 forward + radial weight
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __restrict__ Acc,
@@ -759,7 +901,11 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   // the N = 32 kernel takes sqrt of the pair weights, the general one the weights
   const T* pw = (N == 32) ? pairsw : pairw;
   const T* W = (const T*)(f64 ? (const void*)ctx->d_W : (const void*)ctx->d_W_f);
-  const T* Gm = (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
+  const bool carleman = ctx->p.method == BZ_METHOD_CARLEMAN;
+  // the loss weight: the radial sigma-form weight, or sum_p A_p B_p of the Carleman form
+  const T* Gm = carleman ? (const T*)(f64 ? (const void*)ctx->d_cbeta : (const void*)ctx->d_cbeta_f)
+                         : (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
+  const T* cw = (const T*)(f64 ? (const void*)ctx->d_cw : (const void*)ctx->d_cw_f);
   constexpr int PPB = plane_ppb<T, N>();
   const size_t lds = (N == 32) ? pairs32_lds_bytes<T>() : pairs_lds_bytes<T, N>();
   const void* kp = (N == 32) ? (corrected ? (const void*)k_pairs32<T, 2> : (const void*)k_pairs32<T, 1>)
@@ -779,6 +925,37 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
     // loss: L[u] = IDFT(Gm * uhat)
     hipLaunchKernelGGL((k_col<T, N, +1, COL_PREMUL>), dim3(gcol), dim3(256), 0, st, Fc, Lc, nvol, Gm);
     hipLaunchKernelGGL((k_plane<T, N, +1>), dim3(gpl), dim3(N * PPB), 0, st, Lc, Lc, nvol * N);
+    if (carleman) {
+      // gain accumulated in physical space in the Qh region (B*K reals); the
+      // direction fields use the Z region ([B][N][nf][N][N] complex)
+      T* gain = (T*)Qh;
+      C* D = Z;
+      const unsigned gcc = (unsigned)((B * nf * NN + 255) / 256);
+      const unsigned gcp = (unsigned)((B * N * nf + PPB - 1) / PPB);
+      // algorithmic FLOPs of one direction per cell: nf complex 3D transforms,
+      // the table products (6 per entry) and the accumulation (3 per entry)
+      const double dir_flops = nf * (15.0 * NN * N * __builtin_ctz(N) + 6.0 * NN * N) + 3.0 * NN * N;
+      for (int p = 0; p < ctx->n_dir; ++p) {
+        const T* tab = cw + (size_t)p * 2 * K;
+        if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
+        if (nf == 1) {
+          hipLaunchKernelGGL((k_ccol<T, N, 1>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
+          hipLaunchKernelGGL((k_cplane<T, N, 1>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N, p == 0 ? 1 : 0);
+        } else {
+          hipLaunchKernelGGL((k_ccol<T, N, 2>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
+          hipLaunchKernelGGL((k_cplane<T, N, 2>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N * 2,
+                             p == 0 ? 1 : 0);
+        }
+        if ((s = prof_mark(ctx, st, true, (double)B * dir_flops)) != BZ_OK) return s;
+      }
+      const unsigned ge = (unsigned)((B * K + 255) / 256);
+      if (corrected)
+        hipLaunchKernelGGL((k_ccombine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K);
+      else
+        hipLaunchKernelGGL((k_ccombine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K);
+      BZ_HIP(hipGetLastError());
+      continue;
+    }
     for (int r = 0; r < ctx->n_rho; ++r) {
       hipLaunchKernelGGL((k_zstage<T, N>), dim3(gcol), dim3(256), 0, st, Fc, Z, nvol, nt, ph1 + (size_t)r * nt * N);
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;

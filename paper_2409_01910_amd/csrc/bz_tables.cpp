@@ -10,6 +10,7 @@
 // with a Gauss-Legendre x uniform-azimuth sphere rule and a Gauss-Legendre
 // radial rule on [0, R_g].  The shift f(v + s) is a phase exp(i xi.s) on fh;
 // it separates over the three axes, which the kernels exploit.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -69,6 +70,73 @@ static bz_status upload(bz_ctx* ctx, D** dst, const std::vector<S>& src) {
   std::vector<D> tmp(src.begin(), src.end());
   BZ_HIP(hipMalloc((void**)dst, tmp.size() * sizeof(D)));
   BZ_HIP(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(D), hipMemcpyHostToDevice));
+  return BZ_OK;
+}
+
+// Carleman form of the hard-sphere operator: per direction e_p of the half
+// sphere (the sigma rule's nodes with cos(theta) > 0, weight w_p), the tables
+//   A_p(xi) = 4 w_p psi1(xi.e_p),  psi1(s) = 2 int_0^Rc rho cos(rho s) drho,
+//   B_p(xi) = Phi2(|P_{e_p} xi|),  Phi2(t) = 2 pi Rc J1(Rc t) / t,
+// with Rc = 2R, and the loss weight beta = sum_p A_p B_p.
+static double carleman_psi1(double Rc, double s) {
+  const double x = Rc * s;
+  double v;
+  if (std::fabs(x) < 0.5) {
+    // (x sin x + cos x - 1) / x^2 = sum_n (-1)^n x^{2n} (2n + 1) / (2n + 2)!
+    double fact = 2.0, xp = 1.0;
+    v = 0.0;
+    for (int n = 0; n < 12; ++n) {
+      if (n > 0) {
+        fact *= (2.0 * n + 1.0) * (2.0 * n + 2.0);
+        xp *= -x * x;
+      }
+      v += xp * (2.0 * n + 1.0) / fact;
+    }
+  } else {
+    v = (x * std::sin(x) + std::cos(x) - 1.0) / (x * x);
+  }
+  return 2.0 * Rc * Rc * v;
+}
+
+static double carleman_phi2(double Rc, double t) {
+  const double x = Rc * t;
+  const double v = x > 1e-12 ? std::cyl_bessel_j(1.0, x) / x : 0.5;
+  return 2.0 * M_PI * Rc * Rc * v;
+}
+
+static bz_status build_carleman_tables(bz_ctx* ctx, const std::vector<double>& ct, const std::vector<double>& wt,
+                                       const std::vector<double>& xi) {
+  const int N = ctx->N, K = ctx->K, nt = ctx->n_theta, np = ctx->n_phi;
+  const double Rc = ctx->Rg;
+  const int nd = (nt / 2) * np;
+  std::vector<double> cw((size_t)nd * 2 * K), beta(K, 0.0);
+  int p = 0;
+  for (int t = nt / 2; t < nt; ++t) {  // Gauss-Legendre nodes ascending: cos(theta) > 0
+    const double c = ct[t], st = std::sqrt(std::max(0.0, 1.0 - c * c));
+    for (int j = 0; j < np; ++j, ++p) {
+      const double ph = 2.0 * M_PI * j / np;
+      const double e0 = c, e1 = st * std::cos(ph), e2 = st * std::sin(ph);
+      const double wp = wt[t] * 2.0 * M_PI / np;
+      double* A = cw.data() + (size_t)p * 2 * K;
+      double* B = A + K;
+      for (int l1 = 0; l1 < N; ++l1)
+        for (int l2 = 0; l2 < N; ++l2)
+          for (int l3 = 0; l3 < N; ++l3) {
+            const size_t k = ((size_t)l1 * N + l2) * N + l3;
+            const double s = xi[l1] * e0 + xi[l2] * e1 + xi[l3] * e2;
+            const double x2 = xi[l1] * xi[l1] + xi[l2] * xi[l2] + xi[l3] * xi[l3];
+            A[k] = 4.0 * wp * carleman_psi1(Rc, s);
+            B[k] = carleman_phi2(Rc, std::sqrt(std::max(0.0, x2 - s * s)));
+            beta[k] += A[k] * B[k];
+          }
+    }
+  }
+  bz_status s;
+  if ((s = upload(ctx, &ctx->d_cw, cw)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_cbeta, beta)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_cw_f, cw)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_cbeta_f, beta)) != BZ_OK) return s;
+  ctx->n_dir = nd;
   return BZ_OK;
 }
 
@@ -154,13 +222,14 @@ bz_status build_tables(bz_ctx* ctx) {
   if ((s = upload(ctx, &ctx->d_W_f, W)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_Gm_f, Gm)) != BZ_OK) return s;
   ctx->n_pairs = npairs;
+  if (ctx->p.method == BZ_METHOD_CARLEMAN) return build_carleman_tables(ctx, ct, wt, xi);
   return BZ_OK;
 }
 
 void free_tables(bz_ctx* ctx) {
   void* ptrs[] = {ctx->d_nodes,  ctx->d_ph1,   ctx->d_ph23,     ctx->d_pairw,      ctx->d_pairsw, ctx->d_W,
                   ctx->d_Gm,     ctx->d_ph1_f, ctx->d_ph23_f,   ctx->d_pairw_f,    ctx->d_pairsw_f,
-                  ctx->d_W_f,    ctx->d_Gm_f};
+                  ctx->d_W_f,    ctx->d_Gm_f,   ctx->d_cw,       ctx->d_cbeta,      ctx->d_cw_f,   ctx->d_cbeta_f};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
