@@ -768,6 +768,133 @@ __global__ __launch_bounds__((N * plane_ppb<T, N>())) void k_cplane(const typena
   }
 }
 
+// Inverse 32x32 transform of one plane held by a wave, with the three
+// register stages and two LDS exchanges of k_pairs32.  On entry lane (q, h) =
+// (ln & 31, ln >> 5) holds column q, rows 2m + h in entry m; on return lane
+// (rg, kp) holds rows rg + 8g, columns kp + 8t in entry 4g + t, with
+// kp = (ln & 1) | ((ln >> 2) & 6) and rg = ((ln >> 1) & 3) | ((ln >> 3) & 4).
+// tile is the wave's kPair32Tile slots, twl the 32 roots e^{2 pi i n / 32}.
+template <typename T>
+__device__ __forceinline__ void plane32_inverse(T (&re)[16], T (&im)[16], typename V2<T>::type* tile,
+                                                const typename V2<T>::type* twl, int ln) {
+  using C = typename V2<T>::type;
+  const int q = ln & 31, h = ln >> 5;
+  const int k2 = ln & 15, c2 = ln >> 4;
+  const int kp = (ln & 1) | ((ln >> 2) & 6), rg = ((ln >> 1) & 3) | ((ln >> 3) & 4);
+  fft_reg<T, 16, +1>(re, im);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tile[s1_slot(h, k, q)] = C{re[k], im[k]};
+  wave_sync();
+  const C wk = twl[k2];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const C e = tile[s1_slot(0, k2, c2 + 4 * j)], o = tile[s1_slot(1, k2, c2 + 4 * j)];
+    T tr = o.x, ti = o.y;
+    cmul(tr, ti, wk.x, wk.y);
+    re[j] = e.x + tr;
+    im[j] = e.y + ti;
+    re[8 + j] = e.x - tr;
+    im[8 + j] = e.y - ti;
+  }
+  fft_reg<T, 8, +1>(re, im);
+  fft_reg<T, 8, +1>(re + 8, im + 8);
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    tile[s2_slot(k2, c2, j)] = C{re[j], im[j]};
+    tile[s2_slot(k2 + 16, c2, j)] = C{re[8 + j], im[8 + j]};
+  }
+  wave_sync();
+  const C w1 = twl[kp], w2 = twl[2 * kp], w3 = twl[3 * kp];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int r = rg + 8 * g;
+    const C z0 = tile[s2_slot(r, 0, kp)], z1 = tile[s2_slot(r, 1, kp)];
+    const C z2 = tile[s2_slot(r, 2, kp)], z3 = tile[s2_slot(r, 3, kp)];
+    T x1r = z1.x, x1i = z1.y, x2r = z2.x, x2i = z2.y, x3r = z3.x, x3i = z3.y;
+    cmul(x1r, x1i, w1.x, w1.y);
+    cmul(x2r, x2i, w2.x, w2.y);
+    cmul(x3r, x3i, w3.x, w3.y);
+    const T ar = z0.x + x2r, ai = z0.y + x2i, br = z0.x - x2r, bi = z0.y - x2i;
+    const T cr = x1r + x3r, ci = x1i + x3i, dr = x1r - x3r, di = x1i - x3i;
+    re[4 * g + 0] = ar + cr;
+    im[4 * g + 0] = ai + ci;
+    re[4 * g + 2] = ar - cr;
+    im[4 * g + 2] = ai - ci;
+    re[4 * g + 1] = br - di;
+    im[4 * g + 1] = bi + dr;
+    re[4 * g + 3] = br + di;
+    im[4 * g + 3] = bi - dr;
+  }
+  wave_sync();  // the tile is free again
+}
+
+// N = 32 form of k_cplane: one wave per (cell, i1), the NF planes of that
+// position transformed one after the other by plane32_inverse.  Waves never
+// wait for each other, and a wave's tile is 16.9 KB (FP64) instead of the
+// 67.6 KB block tile of k_cplane, so several waves per SIMD stay resident.
+constexpr int kCplaneWaves = 2;
+
+template <typename T, int NF>
+__global__ __launch_bounds__(64 * kCplaneWaves) void k_cplane32(const typename V2<T>::type* __restrict__ D,
+                                                                T* __restrict__ gain, int64_t npos, int first) {
+  using C = typename V2<T>::type;
+  constexpr int N = 32, NN = N * N;
+  __shared__ C s_tiles[kCplaneWaves * kPair32Tile];
+  __shared__ C s_tw[32];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  if (threadIdx.x < 32) s_tw[threadIdx.x] = C{T(kTw32.c[threadIdx.x]), T(kTw32.s[threadIdx.x])};
+  __syncthreads();
+  const int64_t pos = (int64_t)blockIdx.x * kCplaneWaves + wv;
+  if (pos >= npos) return;  // whole waves only; no block barrier follows
+  C* tile = s_tiles + wv * kPair32Tile;
+  const int q = ln & 31, h = ln >> 5;
+  const int kp = (ln & 1) | ((ln >> 2) & 6), rg = ((ln >> 1) & 3) | ((ln >> 3) & 4);
+  const C* src = D + (size_t)pos * NF * NN + (size_t)h * N + q;
+  T re[16], im[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const C v = src[(size_t)(2 * m) * N];
+    re[m] = v.x;
+    im[m] = v.y;
+  }
+  plane32_inverse<T>(re, im, tile, s_tw, ln);
+  T* dst = gain + (size_t)pos * NN + (size_t)rg * N + kp;
+  if (NF == 1) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const size_t idx = (size_t)(8 * g) * N + 8 * t;
+        const T v = re[4 * g + t] * im[4 * g + t];
+        dst[idx] = first ? v : dst[idx] + v;
+      }
+  } else {
+    T ar[16], ai[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      ar[k] = re[k];
+      ai[k] = im[k];
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const C v = src[(size_t)NN + (size_t)(2 * m) * N];
+      re[m] = v.x;
+      im[m] = v.y;
+    }
+    plane32_inverse<T>(re, im, tile, s_tw, ln);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 4 * g + t;
+        const size_t idx = (size_t)(8 * g) * N + 8 * t;
+        const T v = T(0.5) * (ar[k] * im[k] + ai[k] * re[k]);
+        dst[idx] = first ? v : dst[idx] + v;
+      }
+  }
+}
+
 // Q = gain - loss, with the gain already in physical space (real).
 template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_ccombine(const double* __restrict__ f, const double* __restrict__ GH,
@@ -932,19 +1059,26 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       C* D = Z;
       const unsigned gcc = (unsigned)((B * nf * NN + 255) / 256);
       const unsigned gcp = (unsigned)((B * N * nf + PPB - 1) / PPB);
+      const unsigned gc32 = (unsigned)((B * N + kCplaneWaves - 1) / kCplaneWaves);
       // algorithmic FLOPs of one direction per cell: nf complex 3D transforms,
       // the table products (6 per entry) and the accumulation (3 per entry)
       const double dir_flops = nf * (15.0 * NN * N * __builtin_ctz(N) + 6.0 * NN * N) + 3.0 * NN * N;
       for (int p = 0; p < ctx->n_dir; ++p) {
         const T* tab = cw + (size_t)p * 2 * K;
         if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
+        const int first = p == 0 ? 1 : 0;
         if (nf == 1) {
           hipLaunchKernelGGL((k_ccol<T, N, 1>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
-          hipLaunchKernelGGL((k_cplane<T, N, 1>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N, p == 0 ? 1 : 0);
+          if (N == 32)
+            hipLaunchKernelGGL((k_cplane32<T, 1>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, first);
+          else
+            hipLaunchKernelGGL((k_cplane<T, N, 1>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N, first);
         } else {
           hipLaunchKernelGGL((k_ccol<T, N, 2>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
-          hipLaunchKernelGGL((k_cplane<T, N, 2>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N * 2,
-                             p == 0 ? 1 : 0);
+          if (N == 32)
+            hipLaunchKernelGGL((k_cplane32<T, 2>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, first);
+          else
+            hipLaunchKernelGGL((k_cplane<T, N, 2>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N * 2, first);
         }
         if ((s = prof_mark(ctx, st, true, (double)B * dir_flops)) != BZ_OK) return s;
       }
