@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 N, L, N_THETA, N_PHI, N_RHO = 32, 8.0, 8, 16, 16
 DX = 40.0 / 128
 VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector peaks (vendor)
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E (vendor)
+N_DIR = N_THETA // 2 * N_PHI  # half-sphere directions of the Carleman form
 
 
 def make_inputs(batch, seed=0):
@@ -63,15 +65,15 @@ def traffic_per_launch(precision, total_cell_nodes, launches):
     return per * total_cell_nodes / launches
 
 
-def cpu_baseline(f_np, eps_np, n_cells=2):
+def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
     """The oracle, as it stands, on the same step for a bounded sample of cells."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import cell as OC, collision as OQ
+    from oracle import carleman as OCA, cell as OC, collision as OQ, maxwellian as OM
     from oracle.grid import Spec, velocity_nodes
 
-    sp = Spec(d=3, N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO)
+    sp = Spec(d=3, N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=gamma)
     v1 = velocity_nodes(sp)[:, 0]
     B = f_np.shape[0]
     t0 = time.perf_counter()
@@ -79,7 +81,12 @@ def cpu_baseline(f_np, eps_np, n_cells=2):
         for i in range(n_cells):
             fl, fr = f_np[(i - 1) % B], f_np[(i + 1) % B]
             inflow = (-np.maximum(v1, 0) * fl + np.minimum(v1, 0) * fr) / DX
-            P = OQ.penalty(sp, f_np[i])
+            if method == "carleman":
+                M = OM.discrete_maxwellian(sp, f_np[i])
+                Qc = OQ.mass_project(sp, OQ.q_corrected(sp, f_np[i], M, op=OCA.q_carleman), M)
+                P = OQ.penalty(sp, f_np[i], Q=Qc, M=M)
+            else:
+                P = OQ.penalty(sp, f_np[i])
             r = inflow - P / eps_np[i]
             OC.solve(sp, r, OQ.nu_of(sp, f_np[i]), eps_np[i], DX, f_np[i], mode="pfp", tol=1e-8, max_iter=100)
     dt = time.perf_counter() - t0
@@ -313,6 +320,10 @@ def main():
     ap.add_argument("--gamma", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
+    ap.add_argument("--method", choices=["sigma", "carleman"], default="sigma",
+                    help="spectral form of the main line (carleman: hard spheres, gamma = 1)")
+    ap.add_argument("--no-carleman", action="store_true",
+                    help="skip the secondary hard-sphere Carleman measurement")
     ap.add_argument("--slab-case", default="all",
                     choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_graph10", "n32_mg",
                              "n32_128cells_fp64",
@@ -356,9 +367,11 @@ def main():
     g = torch.empty_like(f)
     torch.cuda.synchronize()
 
-    def measure(precision):
+    def measure(precision, method="sigma"):
         prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
-        ctx = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=args.gamma, precision=prec)
+        carl = method == "carleman"
+        ctx = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=1.0 if carl else args.gamma,
+                         precision=prec, method=bz.BZ_METHOD_CARLEMAN if carl else bz.BZ_METHOD_SIGMA)
 
         def step():
             return ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g)
@@ -381,16 +394,34 @@ def main():
         ctx.profile_enable(False)
         ctx.close()
         dt = "f64" if prec == bz.BZ_FP64 else "f32"
-        achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                "frac": achieved / VALU_PEAK_TFLOPS[dt],
-                "traffic": traffic_per_launch(precision, args.steps * args.batch * N_RHO, prof["launches"]),
-                "kernel": "k_pairs32 (direction-pair transforms)", "launches": prof["launches"],
-                "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
-                "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
+        if carl:
+            # one marked unit = one direction over one chunk (k_ccol + k_cplane32):
+            # spectra read once, the direction fields written and read once,
+            # the gain read and written (the direction tables stay in L2)
+            cs, ts = (16, 8) if dt == "f64" else (8, 4)
+            per_dir_cell = 3 * 2 * N ** 3 * cs + 2 * N ** 3 * ts
+            total = args.steps * args.batch * N_DIR * per_dir_cell
+            achieved = total / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_ccol + k_cplane32 (one Carleman direction)", "launches": prof["launches"],
+                    "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
+                    "bytes_per_direction_cell": per_dir_cell,
+                    "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
+        else:
+            achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
+            roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                    "frac": achieved / VALU_PEAK_TFLOPS[dt],
+                    "traffic": traffic_per_launch(precision, args.steps * args.batch * N_RHO, prof["launches"]),
+                    "kernel": "k_pairs32 (direction-pair transforms)", "launches": prof["launches"],
+                    "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
+                    "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
         return args.steps * args.batch / elapsed, elapsed, dt, roof, ctx.decode_stats(stats)
 
-    value, elapsed, dt, roof, st = measure(args.precision)
+    value, elapsed, dt, roof, st = measure(args.precision, args.method)
+    main_gamma = 1.0 if args.method == "carleman" else args.gamma
+    form = ("Carleman rank-64 form (64 half-sphere directions), hard spheres" if args.method == "carleman"
+            else "sigma form, M=128 (8x16), 16 radial nodes")
     line = {
         "metric": "Q evals/s at 32^3 velocity grid; time-to-residual 1e-8, learned+FP32 vs plain",
         "value": value,
@@ -405,19 +436,24 @@ def main():
         "dtype": dt,
         "data": "synthetic",
         "config": {"workload": f"batched corrected collision term + PFP cell update, {args.batch} cells, "
-                               f"32^3 velocities on [-8,8]^3, M=128 (8x16), 16 radial nodes, gamma={args.gamma}",
-                   "cells": args.batch, "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "gamma": args.gamma,
-                   "spectral_precision": args.precision},
+                               f"32^3 velocities on [-8,8]^3, {form}, gamma={main_gamma}",
+                   "cells": args.batch, "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "gamma": main_gamma,
+                   "method": args.method, "spectral_precision": args.precision},
         "roofline": roof,
         "inner": {"mean_iterations": float(st["iterations"].mean()), "max_iterations": int(st["iterations"].max()),
                   "fallbacks": int(st["fallback"].sum()), "unconverged": int((st["status"] != 0).sum())},
     }
     if args.precision == "fp64" and not args.no_fp32:
-        v32, e32, _, r32, _ = measure("fp32")
+        v32, e32, _, r32, _ = measure("fp32", args.method)
         line["fp32_spectral"] = {"value": v32, "ms_per_step": e32 / args.steps * 1e3, "roofline": r32}
+    if args.method == "sigma" and not args.no_carleman:
+        # the same step for hard spheres (gamma = 1) with the Carleman form, FP64
+        vc, ec, _, rc, _ = measure("fp64", "carleman")
+        line["carleman_hard_spheres"] = {"value": vc, "ms_per_step": ec / args.steps * 1e3, "gamma": 1.0,
+                                         "dtype": "f64", "roofline": rc}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(f_np, eps_np)
+        line["cpu_baseline"] = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)
     print(json.dumps(line), flush=True)
 
 
