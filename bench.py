@@ -395,16 +395,19 @@ def main():
         ctx.close()
         dt = "f64" if prec == bz.BZ_FP64 else "f32"
         if carl:
-            # one marked unit = one direction over one chunk (k_ccol + k_cplane32):
+            # one marked unit = a group of up to 4 directions over one chunk
+            # (k_ccol + k_cplane32); per direction and cell:
             # spectra read once, the direction fields written and read once,
-            # the gain read and written (the direction tables stay in L2)
+            # the gain read and written once per group (the direction tables
+            # stay in L2)
             cs, ts = (16, 8) if dt == "f64" else (8, 4)
-            per_dir_cell = 3 * 2 * N ** 3 * cs + 2 * N ** 3 * ts
+            # (the gain once per group of min(4, n_theta) directions)
+            per_dir_cell = 3 * 2 * N ** 3 * cs + 2 * N ** 3 * ts / min(4, N_THETA)
             total = args.steps * args.batch * N_DIR * per_dir_cell
             achieved = total / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "k_ccol + k_cplane32 (one Carleman direction)", "launches": prof["launches"],
+                    "kernel": "k_ccol + k_cplane32 (a group of Carleman directions)", "launches": prof["launches"],
                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
                     "bytes_per_direction_cell": per_dir_cell,
                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}

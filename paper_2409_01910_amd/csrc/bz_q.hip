@@ -656,23 +656,25 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
 //           c_B = B_p z, so IDFT(c_A) = a[g] + i a[h] and IDFT(c_B) = b[g] + i b[h];
 //           the symmetric bilinear gain (a[g] b[h] + a[h] b[g]) / 2 is
 //           Im(IDFT(c_A) IDFT(c_B)) / 2.
-// k_ccol premultiplies and makes the axis-0 inverse transform, one thread per
-// (cell, field, column); D is [cell][i1][NF][N][N], so the NF planes of one
-// (cell, i1) are adjacent for k_cplane.
+// k_ccol premultiplies and makes the axis-0 inverse transform for nd
+// consecutive directions (tables tab[d][2][K]), one thread per (cell,
+// direction, field, column); D is [cell][i1][nd][NF][N][N], so all planes of
+// one (cell, i1) are adjacent for k_cplane / k_cplane32.
 template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_ccol(const typename V2<T>::type* __restrict__ Fc,
                                               typename V2<T>::type* __restrict__ D, int64_t ncells,
-                                              const T* __restrict__ tab) {
+                                              const T* __restrict__ tab, int nd) {
   using C = typename V2<T>::type;
   constexpr int K = N * N * N, NN = N * N;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= ncells * NF * NN) return;
+  if (gid >= ncells * nd * NF * NN) return;
   const int col = (int)(gid % NN);
   const int which = (int)((gid / NN) % NF);
-  const int64_t b = gid / ((int64_t)NN * NF);
+  const int d = (int)((gid / ((int64_t)NN * NF)) % nd);
+  const int64_t b = gid / ((int64_t)NN * NF * nd);
   const C* fb = Fc + (size_t)b * NF * K + col;
-  const T* ta = tab + col;
-  const T* tb = tab + K + col;
+  const T* ta = tab + (size_t)d * 2 * K + col;
+  const T* tb = ta + K;
   T re[N], im[N];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
@@ -689,9 +691,9 @@ __global__ __launch_bounds__(256) void k_ccol(const typename V2<T>::type* __rest
     }
   }
   fft_reg<T, N, +1>(re, im);
-  C* dst = D + ((size_t)b * N * NF + which) * NN + col;
+  C* dst = D + (((size_t)b * N * nd + d) * NF + which) * NN + col;
 #pragma unroll
-  for (int l = 0; l < N; ++l) dst[(size_t)l * NF * NN] = C{re[l], im[l]};
+  for (int l = 0; l < N; ++l) dst[(size_t)l * nd * NF * NN] = C{re[l], im[l]};
 }
 
 // Axes-1/2 inverse transform of the planes of D and accumulation of the
@@ -837,7 +839,8 @@ constexpr int kCplaneWaves = 2;
 
 template <typename T, int NF>
 __global__ __launch_bounds__(64 * kCplaneWaves) void k_cplane32(const typename V2<T>::type* __restrict__ D,
-                                                                T* __restrict__ gain, int64_t npos, int first) {
+                                                                T* __restrict__ gain, int64_t npos, int nd,
+                                                                int first) {
   using C = typename V2<T>::type;
   constexpr int N = 32, NN = N * N;
   __shared__ C s_tiles[kCplaneWaves * kPair32Tile];
@@ -850,49 +853,48 @@ __global__ __launch_bounds__(64 * kCplaneWaves) void k_cplane32(const typename V
   C* tile = s_tiles + wv * kPair32Tile;
   const int q = ln & 31, h = ln >> 5;
   const int kp = (ln & 1) | ((ln >> 2) & 6), rg = ((ln >> 1) & 3) | ((ln >> 3) & 4);
-  const C* src = D + (size_t)pos * NF * NN + (size_t)h * N + q;
-  T re[16], im[16];
+  T acc[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const C v = src[(size_t)(2 * m) * N];
-    re[m] = v.x;
-    im[m] = v.y;
-  }
-  plane32_inverse<T>(re, im, tile, s_tw, ln);
-  T* dst = gain + (size_t)pos * NN + (size_t)rg * N + kp;
-  if (NF == 1) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const size_t idx = (size_t)(8 * g) * N + 8 * t;
-        const T v = re[4 * g + t] * im[4 * g + t];
-        dst[idx] = first ? v : dst[idx] + v;
-      }
-  } else {
-    T ar[16], ai[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      ar[k] = re[k];
-      ai[k] = im[k];
-    }
+  for (int k = 0; k < 16; ++k) acc[k] = T(0);
+  for (int d = 0; d < nd; ++d) {
+    const C* src = D + ((size_t)pos * nd + d) * NF * NN + (size_t)h * N + q;
+    T re[16], im[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const C v = src[(size_t)NN + (size_t)(2 * m) * N];
+      const C v = src[(size_t)(2 * m) * N];
       re[m] = v.x;
       im[m] = v.y;
     }
     plane32_inverse<T>(re, im, tile, s_tw, ln);
+    if (NF == 1) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+      for (int k = 0; k < 16; ++k) acc[k] += re[k] * im[k];
+    } else {
+      T ar[16], ai[16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = 4 * g + t;
-        const size_t idx = (size_t)(8 * g) * N + 8 * t;
-        const T v = T(0.5) * (ar[k] * im[k] + ai[k] * re[k]);
-        dst[idx] = first ? v : dst[idx] + v;
+      for (int k = 0; k < 16; ++k) {
+        ar[k] = re[k];
+        ai[k] = im[k];
       }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const C v = src[(size_t)NN + (size_t)(2 * m) * N];
+        re[m] = v.x;
+        im[m] = v.y;
+      }
+      plane32_inverse<T>(re, im, tile, s_tw, ln);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[k] += T(0.5) * (ar[k] * im[k] + ai[k] * re[k]);
+    }
   }
+  T* dst = gain + (size_t)pos * NN + (size_t)rg * N + kp;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const size_t idx = (size_t)(8 * g) * N + 8 * t;
+      dst[idx] = first ? acc[4 * g + t] : dst[idx] + acc[4 * g + t];
+    }
 }
 
 // Q = gain - loss, with the gain already in physical space (real).
@@ -1057,30 +1059,36 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       // direction fields use the Z region ([B][N][nf][N][N] complex)
       T* gain = (T*)Qh;
       C* D = Z;
-      const unsigned gcc = (unsigned)((B * nf * NN + 255) / 256);
       const unsigned gcp = (unsigned)((B * N * nf + PPB - 1) / PPB);
       const unsigned gc32 = (unsigned)((B * N + kCplaneWaves - 1) / kCplaneWaves);
       // algorithmic FLOPs of one direction per cell: nf complex 3D transforms,
       // the table products (6 per entry) and the accumulation (3 per entry)
       const double dir_flops = nf * (15.0 * NN * N * __builtin_ctz(N) + 6.0 * NN * N) + 3.0 * NN * N;
-      for (int p = 0; p < ctx->n_dir; ++p) {
+      // N = 32 takes up to 4 directions per launch pair (the gain is read and
+      // written once per group); the workspace holds min(4, n_theta) of them
+      const int group = (N == 32) ? (nt < 4 ? nt : 4) : 1;
+      for (int p = 0; p < ctx->n_dir; p += group) {
+        const int nd = (ctx->n_dir - p) < group ? (ctx->n_dir - p) : group;
         const T* tab = cw + (size_t)p * 2 * K;
         if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
         const int first = p == 0 ? 1 : 0;
+        const unsigned gcc = (unsigned)((B * nd * nf * NN + 255) / 256);
         if (nf == 1) {
-          hipLaunchKernelGGL((k_ccol<T, N, 1>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
+          hipLaunchKernelGGL((k_ccol<T, N, 1>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab, nd);
           if (N == 32)
-            hipLaunchKernelGGL((k_cplane32<T, 1>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, first);
+            hipLaunchKernelGGL((k_cplane32<T, 1>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, nd,
+                               first);
           else
             hipLaunchKernelGGL((k_cplane<T, N, 1>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N, first);
         } else {
-          hipLaunchKernelGGL((k_ccol<T, N, 2>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab);
+          hipLaunchKernelGGL((k_ccol<T, N, 2>), dim3(gcc), dim3(256), 0, st, Fc, D, B, tab, nd);
           if (N == 32)
-            hipLaunchKernelGGL((k_cplane32<T, 2>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, first);
+            hipLaunchKernelGGL((k_cplane32<T, 2>), dim3(gc32), dim3(64 * kCplaneWaves), 0, st, D, gain, B * N, nd,
+                               first);
           else
             hipLaunchKernelGGL((k_cplane<T, N, 2>), dim3(gcp), dim3(N * PPB), 0, st, D, gain, B * N * 2, first);
         }
-        if ((s = prof_mark(ctx, st, true, (double)B * dir_flops)) != BZ_OK) return s;
+        if ((s = prof_mark(ctx, st, true, (double)B * nd * dir_flops)) != BZ_OK) return s;
       }
       const unsigned ge = (unsigned)((B * K + 255) / 256);
       if (corrected)
