@@ -658,8 +658,10 @@ __global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2
 //           Im(IDFT(c_A) IDFT(c_B)) / 2.
 // k_ccol premultiplies and makes the axis-0 inverse transform for nd
 // consecutive directions (tables tab[d][2][K]), one thread per (cell,
-// direction, field, column); D is [cell][i1][nd][NF][N][N], so all planes of
-// one (cell, i1) are adjacent for k_cplane / k_cplane32.
+// direction, field, column).  D is [cell][i1][nd][NF][N][N] for k_cplane,
+// which needs all planes of one (cell, i1) adjacent, and [cell][nd][NF][i1][N][N]
+// for N = 32 (k_cplane32), so that a thread's 32 stores are one plane (16 KB
+// in FP64) apart instead of nd * NF planes.
 template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_ccol(const typename V2<T>::type* __restrict__ Fc,
                                               typename V2<T>::type* __restrict__ D, int64_t ncells,
@@ -691,9 +693,15 @@ __global__ __launch_bounds__(256) void k_ccol(const typename V2<T>::type* __rest
     }
   }
   fft_reg<T, N, +1>(re, im);
-  C* dst = D + (((size_t)b * N * nd + d) * NF + which) * NN + col;
+  if (N == 32) {
+    C* dst = D + (((size_t)b * nd + d) * NF + which) * K + col;
 #pragma unroll
-  for (int l = 0; l < N; ++l) dst[(size_t)l * nd * NF * NN] = C{re[l], im[l]};
+    for (int l = 0; l < N; ++l) dst[(size_t)l * NN] = C{re[l], im[l]};
+  } else {
+    C* dst = D + (((size_t)b * N * nd + d) * NF + which) * NN + col;
+#pragma unroll
+    for (int l = 0; l < N; ++l) dst[(size_t)l * nd * NF * NN] = C{re[l], im[l]};
+  }
 }
 
 // Axes-1/2 inverse transform of the planes of D and accumulation of the
@@ -856,8 +864,10 @@ __global__ __launch_bounds__(64 * kCplaneWaves) void k_cplane32(const typename V
   T acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = T(0);
+  const int64_t cell = pos / N, i1 = pos % N;
   for (int d = 0; d < nd; ++d) {
-    const C* src = D + ((size_t)pos * nd + d) * NF * NN + (size_t)h * N + q;
+    // D is [cell][nd][NF][i1][N][N]; the second field's plane is K entries on
+    const C* src = D + (((size_t)cell * nd + d) * NF * N + i1) * NN + (size_t)h * N + q;
     T re[16], im[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
@@ -878,7 +888,7 @@ __global__ __launch_bounds__(64 * kCplaneWaves) void k_cplane32(const typename V
       }
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        const C v = src[(size_t)NN + (size_t)(2 * m) * N];
+        const C v = src[(size_t)N * NN + (size_t)(2 * m) * N];
         re[m] = v.x;
         im[m] = v.y;
       }
