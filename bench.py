@@ -45,24 +45,30 @@ def make_inputs(batch, seed=0):
     return f, eps
 
 
-def traffic_per_launch(precision, total_cell_nodes, launches):
-    """HBM bytes per pair-kernel launch from the committed counter profile, or
-    None when that profile was taken on a different kernel source or precision."""
+def traffic_per_launch(precision, total_units, launches, method="sigma"):
+    """HBM bytes per marked launch from the committed counter profile, or None
+    when that profile was taken on a different kernel source or precision.
+    Units: (cell, radial node) for the sigma form, (cell, direction) for the
+    Carleman form."""
     import hashlib
 
     if precision != "fp64" or launches == 0:
         return None
-    path = os.path.join(ROOT, "profiles", "k_pairs32_zstage_traffic_fp64.md")
+    name, prefix = (("carleman_hs_fp64_batched_q_4096.md", "carleman") if method == "carleman"
+                    else ("k_pairs32_zstage_traffic_fp64.md", "pairs"))
+    unit = "dir" if method == "carleman" else "node"
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2409_01910_amd", "csrc", "bz_q.hip")
     try:
         kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if kv.get("source_sha256", "").strip() != sha:
             return None
-        per = float(kv["pairs_fetch_bytes_per_cell_node"]) + float(kv["pairs_write_bytes_per_cell_node"])
+        per = (float(kv[f"{prefix}_fetch_bytes_per_cell_{unit}"]) +
+               float(kv[f"{prefix}_write_bytes_per_cell_{unit}"]))
     except (OSError, KeyError, ValueError):
         return None
-    return per * total_cell_nodes / launches
+    return per * total_units / launches
 
 
 def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
@@ -406,7 +412,9 @@ def main():
             total = args.steps * args.batch * N_DIR * per_dir_cell
             achieved = total / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": traffic_per_launch(precision, args.steps * args.batch * N_DIR, prof["launches"],
+                                                  "carleman"),
                     "kernel": "k_ccol + k_cplane32 (a group of Carleman directions)", "launches": prof["launches"],
                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
                     "bytes_per_direction_cell": per_dir_cell,
