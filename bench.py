@@ -401,14 +401,14 @@ def main():
         ctx.close()
         dt = "f64" if prec == bz.BZ_FP64 else "f32"
         if carl:
-            # one marked unit = a group of up to 4 directions over one chunk
-            # (k_ccol + k_cplane32); per direction and cell:
-            # spectra read once, the direction fields written and read once,
-            # the gain read and written once per group (the direction tables
-            # stay in L2)
+            # one marked unit = a group of G = min(4, n_theta) directions over
+            # one chunk (k_ccol + k_cplane32).  The least traffic of that
+            # scheme, per direction and cell: the spectra read once per group,
+            # the direction fields written and read once, the gain read and
+            # written once per group (the direction tables stay in L2)
             cs, ts = (16, 8) if dt == "f64" else (8, 4)
-            # (the gain once per group of min(4, n_theta) directions)
-            per_dir_cell = 3 * 2 * N ** 3 * cs + 2 * N ** 3 * ts / min(4, N_THETA)
+            G = min(4, N_THETA)
+            per_dir_cell = 2 * N ** 3 * cs / G + 2 * (2 * N ** 3 * cs) + 2 * N ** 3 * ts / G
             total = args.steps * args.batch * N_DIR * per_dir_cell
             achieved = total / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
