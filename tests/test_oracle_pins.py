@@ -238,12 +238,14 @@ def test_large_eps_limit():
 
 
 # ------------------------------------------------------------------ sweep
-def test_collisionless_slab_closed_form():
+@pytest.mark.parametrize("order", [1, 2])
+def test_collisionless_slab_closed_form(order):
     # eps huge, BGK (P == 0): right-movers carry the left wall Maxwellian, left-movers
-    # the right one; the discrete zero-flux condition fixes rho_L/rho_R, the mass C the scale
+    # the right one; the discrete zero-flux condition fixes rho_L/rho_R, the mass C the
+    # scale.  The solution is uniform in x, so the second-order slopes vanish on it.
     sp = Spec(d=3, N=8, L=6.0)
-    prob = SW.Slab(spec=sp, nx=6, eps=1e12, collision="bgk", T_L=1.0, T_R=2.0, mass=1.3)
-    f, hist = SW.solve_sgs(prob, SW.initial_state(prob), tol=1e-12, max_iter=20)
+    prob = SW.Slab(spec=sp, nx=6, eps=1e12, collision="bgk", T_L=1.0, T_R=2.0, mass=1.3, order=order)
+    f, hist = SW.solve_sgs(prob, SW.initial_state(prob), tol=1e-12, max_iter=60)
     v1 = velocity_nodes(sp)[:, 0]
     ML, MR = SW.wall_maxwellian(sp, 1.0, (0, 0, 0)), SW.wall_maxwellian(sp, 2.0, (0, 0, 0))
     a = np.sum(np.where(v1 > 0, v1, 0) * ML)
@@ -256,7 +258,27 @@ def test_collisionless_slab_closed_form():
     m = (v1 != 0) & (unit > 1e-6 * unit.max())
     ratio = f[:, m] / unit[None, m]
     assert hist[-1] < 1e-10
-    assert np.ptp(ratio) < 1e-10 * ratio.mean()
+    # the state error at a residual of 1e-12 grows with the contraction rate,
+    # which is slower for the wider second-order stencil
+    assert np.ptp(ratio) < (1e-10 if order == 1 else 1e-9) * ratio.mean()
+
+
+def test_second_order_transport_is_exact_on_quadratic_profiles():
+    # With the slopes of eq. slope, the upwind flux difference of a profile
+    # quadratic in x is exact at interior cells (the slope terms cancel the
+    # O(dx) error of first-order upwinding, |v_1| c dx for f = c x^2).
+    sp = Spec(d=3, N=8, L=6.0, n_theta=2, n_phi=4, n_rho=2)
+    v1 = velocity_nodes(sp)[:, 0]
+    g = np.exp(-0.3 * (velocity_nodes(sp) ** 2).sum(1))  # any velocity profile
+    for order, exact in ((2, True), (1, False)):
+        prob = SW.Slab(spec=sp, nx=10, eps=1.0, collision="bgk", order=order)
+        x = prob.xL + (np.arange(prob.nx) + 0.5) * prob.dx
+        c = 0.7
+        f = 1.0 + c * x[:, None] ** 2 * g[None, :]
+        R = SW.residual_field(prob, f, np.zeros_like(f))
+        ref = v1[None, :] * 2.0 * c * x[:, None] * g[None, :]
+        err = np.abs(R[2:-2] - ref[2:-2]).max() / np.abs(ref).max()
+        assert (err < 1e-12) if exact else (err > 1e-3), (order, err)
 
 
 def test_sgs_fp_and_pfp_reach_the_same_state():
