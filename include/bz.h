@@ -277,6 +277,14 @@ typedef struct {
   double bgk_nu;                     /* BGK only; <= 0: 4 pi rho */
   bz_solve_opts inner;               /* inner solve options */
   double* f;                         /* device [sum nx][K], borrowed */
+  int order;                         /* spatial order of eq. upwind: 1 (zero slopes) or 2
+                                        (piecewise-linear reconstruction with the slopes of
+                                        eq. slope: centred inside, one-sided at the two end
+                                        cells, zero ghost slopes; taken from the iterate
+                                        before each scan, so they enter the static part of
+                                        r, Section 3.1).  The wall density then balances the
+                                        flux of the face value f_0 - s_0/2 (left) or
+                                        f_{nx-1} + s_{nx-1}/2 (right).  0 reads as 1. */
 } bz_slab_desc;
 
 typedef struct bz_slab bz_slab;
@@ -294,7 +302,7 @@ typedef struct {
 } bz_sweep_stats;
 
 /* bz_sgs_sweep: n_iters full SGS iterations (forward then backward scan,
- * eq. SGS; first-order upwind), each followed by the uniform mass rescale of
+ * eq. SGS, at the desc's spatial order), each followed by the uniform mass rescale of
  * Section 4.  P and nu of every cell are computed in one batched collision
  * evaluation before each scan (P is explicit); the cells of a scan are
  * then visited in order, one visit per instance at a time.

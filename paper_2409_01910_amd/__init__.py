@@ -66,7 +66,7 @@ class bz_slab_instance(ctypes.Structure):
 class bz_slab_desc(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int), ("instances", ctypes.POINTER(bz_slab_instance)),
                 ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double), ("inner", bz_solve_opts),
-                ("f", ctypes.c_void_p)]
+                ("f", ctypes.c_void_p), ("order", ctypes.c_int)]
 
 
 class bz_sweep_stats(ctypes.Structure):
@@ -317,10 +317,11 @@ class Slab:
 
     ``instances`` is a list of dicts with keys xL, xR, nx, eps, T_L, T_R, U_L, U_R,
     mass, and optionally bc_L / bc_R ("wall" or "inflow") with rho_L / rho_R.  ``f`` is a float64 device tensor [sum nx, K] that the slab reads and
-    updates in place (borrowed for the slab's lifetime)."""
+    updates in place (borrowed for the slab's lifetime).  ``order`` is the
+    spatial order (1, or 2 for the linear reconstruction)."""
 
     def __init__(self, ctx: Context, instances, f, collision: str = "binary", bgk_nu: float = 0.0,
-                 mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0):
+                 mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, order: int = 1):
         self.ctx = ctx
         self.f = f
         n = len(instances)
@@ -340,7 +341,7 @@ class Slab:
             raise BZError("f must hold sum(nx) cells")
         self._arr = arr
         desc = bz_slab_desc(n, arr, _COLLISIONS[collision], bgk_nu,
-                            Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()))
+                            Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order)
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_slab_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_slab_create")
         self.h = h

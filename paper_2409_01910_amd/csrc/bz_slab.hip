@@ -1,5 +1,8 @@
 // Symmetric Gauss-Seidel scans, outer residual, mass constraint and the FAS
-// multigrid V-cycle on 1D slabs (Sections 3.1, 3.3 and 4), first-order upwind.
+// multigrid V-cycle on 1D slabs (Sections 3.1, 3.3 and 4), upwind finite
+// volumes of first order or with the piecewise-linear reconstruction of
+// eqs. reconstruction / slope (second order; the slopes are taken from the
+// iterate before each scan and enter the static right-hand side).
 //
 // One scan of eq. SGS on every instance:
 //   batched   Q, M[f], nu of every cell from the iterate before the scan
@@ -61,6 +64,7 @@ struct Level {
   double* fc0 = nullptr;  // restricted fine iterate (coarse levels)
   double* cellsum = nullptr;
   double* ghost = nullptr;  // [n_inst][2] wall densities
+  double* S = nullptr;      // [cells][K] slopes of eq. slope (second order only)
   bool q_valid = false;
 };
 
@@ -72,6 +76,7 @@ struct bz_slab {
   std::vector<bz_slab_instance> inst;
   int collision = 0;
   double bgk_nu = 0.0;
+  int order = 1;  // 1: first-order upwind; 2: linear reconstruction (eq. slope)
   bz_solve_opts inner{};
   double* wallM = nullptr;    // [n_inst][2][K] unit-density wall Maxwellians
   double* wall_in = nullptr;  // [n_inst][2] incoming discrete flux of the unit wall Maxwellian
@@ -112,8 +117,12 @@ __global__ __launch_bounds__(kCellThreads) void k_wall_init(const WallDev* __res
   }
 }
 
+// wall density from the zero-mass-flux balance with the wall-adjacent face
+// value: f_0 - s_0 / 2 at the left wall, f_{nx-1} + s_{nx-1} / 2 at the right
+// (S = nullptr at first order)
 template <int N>
-__global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __restrict__ f, const InstDev* __restrict__ inst,
+__global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __restrict__ f, const double* __restrict__ S,
+                                                            const InstDev* __restrict__ inst,
                                                             const double* __restrict__ wall_in,
                                                             const double* __restrict__ bc_fixed,
                                                             double* __restrict__ ghost, const double* __restrict__ nodes,
@@ -125,16 +134,37 @@ __global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __rest
     return;
   }
   const InstDev id = inst[i];
-  const double* fc = f + (size_t)(id.off + (side == 0 ? 0 : id.nx - 1)) * K;
+  const size_t cell = (size_t)(id.off + (side == 0 ? 0 : id.nx - 1));
+  const double* fc = f + cell * K;
+  const double* sc = S ? S + cell * K : fc;
+  const double hs = S ? (side == 0 ? -0.5 : 0.5) : 0.0;
   __shared__ double s_red[kCellThreads / 64];
   double acc[1] = {0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
-    // outgoing half-space of the wall-adjacent cell
-    if (side == 0 ? v0 < 0.0 : v0 > 0.0) acc[0] += fabs(v0) * fc[k];
+    // outgoing half-space of the wall-adjacent cell's face value
+    if (side == 0 ? v0 < 0.0 : v0 > 0.0) acc[0] += fabs(v0) * (fc[k] + hs * sc[k]);
   }
   block_sum<1>(acc, s_red);
   if (threadIdx.x == 0) ghost[i * 2 + side] = w * acc[0] / wall_in[i * 2 + side];
+}
+
+// eq. slope: centred differences inside, one-sided at the two ends, zero for
+// a one-cell instance
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_slopes(const double* __restrict__ f, double* __restrict__ S,
+                                                         const InstDev* __restrict__ inst,
+                                                         const int* __restrict__ cell_inst) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const InstDev id = inst[cell_inst[c]];
+  const int j = c - id.off;
+  const int jp = j < id.nx - 1 ? j + 1 : j, jm = j > 0 ? j - 1 : j;
+  const double wgt = (id.nx < 2) ? 0.0 : (jp - jm == 2 ? 0.5 : 1.0);
+  const double* a = f + (size_t)(id.off + jp) * K;
+  const double* b = f + (size_t)(id.off + jm) * K;
+  double* out = S + (size_t)c * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) out[k] = wgt * (a[k] - b[k]);
 }
 
 // theta -> (axis factors, e^alpha); returns 4 pi rho of the Gaussian in s_nu
@@ -163,7 +193,7 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ pre, double* __restrict__ nu_out,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
     const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w,
-    double u0) {
+    double u0, const double* __restrict__ S) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const int i = cell_inst[c];
@@ -219,6 +249,13 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     A = MR;
     sA = (j == id.nx - 1) ? gR : 0.0;
   }
+  // second order: the reconstruction adds -(v+ s_{j-1} - v_1 s_j + v- s_{j+1}) / (2 dx),
+  // with zero ghost slopes (weights 0 and a valid pointer when a slope is absent)
+  const double* Sc = S ? S + (size_t)c * K : fc;
+  const double* Sl = (S && j > 0) ? Sc - K : Sc;
+  const double* Sr = (S && j < id.nx - 1) ? Sc + K : Sc;
+  const double hsc = S ? 0.5 * idx : 0.0;
+  const double wl = (S && j > 0) ? 1.0 : 0.0, wr = (S && j < id.nx - 1) ? 1.0 : 0.0;
   __shared__ double s_nodes[N];
   if (threadIdx.x < N) s_nodes[threadIdx.x] = nodes[threadIdx.x];
   __syncthreads();
@@ -232,7 +269,8 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     const double vp = fmax(v0 + u0, 0.0), vm = fmin(v0 + u0, 0.0);  // physical v_1
     const double M = ea * s_E[0][a0] * s_E[1][a1] * s_E[2][a2];
     const double fk = fc[k];
-    const double r = -wq * (Qc[k] - nu * (M - fk)) - wb * bp[k] + idx * (vm * sA * A[k] - vp * sB * B[k]);
+    const double r = -wq * (Qc[k] - nu * (M - fk)) - wb * bp[k] + idx * (vm * sA * A[k] - vp * sB * B[k]) -
+                     hsc * (vp * wl * Sl[k] - (vp + vm) * Sc[k] + vm * wr * Sr[k]);
     out[k] = r;
     const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
     const double cc = s_c[a0], rd = r * s_dinv[a0];
@@ -367,7 +405,8 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
     const double* __restrict__ f, const double* __restrict__ Q, const double* __restrict__ theta,
     const double* __restrict__ bsrc, double* __restrict__ Rout, double* __restrict__ cellres,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
-    const double* __restrict__ wallM, int bgk, double bgk_nu, const double* __restrict__ nodes, double w, double u0) {
+    const double* __restrict__ wallM, int bgk, double bgk_nu, const double* __restrict__ nodes, double w, double u0,
+    const double* __restrict__ S) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const int i = cell_inst[c];
@@ -395,6 +434,12 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
   const double wq = bgk ? 0.0 : 1.0, wm = bgk ? 1.0 : 0.0;
   const double* bp = bsrc ? bsrc + (size_t)c * K : fc;
   const double wb = bsrc ? 1.0 : 0.0;
+  // second order: (v+ (s_j - s_{j-1}) + v- (s_j - s_{j+1})) / (2 dx), zero ghost slopes
+  const double* Sc = S ? S + (size_t)c * K : fc;
+  const double* Sl = (S && j > 0) ? Sc - K : Sc;
+  const double* Sr = (S && j < id.nx - 1) ? Sc + K : Sc;
+  const double hsc = S ? 0.5 * idx : 0.0;
+  const double wl = (S && j > 0) ? 1.0 : 0.0, wr = (S && j < id.nx - 1) ? 1.0 : 0.0;
   double acc[1] = {0.0};
 #pragma unroll 4
   for (int k = threadIdx.x; k < K; k += kCellThreads) {
@@ -404,7 +449,8 @@ __global__ __launch_bounds__(kCellThreads) void k_residual(
     const double left = sL * Lp[k], right = sR * Rp[k];
     const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
     const double q = wq * Qc[k] + wm * nu * (M - fk);
-    const double T = (vp * (fk - left) + vm * (right - fk)) * idx - q * ie;
+    const double T = (vp * (fk - left) + vm * (right - fk)) * idx - q * ie -
+                     hsc * (vp * wl * Sl[k] - (vp + vm) * Sc[k] + vm * wr * Sr[k]);
     if (Rout) Rout[(size_t)c * K + k] = T;
     const double d = T - wb * bp[k];
     acc[0] += d * d;
@@ -463,7 +509,7 @@ __global__ void k_prolong_add(double* f, const double* __restrict__ fc, const do
       return set_err(ctx, BZ_EUNSUPPORTED, "N must be 8, 16 or 32"); \
   }
 
-static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg) {
+static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg, bool with_slopes) {
   const size_t K = ctx->K;
   BZ_HIP(hipMalloc((void**)&L.d_inst, sizeof(InstDev) * L.h_inst.size()));
   BZ_HIP(hipMemcpy(L.d_inst, L.h_inst.data(), sizeof(InstDev) * L.h_inst.size(), hipMemcpyHostToDevice));
@@ -480,11 +526,12 @@ static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg) {
   BZ_HIP(hipMalloc((void**)&L.cellsum, sizeof(double) * L.ncell));
   BZ_HIP(hipMalloc((void**)&L.ghost, sizeof(double) * 2 * n_inst));
   if (with_mg) BZ_HIP(hipMalloc((void**)&L.R, sizeof(double) * K * L.ncell));
+  if (with_slopes) BZ_HIP(hipMalloc((void**)&L.S, sizeof(double) * K * L.ncell));
   return BZ_OK;
 }
 
 static void level_free(Level& L) {
-  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.pre, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0};
+  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.pre, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0, L.S};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (L.own_f && L.f) (void)hipFree(L.f);
@@ -506,10 +553,14 @@ static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   return e;
 }
 
+// slopes of the current iterate (second order), then the wall densities
 static bz_status ghosts(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
+  if (s->order == 2)
+    BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_slopes<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.S,
+                                         L.d_inst, L.d_cell_inst));
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_ghost_rho<NN_>), dim3(2 * s->n_inst), dim3(kCellThreads), 0, st, L.f,
-                                       L.d_inst, s->wall_in, s->bc_fixed, L.ghost, ctx->d_nodes, ctx->w,
-                                       ctx->p.v1_shift));
+                                       s->order == 2 ? L.S : nullptr, L.d_inst, s->wall_in, s->bc_fixed, L.ghost,
+                                       ctx->d_nodes, ctx->w, ctx->p.v1_shift));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
@@ -521,7 +572,8 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
   const int bgk = s->collision == BZ_COLL_BGK;
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_static_rhs<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
-                                       forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift));
+                                       forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift,
+                                       s->order == 2 ? L.S : nullptr));
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift};
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.theta,
                                        L.nu,
@@ -559,7 +611,7 @@ static bz_status residual_launch(bz_ctx* ctx, bz_slab* s, Level& L, bool keep_fi
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_residual<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
                                        L.theta, L.b, keep_field ? L.R : nullptr, L.cellsum, L.d_inst, L.d_cell_inst,
                                        L.ghost, s->wallM, bgk, bgk ? s->bgk_nu : 0.0, ctx->d_nodes, ctx->w,
-                                       ctx->p.v1_shift));
+                                       ctx->p.v1_shift, s->order == 2 ? L.S : nullptr));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
@@ -613,7 +665,7 @@ static bz_status build_mg(bz_ctx* ctx, bz_slab* s, int coarsest) {
     const Level& F = s->levels.back();
     L.ncell = F.ncell / 2;
     for (const InstDev& fi : F.h_inst) L.h_inst.push_back(InstDev{fi.off / 2, fi.nx / 2, fi.dx * 2.0, fi.eps, fi.mass});
-    bz_status e = level_alloc(ctx, L, s->n_inst, true);
+    bz_status e = level_alloc(ctx, L, s->n_inst, true, s->order == 2);
     if (e != BZ_OK) return e;
     BZ_HIP(hipMalloc((void**)&L.f, sizeof(double) * K * L.ncell));
     L.own_f = true;
@@ -707,6 +759,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (!ctx || !out) return BZ_EINVAL;
   *out = nullptr;
   if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
+  if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK && d->collision != BZ_COLL_BINARY_CONSERVE)
     return set_err(ctx, BZ_EINVAL, "bad collision");
   const bz_solve_opts& o = d->inner;
@@ -748,12 +801,13 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   s->inst.assign(d->instances, d->instances + d->n_instances);
   s->collision = d->collision;
   s->bgk_nu = d->bgk_nu;
+  s->order = d->order == 0 ? 1 : d->order;
   s->inner = d->inner;
   bz::Level L0;
   L0.ncell = off;
   L0.h_inst = hi;
   L0.f = d->f;
-  bz_status e = bz::level_alloc(ctx, L0, s->n_inst, false);
+  bz_status e = bz::level_alloc(ctx, L0, s->n_inst, false, s->order == 2);
   s->levels.push_back(L0);
   auto fail = [&](bz_status st) {
     bz_slab_destroy(s);

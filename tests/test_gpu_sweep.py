@@ -22,7 +22,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp", bgk_nu=None, T0=1.5):
+def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp", bgk_nu=None, T0=1.5, order=1):
     import paper_2409_01910_amd as bz
 
     sp = Spec(d=3, N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr)
@@ -30,12 +30,13 @@ def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp"
     for d in instances:
         p = SW.Slab(spec=sp, nx=d["nx"], xL=d.get("xL", 0.0), xR=d.get("xR", 1.0), T_L=d.get("T_L", 1.0),
                     T_R=d.get("T_R", 2.0), eps=d["eps"], mass=d.get("mass", 1.0), collision=collision,
-                    bgk_nu=bgk_nu, inner=mode, fixed_inner=fixed_inner)
+                    bgk_nu=bgk_nu, inner=mode, fixed_inner=fixed_inner, order=order)
         probs.append(p)
         f0.append(SW.initial_state(p, T=T0))
     ctx = bz.Context(N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr)
     fg = torch.from_numpy(np.concatenate(f0)).to(dev).contiguous()
-    slab = bz.Slab(ctx, instances, fg, collision=collision, bgk_nu=bgk_nu or 0.0, mode=mode, fixed_iters=fixed_inner)
+    slab = bz.Slab(ctx, instances, fg, collision=collision, bgk_nu=bgk_nu or 0.0, mode=mode, fixed_iters=fixed_inner,
+                   order=order)
     return sp, probs, f0, ctx, slab, fg
 
 
@@ -81,6 +82,35 @@ def test_ragged_instances_are_independent(dev):
 def test_vcycle_matches_oracle(dev, collision):
     inst = [dict(nx=8, eps=0.1, mass=1.0)]
     sp, probs, f0, ctx, slab, fg = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=2)
+    res, _ = slab.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
+    f = SW.vcycle(probs[0], f0[0], None, 2, 1, 1, 0.0, coarse_iters=3)
+    f = f * (probs[0].mass / SW.total_mass(probs[0], f))
+    got = _split(fg, inst)[0]
+    assert np.max(np.abs(got - f)) < 1e-9 * f.max()
+    assert abs(res[0] - SW.outer_residual(probs[0], f)) < 1e-8 * res[0]
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_second_order_sgs_matches_oracle(dev, collision):
+    # ragged instances cover the one-cell (zero slopes), two-cell (one-sided
+    # only) and interior slope cases
+    inst = [dict(nx=5, eps=0.1, mass=1.0), dict(nx=1, eps=0.5, mass=0.9), dict(nx=2, eps=0.05, mass=1.1)]
+    print(f"second order sgs {collision}", flush=True)
+    sp, probs, f0, ctx, slab, fg = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=3, order=2)
+    res, _ = slab.sweep(2)
+    got = _split(fg, inst)
+    for i in range(3):
+        f = f0[i]
+        for _ in range(2):
+            f = SW.sgs_iteration(probs[i], f)
+        assert np.max(np.abs(got[i] - f)) < 1e-10 * f.max(), i
+        assert abs(res[i] - SW.outer_residual(probs[i], f)) < 1e-9 * res[i], i
+
+
+def test_second_order_vcycle_matches_oracle(dev):
+    inst = [dict(nx=8, eps=0.1, mass=1.0)]
+    print("second order vcycle", flush=True)
+    sp, probs, f0, ctx, slab, fg = _setup(dev, 8, 6.0, 2, 4, 3, inst, "binary", fixed_inner=2, order=2)
     res, _ = slab.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
     f = SW.vcycle(probs[0], f0[0], None, 2, 1, 1, 0.0, coarse_iters=3)
     f = f * (probs[0].mass / SW.total_mass(probs[0], f))
@@ -170,6 +200,8 @@ def test_bad_boundary_arguments_are_rejected(dev):
         bz.Slab(ctx, [dict(nx=3, eps=0.1, bc_L="inflow", rho_L=0.0)], f)
     with pytest.raises(bz.BZError):
         bz.Slab(ctx, [dict(nx=3, eps=0.1, U_L=(1.0, 0.0, 0.0))], f)  # a wall moving along x
+    with pytest.raises(bz.BZError):
+        bz.Slab(ctx, [dict(nx=3, eps=0.1)], f, order=3)
 
 
 @pytest.mark.parametrize("collision", ["bgk", "binary"])
