@@ -101,17 +101,20 @@ def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
                       f"numpy FP64, one thread, {dt:.1f} s"}
 
 
-def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0):
+def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0, order=1):
     """Heat slab x in [0, 1], nx cells, diffuse walls T = 1 and 2 at rest, n^3
     velocities on [-l, l]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes,
     initial Maxwellian u = 0, T = 1.5 of total mass 1; SGS-PFP with inner
-    residual 1e-8, one SGS iteration (method "sgs") or one V-cycle (method "mg":
-    coarsest 4 cells, one pre- and one post-smoothing step) per call so that
+    residual 1e-8, one SGS iteration (method "sgs") or one V-cycle (method "mg",
+    with the parameters of tab. mg: coarsest 4 cells, one pre- and one
+    post-smoothing step at first order; coarsest 8 cells, five pre- and one
+    post-smoothing step at second order) per call so that
     the outer residual is read after every iteration; with graph_iters > 0 the
     SGS iterations run as replays of a captured graph of that many iterations
     (residual read once per replay).  plan = [(precision, switch_residual), ...]: run in
     each precision until the residual is below its switch value (or stalls for
-    50 iterations), then continue from the same f in the next one."""
+    50 iterations), then continue from the same f in the next one.  order 2:
+    the linear reconstruction of eq. slope."""
     import numpy as np
     import torch
 
@@ -129,7 +132,7 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
         prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
         ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8, precision=prec)
         slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="binary",
-                       tol=1e-8, max_iter=100)
+                       tol=1e-8, max_iter=100, order=order)
         if not hist:
             hist.append(slab.residual()[0])
         start = len(hist)
@@ -140,7 +143,12 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
                 r, st = graph.launch()
                 hist.extend([None] * (graph_iters - 1))  # residual read once per replay
             else:
-                r, st = slab.sweep(1) if method == "sgs" else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
+                if method == "sgs":
+                    r, st = slab.sweep(1)
+                elif order == 2:
+                    r, st = slab.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
+                else:
+                    r, st = slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
             hist.append(r[0])
             inner += st["inner_iters"]
             visits += st["visits"]
@@ -178,6 +186,8 @@ def slab_workload(args, tol=1e-8):
         "n32_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, method="mg"),
         "n32_128cells_fp64": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 90.0, nx=128),
         "n32_128cells_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, nx=128, method="mg"),
+        "n32_order2": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 120.0, order=2),
+        "n32_order2_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 120.0, method="mg", order=2),
     }
     names = list(cases) if args.slab_case == "all" else [args.slab_case]
     out = {k: cases[k]() for k in names}
@@ -333,7 +343,8 @@ def main():
     ap.add_argument("--slab-case", default="all",
                     choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_graph10", "n32_mg",
                              "n32_128cells_fp64",
-                             "n32_128cells_mg"], help="with --workload slab: run one case only")
+                             "n32_128cells_mg", "n32_order2", "n32_order2_mg"],
+                    help="with --workload slab: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
