@@ -158,9 +158,36 @@ def q_corrected(spec: Spec, f: np.ndarray, M: np.ndarray | None = None, op=q_fsm
     return Q
 
 
-def nu_of(spec: Spec, f: np.ndarray) -> float:
-    """BGK-penalty frequency nu = |S^{d-1}| rho (Section 4.2: 2 pi rho for 2D
-    velocity; the 3D analogue 4 pi rho, Section 4.1.2)."""
+def pair_speed_moment(spec: Spec, T: float) -> float:
+    """<|g|^gamma> over pairs drawn from a Maxwellian of temperature T.  The
+    relative velocity of two such particles is Maxwellian with temperature 2T,
+    so |g|^2 / (2T) is chi-squared with d degrees of freedom and
+    <|g|^gamma> = (4T)^{gamma/2} Gamma((d + gamma)/2) / Gamma(d/2); it is 1 for
+    gamma = 0."""
+    from math import gamma as Gamma
+
+    g, d = spec.gamma, spec.d
+    return (4.0 * T) ** (g / 2.0) * Gamma((d + g) / 2.0) / Gamma(d / 2.0)
+
+
+def nu_of(spec: Spec, f: np.ndarray, theta: np.ndarray | None = None) -> float:
+    """BGK-penalty frequency of eq. Pf: nu = |S^{d-1}| rho <|g|^gamma>, the binary
+    loss frequency averaged over pairs from the cell's Maxwellian, with T the
+    temperature parameter 1 / (2 theta_gamma) of the discrete Maxwellian.  For
+    Maxwell molecules (gamma = 0) this is |S^{d-1}| rho: 2 pi rho for 2D velocity
+    (Section 4.2), 4 pi rho in 3D (Section 4.1.2), where the BGK loss matches
+    the binary loss exactly; for hard spheres the average keeps the penalty of
+    the same size as the loss term it stands in for."""
+    rho = moments(spec, f)[0]
+    if spec.gamma == 0.0:
+        return sphere_area(spec.d) * rho
+    if theta is None:
+        theta = discrete_maxwellian(spec, f, return_theta=True)[1]
+    return sphere_area(spec.d) * rho * pair_speed_moment(spec, 0.5 / theta[-1])
+
+
+def bgk_nu_of(spec: Spec, f: np.ndarray) -> float:
+    """Collision frequency of the BGK model: |S^{d-1}| rho (Section 4.1.2)."""
     return sphere_area(spec.d) * moments(spec, f)[0]
 
 

@@ -30,7 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cell as cellmod
-from .collision import nu_of, q_corrected, q_fsm
+from .collision import bgk_nu_of, nu_of, q_corrected, q_fsm
 from .grid import Spec, sphere_area, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, moments
 
@@ -53,6 +53,7 @@ class Slab:
     rho_R: float = 1.0
     order: int = 1
     collision: str = "binary"  # "binary" (Q^FSM with eq. discrete_Q) or "bgk" (P == 0)
+    q_method: str = "sigma"  # binary: "sigma" (collision.q_fsm) or "carleman" (carleman.q_carleman, gamma = 1)
     conserve: str = "mass"  # binary: project Q onto zero mass ("mass") or all five invariants ("all")
     bgk_nu: float | None = None  # constant nu for "bgk"; None -> |S^{d-1}| rho
     inner: str = "pfp"
@@ -118,11 +119,15 @@ def collision_terms(prob: Slab, f_j: np.ndarray):
     binary mode, or nu (M - f) in BGK
     mode."""
     spec = prob.spec
-    M = discrete_maxwellian(spec, f_j)
+    M, theta = discrete_maxwellian(spec, f_j, return_theta=True)
     if prob.collision == "bgk":
-        nu = prob.bgk_nu if prob.bgk_nu is not None else nu_of(spec, f_j)
+        nu = prob.bgk_nu if prob.bgk_nu is not None else bgk_nu_of(spec, f_j)
         return nu * (M - f_j), M, nu
-    return q_corrected(spec, f_j, M, op=q_fsm, conserve=prob.conserve), M, nu_of(spec, f_j)
+    if prob.q_method == "carleman":
+        from .carleman import q_carleman as op
+    else:
+        op = q_fsm
+    return q_corrected(spec, f_j, M, op=op, conserve=prob.conserve), M, nu_of(spec, f_j, theta)
 
 
 def residual_field(prob: Slab, f: np.ndarray, Q: np.ndarray) -> np.ndarray:

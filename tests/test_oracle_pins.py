@@ -263,6 +263,31 @@ def test_collisionless_slab_closed_form(order):
     assert np.ptp(ratio) < (1e-10 if order == 1 else 1e-9) * ratio.mean()
 
 
+def test_penalty_frequency_is_the_mean_binary_loss_frequency():
+    # Hard spheres: nu equals the Maxwellian average of the exact loss frequency
+    # 4 pi int |v - w| M(w) dw (closed form with erf), integrated radially here;
+    # Maxwell molecules: nu = 4 pi rho exactly (Section 4.1.2)
+    from scipy.integrate import quad
+    from scipy.special import erf
+
+    T, rho = 1.0, 1.3
+    sp = Spec(d=3, N=32, L=8.0, gamma=1.0)
+    v = velocity_nodes(sp)
+    M = rho * (2 * np.pi * T) ** -1.5 * np.exp(-(v * v).sum(1) / (2 * T))
+
+    def nu_hs(r):
+        c = r / np.sqrt(2 * T)
+        if c == 0.0:
+            return rho * np.sqrt(8 * T / np.pi)
+        return rho * np.sqrt(2 * T) * (np.exp(-c * c) / np.sqrt(np.pi) + (c + 0.5 / c) * erf(c))
+
+    dens = lambda r: 4 * np.pi * r * r * (2 * np.pi * T) ** -1.5 * np.exp(-r * r / (2 * T))
+    mean = quad(lambda r: dens(r) * 4 * np.pi * nu_hs(r), 0.0, 40.0, epsabs=0, epsrel=1e-12, limit=200)[0]
+    assert abs(C.nu_of(sp, M) - mean) < 1e-8 * mean
+    sp0 = Spec(d=3, N=32, L=8.0, gamma=0.0)
+    assert C.nu_of(sp0, M) == 4 * np.pi * MX.moments(sp0, M)[0]
+
+
 def test_second_order_transport_is_exact_on_quadratic_profiles():
     # With the slopes of eq. slope, the upwind flux difference of a profile
     # quadratic in x is exact at interior cells (the slope terms cancel the
