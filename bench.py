@@ -101,7 +101,8 @@ def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
                       f"numpy FP64, one thread, {dt:.1f} s"}
 
 
-def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0, order=1):
+def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0, order=1,
+              gamma=0.0, q_method="sigma"):
     """Heat slab x in [0, 1], nx cells, diffuse walls T = 1 and 2 at rest, n^3
     velocities on [-l, l]^3, Maxwell molecules, M = 32 (4 x 8), 8 radial nodes,
     initial Maxwellian u = 0, T = 1.5 of total mass 1; SGS-PFP with inner
@@ -114,7 +115,9 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
     (residual read once per replay).  plan = [(precision, switch_residual), ...]: run in
     each precision until the residual is below its switch value (or stalls for
     50 iterations), then continue from the same f in the next one.  order 2:
-    the linear reconstruction of eq. slope."""
+    the linear reconstruction of eq. slope.  gamma / q_method: the kernel and
+    the spectral form (hard spheres, gamma = 1, with the sigma or the Carleman
+    form)."""
     import numpy as np
     import torch
 
@@ -130,7 +133,8 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
     t0 = time.perf_counter()
     for precision, switch in plan:
         prec = bz.BZ_FP64 if precision == "fp64" else bz.BZ_FP32
-        ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8, precision=prec)
+        ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8, precision=prec, gamma=gamma,
+                         method=bz.BZ_METHOD_CARLEMAN if q_method == "carleman" else bz.BZ_METHOD_SIGMA)
         slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="binary",
                        tol=1e-8, max_iter=100, order=order)
         if not hist:
@@ -188,6 +192,9 @@ def slab_workload(args, tol=1e-8):
         "n32_128cells_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 90.0, nx=128, method="mg"),
         "n32_order2": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 120.0, order=2),
         "n32_order2_mg": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 1000, 120.0, method="mg", order=2),
+        "n32_hs_sigma": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 120.0, gamma=1.0),
+        "n32_hs_carleman": lambda: _slab_run(32, 8.0, [("fp64", tol)], tol, 3000, 120.0, gamma=1.0,
+                                             q_method="carleman"),
     }
     names = list(cases) if args.slab_case == "all" else [args.slab_case]
     out = {k: cases[k]() for k in names}
@@ -343,7 +350,7 @@ def main():
     ap.add_argument("--slab-case", default="all",
                     choices=["all", "n16_fp64", "n32_fp64", "n32_fp32_then_fp64", "n32_graph10", "n32_mg",
                              "n32_128cells_fp64",
-                             "n32_128cells_mg", "n32_order2", "n32_order2_mg"],
+                             "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "

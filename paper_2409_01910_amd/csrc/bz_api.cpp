@@ -94,6 +94,7 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   ctx->w = ctx->dv * ctx->dv * ctx->dv;
   ctx->R = p->R > 0 ? p->R : 2.0 * p->L / (3.0 * std::sqrt(2.0) + 1.0);
   ctx->Rg = 2.0 * ctx->R;
+  ctx->nu_gfac = std::pow(4.0, 0.5 * p->gamma) * std::tgamma(0.5 * (3.0 + p->gamma)) / std::tgamma(1.5);
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) {
     delete ctx;

@@ -97,14 +97,15 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
   }
 }
 
-// r = inflow - (Q - nu (M_theta - f)) / eps ; nu = 4 pi rho
+// r = inflow - (Q - nu (M_theta - f)) / eps ; nu = penalty_nu (4 pi rho for Maxwell molecules)
 template <int N>
 __global__ __launch_bounds__(kCellThreads) void k_penalty_rhs(const double* __restrict__ f, const double* __restrict__ Q,
                                                               const double* __restrict__ theta,
                                                               const double* __restrict__ inflow,
                                                               const double* __restrict__ eps, double* __restrict__ r,
                                                               double* __restrict__ nu_out,
-                                                              const double* __restrict__ nodes, double w) {
+                                                              const double* __restrict__ nodes, double w, double gam,
+                                                              double gfac) {
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
   __shared__ double s_E[3][N];
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kCellThreads) void k_penalty_rhs(const double* __re
     double s[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a)
       for (int i = 0; i < N; ++i) s[a] += s_E[a][i];
-    s_nu = 4.0 * kPi * w * exp(th[0]) * s[0] * s[1] * s[2];
+    s_nu = penalty_nu(w * exp(th[0]) * s[0] * s[1] * s[2], th[4], gam, gfac);
     nu_out[b] = s_nu;
   }
   __syncthreads();
@@ -283,7 +284,8 @@ bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const doubl
                       const double* eps, double* r, double* nu, int64_t batch, hipStream_t st) {
   if (batch == 0) return BZ_OK;
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_penalty_rhs<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, f,
-                                           Q, theta, inflow, eps, r, nu, ctx->d_nodes, ctx->w));
+                                           Q, theta, inflow, eps, r, nu, ctx->d_nodes, ctx->w, ctx->p.gamma,
+                                           ctx->nu_gfac));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

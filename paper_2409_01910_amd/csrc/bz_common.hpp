@@ -117,6 +117,14 @@ __device__ __forceinline__ void fft_reg(T* re, T* im) {
   }
 }
 
+// BGK-penalty frequency of eq. Pf: nu = 4 pi rho <|g|^gamma>, the binary loss
+// frequency averaged over pairs from the cell's Maxwellian, whose temperature
+// parameter is T = 1 / (2 theta_4); gfac = 4^{gamma/2} Gamma((3 + gamma)/2) / Gamma(3/2).
+// For Maxwell molecules (gamma = 0) it is 4 pi rho exactly.
+__device__ __forceinline__ double penalty_nu(double rho, double theta4, double gam, double gfac) {
+  return gam == 0.0 ? 4.0 * kPi * rho : 4.0 * kPi * rho * gfac * pow(0.5 / theta4, 0.5 * gam);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -15,6 +15,7 @@ struct bz_ctx {
   int N = 0, K = 0;
   int n_theta = 0, n_phi = 0, n_rho = 0, n_pairs = 0;
   double dv = 0, w = 0, R = 0, Rg = 0;
+  double nu_gfac = 1.0;  // 4^{gamma/2} Gamma((3 + gamma)/2) / Gamma(3/2), for the penalty frequency
   std::string err;
 
   // host copies of the tables (FP64)

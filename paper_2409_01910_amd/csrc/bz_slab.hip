@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
     const double* __restrict__ bsrc, double* __restrict__ rs, double* __restrict__ pre, double* __restrict__ nu_out,
     const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, const double* __restrict__ ghost,
     const double* __restrict__ wallM, int forward, int bgk, double bgk_nu, const double* __restrict__ nodes, double w,
-    double u0, const double* __restrict__ S) {
+    double u0, const double* __restrict__ S, double gam, double gfac) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const int i = cell_inst[c];
@@ -202,7 +202,9 @@ __global__ __launch_bounds__(kCellThreads) void k_static_rhs(
   __shared__ double s_E[3][N];
   __shared__ double s_rho;
   gauss_tables<N>(theta + (size_t)c * 5, nodes, w, s_E, &s_rho);
-  const double nu = (bgk && bgk_nu > 0.0) ? bgk_nu : 4.0 * kPi * s_rho;
+  // BGK model: its own frequency (4 pi rho unless given); binary: the penalty frequency
+  const double nu = bgk ? (bgk_nu > 0.0 ? bgk_nu : 4.0 * kPi * s_rho)
+                        : penalty_nu(s_rho, theta[(size_t)c * 5 + 4], gam, gfac);
   if (threadIdx.x == 0) nu_out[c] = nu;
   const double ea = exp(theta[(size_t)c * 5]);
   const double ie = 1.0 / id.eps, idx = 1.0 / id.dx;
@@ -573,7 +575,7 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_static_rhs<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.Q,
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift,
-                                       s->order == 2 ? L.S : nullptr));
+                                       s->order == 2 ? L.S : nullptr, ctx->p.gamma, ctx->nu_gfac));
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift};
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.theta,
                                        L.nu,

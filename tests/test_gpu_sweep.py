@@ -204,18 +204,18 @@ def test_bad_boundary_arguments_are_rejected(dev):
         bz.Slab(ctx, [dict(nx=3, eps=0.1)], f, order=3)
 
 
-@pytest.mark.parametrize("collision", ["bgk", "binary"])
-def test_graph_replays_match_eager_sweeps(dev, collision):
+@pytest.mark.parametrize("collision,order", [("bgk", 1), ("binary", 1), ("binary", 2)])
+def test_graph_replays_match_eager_sweeps(dev, collision, order):
     # the same initial state in two slabs: eager sweeps of 2 iterations in one,
     # replays of a captured 2-iteration graph in the other, with eager work and
     # synchronisations between the replays; every replay must match
-    print(f"graph replay {collision}", flush=True)
+    print(f"graph replay {collision} order {order}", flush=True)
     inst = [dict(nx=6, eps=0.1, mass=1.0), dict(nx=4, eps=0.5, T_L=1.2, T_R=1.8, mass=0.9)]
-    sp, probs, f0, ctx, slab_e, fg_e = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=0)
+    sp, probs, f0, ctx, slab_e, fg_e = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=0, order=order)
     import paper_2409_01910_amd as bz
 
     fg_g = fg_e.clone()
-    slab_g = bz.Slab(ctx, inst, fg_g, collision=collision)
+    slab_g = bz.Slab(ctx, inst, fg_g, collision=collision, order=order)
     graph = slab_g.capture(2)
     start = fg_g.clone()
     for rep in range(3):
