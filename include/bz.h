@@ -68,11 +68,14 @@ typedef struct bz_ctx bz_ctx;
  *            BZ_METHOD_CARLEMAN: the fast form for kernels that separate in the
  *            Carleman representation (Section 2.2 cites this family of fast
  *            spectral methods); here hard spheres in 3D, gamma = 1, whose
- *            Carleman kernel is the constant 4.  With x, y truncated to the ball
- *            of radius 2R, the spectral weight separates per direction e of the
- *            half sphere into psi1(xi.e) Phi2(|P_e xi|),
- *              psi1(s) = 2 int_0^{2R} rho cos(rho s) drho,
- *              Phi2(t) = 2 pi (2R) J1(2R t) / t,
+ *            Carleman kernel is the constant 4.  x and y are truncated to the
+ *            ball of radius Rc = sqrt(2) R, the truncation that the cited fast
+ *            spectral construction keeps free of aliasing when
+ *            L = (3 sqrt 2 + 1) R / 2 (Section 4.2).  The spectral weight then
+ *            separates per direction e of the half sphere into
+ *            psi1(xi.e) Phi2(|P_e xi|),
+ *              psi1(s) = 2 int_0^{Rc} rho cos(rho s) drho,
+ *              Phi2(t) = 2 pi Rc J1(Rc t) / t,
  *            P_e the projection perpendicular to e.  The M/2 directions of the
  *            sphere rule with cos(theta) > 0 give the gain
  *              Q+ = sum_p IDFT(A_p fh) IDFT(B_p fh),

@@ -9,9 +9,11 @@ B = |g| (gamma = 1) is such a kernel.  Derivation used here:
 
   Carleman representation of the gain term (x = v' - v, y = v'_* - v, x.y = 0):
       Q+(v) = int int 4 |x + y|^{gamma - 1} delta(x.y) f(v + x) f(v + y) dx dy,
-  so for gamma = 1 the weight is the constant 4.  With x and y truncated to the
-  ball of radius R_c = R_g (it contains every collision of relative speed at
-  most R_g) and x = rho e, the spectral weight of (l, m) is
+  so for gamma = 1 the weight is the constant 4.  x and y are each truncated to
+  the ball of radius R_c = sqrt(2) R, R the support radius of f: in the cited
+  fast spectral construction that truncation is free of aliasing exactly when
+  L >= (3 sqrt 2 + 1) R / 2, the relation between L and R that Section 4.2
+  fixes.  With x = rho e, the spectral weight of (l, m) is
       beta(l, m) = 4 int_{S^2_+} psi1(xi_l . e) Phi2(|P_e xi_m|) de,
       psi1(s) = 2 int_0^{R_c} rho cos(rho s) d rho            (e and -e folded)
       Phi2(t) = int_{y perp e, |y| <= R_c} exp(i xi.y) dy = 2 pi R_c J1(R_c t) / t,
@@ -35,8 +37,8 @@ from .grid import Spec, sphere_rule, xi_grids
 
 
 def carleman_radius(spec: Spec) -> float:
-    """Truncation radius R_c of x and y: R_g = 2R."""
-    return spec.R_g
+    """Truncation radius R_c = sqrt(2) R of x and y (R the support radius)."""
+    return np.sqrt(2.0) * spec.support_R
 
 
 def half_sphere_rule(spec: Spec):

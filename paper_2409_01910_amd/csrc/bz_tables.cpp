@@ -77,7 +77,9 @@ static bz_status upload(bz_ctx* ctx, D** dst, const std::vector<S>& src) {
 // sphere (the sigma rule's nodes with cos(theta) > 0, weight w_p), the tables
 //   A_p(xi) = 4 w_p psi1(xi.e_p),  psi1(s) = 2 int_0^Rc rho cos(rho s) drho,
 //   B_p(xi) = Phi2(|P_{e_p} xi|),  Phi2(t) = 2 pi Rc J1(Rc t) / t,
-// with Rc = 2R, and the loss weight beta = sum_p A_p B_p.
+// with Rc = sqrt(2) R (R the support radius: the truncation of x and y that the
+// cited fast spectral construction keeps free of aliasing on [-L, L]^3 when
+// L = (3 sqrt 2 + 1) R / 2), and the loss weight beta = sum_p A_p B_p.
 static double carleman_psi1(double Rc, double s) {
   const double x = Rc * s;
   double v;
@@ -107,7 +109,7 @@ static double carleman_phi2(double Rc, double t) {
 static bz_status build_carleman_tables(bz_ctx* ctx, const std::vector<double>& ct, const std::vector<double>& wt,
                                        const std::vector<double>& xi) {
   const int N = ctx->N, K = ctx->K, nt = ctx->n_theta, np = ctx->n_phi;
-  const double Rc = ctx->Rg;
+  const double Rc = std::sqrt(2.0) * ctx->R;
   const int nd = (nt / 2) * np;
   std::vector<double> cw((size_t)nd * 2 * K), beta(K, 0.0);
   int p = 0;
