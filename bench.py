@@ -207,6 +207,72 @@ def slab_workload(args, tol=1e-8):
                                             "eps": 0.1}, "runs": out}
 
 
+def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10):
+    """BGK heat slab (x in [0, 1], walls T = 1 and 2 at rest, mass 1, n^3
+    velocities on [-l, l]^3) driven by V-cycles (tab. mg's parameters for the
+    order) to outer residual tol; cell averages of rho and T, V-cycles, seconds."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+    import synth
+
+    dv = 2.0 * l / n
+    m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+    f0 = np.repeat(m[None], nx, axis=0)
+    f0 *= 1.0 / ((1.0 / nx) * dv ** 3 * f0.sum())
+    f = torch.from_numpy(f0).cuda().contiguous()
+    ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8)
+    slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="bgk", tol=1e-11,
+                   max_iter=200, order=order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, cycles = slab.residual()[0], 0
+    mg = dict(coarsest=8, nu1=5, nu2=1) if order == 2 else dict(coarsest=4, nu1=1, nu2=1)
+    while r > tol and cycles < 400:
+        r = slab.vcycle(1, tol=tol, **mg)[0][0]
+        cycles += 1
+    dt = time.perf_counter() - t0
+    F = f.cpu().numpy()
+    slab.close()
+    x = (np.arange(n) - n // 2 + 1) * dv
+    V = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(-1, 3)
+    rho = F.sum(1) * dv ** 3
+    U = (F @ V) * dv ** 3 / rho[:, None]
+    T = ((F * (V * V).sum(1)).sum(1) * dv ** 3 / rho - (U * U).sum(1)) / 3.0
+    return rho, T, cycles, r, dt
+
+
+def order_workload(args):
+    """Section 4.1's order study on the BGK heat slab (16^3 velocities on
+    [-6, 6]^3): L2 errors err = sqrt(dx sum (m_j - m_ref_j)^2) of the cell
+    averages of rho and T for dx = 1/16 ... 1/128, first and second order,
+    against a 1024-cell second-order solution, at eps = 1 and 0.1."""
+    import numpy as np
+
+    out = {}
+    for eps in (1.0, 0.1):
+        rr, Tr, cyc, res, dt = _bgk_slab_averages(16, 6.0, 1024, eps, 2)
+        print(f"# order study eps {eps}: reference 1024 cells, {cyc} V-cycles, {dt:.1f} s", flush=True)
+        runs = {"reference": {"cells": 1024, "vcycles": cyc, "residual": res, "seconds": dt}}
+        for order in (1, 2):
+            rows, prev = [], None
+            for nx in (16, 32, 64, 128):
+                rho, T, cyc, res, dt = _bgk_slab_averages(16, 6.0, nx, eps, order)
+                k = 1024 // nx
+                er = float(np.sqrt(np.sum((rho - rr.reshape(nx, k).mean(1)) ** 2) / nx))
+                eT = float(np.sqrt(np.sum((T - Tr.reshape(nx, k).mean(1)) ** 2) / nx))
+                row = {"cells": nx, "err_rho": er, "err_T": eT, "vcycles": cyc, "seconds": dt}
+                if prev is not None:
+                    row["order_rho"] = float(np.log2(prev[0] / er))
+                    row["order_T"] = float(np.log2(prev[1] / eT))
+                rows.append(row)
+                prev = (er, eT)
+            runs[f"order{order}"] = rows
+        out[f"eps={eps}"] = runs
+    return {"workload": "order", "data": "synthetic", "dtype": "f64", "runs": out}
+
+
 def shock_workload(args, tol=1e-8):
     """Normal shocks between Rankine-Hugoniot inflow states, x in [-20, 20], 128
     cells, 32^3 velocities on [-8, 8]^3 shifted along v_1 to the mean of the two
@@ -352,10 +418,11 @@ def main():
                              "n32_128cells_fp64",
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
-    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock"], default="batched-q",
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
-                         "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded)")
+                         "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded); "
+                         "order: first/second-order accuracy study on the BGK heat slab")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -375,6 +442,9 @@ def main():
         return
     if args.workload == "shock":
         print(json.dumps(shock_workload(args)), flush=True)
+        return
+    if args.workload == "order":
+        print(json.dumps(order_workload(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")

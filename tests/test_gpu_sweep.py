@@ -231,3 +231,48 @@ def test_graph_replays_match_eager_sweeps(dev, collision, order):
     assert (fg_g - start).abs().max().item() > 1e-6 * start.abs().max().item()
     graph.close()
     slab_g.close()
+
+
+def _bgk_heat_slab_moments(dev, nx, order, eps=1.0, N=16, L=6.0, tol=1e-10):
+    # BGK heat slab (walls T = 1 and 2 at rest, mass 1) driven by V-cycles to the
+    # outer residual tol; returns the cell averages of rho and T
+    import paper_2409_01910_amd as bz
+    from oracle.maxwellian import macroscopic
+
+    sp = Spec(d=3, N=N, L=L, n_theta=4, n_phi=8, n_rho=8)
+    prob = SW.Slab(spec=sp, nx=nx, eps=eps, mass=1.0, collision="bgk", order=order)
+    ctx = bz.Context(N=N, L=L, n_theta=4, n_phi=8, n_rho=8)
+    fg = torch.from_numpy(SW.initial_state(prob, T=1.5)).to(dev).contiguous()
+    slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, mass=1.0)], fg, collision="bgk", tol=1e-11, max_iter=200, order=order)
+    r = slab.residual()[0]
+    for _ in range(200):
+        if r <= tol:
+            break
+        mg = dict(coarsest=8, nu1=5, nu2=1) if order == 2 else dict(coarsest=4, nu1=1, nu2=1)
+        r = slab.vcycle(1, tol=tol, **mg)[0][0]
+    assert r <= tol
+    rho, T = [], []
+    for fj in fg.cpu().numpy():
+        rj, _, Tj = macroscopic(sp, fj)
+        rho.append(rj)
+        T.append(Tj)
+    slab.close()
+    return np.array(rho), np.array(T)
+
+
+def test_first_and_second_order_schemes_converge_at_their_order(dev):
+    # Section 4.1's order study on the heat slab: L2 errors of the cell averages of
+    # rho and T against a 512-cell second-order solution, err = sqrt(dx sum (m_j -
+    # m_ref_j)^2), for dx = 1/16, 1/32, 1/64; observed orders near 1 and 2
+    print("order of accuracy, BGK heat slab eps = 1", flush=True)
+    rho_ref, T_ref = _bgk_heat_slab_moments(dev, 512, 2)
+    for order, lo in ((1, 0.85), (2, 1.8)):
+        errs = []
+        for nx in (16, 32, 64):
+            rho, T = _bgk_heat_slab_moments(dev, nx, order)
+            k = 512 // nx
+            ra, Ta = rho_ref.reshape(nx, k).mean(1), T_ref.reshape(nx, k).mean(1)
+            errs.append((np.sqrt(np.sum((rho - ra) ** 2) / nx), np.sqrt(np.sum((T - Ta) ** 2) / nx)))
+        rates = [np.log2(np.array(errs[i]) / np.array(errs[i + 1])) for i in range(2)]
+        print(f"order {order}: errors {errs} observed orders {rates}", flush=True)
+        assert all((r > lo).all() for r in rates)
