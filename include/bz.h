@@ -82,7 +82,19 @@ typedef struct bz_ctx bz_ctx;
  *              A_p = 4 w_p psi1(xi.e_p),  B_p = Phi2(|P_{e_p} xi|),
  *            and the loss f IDFT(beta fh) with beta = sum_p A_p B_p, so the
  *            plain form conserves mass exactly.  n_rho is not used.  A context
- *            with this method and gamma != 1 is refused (BZ_EUNSUPPORTED). */
+ *            with this method and gamma != 1 is refused (BZ_EUNSUPPORTED).
+ *   d        velocity dimension: 3 (or 0, the default) or 2.  Section 4.2 runs
+ *            its binary-collision examples with two-dimensional velocities.
+ *            With d = 2 the grid is N x N (N in {8, 12, 16, 24, 32, 48}, point
+ *            k = i_1 N + i_2), fields are [batch][N^2], moments and Maxwellian
+ *            parameters have 4 entries (1, v_1, v_2, |v|^2), and the sigma
+ *            form runs over the circle: M = n_phi directions
+ *            theta_p = 2 pi p / n_phi with weights 2 pi / n_phi (n_theta is not
+ *            used), S_2(z) = 2 pi J0(z) in place of 4 pi sin(z)/z, radial
+ *            measure rho^{gamma+1}.  d = 2 supports BZ_FP64, BZ_METHOD_SIGMA,
+ *            v1_shift = 0, and the calls bz_eval_Q (flags BZ_Q_CORRECTED and
+ *            BZ_Q_MASS), bz_maxwellian and the bz_cavity_* scans; the other calls
+ *            return BZ_EUNSUPPORTED on such a context. */
 typedef enum { BZ_METHOD_SIGMA = 0, BZ_METHOD_CARLEMAN = 1 } bz_method;
 
 typedef struct {
@@ -97,6 +109,7 @@ typedef struct {
   int device;
   double v1_shift;
   int method;
+  int d;
 } bz_params;
 
 /* Create / destroy a context: host-built quadrature, phase and weight tables

@@ -42,7 +42,7 @@ class bz_params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_rho", ctypes.c_int),
                 ("R", ctypes.c_double), ("precision", ctypes.c_int), ("device", ctypes.c_int),
-                ("v1_shift", ctypes.c_double), ("method", ctypes.c_int)]
+                ("v1_shift", ctypes.c_double), ("method", ctypes.c_int), ("d", ctypes.c_int)]
 
 
 class bz_solve_opts(ctypes.Structure):
@@ -173,6 +173,7 @@ class Params:
     device: int = 0
     v1_shift: float = 0.0  # physical v_1 of the grid origin (transport uses node + v1_shift)
     method: int = 0  # BZ_METHOD_SIGMA, or BZ_METHOD_CARLEMAN (hard spheres, gamma = 1)
+    d: int = 3  # velocity dimension (3, or 2: N x N grid, n_phi circle directions)
 
 
 class Context:
@@ -183,13 +184,14 @@ class Context:
         self.params = params or Params(**kw)
         p = bz_params(self.params.N, self.params.L, self.params.gamma, self.params.n_theta, self.params.n_phi,
                       self.params.n_rho, self.params.R, self.params.precision, self.params.device,
-                      self.params.v1_shift, self.params.method)
+                      self.params.v1_shift, self.params.method, self.params.d)
         h = ctypes.c_void_p()
         st = self.lib.bz_create(ctypes.byref(p), ctypes.byref(h))
         if st != 0:
             raise BZError(f"bz_create: {self.lib.bz_status_str(st).decode()}")
         self.h = h
-        self.K = self.params.N ** 3
+        self.d = self.params.d
+        self.K = self.params.N ** self.d
 
     def close(self):
         if getattr(self, "h", None):
@@ -232,7 +234,7 @@ class Context:
         import torch
 
         B = self._field(f, "f")
-        theta = torch.empty((B, 5), dtype=torch.float64, device=f.device)
+        theta = torch.empty((B, self.d + 2), dtype=torch.float64, device=f.device)
         M = torch.empty_like(f) if want_M else None
         it = torch.empty(B, dtype=torch.int32, device=f.device)
         st = self.lib.bz_maxwellian(self.h, _ptr(f), _ptr(theta), _ptr(M), _ptr(it), B, _stream())

@@ -73,9 +73,13 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   if (!out) return BZ_EINVAL;
   *out = nullptr;
   if (!p) return BZ_EINVAL;
-  if (!(p->N == 8 || p->N == 16 || p->N == 32)) return BZ_EINVAL;
+  const int d = p->d == 0 ? 3 : p->d;
+  if (d != 2 && d != 3) return BZ_EINVAL;
+  if (d == 3 && !(p->N == 8 || p->N == 16 || p->N == 32)) return BZ_EINVAL;
+  if (d == 2 && !(p->N == 8 || p->N == 12 || p->N == 16 || p->N == 24 || p->N == 32 || p->N == 48))
+    return BZ_EINVAL;
   if (!(p->L > 0) || !std::isfinite(p->L)) return BZ_EINVAL;
-  if (p->n_theta < 2 || p->n_theta % 2 || p->n_theta > 64) return BZ_EINVAL;
+  if (d == 3 && (p->n_theta < 2 || p->n_theta % 2 || p->n_theta > 64)) return BZ_EINVAL;
   if (p->n_phi < 2 || p->n_phi % 2 || p->n_phi > 256) return BZ_EINVAL;
   if (p->n_rho < 1 || p->n_rho > 256) return BZ_EINVAL;
   if (p->precision != BZ_FP64 && p->precision != BZ_FP32) return BZ_EINVAL;
@@ -83,18 +87,23 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   if (!std::isfinite(p->v1_shift) || std::fabs(p->v1_shift) > 1e6) return BZ_EINVAL;
   if (p->method != BZ_METHOD_SIGMA && p->method != BZ_METHOD_CARLEMAN) return BZ_EINVAL;
   if (p->method == BZ_METHOD_CARLEMAN && p->gamma != 1.0) return BZ_EUNSUPPORTED;
+  if (d == 2 && (p->precision != BZ_FP64 || p->method != BZ_METHOD_SIGMA || p->v1_shift != 0.0))
+    return BZ_EUNSUPPORTED;
   bz_ctx* ctx = new bz_ctx();
   ctx->p = *p;
+  ctx->p.d = d;
+  ctx->d = d;
   ctx->N = p->N;
-  ctx->K = p->N * p->N * p->N;
+  ctx->K = d == 3 ? p->N * p->N * p->N : p->N * p->N;
   ctx->n_theta = p->n_theta;
   ctx->n_phi = p->n_phi;
   ctx->n_rho = p->n_rho;
   ctx->dv = 2.0 * p->L / p->N;
-  ctx->w = ctx->dv * ctx->dv * ctx->dv;
+  ctx->w = d == 3 ? ctx->dv * ctx->dv * ctx->dv : ctx->dv * ctx->dv;
   ctx->R = p->R > 0 ? p->R : 2.0 * p->L / (3.0 * std::sqrt(2.0) + 1.0);
   ctx->Rg = 2.0 * ctx->R;
-  ctx->nu_gfac = std::pow(4.0, 0.5 * p->gamma) * std::tgamma(0.5 * (3.0 + p->gamma)) / std::tgamma(1.5);
+  // <|g|^gamma> = (4T)^{gamma/2} Gamma((d + gamma)/2) / Gamma(d/2): the T-independent factor
+  ctx->nu_gfac = std::pow(4.0, 0.5 * p->gamma) * std::tgamma(0.5 * (d + p->gamma)) / std::tgamma(0.5 * d);
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) {
     delete ctx;
@@ -158,6 +167,10 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
   if ((flags & BZ_Q_MASS) && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS requires BZ_Q_CORRECTED");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  if (ctx->d == 2) {
+    if (flags & BZ_Q_CONSERVE) return set_err(ctx, BZ_EUNSUPPORTED, "BZ_Q_CONSERVE with d = 2");
+    return bz::v2_eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, (flags & BZ_Q_MASS) != 0, theta, st);
+  }
   if (!(flags & (BZ_Q_MASS | BZ_Q_CONSERVE)) || batch == 0)
     return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, st);
   double* th = theta;
@@ -178,6 +191,7 @@ bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   if (batch > 0 && (!f || !theta)) return set_err(ctx, BZ_EINVAL, "NULL buffer");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  if (ctx->d == 2) return bz::v2_maxwellian(ctx, f, theta, M, newton_iters, batch, (hipStream_t)stream);
   return bz::maxwellian(ctx, f, theta, M, newton_iters, batch, (hipStream_t)stream);
 }
 
@@ -194,6 +208,7 @@ static bz_status check_opts(bz_ctx* ctx, const bz_solve_opts* o) {
 bz_status bz_cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
                         double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, void* stream) {
   if (!ctx) return BZ_EINVAL;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "this call needs d = 3");
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   bz_status s = check_opts(ctx, opts);
   if (s != BZ_OK) return s;
@@ -207,6 +222,7 @@ bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* in
                               double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats,
                               void* stream) {
   if (!ctx) return BZ_EINVAL;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "this call needs d = 3");
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   bz_status s = check_opts(ctx, opts);
   if (s != BZ_OK) return s;
@@ -239,6 +255,7 @@ bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_
                                       const double* eps, double dx, double* g, int64_t batch,
                                       const bz_solve_opts* opts, bz_cell_stats* stats, void* stream) {
   if (!ctx || !mlp) return BZ_EINVAL;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "this call needs d = 3");
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   bz_status s = check_opts(ctx, opts);
   if (s != BZ_OK) return s;

@@ -16,6 +16,7 @@ struct bz_ctx {
   int n_theta = 0, n_phi = 0, n_rho = 0, n_pairs = 0;
   double dv = 0, w = 0, R = 0, Rg = 0;
   double nu_gfac = 1.0;  // 4^{gamma/2} Gamma((3 + gamma)/2) / Gamma(3/2), for the penalty frequency
+  int d = 3;             // velocity dimension (2 or 3)
   std::string err;
 
   // host copies of the tables (FP64)
@@ -34,6 +35,13 @@ struct bz_ctx {
   int n_dir = 0;
   double* d_cw = nullptr;      // [n_dir][2][K] A_p, B_p on the spectrum grid
   double* d_cbeta = nullptr;   // [K] loss weight sum_p A_p B_p
+  // two-dimensional velocity (d = 2): N x N grid, M = n_phi circle directions
+  int v2_npass = 0;             // radix passes of one length-N transform
+  int v2_rad[4] = {0, 0, 0, 0};  // their radices (4, 3 or 2)
+  double* d_v2tw = nullptr;     // [N] complex exp(2 pi i j / N)
+  double* d_v2xi = nullptr;     // [N] xi_l = pi l / L, l in transform order
+  double* d_v2dir = nullptr;    // [n_phi / 2][2] sigma_p of the antipodal pairs
+  double* d_v2rho = nullptr;    // [n_rho] radial nodes
   float* d_ph1_f = nullptr;
   float* d_ph23_f = nullptr;
   float* d_pairw_f = nullptr;
@@ -82,6 +90,16 @@ size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected);
 // sizes the workspace and sets kernel attributes for eval_q on `batch` cells,
 // so that a later eval_q makes no allocation (needed under stream capture)
 bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected);
+
+// two-dimensional velocity (bz_v2.hip, tables in bz_tables.cpp)
+bz_status build_tables_v2(bz_ctx* ctx);
+bz_status v2_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,
+                        hipStream_t st);
+// Q (FP64) of each cell; corrected: Q_s(f - M, f + M) with M from theta (computed
+// here, written to theta_out [batch][4] when non-null); mass: the projection of
+// mass_project on the corrected form
+bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, bool mass,
+                    double* theta_out, hipStream_t st);
 
 // cell kernels (bz_cell.hip)
 bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,

@@ -491,6 +491,7 @@ bz_status bz_mlp_train_step(bz_mlp* mp, const float* X, const float* T, int64_t 
 bz_status bz_mlp_features(bz_ctx* ctx, const double* inflow_r, const double* theta, const double* eps, double dx,
                           float* X, int64_t batch, void* stream) {
   if (!ctx) return BZ_EINVAL;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "features need d = 3");
   if (batch < 0 || (batch > 0 && (!inflow_r || !theta || !eps || !X)) || !(dx > 0))
     return set_err(ctx, BZ_EINVAL, "bad feature arguments");
   if (batch == 0) return BZ_OK;

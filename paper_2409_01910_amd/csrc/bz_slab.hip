@@ -760,6 +760,7 @@ extern "C" {
 bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (!ctx || !out) return BZ_EINVAL;
   *out = nullptr;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "the 1D slab needs d = 3 (use the bz_cavity_* calls)");
   if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
   if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK && d->collision != BZ_COLL_BINARY_CONSERVE)

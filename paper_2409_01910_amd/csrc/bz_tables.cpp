@@ -143,6 +143,7 @@ static bz_status build_carleman_tables(bz_ctx* ctx, const std::vector<double>& c
 }
 
 bz_status build_tables(bz_ctx* ctx) {
+  if (ctx->d == 2) return build_tables_v2(ctx);
   const int N = ctx->N, K = ctx->K, nt = ctx->n_theta, np = ctx->n_phi, nr = ctx->n_rho;
   const double L = ctx->p.L, gam = ctx->p.gamma;
   std::vector<double> ct, wt, rr, wr;
@@ -228,10 +229,67 @@ bz_status build_tables(bz_ctx* ctx) {
   return BZ_OK;
 }
 
+// Two-dimensional velocity (d = 2, the velocity space of the paper's binary
+// runs, Section 4.2): the same sigma form on the circle, with
+//   W_r(z) = w_r rho_r^{gamma+1} 2 pi J0(rho_r z / 2),
+//   Gm(z)  = 2 pi sum_r w_r rho_r^{gamma+1} 2 pi J0(rho_r z),
+// the circle rule theta_p = 2 pi p / M with equal weights 2 pi / M (antipodal
+// pairs p, p + M/2), and transforms of length N = 2^a 3^b by radix-4/3/2 passes.
+bz_status build_tables_v2(bz_ctx* ctx) {
+  const int N = ctx->N, K = ctx->K, nr = ctx->n_rho, M = ctx->n_phi;
+  const double L = ctx->p.L, gam = ctx->p.gamma;
+  int n = N, np = 0;
+  while (n % 4 == 0 && np < 4) ctx->v2_rad[np++] = 4, n /= 4;
+  while (n % 3 == 0 && np < 4) ctx->v2_rad[np++] = 3, n /= 3;
+  while (n % 2 == 0 && np < 4) ctx->v2_rad[np++] = 2, n /= 2;
+  if (n != 1) return set_err(ctx, BZ_EINVAL, "d = 2 needs N = 2^a 3^b with at most four radix-4/3/2 passes");
+  ctx->v2_npass = np;
+  std::vector<double> rr, wr;
+  gauss_legendre(nr, rr, wr);
+  for (int i = 0; i < nr; ++i) {
+    rr[i] = 0.5 * ctx->Rg * (rr[i] + 1.0);
+    wr[i] = 0.5 * ctx->Rg * wr[i];
+  }
+  std::vector<double> xi(N), tw(2 * N), dir(M), W((size_t)nr * K), Gm(K);
+  for (int l = 0; l < N; ++l) xi[l] = M_PI * (l < N / 2 ? l : l - N) / L;
+  for (int j = 0; j < N; ++j) {
+    tw[2 * j] = std::cos(2.0 * M_PI * j / N);
+    tw[2 * j + 1] = std::sin(2.0 * M_PI * j / N);
+  }
+  for (int p = 0; p < M / 2; ++p) {
+    dir[2 * p] = std::cos(2.0 * M_PI * p / M);
+    dir[2 * p + 1] = std::sin(2.0 * M_PI * p / M);
+  }
+  ctx->h_nodes.resize(N);
+  for (int i = 0; i < N; ++i) ctx->h_nodes[i] = (i - N / 2 + 1) * ctx->dv;
+  for (int l1 = 0; l1 < N; ++l1)
+    for (int l2 = 0; l2 < N; ++l2) {
+      const size_t k = (size_t)l1 * N + l2;
+      const double z = std::sqrt(xi[l1] * xi[l1] + xi[l2] * xi[l2]);
+      double g = 0.0;
+      for (int r = 0; r < nr; ++r) {
+        const double rad = wr[r] * std::pow(rr[r], gam + 1.0);
+        W[(size_t)r * K + k] = rad * 2.0 * M_PI * std::cyl_bessel_j(0.0, rr[r] * z / 2.0) / K;
+        g += rad * 2.0 * M_PI * std::cyl_bessel_j(0.0, rr[r] * z);
+      }
+      Gm[k] = 2.0 * M_PI * g;
+    }
+  bz_status s;
+  if ((s = upload(ctx, &ctx->d_nodes, ctx->h_nodes)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_v2xi, xi)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_v2tw, tw)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_v2dir, dir)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_v2rho, rr)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_W, W)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_Gm, Gm)) != BZ_OK) return s;
+  return BZ_OK;
+}
+
 void free_tables(bz_ctx* ctx) {
   void* ptrs[] = {ctx->d_nodes,  ctx->d_ph1,   ctx->d_ph23,     ctx->d_pairw,      ctx->d_pairsw, ctx->d_W,
                   ctx->d_Gm,     ctx->d_ph1_f, ctx->d_ph23_f,   ctx->d_pairw_f,    ctx->d_pairsw_f,
-                  ctx->d_W_f,    ctx->d_Gm_f,   ctx->d_cw,       ctx->d_cbeta,      ctx->d_cw_f,   ctx->d_cbeta_f};
+                  ctx->d_W_f,    ctx->d_Gm_f,   ctx->d_cw,       ctx->d_cbeta,      ctx->d_cw_f,   ctx->d_cbeta_f,
+                  ctx->d_v2tw,   ctx->d_v2xi,   ctx->d_v2dir,    ctx->d_v2rho};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }

@@ -1,0 +1,468 @@
+// Two-dimensional velocity space (d = 2): the Fourier spectral collision
+// operator in its sigma form on the circle, the discrete Maxwellian, and the
+// steady-state corrected form, for independent cells on an N x N grid.
+//
+// Section 4.2 runs its binary-collision examples with two-dimensional
+// velocities and Maxwell molecules.  With f periodic on [-L, L)^2,
+// f(v_j) = sum_l fh_l exp(i xi_l.(v_j - v_0)), the sigma form (Section 2.2,
+// eq. collision, relative speed truncated at R_g = 2R) is
+//   gain  Qh+_k = sum_r W_r(|xi_k|) DFT_k[ sum_p 2 w_p f(v + s) f(v - s) ],
+//         s = rho_r sigma_p / 2 over the M/2 antipodal pairs of the circle rule,
+//   loss  Q- = f IDFT[ Gm(|xi|) fh ],
+// with W_r and Gm as built by the host tables (S_2(z) = 2 pi J0(z)).  The
+// shift f(v + s) is the phase exp(i xi.s) on fh.
+//
+// The steady-state corrected form of eq. discrete_Q is evaluated as the
+// symmetric bilinear form Q_s(g, h) with g = f - M, h = f + M, which equals
+// Q[f,f] - Q[M,M] without the cancellation of the difference: for each pair,
+// one complex transform of gh phi + i hh conj(phi) gives g(v + s) and h(v - s)
+// at once (both real), and a second one h(v + s) and g(v - s).
+//
+// Layout and work split: one workgroup of 512 threads per cell.  K = N^2 is at
+// most 2304, so the two spectra (gh, hh) and the two ping-pong buffers of a
+// transform fit in LDS together (4 K complex doubles, 147 KB at N = 48), and
+// every pass of every transform stays on chip: the cell's field is read from
+// HBM once and Q written once.  Transforms are Stockham autosort passes of
+// radix 4, 3 and 2 along the fast axis, then along the slow axis; thread t owns
+// the points k = t + 512 i for the pointwise work (accumulators in registers).
+#include <cmath>
+
+#include "bz_common.hpp"
+#include "bz_internal.hpp"
+
+namespace bz {
+namespace {
+
+constexpr int kV2Threads = 512;
+constexpr int kV2Own = 5;  // ceil(48^2 / 512) points per thread at the largest N
+
+struct V2Radix {
+  int n;
+  int r[4];
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// y_k = sum_m v_m exp(SIGN 2 pi i m k / R), in place, R in {2, 3, 4}
+__device__ __forceinline__ void small_dft(double2 (&v)[4], int R, int sign) {
+  if (R == 2) {
+    const double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+  } else if (R == 3) {
+    const double h = 0.86602540378443864676 * sign;  // sign * sqrt(3) / 2
+    const double2 t1 = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+    const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
+    const double2 t3 = make_double2(h * (v[1].x - v[2].x), h * (v[1].y - v[2].y));
+    v[0] = make_double2(v[0].x + t1.x, v[0].y + t1.y);
+    // i * t3 = (-t3.y, t3.x)
+    v[1] = make_double2(t2.x - t3.y, t2.y + t3.x);
+    v[2] = make_double2(t2.x + t3.y, t2.y - t3.x);
+  } else {
+    const double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+    const double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+    const double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+    // sign * i * (v1 - v3)
+    const double2 e = make_double2(-sign * (v[1].y - v[3].y), sign * (v[1].x - v[3].x));
+    v[0] = make_double2(a.x + c.x, a.y + c.y);
+    v[2] = make_double2(a.x - c.x, a.y - c.y);
+    v[1] = make_double2(b.x + e.x, b.y + e.y);
+    v[3] = make_double2(b.x - e.x, b.y - e.y);
+  }
+}
+
+// One Stockham pass of radix R over all N lines of an N x N tile along one
+// axis (axis 1: contiguous lines; axis 0: columns).  Ns is the product of the
+// radices of the earlier passes on this axis; tw[q] = exp(2 pi i q / N).
+__device__ __forceinline__ void stockham_pass(const double2* __restrict__ src, double2* __restrict__ dst, int N,
+                                              int R, int Ns, int axis, int sign, const double2* tw) {
+  const int NR = N / R, items = N * NR, step = N / (Ns * R);
+  const int es = axis == 1 ? 1 : N;
+  for (int t = threadIdx.x; t < items; t += blockDim.x) {
+    const int line = t / NR, j = t - line * NR;
+    const int k = j % Ns;
+    const int base = axis == 1 ? line * N : line;
+    double2 v[4];
+    for (int m = 0; m < R; ++m) v[m] = src[base + (j + m * NR) * es];
+    for (int m = 1; m < R; ++m) {
+      double2 w = tw[k * m * step];
+      if (sign < 0) w = cconj(w);
+      v[m] = cmul(v[m], w);
+    }
+    small_dft(v, R, sign);
+    const int d0 = (j / Ns) * Ns * R + k;
+    for (int m = 0; m < R; ++m) dst[base + (d0 + m * Ns) * es] = v[m];
+  }
+}
+
+// 2D transform X_k = sum_j x_j exp(sign 2 pi i k.j / N) of buffer a (b is the
+// ping-pong partner); returns the buffer that holds the result.  Synchronises
+// before returning.
+__device__ __forceinline__ double2* dft2(double2* a, double2* b, int N, const V2Radix& rx, int sign,
+                                         const double2* tw) {
+  double2 *src = a, *dst = b;
+  for (int axis = 1; axis >= 0; --axis) {
+    int Ns = 1;
+    for (int q = 0; q < rx.n; ++q) {
+      stockham_pass(src, dst, N, rx.r[q], Ns, axis, sign, tw);
+      __syncthreads();
+      Ns *= rx.r[q];
+      double2* t = src;
+      src = dst;
+      dst = t;
+    }
+  }
+  return src;
+}
+
+__device__ __forceinline__ double gauss2(const double* th, double x, double y) {
+  return exp(th[0] + th[1] * x + th[2] * y - th[3] * (x * x + y * y));
+}
+
+// Collision term of one cell per workgroup.  theta (corrected only) holds the
+// cell's discrete Maxwellian.  mass: Q <- Q - M sum(Q) / sum(M).
+__global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f, const double* __restrict__ theta,
+                                                   double* __restrict__ Q, int N, V2Radix rx,
+                                                   const double* __restrict__ nodes, const double* __restrict__ xi,
+                                                   const double* __restrict__ tw_g, const double* __restrict__ dir,
+                                                   const double* __restrict__ rho, int n_rho, int n_pairs,
+                                                   double w_pair, const double* __restrict__ W,
+                                                   const double* __restrict__ Gm, int corrected, int mass) {
+  extern __shared__ double2 smem[];
+  const int K = N * N, cell = blockIdx.x, tid = threadIdx.x;
+  double2* SG = smem;
+  double2* SH = SG + K;
+  double2* B0 = SH + K;
+  double2* B1 = B0 + K;
+  double2* TW = B1 + K;
+  double2* E0 = TW + N;
+  double2* E1 = E0 + N;
+  double* red = reinterpret_cast<double*>(E1 + N);
+  for (int j = tid; j < N; j += blockDim.x) TW[j] = make_double2(tw_g[2 * j], tw_g[2 * j + 1]);
+
+  const double* fc = f + (size_t)cell * K;
+  double th[4] = {0.0, 0.0, 0.0, 0.0};
+  if (corrected)
+    for (int q = 0; q < 4; ++q) th[q] = theta[(size_t)cell * 4 + q];
+  double g[kV2Own], h[kV2Own], Mk[kV2Own];
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) {
+    const int k = tid + i * kV2Threads;
+    g[i] = h[i] = Mk[i] = 0.0;
+    if (k < K) {
+      const double fv = fc[k];
+      if (corrected) {
+        Mk[i] = gauss2(th, nodes[k / N], nodes[k % N]);
+        g[i] = fv - Mk[i];
+        h[i] = fv + Mk[i];
+      } else {
+        g[i] = h[i] = fv;
+      }
+      B0[k] = make_double2(g[i], h[i]);
+    }
+  }
+  __syncthreads();
+  // spectra: Z = DFT(g + i h); gh_l = (Z_l + conj Z_-l) / 2K, hh_l = (Z_l - conj Z_-l) / 2iK,
+  // Nyquist modes zeroed
+  {
+    const double2* Z = dft2(B0, B1, N, rx, -1, TW);
+    const double s = 0.5 / K;
+    for (int k = tid; k < K; k += blockDim.x) {
+      const int l1 = k / N, l2 = k - l1 * N;
+      const int m = ((N - l1) % N) * N + (N - l2) % N;
+      const double2 a = Z[k], b = Z[m];
+      const bool nyq = l1 == N / 2 || l2 == N / 2;
+      SG[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.x + b.x), s * (a.y - b.y));
+      SH[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.y + b.y), -s * (a.x - b.x));
+    }
+    __syncthreads();
+  }
+
+  double qr[kV2Own], qi[kV2Own];
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) qr[i] = qi[i] = 0.0;
+  for (int r = 0; r < n_rho; ++r) {
+    double acc[kV2Own];
+#pragma unroll
+    for (int i = 0; i < kV2Own; ++i) acc[i] = 0.0;
+    for (int p = 0; p < n_pairs; ++p) {
+      // axis phases exp(i xi_l s_a), s = rho_r sigma_p / 2
+      if (tid < 2 * N) {
+        const int a = tid / N, l = tid - a * N;
+        const double sa = 0.5 * rho[r] * dir[2 * p + a];
+        double sn, cs;
+        sincos(xi[l] * sa, &sn, &cs);
+        (a == 0 ? E0 : E1)[l] = make_double2(cs, sn);
+      }
+      __syncthreads();
+      double ag[kV2Own], bh[kV2Own];
+      for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
+        const double2* X = pass == 0 ? SG : SH;
+        const double2* Y = pass == 0 ? SH : SG;
+        for (int k = tid; k < K; k += blockDim.x) {
+          const double2 ph = cmul(E0[k / N], E1[k % N]);
+          const double2 u = cmul(X[k], ph), w = cmul(Y[k], cconj(ph));
+          B0[k] = make_double2(u.x - w.y, u.y + w.x);  // u + i w
+        }
+        __syncthreads();
+        const double2* T = dft2(B0, B1, N, rx, +1, TW);
+#pragma unroll
+        for (int i = 0; i < kV2Own; ++i) {
+          const int k = tid + i * kV2Threads;
+          if (k < K) {
+            const double2 t = T[k];
+            if (pass == 0) {
+              ag[i] = t.x;
+              bh[i] = t.y;
+              if (!corrected) acc[i] += w_pair * t.x * t.y;
+            } else {
+              acc[i] += 0.5 * w_pair * (ag[i] * bh[i] + t.x * t.y);
+            }
+          }
+        }
+      }
+    }
+    // Qh += W_r DFT(acc_r)
+#pragma unroll
+    for (int i = 0; i < kV2Own; ++i) {
+      const int k = tid + i * kV2Threads;
+      if (k < K) B0[k] = make_double2(acc[i], 0.0);
+    }
+    __syncthreads();
+    const double2* A = dft2(B0, B1, N, rx, -1, TW);
+    const double* Wr = W + (size_t)r * K;
+#pragma unroll
+    for (int i = 0; i < kV2Own; ++i) {
+      const int k = tid + i * kV2Threads;
+      if (k < K) {
+        qr[i] += Wr[k] * A[k].x;
+        qi[i] += Wr[k] * A[k].y;
+      }
+    }
+    __syncthreads();
+  }
+  // gain = IDFT(Qh)
+  double gain[kV2Own];
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) {
+    const int k = tid + i * kV2Threads;
+    if (k < K) B0[k] = make_double2(qr[i], qi[i]);
+  }
+  __syncthreads();
+  {
+    const double2* G = dft2(B0, B1, N, rx, +1, TW);
+#pragma unroll
+    for (int i = 0; i < kV2Own; ++i) {
+      const int k = tid + i * kV2Threads;
+      gain[i] = k < K ? G[k].x : 0.0;
+    }
+    __syncthreads();
+  }
+  // loss: IDFT(Gm hh + i Gm gh) = L_h + i L_g;  Q- = (g L_h + h L_g) / 2
+  for (int k = tid; k < K; k += blockDim.x) {
+    const double gm = Gm[k];
+    const double2 a = SH[k], b = SG[k];
+    B0[k] = make_double2(gm * (a.x - b.y), gm * (a.y + b.x));
+  }
+  __syncthreads();
+  const double2* Lx = dft2(B0, B1, N, rx, +1, TW);
+  double q[kV2Own], sq = 0.0, sm = 0.0;
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) {
+    const int k = tid + i * kV2Threads;
+    q[i] = 0.0;
+    if (k < K) {
+      q[i] = gain[i] - 0.5 * (g[i] * Lx[k].x + h[i] * Lx[k].y);
+      sq += q[i];
+      sm += Mk[i];
+    }
+  }
+  double c = 0.0;
+  if (mass) {
+    double v[2] = {sq, sm};
+    block_sum<2>(v, red);
+    c = v[0] / v[1];
+  }
+  double* Qc = Q + (size_t)cell * K;
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) {
+    const int k = tid + i * kV2Threads;
+    if (k < K) Qc[k] = q[i] - c * Mk[i];
+  }
+}
+
+// 4 x 4 symmetric positive definite solve (LDL^T without pivoting)
+__device__ __forceinline__ void solve_spd4(double G[4][4], const double b[4], double y[4]) {
+  double d[4], z[4];
+  for (int j = 0; j < 4; ++j) {
+    double dj = G[j][j];
+    for (int k = 0; k < j; ++k) dj -= G[j][k] * G[j][k] * d[k];
+    d[j] = dj;
+    for (int i = j + 1; i < 4; ++i) {
+      double t = G[i][j];
+      for (int k = 0; k < j; ++k) t -= G[i][k] * G[j][k] * d[k];
+      G[i][j] = t / dj;
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    double t = b[i];
+    for (int k = 0; k < i; ++k) t -= G[i][k] * z[k];
+    z[i] = t;
+  }
+  for (int i = 3; i >= 0; --i) {
+    double t = z[i] / d[i];
+    for (int k = i + 1; k < 4; ++k) t -= G[k][i] * y[k];
+    y[i] = t;
+  }
+}
+
+constexpr int kMaxThreads = 256;
+
+// sums over the cell of w phi_i exp(theta.phi~) (4 moments) and of
+// w phi_i phi_j exp(theta.phi~) (10 Gram entries), phi = (1, v_1, v_2, |v|^2);
+// identical in every thread
+__device__ __forceinline__ void gauss_sums2(const double* th, const double* nodes, int N, double w, double* red,
+                                            double (&s)[14]) {
+  for (int q = 0; q < 14; ++q) s[q] = 0.0;
+  for (int k = threadIdx.x; k < N * N; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N], e = w * gauss2(th, x, y);
+    const double ph[4] = {1.0, x, y, x * x + y * y};
+    for (int i = 0; i < 4; ++i) s[i] += ph[i] * e;
+    int o = 4;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i; j < 4; ++j) s[o++] += ph[i] * ph[j] * e;
+  }
+  block_sum<14>(s, red);
+}
+
+// Discrete Maxwellian (eqs. discrete_conservation, discrete_Gaussian) of one
+// cell per workgroup: Newton on theta = (alpha, beta_1, beta_2, gamma) from the
+// continuous-moment guess, with the Gram system as Jacobian and step halving
+// while the max-norm residual does not decrease; converged when it is below
+// 1e-13 (|m_0| + |m_3|).
+__global__ void __launch_bounds__(kMaxThreads) k_max2(const double* __restrict__ f, double* __restrict__ theta,
+                                                      double* __restrict__ Mout, int32_t* __restrict__ iters,
+                                                      const double* __restrict__ nodes, int N, double w) {
+  __shared__ double red[14 * (kMaxThreads / 64)];
+  const int K = N * N, cell = blockIdx.x;
+  const double* fc = f + (size_t)cell * K;
+  double t[14];
+  for (int q = 0; q < 14; ++q) t[q] = 0.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N], e = w * fc[k];
+    t[0] += e;
+    t[1] += x * e;
+    t[2] += y * e;
+    t[3] += (x * x + y * y) * e;
+  }
+  block_sum<14>(t, red);
+  const double rho = t[0], U0 = t[1] / rho, U1 = t[2] / rho;
+  double T = (t[3] / rho - U0 * U0 - U1 * U1) / 2.0;
+  if (!(T > 1e-3)) T = 1e-3;
+  double th[4] = {log(rho / (2.0 * kPi * T)) - (U0 * U0 + U1 * U1) / (2.0 * T), U0 / T, U1 / T, 1.0 / (2.0 * T)};
+  const double scale = fabs(t[0]) + fabs(t[3]) + 1e-300, tol = 1e-13;
+  double s[14], r[4];
+  gauss_sums2(th, nodes, N, w, red, s);
+  double nrm = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    r[i] = s[i] - t[i];
+    nrm = fmax(nrm, fabs(r[i]));
+  }
+  if (!isfinite(nrm)) nrm = INFINITY;
+  int it = 0, status = -1;
+  for (; it < 60; ++it) {
+    if (nrm <= tol * scale) {
+      status = it;
+      break;
+    }
+    double G[4][4], rhs[4], step[4];
+    int o = 4;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i; j < 4; ++j) G[i][j] = G[j][i] = s[o++];
+    for (int i = 0; i < 4; ++i) rhs[i] = -r[i];
+    solve_spd4(G, rhs, step);
+    step[3] = -step[3];  // theta.phi~ carries -gamma |v|^2
+    double a = 1.0, thn[4], sn[14], n_new = INFINITY;
+    while (true) {
+      for (int i = 0; i < 4; ++i) thn[i] = th[i] + a * step[i];
+      gauss_sums2(thn, nodes, N, w, red, sn);
+      n_new = 0.0;
+      for (int i = 0; i < 4; ++i) n_new = fmax(n_new, fabs(sn[i] - t[i]));
+      if (!isfinite(n_new)) n_new = INFINITY;
+      if (isfinite(n_new) && (n_new < nrm || a < 1e-4) && thn[3] > 0.0) break;
+      a *= 0.5;
+      if (a < 1e-6) break;
+    }
+    double dmax = 0.0, tmax = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      dmax = fmax(dmax, fabs(thn[i] - th[i]));
+      tmax = fmax(tmax, fabs(th[i]));
+    }
+    for (int i = 0; i < 4; ++i) {
+      th[i] = thn[i];
+      r[i] = sn[i] - t[i];
+    }
+    for (int q = 0; q < 14; ++q) s[q] = sn[q];
+    nrm = n_new;
+    if (dmax <= 1e-15 * (1.0 + tmax)) {
+      status = nrm <= 1e-10 * scale ? it + 1 : -(it + 2);
+      break;
+    }
+  }
+  if (status == -1) status = nrm <= tol * scale ? it : -(it + 1);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) theta[(size_t)cell * 4 + i] = th[i];
+    if (iters) iters[cell] = status;
+  }
+  if (Mout)
+    for (int k = threadIdx.x; k < K; k += blockDim.x) Mout[(size_t)cell * K + k] = gauss2(th, nodes[k / N], nodes[k % N]);
+}
+
+size_t q2_lds_bytes(int N) { return (size_t)(4 * N * N + 3 * N) * sizeof(double2) + 2 * (kV2Threads / 64) * 8; }
+
+}  // namespace
+
+bz_status v2_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,
+                        hipStream_t st) {
+  if (batch == 0) return BZ_OK;
+  if (batch > INT32_MAX) return set_err(ctx, BZ_EINVAL, "batch too large");
+  hipLaunchKernelGGL(k_max2, dim3((unsigned)batch), dim3(kMaxThreads), 0, st, f, theta, M, iters, ctx->d_nodes,
+                     ctx->N, ctx->w);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, bool mass,
+                    double* theta_out, hipStream_t st) {
+  if (batch == 0) return BZ_OK;
+  if (batch > INT32_MAX) return set_err(ctx, BZ_EINVAL, "batch too large");
+  const int N = ctx->N;
+  if (N * N > kV2Own * kV2Threads) return set_err(ctx, BZ_EINVAL, "d = 2 needs N <= 48");
+  double* th = nullptr;
+  if (corrected) {
+    th = theta_out;
+    if (!th) {
+      bz_status s = ensure_ws(ctx, (size_t)batch * 4 * sizeof(double));
+      if (s != BZ_OK) return s;
+      th = (double*)ctx->ws;
+    }
+    bz_status s = v2_maxwellian(ctx, f, th, nullptr, nullptr, batch, st);
+    if (s != BZ_OK) return s;
+  }
+  V2Radix rx{};
+  rx.n = ctx->v2_npass;
+  for (int q = 0; q < 4; ++q) rx.r[q] = ctx->v2_rad[q];
+  const size_t lds = q2_lds_bytes(N);
+  BZ_HIP(hipFuncSetAttribute((const void*)k_q2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const double w_pair = 2.0 * (2.0 * kPi / ctx->n_phi);
+  hipLaunchKernelGGL(k_q2, dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, N, rx, ctx->d_nodes,
+                     ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,
+                     ctx->d_W, ctx->d_Gm, corrected ? 1 : 0, mass ? 1 : 0);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+}  // namespace bz
