@@ -24,8 +24,13 @@ from .grid import Spec, phi_vectors, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, gaussian, moments, solve_weighted_gaussian, theta_from_macro
 
 
-def transport_coef(spec: Spec, dx: float) -> np.ndarray:
-    """c_k = |v_{k,1}| / dx with the physical v_1 (velocity axis 0, the slowest array axis)."""
+def transport_coef(spec: Spec, dx) -> np.ndarray:
+    """c_k = |v_{k,1}| / dx with the physical v_1 (velocity axis 0, the slowest array
+    axis).  In two space dimensions dx is the pair (dx, dy) and the upwind
+    diagonal is c_k = |v_{k,1}| / dx + |v_{k,2}| / dy."""
+    if isinstance(dx, tuple):
+        v = velocity_nodes(spec)
+        return np.abs(v[:, 0]) / dx[0] + np.abs(v[:, 1]) / dx[1]
     return np.abs(transport_v1(spec)) / dx
 
 

@@ -1,0 +1,62 @@
+"""Pins of the oracle's two-dimensional SGS scans (the lid-driven cavity; CPU
+only): an exact equilibrium, the x <-> y transposition symmetry of the steady
+state, which wall is which (hot wall, lid direction), and the mass rescale."""
+import numpy as np
+import pytest
+
+from oracle import cavity as CV
+from oracle.grid import Spec, velocity_nodes
+from oracle.maxwellian import macroscopic
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_uniform_maxwellian_between_equal_walls_is_a_steady_state(collision):
+    # all walls at T = 1 at rest: the uniform unit-temperature Maxwellian is an
+    # exact discrete steady state (Q vanishes by eq. discrete_Q, the wall
+    # densities balance the outgoing fluxes); L = 8 keeps the one unpaired grid
+    # node's Maxwellian value (v = L) below rounding
+    sp = Spec(d=2, N=16, L=8.0, n_phi=8, n_rho=4)
+    prob = CV.Cavity(spec=sp, nx=3, ny=3, eps=0.1, walls=((1.0, (0.0, 0.0)),) * 4, collision=collision)
+    f0 = CV.initial_state(prob)
+    assert CV.outer_residual(prob, f0) < 1e-11
+    f1 = CV.sgs_iteration(prob, f0)
+    assert np.abs(f1 - f0).max() < 1e-11 * f0.max()
+
+
+def _converge(prob, tol=1e-11, max_iter=100):
+    f = CV.initial_state(prob)
+    for it in range(max_iter):
+        f = CV.sgs_iteration(prob, f)
+        if it % 5 == 4 and CV.outer_residual(prob, f) < tol:
+            return f
+    raise AssertionError("no convergence")
+
+
+def test_steady_state_is_symmetric_under_transposition():
+    # walls x = 0 and y = 0 at T = 1, x = 1 and y = 1 at T = 2: the problem is
+    # invariant under (x, y, v_1, v_2) -> (y, x, v_2, v_1), the scans are not, so
+    # only the converged state must be symmetric
+    N = 8
+    sp = Spec(d=2, N=N, L=4.0, n_phi=8, n_rho=4)
+    walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)))
+    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk")
+    f = _converge(prob).reshape(4, 4, N, N)
+    assert np.abs(f.transpose(1, 0, 3, 2) - f).max() < 1e-11 * f.max()
+    assert abs(CV.total_mass(prob, f.reshape(4, 4, -1)) - 1.0) < 1e-13
+
+
+def test_hot_wall_and_lid_direction():
+    # left wall T = 1, right wall T = 2, bottom and top at T = 1.5, lid (y = 1)
+    # moving in +x: the gas is hotter next to the right wall than next to the
+    # left one, and the lid drives a clockwise vortex (U_1 > 0 under the lid,
+    # < 0 along the bottom)
+    N = 12
+    sp = Spec(d=2, N=N, L=6.0, n_phi=8, n_rho=4)
+    walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.5, (0.0, 0.0)), (1.5, (0.5, 0.0)))
+    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk")
+    f = _converge(prob, tol=1e-8)
+    mac = [[macroscopic(sp, f[i, j]) for j in range(4)] for i in range(4)]
+    T = np.array([[m[2] for m in row] for row in mac])
+    U1 = np.array([[m[1][0] for m in row] for row in mac])
+    assert (T[-1, :] > T[0, :]).all()
+    assert (U1[:, -1] > 0).all() and (U1[:, 0] < 0).all()
