@@ -331,6 +331,61 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* slab, int n_iters, double* residual
  * (Section 4 stopping rule), into residual_out (host) [n_instances]. */
 bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* slab, double* residual_out, void* stream);
 
+/* ---------------------------------------------------------- 2D cavities
+ * The lid-driven cavity family of Section 4.2: the unit square [0, 1]^2 with
+ * nx x ny uniform cells, a diffuse wall (eq. boundary) on each side, two-
+ * dimensional velocities (a context with d = 2), Knudsen number eps and the
+ * total-mass constraint of eq. mass_conserv.  First-order upwind finite
+ * volumes: for cell (i, j),
+ *   [v1+ (f_ij - f_{i-1,j}) + v1- (f_{i+1,j} - f_ij)] / dx
+ *     + [v2+ (f_ij - f_{i,j-1}) + v2- (f_{i,j+1} - f_ij)] / dy = Q[f_ij] / eps.
+ * Cell (i, j) is stored at f + (i ny + j) K (borrowed for the cavity lifetime).
+ * walls[0..3] are the sides x = 0, x = 1, y = 0, y = 1: temperature T and
+ * velocity U (tangential: U[0] = 0 on x = 0 and x = 1, U[1] = 0 on y = 0 and
+ * y = 1).  collision: BZ_COLL_BINARY (Q of eq. discrete_Q with the BZ_Q_MASS
+ * projection, nu = 2 pi rho <|g|^gamma>) or BZ_COLL_BGK (P == 0, nu = bgk_nu if
+ * > 0 else 2 pi rho). */
+typedef struct {
+  double T;
+  double U[2];
+} bz_wall;
+
+typedef struct {
+  int nx, ny;          /* cells along x and y (1 .. 4096 each) */
+  double eps;          /* Knudsen number (> 0) */
+  bz_wall walls[4];    /* x = 0, x = 1, y = 0, y = 1 */
+  double mass;         /* C in eq. mass_conserv (> 0) */
+  int collision;       /* BZ_COLL_BINARY or BZ_COLL_BGK */
+  double bgk_nu;       /* BGK only; <= 0: 2 pi rho */
+  bz_solve_opts inner; /* inner solve options */
+  double* f;           /* device [nx ny][K], borrowed */
+} bz_cavity_desc;
+
+typedef struct bz_cavity bz_cavity;
+
+bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* desc, bz_cavity** out);
+void bz_cavity_destroy(bz_cavity* cav);
+
+/* bz_cavity_sweep: n_iters SGS iterations, each four scans visiting the cells
+ * in lexicographic order along (+x, +y), (-x, -y), (-x, +y), (+x, -y), then the
+ * uniform mass rescale of Section 4.  Before each scan, P and nu of every cell
+ * come from one batched collision evaluation (P is explicit, as in eq. SGS).
+ * A visit uses the latest values of its four neighbours, so the cells of one
+ * anti-diagonal (i + j constant in scan order) are independent: each
+ * anti-diagonal is one launch with one workgroup per cell, which gives exactly
+ * the lexicographic result.  At a wall the ghost value is rho_w M_w on the
+ * incoming half-space, rho_w from the discrete zero-mass-flux balance with the
+ * adjacent cell's latest value.  Each visit solves eq. inner_eqn with the
+ * upwind diagonal c = |v1|/dx + |v2|/dy by the desc's inner options.
+ * residual_out (host, nullable) receives the outer residual after the last
+ * iteration. */
+bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cav, int n_iters, double* residual_out, bz_sweep_stats* stats,
+                          void* stream);
+
+/* bz_cavity_residual: sqrt(dx dy sum_ij sum_k w (v.grad f - Q/eps)^2), the
+ * Section 4 stopping norm, into residual_out (host). */
+bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cav, double* residual_out, void* stream);
+
 /* bz_multigrid_vcycle: n_cycles nonlinear multigrid V-cycles (eq. coarse,
  * H = 2h) with SGS-PFP smoothing (nu1 pre-, nu2 post-steps, tab. mg), a
  * coarsest level of `coarsest` cells smoothed until its residual falls 10x or

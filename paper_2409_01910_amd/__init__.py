@@ -35,6 +35,7 @@ EXPORTED = [
     "bz_mlp_set_output_scale", "bz_mlp_forward", "bz_mlp_grad", "bz_mlp_train_step", "bz_mlp_features",
     "bz_cell_fixed_point_learned",
     "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
+    "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual",
 ]
 
 
@@ -67,6 +68,16 @@ class bz_slab_desc(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int), ("instances", ctypes.POINTER(bz_slab_instance)),
                 ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double), ("inner", bz_solve_opts),
                 ("f", ctypes.c_void_p), ("order", ctypes.c_int)]
+
+
+class bz_wall(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("U", ctypes.c_double * 2)]
+
+
+class bz_cavity_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("eps", ctypes.c_double), ("walls", bz_wall * 4),
+                ("mass", ctypes.c_double), ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double),
+                ("inner", bz_solve_opts), ("f", ctypes.c_void_p)]
 
 
 class bz_sweep_stats(ctypes.Structure):
@@ -114,6 +125,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_slab_destroy.argtypes = [P]
     lib.bz_slab_destroy.restype = None
     lib.bz_sgs_sweep.argtypes = [P, P, ctypes.c_int, P, ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_cavity_create.argtypes = [P, ctypes.POINTER(bz_cavity_desc), ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_cavity_destroy.argtypes = [P]
+    lib.bz_cavity_destroy.restype = None
+    lib.bz_cavity_sweep.argtypes = [P, P, ctypes.c_int, P, ctypes.POINTER(bz_sweep_stats), P]
+    lib.bz_cavity_residual.argtypes = [P, P, P, P]
     lib.bz_outer_residual.argtypes = [P, P, P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
@@ -139,7 +155,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_graph_destroy.restype = None
     for name in EXPORTED:
         if name not in ("bz_destroy", "bz_slab_destroy", "bz_status_str", "bz_workspace_bytes", "bz_mlp_destroy",
-                        "bz_graph_destroy",
+                        "bz_graph_destroy", "bz_cavity_destroy",
                         "bz_mlp_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -389,6 +405,58 @@ class Slab:
     def capture(self, iters: int, with_residual: bool = True) -> "SweepGraph":
         """Capture iters SGS iterations into a replayable HIP graph."""
         return SweepGraph(self, iters, with_residual)
+
+
+class Cavity:
+    """A 2D cavity on [0, 1]^2 (bz_cavity) on a context with d = 2.
+
+    ``walls`` lists (T, (U_1, U_2)) for the sides x = 0, x = 1, y = 0, y = 1.
+    ``f`` is a float64 device tensor [nx * ny, K] (cell (i, j) at row i * ny + j)
+    that the cavity reads and updates in place (borrowed for its lifetime)."""
+
+    def __init__(self, ctx: Context, nx: int, ny: int, eps: float, walls, f, mass: float = 1.0,
+                 collision: str = "binary", bgk_nu: float = 0.0, mode="pfp", tol=1e-8, max_iter=100,
+                 fixed_iters=0):
+        self.ctx = ctx
+        self.f = f
+        ctx._field(f, "f")
+        if f.numel() != nx * ny * ctx.K:
+            raise BZError("f must hold nx * ny cells")
+        wl = (bz_wall * 4)()
+        for s_, (T, U) in enumerate(walls):
+            wl[s_].T = T
+            wl[s_].U[0], wl[s_].U[1] = U
+        desc = bz_cavity_desc(nx, ny, eps, wl, mass, _COLLISIONS[collision], bgk_nu,
+                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()))
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.bz_cavity_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_cavity_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.bz_cavity_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n_iters: int = 1, residual: bool = True):
+        """n_iters SGS iterations (four scans each); returns (outer residual or None, stats)."""
+        res = ctypes.c_double(0.0)
+        st = bz_sweep_stats()
+        self.ctx._check(self.ctx.lib.bz_cavity_sweep(self.ctx.h, self.h, n_iters,
+                                                     ctypes.byref(res) if residual else None, ctypes.byref(st),
+                                                     _stream()), "bz_cavity_sweep")
+        return (res.value if residual else None), Slab._stats(st)
+
+    def residual(self) -> float:
+        res = ctypes.c_double(0.0)
+        self.ctx._check(self.ctx.lib.bz_cavity_residual(self.ctx.h, self.h, ctypes.byref(res), _stream()),
+                        "bz_cavity_residual")
+        return res.value
 
 
 class SweepGraph:

@@ -1,0 +1,594 @@
+// SGS scans on the unit square with two-dimensional velocities: the
+// lid-driven cavity family of Section 4.2.
+//
+// One SGS iteration is four scans, lexicographic along (+x, +y), (-x, -y),
+// (-x, +y) and (+x, -y), then the uniform mass rescale of eq. mass_conserv.
+// Before each scan one batched pass computes every cell's collision split
+// P = Q - nu (M - f) (eq. Pf, explicit in eq. SGS) and stores -P/eps.  Within a
+// scan a visit reads the latest values of its four neighbours.  Cells with
+// equal i + j (in scan order) do not neighbour each other, so the scan runs as
+// nx + ny - 1 launches, one per anti-diagonal, with one workgroup per cell;
+// the result is that of the lexicographic order exactly.
+//
+// A visit assembles the transport right-hand side
+//   r = (-v1+ f_W + v1- f_E) / dx + (-v2+ f_S + v2- f_N) / dy - P / eps,
+// with diffuse-wall ghosts rho_w M_w (eq. boundary; rho_w from the discrete
+// zero-mass-flux balance with the cell's latest value), and solves
+// eq. inner_eqn, c g + r = (nu/eps)(M[g] - g), c = |v1|/dx + |v2|/dy, by the
+// preconditioned iteration of eqs. step1 and step2 (or the plain eq. fix_point):
+// step 1's weighted Newton and the discrete Maxwellian are 4-parameter Newton
+// solves whose sums run over the cell's N^2 points in the workgroup.
+#include <cmath>
+
+#include "bz_common.hpp"
+#include "bz_internal.hpp"
+
+struct bz_cavity {
+  bz_ctx* ctx = nullptr;
+  int nx = 0, ny = 0, ncell = 0;
+  double eps = 0, dx = 0, dy = 0, mass = 0;
+  bz_wall walls[4]{};
+  int collision = 0;
+  double bgk_nu = 0;
+  bz_solve_opts opts{};
+  double* f = nullptr;
+  double* d_Q = nullptr;      // [ncell][K]
+  double* d_rs = nullptr;     // [ncell][K] -P / eps
+  double* d_theta = nullptr;  // [ncell][4]
+  double* d_nu = nullptr;     // [ncell]
+  double* d_part = nullptr;   // [ncell] per-cell partial sums
+  unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
+};
+
+namespace bz {
+namespace {
+
+constexpr int kCavThreads = 256;
+constexpr int kCavOwn = 9;  // ceil(48^2 / 256)
+
+struct CavWalls {
+  double T[4], U1[4], U2[4];
+};
+
+__device__ __forceinline__ double gauss2c(const double* th, double x, double y) {
+  return exp(th[0] + th[1] * x + th[2] * y - th[3] * (x * x + y * y));
+}
+
+__device__ __forceinline__ double wall_m(const CavWalls& wl, int s, double x, double y) {
+  const double a = x - wl.U1[s], b = y - wl.U2[s];
+  return exp(-(a * a + b * b) / (2.0 * wl.T[s])) / (2.0 * kPi * wl.T[s]);
+}
+
+// s[0..3] = sum w c phi_i exp(theta.phi~), s[4..13] = sum w c phi_i phi_j exp(theta.phi~)
+// (upper triangle by rows), phi = (1, x, y, x^2 + y^2), over the cell's points
+__device__ __forceinline__ void wsums(const double* th, const double (&x)[kCavOwn], const double (&y)[kCavOwn],
+                                     const double (&c)[kCavOwn], int K, double w, double* red, double (&s)[14]) {
+  for (int q = 0; q < 14; ++q) s[q] = 0.0;
+#pragma unroll
+  for (int i = 0; i < kCavOwn; ++i) {
+    const int k = threadIdx.x + i * kCavThreads;
+    if (k < K) {
+      const double e = w * c[i] * gauss2c(th, x[i], y[i]);
+      const double ph[4] = {1.0, x[i], y[i], x[i] * x[i] + y[i] * y[i]};
+      for (int a = 0; a < 4; ++a) s[a] += ph[a] * e;
+      int o = 4;
+      for (int a = 0; a < 4; ++a)
+        for (int b = a; b < 4; ++b) s[o++] += ph[a] * ph[b] * e;
+    }
+  }
+  block_sum<14>(s, red);
+}
+
+__device__ __forceinline__ bool spd4_solve(double G[4][4], const double b[4], double y[4]) {
+  double d[4], z[4];
+  for (int j = 0; j < 4; ++j) {
+    double dj = G[j][j];
+    for (int k = 0; k < j; ++k) dj -= G[j][k] * G[j][k] * d[k];
+    d[j] = dj;
+    for (int i = j + 1; i < 4; ++i) {
+      double t = G[i][j];
+      for (int k = 0; k < j; ++k) t -= G[i][k] * G[j][k] * d[k];
+      G[i][j] = t / dj;
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    double t = b[i];
+    for (int k = 0; k < i; ++k) t -= G[i][k] * z[k];
+    z[i] = t;
+  }
+  for (int i = 3; i >= 0; --i) {
+    double t = z[i] / d[i];
+    for (int k = i + 1; k < 4; ++k) t -= G[k][i] * y[k];
+    y[i] = t;
+  }
+  bool ok = true;
+  for (int i = 0; i < 4; ++i) ok = ok && isfinite(y[i]);
+  return ok;
+}
+
+// Newton for sum w c phi exp(theta.phi~) = t (c = 1: the discrete Maxwellian,
+// eq. discrete_conservation; c = |v1|/dx + |v2|/dy: step 1, eq. step1).  With
+// guess, theta starts from the continuous moments of t; otherwise from th.
+// Step halving while the max-norm residual does not decrease.  Returns true
+// when converged (residual <= 1e-13 (|t_0| + |t_3|), or a stalled step with
+// residual <= 1e-10 of that scale).
+__device__ bool newton4(double (&th)[4], const double (&t)[4], bool guess, const double (&x)[kCavOwn],
+                        const double (&y)[kCavOwn], const double (&c)[kCavOwn], int K, double w, double* red) {
+  if (guess) {
+    const double rho = t[0], U0 = t[1] / rho, U1 = t[2] / rho;
+    double T = (t[3] / rho - U0 * U0 - U1 * U1) / 2.0;
+    if (!(T > 1e-3)) T = 1e-3;
+    th[0] = log(rho / (2.0 * kPi * T)) - (U0 * U0 + U1 * U1) / (2.0 * T);
+    th[1] = U0 / T;
+    th[2] = U1 / T;
+    th[3] = 1.0 / (2.0 * T);
+  }
+  const double scale = fabs(t[0]) + fabs(t[3]) + 1e-300, tol = 1e-13;
+  double s[14], r[4];
+  wsums(th, x, y, c, K, w, red, s);
+  double nrm = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    r[i] = s[i] - t[i];
+    nrm = fmax(nrm, fabs(r[i]));
+  }
+  if (!isfinite(nrm)) nrm = INFINITY;
+  for (int it = 0; it < 60; ++it) {
+    if (nrm <= tol * scale) return true;
+    double G[4][4], rhs[4], step[4];
+    int o = 4;
+    bool fin = true;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a; b < 4; ++b) {
+        G[a][b] = G[b][a] = s[o];
+        fin = fin && isfinite(s[o]);
+        ++o;
+      }
+    if (!fin) return false;
+    for (int a = 0; a < 4; ++a) rhs[a] = -r[a];
+    if (!spd4_solve(G, rhs, step)) return false;
+    step[3] = -step[3];
+    double a = 1.0, thn[4], sn[14], n_new = INFINITY;
+    while (true) {
+      for (int i = 0; i < 4; ++i) thn[i] = th[i] + a * step[i];
+      wsums(thn, x, y, c, K, w, red, sn);
+      n_new = 0.0;
+      for (int i = 0; i < 4; ++i) n_new = fmax(n_new, fabs(sn[i] - t[i]));
+      if (!isfinite(n_new)) n_new = INFINITY;
+      if (isfinite(n_new) && (n_new < nrm || a < 1e-4) && thn[3] > 0.0) break;
+      a *= 0.5;
+      if (a < 1e-6) break;
+    }
+    double dmax = 0.0, tmax = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      dmax = fmax(dmax, fabs(thn[i] - th[i]));
+      tmax = fmax(tmax, fabs(th[i]));
+    }
+    for (int i = 0; i < 4; ++i) {
+      th[i] = thn[i];
+      r[i] = sn[i] - t[i];
+    }
+    for (int q = 0; q < 14; ++q) s[q] = sn[q];
+    nrm = n_new;
+    if (dmax <= 1e-15 * (1.0 + tmax)) return nrm <= 1e-10 * scale;
+  }
+  return nrm <= tol * scale;
+}
+
+// the cell (i, j) of anti-diagonal dd of scan (sx, sy), block b of the launch
+__device__ __forceinline__ void diag_cell(int nx, int ny, int dd, int sx, int sy, int b, int& i, int& j) {
+  const int lo = dd - (ny - 1) > 0 ? dd - (ny - 1) : 0;
+  const int ip = lo + b, jp = dd - ip;
+  i = sx > 0 ? ip : nx - 1 - ip;
+  j = sy > 0 ? jp : ny - 1 - jp;
+}
+
+// Wall densities of cell (i, j): dens[s] = rho_w for each side s the cell
+// touches (sum over the outgoing half-space of |v_n| f against the incoming
+// flux of the unit wall Maxwellian), 0 elsewhere.  Every thread returns them.
+__device__ __forceinline__ void wall_densities(const double* fc, int i, int j, int nx, int ny, const CavWalls& wl,
+                                               const double* nodes, int N, double* red, double (&dens)[4]) {
+  const int K = N * N;
+  double v[8];
+  for (int q = 0; q < 8; ++q) v[q] = 0.0;
+  const bool touch[4] = {i == 0, i == nx - 1, j == 0, j == ny - 1};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N], fv = fc[k];
+    for (int s = 0; s < 4; ++s) {
+      if (!touch[s]) continue;
+      const double vn = (s < 2 ? x : y) * (s % 2 == 0 ? 1.0 : -1.0);  // along the inward normal
+      if (vn < 0) v[2 * s] += -vn * fv;
+      if (vn > 0) v[2 * s + 1] += vn * wall_m(wl, s, x, y);
+    }
+  }
+  block_sum<8>(v, red);
+  for (int s = 0; s < 4; ++s) dens[s] = touch[s] ? v[2 * s] / v[2 * s + 1] : 0.0;
+}
+
+// One visit per workgroup: the cells of anti-diagonal dd of scan (sx, sy).
+__global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ f, const double* __restrict__ rs,
+                                                           const double* __restrict__ nu, int nx, int ny, int dd,
+                                                           int sx, int sy, double dx, double dy, double eps,
+                                                           CavWalls wl, const double* __restrict__ nodes, int N,
+                                                           double w, int mode, double tol, int max_iter, int fixed,
+                                                           unsigned long long* __restrict__ stats) {
+  __shared__ double red[14 * (kCavThreads / 64)];
+  const int K = N * N;
+  int i, j;
+  diag_cell(nx, ny, dd, sx, sy, blockIdx.x, i, j);
+  const size_t cell = (size_t)i * ny + j;
+  double* fc = f + cell * K;
+  double dens[4];
+  wall_densities(fc, i, j, nx, ny, wl, nodes, N, red, dens);
+  const double* fW = i > 0 ? f + (cell - ny) * K : nullptr;
+  const double* fE = i < nx - 1 ? f + (cell + ny) * K : nullptr;
+  const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
+  const double* fN = j < ny - 1 ? f + (cell + 1) * K : nullptr;
+  const double lam = nu[cell] / eps;
+  double x[kCavOwn], y[kCavOwn], c[kCavOwn], one[kCavOwn], g[kCavOwn], r[kCavOwn], Mg[kCavOwn];
+#pragma unroll
+  for (int q = 0; q < kCavOwn; ++q) {
+    const int k = threadIdx.x + q * kCavThreads;
+    x[q] = y[q] = c[q] = g[q] = r[q] = Mg[q] = 0.0;
+    one[q] = 1.0;
+    if (k < K) {
+      x[q] = nodes[k / N];
+      y[q] = nodes[k % N];
+      c[q] = fabs(x[q]) / dx + fabs(y[q]) / dy;
+      const double W = fW ? fW[k] : dens[0] * wall_m(wl, 0, x[q], y[q]);
+      const double E = fE ? fE[k] : dens[1] * wall_m(wl, 1, x[q], y[q]);
+      const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x[q], y[q]);
+      const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x[q], y[q]);
+      r[q] = (-fmax(x[q], 0.0) * W + fmin(x[q], 0.0) * E) / dx + (-fmax(y[q], 0.0) * S + fmin(y[q], 0.0) * Nn) / dy +
+             rs[cell * K + k];
+      g[q] = fc[k];
+    }
+  }
+  // M[g] of the initial guess
+  auto moments_of = [&](const double (&a)[kCavOwn], double (&t)[4]) {
+    double v[14];
+    for (int q = 0; q < 14; ++q) v[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCavOwn; ++q) {
+      const double e = threadIdx.x + q * kCavThreads < K ? w * a[q] : 0.0;
+      v[0] += e;
+      v[1] += x[q] * e;
+      v[2] += y[q] * e;
+      v[3] += (x[q] * x[q] + y[q] * y[q]) * e;
+    }
+    block_sum<14>(v, red);
+    for (int q = 0; q < 4; ++q) t[q] = v[q];
+  };
+  double th_g[4], t4[4];
+  moments_of(g, t4);
+  (void)newton4(th_g, t4, true, x, y, one, K, w, red);
+#pragma unroll
+  for (int q = 0; q < kCavOwn; ++q) Mg[q] = gauss2c(th_g, x[q], y[q]);
+  double th_step[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
+  bool fallback = mode == BZ_SOLVE_FP, fell = false;
+  const int n = fixed > 0 ? fixed : max_iter;
+  int it = 0;
+  double res = INFINITY;
+  for (; it < n;) {
+    double Mstep[kCavOwn];
+    if (!fallback) {
+      double sv[kCavOwn], s4[4];
+#pragma unroll
+      for (int q = 0; q < kCavOwn; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
+      moments_of(sv, s4);
+      bool ok = s4[0] > 0.0 && s4[0] * s4[3] > s4[1] * s4[1] + s4[2] * s4[2];
+      double th[4] = {th_step[0], th_step[1], th_step[2], th_step[3]};
+      if (ok) ok = newton4(th, s4, false, x, y, c, K, w, red) && th[3] > 0.0;
+      if (ok) {
+        for (int a = 0; a < 4; ++a) th_step[a] = th[a];
+#pragma unroll
+        for (int q = 0; q < kCavOwn; ++q) Mstep[q] = gauss2c(th, x[q], y[q]);
+      } else {
+        fallback = true;
+        fell = true;
+      }
+    }
+    if (fallback) {
+#pragma unroll
+      for (int q = 0; q < kCavOwn; ++q) Mstep[q] = Mg[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kCavOwn; ++q)
+      g[q] = threadIdx.x + q * kCavThreads < K ? (lam * Mstep[q] - r[q]) / (c[q] + lam) : 0.0;
+    moments_of(g, t4);
+    (void)newton4(th_g, t4, true, x, y, one, K, w, red);
+    double e2[14];
+    for (int q = 0; q < 14; ++q) e2[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCavOwn; ++q) {
+      const int k = threadIdx.x + q * kCavThreads;
+      Mg[q] = gauss2c(th_g, x[q], y[q]);
+      if (k < K) {
+        const double e = c[q] * g[q] + r[q] - lam * (Mg[q] - g[q]);
+        e2[0] += e * e;
+      }
+    }
+    block_sum<14>(e2, red);
+    res = sqrt(w * e2[0]);
+    ++it;
+    if (fixed <= 0 && res <= tol) break;
+  }
+  const bool finite = isfinite(res);
+  if (finite) {
+#pragma unroll
+    for (int q = 0; q < kCavOwn; ++q) {
+      const int k = threadIdx.x + q * kCavThreads;
+      if (k < K) fc[k] = g[q];
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&stats[0], (unsigned long long)it);
+    atomicAdd(&stats[1], 1ull);
+    atomicAdd(&stats[2], fell ? 1ull : 0ull);
+  }
+}
+
+// rs = -(Q - nu (M_theta - f)) / eps (binary) or 0 (BGK), and nu, per cell
+__global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __restrict__ f, const double* __restrict__ Q,
+                                                            const double* __restrict__ theta, double* __restrict__ rs,
+                                                            double* __restrict__ nu, const double* __restrict__ nodes,
+                                                            int N, double w, double eps, int bgk, double bgk_nu,
+                                                            double gam, double gfac) {
+  __shared__ double red[1 * (kCavThreads / 64)];
+  const int K = N * N;
+  const size_t cell = blockIdx.x;
+  const double* fc = f + cell * K;
+  double v[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) v[0] += fc[k];
+  block_sum<1>(v, red);
+  const double rho = w * v[0];
+  double nv;
+  if (bgk) {
+    nv = bgk_nu > 0 ? bgk_nu : 2.0 * kPi * rho;
+  } else {
+    const double* th = theta + cell * 4;
+    nv = gam == 0.0 ? 2.0 * kPi * rho : 2.0 * kPi * rho * gfac * pow(0.5 / th[3], 0.5 * gam);
+  }
+  if (threadIdx.x == 0) nu[cell] = nv;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    if (bgk) {
+      rs[cell * K + k] = 0.0;
+    } else {
+      const double M = gauss2c(theta + cell * 4, nodes[k / N], nodes[k % N]);
+      rs[cell * K + k] = -((Q[cell * K + k] - nv * (M - fc[k])) / eps);
+    }
+  }
+}
+
+// per-cell sum of w R^2 with R = v.grad f - Q/eps (BGK: Q = nu (M - f))
+__global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restrict__ f, const double* __restrict__ Q,
+                                                           const double* __restrict__ theta, int nx, int ny,
+                                                           double dx, double dy, double eps, CavWalls wl,
+                                                           const double* __restrict__ nodes, int N, double w, int bgk,
+                                                           double bgk_nu, double* __restrict__ part) {
+  __shared__ double red[8 * (kCavThreads / 64)];
+  const int K = N * N;
+  const int cell = blockIdx.x, i = cell / ny, j = cell - i * ny;
+  const double* fc = f + (size_t)cell * K;
+  double dens[4];
+  wall_densities(fc, i, j, nx, ny, wl, nodes, N, red, dens);
+  double nv = 0.0;
+  if (bgk) {
+    double v[1] = {0.0};
+    for (int k = threadIdx.x; k < K; k += blockDim.x) v[0] += fc[k];
+    block_sum<1>(v, red);
+    nv = bgk_nu > 0 ? bgk_nu : 2.0 * kPi * w * v[0];
+  }
+  const double* fW = i > 0 ? fc - (size_t)ny * K : nullptr;
+  const double* fE = i < nx - 1 ? fc + (size_t)ny * K : nullptr;
+  const double* fS = j > 0 ? fc - K : nullptr;
+  const double* fN = j < ny - 1 ? fc + K : nullptr;
+  double acc[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N], fv = fc[k];
+    const double W = fW ? fW[k] : dens[0] * wall_m(wl, 0, x, y);
+    const double E = fE ? fE[k] : dens[1] * wall_m(wl, 1, x, y);
+    const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x, y);
+    const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x, y);
+    const double q = bgk ? nv * (gauss2c(theta + (size_t)cell * 4, x, y) - fv) : Q[(size_t)cell * K + k];
+    const double R = (fmax(x, 0.0) * (fv - W) + fmin(x, 0.0) * (E - fv)) / dx +
+                     (fmax(y, 0.0) * (fv - S) + fmin(y, 0.0) * (Nn - fv)) / dy - q / eps;
+    acc[0] += R * R;
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[cell] = w * acc[0];
+}
+
+__global__ void __launch_bounds__(kCavThreads) k_cav_cellsum(const double* __restrict__ f, int K,
+                                                             double* __restrict__ part) {
+  __shared__ double red[kCavThreads / 64];
+  const double* fc = f + (size_t)blockIdx.x * K;
+  double v[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) v[0] += fc[k];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// f <- f C / (dx dy w sum f); every block sums the per-cell partials itself
+__global__ void __launch_bounds__(kCavThreads) k_cav_rescale(double* __restrict__ f, int K, int ncell,
+                                                             const double* __restrict__ part, double cw, double C) {
+  __shared__ double red[kCavThreads / 64];
+  double v[1] = {0.0};
+  for (int q = threadIdx.x; q < ncell; q += blockDim.x) v[0] += part[q];
+  block_sum<1>(v, red);
+  const double sc = C / (cw * v[0]);
+  double* fc = f + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) fc[k] *= sc;
+}
+
+__global__ void __launch_bounds__(kCavThreads) k_cav_total(const double* __restrict__ part, int ncell,
+                                                           double* __restrict__ out) {
+  __shared__ double red[kCavThreads / 64];
+  double v[1] = {0.0};
+  for (int q = threadIdx.x; q < ncell; q += blockDim.x) v[0] += part[q];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) out[0] = v[0];
+}
+
+CavWalls walls_of(const bz_cavity* cv) {
+  CavWalls wl{};
+  for (int s = 0; s < 4; ++s) {
+    wl.T[s] = cv->walls[s].T;
+    wl.U1[s] = cv->walls[s].U[0];
+    wl.U2[s] = cv->walls[s].U[1];
+  }
+  return wl;
+}
+
+// collision split of every cell: theta, nu and rs = -P / eps
+bz_status cav_static(bz_ctx* ctx, bz_cavity* cv, hipStream_t st) {
+  const bool bgk = cv->collision == BZ_COLL_BGK;
+  if (!bgk) {
+    bz_status s = v2_eval_q(ctx, cv->f, cv->d_Q, cv->ncell, true, true, cv->d_theta, st);
+    if (s != BZ_OK) return s;
+  }
+  hipLaunchKernelGGL(k_cav_static, dim3(cv->ncell), dim3(kCavThreads), 0, st, cv->f, cv->d_Q, cv->d_theta, cv->d_rs,
+                     cv->d_nu, ctx->d_nodes, ctx->N, ctx->w, cv->eps, bgk ? 1 : 0, cv->bgk_nu, ctx->p.gamma,
+                     ctx->nu_gfac);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, double* out, hipStream_t st) {
+  const bool bgk = cv->collision == BZ_COLL_BGK;
+  bz_status s = bgk ? v2_maxwellian(ctx, cv->f, cv->d_theta, nullptr, nullptr, cv->ncell, st)
+                    : v2_eval_q(ctx, cv->f, cv->d_Q, cv->ncell, true, true, cv->d_theta, st);
+  if (s != BZ_OK) return s;
+  hipLaunchKernelGGL(k_cav_resid, dim3(cv->ncell), dim3(kCavThreads), 0, st, cv->f, cv->d_Q, cv->d_theta, cv->nx,
+                     cv->ny, cv->dx, cv->dy, cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0,
+                     cv->bgk_nu, cv->d_part);
+  BZ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cav_total, dim3(1), dim3(kCavThreads), 0, st, cv->d_part, cv->ncell, cv->d_part + cv->ncell);
+  BZ_HIP(hipGetLastError());
+  double tot = 0.0;
+  BZ_HIP(hipMemcpyAsync(&tot, cv->d_part + cv->ncell, sizeof(double), hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipStreamSynchronize(st));
+  *out = std::sqrt(cv->dx * cv->dy * tot);
+  return BZ_OK;
+}
+
+}  // namespace
+}  // namespace bz
+
+using bz::set_err;
+
+extern "C" {
+
+bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out) {
+  if (!ctx || !out) return BZ_EINVAL;
+  *out = nullptr;
+  if (ctx->d != 2) return set_err(ctx, BZ_EUNSUPPORTED, "the cavity needs a context with d = 2");
+  if (!d || !d->f) return set_err(ctx, BZ_EINVAL, "bad cavity description");
+  if (d->nx < 1 || d->ny < 1 || d->nx > 4096 || d->ny > 4096 || (int64_t)d->nx * d->ny > (1 << 24))
+    return set_err(ctx, BZ_EINVAL, "nx, ny must be in [1, 4096]");
+  if (!(d->eps > 0) || !std::isfinite(d->eps)) return set_err(ctx, BZ_EINVAL, "eps must be > 0");
+  if (!(d->mass > 0) || !std::isfinite(d->mass)) return set_err(ctx, BZ_EINVAL, "mass must be > 0");
+  if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK)
+    return set_err(ctx, BZ_EINVAL, "collision must be BZ_COLL_BINARY or BZ_COLL_BGK");
+  for (int s = 0; s < 4; ++s) {
+    const bz_wall& wl = d->walls[s];
+    if (!(wl.T > 0) || !std::isfinite(wl.T) || !std::isfinite(wl.U[0]) || !std::isfinite(wl.U[1]))
+      return set_err(ctx, BZ_EINVAL, "wall temperature must be > 0 and velocities finite");
+    if (wl.U[s / 2] != 0.0) return set_err(ctx, BZ_EINVAL, "wall velocities must be tangential");
+  }
+  const bz_solve_opts& o = d->inner;
+  if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad solve mode");
+  if (o.fixed_iters < 0 || o.fixed_iters > 100000 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) ||
+      !(o.tol >= 0) || !std::isfinite(o.tol))
+    return set_err(ctx, BZ_EINVAL, "bad inner solve options");
+  if (ctx->K > bz::kCavOwn * bz::kCavThreads) return set_err(ctx, BZ_EINVAL, "the cavity needs N <= 48");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  bz_cavity* cv = new bz_cavity();
+  cv->ctx = ctx;
+  cv->nx = d->nx;
+  cv->ny = d->ny;
+  cv->ncell = d->nx * d->ny;
+  cv->eps = d->eps;
+  cv->dx = 1.0 / d->nx;
+  cv->dy = 1.0 / d->ny;
+  cv->mass = d->mass;
+  for (int s = 0; s < 4; ++s) cv->walls[s] = d->walls[s];
+  cv->collision = d->collision;
+  cv->bgk_nu = d->bgk_nu;
+  cv->opts = o;
+  cv->f = d->f;
+  const size_t K = ctx->K, nc = cv->ncell;
+  bool ok = hipMalloc((void**)&cv->d_Q, nc * K * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&cv->d_rs, nc * K * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&cv->d_theta, nc * 4 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&cv->d_nu, nc * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&cv->d_part, (nc + 1) * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&cv->d_stats, 3 * sizeof(unsigned long long)) == hipSuccess;
+  if (!ok) {
+    bz_cavity_destroy(cv);
+    return set_err(ctx, BZ_ENOMEM, "cavity workspace");
+  }
+  *out = cv;
+  return BZ_OK;
+}
+
+void bz_cavity_destroy(bz_cavity* cv) {
+  if (!cv) return;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {cv->d_Q, cv->d_rs, cv->d_theta, cv->d_nu, cv->d_part, cv->d_stats};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete cv;
+}
+
+bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cv, int n_iters, double* residual_out, bz_sweep_stats* stats,
+                          void* stream) {
+  if (!ctx || !cv || cv->ctx != ctx) return BZ_EINVAL;
+  if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 3 * sizeof(unsigned long long), st));
+  const bz::CavWalls wl = bz::walls_of(cv);
+  static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+  for (int it = 0; it < n_iters; ++it) {
+    for (int sc = 0; sc < 4; ++sc) {
+      bz_status s = bz::cav_static(ctx, cv, st);
+      if (s != BZ_OK) return s;
+      for (int dd = 0; dd <= cv->nx + cv->ny - 2; ++dd) {
+        const int lo = dd - (cv->ny - 1) > 0 ? dd - (cv->ny - 1) : 0;
+        const int hi = dd < cv->nx - 1 ? dd : cv->nx - 1;
+        hipLaunchKernelGGL(bz::k_cav_visit, dim3(hi - lo + 1), dim3(bz::kCavThreads), 0, st, cv->f, cv->d_rs,
+                           cv->d_nu, cv->nx, cv->ny, dd, scans[sc][0], scans[sc][1], cv->dx, cv->dy, cv->eps, wl,
+                           ctx->d_nodes, ctx->N, ctx->w, cv->opts.mode, cv->opts.tol, cv->opts.max_iter,
+                           cv->opts.fixed_iters, cv->d_stats);
+        BZ_HIP(hipGetLastError());
+      }
+    }
+    hipLaunchKernelGGL(bz::k_cav_cellsum, dim3(cv->ncell), dim3(bz::kCavThreads), 0, st, cv->f, ctx->K, cv->d_part);
+    BZ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bz::k_cav_rescale, dim3(cv->ncell), dim3(bz::kCavThreads), 0, st, cv->f, ctx->K, cv->ncell,
+                       cv->d_part, cv->dx * cv->dy * ctx->w, cv->mass);
+    BZ_HIP(hipGetLastError());
+  }
+  if (residual_out) {
+    bz_status s = bz::cav_residual(ctx, cv, residual_out, st);
+    if (s != BZ_OK) return s;
+  }
+  unsigned long long h[3] = {0, 0, 0};
+  BZ_HIP(hipMemcpyAsync(h, cv->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    stats->n_iters = n_iters;
+    stats->inner_iters = (int64_t)h[0];
+    stats->visits = (int64_t)h[1];
+    stats->fallbacks = (int64_t)h[2];
+  }
+  return BZ_OK;
+}
+
+bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cv, double* residual_out, void* stream) {
+  if (!ctx || !cv || cv->ctx != ctx || !residual_out) return BZ_EINVAL;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return bz::cav_residual(ctx, cv, residual_out, (hipStream_t)stream);
+}
+
+}  // extern "C"

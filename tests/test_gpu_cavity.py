@@ -1,0 +1,96 @@
+"""GPU parity of the 2D SGS scans (lid-driven cavity, d = 2 velocities) against
+the CPU oracle, through the C ABI.  The GPU visits anti-diagonals, the oracle
+the lexicographic order: the iterates must agree one to one (fixed inner
+iteration counts)."""
+import numpy as np
+import pytest
+
+from oracle import cavity as CV
+from oracle.grid import Spec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LID = ((1.0, (0.0, 0.0)), (1.5, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.2, (0.5, 0.0)))
+
+
+@pytest.fixture(scope="module")
+def bz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_01910_amd as bz
+
+    bz.load_library()
+    return bz
+
+
+def _setup(bz, N, L, nx, ny, collision, fixed, mode="pfp", eps=0.1, walls=LID, M=8, nr=4):
+    sp = Spec(d=2, N=N, L=L, n_phi=M, n_rho=nr)
+    prob = CV.Cavity(spec=sp, nx=nx, ny=ny, eps=eps, walls=walls, collision=collision, inner=mode,
+                     fixed_inner=fixed)
+    f0 = CV.initial_state(prob, T=1.2)
+    ctx = bz.Context(N=N, L=L, n_phi=M, n_rho=nr, d=2)
+    fg = torch.from_numpy(f0.reshape(nx * ny, -1).copy()).to("cuda:0").contiguous()
+    cav = bz.Cavity(ctx, nx, ny, eps, walls, fg, collision=collision, mode=mode, fixed_iters=fixed or 0)
+    return prob, f0, ctx, cav, fg
+
+
+@pytest.mark.parametrize("collision,mode,N,L", [("bgk", "pfp", 8, 4.0), ("binary", "pfp", 8, 4.0),
+                                                ("binary", "fp", 8, 4.0), ("binary", "pfp", 12, 6.0)])
+def test_cavity_sweeps_match_oracle(bz, collision, mode, N, L):
+    nx, ny = 3, 4
+    print(f"cavity {collision} {mode} N={N} {nx}x{ny}", flush=True)
+    prob, f0, ctx, cav, fg = _setup(bz, N, L, nx, ny, collision, fixed=2, mode=mode)
+    res, st = cav.sweep(2)
+    f = f0
+    for _ in range(2):
+        f = CV.sgs_iteration(prob, f)
+    got = fg.cpu().numpy().reshape(nx, ny, -1)
+    err = np.abs(got - f).max() / f.max()
+    print(f"max rel diff {err:.3e}, residual {res:.6e} vs {CV.outer_residual(prob, f):.6e}", flush=True)
+    assert err < 1e-10
+    ref = CV.outer_residual(prob, f)
+    assert abs(res - ref) < 1e-9 * ref
+    assert st["visits"] == 2 * 4 * nx * ny and st["inner_iters"] == 2 * st["visits"]
+    assert abs(CV.total_mass(prob, got) - 1.0) < 1e-13
+
+
+def test_equilibrium_between_equal_walls_is_kept(bz):
+    walls = ((1.0, (0.0, 0.0)),) * 4
+    sp = Spec(d=2, N=16, L=8.0, n_phi=8, n_rho=4)
+    prob = CV.Cavity(spec=sp, nx=3, ny=3, eps=0.1, walls=walls)
+    f0 = CV.initial_state(prob)
+    ctx = bz.Context(N=16, L=8.0, n_phi=8, n_rho=4, d=2)
+    fg = torch.from_numpy(f0.reshape(9, -1).copy()).to("cuda:0").contiguous()
+    cav = bz.Cavity(ctx, 3, 3, 0.1, walls, fg)
+    assert cav.residual() < 1e-11
+    res, _ = cav.sweep(1)
+    assert np.abs(fg.cpu().numpy() - f0.reshape(9, -1)).max() < 1e-11 * f0.max()
+    assert res < 1e-11
+
+
+def test_cavity_converges_with_tolerance_based_inner_solves(bz):
+    prob, f0, ctx, cav, fg = _setup(bz, 12, 6.0, 5, 5, "binary", fixed=None)
+    hist = [cav.residual()]
+    for _ in range(60):
+        r, st = cav.sweep(1)
+        hist.append(r)
+        if r < 1e-8:
+            break
+    print("residuals", [f"{h:.2e}" for h in hist[::5]], flush=True)
+    assert hist[-1] < 1e-8 < hist[0]
+    assert abs(CV.total_mass(prob, fg.cpu().numpy().reshape(5, 5, -1)) - 1.0) < 1e-13
+
+
+def test_cavity_rejects_bad_arguments(bz):
+    ctx = bz.Context(N=8, L=4.0, n_phi=8, n_rho=4, d=2)
+    fg = torch.zeros((4, 64), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(bz.BZError):  # normal wall velocity
+        bz.Cavity(ctx, 2, 2, 0.1, ((1.0, (0.3, 0.0)),) + ((1.0, (0.0, 0.0)),) * 3, fg)
+    with pytest.raises(bz.BZError):
+        bz.Cavity(ctx, 2, 2, 0.0, ((1.0, (0.0, 0.0)),) * 4, fg)
+    ctx3 = bz.Context(N=8, L=4.0, n_theta=2, n_phi=4, n_rho=2)
+    f3 = torch.zeros((4, 512), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(bz.BZError):
+        bz.Cavity(ctx3, 2, 2, 0.1, ((1.0, (0.0, 0.0)),) * 4, f3)
