@@ -20,7 +20,7 @@
 //
 // Layout and work split: one workgroup of 512 threads per cell.  K = N^2 is at
 // most 2304, so the two spectra (gh, hh) and the two ping-pong buffers of a
-// transform fit in LDS together (4 K complex doubles, 147 KB at N = 48), and
+// transform (rows padded to N + 1) fit in LDS together (151 KB at N = 48), and
 // every pass of every transform stays on chip: the cell's field is read from
 // HBM once and Q written once.  Transforms are Stockham autosort passes of
 // radix 4, 3 and 2 along the fast axis, then along the slow axis; thread t owns
@@ -34,26 +34,31 @@ namespace bz {
 namespace {
 
 constexpr int kV2Threads = 512;
-constexpr int kV2Own = 5;  // ceil(48^2 / 512) points per thread at the largest N
-
-struct V2Radix {
-  int n;
-  int r[4];
-};
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// The q-th radix of a length-n transform: 4 while it divides, then 3, then 2
+// (1 past the last pass).
+constexpr int radix_at(int n, int q) {
+  for (int i = 0;; ++i) {
+    const int r = n % 4 == 0 ? 4 : n % 3 == 0 ? 3 : n % 2 == 0 ? 2 : 1;
+    if (r == 1 || i == q) return r;
+    n /= r;
+  }
+}
+
 // y_k = sum_m v_m exp(SIGN 2 pi i m k / R), in place, R in {2, 3, 4}
-__device__ __forceinline__ void small_dft(double2 (&v)[4], int R, int sign) {
-  if (R == 2) {
+template <int R, int SIGN>
+__device__ __forceinline__ void small_dft(double2 (&v)[R]) {
+  if constexpr (R == 2) {
     const double2 a = v[0], b = v[1];
     v[0] = make_double2(a.x + b.x, a.y + b.y);
     v[1] = make_double2(a.x - b.x, a.y - b.y);
-  } else if (R == 3) {
-    const double h = 0.86602540378443864676 * sign;  // sign * sqrt(3) / 2
+  } else if constexpr (R == 3) {
+    constexpr double h = 0.86602540378443864676 * SIGN;  // SIGN * sqrt(3) / 2
     const double2 t1 = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
     const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
     const double2 t3 = make_double2(h * (v[1].x - v[2].x), h * (v[1].y - v[2].y));
@@ -65,8 +70,8 @@ __device__ __forceinline__ void small_dft(double2 (&v)[4], int R, int sign) {
     const double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
     const double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
     const double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
-    // sign * i * (v1 - v3)
-    const double2 e = make_double2(-sign * (v[1].y - v[3].y), sign * (v[1].x - v[3].x));
+    // SIGN * i * (v1 - v3)
+    const double2 e = make_double2(-SIGN * (v[1].y - v[3].y), SIGN * (v[1].x - v[3].x));
     v[0] = make_double2(a.x + c.x, a.y + c.y);
     v[2] = make_double2(a.x - c.x, a.y - c.y);
     v[1] = make_double2(b.x + e.x, b.y + e.y);
@@ -75,48 +80,61 @@ __device__ __forceinline__ void small_dft(double2 (&v)[4], int R, int sign) {
 }
 
 // One Stockham pass of radix R over all N lines of an N x N tile along one
-// axis (axis 1: contiguous lines; axis 0: columns).  Ns is the product of the
-// radices of the earlier passes on this axis; tw[q] = exp(2 pi i q / N).
-__device__ __forceinline__ void stockham_pass(const double2* __restrict__ src, double2* __restrict__ dst, int N,
-                                              int R, int Ns, int axis, int sign, const double2* tw) {
-  const int NR = N / R, items = N * NR, step = N / (Ns * R);
-  const int es = axis == 1 ? 1 : N;
+// axis (AXIS 1: rows; AXIS 0: columns).  The tile's rows are P = N + 1 complex
+// values apart, and consecutive threads take consecutive lines, so that the
+// lanes of a wave hit distinct LDS banks along either axis.  NS is the product
+// of the radices of the earlier passes on this axis; tw[q] = exp(2 pi i q / N).
+template <int N, int R, int NS, int AXIS, int SIGN>
+__device__ __forceinline__ void stockham_pass(const double2* __restrict__ src, double2* __restrict__ dst,
+                                              const double2* tw) {
+  constexpr int NR = N / R, items = N * NR, step = N / (NS * R), P = N + 1;
+  constexpr int es = AXIS == 1 ? 1 : P, ls = AXIS == 1 ? P : 1;
   for (int t = threadIdx.x; t < items; t += blockDim.x) {
-    const int line = t / NR, j = t - line * NR;
-    const int k = j % Ns;
-    const int base = axis == 1 ? line * N : line;
-    double2 v[4];
+    const int j = t / N, line = t - j * N;
+    const int k = j % NS;
+    const int base = line * ls;
+    double2 v[R];
+#pragma unroll
     for (int m = 0; m < R; ++m) v[m] = src[base + (j + m * NR) * es];
+#pragma unroll
     for (int m = 1; m < R; ++m) {
       double2 w = tw[k * m * step];
-      if (sign < 0) w = cconj(w);
+      if (SIGN < 0) w = cconj(w);
       v[m] = cmul(v[m], w);
     }
-    small_dft(v, R, sign);
-    const int d0 = (j / Ns) * Ns * R + k;
-    for (int m = 0; m < R; ++m) dst[base + (d0 + m * Ns) * es] = v[m];
+    small_dft<R, SIGN>(v);
+    const int d0 = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[base + (d0 + m * NS) * es] = v[m];
   }
 }
 
-// 2D transform X_k = sum_j x_j exp(sign 2 pi i k.j / N) of buffer a (b is the
-// ping-pong partner); returns the buffer that holds the result.  Synchronises
-// before returning.
-__device__ __forceinline__ double2* dft2(double2* a, double2* b, int N, const V2Radix& rx, int sign,
-                                         const double2* tw) {
-  double2 *src = a, *dst = b;
-  for (int axis = 1; axis >= 0; --axis) {
-    int Ns = 1;
-    for (int q = 0; q < rx.n; ++q) {
-      stockham_pass(src, dst, N, rx.r[q], Ns, axis, sign, tw);
-      __syncthreads();
-      Ns *= rx.r[q];
-      double2* t = src;
-      src = dst;
-      dst = t;
-    }
+template <int N, int SIGN, int AXIS, int Q, int NS>
+__device__ __forceinline__ void axis_passes(double2*& src, double2*& dst, const double2* tw) {
+  constexpr int R = radix_at(N, Q);
+  if constexpr (R > 1) {
+    stockham_pass<N, R, NS, AXIS, SIGN>(src, dst, tw);
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    axis_passes<N, SIGN, AXIS, Q + 1, NS * R>(src, dst, tw);
   }
+}
+
+// 2D transform X_k = sum_j x_j exp(SIGN 2 pi i k.j / N) of tile a (b is the
+// ping-pong partner); returns the tile that holds the result.  Synchronises
+// before returning.
+template <int N, int SIGN>
+__device__ __forceinline__ double2* dft2(double2* a, double2* b, const double2* tw) {
+  double2 *src = a, *dst = b;
+  axis_passes<N, SIGN, 1, 0, 1>(src, dst, tw);
+  axis_passes<N, SIGN, 0, 0, 1>(src, dst, tw);
   return src;
 }
+
+// position of grid point k = i_1 N + i_2 in a transform tile (row pitch N + 1)
+__device__ __forceinline__ int tix(int k, int N) { return k + k / N; }
 
 __device__ __forceinline__ double gauss2(const double* th, double x, double y) {
   return exp(th[0] + th[1] * x + th[2] * y - th[3] * (x * x + y * y));
@@ -124,20 +142,23 @@ __device__ __forceinline__ double gauss2(const double* th, double x, double y) {
 
 // Collision term of one cell per workgroup.  theta (corrected only) holds the
 // cell's discrete Maxwellian.  mass: Q <- Q - M sum(Q) / sum(M).
+template <int N>
 __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f, const double* __restrict__ theta,
-                                                   double* __restrict__ Q, int N, V2Radix rx,
+                                                   double* __restrict__ Q,
                                                    const double* __restrict__ nodes, const double* __restrict__ xi,
                                                    const double* __restrict__ tw_g, const double* __restrict__ dir,
                                                    const double* __restrict__ rho, int n_rho, int n_pairs,
                                                    double w_pair, const double* __restrict__ W,
                                                    const double* __restrict__ Gm, int corrected, int mass) {
   extern __shared__ double2 smem[];
-  const int K = N * N, cell = blockIdx.x, tid = threadIdx.x;
+  constexpr int K = N * N, KP = N * (N + 1);  // KP: a transform tile with padded rows
+  constexpr int kV2Own = (K + kV2Threads - 1) / kV2Threads;
+  const int cell = blockIdx.x, tid = threadIdx.x;
   double2* SG = smem;
   double2* SH = SG + K;
   double2* B0 = SH + K;
-  double2* B1 = B0 + K;
-  double2* TW = B1 + K;
+  double2* B1 = B0 + KP;
+  double2* TW = B1 + KP;
   double2* E0 = TW + N;
   double2* E1 = E0 + N;
   double* red = reinterpret_cast<double*>(E1 + N);
@@ -161,19 +182,19 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
       } else {
         g[i] = h[i] = fv;
       }
-      B0[k] = make_double2(g[i], h[i]);
+      B0[tix(k, N)] = make_double2(g[i], h[i]);
     }
   }
   __syncthreads();
   // spectra: Z = DFT(g + i h); gh_l = (Z_l + conj Z_-l) / 2K, hh_l = (Z_l - conj Z_-l) / 2iK,
   // Nyquist modes zeroed
   {
-    const double2* Z = dft2(B0, B1, N, rx, -1, TW);
+    const double2* Z = dft2<N, -1>(B0, B1, TW);
     const double s = 0.5 / K;
     for (int k = tid; k < K; k += blockDim.x) {
       const int l1 = k / N, l2 = k - l1 * N;
       const int m = ((N - l1) % N) * N + (N - l2) % N;
-      const double2 a = Z[k], b = Z[m];
+      const double2 a = Z[tix(k, N)], b = Z[tix(m, N)];
       const bool nyq = l1 == N / 2 || l2 == N / 2;
       SG[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.x + b.x), s * (a.y - b.y));
       SH[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.y + b.y), -s * (a.x - b.x));
@@ -205,15 +226,15 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
         for (int k = tid; k < K; k += blockDim.x) {
           const double2 ph = cmul(E0[k / N], E1[k % N]);
           const double2 u = cmul(X[k], ph), w = cmul(Y[k], cconj(ph));
-          B0[k] = make_double2(u.x - w.y, u.y + w.x);  // u + i w
+          B0[tix(k, N)] = make_double2(u.x - w.y, u.y + w.x);  // u + i w
         }
         __syncthreads();
-        const double2* T = dft2(B0, B1, N, rx, +1, TW);
+        const double2* T = dft2<N, +1>(B0, B1, TW);
 #pragma unroll
         for (int i = 0; i < kV2Own; ++i) {
           const int k = tid + i * kV2Threads;
           if (k < K) {
-            const double2 t = T[k];
+            const double2 t = T[tix(k, N)];
             if (pass == 0) {
               ag[i] = t.x;
               bh[i] = t.y;
@@ -229,17 +250,18 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
-      if (k < K) B0[k] = make_double2(acc[i], 0.0);
+      if (k < K) B0[tix(k, N)] = make_double2(acc[i], 0.0);
     }
     __syncthreads();
-    const double2* A = dft2(B0, B1, N, rx, -1, TW);
+    const double2* A = dft2<N, -1>(B0, B1, TW);
     const double* Wr = W + (size_t)r * K;
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
       if (k < K) {
-        qr[i] += Wr[k] * A[k].x;
-        qi[i] += Wr[k] * A[k].y;
+        const double2 a = A[tix(k, N)];
+        qr[i] += Wr[k] * a.x;
+        qi[i] += Wr[k] * a.y;
       }
     }
     __syncthreads();
@@ -249,15 +271,15 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
     const int k = tid + i * kV2Threads;
-    if (k < K) B0[k] = make_double2(qr[i], qi[i]);
+    if (k < K) B0[tix(k, N)] = make_double2(qr[i], qi[i]);
   }
   __syncthreads();
   {
-    const double2* G = dft2(B0, B1, N, rx, +1, TW);
+    const double2* G = dft2<N, +1>(B0, B1, TW);
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
-      gain[i] = k < K ? G[k].x : 0.0;
+      gain[i] = k < K ? G[tix(k, N)].x : 0.0;
     }
     __syncthreads();
   }
@@ -265,17 +287,18 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
   for (int k = tid; k < K; k += blockDim.x) {
     const double gm = Gm[k];
     const double2 a = SH[k], b = SG[k];
-    B0[k] = make_double2(gm * (a.x - b.y), gm * (a.y + b.x));
+    B0[tix(k, N)] = make_double2(gm * (a.x - b.y), gm * (a.y + b.x));
   }
   __syncthreads();
-  const double2* Lx = dft2(B0, B1, N, rx, +1, TW);
+  const double2* Lx = dft2<N, +1>(B0, B1, TW);
   double q[kV2Own], sq = 0.0, sm = 0.0;
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
     const int k = tid + i * kV2Threads;
     q[i] = 0.0;
     if (k < K) {
-      q[i] = gain[i] - 0.5 * (g[i] * Lx[k].x + h[i] * Lx[k].y);
+      const double2 l = Lx[tix(k, N)];
+      q[i] = gain[i] - 0.5 * (g[i] * l.x + h[i] * l.y);
       sq += q[i];
       sm += Mk[i];
     }
@@ -421,7 +444,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_max2(const double* __restrict__
     for (int k = threadIdx.x; k < K; k += blockDim.x) Mout[(size_t)cell * K + k] = gauss2(th, nodes[k / N], nodes[k % N]);
 }
 
-size_t q2_lds_bytes(int N) { return (size_t)(4 * N * N + 3 * N) * sizeof(double2) + 2 * (kV2Threads / 64) * 8; }
+size_t q2_lds_bytes(int N) {
+  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * sizeof(double2) + 2 * (kV2Threads / 64) * 8;
+}
 
 }  // namespace
 
@@ -440,7 +465,6 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
   if (batch == 0) return BZ_OK;
   if (batch > INT32_MAX) return set_err(ctx, BZ_EINVAL, "batch too large");
   const int N = ctx->N;
-  if (N * N > kV2Own * kV2Threads) return set_err(ctx, BZ_EINVAL, "d = 2 needs N <= 48");
   double* th = nullptr;
   if (corrected) {
     th = theta_out;
@@ -452,15 +476,26 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
     bz_status s = v2_maxwellian(ctx, f, th, nullptr, nullptr, batch, st);
     if (s != BZ_OK) return s;
   }
-  V2Radix rx{};
-  rx.n = ctx->v2_npass;
-  for (int q = 0; q < 4; ++q) rx.r[q] = ctx->v2_rad[q];
   const size_t lds = q2_lds_bytes(N);
-  BZ_HIP(hipFuncSetAttribute((const void*)k_q2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   const double w_pair = 2.0 * (2.0 * kPi / ctx->n_phi);
-  hipLaunchKernelGGL(k_q2, dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, N, rx, ctx->d_nodes,
-                     ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,
-                     ctx->d_W, ctx->d_Gm, corrected ? 1 : 0, mass ? 1 : 0);
+  const int corr = corrected ? 1 : 0, ms = mass ? 1 : 0;
+#define BZ_Q2_LAUNCH(NN)                                                                                         \
+  case NN:                                                                                                       \
+    BZ_HIP(hipFuncSetAttribute((const void*)k_q2<NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    hipLaunchKernelGGL(k_q2<NN>, dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,       \
+                       ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair, \
+                       ctx->d_W, ctx->d_Gm, corr, ms);                                                           \
+    break;
+  switch (N) {
+    BZ_Q2_LAUNCH(8)
+    BZ_Q2_LAUNCH(12)
+    BZ_Q2_LAUNCH(16)
+    BZ_Q2_LAUNCH(24)
+    BZ_Q2_LAUNCH(32)
+    BZ_Q2_LAUNCH(48)
+    default: return set_err(ctx, BZ_EINVAL, "d = 2 needs N in {8, 12, 16, 24, 32, 48}");
+  }
+#undef BZ_Q2_LAUNCH
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
