@@ -273,6 +273,92 @@ def order_workload(args):
     return {"workload": "order", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
+def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label):
+    """Lid-driven cavity on [0, 1]^2 (all walls T = 1, the lid y = 1 moving at
+    (lid, 0)), n^2 velocities on [-l, l]^2, Maxwell molecules with M circle
+    directions and nr radial nodes, first-order SGS-PFP FP64 (inner residual
+    1e-8), from the uniform unit Maxwellian at rest (mass 1), until the outer
+    residual is below tol or the iteration / time budget is spent."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+
+    dv = 2.0 * l / n
+    x = (np.arange(n) - n // 2 + 1) * dv
+    V = np.stack(np.meshgrid(x, x, indexing="ij"), -1).reshape(-1, 2)
+    m = np.exp(-(V * V).sum(1) / 2.0) / (2.0 * np.pi)
+    f0 = np.repeat(m[None], nx * nx, axis=0)
+    f0 *= 1.0 / (dv * dv * f0.sum() / (nx * nx))
+    f = torch.from_numpy(f0).cuda().contiguous()
+    ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2)
+    walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
+    cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, inner, visits, last = [cav.residual()], 0, 0, t0
+    while hist[-1] >= tol and len(hist) <= max_iters and time.perf_counter() - t0 < max_seconds:
+        r, st = cav.sweep(1)
+        hist.append(r)
+        inner += st["inner_iters"]
+        visits += st["visits"]
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            print(f"# cavity {label} iteration {len(hist) - 1} residual {r:.3e}", flush=True)
+    dt = time.perf_counter() - t0
+    cav.close()
+    it = len(hist) - 1
+    return {"seconds": dt, "iterations": it, "final_residual": hist[-1], "reached": hist[-1] < tol,
+            "ms_per_iteration": 1e3 * dt / max(it, 1), "mean_inner_iterations": inner / max(visits, 1),
+            "residual_every_10": hist[::10]}
+
+
+def cavity_workload(args):
+    """2D2V lid-driven cavity (Section 4.2's family).  paper_40x40: the paper's
+    own case (40 x 40 cells, 32^2 velocities, R = 3 and L = (3 sqrt 2 + 1) R / 2,
+    lid speed 1, walls T = 1; M = 32 and n_rho = 16, which the paper does not
+    state), first-order SGS-PFP to its stopping rule, outer residual 1e-5, at
+    eps = 1, 0.1, 0.01 and 0.001 (each capped at 120 s).  n48_64x64: 64 x 64 cells, 48^2 velocities on [-8, 8]^2,
+    M = 64, n_rho = 24, lid 0.5, eps 0.1, a bounded number of iterations.  Also
+    the batched 2D collision term of that discretisation (4096 cells)."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+    import synth
+
+    out = {}
+    L40 = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
+    for eps in (1.0, 0.1, 0.01, 0.001):
+        key = f"paper_40x40_eps{eps:g}"
+        out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key)
+        print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    key = "n48_64x64_eps0.1"
+    out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 20, 60.0, key)
+    print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    # batched corrected, mass-projected 2D collision term: 4096 cells, 48^2, M = 64, n_rho = 24
+    f = torch.from_numpy(synth.mixture_batch(4096, 48, 8.0, d=2, seed=0)).cuda().contiguous()
+    ctx = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2)
+    Q = torch.empty_like(f)
+    ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    # algorithmic FLOPs: 5 K log2 K per complex 2D transform of K = 48^2 points;
+    # 1 + n_rho (M/2) 2 + n_rho + 2 transforms per corrected cell
+    K = 48 * 48
+    transforms = 1 + 24 * 32 * 2 + 24 + 2
+    flop = transforms * 5.0 * K * np.log2(K)
+    out["batched_q_48x48"] = {"cells": 4096, "ms": 1e3 * dt, "q_evals_per_s": 4096 / dt,
+                              "algorithmic_tflops": 4096 * flop / dt / 1e12,
+                              "frac_fp64_peak": 4096 * flop / dt / 78.6e12}
+    return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
+
+
 def shock_workload(args, tol=1e-8):
     """Normal shocks between Rankine-Hugoniot inflow states, x in [-20, 20], 128
     cells, 32^3 velocities on [-8, 8]^3 shifted along v_1 to the mean of the two
@@ -418,11 +504,12 @@ def main():
                              "n32_128cells_fp64",
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
-    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order"], default="batched-q",
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
                          "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded); "
-                         "order: first/second-order accuracy study on the BGK heat slab")
+                         "order: first/second-order accuracy study on the BGK heat slab; "
+                         "cavity: 2D2V lid-driven cavity and the batched 2D collision term")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -445,6 +532,9 @@ def main():
         return
     if args.workload == "order":
         print(json.dumps(order_workload(args)), flush=True)
+        return
+    if args.workload == "cavity":
+        print(json.dumps(cavity_workload(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")

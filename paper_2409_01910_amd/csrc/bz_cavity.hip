@@ -245,8 +245,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   }
   // M[g] of the initial guess
   auto moments_of = [&](const double (&a)[kCavOwn], double (&t)[4]) {
-    double v[14];
-    for (int q = 0; q < 14; ++q) v[q] = 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < kCavOwn; ++q) {
       const double e = threadIdx.x + q * kCavThreads < K ? w * a[q] : 0.0;
@@ -255,7 +254,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
       v[2] += y[q] * e;
       v[3] += (x[q] * x[q] + y[q] * y[q]) * e;
     }
-    block_sum<14>(v, red);
+    block_sum<4>(v, red);
     for (int q = 0; q < 4; ++q) t[q] = v[q];
   };
   double th_g[4], t4[4];
@@ -295,9 +294,18 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     for (int q = 0; q < kCavOwn; ++q)
       g[q] = threadIdx.x + q * kCavThreads < K ? (lam * Mstep[q] - r[q]) / (c[q] + lam) : 0.0;
     moments_of(g, t4);
-    (void)newton4(th_g, t4, true, x, y, one, K, w, red);
-    double e2[14];
-    for (int q = 0; q < 14; ++q) e2[q] = 0.0;
+    // M[g]: Newton warm-started from the previous iterate's parameters (the
+    // converged parameters do not depend on the start); from the continuous
+    // moments when that start fails
+    {
+      double th_w[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
+      if (newton4(th_w, t4, false, x, y, one, K, w, red)) {
+        for (int a = 0; a < 4; ++a) th_g[a] = th_w[a];
+      } else {
+        (void)newton4(th_g, t4, true, x, y, one, K, w, red);
+      }
+    }
+    double e2[1] = {0.0};
 #pragma unroll
     for (int q = 0; q < kCavOwn; ++q) {
       const int k = threadIdx.x + q * kCavThreads;
@@ -307,7 +315,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
         e2[0] += e * e;
       }
     }
-    block_sum<14>(e2, red);
+    block_sum<1>(e2, red);
     res = sqrt(w * e2[0]);
     ++it;
     if (fixed <= 0 && res <= tol) break;
