@@ -329,13 +329,18 @@ def cavity_workload(args):
 
     out = {}
     L40 = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
+    want = lambda k: args.cavity_case in ("all", k)
     for eps in (1.0, 0.1, 0.01, 0.001):
         key = f"paper_40x40_eps{eps:g}"
-        out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key)
-        print(f"# {key}: {json.dumps(out[key])}", flush=True)
+        if want(key):
+            out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key)
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
     key = "n48_64x64_eps0.1"
-    out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 20, 60.0, key)
-    print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    if want(key):
+        out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 20, 60.0, key)
+        print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    if not want("batched_q_48x48"):
+        return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
     # batched corrected, mass-projected 2D collision term: 4096 cells, 48^2, M = 64, n_rho = 24
     f = torch.from_numpy(synth.mixture_batch(4096, 48, 8.0, d=2, seed=0)).cuda().contiguous()
     ctx = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2)
@@ -504,6 +509,10 @@ def main():
                              "n32_128cells_fp64",
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
+    ap.add_argument("--cavity-case", default="all",
+                    choices=["all", "paper_40x40_eps1", "paper_40x40_eps0.1", "paper_40x40_eps0.01",
+                             "paper_40x40_eps0.001", "n48_64x64_eps0.1", "batched_q_48x48"],
+                    help="with --workload cavity: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
