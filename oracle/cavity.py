@@ -105,7 +105,7 @@ def all_collision(prob: Cavity, f: np.ndarray):
     return Q, M, nu
 
 
-def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int) -> np.ndarray:
+def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = None) -> np.ndarray:
     spec = prob.spec
     v = velocity_nodes(spec)
     v1p, v1m = np.maximum(v[:, 0], 0.0), np.minimum(v[:, 0], 0.0)
@@ -117,6 +117,8 @@ def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int) -> np.ndarray:
         for j in (range(prob.ny) if sy > 0 else range(prob.ny - 1, -1, -1)):
             W, E, S, N = neighbours(prob, f, i, j)
             r = (-v1p * W + v1m * E) / prob.dx + (-v2p * S + v2m * N) / prob.dy - P[i, j] / prob.eps
+            if b is not None:
+                r -= b[i, j]
             g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, (prob.dx, prob.dy), f[i, j], mode=prob.inner,
                                   tol=prob.tol_inner, max_iter=prob.max_inner, fixed_iters=prob.fixed_inner)
             prob.stats["inner"] += st.iterations
@@ -130,10 +132,10 @@ def total_mass(prob: Cavity, f: np.ndarray) -> float:
     return float(prob.dx * prob.dy * prob.spec.w * np.sum(f))
 
 
-def sgs_iteration(prob: Cavity, f: np.ndarray) -> np.ndarray:
+def sgs_iteration(prob: Cavity, f: np.ndarray, b: np.ndarray | None = None, rescale: bool = True) -> np.ndarray:
     for sx, sy in SCANS:
-        f = scan(prob, f, sx, sy)
-    return f * (prob.mass / total_mass(prob, f))
+        f = scan(prob, f, sx, sy, b)
+    return f * (prob.mass / total_mass(prob, f)) if rescale else f
 
 
 def residual_field(prob: Cavity, f: np.ndarray, Q: np.ndarray) -> np.ndarray:
@@ -150,10 +152,78 @@ def residual_field(prob: Cavity, f: np.ndarray, Q: np.ndarray) -> np.ndarray:
     return R
 
 
-def outer_residual(prob: Cavity, f: np.ndarray) -> float:
-    Q, _, _ = all_collision(prob, f)
-    R = residual_field(prob, f, Q)
+def norm(prob: Cavity, R: np.ndarray) -> float:
+    """sqrt(dx dy sum w R^2): the L2(Omega x R^d) norm of Section 4."""
     return float(np.sqrt(prob.dx * prob.dy * prob.spec.w * np.sum(R * R)))
+
+
+def level_R(prob: Cavity, f: np.ndarray) -> np.ndarray:
+    Q, _, _ = all_collision(prob, f)
+    return residual_field(prob, f, Q)
+
+
+def outer_residual(prob: Cavity, f: np.ndarray, b: np.ndarray | None = None) -> float:
+    R = level_R(prob, f)
+    return norm(prob, R if b is None else R - b)
+
+
+# ---------------------------------------------------------------- multigrid
+# The nonlinear multigrid of eq. coarse on the 2D grid, H = 2h in both
+# directions, with the readings of the 1D oracle: restriction averages the four
+# children, prolongation injects the coarse correction piecewise constantly,
+# the coarsest level is smoothed until its residual falls 10x or coarse_iters
+# iterations pass, and a V-cycle stops descending once a level's residual is
+# below the outer tolerance.
+
+
+def coarse(prob: Cavity) -> Cavity:
+    return Cavity(**{k: getattr(prob, k) for k in prob.__dataclass_fields__ if k not in ("nx", "ny", "stats")},
+                  nx=prob.nx // 2, ny=prob.ny // 2)
+
+
+def restrict(f: np.ndarray) -> np.ndarray:
+    return 0.25 * (f[0::2, 0::2] + f[1::2, 0::2] + f[0::2, 1::2] + f[1::2, 1::2])
+
+
+def prolong(e: np.ndarray) -> np.ndarray:
+    return np.repeat(np.repeat(e, 2, axis=0), 2, axis=1)
+
+
+def vcycle(prob: Cavity, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1: int, nu2: int, tol: float,
+           coarse_iters: int = 20) -> np.ndarray:
+    """One FAS V-cycle for R_h(f) = b (eq. coarse); levels halve nx and ny until
+    min(nx, ny) <= coarsest."""
+    if b is None:
+        b = np.zeros_like(f)
+    for _ in range(nu1):
+        f = sgs_iteration(prob, f, b, rescale=False)
+    if min(prob.nx, prob.ny) <= coarsest:
+        r0 = norm(prob, b - level_R(prob, f))
+        for _ in range(coarse_iters):
+            if norm(prob, b - level_R(prob, f)) <= 0.1 * r0:
+                break
+            f = sgs_iteration(prob, f, b, rescale=False)
+        return f
+    res = b - level_R(prob, f)
+    if norm(prob, res) < tol:
+        return f
+    cp = coarse(prob)
+    fc0 = restrict(f)
+    bc = level_R(cp, fc0) + restrict(res)
+    fc = vcycle(cp, fc0.copy(), bc, coarsest, nu1, nu2, tol, coarse_iters)
+    for k in ("inner", "visits", "fallback"):
+        prob.stats[k] += cp.stats[k]
+    f = f + prolong(fc - fc0)
+    for _ in range(nu2):
+        f = sgs_iteration(prob, f, b, rescale=False)
+    return f
+
+
+def mg_iteration(prob: Cavity, f: np.ndarray, coarsest: int = 4, nu1: int = 1, nu2: int = 1,
+                 tol: float = 1e-5) -> np.ndarray:
+    """One V-cycle followed by the mass rescale (MG-SGS-PFP)."""
+    f = vcycle(prob, f, None, coarsest, nu1, nu2, tol)
+    return f * (prob.mass / total_mass(prob, f))
 
 
 def initial_state(prob: Cavity, rho: float = 1.0, T: float = 1.0) -> np.ndarray:

@@ -60,3 +60,22 @@ def test_hot_wall_and_lid_direction():
     U1 = np.array([[m[1][0] for m in row] for row in mac])
     assert (T[-1, :] > T[0, :]).all()
     assert (U1[:, -1] > 0).all() and (U1[:, 0] < 0).all()
+
+
+def test_converged_state_is_a_fixed_point_of_the_vcycle():
+    # FAS consistency (eq. coarse): at a converged fine state the coarse problem
+    # R_H(f_H) = R_H(restrict f) + restrict(b - R_h f) is solved by restrict f
+    # itself, so a V-cycle forced to descend (tol = 0) changes nothing beyond the
+    # residual it starts from; a wrong coarse right-hand side would move f
+    N = 8
+    sp = Spec(d=2, N=N, L=4.0, n_phi=8, n_rho=4)
+    walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.5, 0.0)))
+    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk")
+    f = _converge(prob, tol=1e-12)
+    g = CV.vcycle(prob, f.copy(), None, coarsest=2, nu1=0, nu2=0, tol=0.0)
+    assert np.abs(g - f).max() < 1e-9 * f.max()
+    # and from a perturbed state the V-cycle reduces the residual
+    f1 = CV.sgs_iteration(prob, CV.initial_state(prob))
+    r1 = CV.outer_residual(prob, f1)
+    f2 = CV.mg_iteration(prob, f1, coarsest=2)
+    assert CV.outer_residual(prob, f2) < 0.5 * r1
