@@ -402,6 +402,20 @@ typedef struct {
 bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int n_cycles,
                               double* residual_out, bz_sweep_stats* stats, void* stream);
 
+/* bz_cavity_vcycle: n_cycles nonlinear multigrid V-cycles (eq. coarse) on a
+ * 2D cavity, with H = 2h in both directions.  Each level runs nu1 pre- and nu2
+ * post-smoothing SGS iterations (four scans each) with its FAS source.
+ * Restriction averages the four children; prolongation adds the coarse
+ * correction to each child.  Levels halve nx and ny until min(nx, ny) <=
+ * coarsest, so nx and ny must halve evenly down to there.  That level is
+ * smoothed until its residual falls 10x or coarse_iters iterations pass.  A
+ * cycle stops descending once a level's residual is below tol, and the mass
+ * rescale follows each cycle.  Coarse levels are allocated on the first call.
+ * residual_out (host, nullable) receives the outer residual after the last
+ * cycle. */
+bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cav, const bz_mg_opts* opts, int n_cycles, double* residual_out,
+                           bz_sweep_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- graph replay
  * For callers that run many SGS iterations and want one host synchronisation
  * per segment instead of one per iteration (launch-bound small slabs, serving

@@ -35,7 +35,7 @@ EXPORTED = [
     "bz_mlp_set_output_scale", "bz_mlp_forward", "bz_mlp_grad", "bz_mlp_train_step", "bz_mlp_features",
     "bz_cell_fixed_point_learned",
     "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
-    "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual",
+    "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
 ]
 
 
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_cavity_destroy.restype = None
     lib.bz_cavity_sweep.argtypes = [P, P, ctypes.c_int, P, ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_cavity_residual.argtypes = [P, P, P, P]
+    lib.bz_cavity_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
+                                     ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_outer_residual.argtypes = [P, P, P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
@@ -451,6 +453,16 @@ class Cavity:
                                                      ctypes.byref(res) if residual else None, ctypes.byref(st),
                                                      _stream()), "bz_cavity_sweep")
         return (res.value if residual else None), Slab._stats(st)
+
+    def vcycle(self, n_cycles: int = 1, coarsest: int = 4, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
+               tol: float = 1e-5):
+        """n_cycles FAS V-cycles (each followed by the mass rescale); returns (residual, stats)."""
+        o = bz_mg_opts(coarsest, nu1, nu2, coarse_iters, tol)
+        res = ctypes.c_double(0.0)
+        st = bz_sweep_stats()
+        self.ctx._check(self.ctx.lib.bz_cavity_vcycle(self.ctx.h, self.h, ctypes.byref(o), n_cycles, ctypes.byref(res),
+                                                      ctypes.byref(st), _stream()), "bz_cavity_vcycle")
+        return res.value, Slab._stats(st)
 
     def residual(self) -> float:
         res = ctypes.c_double(0.0)

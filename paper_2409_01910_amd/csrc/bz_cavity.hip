@@ -19,24 +19,36 @@
 // step 1's weighted Newton and the discrete Maxwellian are 4-parameter Newton
 // solves whose sums run over the cell's N^2 points in the workgroup.
 #include <cmath>
+#include <vector>
 
 #include "bz_common.hpp"
 #include "bz_internal.hpp"
 
+// One grid level: level 0 works on the caller's field; coarser levels (nx and
+// ny halved each time) own theirs, with the FAS source b and the restricted
+// copy f0 of eq. coarse.
+struct CavLevel {
+  int nx = 0, ny = 0, ncell = 0;
+  double dx = 0, dy = 0;
+  double* f = nullptr;
+  double* b = nullptr;        // [ncell][K] FAS source (null on level 0)
+  double* f0 = nullptr;       // [ncell][K] restricted fine state (coarse levels)
+  double* res = nullptr;      // [ncell][K] b - R(f)
+  double* Q = nullptr;        // [ncell][K]
+  double* rs = nullptr;       // [ncell][K] -P / eps - b
+  double* theta = nullptr;    // [ncell][4]
+  double* nu = nullptr;       // [ncell]
+  double* part = nullptr;     // [ncell + 1] per-cell partial sums and their total
+};
+
 struct bz_cavity {
   bz_ctx* ctx = nullptr;
-  int nx = 0, ny = 0, ncell = 0;
-  double eps = 0, dx = 0, dy = 0, mass = 0;
+  double eps = 0, mass = 0;
   bz_wall walls[4]{};
   int collision = 0;
   double bgk_nu = 0;
   bz_solve_opts opts{};
-  double* f = nullptr;
-  double* d_Q = nullptr;      // [ncell][K]
-  double* d_rs = nullptr;     // [ncell][K] -P / eps
-  double* d_theta = nullptr;  // [ncell][4]
-  double* d_nu = nullptr;     // [ncell]
-  double* d_part = nullptr;   // [ncell] per-cell partial sums
+  std::vector<CavLevel> lv;
   unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
 };
 
@@ -335,9 +347,11 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   }
 }
 
-// rs = -(Q - nu (M_theta - f)) / eps (binary) or 0 (BGK), and nu, per cell
+// rs = -(Q - nu (M_theta - f)) / eps (binary) or 0 (BGK), minus the FAS source b
+// when given, and nu, per cell
 __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __restrict__ f, const double* __restrict__ Q,
-                                                            const double* __restrict__ theta, double* __restrict__ rs,
+                                                            const double* __restrict__ theta,
+                                                            const double* __restrict__ b, double* __restrict__ rs,
                                                             double* __restrict__ nu, const double* __restrict__ nodes,
                                                             int N, double w, double eps, int bgk, double bgk_nu,
                                                             double gam, double gfac) {
@@ -358,21 +372,23 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __rest
   }
   if (threadIdx.x == 0) nu[cell] = nv;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    if (bgk) {
-      rs[cell * K + k] = 0.0;
-    } else {
+    double v0 = 0.0;
+    if (!bgk) {
       const double M = gauss2c(theta + cell * 4, nodes[k / N], nodes[k % N]);
-      rs[cell * K + k] = -((Q[cell * K + k] - nv * (M - fc[k])) / eps);
+      v0 = -((Q[cell * K + k] - nv * (M - fc[k])) / eps);
     }
+    rs[cell * K + k] = b ? v0 - b[cell * K + k] : v0;
   }
 }
 
-// per-cell sum of w R^2 with R = v.grad f - Q/eps (BGK: Q = nu (M - f))
+// per-cell sum of w (b - R)^2 with R = v.grad f - Q/eps (BGK: Q = nu (M - f)), b the FAS
+// source (0 when null); the field b - R into res when non-null
 __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restrict__ f, const double* __restrict__ Q,
                                                            const double* __restrict__ theta, int nx, int ny,
                                                            double dx, double dy, double eps, CavWalls wl,
                                                            const double* __restrict__ nodes, int N, double w, int bgk,
-                                                           double bgk_nu, double* __restrict__ part) {
+                                                           double bgk_nu, const double* __restrict__ b,
+                                                           double* __restrict__ res, double* __restrict__ part) {
   __shared__ double red[8 * (kCavThreads / 64)];
   const int K = N * N;
   const int cell = blockIdx.x, i = cell / ny, j = cell - i * ny;
@@ -400,7 +416,9 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restr
     const double q = bgk ? nv * (gauss2c(theta + (size_t)cell * 4, x, y) - fv) : Q[(size_t)cell * K + k];
     const double R = (fmax(x, 0.0) * (fv - W) + fmin(x, 0.0) * (E - fv)) / dx +
                      (fmax(y, 0.0) * (fv - S) + fmin(y, 0.0) * (Nn - fv)) / dy - q / eps;
-    acc[0] += R * R;
+    const double rb = (b ? b[(size_t)cell * K + k] : 0.0) - R;  // b - R(f)
+    if (res) res[(size_t)cell * K + k] = rb;
+    acc[0] += rb * rb;
   }
   block_sum<1>(acc, red);
   if (threadIdx.x == 0) part[cell] = w * acc[0];
@@ -437,6 +455,45 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_total(const double* __restr
   if (threadIdx.x == 0) out[0] = v[0];
 }
 
+__global__ void __launch_bounds__(kCavThreads) k_cav_negate(double* __restrict__ a, int K) {
+  double* o = a + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] = -o[k];
+}
+
+// coarse cell (I, J) <- average of its four children
+__global__ void __launch_bounds__(kCavThreads) k_cav_restrict(const double* __restrict__ fine, int nyf,
+                                                              double* __restrict__ coarse, int nyc, int K) {
+  const int I = blockIdx.x / nyc, J = blockIdx.x - (blockIdx.x / nyc) * nyc;
+  const double* a = fine + ((size_t)(2 * I) * nyf + 2 * J) * K;
+  const double* b = fine + ((size_t)(2 * I + 1) * nyf + 2 * J) * K;
+  const double* c = fine + ((size_t)(2 * I) * nyf + 2 * J + 1) * K;
+  const double* d = fine + ((size_t)(2 * I + 1) * nyf + 2 * J + 1) * K;
+  double* o = coarse + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] = 0.25 * (a[k] + b[k] + c[k] + d[k]);
+}
+
+// bc <- bc + restrict(res): bc holds R_H(f0) on entry (eq. coarse)
+__global__ void __launch_bounds__(kCavThreads) k_cav_fas_rhs(double* __restrict__ bc, int nyc,
+                                                             const double* __restrict__ res, int nyf, int K) {
+  const int I = blockIdx.x / nyc, J = blockIdx.x - (blockIdx.x / nyc) * nyc;
+  const double* a = res + ((size_t)(2 * I) * nyf + 2 * J) * K;
+  const double* b = res + ((size_t)(2 * I + 1) * nyf + 2 * J) * K;
+  const double* c = res + ((size_t)(2 * I) * nyf + 2 * J + 1) * K;
+  const double* d = res + ((size_t)(2 * I + 1) * nyf + 2 * J + 1) * K;
+  double* o = bc + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] += 0.25 * (a[k] + b[k] + c[k] + d[k]);
+}
+
+// fine cell (i, j) += fc - fc0 of its parent (piecewise-constant prolongation)
+__global__ void __launch_bounds__(kCavThreads) k_cav_prolong_add(double* __restrict__ fine, int nyf,
+                                                                 const double* __restrict__ fc,
+                                                                 const double* __restrict__ fc0, int nyc, int K) {
+  const int i = blockIdx.x / nyf, j = blockIdx.x - (blockIdx.x / nyf) * nyf;
+  const size_t p = ((size_t)(i / 2) * nyc + j / 2) * K;
+  double* o = fine + (size_t)blockIdx.x * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] += fc[p + k] - fc0[p + k];
+}
+
 CavWalls walls_of(const bz_cavity* cv) {
   CavWalls wl{};
   for (int s = 0; s < 4; ++s) {
@@ -447,35 +504,161 @@ CavWalls walls_of(const bz_cavity* cv) {
   return wl;
 }
 
-// collision split of every cell: theta, nu and rs = -P / eps
-bz_status cav_static(bz_ctx* ctx, bz_cavity* cv, hipStream_t st) {
+bz_status alloc_level(bz_ctx* ctx, CavLevel& L, bool own) {
+  const size_t K = ctx->K, nc = L.ncell;
+  bool ok = hipMalloc((void**)&L.Q, nc * K * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&L.rs, nc * K * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&L.theta, nc * 4 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&L.nu, nc * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&L.part, (nc + 1) * sizeof(double)) == hipSuccess;
+  if (ok && own)
+    ok = hipMalloc((void**)&L.f, nc * K * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&L.b, nc * K * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&L.f0, nc * K * sizeof(double)) == hipSuccess;
+  return ok ? BZ_OK : set_err(ctx, BZ_ENOMEM, "cavity workspace");
+}
+
+void free_level(CavLevel& L, bool own) {
+  void* ptrs[] = {L.Q, L.rs, L.theta, L.nu, L.part, L.res, own ? L.f : nullptr, L.b, L.f0};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  L = CavLevel{};
+}
+
+// collision split of every cell of a level: theta, nu and rs = -P/eps - b
+bz_status cav_static(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   const bool bgk = cv->collision == BZ_COLL_BGK;
   if (!bgk) {
-    bz_status s = v2_eval_q(ctx, cv->f, cv->d_Q, cv->ncell, true, true, cv->d_theta, st);
+    bz_status s = v2_eval_q(ctx, L.f, L.Q, L.ncell, true, true, L.theta, st);
     if (s != BZ_OK) return s;
   }
-  hipLaunchKernelGGL(k_cav_static, dim3(cv->ncell), dim3(kCavThreads), 0, st, cv->f, cv->d_Q, cv->d_theta, cv->d_rs,
-                     cv->d_nu, ctx->d_nodes, ctx->N, ctx->w, cv->eps, bgk ? 1 : 0, cv->bgk_nu, ctx->p.gamma,
-                     ctx->nu_gfac);
+  hipLaunchKernelGGL(k_cav_static, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.b, L.rs, L.nu,
+                     ctx->d_nodes, ctx->N, ctx->w, cv->eps, bgk ? 1 : 0, cv->bgk_nu, ctx->p.gamma, ctx->nu_gfac);
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
 
-bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, double* out, hipStream_t st) {
+// ||b - R(f)|| of a level (host value; synchronises), the field b - R(f) into res
+// when non-null
+bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, double* out, hipStream_t st) {
   const bool bgk = cv->collision == BZ_COLL_BGK;
-  bz_status s = bgk ? v2_maxwellian(ctx, cv->f, cv->d_theta, nullptr, nullptr, cv->ncell, st)
-                    : v2_eval_q(ctx, cv->f, cv->d_Q, cv->ncell, true, true, cv->d_theta, st);
+  bz_status s = bgk ? v2_maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st)
+                    : v2_eval_q(ctx, L.f, L.Q, L.ncell, true, true, L.theta, st);
   if (s != BZ_OK) return s;
-  hipLaunchKernelGGL(k_cav_resid, dim3(cv->ncell), dim3(kCavThreads), 0, st, cv->f, cv->d_Q, cv->d_theta, cv->nx,
-                     cv->ny, cv->dx, cv->dy, cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0,
-                     cv->bgk_nu, cv->d_part);
+  hipLaunchKernelGGL(k_cav_resid, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.nx, L.ny, L.dx, L.dy,
+                     cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0, cv->bgk_nu, L.b, res, L.part);
   BZ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cav_total, dim3(1), dim3(kCavThreads), 0, st, cv->d_part, cv->ncell, cv->d_part + cv->ncell);
+  hipLaunchKernelGGL(k_cav_total, dim3(1), dim3(kCavThreads), 0, st, L.part, L.ncell, L.part + L.ncell);
   BZ_HIP(hipGetLastError());
   double tot = 0.0;
-  BZ_HIP(hipMemcpyAsync(&tot, cv->d_part + cv->ncell, sizeof(double), hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipMemcpyAsync(&tot, L.part + L.ncell, sizeof(double), hipMemcpyDeviceToHost, st));
   BZ_HIP(hipStreamSynchronize(st));
-  *out = std::sqrt(cv->dx * cv->dy * tot);
+  *out = std::sqrt(L.dx * L.dy * tot);
+  return BZ_OK;
+}
+
+// one SGS iteration of a level (four scans, FAS source b when the level has one), no rescale
+bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
+  static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+  const CavWalls wl = walls_of(cv);
+  for (int sc = 0; sc < 4; ++sc) {
+    bz_status s = cav_static(ctx, cv, L, st);
+    if (s != BZ_OK) return s;
+    for (int dd = 0; dd <= L.nx + L.ny - 2; ++dd) {
+      const int lo = dd - (L.ny - 1) > 0 ? dd - (L.ny - 1) : 0;
+      const int hi = dd < L.nx - 1 ? dd : L.nx - 1;
+      hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.nx, L.ny, dd,
+                         scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
+                         cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters, cv->d_stats);
+      BZ_HIP(hipGetLastError());
+    }
+  }
+  return BZ_OK;
+}
+
+bz_status cav_rescale(bz_ctx* ctx, bz_cavity* cv, hipStream_t st) {
+  CavLevel& L = cv->lv[0];
+  hipLaunchKernelGGL(k_cav_cellsum, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, ctx->K, L.part);
+  BZ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cav_rescale, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, ctx->K, L.ncell, L.part,
+                     L.dx * L.dy * ctx->w, cv->mass);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// FAS V-cycle on level l for R(f) = b (eq. coarse); levels halve nx and ny
+// until min(nx, ny) <= coarsest
+bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, hipStream_t st) {
+  CavLevel& L = cv->lv[l];
+  const int K = ctx->K;
+  bz_status s;
+  for (int q = 0; q < o.nu1; ++q)
+    if ((s = cav_sgs(ctx, cv, L, st)) != BZ_OK) return s;
+  double r = 0.0;
+  if ((L.nx < L.ny ? L.nx : L.ny) <= o.coarsest) {
+    double r0 = 0.0;
+    if ((s = cav_residual(ctx, cv, L, nullptr, &r0, st)) != BZ_OK) return s;
+    for (int q = 0; q < o.coarse_iters; ++q) {
+      if ((s = cav_residual(ctx, cv, L, nullptr, &r, st)) != BZ_OK) return s;
+      if (r <= 0.1 * r0) break;
+      if ((s = cav_sgs(ctx, cv, L, st)) != BZ_OK) return s;
+    }
+    return BZ_OK;
+  }
+  if (!L.res && hipMalloc((void**)&L.res, (size_t)L.ncell * K * sizeof(double)) != hipSuccess)
+    return set_err(ctx, BZ_ENOMEM, "cavity residual field");
+  if ((s = cav_residual(ctx, cv, L, L.res, &r, st)) != BZ_OK) return s;
+  if (r < o.tol) return BZ_OK;
+  if (l + 1 >= cv->lv.size()) {
+    CavLevel C;
+    C.nx = L.nx / 2;
+    C.ny = L.ny / 2;
+    C.ncell = C.nx * C.ny;
+    C.dx = 1.0 / C.nx;
+    C.dy = 1.0 / C.ny;
+    if ((s = alloc_level(ctx, C, true)) != BZ_OK) {
+      free_level(C, true);
+      return s;
+    }
+    cv->lv.push_back(C);
+  }
+  CavLevel& Lf = cv->lv[l];  // the vector may have moved
+  CavLevel& C = cv->lv[l + 1];
+  hipLaunchKernelGGL(k_cav_restrict, dim3(C.ncell), dim3(kCavThreads), 0, st, Lf.f, Lf.ny, C.f0, C.ny, K);
+  BZ_HIP(hipGetLastError());
+  BZ_HIP(hipMemcpyAsync(C.f, C.f0, (size_t)C.ncell * K * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // b_H = R_H(f0) + restrict(b - R_h(f)): the residual field of f0 with no source, negated
+  double* bsave = C.b;
+  C.b = nullptr;
+  double dummy = 0.0;
+  s = cav_residual(ctx, cv, C, bsave, &dummy, st);  // bsave <- 0 - R_H(f0)
+  C.b = bsave;
+  if (s != BZ_OK) return s;
+  hipLaunchKernelGGL(k_cav_negate, dim3(C.ncell), dim3(kCavThreads), 0, st, C.b, K);
+  BZ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cav_fas_rhs, dim3(C.ncell), dim3(kCavThreads), 0, st, C.b, C.ny, Lf.res, Lf.ny, K);
+  BZ_HIP(hipGetLastError());
+  if ((s = cav_vcycle(ctx, cv, l + 1, o, st)) != BZ_OK) return s;
+  CavLevel& Lf2 = cv->lv[l];
+  CavLevel& C2 = cv->lv[l + 1];
+  hipLaunchKernelGGL(k_cav_prolong_add, dim3(Lf2.ncell), dim3(kCavThreads), 0, st, Lf2.f, Lf2.ny, C2.f, C2.f0, C2.ny,
+                     K);
+  BZ_HIP(hipGetLastError());
+  for (int q = 0; q < o.nu2; ++q)
+    if ((s = cav_sgs(ctx, cv, cv->lv[l], st)) != BZ_OK) return s;
+  return BZ_OK;
+}
+
+bz_status read_stats(bz_ctx* ctx, bz_cavity* cv, bz_sweep_stats* stats, int n, hipStream_t st) {
+  unsigned long long h[3] = {0, 0, 0};
+  BZ_HIP(hipMemcpyAsync(h, cv->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
+  BZ_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    stats->n_iters = n;
+    stats->inner_iters = (int64_t)h[0];
+    stats->visits = (int64_t)h[1];
+    stats->fallbacks = (int64_t)h[2];
+  }
   return BZ_OK;
 }
 
@@ -512,28 +695,26 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   bz_cavity* cv = new bz_cavity();
   cv->ctx = ctx;
-  cv->nx = d->nx;
-  cv->ny = d->ny;
-  cv->ncell = d->nx * d->ny;
   cv->eps = d->eps;
-  cv->dx = 1.0 / d->nx;
-  cv->dy = 1.0 / d->ny;
   cv->mass = d->mass;
   for (int s = 0; s < 4; ++s) cv->walls[s] = d->walls[s];
   cv->collision = d->collision;
   cv->bgk_nu = d->bgk_nu;
   cv->opts = o;
-  cv->f = d->f;
-  const size_t K = ctx->K, nc = cv->ncell;
-  bool ok = hipMalloc((void**)&cv->d_Q, nc * K * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&cv->d_rs, nc * K * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&cv->d_theta, nc * 4 * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&cv->d_nu, nc * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&cv->d_part, (nc + 1) * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&cv->d_stats, 3 * sizeof(unsigned long long)) == hipSuccess;
-  if (!ok) {
+  CavLevel L0;
+  L0.nx = d->nx;
+  L0.ny = d->ny;
+  L0.ncell = d->nx * d->ny;
+  L0.dx = 1.0 / d->nx;
+  L0.dy = 1.0 / d->ny;
+  L0.f = d->f;
+  bz_status s = bz::alloc_level(ctx, L0, false);
+  cv->lv.push_back(L0);
+  if (s == BZ_OK && hipMalloc((void**)&cv->d_stats, 3 * sizeof(unsigned long long)) != hipSuccess)
+    s = set_err(ctx, BZ_ENOMEM, "cavity statistics");
+  if (s != BZ_OK) {
     bz_cavity_destroy(cv);
-    return set_err(ctx, BZ_ENOMEM, "cavity workspace");
+    return s;
   }
   *out = cv;
   return BZ_OK;
@@ -542,9 +723,8 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
 void bz_cavity_destroy(bz_cavity* cv) {
   if (!cv) return;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {cv->d_Q, cv->d_rs, cv->d_theta, cv->d_nu, cv->d_part, cv->d_stats};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+  for (size_t l = 0; l < cv->lv.size(); ++l) bz::free_level(cv->lv[l], l > 0);
+  if (cv->d_stats) (void)hipFree(cv->d_stats);
   delete cv;
 }
 
@@ -555,48 +735,50 @@ bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cv, int n_iters, double* resid
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 3 * sizeof(unsigned long long), st));
-  const bz::CavWalls wl = bz::walls_of(cv);
-  static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
   for (int it = 0; it < n_iters; ++it) {
-    for (int sc = 0; sc < 4; ++sc) {
-      bz_status s = bz::cav_static(ctx, cv, st);
-      if (s != BZ_OK) return s;
-      for (int dd = 0; dd <= cv->nx + cv->ny - 2; ++dd) {
-        const int lo = dd - (cv->ny - 1) > 0 ? dd - (cv->ny - 1) : 0;
-        const int hi = dd < cv->nx - 1 ? dd : cv->nx - 1;
-        hipLaunchKernelGGL(bz::k_cav_visit, dim3(hi - lo + 1), dim3(bz::kCavThreads), 0, st, cv->f, cv->d_rs,
-                           cv->d_nu, cv->nx, cv->ny, dd, scans[sc][0], scans[sc][1], cv->dx, cv->dy, cv->eps, wl,
-                           ctx->d_nodes, ctx->N, ctx->w, cv->opts.mode, cv->opts.tol, cv->opts.max_iter,
-                           cv->opts.fixed_iters, cv->d_stats);
-        BZ_HIP(hipGetLastError());
-      }
-    }
-    hipLaunchKernelGGL(bz::k_cav_cellsum, dim3(cv->ncell), dim3(bz::kCavThreads), 0, st, cv->f, ctx->K, cv->d_part);
-    BZ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bz::k_cav_rescale, dim3(cv->ncell), dim3(bz::kCavThreads), 0, st, cv->f, ctx->K, cv->ncell,
-                       cv->d_part, cv->dx * cv->dy * ctx->w, cv->mass);
-    BZ_HIP(hipGetLastError());
-  }
-  if (residual_out) {
-    bz_status s = bz::cav_residual(ctx, cv, residual_out, st);
+    bz_status s = bz::cav_sgs(ctx, cv, cv->lv[0], st);
+    if (s == BZ_OK) s = bz::cav_rescale(ctx, cv, st);
     if (s != BZ_OK) return s;
   }
-  unsigned long long h[3] = {0, 0, 0};
-  BZ_HIP(hipMemcpyAsync(h, cv->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
-  BZ_HIP(hipStreamSynchronize(st));
-  if (stats) {
-    stats->n_iters = n_iters;
-    stats->inner_iters = (int64_t)h[0];
-    stats->visits = (int64_t)h[1];
-    stats->fallbacks = (int64_t)h[2];
+  if (residual_out) {
+    bz_status s = bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, st);
+    if (s != BZ_OK) return s;
   }
-  return BZ_OK;
+  return bz::read_stats(ctx, cv, stats, n_iters, st);
+}
+
+bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int n_cycles, double* residual_out,
+                           bz_sweep_stats* stats, void* stream) {
+  if (!ctx || !cv || cv->ctx != ctx || !o) return BZ_EINVAL;
+  if (n_cycles < 0 || o->coarsest < 1 || o->nu1 < 0 || o->nu2 < 0 || o->coarse_iters < 0 || !(o->tol >= 0))
+    return set_err(ctx, BZ_EINVAL, "bad multigrid options");
+  {
+    int nx = cv->lv[0].nx, ny = cv->lv[0].ny;
+    while ((nx < ny ? nx : ny) > o->coarsest) {
+      if (nx % 2 || ny % 2) return set_err(ctx, BZ_EINVAL, "nx and ny must halve evenly down to the coarsest level");
+      nx /= 2;
+      ny /= 2;
+    }
+  }
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 3 * sizeof(unsigned long long), st));
+  for (int c = 0; c < n_cycles; ++c) {
+    bz_status s = bz::cav_vcycle(ctx, cv, 0, *o, st);
+    if (s == BZ_OK) s = bz::cav_rescale(ctx, cv, st);
+    if (s != BZ_OK) return s;
+  }
+  if (residual_out) {
+    bz_status s = bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, st);
+    if (s != BZ_OK) return s;
+  }
+  return bz::read_stats(ctx, cv, stats, n_cycles, st);
 }
 
 bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cv, double* residual_out, void* stream) {
   if (!ctx || !cv || cv->ctx != ctx || !residual_out) return BZ_EINVAL;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
-  return bz::cav_residual(ctx, cv, residual_out, (hipStream_t)stream);
+  return bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, (hipStream_t)stream);
 }
 
 }  // extern "C"

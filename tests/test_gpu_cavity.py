@@ -94,3 +94,46 @@ def test_cavity_rejects_bad_arguments(bz):
     f3 = torch.zeros((4, 512), dtype=torch.float64, device="cuda:0")
     with pytest.raises(bz.BZError):
         bz.Cavity(ctx3, 2, 2, 0.1, ((1.0, (0.0, 0.0)),) * 4, f3)
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_cavity_vcycle_matches_oracle(bz, collision):
+    # one FAS V-cycle forced to descend (tol = 0) on a 4 x 8 grid: levels 4 x 8 and
+    # 2 x 4 (coarsest 2), one pre- and one post-smoothing iteration, at most 3
+    # coarsest iterations, then the mass rescale
+    nx, ny = 4, 8
+    print(f"cavity V-cycle {collision} {nx}x{ny}", flush=True)
+    prob, f0, ctx, cav, fg = _setup(bz, 8, 4.0, nx, ny, collision, fixed=2)
+    res, st = cav.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
+    f = CV.vcycle(prob, f0.copy(), None, coarsest=2, nu1=1, nu2=1, tol=0.0, coarse_iters=3)
+    f = f * (prob.mass / CV.total_mass(prob, f))
+    got = fg.cpu().numpy().reshape(nx, ny, -1)
+    err = np.abs(got - f).max() / f.max()
+    ref = CV.outer_residual(prob, f)
+    print(f"max rel diff {err:.3e}, residual {res:.6e} vs {ref:.6e}, visits {st['visits']}", flush=True)
+    assert err < 1e-10
+    assert abs(res - ref) < 1e-9 * ref
+    assert st["visits"] == prob.stats["visits"]
+
+
+def test_cavity_vcycles_reach_the_sgs_state(bz):
+    # MG-SGS-PFP and plain SGS-PFP converge to the same steady state
+    nx = 8
+    _, f0, ctx, cav, fg = _setup(bz, 8, 4.0, nx, nx, "binary", fixed=None)
+    f1 = torch.from_numpy(f0.reshape(nx * nx, -1).copy()).to("cuda:0").contiguous()
+    import paper_2409_01910_amd as bzm
+
+    cav_sgs = bzm.Cavity(ctx, nx, nx, 0.1, LID, f1)
+    for _ in range(40):
+        r_mg, _ = cav.vcycle(1, coarsest=2, tol=1e-10)
+        if r_mg < 1e-9:
+            break
+    for _ in range(80):
+        r_sgs, _ = cav_sgs.sweep(1)
+        if r_sgs < 1e-9:
+            break
+    print(f"residuals: MG {r_mg:.2e}, SGS {r_sgs:.2e}", flush=True)
+    assert r_mg < 1e-9 and r_sgs < 1e-9
+    assert (fg - f1).abs().max().item() < 1e-7 * f1.abs().max().item()
+    with pytest.raises(bzm.BZError):  # 8 -> 4 -> 2 -> 1 would have to halve 1
+        cav.vcycle(1, coarsest=0)
