@@ -19,6 +19,14 @@ on the incoming half-space, with rho_w from the discrete zero-mass-flux balance
 against the adjacent cell's latest value; the total mass is restored by a
 uniform rescale after each full iteration; the outer residual is the L2(Omega x
 R^d) norm sqrt(dx dy sum w R^2).
+
+Second order (order = 2) applies the linear reconstruction of eqs.
+reconstruction and slope along each axis: slopes s^x, s^y centred inside and
+one-sided at the first and last cell of each line, zero in the ghosts, taken
+from the iterate before each scan.  The face values f -+ s/2 enter the fluxes,
+so a visit's right-hand side gains the static terms
+  -(v1+ s^x_{i-1} - v1 s^x_i + v1- s^x_{i+1}) / (2 dx) - (same along y) / (2 dy),
+and a wall's density balances the outgoing flux of the adjacent face value.
 """
 from __future__ import annotations
 
@@ -49,6 +57,7 @@ class Cavity:
     tol_inner: float = 1e-8
     max_inner: int = 100
     fixed_inner: int | None = None
+    order: int = 1
     stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0})
 
     @property
@@ -77,12 +86,30 @@ def ghost(prob: Cavity, side: int, f_adj: np.ndarray) -> np.ndarray:
     return rho_w * Mw
 
 
-def neighbours(prob: Cavity, f: np.ndarray, i: int, j: int):
-    """(west, east, south, north) values for cell (i, j): cells or wall ghosts."""
-    W = f[i - 1, j] if i > 0 else ghost(prob, 0, f[i, j])
-    E = f[i + 1, j] if i < prob.nx - 1 else ghost(prob, 1, f[i, j])
-    S = f[i, j - 1] if j > 0 else ghost(prob, 2, f[i, j])
-    N = f[i, j + 1] if j < prob.ny - 1 else ghost(prob, 3, f[i, j])
+def slopes(prob: Cavity, f: np.ndarray):
+    """(s^x, s^y) of eq. slope along each axis: centred inside, one-sided at the
+    ends of each line; zeros at first order."""
+    sx, sy = np.zeros_like(f), np.zeros_like(f)
+    if prob.order == 1:
+        return sx, sy
+    if prob.nx > 1:
+        sx[0], sx[-1] = f[1] - f[0], f[-1] - f[-2]
+        sx[1:-1] = 0.5 * (f[2:] - f[:-2])
+    if prob.ny > 1:
+        sy[:, 0], sy[:, -1] = f[:, 1] - f[:, 0], f[:, -1] - f[:, -2]
+        sy[:, 1:-1] = 0.5 * (f[:, 2:] - f[:, :-2])
+    return sx, sy
+
+
+def neighbours(prob: Cavity, f: np.ndarray, i: int, j: int, sx=None, sy=None):
+    """(west, east, south, north) values for cell (i, j): cells or wall ghosts;
+    a wall balances the flux of the adjacent face value f -+ s/2."""
+    hx = 0.0 if sx is None else 0.5 * sx[i, j]
+    hy = 0.0 if sy is None else 0.5 * sy[i, j]
+    W = f[i - 1, j] if i > 0 else ghost(prob, 0, f[i, j] - hx)
+    E = f[i + 1, j] if i < prob.nx - 1 else ghost(prob, 1, f[i, j] + hx)
+    S = f[i, j - 1] if j > 0 else ghost(prob, 2, f[i, j] - hy)
+    N = f[i, j + 1] if j < prob.ny - 1 else ghost(prob, 3, f[i, j] + hy)
     return W, E, S, N
 
 
@@ -112,11 +139,21 @@ def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = N
     v2p, v2m = np.maximum(v[:, 1], 0.0), np.minimum(v[:, 1], 0.0)
     Q, M, nu = all_collision(prob, f)
     P = Q - nu[:, :, None] * (M - f)
+    slx, sly = slopes(prob, f)
+    zero = np.zeros(spec.K)
     f = f.copy()
     for i in (range(prob.nx) if sx > 0 else range(prob.nx - 1, -1, -1)):
         for j in (range(prob.ny) if sy > 0 else range(prob.ny - 1, -1, -1)):
-            W, E, S, N = neighbours(prob, f, i, j)
-            r = (-v1p * W + v1m * E) / prob.dx + (-v2p * S + v2m * N) / prob.dy - P[i, j] / prob.eps
+            W, E, S, N = neighbours(prob, f, i, j, slx, sly)
+            r = (-v1p * W + v1m * E) / prob.dx + (-v2p * S + v2m * N) / prob.dy
+            if prob.order == 2:
+                xw = slx[i - 1, j] if i > 0 else zero
+                xe = slx[i + 1, j] if i < prob.nx - 1 else zero
+                ys = sly[i, j - 1] if j > 0 else zero
+                yn = sly[i, j + 1] if j < prob.ny - 1 else zero
+                r -= (v1p * xw - v[:, 0] * slx[i, j] + v1m * xe) / (2.0 * prob.dx)
+                r -= (v2p * ys - v[:, 1] * sly[i, j] + v2m * yn) / (2.0 * prob.dy)
+            r -= P[i, j] / prob.eps
             if b is not None:
                 r -= b[i, j]
             g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, (prob.dx, prob.dy), f[i, j], mode=prob.inner,
@@ -142,13 +179,21 @@ def residual_field(prob: Cavity, f: np.ndarray, Q: np.ndarray) -> np.ndarray:
     v = velocity_nodes(prob.spec)
     v1p, v1m = np.maximum(v[:, 0], 0.0), np.minimum(v[:, 0], 0.0)
     v2p, v2m = np.maximum(v[:, 1], 0.0), np.minimum(v[:, 1], 0.0)
+    sx, sy = slopes(prob, f)
     R = np.empty_like(f)
     for i in range(prob.nx):
         for j in range(prob.ny):
-            W, E, S, N = neighbours(prob, f, i, j)
-            fij = f[i, j]
-            R[i, j] = ((v1p * (fij - W) + v1m * (E - fij)) / prob.dx + (v2p * (fij - S) + v2m * (N - fij)) / prob.dy
-                       - Q[i, j] / prob.eps)
+            W, E, S, N = neighbours(prob, f, i, j, sx, sy)
+            # face values: east/north faces f + s/2 and west/south faces f - s/2 of
+            # each cell; ghosts carry no slope
+            xw = 0.5 * sx[i - 1, j] if i > 0 else 0.0
+            xe = 0.5 * sx[i + 1, j] if i < prob.nx - 1 else 0.0
+            ys = 0.5 * sy[i, j - 1] if j > 0 else 0.0
+            yn = 0.5 * sy[i, j + 1] if j < prob.ny - 1 else 0.0
+            fe, fw = f[i, j] + 0.5 * sx[i, j], f[i, j] - 0.5 * sx[i, j]
+            fn, fs = f[i, j] + 0.5 * sy[i, j], f[i, j] - 0.5 * sy[i, j]
+            R[i, j] = ((v1p * (fe - (W + xw)) + v1m * ((E - xe) - fw)) / prob.dx
+                       + (v2p * (fn - (S + ys)) + v2m * ((N - yn) - fs)) / prob.dy - Q[i, j] / prob.eps)
     return R
 
 

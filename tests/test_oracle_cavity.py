@@ -32,14 +32,16 @@ def _converge(prob, tol=1e-11, max_iter=100):
     raise AssertionError("no convergence")
 
 
-def test_steady_state_is_symmetric_under_transposition():
+@pytest.mark.parametrize("order", [1, 2])
+def test_steady_state_is_symmetric_under_transposition(order):
     # walls x = 0 and y = 0 at T = 1, x = 1 and y = 1 at T = 2: the problem is
     # invariant under (x, y, v_1, v_2) -> (y, x, v_2, v_1), the scans are not, so
-    # only the converged state must be symmetric
+    # only the converged state must be symmetric (and the scans' fixed point must
+    # zero the residual of the same scheme)
     N = 8
     sp = Spec(d=2, N=N, L=4.0, n_phi=8, n_rho=4)
     walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)))
-    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk")
+    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk", order=order)
     f = _converge(prob).reshape(4, 4, N, N)
     assert np.abs(f.transpose(1, 0, 3, 2) - f).max() < 1e-11 * f.max()
     assert abs(CV.total_mass(prob, f.reshape(4, 4, -1)) - 1.0) < 1e-13
@@ -79,3 +81,26 @@ def test_converged_state_is_a_fixed_point_of_the_vcycle():
     r1 = CV.outer_residual(prob, f1)
     f2 = CV.mg_iteration(prob, f1, coarsest=2)
     assert CV.outer_residual(prob, f2) < 0.5 * r1
+
+
+def test_second_order_transport_is_exact_on_quadratic_profiles_2d():
+    # eqs. reconstruction and slope along both axes: for f = 1 + q(x, y) g(v) with
+    # q quadratic (cross term included), the upwind flux differences with the
+    # centred slopes equal v . grad q g exactly at interior cells; first order
+    # is off by O(dx)
+    sp = Spec(d=2, N=8, L=4.0, n_phi=8, n_rho=4)
+    v = velocity_nodes(sp)
+    g = np.exp(-0.3 * (v * v).sum(1))
+    cx, cy, cxy = 0.7, -0.4, 0.5
+    for order, exact in ((2, True), (1, False)):
+        prob = CV.Cavity(spec=sp, nx=8, ny=7, eps=1.0, collision="bgk", order=order)
+        x = (np.arange(prob.nx) + 0.5) * prob.dx
+        y = (np.arange(prob.ny) + 0.5) * prob.dy
+        X, Y = np.meshgrid(x, y, indexing="ij")
+        q = cx * X * X + cy * Y * Y + cxy * X * Y
+        f = 1.0 + q[:, :, None] * g[None, None, :]
+        R = CV.residual_field(prob, f, np.zeros_like(f))
+        qx, qy = 2 * cx * X + cxy * Y, 2 * cy * Y + cxy * X
+        ref = (v[None, None, :, 0] * qx[:, :, None] + v[None, None, :, 1] * qy[:, :, None]) * g[None, None, :]
+        err = np.abs(R[2:-2, 2:-2] - ref[2:-2, 2:-2]).max() / np.abs(ref).max()
+        assert (err < 1e-12) if exact else (err > 1e-3), (order, err)
