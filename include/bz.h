@@ -335,8 +335,8 @@ bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* slab, double* residual_out, vo
  * The lid-driven cavity family of Section 4.2: the unit square [0, 1]^2 with
  * nx x ny uniform cells, a diffuse wall (eq. boundary) on each side, two-
  * dimensional velocities (a context with d = 2), Knudsen number eps and the
- * total-mass constraint of eq. mass_conserv.  First-order upwind finite
- * volumes: for cell (i, j),
+ * total-mass constraint of eq. mass_conserv.  Upwind finite volumes (first
+ * order shown; second order uses the face values, see `order`): for cell (i, j),
  *   [v1+ (f_ij - f_{i-1,j}) + v1- (f_{i+1,j} - f_ij)] / dx
  *     + [v2+ (f_ij - f_{i,j-1}) + v2- (f_{i,j+1} - f_ij)] / dy = Q[f_ij] / eps.
  * Cell (i, j) is stored at f + (i ny + j) K (borrowed for the cavity lifetime).
@@ -359,6 +359,12 @@ typedef struct {
   double bgk_nu;       /* BGK only; <= 0: 2 pi rho */
   bz_solve_opts inner; /* inner solve options */
   double* f;           /* device [nx ny][K], borrowed */
+  int order;           /* 1 (0 reads as 1) or 2: the linear reconstruction of
+                          eqs. reconstruction and slope along x and y, slopes
+                          centred inside and one-sided at the ends of each line,
+                          zero in the ghosts, taken from the iterate before each
+                          scan; a wall then balances the flux of the adjacent
+                          face value f -+ s/2 */
 } bz_cavity_desc;
 
 typedef struct bz_cavity bz_cavity;

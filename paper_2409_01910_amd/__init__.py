@@ -77,7 +77,7 @@ class bz_wall(ctypes.Structure):
 class bz_cavity_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("eps", ctypes.c_double), ("walls", bz_wall * 4),
                 ("mass", ctypes.c_double), ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double),
-                ("inner", bz_solve_opts), ("f", ctypes.c_void_p)]
+                ("inner", bz_solve_opts), ("f", ctypes.c_void_p), ("order", ctypes.c_int)]
 
 
 class bz_sweep_stats(ctypes.Structure):
@@ -418,7 +418,7 @@ class Cavity:
 
     def __init__(self, ctx: Context, nx: int, ny: int, eps: float, walls, f, mass: float = 1.0,
                  collision: str = "binary", bgk_nu: float = 0.0, mode="pfp", tol=1e-8, max_iter=100,
-                 fixed_iters=0):
+                 fixed_iters=0, order: int = 1):
         self.ctx = ctx
         self.f = f
         ctx._field(f, "f")
@@ -429,7 +429,7 @@ class Cavity:
             wl[s_].T = T
             wl[s_].U[0], wl[s_].U[1] = U
         desc = bz_cavity_desc(nx, ny, eps, wl, mass, _COLLISIONS[collision], bgk_nu,
-                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()))
+                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order)
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_cavity_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_cavity_create")
         self.h = h

@@ -39,6 +39,8 @@ struct CavLevel {
   double* theta = nullptr;    // [ncell][4]
   double* nu = nullptr;       // [ncell]
   double* part = nullptr;     // [ncell + 1] per-cell partial sums and their total
+  double* sx = nullptr;       // [ncell][K] slopes along x and y (second order)
+  double* sy = nullptr;
 };
 
 struct bz_cavity {
@@ -48,6 +50,7 @@ struct bz_cavity {
   int collision = 0;
   double bgk_nu = 0;
   bz_solve_opts opts{};
+  int order = 1;
   std::vector<CavLevel> lv;
   unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
 };
@@ -195,20 +198,25 @@ __device__ __forceinline__ void diag_cell(int nx, int ny, int dd, int sx, int sy
 }
 
 // Wall densities of cell (i, j): dens[s] = rho_w for each side s the cell
-// touches (sum over the outgoing half-space of |v_n| f against the incoming
-// flux of the unit wall Maxwellian), 0 elsewhere.  Every thread returns them.
-__device__ __forceinline__ void wall_densities(const double* fc, int i, int j, int nx, int ny, const CavWalls& wl,
-                                               const double* nodes, int N, double* red, double (&dens)[4]) {
+// touches (sum over the outgoing half-space of |v_n| times the adjacent face
+// value, f -+ s/2 with the cell's slopes when given, against the incoming flux
+// of the unit wall Maxwellian), 0 elsewhere.  Every thread returns them.
+__device__ __forceinline__ void wall_densities(const double* fc, const double* sxc, const double* syc, int i, int j,
+                                               int nx, int ny, const CavWalls& wl, const double* nodes, int N,
+                                               double* red, double (&dens)[4]) {
   const int K = N * N;
   double v[8];
   for (int q = 0; q < 8; ++q) v[q] = 0.0;
   const bool touch[4] = {i == 0, i == nx - 1, j == 0, j == ny - 1};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double x = nodes[k / N], y = nodes[k % N], fv = fc[k];
+    const double hx = sxc ? 0.5 * sxc[k] : 0.0, hy = syc ? 0.5 * syc[k] : 0.0;
     for (int s = 0; s < 4; ++s) {
       if (!touch[s]) continue;
       const double vn = (s < 2 ? x : y) * (s % 2 == 0 ? 1.0 : -1.0);  // along the inward normal
-      if (vn < 0) v[2 * s] += -vn * fv;
+      // the adjacent face value f -+ s/2
+      const double face = s == 0 ? fv - hx : s == 1 ? fv + hx : s == 2 ? fv - hy : fv + hy;
+      if (vn < 0) v[2 * s] += -vn * face;
       if (vn > 0) v[2 * s + 1] += vn * wall_m(wl, s, x, y);
     }
   }
@@ -218,7 +226,9 @@ __device__ __forceinline__ void wall_densities(const double* fc, int i, int j, i
 
 // One visit per workgroup: the cells of anti-diagonal dd of scan (sx, sy).
 __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ f, const double* __restrict__ rs,
-                                                           const double* __restrict__ nu, int nx, int ny, int dd,
+                                                           const double* __restrict__ nu,
+                                                           const double* __restrict__ slx,
+                                                           const double* __restrict__ sly, int nx, int ny, int dd,
                                                            int sx, int sy, double dx, double dy, double eps,
                                                            CavWalls wl, const double* __restrict__ nodes, int N,
                                                            double w, int mode, double tol, int max_iter, int fixed,
@@ -230,7 +240,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const size_t cell = (size_t)i * ny + j;
   double* fc = f + cell * K;
   double dens[4];
-  wall_densities(fc, i, j, nx, ny, wl, nodes, N, red, dens);
+  wall_densities(fc, slx ? slx + cell * K : nullptr, sly ? sly + cell * K : nullptr, i, j, nx, ny, wl, nodes, N, red,
+                 dens);
   const double* fW = i > 0 ? f + (cell - ny) * K : nullptr;
   const double* fE = i < nx - 1 ? f + (cell + ny) * K : nullptr;
   const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
@@ -351,7 +362,10 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
 // when given, and nu, per cell
 __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __restrict__ f, const double* __restrict__ Q,
                                                             const double* __restrict__ theta,
-                                                            const double* __restrict__ b, double* __restrict__ rs,
+                                                            const double* __restrict__ b,
+                                                            const double* __restrict__ slx,
+                                                            const double* __restrict__ sly, int nx, int ny, double dx,
+                                                            double dy, double* __restrict__ rs,
                                                             double* __restrict__ nu, const double* __restrict__ nodes,
                                                             int N, double w, double eps, int bgk, double bgk_nu,
                                                             double gam, double gfac) {
@@ -373,9 +387,17 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __rest
   if (threadIdx.x == 0) nu[cell] = nv;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     double v0 = 0.0;
+    if (slx) {  // second order: -(v1+ s_W - v1 s + v1- s_E) / 2dx - (same along y) / 2dy
+      const int i = (int)(cell / ny), j = (int)(cell - (size_t)i * ny);
+      const double x = nodes[k / N], y = nodes[k % N];
+      const double xw = i > 0 ? slx[(cell - ny) * K + k] : 0.0, xe = i < nx - 1 ? slx[(cell + ny) * K + k] : 0.0;
+      const double ys = j > 0 ? sly[(cell - 1) * K + k] : 0.0, yn = j < ny - 1 ? sly[(cell + 1) * K + k] : 0.0;
+      v0 = -((fmax(x, 0.0) * xw - x * slx[cell * K + k] + fmin(x, 0.0) * xe) / (2.0 * dx)) -
+           (fmax(y, 0.0) * ys - y * sly[cell * K + k] + fmin(y, 0.0) * yn) / (2.0 * dy);
+    }
     if (!bgk) {
       const double M = gauss2c(theta + cell * 4, nodes[k / N], nodes[k % N]);
-      v0 = -((Q[cell * K + k] - nv * (M - fc[k])) / eps);
+      v0 -= (Q[cell * K + k] - nv * (M - fc[k])) / eps;
     }
     rs[cell * K + k] = b ? v0 - b[cell * K + k] : v0;
   }
@@ -388,13 +410,17 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restr
                                                            double dx, double dy, double eps, CavWalls wl,
                                                            const double* __restrict__ nodes, int N, double w, int bgk,
                                                            double bgk_nu, const double* __restrict__ b,
+                                                           const double* __restrict__ slx,
+                                                           const double* __restrict__ sly,
                                                            double* __restrict__ res, double* __restrict__ part) {
   __shared__ double red[8 * (kCavThreads / 64)];
   const int K = N * N;
   const int cell = blockIdx.x, i = cell / ny, j = cell - i * ny;
   const double* fc = f + (size_t)cell * K;
+  const double* sxc = slx ? slx + (size_t)cell * K : nullptr;
+  const double* syc = sly ? sly + (size_t)cell * K : nullptr;
   double dens[4];
-  wall_densities(fc, i, j, nx, ny, wl, nodes, N, red, dens);
+  wall_densities(fc, sxc, syc, i, j, nx, ny, wl, nodes, N, red, dens);
   double nv = 0.0;
   if (bgk) {
     double v[1] = {0.0};
@@ -414,8 +440,18 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restr
     const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x, y);
     const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x, y);
     const double q = bgk ? nv * (gauss2c(theta + (size_t)cell * 4, x, y) - fv) : Q[(size_t)cell * K + k];
-    const double R = (fmax(x, 0.0) * (fv - W) + fmin(x, 0.0) * (E - fv)) / dx +
-                     (fmax(y, 0.0) * (fv - S) + fmin(y, 0.0) * (Nn - fv)) / dy - q / eps;
+    // face values: f +- s/2 of the cell, neighbours' faces toward it, ghosts without slope
+    double xw = 0.0, xe = 0.0, ys = 0.0, yn = 0.0, hx = 0.0, hy = 0.0;
+    if (sxc) {
+      xw = fW ? 0.5 * sxc[k - (ptrdiff_t)ny * K] : 0.0;
+      xe = fE ? 0.5 * sxc[k + (ptrdiff_t)ny * K] : 0.0;
+      ys = fS ? 0.5 * syc[k - K] : 0.0;
+      yn = fN ? 0.5 * syc[k + K] : 0.0;
+      hx = 0.5 * sxc[k];
+      hy = 0.5 * syc[k];
+    }
+    const double R = (fmax(x, 0.0) * ((fv + hx) - (W + xw)) + fmin(x, 0.0) * ((E - xe) - (fv - hx))) / dx +
+                     (fmax(y, 0.0) * ((fv + hy) - (S + ys)) + fmin(y, 0.0) * ((Nn - yn) - (fv - hy))) / dy - q / eps;
     const double rb = (b ? b[(size_t)cell * K + k] : 0.0) - R;  // b - R(f)
     if (res) res[(size_t)cell * K + k] = rb;
     acc[0] += rb * rb;
@@ -453,6 +489,29 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_total(const double* __restr
   for (int q = threadIdx.x; q < ncell; q += blockDim.x) v[0] += part[q];
   block_sum<1>(v, red);
   if (threadIdx.x == 0) out[0] = v[0];
+}
+
+// slopes of eq. slope along x and y: centred inside, one-sided at the ends of each line
+__global__ void __launch_bounds__(kCavThreads) k_cav_slopes(const double* __restrict__ f, int nx, int ny, int K,
+                                                            double* __restrict__ sx, double* __restrict__ sy) {
+  const size_t cell = blockIdx.x;
+  const int i = (int)(cell / ny), j = (int)(cell - (size_t)i * ny);
+  const double* c = f + cell * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    if (nx > 1) {
+      if (i == 0) a = c[k + (size_t)ny * K] - c[k];
+      else if (i == nx - 1) a = c[k] - c[k - (size_t)ny * K];
+      else a = 0.5 * (c[k + (size_t)ny * K] - c[k - (size_t)ny * K]);
+    }
+    if (ny > 1) {
+      if (j == 0) b = c[k + K] - c[k];
+      else if (j == ny - 1) b = c[k] - c[k - K];
+      else b = 0.5 * (c[k + K] - c[k - K]);
+    }
+    sx[cell * K + k] = a;
+    sy[cell * K + k] = b;
+  }
 }
 
 __global__ void __launch_bounds__(kCavThreads) k_cav_negate(double* __restrict__ a, int K) {
@@ -504,13 +563,16 @@ CavWalls walls_of(const bz_cavity* cv) {
   return wl;
 }
 
-bz_status alloc_level(bz_ctx* ctx, CavLevel& L, bool own) {
+bz_status alloc_level(bz_ctx* ctx, CavLevel& L, bool own, bool slopes) {
   const size_t K = ctx->K, nc = L.ncell;
   bool ok = hipMalloc((void**)&L.Q, nc * K * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&L.rs, nc * K * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&L.theta, nc * 4 * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&L.nu, nc * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&L.part, (nc + 1) * sizeof(double)) == hipSuccess;
+  if (ok && slopes)
+    ok = hipMalloc((void**)&L.sx, nc * K * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&L.sy, nc * K * sizeof(double)) == hipSuccess;
   if (ok && own)
     ok = hipMalloc((void**)&L.f, nc * K * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&L.b, nc * K * sizeof(double)) == hipSuccess &&
@@ -519,20 +581,32 @@ bz_status alloc_level(bz_ctx* ctx, CavLevel& L, bool own) {
 }
 
 void free_level(CavLevel& L, bool own) {
-  void* ptrs[] = {L.Q, L.rs, L.theta, L.nu, L.part, L.res, own ? L.f : nullptr, L.b, L.f0};
+  void* ptrs[] = {L.Q, L.rs, L.theta, L.nu, L.part, L.res, own ? L.f : nullptr, L.b, L.f0, L.sx, L.sy};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   L = CavLevel{};
 }
 
-// collision split of every cell of a level: theta, nu and rs = -P/eps - b
+bz_status cav_slopes(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
+  if (cv->order != 2) return BZ_OK;
+  hipLaunchKernelGGL(k_cav_slopes, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.nx, L.ny, ctx->K, L.sx, L.sy);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// collision split of every cell of a level: theta, nu and rs = -P/eps - b, with
+// the static reconstruction terms at second order (slopes of the iterate before
+// the scan)
 bz_status cav_static(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   const bool bgk = cv->collision == BZ_COLL_BGK;
+  bz_status s0 = cav_slopes(ctx, cv, L, st);
+  if (s0 != BZ_OK) return s0;
   if (!bgk) {
     bz_status s = v2_eval_q(ctx, L.f, L.Q, L.ncell, true, true, L.theta, st);
     if (s != BZ_OK) return s;
   }
-  hipLaunchKernelGGL(k_cav_static, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.b, L.rs, L.nu,
+  hipLaunchKernelGGL(k_cav_static, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.b, L.sx, L.sy, L.nx,
+                     L.ny, L.dx, L.dy, L.rs, L.nu,
                      ctx->d_nodes, ctx->N, ctx->w, cv->eps, bgk ? 1 : 0, cv->bgk_nu, ctx->p.gamma, ctx->nu_gfac);
   BZ_HIP(hipGetLastError());
   return BZ_OK;
@@ -544,9 +618,11 @@ bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, dou
   const bool bgk = cv->collision == BZ_COLL_BGK;
   bz_status s = bgk ? v2_maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st)
                     : v2_eval_q(ctx, L.f, L.Q, L.ncell, true, true, L.theta, st);
+  if (s == BZ_OK) s = cav_slopes(ctx, cv, L, st);
   if (s != BZ_OK) return s;
   hipLaunchKernelGGL(k_cav_resid, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.nx, L.ny, L.dx, L.dy,
-                     cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0, cv->bgk_nu, L.b, res, L.part);
+                     cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0, cv->bgk_nu, L.b, L.sx, L.sy,
+                     res, L.part);
   BZ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_cav_total, dim3(1), dim3(kCavThreads), 0, st, L.part, L.ncell, L.part + L.ncell);
   BZ_HIP(hipGetLastError());
@@ -567,7 +643,8 @@ bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
     for (int dd = 0; dd <= L.nx + L.ny - 2; ++dd) {
       const int lo = dd - (L.ny - 1) > 0 ? dd - (L.ny - 1) : 0;
       const int hi = dd < L.nx - 1 ? dd : L.nx - 1;
-      hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.nx, L.ny, dd,
+      hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.sx, L.sy, L.nx,
+                         L.ny, dd,
                          scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
                          cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters, cv->d_stats);
       BZ_HIP(hipGetLastError());
@@ -616,7 +693,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
     C.ncell = C.nx * C.ny;
     C.dx = 1.0 / C.nx;
     C.dy = 1.0 / C.ny;
-    if ((s = alloc_level(ctx, C, true)) != BZ_OK) {
+    if ((s = alloc_level(ctx, C, true, cv->order == 2)) != BZ_OK) {
       free_level(C, true);
       return s;
     }
@@ -680,6 +757,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   if (!(d->mass > 0) || !std::isfinite(d->mass)) return set_err(ctx, BZ_EINVAL, "mass must be > 0");
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK)
     return set_err(ctx, BZ_EINVAL, "collision must be BZ_COLL_BINARY or BZ_COLL_BGK");
+  if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
   for (int s = 0; s < 4; ++s) {
     const bz_wall& wl = d->walls[s];
     if (!(wl.T > 0) || !std::isfinite(wl.T) || !std::isfinite(wl.U[0]) || !std::isfinite(wl.U[1]))
@@ -701,6 +779,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   cv->collision = d->collision;
   cv->bgk_nu = d->bgk_nu;
   cv->opts = o;
+  cv->order = d->order == 2 ? 2 : 1;
   CavLevel L0;
   L0.nx = d->nx;
   L0.ny = d->ny;
@@ -708,7 +787,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   L0.dx = 1.0 / d->nx;
   L0.dy = 1.0 / d->ny;
   L0.f = d->f;
-  bz_status s = bz::alloc_level(ctx, L0, false);
+  bz_status s = bz::alloc_level(ctx, L0, false, cv->order == 2);
   cv->lv.push_back(L0);
   if (s == BZ_OK && hipMalloc((void**)&cv->d_stats, 3 * sizeof(unsigned long long)) != hipSuccess)
     s = set_err(ctx, BZ_ENOMEM, "cavity statistics");

@@ -25,23 +25,24 @@ def bz():
     return bz
 
 
-def _setup(bz, N, L, nx, ny, collision, fixed, mode="pfp", eps=0.1, walls=LID, M=8, nr=4):
+def _setup(bz, N, L, nx, ny, collision, fixed, mode="pfp", eps=0.1, walls=LID, M=8, nr=4, order=1):
     sp = Spec(d=2, N=N, L=L, n_phi=M, n_rho=nr)
     prob = CV.Cavity(spec=sp, nx=nx, ny=ny, eps=eps, walls=walls, collision=collision, inner=mode,
-                     fixed_inner=fixed)
+                     fixed_inner=fixed, order=order)
     f0 = CV.initial_state(prob, T=1.2)
     ctx = bz.Context(N=N, L=L, n_phi=M, n_rho=nr, d=2)
     fg = torch.from_numpy(f0.reshape(nx * ny, -1).copy()).to("cuda:0").contiguous()
-    cav = bz.Cavity(ctx, nx, ny, eps, walls, fg, collision=collision, mode=mode, fixed_iters=fixed or 0)
+    cav = bz.Cavity(ctx, nx, ny, eps, walls, fg, collision=collision, mode=mode, fixed_iters=fixed or 0, order=order)
     return prob, f0, ctx, cav, fg
 
 
-@pytest.mark.parametrize("collision,mode,N,L", [("bgk", "pfp", 8, 4.0), ("binary", "pfp", 8, 4.0),
-                                                ("binary", "fp", 8, 4.0), ("binary", "pfp", 12, 6.0)])
-def test_cavity_sweeps_match_oracle(bz, collision, mode, N, L):
+@pytest.mark.parametrize("collision,mode,N,L,order", [("bgk", "pfp", 8, 4.0, 1), ("binary", "pfp", 8, 4.0, 1),
+                                                      ("binary", "fp", 8, 4.0, 1), ("binary", "pfp", 12, 6.0, 1),
+                                                      ("bgk", "pfp", 8, 4.0, 2), ("binary", "pfp", 8, 4.0, 2)])
+def test_cavity_sweeps_match_oracle(bz, collision, mode, N, L, order):
     nx, ny = 3, 4
-    print(f"cavity {collision} {mode} N={N} {nx}x{ny}", flush=True)
-    prob, f0, ctx, cav, fg = _setup(bz, N, L, nx, ny, collision, fixed=2, mode=mode)
+    print(f"cavity {collision} {mode} N={N} {nx}x{ny} order {order}", flush=True)
+    prob, f0, ctx, cav, fg = _setup(bz, N, L, nx, ny, collision, fixed=2, mode=mode, order=order)
     res, st = cav.sweep(2)
     f = f0
     for _ in range(2):
@@ -96,14 +97,14 @@ def test_cavity_rejects_bad_arguments(bz):
         bz.Cavity(ctx3, 2, 2, 0.1, ((1.0, (0.0, 0.0)),) * 4, f3)
 
 
-@pytest.mark.parametrize("collision", ["bgk", "binary"])
-def test_cavity_vcycle_matches_oracle(bz, collision):
+@pytest.mark.parametrize("collision,order", [("bgk", 1), ("binary", 1), ("binary", 2)])
+def test_cavity_vcycle_matches_oracle(bz, collision, order):
     # one FAS V-cycle forced to descend (tol = 0) on a 4 x 8 grid: levels 4 x 8 and
     # 2 x 4 (coarsest 2), one pre- and one post-smoothing iteration, at most 3
     # coarsest iterations, then the mass rescale
     nx, ny = 4, 8
-    print(f"cavity V-cycle {collision} {nx}x{ny}", flush=True)
-    prob, f0, ctx, cav, fg = _setup(bz, 8, 4.0, nx, ny, collision, fixed=2)
+    print(f"cavity V-cycle {collision} {nx}x{ny} order {order}", flush=True)
+    prob, f0, ctx, cav, fg = _setup(bz, 8, 4.0, nx, ny, collision, fixed=2, order=order)
     res, st = cav.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
     f = CV.vcycle(prob, f0.copy(), None, coarsest=2, nu1=1, nu2=1, tol=0.0, coarse_iters=3)
     f = f * (prob.mass / CV.total_mass(prob, f))
