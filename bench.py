@@ -273,7 +273,8 @@ def order_workload(args):
     return {"workload": "order", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
-def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5):
+def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5, order=1,
+                nu1=1, nu2=1):
     """Lid-driven cavity on [0, 1]^2 (all walls T = 1, the lid y = 1 moving at
     (lid, 0)), n^2 velocities on [-l, l]^2, Maxwell molecules with M circle
     directions and nr radial nodes, first-order SGS-PFP FP64 (inner residual
@@ -295,12 +296,12 @@ def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, m
     f = torch.from_numpy(f0).cuda().contiguous()
     ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2)
     walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
-    cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100)
+    cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100, order=order)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist, inner, visits, last = [cav.residual()], 0, 0, t0
     while hist[-1] >= tol and len(hist) <= max_iters and time.perf_counter() - t0 < max_seconds:
-        r, st = cav.sweep(1) if method == "sgs" else cav.vcycle(1, coarsest=coarsest, nu1=1, nu2=1, tol=tol)
+        r, st = cav.sweep(1) if method == "sgs" else cav.vcycle(1, coarsest=coarsest, nu1=nu1, nu2=nu2, tol=tol)
         hist.append(r)
         inner += st["inner_iters"]
         visits += st["visits"]
@@ -333,7 +334,12 @@ def cavity_workload(args):
 
     out = {}
     L40 = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
-    want = lambda k: args.cavity_case in ("all", k)
+    def want(k):
+        if args.cavity_case == "first_order":
+            return "_o2" not in k and k.startswith("paper")
+        if args.cavity_case == "second_order":
+            return "_o2" in k
+        return args.cavity_case in ("all", k)
     for eps in (1.0, 0.1, 0.01, 0.001):
         key = f"paper_40x40_eps{eps:g}"
         if want(key):
@@ -342,6 +348,16 @@ def cavity_workload(args):
         key = f"paper_40x40_mg_eps{eps:g}"
         if want(key):
             out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 1000, 120.0, key, method="mg", coarsest=5)
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
+        # second order: SGS-PFP, and V-cycles with tab. mg's second-order smoothing (5 pre-, 1 post-)
+        key = f"paper_40x40_o2_eps{eps:g}"
+        if want(key):
+            out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key, order=2)
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
+        key = f"paper_40x40_o2mg_eps{eps:g}"
+        if want(key):
+            out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 1000, 120.0, key, method="mg", coarsest=5,
+                                   order=2, nu1=5, nu2=1)
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
     key = "n48_64x64_mg_eps0.1"
     if want(key):
@@ -518,7 +534,9 @@ def main():
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
     ap.add_argument("--cavity-case", default="all",
-                    choices=["all"] + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg") for e in ("1", "0.1", "0.01", "0.001")]
+                    choices=["all", "first_order", "second_order"]
+                            + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg", "_o2", "_o2mg")
+                               for e in ("1", "0.1", "0.01", "0.001")]
                             + ["n48_64x64_mg_eps0.1", "batched_q_48x48"],
                     help="with --workload cavity: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity"], default="batched-q",
