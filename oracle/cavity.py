@@ -58,6 +58,10 @@ class Cavity:
     max_inner: int = 100
     fixed_inner: int | None = None
     order: int = 1
+    # uniform_y: the problem does not vary along y (ny = 1): no y transport and no
+    # y walls, two scans (+x, -x) per iteration, multigrid coarsens x only.  This
+    # is the 1D slab between two plates with 2D velocities.
+    uniform_y: bool = False
     stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0})
 
     @property
@@ -101,6 +105,10 @@ def slopes(prob: Cavity, f: np.ndarray):
     return sx, sy
 
 
+def scans(prob: Cavity):
+    return SCANS[:2] if prob.uniform_y else SCANS
+
+
 def neighbours(prob: Cavity, f: np.ndarray, i: int, j: int, sx=None, sy=None):
     """(west, east, south, north) values for cell (i, j): cells or wall ghosts;
     a wall balances the flux of the adjacent face value f -+ s/2."""
@@ -108,6 +116,8 @@ def neighbours(prob: Cavity, f: np.ndarray, i: int, j: int, sx=None, sy=None):
     hy = 0.0 if sy is None else 0.5 * sy[i, j]
     W = f[i - 1, j] if i > 0 else ghost(prob, 0, f[i, j] - hx)
     E = f[i + 1, j] if i < prob.nx - 1 else ghost(prob, 1, f[i, j] + hx)
+    if prob.uniform_y:
+        return W, E, None, None
     S = f[i, j - 1] if j > 0 else ghost(prob, 2, f[i, j] - hy)
     N = f[i, j + 1] if j < prob.ny - 1 else ghost(prob, 3, f[i, j] + hy)
     return W, E, S, N
@@ -145,18 +155,22 @@ def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = N
     for i in (range(prob.nx) if sx > 0 else range(prob.nx - 1, -1, -1)):
         for j in (range(prob.ny) if sy > 0 else range(prob.ny - 1, -1, -1)):
             W, E, S, N = neighbours(prob, f, i, j, slx, sly)
-            r = (-v1p * W + v1m * E) / prob.dx + (-v2p * S + v2m * N) / prob.dy
+            r = (-v1p * W + v1m * E) / prob.dx
+            if not prob.uniform_y:
+                r = r + (-v2p * S + v2m * N) / prob.dy
             if prob.order == 2:
                 xw = slx[i - 1, j] if i > 0 else zero
                 xe = slx[i + 1, j] if i < prob.nx - 1 else zero
                 ys = sly[i, j - 1] if j > 0 else zero
                 yn = sly[i, j + 1] if j < prob.ny - 1 else zero
                 r -= (v1p * xw - v[:, 0] * slx[i, j] + v1m * xe) / (2.0 * prob.dx)
-                r -= (v2p * ys - v[:, 1] * sly[i, j] + v2m * yn) / (2.0 * prob.dy)
+                if not prob.uniform_y:
+                    r -= (v2p * ys - v[:, 1] * sly[i, j] + v2m * yn) / (2.0 * prob.dy)
             r -= P[i, j] / prob.eps
             if b is not None:
                 r -= b[i, j]
-            g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, (prob.dx, prob.dy), f[i, j], mode=prob.inner,
+            dxs = prob.dx if prob.uniform_y else (prob.dx, prob.dy)
+            g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, dxs, f[i, j], mode=prob.inner,
                                   tol=prob.tol_inner, max_iter=prob.max_inner, fixed_iters=prob.fixed_inner)
             prob.stats["inner"] += st.iterations
             prob.stats["fallback"] += int(st.fallback)
@@ -170,7 +184,7 @@ def total_mass(prob: Cavity, f: np.ndarray) -> float:
 
 
 def sgs_iteration(prob: Cavity, f: np.ndarray, b: np.ndarray | None = None, rescale: bool = True) -> np.ndarray:
-    for sx, sy in SCANS:
+    for sx, sy in scans(prob):
         f = scan(prob, f, sx, sy, b)
     return f * (prob.mass / total_mass(prob, f)) if rescale else f
 
@@ -192,8 +206,10 @@ def residual_field(prob: Cavity, f: np.ndarray, Q: np.ndarray) -> np.ndarray:
             yn = 0.5 * sy[i, j + 1] if j < prob.ny - 1 else 0.0
             fe, fw = f[i, j] + 0.5 * sx[i, j], f[i, j] - 0.5 * sx[i, j]
             fn, fs = f[i, j] + 0.5 * sy[i, j], f[i, j] - 0.5 * sy[i, j]
-            R[i, j] = ((v1p * (fe - (W + xw)) + v1m * ((E - xe) - fw)) / prob.dx
-                       + (v2p * (fn - (S + ys)) + v2m * ((N - yn) - fs)) / prob.dy - Q[i, j] / prob.eps)
+            R[i, j] = (v1p * (fe - (W + xw)) + v1m * ((E - xe) - fw)) / prob.dx
+            if not prob.uniform_y:
+                R[i, j] += (v2p * (fn - (S + ys)) + v2m * ((N - yn) - fs)) / prob.dy
+            R[i, j] -= Q[i, j] / prob.eps
     return R
 
 
@@ -223,14 +239,18 @@ def outer_residual(prob: Cavity, f: np.ndarray, b: np.ndarray | None = None) -> 
 
 def coarse(prob: Cavity) -> Cavity:
     return Cavity(**{k: getattr(prob, k) for k in prob.__dataclass_fields__ if k not in ("nx", "ny", "stats")},
-                  nx=prob.nx // 2, ny=prob.ny // 2)
+                  nx=prob.nx // 2, ny=prob.ny if prob.uniform_y else prob.ny // 2)
 
 
 def restrict(f: np.ndarray) -> np.ndarray:
+    if f.shape[1] == 1:  # uniform in y: two children along x
+        return 0.5 * (f[0::2] + f[1::2])
     return 0.25 * (f[0::2, 0::2] + f[1::2, 0::2] + f[0::2, 1::2] + f[1::2, 1::2])
 
 
 def prolong(e: np.ndarray) -> np.ndarray:
+    if e.shape[1] == 1:
+        return np.repeat(e, 2, axis=0)
     return np.repeat(np.repeat(e, 2, axis=0), 2, axis=1)
 
 
@@ -242,7 +262,7 @@ def vcycle(prob: Cavity, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1
         b = np.zeros_like(f)
     for _ in range(nu1):
         f = sgs_iteration(prob, f, b, rescale=False)
-    if min(prob.nx, prob.ny) <= coarsest:
+    if (prob.nx if prob.uniform_y else min(prob.nx, prob.ny)) <= coarsest:
         r0 = norm(prob, b - level_R(prob, f))
         for _ in range(coarse_iters):
             if norm(prob, b - level_R(prob, f)) <= 0.1 * r0:

@@ -104,3 +104,28 @@ def test_second_order_transport_is_exact_on_quadratic_profiles_2d():
         ref = (v[None, None, :, 0] * qx[:, :, None] + v[None, None, :, 1] * qy[:, :, None]) * g[None, None, :]
         err = np.abs(R[2:-2, 2:-2] - ref[2:-2, 2:-2]).max() / np.abs(ref).max()
         assert (err < 1e-12) if exact else (err > 1e-3), (order, err)
+
+
+@pytest.mark.parametrize("collision,order", [("bgk", 1), ("binary", 1), ("binary", 2)])
+def test_uniform_y_cavity_is_the_1d_slab(collision, order):
+    # A cavity that does not vary along y (one cell row, no y transport, no y
+    # walls, two scans per iteration) is the heat slab between two plates: its
+    # SGS iterations and V-cycles must be those of the independently written 1D
+    # slab oracle (pinned by its own closed forms) on the same 2D velocity grid.
+    from oracle import sweep as SW
+
+    sp = Spec(d=2, N=8, L=4.0, n_phi=8, n_rho=4)
+    walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)))
+    cav = CV.Cavity(spec=sp, nx=8, ny=1, eps=0.1, walls=walls, collision=collision, uniform_y=True, order=order,
+                    fixed_inner=2)
+    slab = SW.Slab(spec=sp, nx=8, eps=0.1, T_L=1.0, T_R=2.0, U_L=(0.0, 0.0), U_R=(0.0, 0.0), collision=collision,
+                   order=order, fixed_inner=2)
+    f = CV.initial_state(cav, T=1.2)
+    g = f[:, 0, :].copy()
+    f = CV.sgs_iteration(cav, f)
+    g = SW.sgs_iteration(slab, g)
+    assert np.abs(f[:, 0, :] - g).max() <= 1e-14 * g.max()
+    f = CV.vcycle(cav, f, None, coarsest=2, nu1=1, nu2=1, tol=0.0)
+    g = SW.vcycle(slab, g, None, coarsest=2, nu1=1, nu2=1, tol=0.0)
+    assert np.abs(f[:, 0, :] - g).max() <= 1e-14 * g.max()
+    assert abs(CV.outer_residual(cav, f) - SW.outer_residual(slab, g)) <= 1e-14 * SW.outer_residual(slab, g)
