@@ -365,6 +365,11 @@ typedef struct {
                           zero in the ghosts, taken from the iterate before each
                           scan; a wall then balances the flux of the adjacent
                           face value f -+ s/2 */
+  int uniform_y;       /* != 0: the problem does not vary along y (ny must be 1):
+                          no y transport and no y walls (walls[2], walls[3] are
+                          ignored), two scans (+x, -x) per iteration, multigrid
+                          coarsening along x only.  This is the 1D slab between
+                          two plates with 2D velocities (Section 4.2). */
 } bz_cavity_desc;
 
 typedef struct bz_cavity bz_cavity;

@@ -77,7 +77,8 @@ class bz_wall(ctypes.Structure):
 class bz_cavity_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("eps", ctypes.c_double), ("walls", bz_wall * 4),
                 ("mass", ctypes.c_double), ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double),
-                ("inner", bz_solve_opts), ("f", ctypes.c_void_p), ("order", ctypes.c_int)]
+                ("inner", bz_solve_opts), ("f", ctypes.c_void_p), ("order", ctypes.c_int),
+                ("uniform_y", ctypes.c_int)]
 
 
 class bz_sweep_stats(ctypes.Structure):
@@ -413,12 +414,13 @@ class Cavity:
     """A 2D cavity on [0, 1]^2 (bz_cavity) on a context with d = 2.
 
     ``walls`` lists (T, (U_1, U_2)) for the sides x = 0, x = 1, y = 0, y = 1.
+    ``uniform_y`` (ny = 1): the slab between two plates, no y transport or walls.
     ``f`` is a float64 device tensor [nx * ny, K] (cell (i, j) at row i * ny + j)
     that the cavity reads and updates in place (borrowed for its lifetime)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, eps: float, walls, f, mass: float = 1.0,
                  collision: str = "binary", bgk_nu: float = 0.0, mode="pfp", tol=1e-8, max_iter=100,
-                 fixed_iters=0, order: int = 1):
+                 fixed_iters=0, order: int = 1, uniform_y: bool = False):
         self.ctx = ctx
         self.f = f
         ctx._field(f, "f")
@@ -429,7 +431,8 @@ class Cavity:
             wl[s_].T = T
             wl[s_].U[0], wl[s_].U[1] = U
         desc = bz_cavity_desc(nx, ny, eps, wl, mass, _COLLISIONS[collision], bgk_nu,
-                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order)
+                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order,
+                              1 if uniform_y else 0)
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_cavity_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_cavity_create")
         self.h = h

@@ -51,6 +51,7 @@ struct bz_cavity {
   double bgk_nu = 0;
   bz_solve_opts opts{};
   int order = 1;
+  int uy = 0;  // uniform along y: no y transport or y walls, two scans, x-only coarsening
   std::vector<CavLevel> lv;
   unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
 };
@@ -202,12 +203,12 @@ __device__ __forceinline__ void diag_cell(int nx, int ny, int dd, int sx, int sy
 // value, f -+ s/2 with the cell's slopes when given, against the incoming flux
 // of the unit wall Maxwellian), 0 elsewhere.  Every thread returns them.
 __device__ __forceinline__ void wall_densities(const double* fc, const double* sxc, const double* syc, int i, int j,
-                                               int nx, int ny, const CavWalls& wl, const double* nodes, int N,
+                                               int nx, int ny, int uy, const CavWalls& wl, const double* nodes, int N,
                                                double* red, double (&dens)[4]) {
   const int K = N * N;
   double v[8];
   for (int q = 0; q < 8; ++q) v[q] = 0.0;
-  const bool touch[4] = {i == 0, i == nx - 1, j == 0, j == ny - 1};
+  const bool touch[4] = {i == 0, i == nx - 1, !uy && j == 0, !uy && j == ny - 1};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double x = nodes[k / N], y = nodes[k % N], fv = fc[k];
     const double hx = sxc ? 0.5 * sxc[k] : 0.0, hy = syc ? 0.5 * syc[k] : 0.0;
@@ -228,7 +229,8 @@ __device__ __forceinline__ void wall_densities(const double* fc, const double* s
 __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ f, const double* __restrict__ rs,
                                                            const double* __restrict__ nu,
                                                            const double* __restrict__ slx,
-                                                           const double* __restrict__ sly, int nx, int ny, int dd,
+                                                           const double* __restrict__ sly, int nx, int ny, int uy,
+                                                           int dd,
                                                            int sx, int sy, double dx, double dy, double eps,
                                                            CavWalls wl, const double* __restrict__ nodes, int N,
                                                            double w, int mode, double tol, int max_iter, int fixed,
@@ -240,8 +242,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const size_t cell = (size_t)i * ny + j;
   double* fc = f + cell * K;
   double dens[4];
-  wall_densities(fc, slx ? slx + cell * K : nullptr, sly ? sly + cell * K : nullptr, i, j, nx, ny, wl, nodes, N, red,
-                 dens);
+  wall_densities(fc, slx ? slx + cell * K : nullptr, sly ? sly + cell * K : nullptr, i, j, nx, ny, uy, wl, nodes, N,
+                 red, dens);
   const double* fW = i > 0 ? f + (cell - ny) * K : nullptr;
   const double* fE = i < nx - 1 ? f + (cell + ny) * K : nullptr;
   const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
@@ -256,13 +258,18 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     if (k < K) {
       x[q] = nodes[k / N];
       y[q] = nodes[k % N];
-      c[q] = fabs(x[q]) / dx + fabs(y[q]) / dy;
       const double W = fW ? fW[k] : dens[0] * wall_m(wl, 0, x[q], y[q]);
       const double E = fE ? fE[k] : dens[1] * wall_m(wl, 1, x[q], y[q]);
-      const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x[q], y[q]);
-      const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x[q], y[q]);
-      r[q] = (-fmax(x[q], 0.0) * W + fmin(x[q], 0.0) * E) / dx + (-fmax(y[q], 0.0) * S + fmin(y[q], 0.0) * Nn) / dy +
-             rs[cell * K + k];
+      if (uy) {
+        c[q] = fabs(x[q]) / dx;
+        r[q] = (-fmax(x[q], 0.0) * W + fmin(x[q], 0.0) * E) / dx + rs[cell * K + k];
+      } else {
+        const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x[q], y[q]);
+        const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x[q], y[q]);
+        c[q] = fabs(x[q]) / dx + fabs(y[q]) / dy;
+        r[q] = (-fmax(x[q], 0.0) * W + fmin(x[q], 0.0) * E) / dx + (-fmax(y[q], 0.0) * S + fmin(y[q], 0.0) * Nn) / dy +
+               rs[cell * K + k];
+      }
       g[q] = fc[k];
     }
   }
@@ -364,8 +371,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __rest
                                                             const double* __restrict__ theta,
                                                             const double* __restrict__ b,
                                                             const double* __restrict__ slx,
-                                                            const double* __restrict__ sly, int nx, int ny, double dx,
-                                                            double dy, double* __restrict__ rs,
+                                                            const double* __restrict__ sly, int nx, int ny, int uy,
+                                                            double dx, double dy, double* __restrict__ rs,
                                                             double* __restrict__ nu, const double* __restrict__ nodes,
                                                             int N, double w, double eps, int bgk, double bgk_nu,
                                                             double gam, double gfac) {
@@ -392,8 +399,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __rest
       const double x = nodes[k / N], y = nodes[k % N];
       const double xw = i > 0 ? slx[(cell - ny) * K + k] : 0.0, xe = i < nx - 1 ? slx[(cell + ny) * K + k] : 0.0;
       const double ys = j > 0 ? sly[(cell - 1) * K + k] : 0.0, yn = j < ny - 1 ? sly[(cell + 1) * K + k] : 0.0;
-      v0 = -((fmax(x, 0.0) * xw - x * slx[cell * K + k] + fmin(x, 0.0) * xe) / (2.0 * dx)) -
-           (fmax(y, 0.0) * ys - y * sly[cell * K + k] + fmin(y, 0.0) * yn) / (2.0 * dy);
+      v0 = -((fmax(x, 0.0) * xw - x * slx[cell * K + k] + fmin(x, 0.0) * xe) / (2.0 * dx));
+      if (!uy) v0 -= (fmax(y, 0.0) * ys - y * sly[cell * K + k] + fmin(y, 0.0) * yn) / (2.0 * dy);
     }
     if (!bgk) {
       const double M = gauss2c(theta + cell * 4, nodes[k / N], nodes[k % N]);
@@ -406,7 +413,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_static(const double* __rest
 // per-cell sum of w (b - R)^2 with R = v.grad f - Q/eps (BGK: Q = nu (M - f)), b the FAS
 // source (0 when null); the field b - R into res when non-null
 __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restrict__ f, const double* __restrict__ Q,
-                                                           const double* __restrict__ theta, int nx, int ny,
+                                                           const double* __restrict__ theta, int nx, int ny, int uy,
                                                            double dx, double dy, double eps, CavWalls wl,
                                                            const double* __restrict__ nodes, int N, double w, int bgk,
                                                            double bgk_nu, const double* __restrict__ b,
@@ -420,7 +427,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restr
   const double* sxc = slx ? slx + (size_t)cell * K : nullptr;
   const double* syc = sly ? sly + (size_t)cell * K : nullptr;
   double dens[4];
-  wall_densities(fc, sxc, syc, i, j, nx, ny, wl, nodes, N, red, dens);
+  wall_densities(fc, sxc, syc, i, j, nx, ny, uy, wl, nodes, N, red, dens);
   double nv = 0.0;
   if (bgk) {
     double v[1] = {0.0};
@@ -450,8 +457,9 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_resid(const double* __restr
       hx = 0.5 * sxc[k];
       hy = 0.5 * syc[k];
     }
-    const double R = (fmax(x, 0.0) * ((fv + hx) - (W + xw)) + fmin(x, 0.0) * ((E - xe) - (fv - hx))) / dx +
-                     (fmax(y, 0.0) * ((fv + hy) - (S + ys)) + fmin(y, 0.0) * ((Nn - yn) - (fv - hy))) / dy - q / eps;
+    double R = (fmax(x, 0.0) * ((fv + hx) - (W + xw)) + fmin(x, 0.0) * ((E - xe) - (fv - hx))) / dx;
+    if (!uy) R += (fmax(y, 0.0) * ((fv + hy) - (S + ys)) + fmin(y, 0.0) * ((Nn - yn) - (fv - hy))) / dy;
+    R -= q / eps;
     const double rb = (b ? b[(size_t)cell * K + k] : 0.0) - R;  // b - R(f)
     if (res) res[(size_t)cell * K + k] = rb;
     acc[0] += rb * rb;
@@ -521,19 +529,32 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_negate(double* __restrict__
 
 // coarse cell (I, J) <- average of its four children
 __global__ void __launch_bounds__(kCavThreads) k_cav_restrict(const double* __restrict__ fine, int nyf,
-                                                              double* __restrict__ coarse, int nyc, int K) {
+                                                              double* __restrict__ coarse, int nyc, int K, int uy) {
+  double* o = coarse + (size_t)blockIdx.x * K;
+  if (uy) {  // two children along x
+    const double* a = fine + (size_t)(2 * blockIdx.x) * K;
+    const double* b = a + K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] = 0.5 * (a[k] + b[k]);
+    return;
+  }
   const int I = blockIdx.x / nyc, J = blockIdx.x - (blockIdx.x / nyc) * nyc;
   const double* a = fine + ((size_t)(2 * I) * nyf + 2 * J) * K;
   const double* b = fine + ((size_t)(2 * I + 1) * nyf + 2 * J) * K;
   const double* c = fine + ((size_t)(2 * I) * nyf + 2 * J + 1) * K;
   const double* d = fine + ((size_t)(2 * I + 1) * nyf + 2 * J + 1) * K;
-  double* o = coarse + (size_t)blockIdx.x * K;
   for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] = 0.25 * (a[k] + b[k] + c[k] + d[k]);
 }
 
 // bc <- bc + restrict(res): bc holds R_H(f0) on entry (eq. coarse)
 __global__ void __launch_bounds__(kCavThreads) k_cav_fas_rhs(double* __restrict__ bc, int nyc,
-                                                             const double* __restrict__ res, int nyf, int K) {
+                                                             const double* __restrict__ res, int nyf, int K, int uy) {
+  if (uy) {
+    const double* a = res + (size_t)(2 * blockIdx.x) * K;
+    const double* b = a + K;
+    double* o = bc + (size_t)blockIdx.x * K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) o[k] += 0.5 * (a[k] + b[k]);
+    return;
+  }
   const int I = blockIdx.x / nyc, J = blockIdx.x - (blockIdx.x / nyc) * nyc;
   const double* a = res + ((size_t)(2 * I) * nyf + 2 * J) * K;
   const double* b = res + ((size_t)(2 * I + 1) * nyf + 2 * J) * K;
@@ -556,7 +577,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_prolong_add(double* __restr
 CavWalls walls_of(const bz_cavity* cv) {
   CavWalls wl{};
   for (int s = 0; s < 4; ++s) {
-    wl.T[s] = cv->walls[s].T;
+    wl.T[s] = cv->walls[s].T > 0 ? cv->walls[s].T : 1.0;  // y sides of a uniform_y cavity are unused
     wl.U1[s] = cv->walls[s].U[0];
     wl.U2[s] = cv->walls[s].U[1];
   }
@@ -606,7 +627,7 @@ bz_status cav_static(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
     if (s != BZ_OK) return s;
   }
   hipLaunchKernelGGL(k_cav_static, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.b, L.sx, L.sy, L.nx,
-                     L.ny, L.dx, L.dy, L.rs, L.nu,
+                     L.ny, cv->uy, L.dx, L.dy, L.rs, L.nu,
                      ctx->d_nodes, ctx->N, ctx->w, cv->eps, bgk ? 1 : 0, cv->bgk_nu, ctx->p.gamma, ctx->nu_gfac);
   BZ_HIP(hipGetLastError());
   return BZ_OK;
@@ -620,7 +641,8 @@ bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, dou
                     : v2_eval_q(ctx, L.f, L.Q, L.ncell, true, true, L.theta, st);
   if (s == BZ_OK) s = cav_slopes(ctx, cv, L, st);
   if (s != BZ_OK) return s;
-  hipLaunchKernelGGL(k_cav_resid, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.nx, L.ny, L.dx, L.dy,
+  hipLaunchKernelGGL(k_cav_resid, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.Q, L.theta, L.nx, L.ny, cv->uy,
+                     L.dx, L.dy,
                      cv->eps, walls_of(cv), ctx->d_nodes, ctx->N, ctx->w, bgk ? 1 : 0, cv->bgk_nu, L.b, L.sx, L.sy,
                      res, L.part);
   BZ_HIP(hipGetLastError());
@@ -637,14 +659,14 @@ bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, dou
 bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
   const CavWalls wl = walls_of(cv);
-  for (int sc = 0; sc < 4; ++sc) {
+  for (int sc = 0; sc < (cv->uy ? 2 : 4); ++sc) {
     bz_status s = cav_static(ctx, cv, L, st);
     if (s != BZ_OK) return s;
     for (int dd = 0; dd <= L.nx + L.ny - 2; ++dd) {
       const int lo = dd - (L.ny - 1) > 0 ? dd - (L.ny - 1) : 0;
       const int hi = dd < L.nx - 1 ? dd : L.nx - 1;
       hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.sx, L.sy, L.nx,
-                         L.ny, dd,
+                         L.ny, cv->uy, dd,
                          scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
                          cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters, cv->d_stats);
       BZ_HIP(hipGetLastError());
@@ -672,7 +694,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
   for (int q = 0; q < o.nu1; ++q)
     if ((s = cav_sgs(ctx, cv, L, st)) != BZ_OK) return s;
   double r = 0.0;
-  if ((L.nx < L.ny ? L.nx : L.ny) <= o.coarsest) {
+  if ((cv->uy ? L.nx : (L.nx < L.ny ? L.nx : L.ny)) <= o.coarsest) {
     double r0 = 0.0;
     if ((s = cav_residual(ctx, cv, L, nullptr, &r0, st)) != BZ_OK) return s;
     for (int q = 0; q < o.coarse_iters; ++q) {
@@ -689,7 +711,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
   if (l + 1 >= cv->lv.size()) {
     CavLevel C;
     C.nx = L.nx / 2;
-    C.ny = L.ny / 2;
+    C.ny = cv->uy ? L.ny : L.ny / 2;
     C.ncell = C.nx * C.ny;
     C.dx = 1.0 / C.nx;
     C.dy = 1.0 / C.ny;
@@ -701,7 +723,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
   }
   CavLevel& Lf = cv->lv[l];  // the vector may have moved
   CavLevel& C = cv->lv[l + 1];
-  hipLaunchKernelGGL(k_cav_restrict, dim3(C.ncell), dim3(kCavThreads), 0, st, Lf.f, Lf.ny, C.f0, C.ny, K);
+  hipLaunchKernelGGL(k_cav_restrict, dim3(C.ncell), dim3(kCavThreads), 0, st, Lf.f, Lf.ny, C.f0, C.ny, K, cv->uy);
   BZ_HIP(hipGetLastError());
   BZ_HIP(hipMemcpyAsync(C.f, C.f0, (size_t)C.ncell * K * sizeof(double), hipMemcpyDeviceToDevice, st));
   // b_H = R_H(f0) + restrict(b - R_h(f)): the residual field of f0 with no source, negated
@@ -713,7 +735,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
   if (s != BZ_OK) return s;
   hipLaunchKernelGGL(k_cav_negate, dim3(C.ncell), dim3(kCavThreads), 0, st, C.b, K);
   BZ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cav_fas_rhs, dim3(C.ncell), dim3(kCavThreads), 0, st, C.b, C.ny, Lf.res, Lf.ny, K);
+  hipLaunchKernelGGL(k_cav_fas_rhs, dim3(C.ncell), dim3(kCavThreads), 0, st, C.b, C.ny, Lf.res, Lf.ny, K, cv->uy);
   BZ_HIP(hipGetLastError());
   if ((s = cav_vcycle(ctx, cv, l + 1, o, st)) != BZ_OK) return s;
   CavLevel& Lf2 = cv->lv[l];
@@ -758,7 +780,8 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK)
     return set_err(ctx, BZ_EINVAL, "collision must be BZ_COLL_BINARY or BZ_COLL_BGK");
   if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
-  for (int s = 0; s < 4; ++s) {
+  if (d->uniform_y != 0 && d->ny != 1) return set_err(ctx, BZ_EINVAL, "uniform_y needs ny = 1");
+  for (int s = 0; s < (d->uniform_y ? 2 : 4); ++s) {
     const bz_wall& wl = d->walls[s];
     if (!(wl.T > 0) || !std::isfinite(wl.T) || !std::isfinite(wl.U[0]) || !std::isfinite(wl.U[1]))
       return set_err(ctx, BZ_EINVAL, "wall temperature must be > 0 and velocities finite");
@@ -780,6 +803,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   cv->bgk_nu = d->bgk_nu;
   cv->opts = o;
   cv->order = d->order == 2 ? 2 : 1;
+  cv->uy = d->uniform_y != 0;
   CavLevel L0;
   L0.nx = d->nx;
   L0.ny = d->ny;
@@ -833,10 +857,11 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int 
     return set_err(ctx, BZ_EINVAL, "bad multigrid options");
   {
     int nx = cv->lv[0].nx, ny = cv->lv[0].ny;
-    while ((nx < ny ? nx : ny) > o->coarsest) {
-      if (nx % 2 || ny % 2) return set_err(ctx, BZ_EINVAL, "nx and ny must halve evenly down to the coarsest level");
+    while ((cv->uy ? nx : (nx < ny ? nx : ny)) > o->coarsest) {
+      if (nx % 2 || (!cv->uy && ny % 2))
+        return set_err(ctx, BZ_EINVAL, "nx and ny must halve evenly down to the coarsest level");
       nx /= 2;
-      ny /= 2;
+      if (!cv->uy) ny /= 2;
     }
   }
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");

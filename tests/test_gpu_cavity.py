@@ -138,3 +138,32 @@ def test_cavity_vcycles_reach_the_sgs_state(bz):
     assert (fg - f1).abs().max().item() < 1e-7 * f1.abs().max().item()
     with pytest.raises(bzm.BZError):  # 8 -> 4 -> 2 -> 1 would have to halve 1
         cav.vcycle(1, coarsest=0)
+
+
+@pytest.mark.parametrize("collision,order", [("bgk", 1), ("binary", 1), ("binary", 2)])
+def test_plates_uniform_in_y_match_oracle(bz, collision, order):
+    # the slab between two plates with 2D velocities (one cell row, no y
+    # transport): two SGS iterations, then one V-cycle forced to descend
+    nx = 8
+    walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)))
+    print(f"plates {collision} order {order}", flush=True)
+    sp = Spec(d=2, N=8, L=4.0, n_phi=8, n_rho=4)
+    prob = CV.Cavity(spec=sp, nx=nx, ny=1, eps=0.1, walls=walls, collision=collision, fixed_inner=2, order=order,
+                     uniform_y=True)
+    f0 = CV.initial_state(prob, T=1.2)
+    ctx = bz.Context(N=8, L=4.0, n_phi=8, n_rho=4, d=2)
+    fg = torch.from_numpy(f0.reshape(nx, -1).copy()).to("cuda:0").contiguous()
+    cav = bz.Cavity(ctx, nx, 1, 0.1, walls, fg, collision=collision, fixed_iters=2, order=order, uniform_y=True)
+    res, st = cav.sweep(2)
+    f = CV.sgs_iteration(prob, CV.sgs_iteration(prob, f0))
+    err = np.abs(fg.cpu().numpy().reshape(nx, 1, -1) - f).max() / f.max()
+    print(f"sweeps: max rel diff {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert abs(res - CV.outer_residual(prob, f)) < 1e-9 * res
+    assert st["visits"] == 2 * 2 * nx
+    res, _ = cav.vcycle(1, coarsest=2, nu1=1, nu2=1, coarse_iters=3, tol=0.0)
+    f = CV.vcycle(prob, f, None, coarsest=2, nu1=1, nu2=1, tol=0.0, coarse_iters=3)
+    f = f * (prob.mass / CV.total_mass(prob, f))
+    err = np.abs(fg.cpu().numpy().reshape(nx, 1, -1) - f).max() / f.max()
+    print(f"V-cycle: max rel diff {err:.3e}", flush=True)
+    assert err < 1e-10
