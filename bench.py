@@ -388,6 +388,63 @@ def cavity_workload(args):
     return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
+def plates_workload(args):
+    """Section 4.2's 1D2V heat transfer between parallel plates: dx = 1/128 (128
+    cells), 32^2 velocities, R = 3 and L = (3 sqrt 2 + 1) R / 2, plates at rest
+    with T = 1 (x = 0) and T = 2 (x = 1), Maxwell molecules (M = 32 and
+    n_rho = 16, which the paper does not state), from the uniform unit
+    Maxwellian (mass 1), to the outer residual 1e-5.  SGS-PFP and MG-SGS-PFP
+    (V-cycles to 4 cells, one pre- and one post-smoothing step at first order;
+    to 8 cells with five pre- and one post-smoothing steps at second order, tab.
+    mg), each case capped at 120 s."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+
+    n, nx, tol = 32, 128, 1e-5
+    L = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
+    dv = 2.0 * L / n
+    x = (np.arange(n) - n // 2 + 1) * dv
+    V = np.stack(np.meshgrid(x, x, indexing="ij"), -1).reshape(-1, 2)
+    m = np.exp(-(V * V).sum(1) / 2.0) / (2.0 * np.pi)
+    walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)))
+    ctx = bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2)
+    out = {}
+    for order in (1, 2):
+        for method in ("sgs", "mg"):
+            for eps in (1.0, 0.1, 0.01, 0.001):
+                key = f"order{order}_{method}_eps{eps:g}"
+                if args.plates_case not in ("all", key):
+                    continue
+                f0 = np.repeat(m[None], nx, axis=0)
+                f0 *= 1.0 / (dv * dv * f0.sum() / nx)
+                f = torch.from_numpy(f0).cuda().contiguous()
+                cav = bz.Cavity(ctx, nx, 1, eps, walls, f, tol=1e-8, max_iter=100, order=order, uniform_y=True)
+                torch.cuda.synchronize()
+                t0 = last = time.perf_counter()
+                hist, inner, visits = [cav.residual()], 0, 0
+                while hist[-1] >= tol and len(hist) <= 20000 and time.perf_counter() - t0 < 120.0:
+                    if method == "sgs":
+                        r, st = cav.sweep(1)
+                    elif order == 1:
+                        r, st = cav.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
+                    else:
+                        r, st = cav.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
+                    hist.append(r)
+                    inner += st["inner_iters"]
+                    visits += st["visits"]
+                    if time.perf_counter() - last > 10.0:
+                        last = time.perf_counter()
+                        print(f"# plates {key} iteration {len(hist) - 1} residual {r:.3e}", flush=True)
+                dt = time.perf_counter() - t0
+                cav.close()
+                out[key] = {"seconds": dt, "iterations": len(hist) - 1, "final_residual": hist[-1],
+                            "reached": hist[-1] < tol, "mean_inner_iterations": inner / max(visits, 1)}
+                print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    return {"workload": "plates", "data": "synthetic", "dtype": "f64", "runs": out}
+
+
 def shock_workload(args, tol=1e-8):
     """Normal shocks between Rankine-Hugoniot inflow states, x in [-20, 20], 128
     cells, 32^3 velocities on [-8, 8]^3 shifted along v_1 to the mean of the two
@@ -539,12 +596,17 @@ def main():
                                for e in ("1", "0.1", "0.01", "0.001")]
                             + ["n48_64x64_mg_eps0.1", "batched_q_48x48"],
                     help="with --workload cavity: run one case only")
-    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity"], default="batched-q",
+    ap.add_argument("--plates-case", default="all",
+                    choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg")
+                                       for e in ("1", "0.1", "0.01", "0.001")],
+                    help="with --workload plates: run one case only")
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
                          "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded); "
                          "order: first/second-order accuracy study on the BGK heat slab; "
-                         "cavity: 2D2V lid-driven cavity and the batched 2D collision term")
+                         "cavity: 2D2V lid-driven cavity and the batched 2D collision term; "
+                         "plates: 1D2V heat transfer between parallel plates")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -570,6 +632,9 @@ def main():
         return
     if args.workload == "cavity":
         print(json.dumps(cavity_workload(args)), flush=True)
+        return
+    if args.workload == "plates":
+        print(json.dumps(plates_workload(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")
