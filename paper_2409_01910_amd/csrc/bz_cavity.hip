@@ -17,7 +17,7 @@
 // eq. inner_eqn, c g + r = (nu/eps)(M[g] - g), c = |v1|/dx + |v2|/dy, by the
 // preconditioned iteration of eqs. step1 and step2 (or the plain eq. fix_point):
 // step 1's weighted Newton and the discrete Maxwellian are 4-parameter Newton
-// solves whose sums run over the cell's N^2 points in the workgroup.
+// solves whose sums separate over the two velocity axes (1D sums per wave).
 #include <cmath>
 #include <vector>
 
@@ -76,23 +76,49 @@ __device__ __forceinline__ double wall_m(const CavWalls& wl, int s, double x, do
 }
 
 // s[0..3] = sum w c phi_i exp(theta.phi~), s[4..13] = sum w c phi_i phi_j exp(theta.phi~)
-// (upper triangle by rows), phi = (1, x, y, x^2 + y^2), over the cell's points
-__device__ __forceinline__ void wsums(const double* th, const double (&x)[kCavOwn], const double (&y)[kCavOwn],
-                                     const double (&c)[kCavOwn], int K, double w, double* red, double (&s)[14]) {
-  for (int q = 0; q < 14; ++q) s[q] = 0.0;
+// (upper triangle by rows), phi = (1, x, y, x^2 + y^2), over the N x N grid.  On
+// the tensor grid the Gaussian factorises, exp(alpha) E0(x) E1(y) with
+// E_a(u) = exp(beta_a u - gamma u^2), and the weight is c = 1 or the additive
+// c = a0 |x| + a1 |y|, so every sum is a combination of 1D sums over the N nodes:
+//   sum c x^p y^q E0 E1 = a0 Ac_p B_q + a1 A_p Bc_q   (or A_p B_q for c = 1),
+//   A_p = sum x^p E0, Ac_p = sum |x| x^p E0, B_q, Bc_q the same with E1.
+// Each wave forms the 1D sums itself (lane l holds node l, N <= 64) with DPP
+// reductions: no LDS and no block synchronisation.
+__device__ __forceinline__ void sep_sums(const double* th, const double* nodes, int N, double w, bool weighted,
+                                         double a0, double a1, double (&s)[14]) {
+  const int l = threadIdx.x & 63;
+  const bool on = l < N;
+  const double u = on ? nodes[l] : 0.0;
+  const double e0 = on ? exp(th[1] * u - th[3] * u * u) : 0.0;
+  const double e1 = on ? exp(th[2] * u - th[3] * u * u) : 0.0;
+  const double au = fabs(u);
+  double v[20];
+  double up = 1.0;
 #pragma unroll
-  for (int i = 0; i < kCavOwn; ++i) {
-    const int k = threadIdx.x + i * kCavThreads;
-    if (k < K) {
-      const double e = w * c[i] * gauss2c(th, x[i], y[i]);
-      const double ph[4] = {1.0, x[i], y[i], x[i] * x[i] + y[i] * y[i]};
-      for (int a = 0; a < 4; ++a) s[a] += ph[a] * e;
-      int o = 4;
-      for (int a = 0; a < 4; ++a)
-        for (int b = a; b < 4; ++b) s[o++] += ph[a] * ph[b] * e;
-    }
+  for (int p = 0; p < 5; ++p) {
+    v[p] = e0 * up;
+    v[5 + p] = e1 * up;
+    v[10 + p] = au * e0 * up;
+    v[15 + p] = au * e1 * up;
+    up *= u;
   }
-  block_sum<14>(s, red);
+  wave_sums_dpp<20>(v);
+  auto S = [&](int p, int q) { return weighted ? a0 * v[10 + p] * v[5 + q] + a1 * v[p] * v[15 + q] : v[p] * v[5 + q]; };
+  const double sc = w * exp(th[0]);
+  s[0] = sc * S(0, 0);
+  s[1] = sc * S(1, 0);
+  s[2] = sc * S(0, 1);
+  s[3] = sc * (S(2, 0) + S(0, 2));
+  s[4] = s[0];
+  s[5] = s[1];
+  s[6] = s[2];
+  s[7] = s[3];
+  s[8] = sc * S(2, 0);
+  s[9] = sc * S(1, 1);
+  s[10] = sc * (S(3, 0) + S(1, 2));
+  s[11] = sc * S(0, 2);
+  s[12] = sc * (S(2, 1) + S(0, 3));
+  s[13] = sc * (S(4, 0) + 2.0 * S(2, 2) + S(0, 4));
 }
 
 __device__ __forceinline__ bool spd4_solve(double G[4][4], const double b[4], double y[4]) {
@@ -128,8 +154,8 @@ __device__ __forceinline__ bool spd4_solve(double G[4][4], const double b[4], do
 // Step halving while the max-norm residual does not decrease.  Returns true
 // when converged (residual <= 1e-13 (|t_0| + |t_3|), or a stalled step with
 // residual <= 1e-10 of that scale).
-__device__ bool newton4(double (&th)[4], const double (&t)[4], bool guess, const double (&x)[kCavOwn],
-                        const double (&y)[kCavOwn], const double (&c)[kCavOwn], int K, double w, double* red) {
+__device__ bool newton4(double (&th)[4], const double (&t)[4], bool guess, const double* nodes, int N, double w,
+                        bool weighted, double a0, double a1) {
   if (guess) {
     const double rho = t[0], U0 = t[1] / rho, U1 = t[2] / rho;
     double T = (t[3] / rho - U0 * U0 - U1 * U1) / 2.0;
@@ -141,7 +167,7 @@ __device__ bool newton4(double (&th)[4], const double (&t)[4], bool guess, const
   }
   const double scale = fabs(t[0]) + fabs(t[3]) + 1e-300, tol = 1e-13;
   double s[14], r[4];
-  wsums(th, x, y, c, K, w, red, s);
+  sep_sums(th, nodes, N, w, weighted, a0, a1, s);
   double nrm = 0.0;
   for (int i = 0; i < 4; ++i) {
     r[i] = s[i] - t[i];
@@ -166,7 +192,7 @@ __device__ bool newton4(double (&th)[4], const double (&t)[4], bool guess, const
     double a = 1.0, thn[4], sn[14], n_new = INFINITY;
     while (true) {
       for (int i = 0; i < 4; ++i) thn[i] = th[i] + a * step[i];
-      wsums(thn, x, y, c, K, w, red, sn);
+      sep_sums(thn, nodes, N, w, weighted, a0, a1, sn);
       n_new = 0.0;
       for (int i = 0; i < 4; ++i) n_new = fmax(n_new, fabs(sn[i] - t[i]));
       if (!isfinite(n_new)) n_new = INFINITY;
@@ -249,12 +275,11 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
   const double* fN = j < ny - 1 ? f + (cell + 1) * K : nullptr;
   const double lam = nu[cell] / eps;
-  double x[kCavOwn], y[kCavOwn], c[kCavOwn], one[kCavOwn], g[kCavOwn], r[kCavOwn], Mg[kCavOwn];
+  double x[kCavOwn], y[kCavOwn], c[kCavOwn], g[kCavOwn], r[kCavOwn], Mg[kCavOwn];
 #pragma unroll
   for (int q = 0; q < kCavOwn; ++q) {
     const int k = threadIdx.x + q * kCavThreads;
     x[q] = y[q] = c[q] = g[q] = r[q] = Mg[q] = 0.0;
-    one[q] = 1.0;
     if (k < K) {
       x[q] = nodes[k / N];
       y[q] = nodes[k % N];
@@ -287,9 +312,10 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     block_sum<4>(v, red);
     for (int q = 0; q < 4; ++q) t[q] = v[q];
   };
+  const double a0 = 1.0 / dx, a1 = uy ? 0.0 : 1.0 / dy;  // c = a0 |v1| + a1 |v2|
   double th_g[4], t4[4];
   moments_of(g, t4);
-  (void)newton4(th_g, t4, true, x, y, one, K, w, red);
+  (void)newton4(th_g, t4, true, nodes, N, w, false, a0, a1);
 #pragma unroll
   for (int q = 0; q < kCavOwn; ++q) Mg[q] = gauss2c(th_g, x[q], y[q]);
   double th_step[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
@@ -306,7 +332,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
       moments_of(sv, s4);
       bool ok = s4[0] > 0.0 && s4[0] * s4[3] > s4[1] * s4[1] + s4[2] * s4[2];
       double th[4] = {th_step[0], th_step[1], th_step[2], th_step[3]};
-      if (ok) ok = newton4(th, s4, false, x, y, c, K, w, red) && th[3] > 0.0;
+      if (ok) ok = newton4(th, s4, false, nodes, N, w, true, a0, a1) && th[3] > 0.0;
       if (ok) {
         for (int a = 0; a < 4; ++a) th_step[a] = th[a];
 #pragma unroll
@@ -329,10 +355,10 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     // moments when that start fails
     {
       double th_w[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
-      if (newton4(th_w, t4, false, x, y, one, K, w, red)) {
+      if (newton4(th_w, t4, false, nodes, N, w, false, a0, a1)) {
         for (int a = 0; a < 4; ++a) th_g[a] = th_w[a];
       } else {
-        (void)newton4(th_g, t4, true, x, y, one, K, w, red);
+        (void)newton4(th_g, t4, true, nodes, N, w, false, a0, a1);
       }
     }
     double e2[1] = {0.0};
