@@ -35,10 +35,30 @@ namespace {
 
 constexpr int kV2Threads = 512;
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// complex values of the transform stage: double2 (FP64) or float2 (FP32)
+template <typename T>
+struct Cx;
+template <>
+struct Cx<double> {
+  using C = double2;
+  __device__ static C make(double a, double b) { return make_double2(a, b); }
+};
+template <>
+struct Cx<float> {
+  using C = float2;
+  __device__ static C make(float a, float b) { return make_float2(a, b); }
+};
+template <typename T>
+using cx_t = typename Cx<T>::C;
+
+template <typename T>
+__device__ __forceinline__ cx_t<T> cmul(cx_t<T> a, cx_t<T> b) {
+  return Cx<T>::make(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cx_t<T> cconj(cx_t<T> a) {
+  return Cx<T>::make(a.x, -a.y);
+}
 
 // The q-th radix of a length-n transform: 4 while it divides, then 3, then 2
 // (1 past the last pass).
@@ -51,31 +71,32 @@ constexpr int radix_at(int n, int q) {
 }
 
 // y_k = sum_m v_m exp(SIGN 2 pi i m k / R), in place, R in {2, 3, 4}
-template <int R, int SIGN>
-__device__ __forceinline__ void small_dft(double2 (&v)[R]) {
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void small_dft(cx_t<T> (&v)[R]) {
+  using X = Cx<T>;
   if constexpr (R == 2) {
-    const double2 a = v[0], b = v[1];
-    v[0] = make_double2(a.x + b.x, a.y + b.y);
-    v[1] = make_double2(a.x - b.x, a.y - b.y);
+    const cx_t<T> a = v[0], b = v[1];
+    v[0] = X::make(a.x + b.x, a.y + b.y);
+    v[1] = X::make(a.x - b.x, a.y - b.y);
   } else if constexpr (R == 3) {
-    constexpr double h = 0.86602540378443864676 * SIGN;  // SIGN * sqrt(3) / 2
-    const double2 t1 = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
-    const double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
-    const double2 t3 = make_double2(h * (v[1].x - v[2].x), h * (v[1].y - v[2].y));
-    v[0] = make_double2(v[0].x + t1.x, v[0].y + t1.y);
+    const T h = T(0.86602540378443864676 * SIGN);  // SIGN * sqrt(3) / 2
+    const cx_t<T> t1 = X::make(v[1].x + v[2].x, v[1].y + v[2].y);
+    const cx_t<T> t2 = X::make(v[0].x - T(0.5) * t1.x, v[0].y - T(0.5) * t1.y);
+    const cx_t<T> t3 = X::make(h * (v[1].x - v[2].x), h * (v[1].y - v[2].y));
+    v[0] = X::make(v[0].x + t1.x, v[0].y + t1.y);
     // i * t3 = (-t3.y, t3.x)
-    v[1] = make_double2(t2.x - t3.y, t2.y + t3.x);
-    v[2] = make_double2(t2.x + t3.y, t2.y - t3.x);
+    v[1] = X::make(t2.x - t3.y, t2.y + t3.x);
+    v[2] = X::make(t2.x + t3.y, t2.y - t3.x);
   } else {
-    const double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
-    const double2 b = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
-    const double2 c = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+    const cx_t<T> a = X::make(v[0].x + v[2].x, v[0].y + v[2].y);
+    const cx_t<T> b = X::make(v[0].x - v[2].x, v[0].y - v[2].y);
+    const cx_t<T> c = X::make(v[1].x + v[3].x, v[1].y + v[3].y);
     // SIGN * i * (v1 - v3)
-    const double2 e = make_double2(-SIGN * (v[1].y - v[3].y), SIGN * (v[1].x - v[3].x));
-    v[0] = make_double2(a.x + c.x, a.y + c.y);
-    v[2] = make_double2(a.x - c.x, a.y - c.y);
-    v[1] = make_double2(b.x + e.x, b.y + e.y);
-    v[3] = make_double2(b.x - e.x, b.y - e.y);
+    const cx_t<T> e = X::make(T(-SIGN) * (v[1].y - v[3].y), T(SIGN) * (v[1].x - v[3].x));
+    v[0] = X::make(a.x + c.x, a.y + c.y);
+    v[2] = X::make(a.x - c.x, a.y - c.y);
+    v[1] = X::make(b.x + e.x, b.y + e.y);
+    v[3] = X::make(b.x - e.x, b.y - e.y);
   }
 }
 
@@ -84,52 +105,53 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R]) {
 // values apart, and consecutive threads take consecutive lines, so that the
 // lanes of a wave hit distinct LDS banks along either axis.  NS is the product
 // of the radices of the earlier passes on this axis; tw[q] = exp(2 pi i q / N).
-template <int N, int R, int NS, int AXIS, int SIGN>
-__device__ __forceinline__ void stockham_pass(const double2* __restrict__ src, double2* __restrict__ dst,
-                                              const double2* tw) {
+template <typename T, int N, int R, int NS, int AXIS, int SIGN>
+__device__ __forceinline__ void stockham_pass(const cx_t<T>* __restrict__ src, cx_t<T>* __restrict__ dst,
+                                              const cx_t<T>* tw) {
   constexpr int NR = N / R, items = N * NR, step = N / (NS * R), P = N + 1;
   constexpr int es = AXIS == 1 ? 1 : P, ls = AXIS == 1 ? P : 1;
   for (int t = threadIdx.x; t < items; t += blockDim.x) {
     const int j = t / N, line = t - j * N;
     const int k = j % NS;
     const int base = line * ls;
-    double2 v[R];
+    cx_t<T> v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = src[base + (j + m * NR) * es];
 #pragma unroll
     for (int m = 1; m < R; ++m) {
-      double2 w = tw[k * m * step];
-      if (SIGN < 0) w = cconj(w);
-      v[m] = cmul(v[m], w);
+      cx_t<T> w = tw[k * m * step];
+      if (SIGN < 0) w = cconj<T>(w);
+      v[m] = cmul<T>(v[m], w);
     }
-    small_dft<R, SIGN>(v);
+    small_dft<T, R, SIGN>(v);
     const int d0 = (j / NS) * NS * R + k;
 #pragma unroll
     for (int m = 0; m < R; ++m) dst[base + (d0 + m * NS) * es] = v[m];
   }
 }
 
-template <int N, int SIGN, int AXIS, int Q, int NS>
-__device__ __forceinline__ void axis_passes(double2*& src, double2*& dst, const double2* tw) {
+template <typename T, int N, int SIGN, int AXIS, int Q, int NS>
+__device__ __forceinline__ void axis_passes(cx_t<T>*& src, cx_t<T>*& dst, const cx_t<T>* tw) {
   constexpr int R = radix_at(N, Q);
   if constexpr (R > 1) {
-    stockham_pass<N, R, NS, AXIS, SIGN>(src, dst, tw);
+    stockham_pass<T, N, R, NS, AXIS, SIGN>(src, dst, tw);
     __syncthreads();
-    double2* t = src;
+    cx_t<T>* t = src;
     src = dst;
     dst = t;
-    axis_passes<N, SIGN, AXIS, Q + 1, NS * R>(src, dst, tw);
+    axis_passes<T, N, SIGN, AXIS, Q + 1, NS * R>(src, dst, tw);
   }
 }
 
 // 2D transform X_k = sum_j x_j exp(SIGN 2 pi i k.j / N) of tile a (b is the
 // ping-pong partner); returns the tile that holds the result.  Synchronises
 // before returning.
-template <int N, int SIGN>
-__device__ __forceinline__ double2* dft2(double2* a, double2* b, const double2* tw) {
-  double2 *src = a, *dst = b;
-  axis_passes<N, SIGN, 1, 0, 1>(src, dst, tw);
-  axis_passes<N, SIGN, 0, 0, 1>(src, dst, tw);
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ cx_t<T>* dft2(cx_t<T>* a, cx_t<T>* b, const cx_t<T>* tw) {
+  cx_t<T>* src = a;
+  cx_t<T>* dst = b;
+  axis_passes<T, N, SIGN, 1, 0, 1>(src, dst, tw);
+  axis_passes<T, N, SIGN, 0, 0, 1>(src, dst, tw);
   return src;
 }
 
@@ -141,28 +163,35 @@ __device__ __forceinline__ double gauss2(const double* th, double x, double y) {
 }
 
 // Collision term of one cell per workgroup.  theta (corrected only) holds the
-// cell's discrete Maxwellian.  mass: Q <- Q - M sum(Q) / sum(M).
-template <int N>
-__global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f, const double* __restrict__ theta,
+// cell's discrete Maxwellian.  mass: Q <- Q - M sum(Q) / sum(M).  T is the
+// arithmetic of the transform stage (transforms, direction products and their
+// accumulation); the fields g, h, M, the loss combination, Q and the mass
+// projection are FP64.
+template <typename T, int N>
+__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_q2(const double* __restrict__ f, const double* __restrict__ theta,
                                                    double* __restrict__ Q,
                                                    const double* __restrict__ nodes, const double* __restrict__ xi,
                                                    const double* __restrict__ tw_g, const double* __restrict__ dir,
                                                    const double* __restrict__ rho, int n_rho, int n_pairs,
                                                    double w_pair, const double* __restrict__ W,
                                                    const double* __restrict__ Gm, int corrected, int mass) {
-  extern __shared__ double2 smem[];
+  using C = cx_t<T>;
+  using X = Cx<T>;
+  extern __shared__ double2 smem_[];
+  C* smem = reinterpret_cast<C*>(smem_);
   constexpr int K = N * N, KP = N * (N + 1);  // KP: a transform tile with padded rows
   constexpr int kV2Own = (K + kV2Threads - 1) / kV2Threads;
   const int cell = blockIdx.x, tid = threadIdx.x;
-  double2* SG = smem;
-  double2* SH = SG + K;
-  double2* B0 = SH + K;
-  double2* B1 = B0 + KP;
-  double2* TW = B1 + KP;
-  double2* E0 = TW + N;
-  double2* E1 = E0 + N;
+  C* SG = smem;
+  C* SH = SG + K;
+  C* B0 = SH + K;
+  C* B1 = B0 + KP;
+  C* TW = B1 + KP;
+  C* E0 = TW + N;
+  C* E1 = E0 + N;
   double* red = reinterpret_cast<double*>(E1 + N);
-  for (int j = tid; j < N; j += blockDim.x) TW[j] = make_double2(tw_g[2 * j], tw_g[2 * j + 1]);
+  for (int j = tid; j < N; j += blockDim.x) TW[j] = X::make(T(tw_g[2 * j]), T(tw_g[2 * j + 1]));
 
   const double* fc = f + (size_t)cell * K;
   double th[4] = {0.0, 0.0, 0.0, 0.0};
@@ -182,33 +211,33 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
       } else {
         g[i] = h[i] = fv;
       }
-      B0[tix(k, N)] = make_double2(g[i], h[i]);
+      B0[tix(k, N)] = X::make(T(g[i]), T(h[i]));
     }
   }
   __syncthreads();
   // spectra: Z = DFT(g + i h); gh_l = (Z_l + conj Z_-l) / 2K, hh_l = (Z_l - conj Z_-l) / 2iK,
   // Nyquist modes zeroed
   {
-    const double2* Z = dft2<N, -1>(B0, B1, TW);
-    const double s = 0.5 / K;
+    const C* Z = dft2<T, N, -1>(B0, B1, TW);
+    const T s = T(0.5 / K);
     for (int k = tid; k < K; k += blockDim.x) {
       const int l1 = k / N, l2 = k - l1 * N;
       const int m = ((N - l1) % N) * N + (N - l2) % N;
-      const double2 a = Z[tix(k, N)], b = Z[tix(m, N)];
+      const C a = Z[tix(k, N)], b = Z[tix(m, N)];
       const bool nyq = l1 == N / 2 || l2 == N / 2;
-      SG[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.x + b.x), s * (a.y - b.y));
-      SH[k] = nyq ? make_double2(0.0, 0.0) : make_double2(s * (a.y + b.y), -s * (a.x - b.x));
+      SG[k] = nyq ? X::make(T(0), T(0)) : X::make(s * (a.x + b.x), s * (a.y - b.y));
+      SH[k] = nyq ? X::make(T(0), T(0)) : X::make(s * (a.y + b.y), -s * (a.x - b.x));
     }
     __syncthreads();
   }
 
-  double qr[kV2Own], qi[kV2Own];
+  T qr[kV2Own], qi[kV2Own];
 #pragma unroll
-  for (int i = 0; i < kV2Own; ++i) qr[i] = qi[i] = 0.0;
+  for (int i = 0; i < kV2Own; ++i) qr[i] = qi[i] = T(0);
   for (int r = 0; r < n_rho; ++r) {
-    double acc[kV2Own];
+    T acc[kV2Own];
 #pragma unroll
-    for (int i = 0; i < kV2Own; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kV2Own; ++i) acc[i] = T(0);
     for (int p = 0; p < n_pairs; ++p) {
       // axis phases exp(i xi_l s_a), s = rho_r sigma_p / 2
       if (tid < 2 * N) {
@@ -216,31 +245,32 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
         const double sa = 0.5 * rho[r] * dir[2 * p + a];
         double sn, cs;
         sincos(xi[l] * sa, &sn, &cs);
-        (a == 0 ? E0 : E1)[l] = make_double2(cs, sn);
+        (a == 0 ? E0 : E1)[l] = X::make(T(cs), T(sn));
       }
       __syncthreads();
-      double ag[kV2Own], bh[kV2Own];
+      T ag[kV2Own], bh[kV2Own];
+      const T wp = T(w_pair), hwp = T(0.5 * w_pair);
       for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
-        const double2* X = pass == 0 ? SG : SH;
-        const double2* Y = pass == 0 ? SH : SG;
+        const C* Xs = pass == 0 ? SG : SH;
+        const C* Ys = pass == 0 ? SH : SG;
         for (int k = tid; k < K; k += blockDim.x) {
-          const double2 ph = cmul(E0[k / N], E1[k % N]);
-          const double2 u = cmul(X[k], ph), w = cmul(Y[k], cconj(ph));
-          B0[tix(k, N)] = make_double2(u.x - w.y, u.y + w.x);  // u + i w
+          const C ph = cmul<T>(E0[k / N], E1[k % N]);
+          const C u = cmul<T>(Xs[k], ph), w = cmul<T>(Ys[k], cconj<T>(ph));
+          B0[tix(k, N)] = X::make(u.x - w.y, u.y + w.x);  // u + i w
         }
         __syncthreads();
-        const double2* T = dft2<N, +1>(B0, B1, TW);
+        const C* Tt = dft2<T, N, +1>(B0, B1, TW);
 #pragma unroll
         for (int i = 0; i < kV2Own; ++i) {
           const int k = tid + i * kV2Threads;
           if (k < K) {
-            const double2 t = T[tix(k, N)];
+            const C t = Tt[tix(k, N)];
             if (pass == 0) {
               ag[i] = t.x;
               bh[i] = t.y;
-              if (!corrected) acc[i] += w_pair * t.x * t.y;
+              if (!corrected) acc[i] += wp * t.x * t.y;
             } else {
-              acc[i] += 0.5 * w_pair * (ag[i] * bh[i] + t.x * t.y);
+              acc[i] += hwp * (ag[i] * bh[i] + t.x * t.y);
             }
           }
         }
@@ -250,18 +280,19 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
-      if (k < K) B0[tix(k, N)] = make_double2(acc[i], 0.0);
+      if (k < K) B0[tix(k, N)] = X::make(acc[i], T(0));
     }
     __syncthreads();
-    const double2* A = dft2<N, -1>(B0, B1, TW);
+    const C* A = dft2<T, N, -1>(B0, B1, TW);
     const double* Wr = W + (size_t)r * K;
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
       if (k < K) {
-        const double2 a = A[tix(k, N)];
-        qr[i] += Wr[k] * a.x;
-        qi[i] += Wr[k] * a.y;
+        const C a = A[tix(k, N)];
+        const T wr = T(Wr[k]);
+        qr[i] += wr * a.x;
+        qi[i] += wr * a.y;
       }
     }
     __syncthreads();
@@ -271,34 +302,34 @@ __global__ void __launch_bounds__(kV2Threads) k_q2(const double* __restrict__ f,
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
     const int k = tid + i * kV2Threads;
-    if (k < K) B0[tix(k, N)] = make_double2(qr[i], qi[i]);
+    if (k < K) B0[tix(k, N)] = X::make(qr[i], qi[i]);
   }
   __syncthreads();
   {
-    const double2* G = dft2<N, +1>(B0, B1, TW);
+    const C* G = dft2<T, N, +1>(B0, B1, TW);
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
       const int k = tid + i * kV2Threads;
-      gain[i] = k < K ? G[tix(k, N)].x : 0.0;
+      gain[i] = k < K ? double(G[tix(k, N)].x) : 0.0;
     }
     __syncthreads();
   }
   // loss: IDFT(Gm hh + i Gm gh) = L_h + i L_g;  Q- = (g L_h + h L_g) / 2
   for (int k = tid; k < K; k += blockDim.x) {
-    const double gm = Gm[k];
-    const double2 a = SH[k], b = SG[k];
-    B0[tix(k, N)] = make_double2(gm * (a.x - b.y), gm * (a.y + b.x));
+    const T gm = T(Gm[k]);
+    const C a = SH[k], b = SG[k];
+    B0[tix(k, N)] = X::make(gm * (a.x - b.y), gm * (a.y + b.x));
   }
   __syncthreads();
-  const double2* Lx = dft2<N, +1>(B0, B1, TW);
+  const C* Lx = dft2<T, N, +1>(B0, B1, TW);
   double q[kV2Own], sq = 0.0, sm = 0.0;
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
     const int k = tid + i * kV2Threads;
     q[i] = 0.0;
     if (k < K) {
-      const double2 l = Lx[tix(k, N)];
-      q[i] = gain[i] - 0.5 * (g[i] * l.x + h[i] * l.y);
+      const C l = Lx[tix(k, N)];
+      q[i] = gain[i] - 0.5 * (g[i] * double(l.x) + h[i] * double(l.y));
       sq += q[i];
       sm += Mk[i];
     }
@@ -444,8 +475,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_max2(const double* __restrict__
     for (int k = threadIdx.x; k < K; k += blockDim.x) Mout[(size_t)cell * K + k] = gauss2(th, nodes[k / N], nodes[k % N]);
 }
 
-size_t q2_lds_bytes(int N) {
-  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * sizeof(double2) + 2 * (kV2Threads / 64) * 8;
+size_t q2_lds_bytes(int N, size_t csize) {
+  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * csize + 2 * (kV2Threads / 64) * 8;
 }
 
 }  // namespace
@@ -476,15 +507,22 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
     bz_status s = v2_maxwellian(ctx, f, th, nullptr, nullptr, batch, st);
     if (s != BZ_OK) return s;
   }
-  const size_t lds = q2_lds_bytes(N);
+  const bool fp32 = ctx->p.precision == BZ_FP32;
+  const size_t lds = q2_lds_bytes(N, fp32 ? sizeof(float2) : sizeof(double2));
   const double w_pair = 2.0 * (2.0 * kPi / ctx->n_phi);
   const int corr = corrected ? 1 : 0, ms = mass ? 1 : 0;
-#define BZ_Q2_LAUNCH(NN)                                                                                         \
-  case NN:                                                                                                       \
-    BZ_HIP(hipFuncSetAttribute((const void*)k_q2<NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    hipLaunchKernelGGL(k_q2<NN>, dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,       \
-                       ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair, \
-                       ctx->d_W, ctx->d_Gm, corr, ms);                                                           \
+#define BZ_Q2_LAUNCH_T(TT, NN)                                                                                    \
+  BZ_HIP(hipFuncSetAttribute((const void*)k_q2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+  hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,    \
+                     ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,   \
+                     ctx->d_W, ctx->d_Gm, corr, ms);
+#define BZ_Q2_LAUNCH(NN)         \
+  case NN:                       \
+    if (fp32) {                  \
+      BZ_Q2_LAUNCH_T(float, NN)  \
+    } else {                     \
+      BZ_Q2_LAUNCH_T(double, NN) \
+    }                            \
     break;
   switch (N) {
     BZ_Q2_LAUNCH(8)
@@ -496,6 +534,7 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
     default: return set_err(ctx, BZ_EINVAL, "d = 2 needs N in {8, 12, 16, 24, 32, 48}");
   }
 #undef BZ_Q2_LAUNCH
+#undef BZ_Q2_LAUNCH_T
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

@@ -101,4 +101,23 @@ def test_2d_context_refuses_what_it_does_not_implement(bz):
     with pytest.raises(bz.BZError):
         bz.Context(N=20, L=4.0, n_phi=8, n_rho=4, d=2)
     with pytest.raises(bz.BZError):
-        bz.Context(N=8, L=4.0, n_phi=8, n_rho=4, d=2, precision=bz.BZ_FP32)
+        bz.Context(N=8, L=4.0, n_phi=8, n_rho=4, d=2, method=bz.BZ_METHOD_CARLEMAN, gamma=1.0)
+
+
+@pytest.mark.parametrize("N,L,M,nr", [(12, 6.0, 16, 6), (48, 8.0, 64, 24)])
+def test_eval_q_2d_fp32_spectral_stage_within_stated_bound(bz, N, L, M, nr):
+    # transforms, direction products and their accumulation in FP32; fields,
+    # Maxwellian, loss combination and mass projection in FP64.  Bound: 2e-6 of
+    # max(|Q|, |Q-|), as for the 3D FP32 stage
+    B = 3
+    sp = Spec(d=2, N=N, L=L, n_phi=M, n_rho=nr)
+    f = synth.mixture_batch(B, N, L, d=2, seed=43)
+    ctx = bz.Context(N=N, L=L, n_phi=M, n_rho=nr, d=2, precision=bz.BZ_FP32)
+    Q = ctx.eval_Q(_T(f), corrected=True, conserve="mass").cpu().numpy()
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i], conserve="mass")
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        err = float(np.abs(Q[i] - ref).max() / max(np.abs(ref).max(), np.abs(loss).max()))
+        print(f"FP32 d=2 N={N} cell {i} rel err {err:.3e}", flush=True)
+        assert err < 2e-6
+        assert abs(Q[i].sum()) < 1e-13 * np.abs(Q[i]).sum()
