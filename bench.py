@@ -274,7 +274,7 @@ def order_workload(args):
 
 
 def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5, order=1,
-                nu1=1, nu2=1):
+                nu1=1, nu2=1, fp32=False):
     """Lid-driven cavity on [0, 1]^2 (all walls T = 1, the lid y = 1 moving at
     (lid, 0)), n^2 velocities on [-l, l]^2, Maxwell molecules with M circle
     directions and nr radial nodes, first-order SGS-PFP FP64 (inner residual
@@ -294,7 +294,7 @@ def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, m
     f0 = np.repeat(m[None], nx * nx, axis=0)
     f0 *= 1.0 / (dv * dv * f0.sum() / (nx * nx))
     f = torch.from_numpy(f0).cuda().contiguous()
-    ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2)
+    ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2, precision=bz.BZ_FP32 if fp32 else bz.BZ_FP64)
     walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
     cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100, order=order)
     torch.cuda.synchronize()
@@ -359,32 +359,35 @@ def cavity_workload(args):
             out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 1000, 120.0, key, method="mg", coarsest=5,
                                    order=2, nu1=5, nu2=1)
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
-    key = "n48_64x64_mg_eps0.1"
-    if want(key):
-        out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 40, 90.0, key, method="mg", coarsest=4)
-        print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    for fp32 in (False, True):
+        key = "n48_64x64_mg_eps0.1" + ("_fp32" if fp32 else "")
+        if want(key):
+            out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 40, 90.0, key, method="mg", coarsest=4,
+                                   fp32=fp32)
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
     if not want("batched_q_48x48"):
         return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
     # batched corrected, mass-projected 2D collision term: 4096 cells, 48^2, M = 64, n_rho = 24
     f = torch.from_numpy(synth.mixture_batch(4096, 48, 8.0, d=2, seed=0)).cuda().contiguous()
-    ctx = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2)
-    Q = torch.empty_like(f)
-    ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 5
-    for _ in range(reps):
-        ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
     # algorithmic FLOPs: 5 K log2 K per complex 2D transform of K = 48^2 points;
     # 1 + n_rho (M/2) 2 + n_rho + 2 transforms per corrected cell
     K = 48 * 48
     transforms = 1 + 24 * 32 * 2 + 24 + 2
     flop = transforms * 5.0 * K * np.log2(K)
-    out["batched_q_48x48"] = {"cells": 4096, "ms": 1e3 * dt, "q_evals_per_s": 4096 / dt,
-                              "algorithmic_tflops": 4096 * flop / dt / 1e12,
-                              "frac_fp64_peak": 4096 * flop / dt / 78.6e12}
+    for prec, name, peak in ((bz.BZ_FP64, "fp64", 78.6e12), (bz.BZ_FP32, "fp32", 157.3e12)):
+        ctx = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2, precision=prec)
+        Q = torch.empty_like(f)
+        ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["batched_q_48x48_" + name] = {"cells": 4096, "ms": 1e3 * dt, "q_evals_per_s": 4096 / dt,
+                                          "algorithmic_tflops": 4096 * flop / dt / 1e12,
+                                          "frac_peak": 4096 * flop / dt / peak}
     return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
@@ -594,7 +597,7 @@ def main():
                     choices=["all", "first_order", "second_order"]
                             + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg", "_o2", "_o2mg")
                                for e in ("1", "0.1", "0.01", "0.001")]
-                            + ["n48_64x64_mg_eps0.1", "batched_q_48x48"],
+                            + ["n48_64x64_mg_eps0.1", "n48_64x64_mg_eps0.1_fp32", "batched_q_48x48"],
                     help="with --workload cavity: run one case only")
     ap.add_argument("--plates-case", default="all",
                     choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg")

@@ -91,7 +91,8 @@ typedef struct bz_ctx bz_ctx;
  *            form runs over the circle: M = n_phi directions
  *            theta_p = 2 pi p / n_phi with weights 2 pi / n_phi (n_theta is not
  *            used), S_2(z) = 2 pi J0(z) in place of 4 pi sin(z)/z, radial
- *            measure rho^{gamma+1}.  d = 2 supports BZ_FP64, BZ_METHOD_SIGMA,
+ *            measure rho^{gamma+1}.  d = 2 supports BZ_FP64 and BZ_FP32 (the
+ *            transform stage; the rest stays FP64), BZ_METHOD_SIGMA,
  *            v1_shift = 0, and the calls bz_eval_Q (flags BZ_Q_CORRECTED and
  *            BZ_Q_MASS), bz_maxwellian and the bz_cavity_* scans; the other calls
  *            return BZ_EUNSUPPORTED on such a context. */
