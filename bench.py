@@ -586,6 +586,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the secondary FP32-spectral measurement")
     ap.add_argument("--method", choices=["sigma", "carleman"], default="sigma",
                     help="spectral form of the main line (carleman: hard spheres, gamma = 1)")
+    ap.add_argument("--no-2d", action="store_true",
+                    help="skip the secondary two-dimensional-velocity measurement")
     ap.add_argument("--no-carleman", action="store_true",
                     help="skip the secondary hard-sphere Carleman measurement")
     ap.add_argument("--slab-case", default="all",
@@ -743,6 +745,20 @@ def main():
         vc, ec, _, rc, _ = measure("fp64", "carleman")
         line["carleman_hard_spheres"] = {"value": vc, "ms_per_step": ec / args.steps * 1e3, "gamma": 1.0,
                                          "dtype": "f64", "roofline": rc}
+    if not args.no_2d:
+        # two-dimensional velocities: the batched 48^2 collision term (the cavity's
+        # velocity discretisation) and the paper's lid-driven cavity, MG-SGS-PFP
+        print("# 2D velocities", file=sys.stderr, flush=True)
+        q2 = cavity_workload(argparse.Namespace(cavity_case="batched_q_48x48"))["runs"]
+        cav = _cavity_run(32, (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0, 32, 16, 40, 0.1, 1.0, 1e-5, 1000, 60.0,
+                          "paper_40x40_mg_eps0.1", method="mg", coarsest=5)
+        line["two_d_velocity"] = {
+            "batched_q_48x48": {k.split("_")[-1]: {"q_evals_per_s": v["q_evals_per_s"], "ms": v["ms"],
+                                                   "algorithmic_tflops": v["algorithmic_tflops"],
+                                                   "frac_peak": v["frac_peak"]} for k, v in q2.items()},
+            "cavity_40x40_mg_eps0.1": {"seconds": cav["seconds"], "vcycles": cav["iterations"],
+                                       "final_residual": cav["final_residual"], "reached": cav["reached"],
+                                       "paper_seconds_unstated_hardware": 268.42}}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)
