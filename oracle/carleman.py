@@ -114,3 +114,58 @@ def q_carleman(spec: Spec, f: np.ndarray, parts: bool = False):
     if parts:
         return gain, loss
     return gain - loss
+
+
+# ---------------------------------------------------------------- 2D, Maxwell molecules
+# In two dimensions the Carleman weight of B = |g|^gamma is 2 |x + y|^gamma, the
+# constant 2 for Maxwell molecules (gamma = 0).  With x = rho e over the half
+# circle (rho of either sign) and y perpendicular to x, y = rho' e_perp, the
+# delta(x.y) integral cancels the Jacobian |rho| of x, so
+#     Q+(v) = 2 int_{half circle} de int int f(v + rho e) f(v + rho' e_perp) drho drho'.
+# Truncating rho and rho' to [-R_c, R_c] (R_c = sqrt(2) R, as in 3D), the shift
+# integrals are psi2(xi.e) and psi2(xi.e_perp) with
+#     psi2(s) = int_{-R_c}^{R_c} exp(i rho s) drho = 2 R_c sinc(R_c s),
+# so a half-circle rule (nodes e_p, weights w_p) gives the rank-M/2 form
+#     Q+ = sum_p IDFT(A_p fh) IDFT(B_p fh),  A_p = 2 w_p psi2(xi.e_p),  B_p = psi2(xi.e_p_perp),
+# and the loss f IDFT(beta fh) with beta = sum_p A_p B_p, which conserves mass
+# exactly (A_p, B_p even).  The half-circle rule is the circle rule's nodes
+# theta_p = 2 pi p / M with p < M / 2 and weights 2 pi / M (they sum to pi).
+
+
+def psi2(spec: Spec, s):
+    """int_{-R_c}^{R_c} exp(i rho s) drho = 2 R_c sinc(R_c s)."""
+    Rc = carleman_radius(spec)
+    return 2.0 * Rc * np.sinc(Rc * np.asarray(s, dtype=np.float64) / np.pi)
+
+
+def direction_weights_2d(spec: Spec):
+    """A_p and B_p on the 2D spectrum grid: two arrays [M/2, N, N]."""
+    M = spec.n_phi
+    xg = xi_grids(spec)
+    A, B = [], []
+    for p in range(M // 2):
+        t = 2.0 * np.pi * p / M
+        e, ep = (np.cos(t), np.sin(t)), (-np.sin(t), np.cos(t))
+        wp = 2.0 * np.pi / M
+        A.append(2.0 * wp * psi2(spec, xg[0] * e[0] + xg[1] * e[1]))
+        B.append(psi2(spec, xg[0] * ep[0] + xg[1] * ep[1]))
+    return np.array(A), np.array(B)
+
+
+def q_carleman_2d(spec: Spec, f: np.ndarray, parts: bool = False):
+    """Q[f, f] for 2D Maxwell molecules by the rank-M/2 Carleman form."""
+    if spec.d != 2 or spec.gamma != 0.0 or spec.n_phi % 2:
+        raise ValueError("the 2D Carleman form is for Maxwell molecules (gamma = 0) on an even circle rule")
+    K = spec.K
+    fh = spectrum(spec, f)
+    A, B = direction_weights_2d(spec)
+    gain = np.zeros(K)
+    for Ap, Bp in zip(A, B):
+        a = (np.fft.ifftn(Ap * fh) * K).real.reshape(-1)
+        b = (np.fft.ifftn(Bp * fh) * K).real.reshape(-1)
+        gain += a * b
+    beta = (A * B).sum(0)
+    loss = f * (np.fft.ifftn(beta * fh) * K).real.reshape(-1)
+    if parts:
+        return gain, loss
+    return gain - loss

@@ -90,3 +90,41 @@ def test_direction_rule_converges_and_agrees_with_the_sigma_form():
 def test_rejects_other_kernels():
     with pytest.raises(ValueError):
         CA.q_carleman(Spec(d=3, N=8, L=4.0, gamma=0.0), np.ones(512))
+
+
+def _bkw2d(sp, t=1.0):
+    v2 = (velocity_nodes(sp) ** 2).sum(1)
+    K = 1.0 - 0.5 * np.exp(-t / 8.0)
+    dK = np.exp(-t / 8.0) / 16.0
+    E = np.exp(-v2 / (2 * K))
+    poly = 2 * K - 1 + (1 - K) * v2 / (2 * K)
+    f = E / (2 * np.pi * K * K) * poly
+    df = E / (2 * np.pi * K * K) * (v2 / (2 * K * K) * poly - 2 / K * poly + 2 - v2 / (2 * K * K)) * dK
+    return f, 2 * np.pi * df
+
+
+def test_2d_maxwell_carleman_matches_bkw_closed_form():
+    # 2D Maxwell molecules, B = 1: the 2D BKW solution (K = 1 - exp(-t/8)/2) gives
+    # Q[f] = 2 pi df/dt; this fixes the Carleman constant 2 and both weights.  The
+    # error is the sqrt(2) R truncation and the grid: it falls to 1.3e-8 on a
+    # wider, finer box
+    errs = []
+    for N, L in ((24, 8.0), (64, 12.0)):
+        sp = Spec(d=2, N=N, L=L, n_phi=32)
+        f, ref = _bkw2d(sp)
+        errs.append(np.abs(CA.q_carleman_2d(sp, f) - ref).max() / np.abs(ref).max())
+    assert errs[1] < 1e-7 < errs[0]
+
+
+def test_2d_maxwell_carleman_conserves_mass_and_agrees_with_the_sigma_form():
+    sp = Spec(d=2, N=48, L=8.0, n_phi=32, n_rho=24)
+    f = synth.mixture_batch(1, 48, 8.0, d=2, seed=9)[0]
+    gain, loss = CA.q_carleman_2d(sp, f, parts=True)
+    assert abs(np.sum(gain - loss)) < 1e-13 * np.sum(np.abs(gain))
+    g, l = C.q_fsm(sp, f, parts=True)
+    scale = max(np.abs(g - l).max(), np.abs(l).max())
+    # two discretisations of one operator, truncated differently (sqrt(2) R for x
+    # and y, 2R for |g|): on this broad mixture they differ by 7e-3
+    assert np.abs((gain - loss) - (g - l)).max() < 2e-2 * scale
+    with pytest.raises(ValueError):
+        CA.q_carleman_2d(Spec(d=2, N=8, L=4.0, gamma=1.0, n_phi=8), np.ones(64))
