@@ -83,6 +83,14 @@ typedef struct bz_ctx bz_ctx;
  *            and the loss f IDFT(beta fh) with beta = sum_p A_p B_p, so the
  *            plain form conserves mass exactly.  n_rho is not used.  A context
  *            with this method and gamma != 1 is refused (BZ_EUNSUPPORTED).
+ *            With d = 2 the method is the Carleman form of Maxwell molecules
+ *            (gamma = 0; other gamma are refused): the weight is the constant
+ *            2, x runs over the half circle (the circle rule's M/2 nodes with
+ *            p < M/2, weights 2 pi / M) and y along e_perp, both truncated at
+ *            Rc = sqrt(2) R, psi2(s) = 2 Rc sinc(Rc s), and
+ *              Q+ = sum_p IDFT(A_p fh) IDFT(B_p fh),
+ *              A_p = 2 w_p psi2(xi.e_p),  B_p = psi2(xi.e_p_perp),
+ *            with the loss f IDFT(beta fh), beta = sum_p A_p B_p.
  *   d        velocity dimension: 3 (or 0, the default) or 2.  Section 4.2 runs
  *            its binary-collision examples with two-dimensional velocities.
  *            With d = 2 the grid is N x N (N in {8, 12, 16, 24, 32, 48}, point
@@ -92,7 +100,8 @@ typedef struct bz_ctx bz_ctx;
  *            theta_p = 2 pi p / n_phi with weights 2 pi / n_phi (n_theta is not
  *            used), S_2(z) = 2 pi J0(z) in place of 4 pi sin(z)/z, radial
  *            measure rho^{gamma+1}.  d = 2 supports BZ_FP64 and BZ_FP32 (the
- *            transform stage; the rest stays FP64), BZ_METHOD_SIGMA,
+ *            transform stage; the rest stays FP64), BZ_METHOD_SIGMA and
+ *            BZ_METHOD_CARLEMAN (gamma = 0),
  *            v1_shift = 0, and the calls bz_eval_Q (flags BZ_Q_CORRECTED and
  *            BZ_Q_MASS), bz_maxwellian and the bz_cavity_* scans; the other calls
  *            return BZ_EUNSUPPORTED on such a context. */

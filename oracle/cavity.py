@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cell as cellmod
-from .collision import bgk_nu_of, nu_of, q_corrected
+from .collision import bgk_nu_of, nu_of, q_corrected, q_fsm
 from .grid import Spec, velocity_nodes
 from .maxwellian import discrete_maxwellian
 
@@ -52,6 +52,7 @@ class Cavity:
     walls: tuple = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.5, 0.0)))
     mass: float = 1.0
     collision: str = "binary"  # "binary" (mass-projected corrected Q) or "bgk"
+    q_method: str = "sigma"  # binary: "sigma" (collision.q_fsm) or "carleman" (carleman.q_carleman_2d, gamma = 0)
     bgk_nu: float | None = None
     inner: str = "pfp"
     tol_inner: float = 1e-8
@@ -130,7 +131,11 @@ def collision_terms(prob: Cavity, f_ij: np.ndarray):
     if prob.collision == "bgk":
         nu = prob.bgk_nu if prob.bgk_nu is not None else bgk_nu_of(spec, f_ij)
         return nu * (M - f_ij), M, nu
-    return q_corrected(spec, f_ij, M, conserve="mass"), M, nu_of(spec, f_ij, theta)
+    if prob.q_method == "carleman":
+        from .carleman import q_carleman_2d as op
+    else:
+        op = q_fsm
+    return q_corrected(spec, f_ij, M, op=op, conserve="mass"), M, nu_of(spec, f_ij, theta)
 
 
 def all_collision(prob: Cavity, f: np.ndarray):

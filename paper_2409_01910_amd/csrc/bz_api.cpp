@@ -86,8 +86,10 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   if (!(p->gamma > -3.0) || p->gamma > 2.0) return BZ_EINVAL;
   if (!std::isfinite(p->v1_shift) || std::fabs(p->v1_shift) > 1e6) return BZ_EINVAL;
   if (p->method != BZ_METHOD_SIGMA && p->method != BZ_METHOD_CARLEMAN) return BZ_EINVAL;
-  if (p->method == BZ_METHOD_CARLEMAN && p->gamma != 1.0) return BZ_EUNSUPPORTED;
-  if (d == 2 && (p->method != BZ_METHOD_SIGMA || p->v1_shift != 0.0)) return BZ_EUNSUPPORTED;
+  // Carleman form: hard spheres in 3D, Maxwell molecules in 2D (the kernels whose
+  // Carleman weight is constant)
+  if (p->method == BZ_METHOD_CARLEMAN && p->gamma != (d == 3 ? 1.0 : 0.0)) return BZ_EUNSUPPORTED;
+  if (d == 2 && p->v1_shift != 0.0) return BZ_EUNSUPPORTED;
   bz_ctx* ctx = new bz_ctx();
   ctx->p = *p;
   ctx->p.d = d;

@@ -282,6 +282,29 @@ bz_status build_tables_v2(bz_ctx* ctx) {
   if ((s = upload(ctx, &ctx->d_v2rho, rr)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_W, W)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_Gm, Gm)) != BZ_OK) return s;
+  if (ctx->p.method != BZ_METHOD_CARLEMAN) return BZ_OK;
+  // Carleman form for Maxwell molecules: x = rho e over the half circle, y along
+  // e_perp, both truncated at Rc = sqrt(2) R; psi2(s) = 2 Rc sinc(Rc s) and
+  // A_p = 2 w_p psi2(xi.e_p), B_p = psi2(xi.e_p_perp), beta = sum_p A_p B_p
+  const double Rc = std::sqrt(2.0) * ctx->R;
+  const int nd = M / 2;
+  std::vector<double> cw((size_t)nd * 2 * K), beta(K, 0.0);
+  auto psi2 = [&](double t) { const double z = Rc * t; return 2.0 * Rc * (z == 0.0 ? 1.0 : std::sin(z) / z); };
+  for (int p = 0; p < nd; ++p) {
+    const double c = std::cos(2.0 * M_PI * p / M), sn = std::sin(2.0 * M_PI * p / M), wp = 2.0 * M_PI / M;
+    for (int l1 = 0; l1 < N; ++l1)
+      for (int l2 = 0; l2 < N; ++l2) {
+        const size_t k = (size_t)l1 * N + l2;
+        const double a = 2.0 * wp * psi2(xi[l1] * c + xi[l2] * sn);
+        const double b = psi2(-xi[l1] * sn + xi[l2] * c);
+        cw[((size_t)p * 2 + 0) * K + k] = a;
+        cw[((size_t)p * 2 + 1) * K + k] = b;
+        beta[k] += a * b;
+      }
+  }
+  ctx->n_dir = nd;
+  if ((s = upload(ctx, &ctx->d_cw, cw)) != BZ_OK) return s;
+  if ((s = upload(ctx, &ctx->d_cbeta, beta)) != BZ_OK) return s;
   return BZ_OK;
 }
 

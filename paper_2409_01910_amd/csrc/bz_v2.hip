@@ -18,6 +18,10 @@
 // one complex transform of gh phi + i hh conj(phi) gives g(v + s) and h(v - s)
 // at once (both real), and a second one h(v + s) and g(v - s).
 //
+// With BZ_METHOD_CARLEMAN (Maxwell molecules) the same machinery evaluates the
+// Carleman form (k_c2): no radial quadrature, one or two transforms per
+// half-circle direction.
+//
 // Layout and work split: one workgroup of 512 threads per cell.  K = N^2 is at
 // most 2304, so the two spectra (gh, hh) and the two ping-pong buffers of a
 // transform (rows padded to N + 1) fit in LDS together (151 KB at N = 48), and
@@ -348,6 +352,135 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   }
 }
 
+// Carleman form for 2D Maxwell molecules, one cell per workgroup: the gain is
+// sum_p IDFT(A_p fh) IDFT(B_p fh) over the M/2 half-circle directions (tables
+// cw [nd][2][K]: A_p = 2 w_p psi2(xi.e_p), B_p = psi2(xi.e_p_perp)), accumulated
+// in physical space; the loss is f IDFT(beta fh), beta = sum_p A_p B_p.  In the
+// corrected form, Q_s(g, h): per direction one complex transform of
+// A_p gh + i B_p hh gives g_a and h_b, a second one h_a and g_b, and the gain
+// gains (g_a h_b + h_a g_b) / 2.  Spectra, tiles and the FP64 / FP32 split are
+// those of k_q2.
+template <typename T, int N>
+__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __restrict__ Q,
+     const double* __restrict__ nodes, const double* __restrict__ tw_g, const double* __restrict__ cw, int nd,
+     const double* __restrict__ beta, int corrected, int mass) {
+  using C = cx_t<T>;
+  using X = Cx<T>;
+  extern __shared__ double2 smem_[];
+  C* smem = reinterpret_cast<C*>(smem_);
+  constexpr int K = N * N, KP = N * (N + 1);
+  constexpr int kOwn = (K + kV2Threads - 1) / kV2Threads;
+  const int cell = blockIdx.x, tid = threadIdx.x;
+  C* SG = smem;
+  C* SH = SG + K;
+  C* B0 = SH + K;
+  C* B1 = B0 + KP;
+  C* TW = B1 + KP;
+  double* red = reinterpret_cast<double*>(TW + 3 * N);
+  for (int j = tid; j < N; j += blockDim.x) TW[j] = X::make(T(tw_g[2 * j]), T(tw_g[2 * j + 1]));
+  const double* fc = f + (size_t)cell * K;
+  double th[4] = {0.0, 0.0, 0.0, 0.0};
+  if (corrected)
+    for (int q = 0; q < 4; ++q) th[q] = theta[(size_t)cell * 4 + q];
+  double g[kOwn], h[kOwn], Mk[kOwn];
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const int k = tid + i * kV2Threads;
+    g[i] = h[i] = Mk[i] = 0.0;
+    if (k < K) {
+      const double fv = fc[k];
+      if (corrected) {
+        Mk[i] = gauss2(th, nodes[k / N], nodes[k % N]);
+        g[i] = fv - Mk[i];
+        h[i] = fv + Mk[i];
+      } else {
+        g[i] = h[i] = fv;
+      }
+      B0[tix(k, N)] = X::make(T(g[i]), T(h[i]));
+    }
+  }
+  __syncthreads();
+  {
+    const C* Z = dft2<T, N, -1>(B0, B1, TW);
+    const T s = T(0.5 / K);
+    for (int k = tid; k < K; k += blockDim.x) {
+      const int l1 = k / N, l2 = k - l1 * N;
+      const int m = ((N - l1) % N) * N + (N - l2) % N;
+      const C a = Z[tix(k, N)], b = Z[tix(m, N)];
+      const bool nyq = l1 == N / 2 || l2 == N / 2;
+      SG[k] = nyq ? X::make(T(0), T(0)) : X::make(s * (a.x + b.x), s * (a.y - b.y));
+      SH[k] = nyq ? X::make(T(0), T(0)) : X::make(s * (a.y + b.y), -s * (a.x - b.x));
+    }
+    __syncthreads();
+  }
+  T gain[kOwn];
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) gain[i] = T(0);
+  for (int p = 0; p < nd; ++p) {
+    const double* Ap = cw + (size_t)p * 2 * K;
+    const double* Bp = Ap + K;
+    T ga[kOwn], hb[kOwn];
+    for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
+      const C* Xs = pass == 0 ? SG : SH;
+      const C* Ys = pass == 0 ? SH : SG;
+      for (int k = tid; k < K; k += blockDim.x) {
+        const T a = T(Ap[k]), b = T(Bp[k]);
+        const C u = Xs[k], w = Ys[k];
+        B0[tix(k, N)] = X::make(a * u.x - b * w.y, a * u.y + b * w.x);  // A u + i B w
+      }
+      __syncthreads();
+      const C* Tt = dft2<T, N, +1>(B0, B1, TW);
+#pragma unroll
+      for (int i = 0; i < kOwn; ++i) {
+        const int k = tid + i * kV2Threads;
+        if (k < K) {
+          const C t = Tt[tix(k, N)];
+          if (pass == 0) {
+            ga[i] = t.x;
+            hb[i] = t.y;
+            if (!corrected) gain[i] += t.x * t.y;
+          } else {
+            gain[i] += T(0.5) * (ga[i] * hb[i] + t.x * t.y);
+          }
+        }
+      }
+    }
+  }
+  // loss: IDFT(beta hh + i beta gh) = L_h + i L_g;  Q- = (g L_h + h L_g) / 2
+  for (int k = tid; k < K; k += blockDim.x) {
+    const T bt = T(beta[k]);
+    const C a = SH[k], b = SG[k];
+    B0[tix(k, N)] = X::make(bt * (a.x - b.y), bt * (a.y + b.x));
+  }
+  __syncthreads();
+  const C* Lx = dft2<T, N, +1>(B0, B1, TW);
+  double q[kOwn], sq = 0.0, sm = 0.0;
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const int k = tid + i * kV2Threads;
+    q[i] = 0.0;
+    if (k < K) {
+      const C l = Lx[tix(k, N)];
+      q[i] = double(gain[i]) - 0.5 * (g[i] * double(l.x) + h[i] * double(l.y));
+      sq += q[i];
+      sm += Mk[i];
+    }
+  }
+  double c = 0.0;
+  if (mass) {
+    double v[2] = {sq, sm};
+    block_sum<2>(v, red);
+    c = v[0] / v[1];
+  }
+  double* Qc = Q + (size_t)cell * K;
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const int k = tid + i * kV2Threads;
+    if (k < K) Qc[k] = q[i] - c * Mk[i];
+  }
+}
+
 // 4 x 4 symmetric positive definite solve (LDL^T without pivoting)
 __device__ __forceinline__ void solve_spd4(double G[4][4], const double b[4], double y[4]) {
   double d[4], z[4];
@@ -511,11 +644,18 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
   const size_t lds = q2_lds_bytes(N, fp32 ? sizeof(float2) : sizeof(double2));
   const double w_pair = 2.0 * (2.0 * kPi / ctx->n_phi);
   const int corr = corrected ? 1 : 0, ms = mass ? 1 : 0;
-#define BZ_Q2_LAUNCH_T(TT, NN)                                                                                    \
-  BZ_HIP(hipFuncSetAttribute((const void*)k_q2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-  hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,    \
-                     ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,   \
-                     ctx->d_W, ctx->d_Gm, corr, ms);
+  const bool carl = ctx->p.method == BZ_METHOD_CARLEMAN;
+#define BZ_Q2_LAUNCH_T(TT, NN)                                                                                      \
+  if (carl) {                                                                                                      \
+    BZ_HIP(hipFuncSetAttribute((const void*)k_c2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    hipLaunchKernelGGL((k_c2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,      \
+                       ctx->d_v2tw, ctx->d_cw, ctx->n_dir, ctx->d_cbeta, corr, ms);                                \
+  } else {                                                                                                         \
+    BZ_HIP(hipFuncSetAttribute((const void*)k_q2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,      \
+                       ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,     \
+                       ctx->d_W, ctx->d_Gm, corr, ms);                                                             \
+  }
 #define BZ_Q2_LAUNCH(NN)         \
   case NN:                       \
     if (fp32) {                  \

@@ -167,3 +167,22 @@ def test_plates_uniform_in_y_match_oracle(bz, collision, order):
     err = np.abs(fg.cpu().numpy().reshape(nx, 1, -1) - f).max() / f.max()
     print(f"V-cycle: max rel diff {err:.3e}", flush=True)
     assert err < 1e-10
+
+
+def test_cavity_with_the_carleman_form_matches_oracle(bz):
+    # the 2D scans with the Carleman form of the collision term (Maxwell molecules)
+    nx, ny = 3, 4
+    sp = Spec(d=2, N=8, L=4.0, n_phi=8, n_rho=4)
+    prob = CV.Cavity(spec=sp, nx=nx, ny=ny, eps=0.1, walls=LID, collision="binary", q_method="carleman",
+                     fixed_inner=2)
+    f0 = CV.initial_state(prob, T=1.2)
+    ctx = bz.Context(N=8, L=4.0, n_phi=8, n_rho=4, d=2, method=bz.BZ_METHOD_CARLEMAN)
+    fg = torch.from_numpy(f0.reshape(nx * ny, -1).copy()).to("cuda:0").contiguous()
+    cav = bz.Cavity(ctx, nx, ny, 0.1, LID, fg, fixed_iters=2)
+    res, _ = cav.sweep(1)
+    f = CV.sgs_iteration(prob, f0)
+    ref = CV.outer_residual(prob, f)
+    err = np.abs(fg.cpu().numpy().reshape(nx, ny, -1) - f).max() / f.max()
+    print(f"Carleman cavity: max rel diff {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert abs(res - ref) < 1e-9 * ref

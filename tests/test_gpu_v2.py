@@ -121,3 +121,27 @@ def test_eval_q_2d_fp32_spectral_stage_within_stated_bound(bz, N, L, M, nr):
         print(f"FP32 d=2 N={N} cell {i} rel err {err:.3e}", flush=True)
         assert err < 2e-6
         assert abs(Q[i].sum()) < 1e-13 * np.abs(Q[i]).sum()
+
+
+@pytest.mark.parametrize("N,L,M,B", [(12, 6.0, 8, 3), (24, 8.0, 16, 2), (48, 8.0, 64, 2)])
+@pytest.mark.parametrize("form", ["plain", "corrected", "mass"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_carleman_2d_maxwell_matches_oracle(bz, N, L, M, B, form, prec, tol):
+    from oracle import carleman as CA
+
+    print(f"2D Carleman N={N} M={M} form={form} precision={prec}", flush=True)
+    sp = Spec(d=2, N=N, L=L, n_phi=M)
+    f = synth.mixture_batch(B, N, L, d=2, seed=44)
+    ctx = bz.Context(N=N, L=L, n_phi=M, n_rho=2, d=2, method=bz.BZ_METHOD_CARLEMAN, precision=prec)
+    Q = ctx.eval_Q(_T(f), corrected=form != "plain", conserve="mass" if form == "mass" else None).cpu().numpy()
+    for i in range(B):
+        gain, loss = CA.q_carleman_2d(sp, f[i], parts=True)
+        if form == "plain":
+            ref = gain - loss
+        else:
+            ref = OQ.q_corrected(sp, f[i], op=CA.q_carleman_2d, conserve="mass" if form == "mass" else None)
+        err = float(np.abs(Q[i] - ref).max() / max(np.abs(ref).max(), np.abs(loss).max()))
+        print(f"cell {i} rel err {err:.3e}", flush=True)
+        assert err < tol
+        if form == "plain" and prec == 0:  # exact mass conservation of the plain form
+            assert abs(Q[i].sum()) < 1e-12 * np.abs(gain).sum()
