@@ -274,7 +274,7 @@ def order_workload(args):
 
 
 def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5, order=1,
-                nu1=1, nu2=1, fp32=False):
+                nu1=1, nu2=1, fp32=False, carleman=False):
     """Lid-driven cavity on [0, 1]^2 (all walls T = 1, the lid y = 1 moving at
     (lid, 0)), n^2 velocities on [-l, l]^2, Maxwell molecules with M circle
     directions and nr radial nodes, first-order SGS-PFP FP64 (inner residual
@@ -294,7 +294,8 @@ def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, m
     f0 = np.repeat(m[None], nx * nx, axis=0)
     f0 *= 1.0 / (dv * dv * f0.sum() / (nx * nx))
     f = torch.from_numpy(f0).cuda().contiguous()
-    ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2, precision=bz.BZ_FP32 if fp32 else bz.BZ_FP64)
+    ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2, precision=bz.BZ_FP32 if fp32 else bz.BZ_FP64,
+                     method=bz.BZ_METHOD_CARLEMAN if carleman else bz.BZ_METHOD_SIGMA)
     walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
     cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100, order=order)
     torch.cuda.synchronize()
@@ -336,7 +337,9 @@ def cavity_workload(args):
     L40 = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
     def want(k):
         if args.cavity_case == "first_order":
-            return "_o2" not in k and k.startswith("paper")
+            return "_o2" not in k and "_carl" not in k and k.startswith("paper")
+        if args.cavity_case == "carleman":
+            return "_carl" in k
         if args.cavity_case == "second_order":
             return "_o2" in k
         return args.cavity_case in ("all", k)
@@ -359,6 +362,13 @@ def cavity_workload(args):
             out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 1000, 120.0, key, method="mg", coarsest=5,
                                    order=2, nu1=5, nu2=1)
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
+        # the Carleman form of the collision term (Maxwell molecules, M = 32 half-circle pairs)
+        for m in ("sgs", "mg"):
+            key = f"paper_40x40_carl{'_mg' if m == 'mg' else ''}_eps{eps:g}"
+            if want(key):
+                out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key, method=m, coarsest=5,
+                                       carleman=True)
+                print(f"# {key}: {json.dumps(out[key])}", flush=True)
     for fp32 in (False, True):
         key = "n48_64x64_mg_eps0.1" + ("_fp32" if fp32 else "")
         if want(key):
@@ -388,6 +398,19 @@ def cavity_workload(args):
         out["batched_q_48x48_" + name] = {"cells": 4096, "ms": 1e3 * dt, "q_evals_per_s": 4096 / dt,
                                           "algorithmic_tflops": 4096 * flop / dt / 1e12,
                                           "frac_peak": 4096 * flop / dt / peak}
+        # the Carleman form (Maxwell molecules): 1 + (M/2) 2 + 1 transforms per corrected cell
+        ctx = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2, precision=prec, method=bz.BZ_METHOD_CARLEMAN)
+        ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eval_Q(f, corrected=True, conserve="mass", out=Q)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        flop_c = (1 + 32 * 2 + 1) * 5.0 * K * np.log2(K)
+        out["batched_q_48x48_carleman_" + name] = {"cells": 4096, "ms": 1e3 * dt, "q_evals_per_s": 4096 / dt,
+                                                   "algorithmic_tflops": 4096 * flop_c / dt / 1e12,
+                                                   "frac_peak": 4096 * flop_c / dt / peak}
     return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
@@ -399,7 +422,8 @@ def plates_workload(args):
     Maxwellian (mass 1), to the outer residual 1e-5.  SGS-PFP and MG-SGS-PFP
     (V-cycles to 4 cells, one pre- and one post-smoothing step at first order;
     to 8 cells with five pre- and one post-smoothing steps at second order, tab.
-    mg), each case capped at 120 s."""
+    mg), each case capped at 120 s; and MG-SGS-PFP at first order with the
+    Carleman form of the collision term."""
     import numpy as np
     import torch
 
@@ -412,39 +436,40 @@ def plates_workload(args):
     V = np.stack(np.meshgrid(x, x, indexing="ij"), -1).reshape(-1, 2)
     m = np.exp(-(V * V).sum(1) / 2.0) / (2.0 * np.pi)
     walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)))
-    ctx = bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2)
+    ctxs = {False: bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2),
+            True: bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2, method=bz.BZ_METHOD_CARLEMAN)}
     out = {}
-    for order in (1, 2):
-        for method in ("sgs", "mg"):
-            for eps in (1.0, 0.1, 0.01, 0.001):
-                key = f"order{order}_{method}_eps{eps:g}"
-                if args.plates_case not in ("all", key):
-                    continue
-                f0 = np.repeat(m[None], nx, axis=0)
-                f0 *= 1.0 / (dv * dv * f0.sum() / nx)
-                f = torch.from_numpy(f0).cuda().contiguous()
-                cav = bz.Cavity(ctx, nx, 1, eps, walls, f, tol=1e-8, max_iter=100, order=order, uniform_y=True)
-                torch.cuda.synchronize()
-                t0 = last = time.perf_counter()
-                hist, inner, visits = [cav.residual()], 0, 0
-                while hist[-1] >= tol and len(hist) <= 20000 and time.perf_counter() - t0 < 120.0:
-                    if method == "sgs":
-                        r, st = cav.sweep(1)
-                    elif order == 1:
-                        r, st = cav.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
-                    else:
-                        r, st = cav.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
-                    hist.append(r)
-                    inner += st["inner_iters"]
-                    visits += st["visits"]
-                    if time.perf_counter() - last > 10.0:
-                        last = time.perf_counter()
-                        print(f"# plates {key} iteration {len(hist) - 1} residual {r:.3e}", flush=True)
-                dt = time.perf_counter() - t0
-                cav.close()
-                out[key] = {"seconds": dt, "iterations": len(hist) - 1, "final_residual": hist[-1],
-                            "reached": hist[-1] < tol, "mean_inner_iterations": inner / max(visits, 1)}
-                print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    for order, method, carl in [(o, m, False) for o in (1, 2) for m in ("sgs", "mg")] + [(1, "mg", True)]:
+        ctx = ctxs[carl]
+        for eps in (1.0, 0.1, 0.01, 0.001):
+            key = f"order{order}_{method}{'_carleman' if carl else ''}_eps{eps:g}"
+            if args.plates_case not in ("all", key):
+                continue
+            f0 = np.repeat(m[None], nx, axis=0)
+            f0 *= 1.0 / (dv * dv * f0.sum() / nx)
+            f = torch.from_numpy(f0).cuda().contiguous()
+            cav = bz.Cavity(ctx, nx, 1, eps, walls, f, tol=1e-8, max_iter=100, order=order, uniform_y=True)
+            torch.cuda.synchronize()
+            t0 = last = time.perf_counter()
+            hist, inner, visits = [cav.residual()], 0, 0
+            while hist[-1] >= tol and len(hist) <= 20000 and time.perf_counter() - t0 < 120.0:
+                if method == "sgs":
+                    r, st = cav.sweep(1)
+                elif order == 1:
+                    r, st = cav.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
+                else:
+                    r, st = cav.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
+                hist.append(r)
+                inner += st["inner_iters"]
+                visits += st["visits"]
+                if time.perf_counter() - last > 10.0:
+                    last = time.perf_counter()
+                    print(f"# plates {key} iteration {len(hist) - 1} residual {r:.3e}", flush=True)
+            dt = time.perf_counter() - t0
+            cav.close()
+            out[key] = {"seconds": dt, "iterations": len(hist) - 1, "final_residual": hist[-1],
+                        "reached": hist[-1] < tol, "mean_inner_iterations": inner / max(visits, 1)}
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
     return {"workload": "plates", "data": "synthetic", "dtype": "f64", "runs": out}
 
 
@@ -596,13 +621,13 @@ def main():
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
     ap.add_argument("--cavity-case", default="all",
-                    choices=["all", "first_order", "second_order"]
-                            + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg", "_o2", "_o2mg")
+                    choices=["all", "first_order", "second_order", "carleman"]
+                            + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg", "_o2", "_o2mg", "_carl", "_carl_mg")
                                for e in ("1", "0.1", "0.01", "0.001")]
                             + ["n48_64x64_mg_eps0.1", "n48_64x64_mg_eps0.1_fp32", "batched_q_48x48"],
                     help="with --workload cavity: run one case only")
     ap.add_argument("--plates-case", default="all",
-                    choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg")
+                    choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg", "mg_carleman")
                                        for e in ("1", "0.1", "0.01", "0.001")],
                     help="with --workload plates: run one case only")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates"], default="batched-q",
@@ -750,15 +775,21 @@ def main():
         # velocity discretisation) and the paper's lid-driven cavity, MG-SGS-PFP
         print("# 2D velocities", file=sys.stderr, flush=True)
         q2 = cavity_workload(argparse.Namespace(cavity_case="batched_q_48x48"))["runs"]
-        cav = _cavity_run(32, (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0, 32, 16, 40, 0.1, 1.0, 1e-5, 1000, 60.0,
-                          "paper_40x40_mg_eps0.1", method="mg", coarsest=5)
+        L40 = (3.0 * np.sqrt(2.0) + 1.0) / 2.0 * 3.0
+        cav = _cavity_run(32, L40, 32, 16, 40, 0.1, 1.0, 1e-5, 1000, 60.0, "paper_40x40_mg_eps0.1", method="mg",
+                          coarsest=5)
+        cavc = _cavity_run(32, L40, 32, 16, 40, 0.1, 1.0, 1e-5, 1000, 60.0, "paper_40x40_carl_mg_eps0.1",
+                           method="mg", coarsest=5, carleman=True)
         line["two_d_velocity"] = {
-            "batched_q_48x48": {k.split("_")[-1]: {"q_evals_per_s": v["q_evals_per_s"], "ms": v["ms"],
-                                                   "algorithmic_tflops": v["algorithmic_tflops"],
-                                                   "frac_peak": v["frac_peak"]} for k, v in q2.items()},
+            "batched_q_48x48": {k[len("batched_q_48x48_"):]: {"q_evals_per_s": v["q_evals_per_s"], "ms": v["ms"],
+                                                              "algorithmic_tflops": v["algorithmic_tflops"],
+                                                              "frac_peak": v["frac_peak"]} for k, v in q2.items()},
             "cavity_40x40_mg_eps0.1": {"seconds": cav["seconds"], "vcycles": cav["iterations"],
                                        "final_residual": cav["final_residual"], "reached": cav["reached"],
-                                       "paper_seconds_unstated_hardware": 268.42}}
+                                       "paper_seconds_unstated_hardware": 268.42},
+            "cavity_40x40_mg_eps0.1_carleman": {"seconds": cavc["seconds"], "vcycles": cavc["iterations"],
+                                                "final_residual": cavc["final_residual"], "reached": cavc["reached"],
+                                                "paper_seconds_unstated_hardware": 268.42}}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)
