@@ -7,7 +7,13 @@ eq. inner_eqn:  (|v_1|/dx) g + r = (nu/eps) (M[g] - g)  for the unknown g.
         sum w phi (|v_1|/dx) M' = sum w phi ((|v_1|/dx)(M[g] - g) - r),
     step 2 sets g <- D^{-1} ((nu/eps) M' - r).  Step 1 is solvable only if the
     right-hand side s satisfies eq. existence (s_0 > 0, s_0 s_{d+1} > sum s_i^2);
-    otherwise the visit continues with FP (Section 3.2).
+    otherwise the visit continues with FP (Section 3.2).  The alternative of the
+    remark in Section 3.2 (fallback="relax") revises step 1 with a relaxation
+    factor tau: its right-hand side becomes
+        s_tau = sum w phi (c ((1 + tau) M[g] - g) - r) / (1 + tau),
+    which is s at tau = 0 and tends to the moments of c M[g] (the plain
+    iteration) as tau grows.  Reading: each update takes the smallest tau in
+    {0, 1, 2, 4, ..., 2^20} whose s_tau satisfies eq. existence.
   * The residual |(|v_1|/dx) g + r - (nu/eps)(M[g] - g)|_{L2(R^d)} stops both
     (Section 4, tolerance 1e-8).  It is evaluated after every update.
   * ``theta_solve`` finds the fixed point independently: since M[g] depends
@@ -49,6 +55,7 @@ class SolveStats:
     fallback: bool = False
     residual: float = np.inf
     history: list = None
+    relaxed: int = 0  # updates whose step 1 used the relaxation factor
 
 
 def existence_ok(spec: Spec, s: np.ndarray) -> bool:
@@ -57,9 +64,11 @@ def existence_ok(spec: Spec, s: np.ndarray) -> bool:
 
 
 def solve(spec: Spec, r, nu, eps, dx, g0, mode: str = "pfp", tol: float = 1e-8, max_iter: int = 100,
-          fixed_iters: int | None = None):
+          fixed_iters: int | None = None, fallback: str = "fp"):
     """Iterate FP or PFP from g0.  With ``fixed_iters`` exactly that many updates are
-    made (tolerance ignored), for one-to-one comparisons of iterates."""
+    made (tolerance ignored), for one-to-one comparisons of iterates.  fallback:
+    "fp" (continue the visit with FP when eq. existence fails) or "relax" (the
+    relaxed step 1 described above; FP only if its Newton fails)."""
     c = transport_coef(spec, dx)
     lam = nu / eps
     D = c + lam
@@ -67,13 +76,24 @@ def solve(spec: Spec, r, nu, eps, dx, g0, mode: str = "pfp", tol: float = 1e-8, 
     g = np.array(g0, dtype=np.float64)
     Mg, th_g = discrete_maxwellian(spec, g, return_theta=True)
     theta_step = th_g.copy()
-    st = SolveStats(history=[])
+    st = SolveStats(history=[], relaxed=0)
+    relax = fallback == "relax"
     fallback = mode == "fp"
     n = fixed_iters if fixed_iters is not None else max_iter
     for k in range(n):
         if not fallback:
             s = spec.w * phi.T @ (c * (Mg - g) - r)
             ok = existence_ok(spec, s)
+            if not ok and relax:
+                cM = spec.w * phi.T @ (c * Mg)
+                tau = 1.0
+                while tau <= 2.0 ** 20:
+                    s_tau = (s + tau * cM) / (1.0 + tau)
+                    if existence_ok(spec, s_tau):
+                        s, ok = s_tau, True
+                        st.relaxed += 1
+                        break
+                    tau *= 2.0
             if ok:
                 th, _, conv = solve_weighted_gaussian(spec, s, weight=c, theta0=theta_step)
                 ok = conv and th[-1] > 0.0

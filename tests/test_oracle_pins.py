@@ -364,3 +364,26 @@ def test_collisionless_inflow_closed_form_on_a_shifted_grid():
     for _ in range(3):
         f = SW.sgs_iteration(prob, f)
     assert np.abs(f - exact[None]).max() < 1e-10 * exact.max()
+
+
+def test_relaxed_step1_keeps_the_preconditioned_iteration_and_reaches_the_fixed_point():
+    # Section 3.2's remark: when eq. existence fails, step 1 with a relaxation
+    # factor tau >= 1 has a solvable right-hand side.  A start of two cold beams
+    # along v_1 (more |v_1|-weighted mass than its Maxwellian) violates eq.
+    # existence at the first update; the relaxed iteration stays preconditioned
+    # and reaches the fixed point of the independent theta-Newton solve, while the
+    # plain-iteration fallback is still far from it after 100 updates
+    sp, r, nu, _, dx = _cell_case()
+    g0 = synth.maxwellian_mixture([(5.0, np.array([2.5, 0, 0]), 0.3), (5.0, np.array([-2.5, 0, 0]), 0.3)], 8, 6.0)
+    eps = 0.01
+    g, st = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", tol=1e-11, fallback="relax")
+    assert st.relaxed >= 1 and not st.fallback and st.iterations < 20
+    gs, _ = cell.theta_solve(sp, r, nu, eps, dx)
+    assert np.abs(g - gs).max() < 1e-10 * np.abs(gs).max()
+    _, st_fp = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", tol=1e-11)
+    assert st_fp.fallback and st_fp.iterations == 100
+    # at tau = 0 the relaxed right-hand side is step 1's: without a violation nothing changes
+    sp, r, nu, g0, dx = _cell_case()
+    g1, s1 = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", fixed_iters=3, fallback="relax")
+    g2, s2 = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", fixed_iters=3)
+    assert s1.relaxed == 0 and np.array_equal(g1, g2)
