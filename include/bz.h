@@ -189,11 +189,20 @@ bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
  * comparisons of iterates). */
 typedef enum { BZ_SOLVE_PFP = 0, BZ_SOLVE_FP = 1 } bz_solve_mode;
 
+/* What a PFP update does when eq. existence fails for step 1's right-hand side s:
+ * BZ_FALLBACK_FP continues the visit with the plain iteration (Section 3.2);
+ * BZ_FALLBACK_RELAX takes the relaxed step 1 of the remark in Section 3.2,
+ * s_tau = (s + tau sum w phi c M[g]) / (1 + tau), with the smallest tau in
+ * {1, 2, 4, ..., 2^20} that satisfies eq. existence, and stays preconditioned
+ * (falling back to the plain iteration only if that Newton solve fails). */
+typedef enum { BZ_FALLBACK_FP = 0, BZ_FALLBACK_RELAX = 1 } bz_fallback;
+
 typedef struct {
   int mode;        /* bz_solve_mode */
   double tol;      /* inner residual tolerance (1e-8 in Section 4) */
   int max_iter;    /* cap on updates per visit */
   int fixed_iters; /* > 0: exactly this many updates */
+  int fallback;    /* bz_fallback (0: the plain iteration) */
 } bz_solve_opts;
 
 /* Per-cell statistics (device memory, written by the solve). */
@@ -204,7 +213,7 @@ typedef struct {
   int32_t status;      /* 0 ok, 1 residual not below tol, 2 non-finite */
   double residual;     /* last inner residual */
   int32_t learned;     /* 1 if the learned initial guess was kept (learned path) */
-  int32_t reserved;
+  int32_t relaxed;     /* updates whose step 1 used the relaxation factor (BZ_FALLBACK_RELAX) */
 } bz_cell_stats;
 
 /* bz_cell_solve: `batch` independent inner problems.

@@ -58,6 +58,7 @@ class Cavity:
     tol_inner: float = 1e-8
     max_inner: int = 100
     fixed_inner: int | None = None
+    fallback: str = "fp"  # inner solve when eq. existence fails: "fp" or "relax" (cell.solve)
     order: int = 1
     # uniform_y: the problem does not vary along y (ny = 1): no y transport and no
     # y walls, two scans (+x, -x) per iteration, multigrid coarsens x only.  This
@@ -176,7 +177,9 @@ def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = N
                 r -= b[i, j]
             dxs = prob.dx if prob.uniform_y else (prob.dx, prob.dy)
             g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, dxs, f[i, j], mode=prob.inner,
-                                  tol=prob.tol_inner, max_iter=prob.max_inner, fixed_iters=prob.fixed_inner)
+                                  tol=prob.tol_inner, max_iter=prob.max_inner, fixed_iters=prob.fixed_inner,
+                                  fallback=prob.fallback)
+            prob.stats["relaxed"] = prob.stats.get("relaxed", 0) + st.relaxed
             prob.stats["inner"] += st.iterations
             prob.stats["fallback"] += int(st.fallback)
             prob.stats["visits"] += 1

@@ -48,13 +48,13 @@ class bz_params(ctypes.Structure):
 
 class bz_solve_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("fixed_iters", ctypes.c_int)]
+                ("fixed_iters", ctypes.c_int), ("fallback", ctypes.c_int)]
 
 
 class bz_cell_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("fallback", ctypes.c_int32), ("newton_fail", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("residual", ctypes.c_double), ("learned", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("relaxed", ctypes.c_int32)]
 
 
 class bz_slab_instance(ctypes.Structure):
@@ -96,7 +96,7 @@ class bz_profile_info(ctypes.Structure):
 
 
 CELL_STATS_DTYPE_FIELDS = [("iterations", "<i4"), ("fallback", "<i4"), ("newton_fail", "<i4"), ("status", "<i4"),
-                           ("residual", "<f8"), ("learned", "<i4"), ("reserved", "<i4")]
+                           ("residual", "<f8"), ("learned", "<i4"), ("relaxed", "<i4")]
 
 _lib = None
 
@@ -261,8 +261,10 @@ class Context:
         return theta, M, it
 
     @staticmethod
-    def _opts(mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0):
-        return bz_solve_opts(BZ_SOLVE_PFP if mode == "pfp" else BZ_SOLVE_FP, tol, max_iter, fixed_iters)
+    def _opts(mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, fallback="fp"):
+        """fallback: "fp" (the plain iteration) or "relax" (the relaxed step 1)."""
+        return bz_solve_opts(BZ_SOLVE_PFP if mode == "pfp" else BZ_SOLVE_FP, tol, max_iter, fixed_iters,
+                             {"fp": 0, "relax": 1}[fallback])
 
     @staticmethod
     def _stats_tensor(B, device):
@@ -277,13 +279,14 @@ class Context:
         raw = t.detach().cpu().numpy().tobytes()
         return np.frombuffer(raw, dtype=np.dtype(CELL_STATS_DTYPE_FIELDS))
 
-    def cell_solve(self, r, nu, eps, dx, g0, mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, out=None):
+    def cell_solve(self, r, nu, eps, dx, g0, mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, out=None,
+                   fallback="fp"):
         import torch
 
         B = self._field(r, "r")
         g = torch.empty_like(r) if out is None else out
         stats = self._stats_tensor(B, r.device)
-        o = self._opts(mode, tol, max_iter, fixed_iters)
+        o = self._opts(mode, tol, max_iter, fixed_iters, fallback)
         st = self.lib.bz_cell_solve(self.h, _ptr(r), _ptr(nu), _ptr(eps), float(dx), _ptr(g0), _ptr(g), B,
                                     ctypes.byref(o), _ptr(stats), _stream())
         self._check(st, "bz_cell_solve")
@@ -420,7 +423,7 @@ class Cavity:
 
     def __init__(self, ctx: Context, nx: int, ny: int, eps: float, walls, f, mass: float = 1.0,
                  collision: str = "binary", bgk_nu: float = 0.0, mode="pfp", tol=1e-8, max_iter=100,
-                 fixed_iters=0, order: int = 1, uniform_y: bool = False):
+                 fixed_iters=0, order: int = 1, uniform_y: bool = False, fallback: str = "fp"):
         self.ctx = ctx
         self.f = f
         ctx._field(f, "f")
@@ -431,7 +434,8 @@ class Cavity:
             wl[s_].T = T
             wl[s_].U[0], wl[s_].U[1] = U
         desc = bz_cavity_desc(nx, ny, eps, wl, mass, _COLLISIONS[collision], bgk_nu,
-                              Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order,
+                              Context._opts(mode, tol, max_iter, fixed_iters, fallback), ctypes.c_void_p(f.data_ptr()),
+                              order,
                               1 if uniform_y else 0)
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_cavity_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_cavity_create")

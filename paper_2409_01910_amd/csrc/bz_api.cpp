@@ -203,6 +203,7 @@ static bz_status check_opts(bz_ctx* ctx, const bz_solve_opts* o) {
   if (o->fixed_iters == 0 && (o->max_iter < 1 || o->max_iter > 100000))
     return set_err(ctx, BZ_EINVAL, "max_iter must be in [1, 100000]");
   if (!(o->tol >= 0) || !std::isfinite(o->tol)) return set_err(ctx, BZ_EINVAL, "bad tol");
+  if (o->fallback != BZ_FALLBACK_FP && o->fallback != BZ_FALLBACK_RELAX) return set_err(ctx, BZ_EINVAL, "bad fallback");
   return BZ_OK;
 }
 

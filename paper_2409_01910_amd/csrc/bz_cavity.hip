@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
                                                            int sx, int sy, double dx, double dy, double eps,
                                                            CavWalls wl, const double* __restrict__ nodes, int N,
                                                            double w, int mode, double tol, int max_iter, int fixed,
-                                                           unsigned long long* __restrict__ stats) {
+                                                           int relax, unsigned long long* __restrict__ stats) {
   __shared__ double red[14 * (kCavThreads / 64)];
   const int K = N * N;
   int i, j;
@@ -331,6 +331,22 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
       for (int q = 0; q < kCavOwn; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
       moments_of(sv, s4);
       bool ok = s4[0] > 0.0 && s4[0] * s4[3] > s4[1] * s4[1] + s4[2] * s4[2];
+      if (!ok && relax) {
+        // relaxed step 1 (Section 3.2, remark): (s + tau sum w phi c M[g]) / (1 + tau)
+        double cm[kCavOwn], m4[4];
+#pragma unroll
+        for (int q = 0; q < kCavOwn; ++q) cm[q] = c[q] * Mg[q];
+        moments_of(cm, m4);
+        for (double tau = 1.0; tau <= 1048576.0; tau *= 2.0) {
+          double st[4];
+          for (int a = 0; a < 4; ++a) st[a] = (s4[a] + tau * m4[a]) / (1.0 + tau);
+          if (st[0] > 0.0 && st[0] * st[3] > st[1] * st[1] + st[2] * st[2]) {
+            for (int a = 0; a < 4; ++a) s4[a] = st[a];
+            ok = true;
+            break;
+          }
+        }
+      }
       double th[4] = {th_step[0], th_step[1], th_step[2], th_step[3]};
       if (ok) ok = newton4(th, s4, false, nodes, N, w, true, a0, a1) && th[3] > 0.0;
       if (ok) {
@@ -694,7 +710,8 @@ bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
       hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.sx, L.sy, L.nx,
                          L.ny, cv->uy, dd,
                          scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
-                         cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters, cv->d_stats);
+                         cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters,
+                         cv->opts.fallback == BZ_FALLBACK_RELAX ? 1 : 0, cv->d_stats);
       BZ_HIP(hipGetLastError());
     }
   }
@@ -816,7 +833,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   const bz_solve_opts& o = d->inner;
   if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad solve mode");
   if (o.fixed_iters < 0 || o.fixed_iters > 100000 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) ||
-      !(o.tol >= 0) || !std::isfinite(o.tol))
+      !(o.tol >= 0) || !std::isfinite(o.tol) || (o.fallback != BZ_FALLBACK_FP && o.fallback != BZ_FALLBACK_RELAX))
     return set_err(ctx, BZ_EINVAL, "bad inner solve options");
   if (ctx->K > bz::kCavOwn * bz::kCavThreads) return set_err(ctx, BZ_EINVAL, "the cavity needs N <= 48");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");

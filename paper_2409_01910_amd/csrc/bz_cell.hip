@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
     st.status = o.status;
     st.residual = o.residual;
     st.learned = o.used_b;
-    st.reserved = 0;
+    st.relaxed = o.relaxed;
     stats[b] = st;
   }
 }
@@ -257,7 +257,8 @@ bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const doubl
                      double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
                      const double* g0b) {
   if (batch == 0) return BZ_OK;
-  SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters, ctx->p.v1_shift};
+  SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters, ctx->p.v1_shift,
+              opts->fallback == BZ_FALLBACK_RELAX ? 1 : 0};
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_cell_solve<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, r,
                                            nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b));
   BZ_HIP(hipGetLastError());

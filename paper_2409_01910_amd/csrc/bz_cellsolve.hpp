@@ -91,12 +91,14 @@ struct SolveArgs {
   int max_iter;
   int fixed_iters;
   double u0;  // grid v_1 shift: physical v_1 = node + u0
+  int relax;  // 1: relaxed step 1 when eq. existence fails (BZ_FALLBACK_RELAX)
 };
 
 struct SolveOut {
   int used_b;  // 1 if the second initial guess was kept
   int iterations;
   int fallback;
+  int relaxed;  // updates whose step 1 used the relaxation factor
   int newton_fail;
   int status;
   double residual;
@@ -139,8 +141,9 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
   __shared__ double s_Et[3][N], s_Ee[3][N];  // axis factors of M_theta and M_eta
   __shared__ double s_th[5], s_eta[5], s_res[2];
   __shared__ int s_chk[2];
-  __shared__ int s_flags[4];  // fallback, newton_fail, nonfinite, keep g0
-  if (threadIdx.x < 4) s_flags[threadIdx.x] = 0;
+  __shared__ int s_flags[5];  // fallback, newton_fail, nonfinite, keep g0, relaxed updates
+  if (threadIdx.x < 5) s_flags[threadIdx.x] = 0;
+  int relaxed = 0;
   __syncthreads();
   // the update loop: wave 0 iterates in theta-space, the block joins only for a
   // pointwise residual when the separable one cannot decide
@@ -164,6 +167,22 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
         for (int i = 0; i < 5; ++i) sv[i] = mom[i] - vm.cg[i] - vm.R0[i];
         // eq. existence
         bool ok = sv[0] > 0.0 && sv[0] * sv[4] > sv[1] * sv[1] + sv[2] * sv[2] + sv[3] * sv[3];
+        if (!ok && opt.relax) {
+          // relaxed step 1 (Section 3.2, remark): (s + tau sum w phi c M[g]) / (1 + tau),
+          // mom being that weighted moment of M[g^k] = M_eta
+          for (double tau = 1.0; tau <= 1048576.0; tau *= 2.0) {
+            double st[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) st[i] = (sv[i] + tau * mom[i]) / (1.0 + tau);
+            if (st[0] > 0.0 && st[0] * st[4] > st[1] * st[1] + st[2] * st[2] + st[3] * st[3]) {
+#pragma unroll
+              for (int i = 0; i < 5; ++i) sv[i] = st[i];
+              ok = true;
+              ++relaxed;
+              break;
+            }
+          }
+        }
         double tt[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) tt[i] = th[i];
@@ -223,6 +242,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
         s_chk[slot] = chk;
         s_flags[0] = fallback ? 1 : 0;
         s_flags[1] = newton_fail;
+        s_flags[4] = relaxed;
       }
     }
     __syncthreads();
@@ -375,6 +395,7 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
   out.used_b = used_b;
   out.iterations = k_done;
   out.fallback = s_flags[0];
+  out.relaxed = s_flags[4];
   out.newton_fail = s_flags[1];
   out.residual = res;
   out.status = (s_flags[2] || !isfinite(res)) ? 2 : ((opt.fixed_iters > 0 || res <= opt.tol) ? 0 : 1);

@@ -576,7 +576,8 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift,
                                        s->order == 2 ? L.S : nullptr, ctx->p.gamma, ctx->nu_gfac));
-  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift};
+  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift,
+              s->inner.fallback == BZ_FALLBACK_RELAX ? 1 : 0};
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.theta,
                                        L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
@@ -767,6 +768,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
     return set_err(ctx, BZ_EINVAL, "bad collision");
   const bz_solve_opts& o = d->inner;
   if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad inner mode");
+  if (o.fallback != BZ_FALLBACK_FP && o.fallback != BZ_FALLBACK_RELAX) return set_err(ctx, BZ_EINVAL, "bad fallback");
   if (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0))
     return set_err(ctx, BZ_EINVAL, "bad inner options");
   int off = 0;

@@ -186,3 +186,28 @@ def test_cavity_with_the_carleman_form_matches_oracle(bz):
     print(f"Carleman cavity: max rel diff {err:.3e}", flush=True)
     assert err < 1e-10
     assert abs(res - ref) < 1e-9 * ref
+
+
+def test_cavity_relaxed_step1_fallback_matches_oracle(bz):
+    # one cell starts as a dense ring |v| = 2 in a cavity at rest: its first visit
+    # violates eq. existence; with the relaxed step 1 it stays preconditioned
+    from oracle.grid import velocity_nodes
+
+    nx, ny = 3, 4
+    sp = Spec(d=2, N=12, L=5.0, n_phi=8, n_rho=4)
+    prob = CV.Cavity(spec=sp, nx=nx, ny=ny, eps=0.01, walls=LID, collision="bgk", fixed_inner=3, fallback="relax")
+    f0 = CV.initial_state(prob, T=1.0)
+    sv = np.sqrt((velocity_nodes(sp) ** 2).sum(1))
+    ring = np.exp(-(sv - 2.0) ** 2 / 0.1)
+    f0[1, 1] = 20.0 * ring * f0[0, 0].sum() / ring.sum()
+    f0 *= 1.0 / CV.total_mass(prob, f0)
+    ctx = bz.Context(N=12, L=5.0, n_phi=8, n_rho=4, d=2)
+    fg = torch.from_numpy(f0.reshape(nx * ny, -1).copy()).to("cuda:0").contiguous()
+    cav = bz.Cavity(ctx, nx, ny, 0.01, LID, fg, collision="bgk", fixed_iters=3, fallback="relax")
+    _, st = cav.sweep(1)
+    f = CV.sgs_iteration(prob, f0)
+    err = np.abs(fg.cpu().numpy().reshape(nx, ny, -1) - f).max() / f.max()
+    print(f"relaxed cavity: rel diff {err:.3e}, oracle relaxed {prob.stats['relaxed']}, fallbacks {st['fallbacks']}",
+          flush=True)
+    assert prob.stats["relaxed"] >= 1 and st["fallbacks"] == 0 == prob.stats["fallback"]
+    assert err < 1e-10
