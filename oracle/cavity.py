@@ -60,6 +60,7 @@ class Cavity:
     fixed_inner: int | None = None
     fallback: str = "fp"  # inner solve when eq. existence fails: "fp" or "relax" (cell.solve)
     order: int = 1
+    limiter: str = "none"  # second order: "none" (eq. slope) or "minmod" along each axis
     # uniform_y: the problem does not vary along y (ny = 1): no y transport and no
     # y walls, two scans (+x, -x) per iteration, multigrid coarsens x only.  This
     # is the 1D slab between two plates with 2D velocities.
@@ -94,16 +95,19 @@ def ghost(prob: Cavity, side: int, f_adj: np.ndarray) -> np.ndarray:
 
 def slopes(prob: Cavity, f: np.ndarray):
     """(s^x, s^y) of eq. slope along each axis: centred inside, one-sided at the
-    ends of each line; zeros at first order."""
+    ends of each line; zeros at first order; minmod inside with limiter="minmod"."""
+    from .sweep import minmod
+
     sx, sy = np.zeros_like(f), np.zeros_like(f)
     if prob.order == 1:
         return sx, sy
+    lim = prob.limiter == "minmod"
     if prob.nx > 1:
         sx[0], sx[-1] = f[1] - f[0], f[-1] - f[-2]
-        sx[1:-1] = 0.5 * (f[2:] - f[:-2])
+        sx[1:-1] = minmod(f[2:] - f[1:-1], f[1:-1] - f[:-2]) if lim else 0.5 * (f[2:] - f[:-2])
     if prob.ny > 1:
         sy[:, 0], sy[:, -1] = f[:, 1] - f[:, 0], f[:, -1] - f[:, -2]
-        sy[:, 1:-1] = 0.5 * (f[:, 2:] - f[:, :-2])
+        sy[:, 1:-1] = minmod(f[:, 2:] - f[:, 1:-1], f[:, 1:-1] - f[:, :-2]) if lim else 0.5 * (f[:, 2:] - f[:, :-2])
     return sx, sy
 
 

@@ -52,6 +52,7 @@ class Slab:
     rho_L: float = 1.0  # inflow densities (unused at walls)
     rho_R: float = 1.0
     order: int = 1
+    limiter: str = "none"  # second order: "none" (eq. slope) or "minmod"
     collision: str = "binary"  # "binary" (Q^FSM with eq. discrete_Q) or "bgk" (P == 0)
     q_method: str = "sigma"  # binary: "sigma" (collision.q_fsm) or "carleman" (carleman.q_carleman, gamma = 1)
     conserve: str = "mass"  # binary: project Q onto zero mass ("mass") or all five invariants ("all")
@@ -81,14 +82,25 @@ def wall_maxwellian(spec: Spec, T: float, U) -> np.ndarray:
     return (2.0 * np.pi * T) ** (-d / 2.0) * np.exp(-r2 / (2.0 * T))
 
 
+def minmod(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """sign(a) min(|a|, |b|) where a and b agree in sign, else 0."""
+    return np.where(a * b > 0.0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
+
+
 def slopes(prob: Slab, f: np.ndarray) -> np.ndarray:
-    """eq. slope (one-sided at the ends, centred inside); zeros at first order."""
+    """eq. slope (one-sided at the ends, centred inside); zeros at first order.
+    With limiter="minmod" the inside slopes are minmod(f_{j+1} - f_j, f_j - f_{j-1})
+    (a nonlinear limiter, which the explicit treatment of the slopes in eq. SGS
+    allows, Section 3.1); the end cells keep their one-sided differences."""
     s = np.zeros_like(f)
     if prob.order == 1 or prob.nx < 2:
         return s
     s[0] = f[1] - f[0]
     s[-1] = f[-1] - f[-2]
-    s[1:-1] = 0.5 * (f[2:] - f[:-2])
+    if prob.limiter == "minmod":
+        s[1:-1] = minmod(f[2:] - f[1:-1], f[1:-1] - f[:-2])
+    else:
+        s[1:-1] = 0.5 * (f[2:] - f[:-2])
     return s
 
 

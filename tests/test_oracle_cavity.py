@@ -32,8 +32,8 @@ def _converge(prob, tol=1e-11, max_iter=100):
     raise AssertionError("no convergence")
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_steady_state_is_symmetric_under_transposition(order):
+@pytest.mark.parametrize("order,limiter", [(1, "none"), (2, "none"), (2, "minmod")])
+def test_steady_state_is_symmetric_under_transposition(order, limiter):
     # walls x = 0 and y = 0 at T = 1, x = 1 and y = 1 at T = 2: the problem is
     # invariant under (x, y, v_1, v_2) -> (y, x, v_2, v_1), the scans are not, so
     # only the converged state must be symmetric (and the scans' fixed point must
@@ -41,7 +41,7 @@ def test_steady_state_is_symmetric_under_transposition(order):
     N = 8
     sp = Spec(d=2, N=N, L=4.0, n_phi=8, n_rho=4)
     walls = ((1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (2.0, (0.0, 0.0)))
-    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk", order=order)
+    prob = CV.Cavity(spec=sp, nx=4, ny=4, eps=0.1, walls=walls, collision="bgk", order=order, limiter=limiter)
     f = _converge(prob).reshape(4, 4, N, N)
     assert np.abs(f.transpose(1, 0, 3, 2) - f).max() < 1e-11 * f.max()
     assert abs(CV.total_mass(prob, f.reshape(4, 4, -1)) - 1.0) < 1e-13

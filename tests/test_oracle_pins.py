@@ -387,3 +387,36 @@ def test_relaxed_step1_keeps_the_preconditioned_iteration_and_reaches_the_fixed_
     g1, s1 = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", fixed_iters=3, fallback="relax")
     g2, s2 = cell.solve(sp, r, nu, eps, dx, g0, mode="pfp", fixed_iters=3)
     assert s1.relaxed == 0 and np.array_equal(g1, g2)
+
+
+def test_minmod_limited_slopes_create_no_new_extrema():
+    # With the minmod limiter the reconstructed face values f_j -+ s_j/2 stay
+    # within the range of the neighbouring cell values (no new extrema: the
+    # interior face values never leave [min, max] of the cells they join), the
+    # slope vanishes at a local extremum and next to a jump, and on a monotone
+    # smooth profile the slope is the smaller one-sided difference; the unlimited
+    # centred slopes overshoot at a jump
+    sp = Spec(d=3, N=4, L=4.0, n_theta=2, n_phi=4, n_rho=2)
+    x = np.linspace(0.0, 1.0, 12)
+    profiles = [np.where(x < 0.5, 1.0, 3.0), np.sin(6 * x) + 2.0, np.exp(x)]
+    for prof in profiles:
+        f = np.repeat(prof[:, None], sp.K, axis=1)
+        for lim, bounded in (("minmod", True), ("none", False)):
+            prob = SW.Slab(spec=sp, nx=12, order=2, limiter=lim, collision="bgk")
+            s = SW.slopes(prob, f)[:, 0]
+            east, west = prof + 0.5 * s, prof - 0.5 * s
+            lo = np.minimum(prof[1:-2], prof[2:-1])
+            hi = np.maximum(prof[1:-2], prof[2:-1])
+            inside = np.all((east[1:-2] >= lo - 1e-15) & (east[1:-2] <= hi + 1e-15)
+                            & (west[2:-1] >= lo - 1e-15) & (west[2:-1] <= hi + 1e-15))
+            if bounded:
+                assert inside
+            elif prof is profiles[0]:
+                assert not inside  # the centred slope overshoots at the jump
+    # zero at a jump's neighbours and at extrema; the smaller difference on a monotone profile
+    prob = SW.Slab(spec=sp, nx=12, order=2, limiter="minmod", collision="bgk")
+    fj = np.repeat(profiles[0][:, None], sp.K, axis=1)
+    assert np.all(SW.slopes(prob, fj)[1:-1, 0] == 0.0)
+    fe = np.repeat(profiles[2][:, None], sp.K, axis=1)
+    d = np.diff(profiles[2])
+    assert np.allclose(SW.slopes(prob, fe)[1:-1, 0], np.minimum(d[1:], d[:-1]), rtol=0, atol=1e-15)
