@@ -292,6 +292,12 @@ typedef enum { BZ_COLL_BINARY = 0, BZ_COLL_BGK = 1, BZ_COLL_BINARY_CONSERVE = 2 
 
 typedef enum { BZ_BC_WALL = 0, BZ_BC_INFLOW = 1 } bz_boundary;
 
+/* Slopes of the second-order scheme: BZ_LIMITER_NONE takes eq. slope (centred
+ * inside); BZ_LIMITER_MINMOD takes minmod(f_{j+1} - f_j, f_j - f_{j-1}) inside
+ * (a nonlinear limiter, which the explicit slopes of eq. SGS allow, Section
+ * 3.1).  Both keep the one-sided differences at the first and last cell. */
+typedef enum { BZ_LIMITER_NONE = 0, BZ_LIMITER_MINMOD = 1 } bz_limiter;
+
 typedef struct {
   double xL, xR;
   int nx;
@@ -320,6 +326,7 @@ typedef struct {
                                         r, Section 3.1).  The wall density then balances the
                                         flux of the face value f_0 - s_0/2 (left) or
                                         f_{nx-1} + s_{nx-1}/2 (right).  0 reads as 1. */
+  int limiter;                       /* bz_limiter for second order (0: none) */
 } bz_slab_desc;
 
 typedef struct bz_slab bz_slab;
@@ -389,6 +396,7 @@ typedef struct {
                           ignored), two scans (+x, -x) per iteration, multigrid
                           coarsening along x only.  This is the 1D slab between
                           two plates with 2D velocities (Section 4.2). */
+  int limiter;         /* bz_limiter for second order, along each axis (0: none) */
 } bz_cavity_desc;
 
 typedef struct bz_cavity bz_cavity;

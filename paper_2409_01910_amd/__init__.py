@@ -24,6 +24,7 @@ BZ_BC_WALL, BZ_BC_INFLOW = 0, 1
 BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
 BZ_COLL_BINARY, BZ_COLL_BGK, BZ_COLL_BINARY_CONSERVE = 0, 1, 2
 _COLLISIONS = {"binary": BZ_COLL_BINARY, "bgk": BZ_COLL_BGK, "binary_conserve": BZ_COLL_BINARY_CONSERVE}
+_LIMITERS = {"none": 0, "minmod": 1}
 
 # every symbol include/bz.h declares
 EXPORTED = [
@@ -67,7 +68,7 @@ class bz_slab_instance(ctypes.Structure):
 class bz_slab_desc(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int), ("instances", ctypes.POINTER(bz_slab_instance)),
                 ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double), ("inner", bz_solve_opts),
-                ("f", ctypes.c_void_p), ("order", ctypes.c_int)]
+                ("f", ctypes.c_void_p), ("order", ctypes.c_int), ("limiter", ctypes.c_int)]
 
 
 class bz_wall(ctypes.Structure):
@@ -78,7 +79,7 @@ class bz_cavity_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("eps", ctypes.c_double), ("walls", bz_wall * 4),
                 ("mass", ctypes.c_double), ("collision", ctypes.c_int), ("bgk_nu", ctypes.c_double),
                 ("inner", bz_solve_opts), ("f", ctypes.c_void_p), ("order", ctypes.c_int),
-                ("uniform_y", ctypes.c_int)]
+                ("uniform_y", ctypes.c_int), ("limiter", ctypes.c_int)]
 
 
 class bz_sweep_stats(ctypes.Structure):
@@ -345,7 +346,8 @@ class Slab:
     spatial order (1, or 2 for the linear reconstruction)."""
 
     def __init__(self, ctx: Context, instances, f, collision: str = "binary", bgk_nu: float = 0.0,
-                 mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, order: int = 1):
+                 mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, order: int = 1, limiter: str = "none",
+                 fallback: str = "fp"):
         self.ctx = ctx
         self.f = f
         n = len(instances)
@@ -365,7 +367,8 @@ class Slab:
             raise BZError("f must hold sum(nx) cells")
         self._arr = arr
         desc = bz_slab_desc(n, arr, _COLLISIONS[collision], bgk_nu,
-                            Context._opts(mode, tol, max_iter, fixed_iters), ctypes.c_void_p(f.data_ptr()), order)
+                            Context._opts(mode, tol, max_iter, fixed_iters, fallback), ctypes.c_void_p(f.data_ptr()),
+                            order, _LIMITERS[limiter])
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_slab_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_slab_create")
         self.h = h
@@ -423,7 +426,8 @@ class Cavity:
 
     def __init__(self, ctx: Context, nx: int, ny: int, eps: float, walls, f, mass: float = 1.0,
                  collision: str = "binary", bgk_nu: float = 0.0, mode="pfp", tol=1e-8, max_iter=100,
-                 fixed_iters=0, order: int = 1, uniform_y: bool = False, fallback: str = "fp"):
+                 fixed_iters=0, order: int = 1, uniform_y: bool = False, fallback: str = "fp",
+                 limiter: str = "none"):
         self.ctx = ctx
         self.f = f
         ctx._field(f, "f")
@@ -436,7 +440,7 @@ class Cavity:
         desc = bz_cavity_desc(nx, ny, eps, wl, mass, _COLLISIONS[collision], bgk_nu,
                               Context._opts(mode, tol, max_iter, fixed_iters, fallback), ctypes.c_void_p(f.data_ptr()),
                               order,
-                              1 if uniform_y else 0)
+                              1 if uniform_y else 0, _LIMITERS[limiter])
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.bz_cavity_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)), "bz_cavity_create")
         self.h = h

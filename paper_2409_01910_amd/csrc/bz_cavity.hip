@@ -52,6 +52,7 @@ struct bz_cavity {
   bz_solve_opts opts{};
   int order = 1;
   int uy = 0;  // uniform along y: no y transport or y walls, two scans, x-only coarsening
+  int limiter = 0;  // second order: 0 none, 1 minmod
   std::vector<CavLevel> lv;
   unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
 };
@@ -541,9 +542,14 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_total(const double* __restr
   if (threadIdx.x == 0) out[0] = v[0];
 }
 
-// slopes of eq. slope along x and y: centred inside, one-sided at the ends of each line
+__device__ __forceinline__ double minmod2(double d1, double d0) {
+  return d1 * d0 > 0.0 ? copysign(fmin(fabs(d1), fabs(d0)), d1) : 0.0;
+}
+
+// slopes of eq. slope along x and y: centred inside (minmod of the one-sided
+// differences with the limiter), one-sided at the ends of each line
 __global__ void __launch_bounds__(kCavThreads) k_cav_slopes(const double* __restrict__ f, int nx, int ny, int K,
-                                                            double* __restrict__ sx, double* __restrict__ sy) {
+                                                            int lim, double* __restrict__ sx, double* __restrict__ sy) {
   const size_t cell = blockIdx.x;
   const int i = (int)(cell / ny), j = (int)(cell - (size_t)i * ny);
   const double* c = f + cell * K;
@@ -552,11 +558,13 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_slopes(const double* __rest
     if (nx > 1) {
       if (i == 0) a = c[k + (size_t)ny * K] - c[k];
       else if (i == nx - 1) a = c[k] - c[k - (size_t)ny * K];
+      else if (lim) a = minmod2(c[k + (size_t)ny * K] - c[k], c[k] - c[k - (size_t)ny * K]);
       else a = 0.5 * (c[k + (size_t)ny * K] - c[k - (size_t)ny * K]);
     }
     if (ny > 1) {
       if (j == 0) b = c[k + K] - c[k];
       else if (j == ny - 1) b = c[k] - c[k - K];
+      else if (lim) b = minmod2(c[k + K] - c[k], c[k] - c[k - K]);
       else b = 0.5 * (c[k + K] - c[k - K]);
     }
     sx[cell * K + k] = a;
@@ -652,7 +660,8 @@ void free_level(CavLevel& L, bool own) {
 
 bz_status cav_slopes(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   if (cv->order != 2) return BZ_OK;
-  hipLaunchKernelGGL(k_cav_slopes, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.nx, L.ny, ctx->K, L.sx, L.sy);
+  hipLaunchKernelGGL(k_cav_slopes, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, L.nx, L.ny, ctx->K, cv->limiter,
+                     L.sx, L.sy);
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
@@ -824,6 +833,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
     return set_err(ctx, BZ_EINVAL, "collision must be BZ_COLL_BINARY or BZ_COLL_BGK");
   if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
   if (d->uniform_y != 0 && d->ny != 1) return set_err(ctx, BZ_EINVAL, "uniform_y needs ny = 1");
+  if (d->limiter != BZ_LIMITER_NONE && d->limiter != BZ_LIMITER_MINMOD) return set_err(ctx, BZ_EINVAL, "bad limiter");
   for (int s = 0; s < (d->uniform_y ? 2 : 4); ++s) {
     const bz_wall& wl = d->walls[s];
     if (!(wl.T > 0) || !std::isfinite(wl.T) || !std::isfinite(wl.U[0]) || !std::isfinite(wl.U[1]))
@@ -847,6 +857,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   cv->opts = o;
   cv->order = d->order == 2 ? 2 : 1;
   cv->uy = d->uniform_y != 0;
+  cv->limiter = d->limiter;
   CavLevel L0;
   L0.nx = d->nx;
   L0.ny = d->ny;

@@ -77,6 +77,7 @@ struct bz_slab {
   int collision = 0;
   double bgk_nu = 0.0;
   int order = 1;  // 1: first-order upwind; 2: linear reconstruction (eq. slope)
+  int limiter = 0;  // second order: 0 none, 1 minmod (BZ_LIMITER_MINMOD)
   bz_solve_opts inner{};
   double* wallM = nullptr;    // [n_inst][2][K] unit-density wall Maxwellians
   double* wall_in = nullptr;  // [n_inst][2] incoming discrete flux of the unit wall Maxwellian
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kCellThreads) void k_ghost_rho(const double* __rest
 template <int N>
 __global__ __launch_bounds__(kCellThreads) void k_slopes(const double* __restrict__ f, double* __restrict__ S,
                                                          const InstDev* __restrict__ inst,
-                                                         const int* __restrict__ cell_inst) {
+                                                         const int* __restrict__ cell_inst, int lim) {
   constexpr int K = N * N * N;
   const int c = blockIdx.x;
   const InstDev id = inst[cell_inst[c]];
@@ -164,6 +165,14 @@ __global__ __launch_bounds__(kCellThreads) void k_slopes(const double* __restric
   const double* a = f + (size_t)(id.off + jp) * K;
   const double* b = f + (size_t)(id.off + jm) * K;
   double* out = S + (size_t)c * K;
+  if (lim && jp - jm == 2) {  // minmod of the one-sided differences inside
+    const double* m = f + (size_t)(id.off + j) * K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const double d1 = a[k] - m[k], d0 = m[k] - b[k];
+      out[k] = d1 * d0 > 0.0 ? copysign(fmin(fabs(d1), fabs(d0)), d1) : 0.0;
+    }
+    return;
+  }
   for (int k = threadIdx.x; k < K; k += blockDim.x) out[k] = wgt * (a[k] - b[k]);
 }
 
@@ -559,7 +568,7 @@ static bz_status collide(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
 static bz_status ghosts(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   if (s->order == 2)
     BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_slopes<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.S,
-                                         L.d_inst, L.d_cell_inst));
+                                         L.d_inst, L.d_cell_inst, s->limiter));
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_ghost_rho<NN_>), dim3(2 * s->n_inst), dim3(kCellThreads), 0, st, L.f,
                                        s->order == 2 ? L.S : nullptr, L.d_inst, s->wall_in, s->bc_fixed, L.ghost,
                                        ctx->d_nodes, ctx->w, ctx->p.v1_shift));
@@ -764,6 +773,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "the 1D slab needs d = 3 (use the bz_cavity_* calls)");
   if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
   if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
+  if (d->limiter != BZ_LIMITER_NONE && d->limiter != BZ_LIMITER_MINMOD) return set_err(ctx, BZ_EINVAL, "bad limiter");
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK && d->collision != BZ_COLL_BINARY_CONSERVE)
     return set_err(ctx, BZ_EINVAL, "bad collision");
   const bz_solve_opts& o = d->inner;
@@ -807,6 +817,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   s->collision = d->collision;
   s->bgk_nu = d->bgk_nu;
   s->order = d->order == 0 ? 1 : d->order;
+  s->limiter = d->limiter;
   s->inner = d->inner;
   bz::Level L0;
   L0.ncell = off;

@@ -25,14 +25,15 @@ def bz():
     return bz
 
 
-def _setup(bz, N, L, nx, ny, collision, fixed, mode="pfp", eps=0.1, walls=LID, M=8, nr=4, order=1):
+def _setup(bz, N, L, nx, ny, collision, fixed, mode="pfp", eps=0.1, walls=LID, M=8, nr=4, order=1, limiter="none"):
     sp = Spec(d=2, N=N, L=L, n_phi=M, n_rho=nr)
     prob = CV.Cavity(spec=sp, nx=nx, ny=ny, eps=eps, walls=walls, collision=collision, inner=mode,
-                     fixed_inner=fixed, order=order)
+                     fixed_inner=fixed, order=order, limiter=limiter)
     f0 = CV.initial_state(prob, T=1.2)
     ctx = bz.Context(N=N, L=L, n_phi=M, n_rho=nr, d=2)
     fg = torch.from_numpy(f0.reshape(nx * ny, -1).copy()).to("cuda:0").contiguous()
-    cav = bz.Cavity(ctx, nx, ny, eps, walls, fg, collision=collision, mode=mode, fixed_iters=fixed or 0, order=order)
+    cav = bz.Cavity(ctx, nx, ny, eps, walls, fg, collision=collision, mode=mode, fixed_iters=fixed or 0, order=order,
+                    limiter=limiter)
     return prob, f0, ctx, cav, fg
 
 
@@ -211,3 +212,14 @@ def test_cavity_relaxed_step1_fallback_matches_oracle(bz):
           flush=True)
     assert prob.stats["relaxed"] >= 1 and st["fallbacks"] == 0 == prob.stats["fallback"]
     assert err < 1e-10
+
+
+def test_cavity_minmod_limited_second_order_matches_oracle(bz):
+    nx, ny = 4, 5
+    prob, f0, ctx, cav, fg = _setup(bz, 8, 4.0, nx, ny, "binary", fixed=2, order=2, limiter="minmod")
+    res, _ = cav.sweep(2)
+    f = CV.sgs_iteration(prob, CV.sgs_iteration(prob, f0))
+    err = np.abs(fg.cpu().numpy().reshape(nx, ny, -1) - f).max() / f.max()
+    print(f"minmod cavity: max rel diff {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert abs(res - CV.outer_residual(prob, f)) < 1e-9 * res

@@ -22,7 +22,8 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp", bgk_nu=None, T0=1.5, order=1):
+def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp", bgk_nu=None, T0=1.5, order=1,
+           limiter="none"):
     import paper_2409_01910_amd as bz
 
     sp = Spec(d=3, N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr)
@@ -30,13 +31,13 @@ def _setup(dev, N, L, nt, nph, nr, instances, collision, fixed_inner, mode="pfp"
     for d in instances:
         p = SW.Slab(spec=sp, nx=d["nx"], xL=d.get("xL", 0.0), xR=d.get("xR", 1.0), T_L=d.get("T_L", 1.0),
                     T_R=d.get("T_R", 2.0), eps=d["eps"], mass=d.get("mass", 1.0), collision=collision,
-                    bgk_nu=bgk_nu, inner=mode, fixed_inner=fixed_inner, order=order)
+                    bgk_nu=bgk_nu, inner=mode, fixed_inner=fixed_inner, order=order, limiter=limiter)
         probs.append(p)
         f0.append(SW.initial_state(p, T=T0))
     ctx = bz.Context(N=N, L=L, n_theta=nt, n_phi=nph, n_rho=nr)
     fg = torch.from_numpy(np.concatenate(f0)).to(dev).contiguous()
     slab = bz.Slab(ctx, instances, fg, collision=collision, bgk_nu=bgk_nu or 0.0, mode=mode, fixed_iters=fixed_inner,
-                   order=order)
+                   order=order, limiter=limiter)
     return sp, probs, f0, ctx, slab, fg
 
 
@@ -276,3 +277,24 @@ def test_first_and_second_order_schemes_converge_at_their_order(dev):
         rates = [np.log2(np.array(errs[i]) / np.array(errs[i + 1])) for i in range(2)]
         print(f"order {order}: errors {errs} observed orders {rates}", flush=True)
         assert all((r > lo).all() for r in rates)
+
+
+@pytest.mark.parametrize("collision", ["bgk", "binary"])
+def test_minmod_limited_second_order_matches_oracle(dev, collision):
+    # second order with the minmod limiter: three SGS iterations (the slopes of the
+    # later ones come from a non-uniform iterate) and one V-cycle
+    inst = [dict(nx=8, eps=0.1, mass=1.0)]
+    print(f"minmod second order {collision}", flush=True)
+    sp, probs, f0, ctx, slab, fg = _setup(dev, 8, 6.0, 2, 4, 3, inst, collision, fixed_inner=3, order=2,
+                                          limiter="minmod")
+    res, _ = slab.sweep(3)
+    f = f0[0]
+    for _ in range(3):
+        f = SW.sgs_iteration(probs[0], f)
+    got = _split(fg, inst)[0]
+    print(f"max rel diff {np.max(np.abs(got - f)) / f.max():.3e}", flush=True)
+    assert np.max(np.abs(got - f)) < 1e-10 * f.max()
+    assert abs(res[0] - SW.outer_residual(probs[0], f)) < 1e-9 * res[0]
+    # the limited slopes differ from the centred ones on this iterate
+    p2 = SW.Slab(**{k: getattr(probs[0], k) for k in ("spec", "nx", "eps", "mass", "collision", "order")})
+    assert np.abs(SW.slopes(p2, f) - SW.slopes(probs[0], f)).max() > 1e-6 * f.max()
