@@ -103,7 +103,12 @@ __device__ __forceinline__ void sep_sums(const double* th, const double* nodes, 
     v[15 + p] = au * e1 * up;
     up *= u;
   }
-  wave_sums_dpp<20>(v);
+  if (weighted) {
+    wave_sums_dpp<20>(v);
+  } else {  // c = 1 needs only A_p and B_q
+    double* v10 = v;
+    wave_sums_dpp<10>(*reinterpret_cast<double(*)[10]>(v10));
+  }
   auto S = [&](int p, int q) { return weighted ? a0 * v[10 + p] * v[5 + q] + a1 * v[p] * v[15 + q] : v[p] * v[5 + q]; };
   const double sc = w * exp(th[0]);
   s[0] = sc * S(0, 0);
@@ -324,13 +329,19 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const int n = fixed > 0 ? fixed : max_iter;
   int it = 0;
   double res = INFINITY;
+  // step 1's right-hand side s = sum w phi (c (M[g] - g) - r); after the first
+  // update it comes from the same block pass as the inner residual
+  double s4[4];
+  bool have_s = false;
   for (; it < n;) {
     double Mstep[kCavOwn];
     if (!fallback) {
-      double sv[kCavOwn], s4[4];
+      if (!have_s) {
+        double sv[kCavOwn];
 #pragma unroll
-      for (int q = 0; q < kCavOwn; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
-      moments_of(sv, s4);
+        for (int q = 0; q < kCavOwn; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
+        moments_of(sv, s4);
+      }
       bool ok = s4[0] > 0.0 && s4[0] * s4[3] > s4[1] * s4[1] + s4[2] * s4[2];
       if (!ok && relax) {
         // relaxed step 1 (Section 3.2, remark): (s + tau sum w phi c M[g]) / (1 + tau)
@@ -378,7 +389,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
         (void)newton4(th_g, t4, true, nodes, N, w, false, a0, a1);
       }
     }
-    double e2[1] = {0.0};
+    // one block pass: the inner residual and the next update's step-1 moments
+    double e2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < kCavOwn; ++q) {
       const int k = threadIdx.x + q * kCavThreads;
@@ -386,10 +398,17 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
       if (k < K) {
         const double e = c[q] * g[q] + r[q] - lam * (Mg[q] - g[q]);
         e2[0] += e * e;
+        const double sv = w * (c[q] * (Mg[q] - g[q]) - r[q]);
+        e2[1] += sv;
+        e2[2] += x[q] * sv;
+        e2[3] += y[q] * sv;
+        e2[4] += (x[q] * x[q] + y[q] * y[q]) * sv;
       }
     }
-    block_sum<1>(e2, red);
+    block_sum<5>(e2, red);
     res = sqrt(w * e2[0]);
+    for (int a = 0; a < 4; ++a) s4[a] = e2[1 + a];
+    have_s = true;
     ++it;
     if (fixed <= 0 && res <= tol) break;
   }
