@@ -37,7 +37,19 @@
 namespace bz {
 namespace {
 
-constexpr int kV2Threads = 512;
+// Threads per workgroup: 512, and 768 for the 48 x 48 grid, where each radix-4
+// pass has 576 butterflies and each radix-3 pass 768, so that every pass takes
+// one round of the workgroup instead of two.  FP32 workgroups of 512 threads
+// are held to 128 registers so that two share a CU.
+constexpr int kV2MaxThreads = 768;
+template <typename T, int N>
+constexpr int v2_threads() {
+  return N == 48 ? 768 : 512;
+}
+template <typename T, int N>
+constexpr int v2_waves_per_eu() {
+  return sizeof(T) == 4 && v2_threads<T, N>() == 512 ? 4 : 1;
+}
 
 // complex values of the transform stage: double2 (FP64) or float2 (FP32)
 template <typename T>
@@ -121,11 +133,13 @@ __device__ __forceinline__ void stockham_pass(const cx_t<T>* __restrict__ src, c
     cx_t<T> v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = src[base + (j + m * NR) * es];
+    if constexpr (NS > 1) {  // the first pass of an axis has unit twiddles
 #pragma unroll
-    for (int m = 1; m < R; ++m) {
-      cx_t<T> w = tw[k * m * step];
-      if (SIGN < 0) w = cconj<T>(w);
-      v[m] = cmul<T>(v[m], w);
+      for (int m = 1; m < R; ++m) {
+        cx_t<T> w = tw[k * m * step];
+        if (SIGN < 0) w = cconj<T>(w);
+        v[m] = cmul<T>(v[m], w);
+      }
     }
     small_dft<T, R, SIGN>(v);
     const int d0 = (j / NS) * NS * R + k;
@@ -159,6 +173,99 @@ __device__ __forceinline__ cx_t<T>* dft2(cx_t<T>* a, cx_t<T>* b, const cx_t<T>* 
   return src;
 }
 
+// Fused transforms for the inner loops.  A radix pass in general form: item t
+// (line fastest, as in stockham_pass) gathers its R inputs through ld(line, e)
+// and hands its R outputs to st(o, line, e, v), where e is the position along
+// the pass axis and o = round * R + m numbers the outputs a thread produces.
+// Twiddle powers w^m are formed from one table value.
+template <typename T, int N, int R, int NS, int SIGN, int NT, class Ld, class St>
+__device__ __forceinline__ void radix_pass(const Ld& ld, const St& st, const cx_t<T>* tw) {
+  constexpr int NR = N / R, items = N * NR, step = N / (NS * R);
+  constexpr int rounds = (items + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < rounds; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (items % NT == 0 || t < items) {
+      const int j = t / N, line = t - j * N;
+      const int k = j % NS;
+      cx_t<T> v[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = ld(line, j + m * NR);
+      if constexpr (NS > 1) {
+        cx_t<T> w = tw[k * step];
+        if (SIGN < 0) w = cconj<T>(w);
+        cx_t<T> wm = w;
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+          v[m] = cmul<T>(v[m], wm);
+          if (m + 1 < R) wm = cmul<T>(wm, w);
+        }
+      }
+      small_dft<T, R, SIGN>(v);
+      const int d0 = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) st(q * R + m, line, d0 + m * NS, v[m]);
+    }
+  }
+}
+
+constexpr int n_radix(int n) {
+  int q = 0;
+  while (radix_at(n, q) > 1) ++q;
+  return q;
+}
+
+// All passes of a 2D transform, axis A (0: columns, 1: rows) first.  The first
+// pass reads its input through ld0(line, e) (line and e along axis A) and
+// writes tile oth; the last pass (along the other axis) hands its outputs to
+// sink(o, line, e, v) instead of a tile.  Tiles cur and oth alternate between
+// the passes in between.  Synchronises after every pass, the last included.
+template <typename T, int N, int SIGN, int NT, int A, int AXIS, int Q, int NS, class Ld, class Sk>
+__device__ __forceinline__ void fused_passes(const Ld& ld0, const Sk& sink, cx_t<T>* cur, cx_t<T>* oth,
+                                             const cx_t<T>* tw) {
+  constexpr int R = radix_at(N, Q), RN = radix_at(N, Q + 1), P = N + 1;
+  constexpr int es = AXIS == 1 ? 1 : P, ls = AXIS == 1 ? P : 1;
+  constexpr bool first = AXIS == A && Q == 0, last = AXIS != A && RN == 1;
+  static_assert(!(first && last), "a transform has at least two passes");
+  const auto ld_lds = [cur](int line, int e) { return cur[line * ls + e * es]; };
+  const auto st_lds = [oth](int, int line, int e, cx_t<T> v) { oth[line * ls + e * es] = v; };
+  if constexpr (first)
+    radix_pass<T, N, R, NS, SIGN, NT>(ld0, st_lds, tw);
+  else if constexpr (last)
+    radix_pass<T, N, R, NS, SIGN, NT>(ld_lds, sink, tw);
+  else
+    radix_pass<T, N, R, NS, SIGN, NT>(ld_lds, st_lds, tw);
+  __syncthreads();
+  if constexpr (RN > 1)
+    fused_passes<T, N, SIGN, NT, A, AXIS, Q + 1, NS * R>(ld0, sink, oth, cur, tw);
+  else if constexpr (AXIS == A)
+    fused_passes<T, N, SIGN, NT, A, 1 - A, 0, 1>(ld0, sink, oth, cur, tw);
+}
+
+template <typename T, int N, int SIGN, int NT, int A, class Ld, class Sk>
+__device__ __forceinline__ void dft2_fused(const Ld& ld0, const Sk& sink, cx_t<T>* cur, cx_t<T>* oth,
+                                           const cx_t<T>* tw) {
+  fused_passes<T, N, SIGN, NT, A, A, 0, 1>(ld0, sink, cur, oth, tw);
+}
+
+// Outputs per thread of the last pass of dft2_fused, and the grid point
+// k = i_1 N + i_2 of output o (-1 if the thread has no such output); the last
+// pass runs along axis 1 - A.
+template <int N, int NT>
+constexpr int fused_own() {
+  constexpr int R = radix_at(N, n_radix(N) - 1);
+  return (N * (N / R) + NT - 1) / NT * R;
+}
+template <int N, int NT, int A>
+__device__ __forceinline__ int fused_point(int o) {
+  constexpr int R = radix_at(N, n_radix(N) - 1), NS = N / R, items = N * (N / R);
+  const int q = o / R, m = o - q * R, t = threadIdx.x + q * NT;
+  if (t >= items) return -1;
+  const int j = t / N, line = t - j * N, k = j % NS;
+  const int e = (j / NS) * NS * R + k + m * NS;
+  return A == 0 ? line * N + e : e * N + line;
+}
+
 // position of grid point k = i_1 N + i_2 in a transform tile (row pitch N + 1)
 __device__ __forceinline__ int tix(int k, int N) { return k + k / N; }
 
@@ -172,7 +279,7 @@ __device__ __forceinline__ double gauss2(const double* th, double x, double y) {
 // accumulation); the fields g, h, M, the loss combination, Q and the mass
 // projection are FP64.
 template <typename T, int N>
-__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__((v2_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(v2_waves_per_eu<T, N>())))
 k_q2(const double* __restrict__ f, const double* __restrict__ theta,
                                                    double* __restrict__ Q,
                                                    const double* __restrict__ nodes, const double* __restrict__ xi,
@@ -185,7 +292,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   extern __shared__ double2 smem_[];
   C* smem = reinterpret_cast<C*>(smem_);
   constexpr int K = N * N, KP = N * (N + 1);  // KP: a transform tile with padded rows
-  constexpr int kV2Own = (K + kV2Threads - 1) / kV2Threads;
+  constexpr int kThreads = v2_threads<T, N>(), kV2Own = (K + kThreads - 1) / kThreads;
   const int cell = blockIdx.x, tid = threadIdx.x;
   C* SG = smem;
   C* SH = SG + K;
@@ -204,7 +311,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   double g[kV2Own], h[kV2Own], Mk[kV2Own];
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     g[i] = h[i] = Mk[i] = 0.0;
     if (k < K) {
       const double fv = fc[k];
@@ -235,13 +342,19 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
     __syncthreads();
   }
 
-  T qr[kV2Own], qi[kV2Own];
+  // The direction-pair transforms run columns first (their inputs are read
+  // along i_2 from the unpadded spectra) and leave their outputs in registers
+  // (acc, ag, bh: the points of fused_point<N, kThreads, 0>); the transform of
+  // acc per radial node runs rows first, so that its outputs (qr, qi: the
+  // points of fused_point<N, kThreads, 1>) meet W_r along i_2.
+  constexpr int OWN = fused_own<N, kThreads>();
+  T qr[OWN], qi[OWN];
 #pragma unroll
-  for (int i = 0; i < kV2Own; ++i) qr[i] = qi[i] = T(0);
+  for (int o = 0; o < OWN; ++o) qr[o] = qi[o] = T(0);
   for (int r = 0; r < n_rho; ++r) {
-    T acc[kV2Own];
+    T acc[OWN];
 #pragma unroll
-    for (int i = 0; i < kV2Own; ++i) acc[i] = T(0);
+    for (int o = 0; o < OWN; ++o) acc[o] = T(0);
     for (int p = 0; p < n_pairs; ++p) {
       // axis phases exp(i xi_l s_a), s = rho_r sigma_p / 2
       if (tid < 2 * N) {
@@ -252,68 +365,59 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
         (a == 0 ? E0 : E1)[l] = X::make(T(cs), T(sn));
       }
       __syncthreads();
-      T ag[kV2Own], bh[kV2Own];
+      T ag[OWN], bh[OWN];
       const T wp = T(w_pair), hwp = T(0.5 * w_pair);
       for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
         const C* Xs = pass == 0 ? SG : SH;
         const C* Ys = pass == 0 ? SH : SG;
-        for (int k = tid; k < K; k += blockDim.x) {
-          const C ph = cmul<T>(E0[k / N], E1[k % N]);
+        // input u + i w at (i_1, i_2) = (e, line): u = Xs ph, w = Ys conj(ph)
+        const auto ld0 = [&](int line, int e) {
+          const int k = e * N + line;
+          const C ph = cmul<T>(E0[e], E1[line]);
           const C u = cmul<T>(Xs[k], ph), w = cmul<T>(Ys[k], cconj<T>(ph));
-          B0[tix(k, N)] = X::make(u.x - w.y, u.y + w.x);  // u + i w
-        }
-        __syncthreads();
-        const C* Tt = dft2<T, N, +1>(B0, B1, TW);
-#pragma unroll
-        for (int i = 0; i < kV2Own; ++i) {
-          const int k = tid + i * kV2Threads;
-          if (k < K) {
-            const C t = Tt[tix(k, N)];
-            if (pass == 0) {
-              ag[i] = t.x;
-              bh[i] = t.y;
-              if (!corrected) acc[i] += wp * t.x * t.y;
-            } else {
-              acc[i] += hwp * (ag[i] * bh[i] + t.x * t.y);
-            }
+          return X::make(u.x - w.y, u.y + w.x);
+        };
+        const auto sink = [&](int o, int, int, C t) {
+          if (pass == 0) {
+            ag[o] = t.x;
+            bh[o] = t.y;
+            if (!corrected) acc[o] += wp * t.x * t.y;
+          } else {
+            acc[o] += hwp * (ag[o] * bh[o] + t.x * t.y);
           }
-        }
+        };
+        dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, B1, B0, TW);
       }
     }
     // Qh += W_r DFT(acc_r)
 #pragma unroll
-    for (int i = 0; i < kV2Own; ++i) {
-      const int k = tid + i * kV2Threads;
-      if (k < K) B0[tix(k, N)] = X::make(acc[i], T(0));
+    for (int o = 0; o < OWN; ++o) {
+      const int k = fused_point<N, kThreads, 0>(o);
+      if (k >= 0) B0[tix(k, N)] = X::make(acc[o], T(0));
     }
     __syncthreads();
-    const C* A = dft2<T, N, -1>(B0, B1, TW);
     const double* Wr = W + (size_t)r * K;
-#pragma unroll
-    for (int i = 0; i < kV2Own; ++i) {
-      const int k = tid + i * kV2Threads;
-      if (k < K) {
-        const C a = A[tix(k, N)];
-        const T wr = T(Wr[k]);
-        qr[i] += wr * a.x;
-        qi[i] += wr * a.y;
-      }
-    }
-    __syncthreads();
+    const auto ld0 = [&](int line, int e) { return B0[line * (N + 1) + e]; };
+    const auto sink = [&](int o, int line, int e, C a) {
+      const T wr = T(Wr[e * N + line]);
+      qr[o] += wr * a.x;
+      qi[o] += wr * a.y;
+    };
+    dft2_fused<T, N, -1, kThreads, 1>(ld0, sink, B0, B1, TW);
   }
   // gain = IDFT(Qh)
   double gain[kV2Own];
 #pragma unroll
-  for (int i = 0; i < kV2Own; ++i) {
-    const int k = tid + i * kV2Threads;
-    if (k < K) B0[tix(k, N)] = X::make(qr[i], qi[i]);
+  for (int o = 0; o < OWN; ++o) {
+    const int k = fused_point<N, kThreads, 1>(o);
+    if (k >= 0) B0[tix(k, N)] = X::make(qr[o], qi[o]);
   }
   __syncthreads();
   {
     const C* G = dft2<T, N, +1>(B0, B1, TW);
 #pragma unroll
     for (int i = 0; i < kV2Own; ++i) {
-      const int k = tid + i * kV2Threads;
+      const int k = tid + i * kThreads;
       gain[i] = k < K ? double(G[tix(k, N)].x) : 0.0;
     }
     __syncthreads();
@@ -329,7 +433,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   double q[kV2Own], sq = 0.0, sm = 0.0;
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     q[i] = 0.0;
     if (k < K) {
       const C l = Lx[tix(k, N)];
@@ -347,7 +451,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   double* Qc = Q + (size_t)cell * K;
 #pragma unroll
   for (int i = 0; i < kV2Own; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     if (k < K) Qc[k] = q[i] - c * Mk[i];
   }
 }
@@ -361,7 +465,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
 // gains (g_a h_b + h_a g_b) / 2.  Spectra, tiles and the FP64 / FP32 split are
 // those of k_q2.
 template <typename T, int N>
-__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__((v2_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(v2_waves_per_eu<T, N>())))
 k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __restrict__ Q,
      const double* __restrict__ nodes, const double* __restrict__ tw_g, const double* __restrict__ cw, int nd,
      const double* __restrict__ beta, int corrected, int mass) {
@@ -370,7 +474,7 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
   extern __shared__ double2 smem_[];
   C* smem = reinterpret_cast<C*>(smem_);
   constexpr int K = N * N, KP = N * (N + 1);
-  constexpr int kOwn = (K + kV2Threads - 1) / kV2Threads;
+  constexpr int kThreads = v2_threads<T, N>(), kOwn = (K + kThreads - 1) / kThreads;
   const int cell = blockIdx.x, tid = threadIdx.x;
   C* SG = smem;
   C* SH = SG + K;
@@ -386,7 +490,7 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
   double g[kOwn], h[kOwn], Mk[kOwn];
 #pragma unroll
   for (int i = 0; i < kOwn; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     g[i] = h[i] = Mk[i] = 0.0;
     if (k < K) {
       const double fv = fc[k];
@@ -414,39 +518,51 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
     }
     __syncthreads();
   }
-  T gain[kOwn];
+  // Per direction, columns first (inputs read along i_2, tables coalesced),
+  // outputs kept in registers at the points of fused_point<N, kThreads, 0>.
+  constexpr int OWN = fused_own<N, kThreads>();
+  T gacc[OWN];
 #pragma unroll
-  for (int i = 0; i < kOwn; ++i) gain[i] = T(0);
+  for (int o = 0; o < OWN; ++o) gacc[o] = T(0);
   for (int p = 0; p < nd; ++p) {
     const double* Ap = cw + (size_t)p * 2 * K;
     const double* Bp = Ap + K;
-    T ga[kOwn], hb[kOwn];
+    T ga[OWN], hb[OWN];
     for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
       const C* Xs = pass == 0 ? SG : SH;
       const C* Ys = pass == 0 ? SH : SG;
-      for (int k = tid; k < K; k += blockDim.x) {
+      const auto ld0 = [&](int line, int e) {  // A u + i B w at (i_1, i_2) = (e, line)
+        const int k = e * N + line;
         const T a = T(Ap[k]), b = T(Bp[k]);
         const C u = Xs[k], w = Ys[k];
-        B0[tix(k, N)] = X::make(a * u.x - b * w.y, a * u.y + b * w.x);  // A u + i B w
-      }
-      __syncthreads();
-      const C* Tt = dft2<T, N, +1>(B0, B1, TW);
-#pragma unroll
-      for (int i = 0; i < kOwn; ++i) {
-        const int k = tid + i * kV2Threads;
-        if (k < K) {
-          const C t = Tt[tix(k, N)];
-          if (pass == 0) {
-            ga[i] = t.x;
-            hb[i] = t.y;
-            if (!corrected) gain[i] += t.x * t.y;
-          } else {
-            gain[i] += T(0.5) * (ga[i] * hb[i] + t.x * t.y);
-          }
+        return X::make(a * u.x - b * w.y, a * u.y + b * w.x);
+      };
+      const auto sink = [&](int o, int, int, C t) {
+        if (pass == 0) {
+          ga[o] = t.x;
+          hb[o] = t.y;
+          if (!corrected) gacc[o] += t.x * t.y;
+        } else {
+          gacc[o] += T(0.5) * (ga[o] * hb[o] + t.x * t.y);
         }
-      }
+      };
+      dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, B1, B0, TW);
     }
   }
+  // the gain back to the points k = tid + i * kThreads
+#pragma unroll
+  for (int o = 0; o < OWN; ++o) {
+    const int k = fused_point<N, kThreads, 0>(o);
+    if (k >= 0) B1[tix(k, N)] = X::make(gacc[o], T(0));
+  }
+  __syncthreads();
+  T gain[kOwn];
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const int k = tid + i * kThreads;
+    gain[i] = k < K ? B1[tix(k, N)].x : T(0);
+  }
+  __syncthreads();
   // loss: IDFT(beta hh + i beta gh) = L_h + i L_g;  Q- = (g L_h + h L_g) / 2
   for (int k = tid; k < K; k += blockDim.x) {
     const T bt = T(beta[k]);
@@ -458,7 +574,7 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
   double q[kOwn], sq = 0.0, sm = 0.0;
 #pragma unroll
   for (int i = 0; i < kOwn; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     q[i] = 0.0;
     if (k < K) {
       const C l = Lx[tix(k, N)];
@@ -476,7 +592,7 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
   double* Qc = Q + (size_t)cell * K;
 #pragma unroll
   for (int i = 0; i < kOwn; ++i) {
-    const int k = tid + i * kV2Threads;
+    const int k = tid + i * kThreads;
     if (k < K) Qc[k] = q[i] - c * Mk[i];
   }
 }
@@ -609,7 +725,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_max2(const double* __restrict__
 }
 
 size_t q2_lds_bytes(int N, size_t csize) {
-  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * csize + 2 * (kV2Threads / 64) * 8;
+  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * csize + 2 * (kV2MaxThreads / 64) * 8;
 }
 
 }  // namespace
@@ -648,11 +764,11 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
 #define BZ_Q2_LAUNCH_T(TT, NN)                                                                                      \
   if (carl) {                                                                                                      \
     BZ_HIP(hipFuncSetAttribute((const void*)k_c2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    hipLaunchKernelGGL((k_c2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,      \
+    hipLaunchKernelGGL((k_c2<TT, NN>), dim3((unsigned)batch), dim3(v2_threads<TT, NN>()), lds, st, f, th, Q, ctx->d_nodes,      \
                        ctx->d_v2tw, ctx->d_cw, ctx->n_dir, ctx->d_cbeta, corr, ms);                                \
   } else {                                                                                                         \
     BZ_HIP(hipFuncSetAttribute((const void*)k_q2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(kV2Threads), lds, st, f, th, Q, ctx->d_nodes,      \
+    hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(v2_threads<TT, NN>()), lds, st, f, th, Q, ctx->d_nodes,      \
                        ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,     \
                        ctx->d_W, ctx->d_Gm, corr, ms);                                                             \
   }
