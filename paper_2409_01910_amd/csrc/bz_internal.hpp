@@ -42,6 +42,7 @@ struct bz_ctx {
   double* d_v2xi = nullptr;     // [N] xi_l = pi l / L, l in transform order
   double* d_v2dir = nullptr;    // [n_phi / 2][2] sigma_p of the antipodal pairs
   double* d_v2rho = nullptr;    // [n_rho] radial nodes
+  double* d_v2ph = nullptr;     // [n_rho][n_phi / 2][2][N] (cos, sin)(xi_l rho_r sigma_p,a / 2)
   float* d_ph1_f = nullptr;
   float* d_ph23_f = nullptr;
   float* d_pairw_f = nullptr;

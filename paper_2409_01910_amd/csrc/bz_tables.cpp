@@ -280,6 +280,19 @@ bz_status build_tables_v2(bz_ctx* ctx) {
   if ((s = upload(ctx, &ctx->d_v2tw, tw)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_v2dir, dir)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_v2rho, rr)) != BZ_OK) return s;
+  // axis phases (cos, sin)(xi_l s_a), s = rho_r sigma_p / 2, per (radial node,
+  // pair, axis a, l)
+  std::vector<double> ph((size_t)nr * (M / 2) * 2 * N * 2);
+  for (int r = 0; r < nr; ++r)
+    for (int p = 0; p < M / 2; ++p)
+      for (int a = 0; a < 2; ++a)
+        for (int l = 0; l < N; ++l) {
+          const double t = xi[l] * (0.5 * rr[r] * dir[2 * p + a]);
+          const size_t i = ((((size_t)r * (M / 2) + p) * 2 + a) * N + l) * 2;
+          ph[i] = std::cos(t);
+          ph[i + 1] = std::sin(t);
+        }
+  if ((s = upload(ctx, &ctx->d_v2ph, ph)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_W, W)) != BZ_OK) return s;
   if ((s = upload(ctx, &ctx->d_Gm, Gm)) != BZ_OK) return s;
   if (ctx->p.method != BZ_METHOD_CARLEMAN) return BZ_OK;
@@ -312,7 +325,7 @@ void free_tables(bz_ctx* ctx) {
   void* ptrs[] = {ctx->d_nodes,  ctx->d_ph1,   ctx->d_ph23,     ctx->d_pairw,      ctx->d_pairsw, ctx->d_W,
                   ctx->d_Gm,     ctx->d_ph1_f, ctx->d_ph23_f,   ctx->d_pairw_f,    ctx->d_pairsw_f,
                   ctx->d_W_f,    ctx->d_Gm_f,   ctx->d_cw,       ctx->d_cbeta,      ctx->d_cw_f,   ctx->d_cbeta_f,
-                  ctx->d_v2tw,   ctx->d_v2xi,   ctx->d_v2dir,    ctx->d_v2rho};
+                  ctx->d_v2tw,   ctx->d_v2xi,   ctx->d_v2dir,    ctx->d_v2rho,      ctx->d_v2ph};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }

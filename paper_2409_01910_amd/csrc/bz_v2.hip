@@ -282,9 +282,9 @@ template <typename T, int N>
 __global__ void __launch_bounds__((v2_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(v2_waves_per_eu<T, N>())))
 k_q2(const double* __restrict__ f, const double* __restrict__ theta,
                                                    double* __restrict__ Q,
-                                                   const double* __restrict__ nodes, const double* __restrict__ xi,
-                                                   const double* __restrict__ tw_g, const double* __restrict__ dir,
-                                                   const double* __restrict__ rho, int n_rho, int n_pairs,
+                                                   const double* __restrict__ nodes,
+                                                   const double* __restrict__ tw_g, const double* __restrict__ ph,
+                                                   int n_rho, int n_pairs,
                                                    double w_pair, const double* __restrict__ W,
                                                    const double* __restrict__ Gm, int corrected, int mass) {
   using C = cx_t<T>;
@@ -299,10 +299,10 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   C* B0 = SH + K;
   C* B1 = B0 + KP;
   C* TW = B1 + KP;
-  C* E0 = TW + N;
-  C* E1 = E0 + N;
-  double* red = reinterpret_cast<double*>(E1 + N);
+  C* E = TW + N;  // axis phases of two consecutive pairs: [2][2][N]
+  double* red = reinterpret_cast<double*>(E + 4 * N);
   for (int j = tid; j < N; j += blockDim.x) TW[j] = X::make(T(tw_g[2 * j]), T(tw_g[2 * j + 1]));
+  for (int j = tid; j < 2 * N; j += blockDim.x) E[j] = X::make(T(ph[2 * j]), T(ph[2 * j + 1]));
 
   const double* fc = f + (size_t)cell * K;
   double th[4] = {0.0, 0.0, 0.0, 0.0};
@@ -351,20 +351,26 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   T qr[OWN], qi[OWN];
 #pragma unroll
   for (int o = 0; o < OWN; ++o) qr[o] = qi[o] = T(0);
+  // The axis phases exp(i xi_l s_a), s = rho_r sigma_p / 2, come from the table
+  // ph, one pair ahead: threads below 2N load the next pair's phases while the
+  // current pair is transformed and store them in the other half of E after
+  // its first transform (barriers of the second transform, or the one below
+  // in the plain form, order the store before the next pair's reads).
+  const int n_rp = n_rho * n_pairs;
   for (int r = 0; r < n_rho; ++r) {
     T acc[OWN];
 #pragma unroll
     for (int o = 0; o < OWN; ++o) acc[o] = T(0);
     for (int p = 0; p < n_pairs; ++p) {
-      // axis phases exp(i xi_l s_a), s = rho_r sigma_p / 2
-      if (tid < 2 * N) {
-        const int a = tid / N, l = tid - a * N;
-        const double sa = 0.5 * rho[r] * dir[2 * p + a];
-        double sn, cs;
-        sincos(xi[l] * sa, &sn, &cs);
-        (a == 0 ? E0 : E1)[l] = X::make(T(cs), T(sn));
+      const int rp = r * n_pairs + p;
+      double nph[2] = {0.0, 0.0};
+      if (tid < 2 * N && rp + 1 < n_rp) {
+        const double* q = ph + ((size_t)(rp + 1) * 2 * N + tid) * 2;
+        nph[0] = q[0];
+        nph[1] = q[1];
       }
-      __syncthreads();
+      const C* E0 = E + (rp & 1) * 2 * N;
+      const C* E1 = E0 + N;
       T ag[OWN], bh[OWN];
       const T wp = T(w_pair), hwp = T(0.5 * w_pair);
       for (int pass = 0; pass < (corrected ? 2 : 1); ++pass) {
@@ -387,6 +393,10 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
           }
         };
         dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, B1, B0, TW);
+        if (pass == 0) {
+          if (tid < 2 * N && rp + 1 < n_rp) E[((rp + 1) & 1) * 2 * N + tid] = X::make(T(nph[0]), T(nph[1]));
+          if (!corrected) __syncthreads();
+        }
       }
     }
     // Qh += W_r DFT(acc_r)
@@ -725,7 +735,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_max2(const double* __restrict__
 }
 
 size_t q2_lds_bytes(int N, size_t csize) {
-  return (size_t)(2 * N * N + 2 * N * (N + 1) + 3 * N) * csize + 2 * (kV2MaxThreads / 64) * 8;
+  return (size_t)(2 * N * N + 2 * N * (N + 1) + 5 * N) * csize + 2 * (kV2MaxThreads / 64) * 8;
 }
 
 }  // namespace
@@ -769,7 +779,7 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
   } else {                                                                                                         \
     BZ_HIP(hipFuncSetAttribute((const void*)k_q2<TT, NN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
     hipLaunchKernelGGL((k_q2<TT, NN>), dim3((unsigned)batch), dim3(v2_threads<TT, NN>()), lds, st, f, th, Q, ctx->d_nodes,      \
-                       ctx->d_v2xi, ctx->d_v2tw, ctx->d_v2dir, ctx->d_v2rho, ctx->n_rho, ctx->n_phi / 2, w_pair,     \
+                       ctx->d_v2tw, ctx->d_v2ph, ctx->n_rho, ctx->n_phi / 2, w_pair,                                \
                        ctx->d_W, ctx->d_Gm, corr, ms);                                                             \
   }
 #define BZ_Q2_LAUNCH(NN)         \
