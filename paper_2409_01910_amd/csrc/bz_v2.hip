@@ -219,7 +219,11 @@ constexpr int n_radix(int n) {
 // pass reads its input through ld0(line, e) (line and e along axis A) and
 // writes tile oth; the last pass (along the other axis) hands its outputs to
 // sink(o, line, e, v) instead of a tile.  Tiles cur and oth alternate between
-// the passes in between.  Synchronises after every pass, the last included.
+// the passes in between; the pass count is even, so the last pass reads oth.
+// Synchronises after every pass but the last: a caller that starts another
+// transform right away gives it the tiles swapped (its first pass then writes
+// the tile no thread still reads), and synchronises before it writes a tile
+// itself.
 template <typename T, int N, int SIGN, int NT, int A, int AXIS, int Q, int NS, class Ld, class Sk>
 __device__ __forceinline__ void fused_passes(const Ld& ld0, const Sk& sink, cx_t<T>* cur, cx_t<T>* oth,
                                              const cx_t<T>* tw) {
@@ -235,7 +239,7 @@ __device__ __forceinline__ void fused_passes(const Ld& ld0, const Sk& sink, cx_t
     radix_pass<T, N, R, NS, SIGN, NT>(ld_lds, sink, tw);
   else
     radix_pass<T, N, R, NS, SIGN, NT>(ld_lds, st_lds, tw);
-  __syncthreads();
+  if constexpr (!last) __syncthreads();
   if constexpr (RN > 1)
     fused_passes<T, N, SIGN, NT, A, AXIS, Q + 1, NS * R>(ld0, sink, oth, cur, tw);
   else if constexpr (AXIS == A)
@@ -357,6 +361,8 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
   // its first transform (barriers of the second transform, or the one below
   // in the plain form, order the store before the next pair's reads).
   const int n_rp = n_rho * n_pairs;
+  C* ta = B1;  // (cur, oth) of the next direction-pair transform
+  C* tb = B0;
   for (int r = 0; r < n_rho; ++r) {
     T acc[OWN];
 #pragma unroll
@@ -392,7 +398,10 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
             acc[o] += hwp * (ag[o] * bh[o] + t.x * t.y);
           }
         };
-        dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, B1, B0, TW);
+        dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, ta, tb, TW);
+        C* const tt = ta;
+        ta = tb;
+        tb = tt;
         if (pass == 0) {
           if (tid < 2 * N && rp + 1 < n_rp) E[((rp + 1) & 1) * 2 * N + tid] = X::make(T(nph[0]), T(nph[1]));
           if (!corrected) __syncthreads();
@@ -400,6 +409,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
       }
     }
     // Qh += W_r DFT(acc_r)
+    __syncthreads();
 #pragma unroll
     for (int o = 0; o < OWN; ++o) {
       const int k = fused_point<N, kThreads, 0>(o);
@@ -414,6 +424,8 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
       qi[o] += wr * a.y;
     };
     dft2_fused<T, N, -1, kThreads, 1>(ld0, sink, B0, B1, TW);
+    ta = B1;  // its last pass reads B1: the next first pass writes B0
+    tb = B0;
   }
   // gain = IDFT(Qh)
   double gain[kV2Own];
@@ -531,6 +543,8 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
   // Per direction, columns first (inputs read along i_2, tables coalesced),
   // outputs kept in registers at the points of fused_point<N, kThreads, 0>.
   constexpr int OWN = fused_own<N, kThreads>();
+  C* ta = B1;  // (cur, oth) of the next direction transform
+  C* tb = B0;
   T gacc[OWN];
 #pragma unroll
   for (int o = 0; o < OWN; ++o) gacc[o] = T(0);
@@ -556,10 +570,14 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
           gacc[o] += T(0.5) * (ga[o] * hb[o] + t.x * t.y);
         }
       };
-      dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, B1, B0, TW);
+      dft2_fused<T, N, +1, kThreads, 0>(ld0, sink, ta, tb, TW);
+      C* const tt = ta;
+      ta = tb;
+      tb = tt;
     }
   }
   // the gain back to the points k = tid + i * kThreads
+  __syncthreads();
 #pragma unroll
   for (int o = 0; o < OWN; ++o) {
     const int k = fused_point<N, kThreads, 0>(o);
