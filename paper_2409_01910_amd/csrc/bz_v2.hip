@@ -50,6 +50,12 @@ template <typename T, int N>
 constexpr int v2_waves_per_eu() {
   return sizeof(T) == 4 && v2_threads<T, N>() == 512 ? 4 : 1;
 }
+// The Carleman kernel's FP32 48 x 48 workgroups (76 KB of LDS) are held to 80
+// registers, so that two share a CU.
+template <typename T, int N>
+constexpr int c2_waves_per_eu() {
+  return sizeof(T) == 4 && N == 48 ? 6 : v2_waves_per_eu<T, N>();
+}
 
 // complex values of the transform stage: double2 (FP64) or float2 (FP32)
 template <typename T>
@@ -487,7 +493,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
 // gains (g_a h_b + h_a g_b) / 2.  Spectra, tiles and the FP64 / FP32 split are
 // those of k_q2.
 template <typename T, int N>
-__global__ void __launch_bounds__((v2_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(v2_waves_per_eu<T, N>())))
+__global__ void __launch_bounds__((v2_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(c2_waves_per_eu<T, N>())))
 k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __restrict__ Q,
      const double* __restrict__ nodes, const double* __restrict__ tw_g, const double* __restrict__ cw, int nd,
      const double* __restrict__ beta, int corrected, int mass) {
