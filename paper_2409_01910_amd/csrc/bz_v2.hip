@@ -46,15 +46,15 @@ template <typename T, int N>
 constexpr int v2_threads() {
   return N == 48 ? 768 : 512;
 }
+// FP32 48 x 48 workgroups (76 KB of LDS) are held to 80 registers, so that two
+// share a CU.
 template <typename T, int N>
 constexpr int v2_waves_per_eu() {
-  return sizeof(T) == 4 && v2_threads<T, N>() == 512 ? 4 : 1;
+  return sizeof(T) == 4 ? (v2_threads<T, N>() == 512 ? 4 : 6) : 1;
 }
-// The Carleman kernel's FP32 48 x 48 workgroups (76 KB of LDS) are held to 80
-// registers, so that two share a CU.
 template <typename T, int N>
 constexpr int c2_waves_per_eu() {
-  return sizeof(T) == 4 && N == 48 ? 6 : v2_waves_per_eu<T, N>();
+  return v2_waves_per_eu<T, N>();
 }
 
 // complex values of the transform stage: double2 (FP64) or float2 (FP32)
