@@ -258,6 +258,7 @@ __device__ __forceinline__ void wall_densities(const double* fc, const double* s
 }
 
 // One visit per workgroup: the cells of anti-diagonal dd of scan (sx, sy).
+template <int OWN>
 __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ f, const double* __restrict__ rs,
                                                            const double* __restrict__ nu,
                                                            const double* __restrict__ slx,
@@ -281,9 +282,9 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
   const double* fN = j < ny - 1 ? f + (cell + 1) * K : nullptr;
   const double lam = nu[cell] / eps;
-  double x[kCavOwn], y[kCavOwn], c[kCavOwn], g[kCavOwn], r[kCavOwn], Mg[kCavOwn];
+  double x[OWN], y[OWN], c[OWN], g[OWN], r[OWN], Mg[OWN];
 #pragma unroll
-  for (int q = 0; q < kCavOwn; ++q) {
+  for (int q = 0; q < OWN; ++q) {
     const int k = threadIdx.x + q * kCavThreads;
     x[q] = y[q] = c[q] = g[q] = r[q] = Mg[q] = 0.0;
     if (k < K) {
@@ -305,10 +306,10 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     }
   }
   // M[g] of the initial guess
-  auto moments_of = [&](const double (&a)[kCavOwn], double (&t)[4]) {
+  auto moments_of = [&](const double (&a)[OWN], double (&t)[4]) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < kCavOwn; ++q) {
+    for (int q = 0; q < OWN; ++q) {
       const double e = threadIdx.x + q * kCavThreads < K ? w * a[q] : 0.0;
       v[0] += e;
       v[1] += x[q] * e;
@@ -323,7 +324,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   moments_of(g, t4);
   (void)newton4(th_g, t4, true, nodes, N, w, false, a0, a1);
 #pragma unroll
-  for (int q = 0; q < kCavOwn; ++q) Mg[q] = gauss2c(th_g, x[q], y[q]);
+  for (int q = 0; q < OWN; ++q) Mg[q] = gauss2c(th_g, x[q], y[q]);
   double th_step[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
   bool fallback = mode == BZ_SOLVE_FP, fell = false;
   const int n = fixed > 0 ? fixed : max_iter;
@@ -334,20 +335,20 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   double s4[4];
   bool have_s = false;
   for (; it < n;) {
-    double Mstep[kCavOwn];
+    double Mstep[OWN];
     if (!fallback) {
       if (!have_s) {
-        double sv[kCavOwn];
+        double sv[OWN];
 #pragma unroll
-        for (int q = 0; q < kCavOwn; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
+        for (int q = 0; q < OWN; ++q) sv[q] = c[q] * (Mg[q] - g[q]) - r[q];
         moments_of(sv, s4);
       }
       bool ok = s4[0] > 0.0 && s4[0] * s4[3] > s4[1] * s4[1] + s4[2] * s4[2];
       if (!ok && relax) {
         // relaxed step 1 (Section 3.2, remark): (s + tau sum w phi c M[g]) / (1 + tau)
-        double cm[kCavOwn], m4[4];
+        double cm[OWN], m4[4];
 #pragma unroll
-        for (int q = 0; q < kCavOwn; ++q) cm[q] = c[q] * Mg[q];
+        for (int q = 0; q < OWN; ++q) cm[q] = c[q] * Mg[q];
         moments_of(cm, m4);
         for (double tau = 1.0; tau <= 1048576.0; tau *= 2.0) {
           double st[4];
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
       if (ok) {
         for (int a = 0; a < 4; ++a) th_step[a] = th[a];
 #pragma unroll
-        for (int q = 0; q < kCavOwn; ++q) Mstep[q] = gauss2c(th, x[q], y[q]);
+        for (int q = 0; q < OWN; ++q) Mstep[q] = gauss2c(th, x[q], y[q]);
       } else {
         fallback = true;
         fell = true;
@@ -372,10 +373,10 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     }
     if (fallback) {
 #pragma unroll
-      for (int q = 0; q < kCavOwn; ++q) Mstep[q] = Mg[q];
+      for (int q = 0; q < OWN; ++q) Mstep[q] = Mg[q];
     }
 #pragma unroll
-    for (int q = 0; q < kCavOwn; ++q)
+    for (int q = 0; q < OWN; ++q)
       g[q] = threadIdx.x + q * kCavThreads < K ? (lam * Mstep[q] - r[q]) / (c[q] + lam) : 0.0;
     moments_of(g, t4);
     // M[g]: Newton warm-started from the previous iterate's parameters (the
@@ -392,7 +393,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     // one block pass: the inner residual and the next update's step-1 moments
     double e2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < kCavOwn; ++q) {
+    for (int q = 0; q < OWN; ++q) {
       const int k = threadIdx.x + q * kCavThreads;
       Mg[q] = gauss2c(th_g, x[q], y[q]);
       if (k < K) {
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   const bool finite = isfinite(res);
   if (finite) {
 #pragma unroll
-    for (int q = 0; q < kCavOwn; ++q) {
+    for (int q = 0; q < OWN; ++q) {
       const int k = threadIdx.x + q * kCavThreads;
       if (k < K) fc[k] = g[q];
     }
@@ -729,13 +730,15 @@ bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, dou
 bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
   const CavWalls wl = walls_of(cv);
+  // points per thread: 4 up to 32 x 32 velocities, 9 up to 48 x 48
+  const auto visit = ctx->K <= 4 * kCavThreads ? k_cav_visit<4> : k_cav_visit<kCavOwn>;
   for (int sc = 0; sc < (cv->uy ? 2 : 4); ++sc) {
     bz_status s = cav_static(ctx, cv, L, st);
     if (s != BZ_OK) return s;
     for (int dd = 0; dd <= L.nx + L.ny - 2; ++dd) {
       const int lo = dd - (L.ny - 1) > 0 ? dd - (L.ny - 1) : 0;
       const int hi = dd < L.nx - 1 ? dd : L.nx - 1;
-      hipLaunchKernelGGL(k_cav_visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.sx, L.sy, L.nx,
+      hipLaunchKernelGGL(visit, dim3(hi - lo + 1), dim3(kCavThreads), 0, st, L.f, L.rs, L.nu, L.sx, L.sy, L.nx,
                          L.ny, cv->uy, dd,
                          scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
                          cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters,
