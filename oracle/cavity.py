@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cell as cellmod
-from .collision import bgk_nu_of, nu_of, q_corrected, q_fsm
+from .collision import bgk_nu_of, nu_of, penalty_split, q_corrected, q_fsm
 from .grid import Spec, velocity_nodes
 from .maxwellian import discrete_maxwellian
 
@@ -158,7 +158,7 @@ def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = N
     v1p, v1m = np.maximum(v[:, 0], 0.0), np.minimum(v[:, 0], 0.0)
     v2p, v2m = np.maximum(v[:, 1], 0.0), np.minimum(v[:, 1], 0.0)
     Q, M, nu = all_collision(prob, f)
-    P = Q - nu[:, :, None] * (M - f)
+    P = penalty_split(Q, M, f, nu)
     slx, sly = slopes(prob, f)
     zero = np.zeros(spec.K)
     f = f.copy()

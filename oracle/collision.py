@@ -191,6 +191,12 @@ def bgk_nu_of(spec: Spec, f: np.ndarray) -> float:
     return sphere_area(spec.d) * moments(spec, f)[0]
 
 
+def penalty_split(Q: np.ndarray, M: np.ndarray, f: np.ndarray, nu) -> np.ndarray:
+    """P = Q - nu (M - f), eq. Pf: the part of the collision term that the scans
+    treat explicitly (Section 3.3).  Broadcasts nu over the trailing velocity axis."""
+    return Q - np.asarray(nu)[..., None] * (M - f)
+
+
 def penalty(spec: Spec, f: np.ndarray, Q: np.ndarray | None = None, M: np.ndarray | None = None,
             conserve: str | None = "mass"):
     """P[f] = Q[f,f] - nu (M[f] - f), eq. Pf, with the mass-projected corrected Q."""
@@ -198,4 +204,4 @@ def penalty(spec: Spec, f: np.ndarray, Q: np.ndarray | None = None, M: np.ndarra
         M = discrete_maxwellian(spec, f)
     if Q is None:
         Q = q_corrected(spec, f, M, conserve=conserve)
-    return Q - nu_of(spec, f) * (M - f)
+    return penalty_split(Q, M, f, nu_of(spec, f))

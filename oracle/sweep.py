@@ -30,7 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cell as cellmod
-from .collision import bgk_nu_of, nu_of, q_corrected, q_fsm
+from .collision import bgk_nu_of, nu_of, penalty_split, q_corrected, q_fsm
 from .grid import Spec, sphere_area, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, moments
 
@@ -181,7 +181,7 @@ def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) 
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
     dx, eps = prob.dx, prob.eps
     Q, M, nu = all_collision(prob, f)
-    P = Q - nu[:, None] * (M - f)
+    P = penalty_split(Q, M, f, nu)
     s = slopes(prob, f)
     f = f.copy()
     order = range(prob.nx) if forward else range(prob.nx - 1, -1, -1)

@@ -306,14 +306,21 @@ def test_second_order_transport_is_exact_on_quadratic_profiles():
         assert (err < 1e-12) if exact else (err > 1e-3), (order, err)
 
 
+@pytest.mark.slow
 def test_sgs_fp_and_pfp_reach_the_same_state():
+    # Section 4.1: with inner solves tight enough, SGS-FP and SGS-PFP follow the
+    # same outer history and reach the same state.  The plain iteration needs
+    # ~740 updates per visit here (eps = 0.1), hence the runtime (~70 s).
     sp = Spec(d=3, N=8, L=6.0)
-    out = []
+    out, hists = [], []
     for inner in ("pfp", "fp"):
-        prob = SW.Slab(spec=sp, nx=4, eps=0.5, collision="bgk", inner=inner, tol_inner=1e-10, max_inner=5000)
-        f, hist = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-8, max_iter=200)
+        prob = SW.Slab(spec=sp, nx=4, eps=0.1, collision="bgk", inner=inner, tol_inner=1e-11, max_inner=5000)
+        f, hist = SW.solve_sgs(prob, SW.initial_state(prob, T=1.5), tol=1e-9, max_iter=200)
         out.append(f)
-    assert np.abs(out[0] - out[1]).max() < 1e-7 * out[0].max()
+        hists.append(np.array(hist))
+    assert np.abs(out[0] - out[1]).max() < 1e-8 * out[0].max()
+    assert len(hists[0]) == len(hists[1])
+    assert np.allclose(hists[0], hists[1], rtol=0.05, atol=0.0)
 
 
 def test_multigrid_reaches_the_sgs_state():
