@@ -174,6 +174,27 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _arg(t, name, numel, dtype="float64", device=None, optional=False):
+    """Check a tensor argument before its pointer reaches the library: a
+    contiguous device tensor of the given dtype with exactly ``numel`` elements
+    (on ``device`` when given).  Raises BZError otherwise; None passes only
+    when ``optional``."""
+    import torch
+
+    if t is None:
+        if optional:
+            return None
+        raise BZError(f"{name} is required")
+    want = getattr(torch, dtype)
+    if not isinstance(t, torch.Tensor) or t.dtype != want or not t.is_cuda or not t.is_contiguous():
+        raise BZError(f"{name} must be a contiguous {dtype} device tensor")
+    if device is not None and t.device != device:
+        raise BZError(f"{name} is on {t.device}, expected {device}")
+    if t.numel() != numel:
+        raise BZError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t
+
+
 def _stream():
     import torch
 
@@ -233,8 +254,10 @@ class Context:
     def _field(self, t, name):
         import torch
 
-        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
             raise BZError(f"{name} must be a contiguous float64 device tensor")
+        if t.device.index != self.params.device:
+            raise BZError(f"{name} is on {t.device}, the context on cuda:{self.params.device}")
         if t.numel() % self.K:
             raise BZError(f"{name}: size not a multiple of K = {self.K}")
         return t.numel() // self.K
@@ -244,7 +267,8 @@ class Context:
         import torch
 
         B = self._field(f, "f")
-        Q = torch.empty_like(f) if out is None else out
+        Q = torch.empty_like(f) if out is None else _arg(out, "out", f.numel(), device=f.device)
+        _arg(theta, "theta", B * (self.d + 2), device=f.device, optional=True)
         flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
         st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, flags, _ptr(theta), _stream())
         self._check(st, "bz_eval_Q")
@@ -285,7 +309,9 @@ class Context:
         import torch
 
         B = self._field(r, "r")
-        g = torch.empty_like(r) if out is None else out
+        for t, n, k in ((nu, "nu", B), (eps, "eps", B), (g0, "g0", B * self.K)):
+            _arg(t, n, k, device=r.device)
+        g = torch.empty_like(r) if out is None else _arg(out, "out", r.numel(), device=r.device)
         stats = self._stats_tensor(B, r.device)
         o = self._opts(mode, tol, max_iter, fixed_iters, fallback)
         st = self.lib.bz_cell_solve(self.h, _ptr(r), _ptr(nu), _ptr(eps), float(dx), _ptr(g0), _ptr(g), B,
@@ -298,7 +324,9 @@ class Context:
         import torch
 
         B = self._field(f_old, "f_old")
-        g = torch.empty_like(f_old) if out is None else out
+        _arg(inflow_r, "inflow_r", f_old.numel(), device=f_old.device)
+        _arg(eps, "eps", B, device=f_old.device)
+        g = torch.empty_like(f_old) if out is None else _arg(out, "out", f_old.numel(), device=f_old.device)
         stats = self._stats_tensor(B, f_old.device)
         o = self._opts(mode, tol, max_iter, fixed_iters)
         st = self.lib.bz_cell_fixed_point(self.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx), _ptr(g), B,
@@ -311,7 +339,11 @@ class Context:
         import torch
 
         B = self._field(f_old, "f_old")
-        g = torch.empty_like(f_old) if out is None else out
+        _arg(inflow_r, "inflow_r", f_old.numel(), device=f_old.device)
+        _arg(eps, "eps", B, device=f_old.device)
+        if mlp.n_in != self.K + 6 or mlp.n_out != self.K:
+            raise BZError(f"the network must map K + 6 = {self.K + 6} inputs to K = {self.K} outputs")
+        g = torch.empty_like(f_old) if out is None else _arg(out, "out", f_old.numel(), device=f_old.device)
         stats = self._stats_tensor(B, f_old.device)
         o = self._opts(mode, tol, max_iter, fixed_iters)
         st = self.lib.bz_cell_fixed_point_learned(self.h, mlp.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx),
@@ -323,6 +355,8 @@ class Context:
         import torch
 
         B = self._field(inflow_r, "inflow_r")
+        _arg(theta, "theta", B * (self.d + 2), device=inflow_r.device)
+        _arg(eps, "eps", B, device=inflow_r.device)
         X = torch.empty((B, self.K + 6), dtype=torch.float32, device=inflow_r.device)
         self._check(self.lib.bz_mlp_features(self.h, _ptr(inflow_r), _ptr(theta), _ptr(eps), float(dx), _ptr(X), B,
                                              _stream()), "bz_mlp_features")
@@ -564,10 +598,19 @@ class MLP:
     def set_output_scale(self, s: float):
         self.ctx._check(self.ctx.lib.bz_mlp_set_output_scale(self.h, float(s)), "bz_mlp_set_output_scale")
 
+    def _xt(self, X, T=None):
+        B = X.shape[0] if X.dim() == 2 else -1
+        if B < 0:
+            raise BZError("X must be [batch, n_in]")
+        _arg(X, "X", B * self.n_in, dtype="float32")
+        if T is not None:
+            _arg(T, "T", B * self.n_out, dtype="float32", device=X.device)
+        return B
+
     def forward(self, X, bf16: bool = False):
         import torch
 
-        B = X.shape[0]
+        B = self._xt(X)
         Y = torch.empty((B, self.n_out), dtype=torch.float32, device=X.device)
         self.ctx._check(self.ctx.lib.bz_mlp_forward(self.h, _ptr(X), _ptr(Y), B, 1 if bf16 else 0, _stream()),
                         "bz_mlp_forward")
@@ -576,6 +619,7 @@ class MLP:
     def grad(self, X, T):
         import torch
 
+        self._xt(X, T)
         g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
         loss = ctypes.c_double()
         self.ctx._check(self.ctx.lib.bz_mlp_grad(self.h, _ptr(X), _ptr(T), X.shape[0], _ptr(g), ctypes.byref(loss),
@@ -583,6 +627,7 @@ class MLP:
         return loss.value, g
 
     def train_step(self, X, T, lr: float, want_loss: bool = False):
+        self._xt(X, T)
         loss = ctypes.c_double()
         self.ctx._check(self.ctx.lib.bz_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], float(lr),
                                                        ctypes.byref(loss) if want_loss else None, _stream()),
