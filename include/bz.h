@@ -168,6 +168,23 @@ size_t bz_workspace_bytes(bz_ctx* ctx);
 bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
                     double* theta, void* stream);
 
+/* bz_eval_Q_noalloc: bz_eval_Q for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, flags, layouts, results and errors as
+ * bz_eval_Q, but no allocating call (no hipMalloc, hipMallocAsync or hipFree)
+ * is made.  The collision workspace, and the Maxwellian parameters the flags
+ * need when theta is NULL, live in a static device array of 64 MiB per device,
+ * held by the library until the process ends; cells are processed in chunks
+ * that fit it.  Returns BZ_EINVAL, with a message, when one cell's workspace
+ * exceeds the array: with d = 3 in FP64 the corrected form needs
+ * N^3 (112 + 32 n_theta) bytes per cell (12.1 MB at 32^3 with n_theta = 8, so 5
+ * cells per chunk; n_theta = 64 at 32^3 is refused); d = 2 needs 32 bytes per
+ * cell.  All calls on one device share that device's array and leave it
+ * holding the last call's contents: calls that overlap on one device (other
+ * streams, other host threads) race, and the caller must serialise them. */
+bz_status bz_eval_Q_noalloc(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
+                            double* theta, void* stream);
+
 /* bz_maxwellian: discrete Maxwellian of each cell (eqs. discrete_conservation,
  * discrete_Gaussian; Newton's method, Section 2.2).
  *   f [batch][K] in;  theta [batch][5] out (alpha, beta, gamma);

@@ -29,7 +29,7 @@ _LIMITERS = {"none": 0, "minmod": 1}
 # every symbol include/bz.h declares
 EXPORTED = [
     "bz_create", "bz_destroy", "bz_status_str", "bz_last_error", "bz_workspace_bytes",
-    "bz_eval_Q", "bz_maxwellian", "bz_cell_solve", "bz_cell_fixed_point",
+    "bz_eval_Q", "bz_eval_Q_noalloc", "bz_maxwellian", "bz_cell_solve", "bz_cell_fixed_point",
     "bz_slab_create", "bz_slab_destroy", "bz_sgs_sweep", "bz_outer_residual", "bz_multigrid_vcycle",
     "bz_profile_enable", "bz_profile_get",
     "bz_mlp_create", "bz_mlp_destroy", "bz_mlp_num_params", "bz_mlp_get_params", "bz_mlp_set_params",
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_workspace_bytes.argtypes = [P]
     lib.bz_workspace_bytes.restype = ctypes.c_size_t
     lib.bz_eval_Q.argtypes = [P, P, P, I64, U32, P, P]
+    lib.bz_eval_Q_noalloc.argtypes = [P, P, P, I64, U32, P, P]
     lib.bz_maxwellian.argtypes = [P, P, P, P, P, I64, P]
     lib.bz_cell_solve.argtypes = [P, P, P, P, D, P, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
     lib.bz_cell_fixed_point.argtypes = [P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
@@ -273,6 +274,17 @@ class Context:
         st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, flags, _ptr(theta), _stream())
         self._check(st, "bz_eval_Q")
         return Q
+
+    def eval_Q_noalloc(self, f, out, corrected: bool = True, theta=None, conserve: str | None = None):
+        """bz_eval_Q_noalloc: the collision term into the caller's ``out`` with no
+        device allocation, neither by the library nor here."""
+        B = self._field(f, "f")
+        _arg(out, "out", f.numel(), device=f.device)
+        _arg(theta, "theta", B * (self.d + 2), device=f.device, optional=True)
+        flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
+        st = self.lib.bz_eval_Q_noalloc(self.h, _ptr(f), _ptr(out), B, flags, _ptr(theta), _stream())
+        self._check(st, "bz_eval_Q_noalloc")
+        return out
 
     def maxwellian(self, f, want_M: bool = True):
         import torch

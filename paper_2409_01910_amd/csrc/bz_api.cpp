@@ -111,6 +111,7 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
     return BZ_EHIP;
   }
   bz_status s = bz::build_tables(ctx);
+  if (s == BZ_OK) s = bz::scratch_attach(ctx);
   if (s != BZ_OK) {
     bz::free_tables(ctx);
     delete ctx;
@@ -155,8 +156,12 @@ bz_status bz_profile_get(bz_ctx* ctx, bz_profile_info* out) {
   return BZ_OK;
 }
 
-bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags, double* theta,
-                    void* stream) {
+}  // extern "C"
+
+namespace bz {
+
+bz_status check_eval_q_args(bz_ctx* ctx, const double* f, const double* Q, int64_t batch, uint32_t flags,
+                            const double* theta) {
   if (!ctx) return BZ_EINVAL;
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   if (batch > 0 && (!f || !Q)) return set_err(ctx, BZ_EINVAL, "NULL field buffer");
@@ -166,12 +171,22 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
     return set_err(ctx, BZ_EINVAL, "BZ_Q_CONSERVE requires BZ_Q_CORRECTED");
   if (theta && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "theta requires BZ_Q_CORRECTED");
   if ((flags & BZ_Q_MASS) && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS requires BZ_Q_CORRECTED");
+  if (ctx->d == 2 && (flags & BZ_Q_CONSERVE)) return set_err(ctx, BZ_EUNSUPPORTED, "BZ_Q_CONSERVE with d = 2");
+  return BZ_OK;
+}
+
+}  // namespace bz
+
+extern "C" {
+
+bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags, double* theta,
+                    void* stream) {
+  bz_status cs = bz::check_eval_q_args(ctx, f, Q, batch, flags, theta);
+  if (cs != BZ_OK) return cs;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if (ctx->d == 2) {
-    if (flags & BZ_Q_CONSERVE) return set_err(ctx, BZ_EUNSUPPORTED, "BZ_Q_CONSERVE with d = 2");
+  if (ctx->d == 2)
     return bz::v2_eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, (flags & BZ_Q_MASS) != 0, theta, st);
-  }
   if (!(flags & (BZ_Q_MASS | BZ_Q_CONSERVE)) || batch == 0)
     return bz::eval_q(ctx, f, Q, batch, (flags & BZ_Q_CORRECTED) != 0, theta, st);
   double* th = theta;

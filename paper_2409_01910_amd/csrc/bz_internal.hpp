@@ -61,6 +61,10 @@ struct bz_ctx {
   // workspace (grown on demand, never shrunk until destroy)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device address of the static scratch array of the allocation-free entry
+  // point on this context's device (resolved at create)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
 };
 
 namespace bz {
@@ -85,8 +89,11 @@ void free_tables(bz_ctx* ctx);
 // collision pipeline (bz_q.hip).  Writes Q (FP64).  When rho_out / theta_out are
 // non-null (corrected mode), the discrete Maxwellian parameters and density of
 // each cell are returned too.
+// With ws_ext non-null the pipeline runs in that caller-provided workspace of
+// ws_ext_bytes (chunks sized to it; BZ_EINVAL if one cell does not fit) and
+// allocates nothing.
 bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
-                 hipStream_t st);
+                 hipStream_t st, void* ws_ext = nullptr, size_t ws_ext_bytes = 0);
 size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected);
 // sizes the workspace and sets kernel attributes for eval_q on `batch` cells,
 // so that a later eval_q makes no allocation (needed under stream capture)
@@ -99,8 +106,16 @@ bz_status v2_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
 // Q (FP64) of each cell; corrected: Q_s(f - M, f + M) with M from theta (computed
 // here, written to theta_out [batch][4] when non-null); mass: the projection of
 // mass_project on the corrected form
+// ws_ext as for eval_q: the [batch][4] parameters of the corrected form go there
+// when theta_out is NULL (BZ_EINVAL if they do not fit)
 bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, bool mass,
-                    double* theta_out, hipStream_t st);
+                    double* theta_out, hipStream_t st, void* ws_ext = nullptr, size_t ws_ext_bytes = 0);
+// allocation-free collision evaluation (bz_noalloc.hip): resolves, once per
+// device, the device address of the library's static scratch array
+bz_status scratch_attach(bz_ctx* ctx);
+// argument checks shared by bz_eval_Q and bz_eval_Q_noalloc (bz_api.cpp)
+bz_status check_eval_q_args(bz_ctx* ctx, const double* f, const double* Q, int64_t batch, uint32_t flags,
+                            const double* theta);
 
 // cell kernels (bz_cell.hip)
 bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int32_t* iters, int64_t batch,

@@ -991,11 +991,12 @@ static size_t ws_per_cell(int N, int n_theta, int nf) {
               cs /*Qh*/);
 }
 
-// cells per chunk of the collision workspace (2 GiB budget)
+// cells per chunk of the collision workspace (2 GiB budget, or the bytes of a
+// caller-provided workspace)
 template <typename T, int N>
-static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected) {
+static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected, size_t budget = (size_t)2 << 30) {
   const size_t per = ws_per_cell<T>(N, ctx->n_theta, corrected ? 2 : 1);
-  int64_t chunk = (int64_t)(((size_t)2 << 30) / per);
+  int64_t chunk = (int64_t)(budget / per);
   if (chunk < 1) chunk = 1;
   if (chunk > batch) chunk = batch;
   return chunk;
@@ -1016,16 +1017,26 @@ static bz_status prepare_chunked(bz_ctx* ctx, int64_t batch, bool corrected) {
 
 template <typename T, int N>
 static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
-                             hipStream_t st) {
+                             hipStream_t st, void* ws_ext, size_t ws_ext_bytes) {
   using C = typename V2<T>::type;
   constexpr int K = N * N * N, NN = N * N;
   const int nf = corrected ? 2 : 1;
   const int nt = ctx->n_theta;
   const size_t per = ws_per_cell<T>(N, nt, nf);
-  const int64_t chunk = chunk_cells<T, N>(ctx, batch, corrected);
-  bz_status s = ensure_ws(ctx, per * chunk);
-  if (s != BZ_OK) return s;
-  unsigned char* base = (unsigned char*)ctx->ws;
+  bz_status s = BZ_OK;
+  int64_t chunk;
+  unsigned char* base;
+  if (ws_ext) {
+    // the caller's workspace: no allocation, chunks sized to it
+    if (per > ws_ext_bytes) return set_err(ctx, BZ_EINVAL, "one cell's collision workspace exceeds the given workspace");
+    chunk = chunk_cells<T, N>(ctx, batch, corrected, ws_ext_bytes);
+    base = (unsigned char*)ws_ext;
+  } else {
+    chunk = chunk_cells<T, N>(ctx, batch, corrected);
+    s = ensure_ws(ctx, per * chunk);
+    if (s != BZ_OK) return s;
+    base = (unsigned char*)ctx->ws;
+  }
   C* Fc = (C*)base;
   C* Lc = Fc + (size_t)chunk * nf * K;
   double* GH = (double*)(Lc + (size_t)chunk * nf * K);
@@ -1157,19 +1168,19 @@ bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected) {
 }
 
 bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
-                 hipStream_t st) {
+                 hipStream_t st, void* ws_ext, size_t ws_ext_bytes) {
   if (batch == 0) return BZ_OK;
   const bool fp32 = ctx->p.precision == BZ_FP32;
   switch (ctx->N) {
     case 8:
-      return fp32 ? run_chunked<float, 8>(ctx, f, Q, batch, corrected, theta_out, st)
-                  : run_chunked<double, 8>(ctx, f, Q, batch, corrected, theta_out, st);
+      return fp32 ? run_chunked<float, 8>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes)
+                  : run_chunked<double, 8>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes);
     case 16:
-      return fp32 ? run_chunked<float, 16>(ctx, f, Q, batch, corrected, theta_out, st)
-                  : run_chunked<double, 16>(ctx, f, Q, batch, corrected, theta_out, st);
+      return fp32 ? run_chunked<float, 16>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes)
+                  : run_chunked<double, 16>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes);
     case 32:
-      return fp32 ? run_chunked<float, 32>(ctx, f, Q, batch, corrected, theta_out, st)
-                  : run_chunked<double, 32>(ctx, f, Q, batch, corrected, theta_out, st);
+      return fp32 ? run_chunked<float, 32>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes)
+                  : run_chunked<double, 32>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes);
     default:
       return set_err(ctx, BZ_EUNSUPPORTED, "N must be 8, 16 or 32");
   }

@@ -822,14 +822,18 @@ bz_status v2_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
 }
 
 bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, bool mass,
-                    double* theta_out, hipStream_t st) {
+                    double* theta_out, hipStream_t st, void* ws_ext, size_t ws_ext_bytes) {
   if (batch == 0) return BZ_OK;
   if (batch > INT32_MAX) return set_err(ctx, BZ_EINVAL, "batch too large");
   const int N = ctx->N;
   double* th = nullptr;
   if (corrected) {
     th = theta_out;
-    if (!th) {
+    if (!th && ws_ext) {
+      if ((size_t)batch * 4 * sizeof(double) > ws_ext_bytes)
+        return set_err(ctx, BZ_EINVAL, "the Maxwellian parameters of the batch exceed the given workspace");
+      th = (double*)ws_ext;
+    } else if (!th) {
       bz_status s = ensure_ws(ctx, (size_t)batch * 4 * sizeof(double));
       if (s != BZ_OK) return s;
       th = (double*)ctx->ws;
