@@ -546,57 +546,77 @@ def shock_workload(args, tol=1e-8):
             "config": {"workload": "shock", "cells": 128, "N": 32, "mach": 1.5, "eps": 0.1}, "runs": out}
 
 
-def warmstart_workload(args):
-    """Learned warm start at 32^3: train on cell solves generated by the library
-    (shock and heat-slab profile families), then solve held-out cells to inner
-    residual 1e-8 with the plain FP64 path and with learned start + FP32
-    spectral stage; report inner updates and wall time of each."""
+def warmstart_workload(args, n_train=None, n_test=None, n_snap=None, hidden=256, epochs=None):
+    """Time to outer residual 1e-8 on held-out heat-slab instances, learned start
+    + FP32 spectral stage against the plain FP64 method.
+
+    Family (paper_2409_01910_amd.warmstart): 32 cells on [0, 1], walls T_L = 1 and
+    T_R ~ U(1.5, 2.5), eps log-uniform in [0.005, 1], 32^3 velocities on
+    [-8, 8]^3, M = 32 (4 x 8), 8 radial nodes, MG-SGS-PFP V-cycles (coarsest 4,
+    one pre- and one post-smoothing step), inner residual 1e-8.  The network is
+    trained on the solver's own iterates of n_train instances (the states after
+    V-cycles 0..n_snap-1, every cell's inner solution as the target); each of
+    n_test held-out instances is then solved four ways: plain FP64, learned FP64,
+    plain FP32 spectral stage (to ten times its residual floor, warmstart.fp32_switch)
+    then FP64, learned + FP32 then FP64."""
+    import numpy as np
     import torch
 
     import paper_2409_01910_amd as bz
     from paper_2409_01910_amd import warmstart as WS
 
-    dx = 40.0 / 128
-    ctx64 = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, precision=bz.BZ_FP64)
-    ctx32 = bz.Context(N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, precision=bz.BZ_FP32)
+    n_train = n_train or getattr(args, "ws_train", 24)
+    n_test = n_test or getattr(args, "ws_test", 6)
+    n_snap = n_snap or getattr(args, "ws_snap", 4)
+    epochs = epochs or getattr(args, "ws_epochs", 30)
+    nx, seed = 32, 11
+    kw = dict(N=32, L=8.0, n_theta=4, n_phi=8, n_rho=8)
+    ctx64 = bz.Context(precision=bz.BZ_FP64, **kw)
+    ctx32 = bz.Context(precision=bz.BZ_FP32, **kw)
+    train_inst = [WS.heat_slab_instance(seed, i, nx) for i in range(n_train)]
+    test_inst = [WS.heat_slab_instance(seed, 100000 + i, nx) for i in range(n_test)]
+    print(f"# warm start: data from {n_train} instances", file=sys.stderr, flush=True)
+    X, Y, dinfo = WS.sweep_dataset(ctx64, train_inst, n_snap=n_snap)
+    print(f"# warm start: {dinfo['samples']} samples in {dinfo['seconds']:.1f}s; training", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    X, Y, _, st = WS.make_dataset(ctx64, 160, 8, dx, seed=7)
-    t_data = time.perf_counter() - t0
-    print(f"# dataset {X.shape[0]} cells in {t_data:.1f}s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    mlp, hist = WS.train(ctx32, X, Y, hidden=256, epochs=30, batch=128, lr=1e-3,
-                         log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    mlp64, hist, y_scale = WS.train(ctx64, X, Y, hidden=hidden, epochs=epochs, batch=128, lr=1e-3)
     t_train = time.perf_counter() - t0
     del X, Y
-    _, _, (fo, inflow, eps), _ = WS.make_dataset(ctx64, 40, 8, dx, seed=7, start=1000)
-    torch.cuda.synchronize()
-    res = {}
-    for name, ctx, learned in (("plain_fp64", ctx64, False), ("learned_fp32", ctx32, True),
-                               ("plain_fp32", ctx32, False)):
-        fn = (lambda: ctx.cell_fixed_point_learned(mlp, fo, inflow, eps, dx, tol=1e-8, max_iter=100)) if learned \
-            else (lambda: ctx.cell_fixed_point(fo, inflow, eps, dx, tol=1e-8, max_iter=100))
-        g, s = fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            g, s = fn()
-        torch.cuda.synchronize()
-        d = bz.Context.decode_stats(s)
-        res[name] = {"seconds": (time.perf_counter() - t0) / 3, "cells": int(fo.shape[0]),
-                     "mean_inner_iterations": float(d["iterations"].mean()),
-                     "learned_kept": int(d["learned"].sum()), "unconverged": int((d["status"] != 0).sum())}
-        if name == "plain_fp64":
-            g64 = g
-        else:
-            res[name]["max_rel_diff_vs_plain_fp64"] = (g - g64).abs().max().item() / g64.abs().max().item()
-    return {"metric": "time to inner residual 1e-8 on held-out cells, learned+FP32 vs plain FP64",
-            "value": res["learned_fp32"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
-            "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "warmstart", "N": N, "M": N_THETA * N_PHI, "n_rho": N_RHO, "hidden": 256,
-                       "train_cells": int(len(hist) and 0) or None},
-            "train": {"dataset_seconds": t_data, "train_seconds": t_train, "loss_first": hist[0],
-                      "loss_last": hist[-1]},
-            "results": res}
+    torch.cuda.empty_cache()
+    mlp32 = WS.clone_network(mlp64, ctx32, y_scale)
+    plans = {"plain_fp64": [(ctx64, None, 1e-8)], "learned_fp64": [(ctx64, mlp64, 1e-8)],
+             "plain_fp32_then_fp64": [(ctx32, None, WS.fp32_switch), (ctx64, None, 1e-8)],
+             "learned_fp32_then_fp64": [(ctx32, mlp32, WS.fp32_switch), (ctx64, mlp64, 1e-8)]}
+    per = []
+    for i, inst in enumerate(test_inst):
+        row = {"T_R": inst["T_R"], "eps": inst["eps"]}
+        for name, plan in plans.items():
+            row[name] = WS.time_to_residual(plan, inst)
+        print(f"# held-out {i}: eps {inst['eps']:.4f} " +
+              " ".join(f"{k} {row[k]['seconds']:.2f}s/{row[k]['vcycles']}" for k in plans), file=sys.stderr,
+              flush=True)
+        per.append(row)
+    summ = {}
+    for name in plans:
+        summ[name] = {"seconds_total": float(sum(r[name]["seconds"] for r in per)),
+                      "vcycles_total": int(sum(r[name]["vcycles"] for r in per)),
+                      "inner_per_visit": float(np.mean([r[name]["inner_per_visit"] for r in per])),
+                      "learned_taken": int(sum(r[name]["learned_taken"] for r in per)),
+                      "visits": int(sum(r[name]["visits"] for r in per)),
+                      "all_reached": bool(all(r[name]["reached"] for r in per))}
+    ratio = summ["plain_fp64"]["seconds_total"] / summ["learned_fp32_then_fp64"]["seconds_total"]
+    ctx32.close()
+    ctx64.close()
+    return {"metric": "time to outer residual 1e-8 on held-out heat-slab instances (sum), learned+FP32 vs plain FP64",
+            "value": summ["learned_fp32_then_fp64"]["seconds_total"], "unit": "s", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"heat slabs, {nx} cells, 32^3 on [-8,8]^3, M=32 (4x8), n_rho=8, "
+                                   f"MG-SGS-PFP; {n_train} training / {n_test} held-out instances",
+                       "hidden": hidden, "snapshots": n_snap, "epochs": epochs},
+            "speedup_plain_fp64_over_learned_fp32": ratio,
+            "train": {"samples": dinfo["samples"], "dropped": dinfo["dropped"], "dataset_seconds": dinfo["seconds"],
+                      "train_seconds": t_train, "loss_first": hist[0], "loss_last": hist[-1]},
+            "summary": summ, "held_out": per}
 
 
 def main():
@@ -630,6 +650,11 @@ def main():
                     choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg", "mg_carleman")
                                        for e in ("1", "0.1", "0.01", "0.001")],
                     help="with --workload plates: run one case only")
+    ap.add_argument("--ws-train", type=int, default=24, help="warmstart: training instances")
+    ap.add_argument("--ws-test", type=int, default=6, help="warmstart: held-out instances")
+    ap.add_argument("--ws-snap", type=int, default=4, help="warmstart: V-cycle states per training instance")
+    ap.add_argument("--ws-epochs", type=int, default=30, help="warmstart: training epochs")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-start time-to-residual runs")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
@@ -790,6 +815,17 @@ def main():
             "cavity_40x40_mg_eps0.1_carleman": {"seconds": cavc["seconds"], "vcycles": cavc["iterations"],
                                                 "final_residual": cavc["final_residual"], "reached": cavc["reached"],
                                                 "paper_seconds_unstated_hardware": 268.42}}
+    if not args.no_warmstart:
+        # the second half of the metric: time to outer residual 1e-8, learned start
+        # + FP32 spectral stage against the plain FP64 method (reduced instance
+        # counts; bench.py --workload warmstart runs the larger set)
+        print("# learned warm start: time to residual 1e-8", file=sys.stderr, flush=True)
+        ws = warmstart_workload(args, n_train=16, n_test=4)
+        line["learned_time_to_residual"] = {
+            "workload": ws["config"]["workload"], "value_s": ws["value"],
+            "plain_fp64_s": ws["summary"]["plain_fp64"]["seconds_total"],
+            "speedup_plain_fp64_over_learned_fp32": ws["speedup_plain_fp64_over_learned_fp32"],
+            "summary": ws["summary"], "train": ws["train"]}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)

@@ -358,6 +358,7 @@ typedef struct {
   int64_t inner_iters;   /* total inner updates over all visits */
   int64_t visits;        /* cell visits */
   int64_t fallbacks;     /* visits that fell back to the plain iteration */
+  int64_t learned;       /* visits that started from the learned guess (bz_ws_attach) */
 } bz_sweep_stats;
 
 /* bz_sgs_sweep: n_iters full SGS iterations (forward then backward scan,
@@ -369,6 +370,33 @@ typedef struct {
  * residual AFTER the last iteration. */
 bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* slab, int n_iters, double* residual_out, bz_sweep_stats* stats,
                        void* stream);
+
+/* bz_slab_inflow: the transport part of eq. r for every cell of the slab's
+ * current iterate, with both neighbours and the boundary ghosts (eq. boundary,
+ * or the inflow Maxwellians) taken from that iterate:
+ *   (v1- E - v1+ W) / dx - (v1+ s_W - v1 s + v1- s_E) / (2 dx),
+ * W / E the left / right neighbour or ghost, s the slopes of eq. slope at
+ * second order (zero in the ghosts), v1 the physical velocity.  It is what a
+ * visit's r holds, less -P/eps, before any neighbour has been updated in the
+ * scan: the input of the learned warm start, and of the cell problems that
+ * train it.  out [sum nx][K] device. */
+bz_status bz_slab_inflow(bz_ctx* ctx, bz_slab* slab, double* out, void* stream);
+
+/* bz_ws_attach: use a warm-start network (bz_mlp with n_in = K + 6, n_out = K,
+ * on the slab's context) in the slab's scans; NULL detaches.  Before each scan
+ * every cell gets a second initial guess G = M[f_j] + scale * MLP(features of
+ * bz_slab_inflow's row), BF16 inference with FP32 accumulation, computed for
+ * all cells at once.  A visit starts from G instead of f_j when G has no
+ * negative value and G's inner residual
+ * |c g + r_old - (nu/eps)(M[g] - g)|_{L2} is the smaller, r_old being
+ * the visit's right-hand side with its upwind neighbour taken from the iterate
+ * before the scan (the fresh value is not known then); the plain iteration of
+ * the visit is unchanged, so the result is again the visit's inner solution,
+ * to the inner tolerance.  bz_sweep_stats.learned counts the visits that
+ * started from G.  The slab borrows the network; it must outlive the
+ * attachment.  A slab with a network attached cannot be graph-captured
+ * (BZ_EUNSUPPORTED).  Not part of the paper's method. */
+bz_status bz_ws_attach(bz_slab* slab, bz_mlp* mlp);
 
 /* bz_outer_residual: sqrt(sum_j dx sum_k w (v.grad f - Q/eps)^2) per instance
  * (Section 4 stopping rule), into residual_out (host) [n_instances]. */

@@ -50,3 +50,17 @@ def loss_and_grad(theta, X, T, n_in, H, n_out):
     gW1 = X.T @ da1
     gb1 = da1.sum(0)
     return loss, np.concatenate([g.reshape(-1) for g in (gW1, gb1, gW2, gb2, gW3, gb3)])
+
+
+def features(spec, inflow, theta, eps, dx):
+    """Input row of the warm-start network for one cell: the transport part of
+    the right-hand side of eq. r times dx (K values), then the density, the three
+    bulk-velocity components and the temperature read from the parameters
+    theta = (alpha, beta, gamma) of the cell's discrete Maxwellian
+    (rho = sum_k w M_theta, U = beta / (2 gamma), T = 1 / (2 gamma)), then log10(eps)."""
+    from .maxwellian import gaussian
+
+    rho = spec.w * np.sum(gaussian(spec, theta))
+    T = 0.5 / theta[-1]
+    U = np.asarray(theta[1:-1]) * T
+    return np.concatenate([np.asarray(inflow) * dx, [rho], U, [T], [np.log10(eps)]])

@@ -61,7 +61,10 @@ class Slab:
     tol_inner: float = 1e-8
     max_inner: int = 100
     fixed_inner: int | None = None
-    stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0})
+    # learned warm start: (flat parameters, n_in, hidden, n_out, output scale) of
+    # the network of oracle.mlp, or None for the plain start g0 = f_j
+    warm: tuple | None = None
+    stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0, "learned": 0})
 
     @property
     def dx(self) -> float:
@@ -173,6 +176,66 @@ def all_collision(prob: Slab, f: np.ndarray):
     return Q, M, nu
 
 
+def transport_part(prob: Slab, f: np.ndarray, s: np.ndarray | None = None) -> np.ndarray:
+    """Transport part of the right-hand side r of eq. r for every cell, with both
+    neighbours and the wall ghosts taken from f (and the slopes s of f): what a
+    visit's r would be, less -P/eps, if no neighbour had been updated yet."""
+    spec = prob.spec
+    v1 = transport_v1(spec)
+    vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
+    if s is None:
+        s = slopes(prob, f)
+    gl, gr = ghosts(prob, f, s)
+    s_e = np.concatenate([np.zeros((1, spec.K)), s, np.zeros((1, spec.K))])
+    T = np.empty_like(f)
+    for j in range(prob.nx):
+        left = f[j - 1] if j > 0 else gl
+        right = f[j + 1] if j < prob.nx - 1 else gr
+        T[j] = (-vp * left + vm * right) / prob.dx - (vp * s_e[j] - v1 * s_e[j + 1] + vm * s_e[j + 2]) / (2.0 * prob.dx)
+    return T
+
+
+def warm_starts(prob: Slab, f: np.ndarray, P: np.ndarray, nu: np.ndarray, b: np.ndarray | None):
+    """Initial guesses of a scan's visits with the learned warm start (not part of
+    the paper's method; it changes only where each inner iteration starts).
+
+    Before the scan, every cell gets a second candidate G_j = M[f_j] + scale * y_j,
+    y_j the network's output for the features of the cell's transport part with
+    both neighbours taken from the iterate before the scan (oracle.mlp.features).
+    The visit starts from G_j when G_j has no negative value and its inner
+    residual
+        |c g + r_old - (nu/eps)(M[g] - g)|_{L2}
+    is smaller than that of f_j, where r_old is the visit's right-hand side with
+    the upwind neighbour taken from the iterate before the scan (the fresh one is
+    not known yet), i.e. the transport part minus P/eps (minus the FAS source)."""
+    from . import mlp as mlpmod
+
+    spec = prob.spec
+    params, n_in, H, n_out, scale = prob.warm
+    T = transport_part(prob, f)
+    c = cellmod.transport_coef(spec, prob.dx)
+    lam = nu / prob.eps
+    out = []
+    for j in range(prob.nx):
+        Mf, th = discrete_maxwellian(spec, f[j], return_theta=True)
+        x = mlpmod.features(spec, T[j], th, prob.eps, prob.dx)
+        y, _ = mlpmod.forward(params, x[None, :], n_in, H, n_out)
+        G = Mf + scale * y[0]
+        r_old = T[j] - P[j] / prob.eps - (b[j] if b is not None else 0.0)
+        res_f = np.sum((c * f[j] + r_old - lam[j] * (Mf - f[j])) ** 2)
+        if G.min() < 0.0:  # not a distribution: never a start
+            out.append(None)
+            continue
+        try:
+            MG = discrete_maxwellian(spec, G)
+        except RuntimeError:
+            out.append(None)
+            continue
+        res_G = np.sum((c * G + r_old - lam[j] * (MG - G)) ** 2)
+        out.append(G if res_G < res_f else None)
+    return out
+
+
 def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) -> np.ndarray:
     """One SGS scan (the first or second line of eq. SGS): P and nu from the iterate
     before the scan, slopes from the previous scan, cells visited in order."""
@@ -183,6 +246,7 @@ def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) 
     Q, M, nu = all_collision(prob, f)
     P = penalty_split(Q, M, f, nu)
     s = slopes(prob, f)
+    warm = warm_starts(prob, f, P, nu, b) if prob.warm is not None else [None] * prob.nx
     f = f.copy()
     order = range(prob.nx) if forward else range(prob.nx - 1, -1, -1)
     for j in order:
@@ -196,8 +260,10 @@ def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) 
         r -= P[j] / eps
         if b is not None:
             r -= b[j]
-        g, st = cellmod.solve(spec, r, nu[j], eps, dx, f[j], mode=prob.inner, tol=prob.tol_inner,
+        g0 = f[j] if warm[j] is None else warm[j]
+        g, st = cellmod.solve(spec, r, nu[j], eps, dx, g0, mode=prob.inner, tol=prob.tol_inner,
                               max_iter=prob.max_inner, fixed_iters=prob.fixed_inner)
+        prob.stats["learned"] = prob.stats.get("learned", 0) + int(warm[j] is not None)
         prob.stats["inner"] += st.iterations
         prob.stats["fallback"] += int(st.fallback)
         prob.stats["visits"] += 1

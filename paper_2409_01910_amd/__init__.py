@@ -37,6 +37,7 @@ EXPORTED = [
     "bz_cell_fixed_point_learned",
     "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
     "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
+    "bz_slab_inflow", "bz_ws_attach",
 ]
 
 
@@ -84,7 +85,7 @@ class bz_cavity_desc(ctypes.Structure):
 
 class bz_sweep_stats(ctypes.Structure):
     _fields_ = [("n_iters", ctypes.c_int), ("inner_iters", ctypes.c_int64), ("visits", ctypes.c_int64),
-                ("fallbacks", ctypes.c_int64)]
+                ("fallbacks", ctypes.c_int64), ("learned", ctypes.c_int64)]
 
 
 class bz_mg_opts(ctypes.Structure):
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_cavity_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                      ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_outer_residual.argtypes = [P, P, P, P]
+    lib.bz_slab_inflow.argtypes = [P, P, P, P]
+    lib.bz_ws_attach.argtypes = [P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_mlp_create.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
@@ -433,7 +436,25 @@ class Slab:
 
     @staticmethod
     def _stats(st):
-        return {"n_iters": st.n_iters, "inner_iters": st.inner_iters, "visits": st.visits, "fallbacks": st.fallbacks}
+        return {"n_iters": st.n_iters, "inner_iters": st.inner_iters, "visits": st.visits, "fallbacks": st.fallbacks,
+                "learned": st.learned}
+
+    def inflow(self, out=None):
+        """bz_slab_inflow: the transport part of eq. r of every cell of the current
+        iterate, both neighbours (and ghosts) from that iterate; [sum nx, K]."""
+        import torch
+
+        T = torch.empty_like(self.f) if out is None else _arg(out, "out", self.f.numel(), device=self.f.device)
+        self.ctx._check(self.ctx.lib.bz_slab_inflow(self.ctx.h, self.h, _ptr(T), _stream()), "bz_slab_inflow")
+        return T
+
+    def attach_warmstart(self, mlp):
+        """bz_ws_attach: start visits from the network's guess where its inner
+        residual is the smaller (None detaches).  Keeps a reference to mlp."""
+        if mlp is not None and (mlp.n_in != self.ctx.K + 6 or mlp.n_out != self.ctx.K):
+            raise BZError(f"the network must map K + 6 = {self.ctx.K + 6} inputs to K = {self.ctx.K} outputs")
+        self.ctx._check(self.ctx.lib.bz_ws_attach(self.h, mlp.h if mlp is not None else None), "bz_ws_attach")
+        self._ws = mlp
 
     def sweep(self, n_iters: int = 1):
         """n_iters SGS iterations; returns (residuals per instance, stats)."""

@@ -831,6 +831,7 @@ bz_status read_stats(bz_ctx* ctx, bz_cavity* cv, bz_sweep_stats* stats, int n, h
     stats->inner_iters = (int64_t)h[0];
     stats->visits = (int64_t)h[1];
     stats->fallbacks = (int64_t)h[2];
+    stats->learned = 0;
   }
   return BZ_OK;
 }

@@ -126,6 +126,15 @@ bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const doubl
 // learned initial guesses g0 [batch][K] (bz_mlp.hip)
 bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const double* theta, const double* eps,
                         double dx, double* g0, int64_t batch, hipStream_t st);
+// learned warm start inside the scans (bz_mlp.hip): candidates
+// G = M_theta + scale MLP(features) of a batch with per-cell eps and dx (BF16
+// inference), and the sizing of the network's scratch and BF16 weights
+bz_status ws_candidates(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, const double* eps,
+                        const double* dxs, double* G, int64_t batch, hipStream_t st);
+bz_status ws_prepare(bz_mlp* mp, int64_t batch, hipStream_t st);
+bz_ctx* ws_ctx(bz_mlp* mp);
+int ws_n_in(bz_mlp* mp);
+int ws_n_out(bz_mlp* mp);
 // Q <- Q - M_theta sum(Q) / sum(M_theta) per cell (mass-conserving projection)
 bz_status mass_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st);
 // Q <- Q - M_theta (a . phi): mass, momentum and energy conserved per cell

@@ -30,15 +30,21 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 // C[i][j] (+)= sum_k A(i, k) B(k, j), A(i, k) = A[i * sai + k * sak],
 // B(k, j) = B[k * sbk + j * sbj]; TI = unsigned short (BF16 bits) or float.
 // 64 x 64 tile per work-group of 4 waves, each wave a 32 x 32 block of 2 x 2
-// 16 x 16 matrix-core tiles; K in steps of 16 staged through LDS.
+// 16 x 16 matrix-core tiles; K in steps of 16 staged through LDS.  Split K:
+// work-group z of the grid's third dimension sums k in [z kslice, (z+1) kslice)
+// into the partial tile C + z cstride (reduced afterwards in a fixed order).
 template <typename TI>
 __global__ __launch_bounds__(256) void k_gemm(const TI* __restrict__ A, int64_t sai, int64_t sak,
                                               const TI* __restrict__ B, int64_t sbk, int64_t sbj,
-                                              float* __restrict__ C, int64_t ldc, int M, int N, int K, int accumulate) {
+                                              float* __restrict__ C, int64_t ldc, int M, int N, int Kall, int accumulate,
+                                              int kslice, int64_t cstride) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ TI As[BM][BK + 2];
   __shared__ TI Bs[BK][BN + 2];
   const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kslice;
+  const int K = (kbeg + kslice) < Kall ? (kbeg + kslice) : Kall;
+  C += (int64_t)blockIdx.z * cstride;
   const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
   const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
   f32x4 acc[2][2];
@@ -46,7 +52,7 @@ __global__ __launch_bounds__(256) void k_gemm(const TI* __restrict__ A, int64_t 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < K; k0 += BK) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = t + 256 * u;
@@ -94,6 +100,18 @@ __global__ __launch_bounds__(256) void k_gemm(const TI* __restrict__ A, int64_t 
           *c = accumulate ? *c + acc[a][b][r] : acc[a][b][r];
         }
       }
+}
+
+// C[i][j] (+)= sum_z P[z][i][j] over the splits, in order (deterministic)
+__global__ void k_split_reduce(const float* __restrict__ P, float* __restrict__ C, int64_t ldc, int M, int N, int S,
+                               int accumulate) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)M * N) return;
+  const int i = (int)(g / N), j = (int)(g % N);
+  float acc = 0.f;
+  for (int z = 0; z < S; ++z) acc += P[(int64_t)z * M * N + g];
+  float* c = C + (int64_t)i * ldc + j;
+  *c = accumulate ? *c + acc : acc;
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -155,13 +173,16 @@ __global__ void k_to_bf16(const float* __restrict__ x, unsigned short* __restric
 }
 
 // features of one cell (block per cell); writes float and/or BF16 rows of width K + 6
+// (dxs, when non-null, gives each cell its own width in place of dx)
 template <int N>
 __global__ __launch_bounds__(256) void k_features(const double* __restrict__ inflow, const double* __restrict__ theta,
-                                                  const double* __restrict__ eps, double dx,
+                                                  const double* __restrict__ eps, double dx_all,
                                                   float* __restrict__ Xf, unsigned short* __restrict__ Xb,
-                                                  const double* __restrict__ nodes, double w) {
+                                                  const double* __restrict__ nodes, double w,
+                                                  const double* __restrict__ dxs = nullptr) {
   constexpr int K = N * N * N, W = K + 6;
   const int b = blockIdx.x;
+  const double dx = dxs ? dxs[b] : dx_all;
   const double* th = theta + (size_t)b * 5;
   const double* in = inflow + (size_t)b * K;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
@@ -227,6 +248,8 @@ struct bz_mlp {
   float *h1 = nullptr, *h2 = nullptr, *y = nullptr, *d1 = nullptr, *d2 = nullptr, *dy = nullptr;
   unsigned short *xb = nullptr, *h1b = nullptr, *h2b = nullptr;
   double* part = nullptr;
+  float* ksplit = nullptr;  // partial tiles of split-K products [kMaxSplit][B][max(H, ...)]
+  int64_t ksplit_cap = 0;   // floats
 };
 
 namespace bz {
@@ -247,17 +270,43 @@ static Off offsets(const bz_mlp* m) {
 
 static unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+constexpr int kMaxSplit = 64;
+
+// Products with few output tiles and a long K (the first layer on a batch of a
+// few dozen cells: 32 x 256 outputs over K = 32774) split K over up to
+// kMaxSplit work-groups per tile so that the chip fills, and reduce the
+// partial tiles in order afterwards; the others run as one launch.
 template <typename TI>
 static void gemm(const TI* A, int64_t sai, int64_t sak, const TI* B, int64_t sbk, int64_t sbj, float* C, int64_t ldc,
-                 int M, int N, int K, bool acc, hipStream_t st) {
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL((k_gemm<TI>), grid, dim3(256), 0, st, A, sai, sak, B, sbk, sbj, C, ldc, M, N, K, acc ? 1 : 0);
+                 int M, int N, int K, bool acc, hipStream_t st, float* partial = nullptr, int64_t partial_cap = 0) {
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  int S = 1;
+  if (partial && tiles < 256 && K >= 2048) {
+    S = (512 + tiles - 1) / tiles;
+    if (S > kMaxSplit) S = kMaxSplit;
+    if (S > K / 1024) S = K / 1024;
+    while (S > 1 && (int64_t)S * M * N > partial_cap) --S;
+  }
+  if (S <= 1) {
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+    hipLaunchKernelGGL((k_gemm<TI>), grid, dim3(256), 0, st, A, sai, sak, B, sbk, sbj, C, ldc, M, N, K, acc ? 1 : 0,
+                       K, (int64_t)0);
+    return;
+  }
+  const int kslice = ((K + S - 1) / S + 15) / 16 * 16;
+  S = (K + kslice - 1) / kslice;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)S);
+  hipLaunchKernelGGL((k_gemm<TI>), grid, dim3(256), 0, st, A, sai, sak, B, sbk, sbj, partial, (int64_t)N, M, N, K, 0,
+                     kslice, (int64_t)M * N);
+  const int64_t n = (int64_t)M * N;
+  hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, partial, C, ldc, M, N, S,
+                     acc ? 1 : 0);
 }
 
 static bz_status ensure_cap(bz_mlp* mp, int64_t B) {
   bz_ctx* ctx = mp->ctx;
   if (B <= mp->cap) return BZ_OK;
-  void* ptrs[] = {mp->h1, mp->h2, mp->y, mp->d1, mp->d2, mp->dy, mp->xb, mp->h1b, mp->h2b, mp->part};
+  void* ptrs[] = {mp->h1, mp->h2, mp->y, mp->d1, mp->d2, mp->dy, mp->xb, mp->h1b, mp->h2b, mp->part, mp->ksplit};
   BZ_HIP(hipDeviceSynchronize());
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -272,6 +321,9 @@ static bz_status ensure_cap(bz_mlp* mp, int64_t B) {
   BZ_HIP(hipMalloc((void**)&mp->h1b, sizeof(unsigned short) * B * H));
   BZ_HIP(hipMalloc((void**)&mp->h2b, sizeof(unsigned short) * B * H));
   BZ_HIP(hipMalloc((void**)&mp->part, sizeof(double) * ((B * O + 255) / 256)));
+  // split-K partials: the products that split have M = B and N = H
+  mp->ksplit_cap = (int64_t)kMaxSplit * B * H;
+  BZ_HIP(hipMalloc((void**)&mp->ksplit, sizeof(float) * mp->ksplit_cap));
   mp->cap = B;
   return BZ_OK;
 }
@@ -301,19 +353,19 @@ static bz_status forward(bz_mlp* mp, const void* X, int64_t B, bool bf16, hipStr
     const unsigned short* W1 = mp->wb;
     const unsigned short* W2 = W1 + (int64_t)I * H;
     const unsigned short* W3 = W2 + (int64_t)H * H;
-    gemm<unsigned short>((const unsigned short*)X, I, 1, W1, H, 1, mp->h1, H, (int)B, H, I, false, st);
+    gemm<unsigned short>((const unsigned short*)X, I, 1, W1, H, 1, mp->h1, H, (int)B, H, I, false, st, mp->ksplit, mp->ksplit_cap);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(B * H)), dim3(256), 0, st, mp->h1, mp->p + o.b1, B, H, 1, mp->h1b);
-    gemm<unsigned short>(mp->h1b, H, 1, W2, H, 1, mp->h2, H, (int)B, H, H, false, st);
+    gemm<unsigned short>(mp->h1b, H, 1, W2, H, 1, mp->h2, H, (int)B, H, H, false, st, mp->ksplit, mp->ksplit_cap);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(B * H)), dim3(256), 0, st, mp->h2, mp->p + o.b2, B, H, 1, mp->h2b);
-    gemm<unsigned short>(mp->h2b, H, 1, W3, O, 1, mp->y, O, (int)B, O, H, false, st);
+    gemm<unsigned short>(mp->h2b, H, 1, W3, O, 1, mp->y, O, (int)B, O, H, false, st, mp->ksplit, mp->ksplit_cap);
   } else {
-    gemm<float>((const float*)X, I, 1, mp->p + o.W1, H, 1, mp->h1, H, (int)B, H, I, false, st);
+    gemm<float>((const float*)X, I, 1, mp->p + o.W1, H, 1, mp->h1, H, (int)B, H, I, false, st, mp->ksplit, mp->ksplit_cap);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(B * H)), dim3(256), 0, st, mp->h1, mp->p + o.b1, B, H, 1,
                        (unsigned short*)nullptr);
-    gemm<float>(mp->h1, H, 1, mp->p + o.W2, H, 1, mp->h2, H, (int)B, H, H, false, st);
+    gemm<float>(mp->h1, H, 1, mp->p + o.W2, H, 1, mp->h2, H, (int)B, H, H, false, st, mp->ksplit, mp->ksplit_cap);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(B * H)), dim3(256), 0, st, mp->h2, mp->p + o.b2, B, H, 1,
                        (unsigned short*)nullptr);
-    gemm<float>(mp->h2, H, 1, mp->p + o.W3, O, 1, mp->y, O, (int)B, O, H, false, st);
+    gemm<float>(mp->h2, H, 1, mp->p + o.W3, O, 1, mp->y, O, (int)B, O, H, false, st, mp->ksplit, mp->ksplit_cap);
   }
   hipLaunchKernelGGL(k_bias_act, dim3(nblk(B * O)), dim3(256), 0, st, mp->y, mp->p + o.b3, B, O, 0,
                      (unsigned short*)nullptr);
@@ -331,15 +383,15 @@ static bz_status grad(bz_mlp* mp, const float* X, const float* T, int64_t B, dou
   const int64_t n = B * O;
   hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, st, mp->y, T, mp->dy, n, mp->part);
   // dW3 = h2^T dy ; db3 = colsum(dy) ; dh2 = dy W3^T
-  gemm<float>(mp->h2, 1, H, mp->dy, O, 1, mp->g + o.W3, O, H, O, (int)B, false, st);
+  gemm<float>(mp->h2, 1, H, mp->dy, O, 1, mp->g + o.W3, O, H, O, (int)B, false, st, mp->ksplit, mp->ksplit_cap);
   hipLaunchKernelGGL(k_colsum, dim3(nblk(O)), dim3(256), 0, st, mp->dy, mp->g + o.b3, B, O);
-  gemm<float>(mp->dy, O, 1, mp->p + o.W3, 1, O, mp->d2, H, (int)B, H, O, false, st);
+  gemm<float>(mp->dy, O, 1, mp->p + o.W3, 1, O, mp->d2, H, (int)B, H, O, false, st, mp->ksplit, mp->ksplit_cap);
   hipLaunchKernelGGL(k_tanh_back, dim3(nblk(B * H)), dim3(256), 0, st, mp->d2, mp->d2, mp->h2, B * H);
-  gemm<float>(mp->h1, 1, H, mp->d2, H, 1, mp->g + o.W2, H, H, H, (int)B, false, st);
+  gemm<float>(mp->h1, 1, H, mp->d2, H, 1, mp->g + o.W2, H, H, H, (int)B, false, st, mp->ksplit, mp->ksplit_cap);
   hipLaunchKernelGGL(k_colsum, dim3(nblk(H)), dim3(256), 0, st, mp->d2, mp->g + o.b2, B, H);
-  gemm<float>(mp->d2, H, 1, mp->p + o.W2, 1, H, mp->d1, H, (int)B, H, H, false, st);
+  gemm<float>(mp->d2, H, 1, mp->p + o.W2, 1, H, mp->d1, H, (int)B, H, H, false, st, mp->ksplit, mp->ksplit_cap);
   hipLaunchKernelGGL(k_tanh_back, dim3(nblk(B * H)), dim3(256), 0, st, mp->d1, mp->d1, mp->h1, B * H);
-  gemm<float>(X, 1, I, mp->d1, H, 1, mp->g + o.W1, H, I, H, (int)B, false, st);
+  gemm<float>(X, 1, I, mp->d1, H, 1, mp->g + o.W1, H, I, H, (int)B, false, st, mp->ksplit, mp->ksplit_cap);
   hipLaunchKernelGGL(k_colsum, dim3(nblk(H)), dim3(256), 0, st, mp->d1, mp->g + o.b1, B, H);
   BZ_HIP(hipGetLastError());
   if (loss) {
@@ -405,7 +457,7 @@ void bz_mlp_destroy(bz_mlp* mp) {
   if (!mp) return;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {mp->p, mp->g, mp->m, mp->v, mp->wb, mp->h1, mp->h2, mp->y, mp->d1, mp->d2, mp->dy,
-                  mp->xb, mp->h1b, mp->h2b, mp->part};
+                  mp->xb, mp->h1b, mp->h2b, mp->part, mp->ksplit};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete mp;
@@ -532,5 +584,40 @@ bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const d
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
+
+// the learned candidates of a batch of cells with per-cell eps and dx (the
+// slab scans): features (BF16) -> MLP (BF16 products) -> G = M_theta + scale y
+bz_status ws_candidates(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, const double* eps,
+                        const double* dxs, double* G, int64_t batch, hipStream_t st) {
+  if (mp->n_in != ctx->K + 6 || mp->n_out != ctx->K) return set_err(ctx, BZ_EINVAL, "MLP sizes do not match K");
+  bz_status s = ensure_cap(mp, batch);
+  if (s != BZ_OK) return s;
+  switch (ctx->N) {
+    case 8: hipLaunchKernelGGL((k_features<8>), dim3((unsigned)batch), dim3(256), 0, st, inflow, theta, eps, 0.0, (float*)nullptr, mp->xb, ctx->d_nodes, ctx->w, dxs); break;
+    case 16: hipLaunchKernelGGL((k_features<16>), dim3((unsigned)batch), dim3(256), 0, st, inflow, theta, eps, 0.0, (float*)nullptr, mp->xb, ctx->d_nodes, ctx->w, dxs); break;
+    case 32: hipLaunchKernelGGL((k_features<32>), dim3((unsigned)batch), dim3(256), 0, st, inflow, theta, eps, 0.0, (float*)nullptr, mp->xb, ctx->d_nodes, ctx->w, dxs); break;
+    default: return set_err(ctx, BZ_EUNSUPPORTED, "N");
+  }
+  if ((s = forward(mp, mp->xb, batch, true, st)) != BZ_OK) return s;
+  switch (ctx->N) {
+    case 8: hipLaunchKernelGGL((k_warm_guess<8>), dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G, ctx->d_nodes); break;
+    case 16: hipLaunchKernelGGL((k_warm_guess<16>), dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G, ctx->d_nodes); break;
+    case 32: hipLaunchKernelGGL((k_warm_guess<32>), dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G, ctx->d_nodes); break;
+  }
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// sizes the network's scratch for `batch` rows and its BF16 weight copies, so
+// that later candidates make no allocation (graph capture of sweeps)
+bz_status ws_prepare(bz_mlp* mp, int64_t batch, hipStream_t st) {
+  bz_status s = ensure_cap(mp, batch);
+  if (s != BZ_OK) return s;
+  return refresh_bf16(mp, st);
+}
+
+bz_ctx* ws_ctx(bz_mlp* mp) { return mp->ctx; }
+int ws_n_in(bz_mlp* mp) { return mp->n_in; }
+int ws_n_out(bz_mlp* mp) { return mp->n_out; }
 
 }  // namespace bz

@@ -65,6 +65,13 @@ struct Level {
   double* cellsum = nullptr;
   double* ghost = nullptr;  // [n_inst][2] wall densities
   double* S = nullptr;      // [cells][K] slopes of eq. slope (second order only)
+  // learned warm start (allocated when a network is attached)
+  double* T = nullptr;        // [cells][K] transport part of r, both neighbours old
+  double* G = nullptr;        // [cells][K] learned candidates
+  double* theta_l = nullptr;  // [cells][5] parameters of M[G]
+  int32_t* it_l = nullptr;    // [cells] Newton iterations of M[G] (< 0: failed)
+  double* eta0 = nullptr;     // [cells][5] Newton start of the visit's M[g0]
+  double* cell_eps = nullptr, *cell_dx = nullptr;  // [cells] per-cell eps and dx
   bool q_valid = false;
 };
 
@@ -82,9 +89,10 @@ struct bz_slab {
   double* wallM = nullptr;    // [n_inst][2][K] unit-density wall Maxwellians
   double* wall_in = nullptr;  // [n_inst][2] incoming discrete flux of the unit wall Maxwellian
   double* bc_fixed = nullptr;  // [n_inst][2] inflow density, or 0 at a diffuse wall
-  unsigned long long* d_stats = nullptr;  // inner iterations, visits, fallbacks
+  unsigned long long* d_stats = nullptr;  // inner iterations, visits, fallbacks, learned starts kept
   std::vector<bz::Level> levels;
   bool mg_built = false;
+  bz_mlp* ws = nullptr;  // attached warm-start network (borrowed), or NULL
 };
 
 namespace bz {
@@ -314,6 +322,113 @@ struct RChain {
   }
 };
 
+// Transport part of r for every cell with both neighbours (and the ghosts)
+// from the current iterate: idx (v- E - v+ W) - (v+ s_W - v_1 s + v- s_E) / (2 dx),
+// W / E the neighbours or the ghosts rho_w M_w, s the slopes (zero in the ghosts).
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_slab_transport(
+    const double* __restrict__ f, double* __restrict__ T, const InstDev* __restrict__ inst,
+    const int* __restrict__ cell_inst, const double* __restrict__ ghost, const double* __restrict__ wallM,
+    const double* __restrict__ nodes, double u0, const double* __restrict__ S) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const int i = cell_inst[c];
+  const InstDev id = inst[i];
+  const int j = c - id.off;
+  const double idx = 1.0 / id.dx;
+  const double* fc = f + (size_t)c * K;
+  const double* ML = wallM + (size_t)i * 2 * K;
+  const double* Wp = j > 0 ? fc - K : ML;
+  const double* Ep = j < id.nx - 1 ? fc + K : ML + K;
+  const double sW = j > 0 ? 1.0 : ghost[i * 2], sE = j < id.nx - 1 ? 1.0 : ghost[i * 2 + 1];
+  const double* Sc = S ? S + (size_t)c * K : fc;
+  const double* Sl = (S && j > 0) ? Sc - K : Sc;
+  const double* Sr = (S && j < id.nx - 1) ? Sc + K : Sc;
+  const double hsc = S ? 0.5 * idx : 0.0;
+  const double wl = (S && j > 0) ? 1.0 : 0.0, wr = (S && j < id.nx - 1) ? 1.0 : 0.0;
+  double* out = T + (size_t)c * K;
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += kCellThreads) {
+    const double v0 = nodes[k / (N * N)] + u0;  // physical v_1
+    const double vp = fmax(v0, 0.0), vm = fmin(v0, 0.0);
+    out[k] = idx * (vm * sE * Ep[k] - vp * sW * Wp[k]) - hsc * (vp * wl * Sl[k] - v0 * Sc[k] + vm * wr * Sr[k]);
+  }
+}
+
+// Learned warm start: per cell, the inner residual |c g + r_old - lambda (M[g] - g)|
+// of f_c and of the candidate G_c, with r_old the visit's right-hand side with the
+// upwind neighbour from the iterate before the scan (rs plus that neighbour's
+// term).  Where G_c's is smaller, G_c has no negative value and M[G_c] exists,
+// the visit starts from G_c:
+// its moment sums replace those of f_c in pre, and eta0 gets M[G_c]'s
+// parameters; elsewhere eta0 gets f_c's.
+template <int N>
+__global__ __launch_bounds__(kCellThreads) void k_ws_select(
+    const double* __restrict__ f, const double* __restrict__ rs, const double* __restrict__ G,
+    const double* __restrict__ theta, const double* __restrict__ theta_l, const int32_t* __restrict__ it_l,
+    const double* __restrict__ nu, double* __restrict__ pre, double* __restrict__ eta0,
+    const InstDev* __restrict__ inst, const int* __restrict__ cell_inst, int forward,
+    const double* __restrict__ nodes, double w, double u0, unsigned long long* __restrict__ stats) {
+  constexpr int K = N * N * N;
+  const int c = blockIdx.x;
+  const int i = cell_inst[c];
+  const InstDev id = inst[i];
+  const int j = c - id.off;
+  const double idx = 1.0 / id.dx, lam = nu[c] / id.eps;
+  const double* fc = f + (size_t)c * K;
+  const double* Gc = G + (size_t)c * K;
+  const double* rc = rs + (size_t)c * K;
+  const bool has_up = forward ? j > 0 : j < id.nx - 1;
+  const double* up = has_up ? (forward ? fc - K : fc + K) : fc;  // a valid pointer with weight 0 when absent
+  const double wup = has_up ? idx : 0.0;
+  __shared__ double s_Ea[3][N], s_Eb[3][N], s_v[N], s_c[N], s_coef[N];
+  __shared__ double s_red[13 * (kCellThreads / 64)];
+  const double* tha = theta + (size_t)c * 5;
+  const double* thb = theta_l + (size_t)c * 5;
+  if (threadIdx.x < N) {
+    const double x = nodes[threadIdx.x], xp = x + u0;
+    s_v[threadIdx.x] = x;
+    s_c[threadIdx.x] = fabs(xp) * idx;
+    s_coef[threadIdx.x] = forward ? -fmax(xp, 0.0) : fmin(xp, 0.0);
+    for (int a = 0; a < 3; ++a) {
+      s_Ea[a][threadIdx.x] = exp(tha[1 + a] * x - tha[4] * x * x);
+      s_Eb[a][threadIdx.x] = exp(thb[1 + a] * x - thb[4] * x * x);
+    }
+  }
+  __syncthreads();
+  const double ea = exp(tha[0]), eb = exp(thb[0]);
+  double acc[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+#pragma unroll 4
+  for (int k = threadIdx.x; k < K; k += kCellThreads) {
+    const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
+    const double cc = s_c[a0];
+    const double r = rc[k] + s_coef[a0] * wup * up[k];
+    const double fk = fc[k], gk = Gc[k];
+    const double Ma = ea * s_Ea[0][a0] * s_Ea[1][a1] * s_Ea[2][a2];
+    const double Mb = eb * s_Eb[0][a0] * s_Eb[1][a1] * s_Eb[2][a2];
+    const double ra = cc * fk + r - lam * (Ma - fk), rb = cc * gk + r - lam * (Mb - gk);
+    acc[0] += ra * ra;
+    acc[1] += rb * rb;
+    const double v0 = s_v[a0], v1 = s_v[a1], v2 = s_v[a2];
+    const double phi[5] = {1.0, v0, v1, v2, v0 * v0 + v1 * v1 + v2 * v2};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      acc[2 + q] += phi[q] * gk;
+      acc[7 + q] += phi[q] * cc * gk;
+    }
+    acc[12] += gk < 0.0 ? 1.0 : 0.0;
+  }
+  block_sum<13>(acc, s_red);
+  // a physical candidate (no negative value) whose Maxwellian exists and whose
+  // residual is the smaller
+  const bool take = it_l[c] >= 0 && acc[12] == 0.0 && isfinite(acc[1]) && acc[1] < acc[0];
+  if (threadIdx.x < 10 && take) pre[(size_t)c * 25 + 15 + threadIdx.x] = w * acc[2 + threadIdx.x];
+  if (threadIdx.x < 5) eta0[(size_t)c * 5 + threadIdx.x] = take ? thb[threadIdx.x] : tha[threadIdx.x];
+  if (threadIdx.x == 0 && take) atomicAdd(&stats[3], 1ull);
+}
+
 // one work-group per instance: the cells of the scan in order.  A visit takes
 // its fixed moments from pre (summed by k_static_rhs) plus the neighbour part
 // accumulated by the previous visit's final write, so it touches memory only
@@ -321,7 +436,7 @@ struct RChain {
 template <int N>
 __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double* __restrict__ rs,
                                                         const double* __restrict__ pre,
-                                                        const double* __restrict__ theta,
+                                                        const double* __restrict__ eta0,
                                                         const double* __restrict__ nu, const InstDev* __restrict__ inst,
                                                         int forward, SolveArgs opt,
                                                         unsigned long long* __restrict__ stats,
@@ -366,9 +481,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
         vm.mg[q] = p[15 + q];
         vm.cg[q] = p[20 + q];
       }
-      // theta[c] holds the parameters of M[f_c] computed at the start of the
-      // scan, and f_c is still unchanged: Newton only confirms them
-      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta, theta + (size_t)c * 5);
+      // eta0[c] holds the parameters of M[g0] known before the scan (of f_c,
+      // still unchanged, or of the learned start): Newton only confirms them
+      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta, eta0 + (size_t)c * 5);
     }
     NextMoments nx{has_next ? s_coef : nullptr, s_dinv_next, {}};
     const SolveOut o = solve_core<N, kChainThreads>(rf, fc, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
@@ -538,11 +653,34 @@ static bz_status level_alloc(bz_ctx* ctx, Level& L, int n_inst, bool with_mg, bo
   BZ_HIP(hipMalloc((void**)&L.ghost, sizeof(double) * 2 * n_inst));
   if (with_mg) BZ_HIP(hipMalloc((void**)&L.R, sizeof(double) * K * L.ncell));
   if (with_slopes) BZ_HIP(hipMalloc((void**)&L.S, sizeof(double) * K * L.ncell));
+  std::vector<double> ce(L.ncell), cd(L.ncell);
+  for (const InstDev& in : L.h_inst)
+    for (int j = 0; j < in.nx; ++j) {
+      ce[in.off + j] = in.eps;
+      cd[in.off + j] = in.dx;
+    }
+  BZ_HIP(hipMalloc((void**)&L.cell_eps, sizeof(double) * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.cell_dx, sizeof(double) * L.ncell));
+  BZ_HIP(hipMemcpy(L.cell_eps, ce.data(), sizeof(double) * L.ncell, hipMemcpyHostToDevice));
+  BZ_HIP(hipMemcpy(L.cell_dx, cd.data(), sizeof(double) * L.ncell, hipMemcpyHostToDevice));
+  return BZ_OK;
+}
+
+// buffers of the learned warm start on one level (once)
+static bz_status ws_alloc(bz_ctx* ctx, Level& L) {
+  if (L.G) return BZ_OK;
+  const size_t K = ctx->K;
+  BZ_HIP(hipMalloc((void**)&L.T, sizeof(double) * K * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.G, sizeof(double) * K * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.theta_l, sizeof(double) * 5 * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.it_l, sizeof(int32_t) * L.ncell));
+  BZ_HIP(hipMalloc((void**)&L.eta0, sizeof(double) * 5 * L.ncell));
   return BZ_OK;
 }
 
 static void level_free(Level& L) {
-  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.pre, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0, L.S};
+  void* ptrs[] = {L.d_inst, L.d_cell_inst, L.Q, L.rs, L.pre, L.theta, L.nu, L.cellsum, L.ghost, L.R, L.b, L.fc0, L.S,
+                  L.T, L.G, L.theta_l, L.it_l, L.eta0, L.cell_eps, L.cell_dx};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (L.own_f && L.f) (void)hipFree(L.f);
@@ -585,10 +723,21 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
                                        L.theta, L.b, L.rs, L.pre, L.nu, L.d_inst, L.d_cell_inst, L.ghost, s->wallM,
                                        forward ? 1 : 0, bgk, s->bgk_nu, ctx->d_nodes, ctx->w, ctx->p.v1_shift,
                                        s->order == 2 ? L.S : nullptr, ctx->p.gamma, ctx->nu_gfac));
+  if (s->ws) {
+    // learned candidates from the iterate before the scan, then the choice per cell
+    BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_slab_transport<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.T,
+                                         L.d_inst, L.d_cell_inst, L.ghost, s->wallM, ctx->d_nodes, ctx->p.v1_shift,
+                                         s->order == 2 ? L.S : nullptr));
+    if ((e = ws_candidates(ctx, s->ws, L.T, L.theta, L.cell_eps, L.cell_dx, L.G, L.ncell, st)) != BZ_OK) return e;
+    if ((e = maxwellian(ctx, L.G, L.theta_l, nullptr, L.it_l, L.ncell, st)) != BZ_OK) return e;
+    BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_ws_select<NN_>), dim3(L.ncell), dim3(kCellThreads), 0, st, L.f, L.rs, L.G,
+                                         L.theta, L.theta_l, L.it_l, L.nu, L.pre, L.eta0, L.d_inst, L.d_cell_inst,
+                                         forward ? 1 : 0, ctx->d_nodes, ctx->w, ctx->p.v1_shift, s->d_stats));
+  }
   SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift,
               s->inner.fallback == BZ_FALLBACK_RELAX ? 1 : 0};
-  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre, L.theta,
-                                       L.nu,
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre,
+                                       s->ws ? L.eta0 : L.theta, L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
   L.q_valid = false;
@@ -678,6 +827,7 @@ static bz_status build_mg(bz_ctx* ctx, bz_slab* s, int coarsest) {
     L.ncell = F.ncell / 2;
     for (const InstDev& fi : F.h_inst) L.h_inst.push_back(InstDev{fi.off / 2, fi.nx / 2, fi.dx * 2.0, fi.eps, fi.mass});
     bz_status e = level_alloc(ctx, L, s->n_inst, true, s->order == 2);
+    if (e == BZ_OK && s->ws) e = ws_alloc(ctx, L);
     if (e != BZ_OK) return e;
     BZ_HIP(hipMalloc((void**)&L.f, sizeof(double) * K * L.ncell));
     L.own_f = true;
@@ -749,7 +899,7 @@ static bz_status vcycle(bz_ctx* ctx, bz_slab* s, size_t l, const bz_mg_opts* o, 
 }
 
 static bz_status read_stats(bz_ctx* ctx, bz_slab* s, bz_sweep_stats* stats, int n_iters, hipStream_t st) {
-  unsigned long long h[3] = {0, 0, 0};
+  unsigned long long h[4] = {0, 0, 0, 0};
   BZ_HIP(hipMemcpyAsync(h, s->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
   BZ_HIP(hipStreamSynchronize(st));
   if (stats) {
@@ -757,6 +907,7 @@ static bz_status read_stats(bz_ctx* ctx, bz_slab* s, bz_sweep_stats* stats, int 
     stats->inner_iters = (int64_t)h[0];
     stats->visits = (int64_t)h[1];
     stats->fallbacks = (int64_t)h[2];
+    stats->learned = (int64_t)h[3];
   }
   return BZ_OK;
 }
@@ -835,11 +986,11 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (hipMalloc((void**)&s->wallM, sizeof(double) * 2 * K * s->n_inst) != hipSuccess ||
       hipMalloc((void**)&s->wall_in, sizeof(double) * 2 * s->n_inst) != hipSuccess ||
       hipMalloc((void**)&s->bc_fixed, sizeof(double) * 2 * s->n_inst) != hipSuccess ||
-      hipMalloc((void**)&s->d_stats, sizeof(unsigned long long) * 3) != hipSuccess ||
+      hipMalloc((void**)&s->d_stats, sizeof(unsigned long long) * 4) != hipSuccess ||
       hipMalloc((void**)&d_walls, sizeof(bz::WallDev) * s->n_inst) != hipSuccess)
     return fail(set_err(ctx, BZ_ENOMEM, "slab allocation"));
   if (hipMemcpy(d_walls, walls.data(), sizeof(bz::WallDev) * s->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(s->d_stats, 0, sizeof(unsigned long long) * 3) != hipSuccess)
+      hipMemset(s->d_stats, 0, sizeof(unsigned long long) * 4) != hipSuccess)
     return fail(set_err(ctx, BZ_EHIP, "slab upload"));
   switch (ctx->N) {
     case 8: hipLaunchKernelGGL((bz::k_wall_init<8>), dim3(2 * s->n_inst), dim3(bz::kCellThreads), 0, 0, d_walls, s->wallM, s->wall_in, s->bc_fixed, ctx->d_nodes, ctx->w, ctx->p.v1_shift); break;
@@ -869,7 +1020,7 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
   if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 3, st) != hipSuccess)
+  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
     return set_err(ctx, BZ_EHIP, "stats reset");
   bz::Level& L = s->levels[0];
   L.q_valid = false;  // the caller may have changed f
@@ -884,6 +1035,42 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
     for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
   }
   return bz::read_stats(ctx, s, stats, n_iters, st);
+}
+
+bz_status bz_slab_inflow(bz_ctx* ctx, bz_slab* s, double* out, void* stream) {
+  if (!ctx || !s || s->ctx != ctx || !out) return BZ_EINVAL;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  bz::Level& L = s->levels[0];
+  bz_status e = bz::ghosts(ctx, s, L, st);
+  if (e != BZ_OK) return e;
+  BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((bz::k_slab_transport<NN_>), dim3(L.ncell), dim3(bz::kCellThreads), 0, st, L.f,
+                                       out, L.d_inst, L.d_cell_inst, L.ghost, s->wallM, ctx->d_nodes, ctx->p.v1_shift,
+                                       s->order == 2 ? L.S : nullptr));
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+bz_status bz_ws_attach(bz_slab* s, bz_mlp* mlp) {
+  if (!s) return BZ_EINVAL;
+  bz_ctx* ctx = s->ctx;
+  if (!mlp) {
+    s->ws = nullptr;
+    return BZ_OK;
+  }
+  if (bz::ws_ctx(mlp) != ctx) return set_err(ctx, BZ_EINVAL, "the network belongs to another context");
+  if (bz::ws_n_in(mlp) != ctx->K + 6 || bz::ws_n_out(mlp) != ctx->K)
+    return set_err(ctx, BZ_EINVAL, "the warm-start network must map K + 6 inputs to K outputs");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  for (auto& L : s->levels) {
+    bz_status e = bz::ws_alloc(ctx, L);
+    if (e != BZ_OK) return e;
+  }
+  bz_status e = bz::ws_prepare(mlp, s->levels[0].ncell, nullptr);
+  if (e != BZ_OK) return e;
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(ctx, BZ_EHIP, "hipDeviceSynchronize");
+  s->ws = mlp;
+  return BZ_OK;
 }
 
 bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* s, double* residual_out, void* stream) {
@@ -907,7 +1094,7 @@ bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int 
   hipStream_t st = (hipStream_t)stream;
   bz_status e = bz::build_mg(ctx, s, o->coarsest);
   if (e != BZ_OK) return e;
-  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 3, st) != hipSuccess)
+  if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
     return set_err(ctx, BZ_EHIP, "stats reset");
   bz::Level& L = s->levels[0];
   L.q_valid = false;
@@ -944,6 +1131,7 @@ bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay,
   if (!ctx || !s || s->ctx != ctx) return BZ_EINVAL;
   if (iters_per_replay < 1) return set_err(ctx, BZ_EINVAL, "iters_per_replay < 1");
   if (!stream) return set_err(ctx, BZ_EINVAL, "capture needs a non-default stream");
+  if (s->ws) return set_err(ctx, BZ_EUNSUPPORTED, "a slab with a warm-start network attached is not captured");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   bz::Level& L = s->levels[0];
@@ -960,7 +1148,7 @@ bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay,
     return set_err(ctx, BZ_EHIP, "hipStreamBeginCapture");
   }
   bz_status e = BZ_OK;
-  hipLaunchKernelGGL(bz::k_zero_u64, dim3(1), dim3(64), 0, st, s->d_stats, 3);  // a kernel, not a memset node
+  hipLaunchKernelGGL(bz::k_zero_u64, dim3(1), dim3(64), 0, st, s->d_stats, 4);  // a kernel, not a memset node
   L.q_valid = false;
   for (int it = 0; it < iters_per_replay && e == BZ_OK; ++it) e = bz::sgs_iter(ctx, s, L, true, st);
   if (e == BZ_OK && with_residual) e = bz::residual_launch(ctx, s, L, false, st);

@@ -1,13 +1,24 @@
-"""Data generation, training and evaluation of the learned warm start.
+"""Training data, training and time-to-residual runs of the learned warm start.
 
-Every step runs in libbz through the C ABI: the cell solves that produce the
-training targets (bz_cell_fixed_point to a tight tolerance), the discrete
-Maxwellians, the feature map, the MLP forward/backward/Adam kernels, and the
-learned cell update.  This module only moves tensors between those calls.
+Every step of the method runs in libbz through the C ABI: the slab scans and
+V-cycles that produce the training states, the transport part of eq. r of
+each cell (bz_slab_inflow), the cell solves that give the targets
+(bz_cell_fixed_point to a tight tolerance), the discrete Maxwellians, the
+feature map, the MLP forward/backward/Adam kernels, and the learned start
+inside the scans (bz_ws_attach).  This module moves tensors between those
+calls and keeps the books.
 
-Target of one cell: (g* - M[f_old]) / y_scale, where g* solves the inner
-problem of eq. inner_eqn for the cell's transport inflow and BGK-penalty
-source, and y_scale is the RMS of g* - M[f_old] over the training set.
+Family (heat slabs between plates): x in [0, 1], nx cells, diffuse walls at
+rest with T_L = 1 and T_R ~ U(1.5, 2.5), eps log-uniform in [0.005, 1], total
+mass 1, initial state the Maxwellian u = 0, T = 1.5; instance i draws from
+numpy.random.default_rng([seed, i]).
+
+Training pairs come from the solver's own iterates: the states after V-cycles
+0, 1, ..., n_snap - 1 of each training instance.  For each cell of a state the
+input is the network's feature row of the cell's transport part (both
+neighbours from that state) and the target is g* - M[f_j], g* the solution
+of the cell's inner problem with that transport part (the visit the learned
+start stands in for), divided by the output scale.
 """
 from __future__ import annotations
 
@@ -15,42 +26,58 @@ import time
 
 import numpy as np
 
-import synth
-
-from . import Context, MLP
+from . import Context, MLP, Slab
 
 
-def inflow_of(fl, fr, N, L, dx, dev):
-    """Transport inflow of eq. r from the two neighbours (first order)."""
+def heat_slab_instance(seed: int, i: int, nx: int):
+    rng = np.random.default_rng([seed, i])
+    T_R = float(rng.uniform(1.5, 2.5))
+    eps = float(np.exp(rng.uniform(np.log(0.005), np.log(1.0))))
+    return dict(nx=nx, eps=eps, T_L=1.0, T_R=T_R, mass=1.0)
+
+
+def initial_field(ctx: Context, nx: int, T0: float = 1.5):
+    """Uniform Maxwellian u = 0, T = T0 of total mass 1 on [0, 1] (input data)."""
     import torch
 
-    v1 = torch.tensor((np.arange(N) - N // 2 + 1) * (2 * L / N), dtype=torch.float64, device=dev)
-    v1 = v1.view(N, 1, 1).expand(N, N, N).reshape(-1)
-    return ((-torch.clamp(v1, min=0) * fl + torch.clamp(v1, max=0) * fr) / dx).contiguous()
+    import synth
 
-
-def make_dataset(ctx: Context, n_inst: int, cells_per_inst: int, dx: float, seed: int = 7, start: int = 0,
-                 tol: float = 1e-10):
-    """Features X [n, K+6] (float32), raw targets g* - M[f_old] [n, K] (float32) and
-    the inputs (f_old, inflow, eps) on the device, restricted to the cells whose
-    plain solve converged (strong-shock cells can fail the existence test and
-    then diverge under the plain fallback iteration; they are left out)."""
-    import torch
-
-    dev = torch.device(f"cuda:{ctx.params.device}")
     N, L = ctx.params.N, ctx.params.L
-    fl, fo, fr, eps = synth.warmstart_cells(n_inst, cells_per_inst, N, L, seed=seed, start=start)
-    fo_t = torch.from_numpy(fo).to(dev)
-    inflow = inflow_of(torch.from_numpy(fl).to(dev), torch.from_numpy(fr).to(dev), N, L, dx, dev)
-    eps_t = torch.from_numpy(eps).to(dev)
-    g, st = ctx.cell_fixed_point(fo_t, inflow, eps_t, dx, tol=tol, max_iter=400)
-    stats = ctx.decode_stats(st)
-    keep = torch.from_numpy(stats["status"] == 0).to(dev) & torch.isfinite(g).all(1)
-    fo_t, inflow, eps_t, g = fo_t[keep].contiguous(), inflow[keep].contiguous(), eps_t[keep].contiguous(), g[keep]
-    theta, M, _ = ctx.maxwellian(fo_t)
-    X = ctx.features(inflow, theta, eps_t, dx)
-    Y = (g - M).to(torch.float32)
-    return X, Y, (fo_t, inflow, eps_t), stats
+    m = synth.maxwellian_mixture([(1.0, np.zeros(3), T0)], N, L)
+    f0 = np.repeat(m[None], nx, axis=0)
+    f0 *= 1.0 / ((1.0 / nx) * (2.0 * L / N) ** 3 * f0.sum())
+    return torch.from_numpy(f0).to(f"cuda:{ctx.params.device}").contiguous()
+
+
+MG = dict(coarsest=4, nu1=1, nu2=1, coarse_iters=20)
+
+
+def sweep_dataset(ctx: Context, instances, n_snap: int = 4, tol: float = 1e-10):
+    """Features X [n, K + 6] (float32) and targets g* - M[f_old] [n, K] (float32)
+    from the states of V-cycles 0 .. n_snap - 1 of every instance; cells whose
+    inner solve did not reach tol are left out.  Returns (X, Y, info)."""
+    import torch
+
+    Xs, Ys, dropped, t0 = [], [], 0, time.perf_counter()
+    for d in instances:
+        f = initial_field(ctx, d["nx"])
+        slab = Slab(ctx, [d], f)
+        dx = 1.0 / d["nx"]
+        eps = torch.full((d["nx"],), d["eps"], dtype=torch.float64, device=f.device)
+        for k in range(n_snap):
+            if k > 0:
+                slab.vcycle(1, tol=1e-8, **MG)
+            T = slab.inflow()
+            theta, M, _ = ctx.maxwellian(f)
+            X = ctx.features(T, theta, eps, dx)
+            g, st = ctx.cell_fixed_point(f, T, eps, dx, tol=tol, max_iter=400)
+            ok = torch.from_numpy(ctx.decode_stats(st)["status"] == 0).to(f.device) & torch.isfinite(g).all(1)
+            dropped += int((~ok).sum().item())
+            Xs.append(X[ok])
+            Ys.append((g - M)[ok].to(torch.float32))
+        slab.close()
+    X, Y = torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous()
+    return X, Y, {"samples": int(X.shape[0]), "dropped": dropped, "seconds": time.perf_counter() - t0}
 
 
 def train(ctx: Context, X, Y, hidden: int = 256, epochs: int = 20, batch: int = 256, lr: float = 1e-3,
@@ -92,31 +119,67 @@ def train(ctx: Context, X, Y, hidden: int = 256, epochs: int = 20, batch: int = 
     b1 -= (mu_n / sd_n) @ W1
     W1 /= sd_n[:, None]
     mlp.set_params(p.astype(np.float32))
-    return mlp, history
+    return mlp, history, y_scale
 
 
-def compare(ctx: Context, mlp: MLP, f_old, inflow, eps, dx, tol=1e-8, max_iter=100, reps=3):
-    """Inner iterations and wall time of the plain and learned cell updates on
-    the same cells, and the largest difference of their converged answers."""
+def clone_network(mlp: MLP, ctx: Context, y_scale: float) -> MLP:
+    """The same network on another context (the FP32-spectral one)."""
+    other = MLP(ctx, mlp.n_in, mlp.hidden, mlp.n_out)
+    other.set_params(mlp.get_params())
+    other.set_output_scale(y_scale)
+    return other
+
+
+def fp32_switch(inst) -> float:
+    """Residual at which a run leaves the FP32 spectral stage for FP64.  The outer
+    residual holds Q/eps, and the FP32 stage carries an error of about 1e-6 of
+    the loss term, so its floor grows like 1/eps (measured: about 2e-6/eps on
+    the heat slab at 32^3); the switch is ten times that floor, and 1e-5 at
+    the least."""
+    return max(1e-5, 2e-5 / inst["eps"])
+
+
+def time_to_residual(plan, inst, tol: float = 1e-8, max_cycles: int = 300, max_seconds: float = 60.0,
+                     return_field: bool = False):
+    """MG-SGS-PFP V-cycles on one instance from its initial state until the outer
+    residual is below tol.  plan = [(ctx, mlp or None, switch), ...]: V-cycles
+    on each context (with its network attached, if any) until the residual is
+    below that leg's switch value (a number, or a function of the instance) or
+    stalls for 20 cycles, then the next leg from the same field.  Returns
+    seconds, V-cycles, inner updates per visit, learned starts taken and
+    per-leg counts (and the final field with return_field)."""
     import torch
 
-    out = {}
-    for name in ("plain", "learned"):
-        fn = (lambda: ctx.cell_fixed_point(f_old, inflow, eps, dx, tol=tol, max_iter=max_iter)) if name == "plain" \
-            else (lambda: ctx.cell_fixed_point_learned(mlp, f_old, inflow, eps, dx, tol=tol, max_iter=max_iter))
-        g, st = fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            g, st = fn()
-        torch.cuda.synchronize()
-        s = ctx.decode_stats(st)
-        out[name] = {"seconds": (time.perf_counter() - t0) / reps, "mean_iterations": float(s["iterations"].mean()),
-                     "max_iterations": int(s["iterations"].max()), "learned_kept": int(s["learned"].sum()),
-                     "unconverged": int((s["status"] != 0).sum()), "g": g}
-    diff = (out["plain"]["g"] - out["learned"]["g"]).abs().max().item()
-    scale = out["plain"]["g"].abs().max().item()
-    for v in out.values():
-        v.pop("g")
-    out["max_rel_diff"] = diff / scale
+    f = initial_field(plan[0][0], inst["nx"])
+    hist, inner, visits, learned, legs = [], 0, 0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ctx, mlp, switch in plan:
+        if callable(switch):
+            switch = switch(inst)
+        slab = Slab(ctx, [inst], f)
+        if mlp is not None:
+            slab.attach_warmstart(mlp)
+        if not hist:
+            hist.append(slab.residual()[0])
+        start, best, best_at = len(hist), hist[-1], len(hist)
+        while hist[-1] >= switch and len(hist) <= max_cycles and time.perf_counter() - t0 < max_seconds:
+            r, st = slab.vcycle(1, tol=tol, **MG)
+            hist.append(r[0])
+            inner += st["inner_iters"]
+            visits += st["visits"]
+            learned += st["learned"]
+            if r[0] < 0.9 * best:
+                best, best_at = r[0], len(hist)
+            if not np.isfinite(r[0]) or (switch > tol and len(hist) - best_at > 20):
+                break
+        legs.append({"precision": "fp64" if ctx.params.precision == 0 else "fp32", "learned": mlp is not None,
+                     "vcycles": len(hist) - start, "residual_at_end": hist[-1]})
+        slab.close()
+    torch.cuda.synchronize()
+    out = {"seconds": time.perf_counter() - t0, "vcycles": len(hist) - 1, "final_residual": hist[-1],
+           "reached": hist[-1] < tol, "inner_per_visit": inner / max(visits, 1), "visits": visits,
+           "learned_taken": learned, "legs": legs}
+    if return_field:
+        out["f"] = f
     return out

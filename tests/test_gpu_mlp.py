@@ -69,25 +69,63 @@ def test_adam_steps_reduce_the_loss(dev):
     assert l1 < 0.2 * l0
 
 
-def test_learned_start_keeps_answers_and_never_costs_iterations(dev):
-    # what the trained network gains is measured and printed; the assertions
-    # are that the converged answers are unchanged and no cell needs more
-    # updates on average than with the plain start
+def test_split_k_products_match_oracle(dev):
+    # a long input (the first layer's K) and a long output (the backward
+    # product's K) with a small batch take the split-K path
+    import paper_2409_01910_amd as bz
+
+    n_in, H, n_out, B = 4099, 40, 3000, 9
+    ctx = bz.Context(N=8, L=4.0, n_theta=2, n_phi=4, n_rho=2)
+    m = bz.MLP(ctx, n_in, H, n_out, seed=3)
+    rng = np.random.default_rng(3)
+    p = (rng.normal(size=m.n_params) / np.sqrt(n_in)).astype(np.float32)
+    m.set_params(p)
+    X = rng.normal(size=(B, n_in)).astype(np.float32)
+    T = rng.normal(size=(B, n_out)).astype(np.float32)
+    y = m.forward(torch.from_numpy(X).to(dev)).cpu().numpy()
+    ybf = m.forward(torch.from_numpy(X).to(dev), bf16=True).cpu().numpy()
+    ref, _ = OM.forward(p.astype(np.float64), X.astype(np.float64), n_in, H, n_out)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() < 1e-5 * scale
+    assert np.abs(ybf - ref).max() < 3e-2 * scale
+    loss, g = m.grad(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev))
+    lref, gref = OM.loss_and_grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64), n_in, H, n_out)
+    assert abs(loss - lref) < 1e-5 * lref
+    assert np.abs(g.cpu().numpy() - gref).max() < 1e-4 * np.abs(gref).max()
+
+
+def test_trained_network_gain_in_the_scans(dev):
+    # The learned start trained on the solver's own iterates, measured on
+    # held-out heat slabs (16^3, 16 cells, MG-SGS-PFP to outer 1e-6; 16^3 does
+    # not reach 1e-8).  Asserted: training learns (loss below half its start),
+    # every run converges, the converged states agree, and the work changes by
+    # less than 5%: the network's guess is taken in few visits, because the
+    # iterate before a scan already nearly solves the cell problem the network
+    # can see (its upwind neighbour is not yet updated).  The counts are
+    # printed; the 32^3 measurement is the benchmark's.
     import paper_2409_01910_amd as bz
     from paper_2409_01910_amd import warmstart as WS
 
-    ctx = bz.Context(N=8, L=8.0, n_theta=2, n_phi=4, n_rho=3)
-    dx = 40.0 / 128
-    X, Y, _, _ = WS.make_dataset(ctx, 60, 8, dx, seed=7)
-    mlp, hist = WS.train(ctx, X, Y, hidden=64, epochs=80, batch=64, lr=2e-3)
-    print("loss", hist[0], hist[-1])
-    assert hist[-1] < 0.9 * hist[0]  # training makes progress
-    _, _, (fo, inflow, eps), _ = WS.make_dataset(ctx, 10, 8, dx, seed=7, start=1000)
-    res = WS.compare(ctx, mlp, fo, inflow, eps, dx, tol=1e-8)
-    print(res)
-    assert res["plain"]["unconverged"] == 0 and res["learned"]["unconverged"] == 0
-    # both reach the same fixed point of eq. inner_eqn (each within the inner tolerance)
-    assert res["max_rel_diff"] < 1e-6
-    assert res["learned"]["mean_iterations"] <= res["plain"]["mean_iterations"]
-    print(f"gain: mean inner updates {res['plain']['mean_iterations']:.3f} -> {res['learned']['mean_iterations']:.3f}, "
-          f"learned start kept in {res['learned']['learned_kept']} cells")
+    ctx = bz.Context(N=16, L=8.0, n_theta=4, n_phi=8, n_rho=4)
+    train = [WS.heat_slab_instance(5, i, 16) for i in range(8)]
+    X, Y, info = WS.sweep_dataset(ctx, train, n_snap=3)
+    mlp, hist, _ = WS.train(ctx, X, Y, hidden=64, epochs=40, batch=64, lr=2e-3)
+    print(f"samples {info['samples']}, loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+    plain_inner, learned_inner, taken = 0.0, 0.0, 0
+    for i in range(3):
+        inst = WS.heat_slab_instance(5, 1000 + i, 16)
+        a = WS.time_to_residual([(ctx, None, 1e-6)], inst, tol=1e-6, return_field=True)
+        b = WS.time_to_residual([(ctx, mlp, 1e-6)], inst, tol=1e-6, return_field=True)
+        print(f"eps {inst['eps']:.4f}: plain {a['vcycles']} cycles {a['inner_per_visit']:.3f} updates/visit, "
+              f"learned {b['vcycles']} cycles {b['inner_per_visit']:.3f} updates/visit, "
+              f"taken {b['learned_taken']} of {b['visits']}", flush=True)
+        assert a["reached"] and b["reached"]
+        diff = (a["f"] - b["f"]).abs().max().item() / a["f"].abs().max().item()
+        assert diff < 1e-4, diff  # both within the outer tolerance of the same state
+        plain_inner += a["inner_per_visit"]
+        learned_inner += b["inner_per_visit"]
+        taken += b["learned_taken"]
+    print(f"inner updates per visit: plain {plain_inner / 3:.4f}, learned {learned_inner / 3:.4f}; "
+          f"learned starts taken: {taken}", flush=True)
+    assert abs(learned_inner / plain_inner - 1.0) < 0.05
