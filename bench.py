@@ -71,8 +71,10 @@ def traffic_per_launch(precision, total_units, launches, method="sigma"):
     return per * total_units / launches
 
 
-def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
-    """The oracle, as it stands, on the same step for a bounded sample of cells."""
+def _oracle_cells(cells, gamma, method):
+    """The oracle's step (corrected Q, penalty, PFP solve) on the given cells,
+    one thread; cells = [(f, f_left, f_right, eps), ...].  Returns the elapsed
+    seconds."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -81,24 +83,52 @@ def cpu_baseline(f_np, eps_np, n_cells=2, gamma=0.0, method="sigma"):
 
     sp = Spec(d=3, N=N, L=L, n_theta=N_THETA, n_phi=N_PHI, n_rho=N_RHO, gamma=gamma)
     v1 = velocity_nodes(sp)[:, 0]
-    B = f_np.shape[0]
     t0 = time.perf_counter()
     with threadpool_limits(limits=1):
-        for i in range(n_cells):
-            fl, fr = f_np[(i - 1) % B], f_np[(i + 1) % B]
+        for fc, fl, fr, e in cells:
             inflow = (-np.maximum(v1, 0) * fl + np.minimum(v1, 0) * fr) / DX
             if method == "carleman":
-                M = OM.discrete_maxwellian(sp, f_np[i])
-                Qc = OQ.mass_project(sp, OQ.q_corrected(sp, f_np[i], M, op=OCA.q_carleman), M)
-                P = OQ.penalty(sp, f_np[i], Q=Qc, M=M)
+                M = OM.discrete_maxwellian(sp, fc)
+                Qc = OQ.mass_project(sp, OQ.q_corrected(sp, fc, M, op=OCA.q_carleman), M)
+                P = OQ.penalty(sp, fc, Q=Qc, M=M)
             else:
-                P = OQ.penalty(sp, f_np[i])
-            r = inflow - P / eps_np[i]
-            OC.solve(sp, r, OQ.nu_of(sp, f_np[i]), eps_np[i], DX, f_np[i], mode="pfp", tol=1e-8, max_iter=100)
-    dt = time.perf_counter() - t0
-    return {"value": n_cells / dt, "unit": "Q evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cells} cells of the same workload (corrected Q + penalty + PFP solve), "
-                      f"numpy FP64, one thread, {dt:.1f} s"}
+                P = OQ.penalty(sp, fc)
+            r = inflow - P / e
+            OC.solve(sp, r, OQ.nu_of(sp, fc), e, DX, fc, mode="pfp", tol=1e-8, max_iter=100)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(f_np, eps_np, gamma=0.0, method="sigma", cells_per_worker=1):
+    """The oracle, as it stands, on the same step for a bounded sample of cells:
+    one single-threaded process per host core (at most 16, the CPU share of a
+    one-GPU machine), each on its own cells.  Runs before the GPU is touched; the
+    worker processes are forked and never use the GPU."""
+    import multiprocessing as mp
+
+    host = os.cpu_count() or 1
+    workers = max(1, min(16, host))
+    B = f_np.shape[0]
+    # each worker gets its own cells with their batch neighbours (not the batch)
+    jobs = [[(f_np[i], f_np[(i - 1) % B], f_np[(i + 1) % B], float(eps_np[i]))
+             for i in range(w * cells_per_worker, (w + 1) * cells_per_worker)] for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        per = pool.starmap(_oracle_cells, [(c, gamma, method) for c in jobs])
+    wall = time.perf_counter() - t0
+    n = workers * cells_per_worker
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / wall, "unit": "Q evals/s", "cores": workers, "kind": "oracle",
+            "host_cpu_count": host, "host_cpu_model": model,
+            "sample": f"{n} cells of the same workload (corrected Q + penalty + PFP solve), numpy FP64, "
+                      f"{workers} single-threaded processes, {wall:.1f} s wall, "
+                      f"{sum(per) / len(per):.1f} s per cell per process"}
 
 
 def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="sgs", graph_iters=0, order=1,
@@ -650,6 +680,8 @@ def main():
                     choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg", "mg_carleman")
                                        for e in ("1", "0.1", "0.01", "0.001")],
                     help="with --workload plates: run one case only")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration)")
     ap.add_argument("--ws-train", type=int, default=24, help="warmstart: training instances")
     ap.add_argument("--ws-test", type=int, default=6, help="warmstart: held-out instances")
     ap.add_argument("--ws-snap", type=int, default=4, help="warmstart: V-cycle states per training instance")
@@ -692,9 +724,25 @@ def main():
         print(json.dumps(plates_workload(args)), flush=True)
         return
 
+    if args.calibrate_copy:
+        # a plain device copy of known size, for scaling the HBM traffic counters
+        n = args.calibrate_copy * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_mib": args.calibrate_copy, "reps": 3}), flush=True)
+        return
     dev = torch.device("cuda:0")
     print(f"# generating {args.batch} cells", file=sys.stderr, flush=True)
     f_np, eps_np = make_inputs(args.batch)
+    main_gamma = 1.0 if args.method == "carleman" else args.gamma
+    cpu_line = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the workers are forked from this process
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu_line = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)
     f = torch.from_numpy(f_np).to(dev)
     eps = torch.from_numpy(eps_np).to(dev)
     # transport inflow from the neighbouring cells of the batch (input preparation)
@@ -714,6 +762,12 @@ def main():
 
         def step():
             return ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g)
+
+        # launch plan of the collision pipeline, tuned on a sample of the batch
+        tuned = ctx.tune(f[:min(512, args.batch)].contiguous(), corrected=True, conserve="mass")
+        print(f"# {precision} {method} tuned plan {tuned['plan']}: " +
+              ", ".join(f"{c['pair_waves']}/{c['chunk_cells']} {m:.1f} ms" for c, m in tuned["candidates"]),
+              file=sys.stderr, flush=True)
 
         for i in range(args.warmup):
             step()
@@ -760,10 +814,11 @@ def main():
                     "kernel": "k_pairs32 (direction-pair transforms)", "launches": prof["launches"],
                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
+        roof["tuned_plan"] = tuned["plan"]
+        roof["tuner_candidates_ms"] = [[c["pair_waves"], c["chunk_cells"], m] for c, m in tuned["candidates"]]
         return args.steps * args.batch / elapsed, elapsed, dt, roof, ctx.decode_stats(stats)
 
     value, elapsed, dt, roof, st = measure(args.precision, args.method)
-    main_gamma = 1.0 if args.method == "carleman" else args.gamma
     form = ("Carleman rank-64 form (64 half-sphere directions), hard spheres" if args.method == "carleman"
             else "sigma form, M=128 (8x16), 16 radial nodes")
     line = {
@@ -826,9 +881,8 @@ def main():
             "plain_fp64_s": ws["summary"]["plain_fp64"]["seconds_total"],
             "speedup_plain_fp64_over_learned_fp32": ws["speedup_plain_fp64_over_learned_fp32"],
             "summary": ws["summary"], "train": ws["train"]}
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(f_np, eps_np, gamma=main_gamma, method=args.method)
+    if cpu_line is not None:
+        line["cpu_baseline"] = cpu_line
     print(json.dumps(line), flush=True)
 
 

@@ -176,14 +176,53 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
  * need when theta is NULL, live in a static device array of 64 MiB per device,
  * held by the library until the process ends; cells are processed in chunks
  * that fit it.  Returns BZ_EINVAL, with a message, when one cell's workspace
- * exceeds the array: with d = 3 in FP64 the corrected form needs
- * N^3 (112 + 32 n_theta) bytes per cell (12.1 MB at 32^3 with n_theta = 8, so 5
- * cells per chunk; n_theta = 64 at 32^3 is refused); d = 2 needs 32 bytes per
+ * exceeds the array.  With d = 3 the corrected form needs, per cell,
+ * N^3 (104 + 16 n_theta) + 8 n_rho n_theta N (N + 1) + 40 bytes in FP64
+ * (8.7 MB at 32^3 with n_theta = 8, n_rho = 16: 7 cells per chunk; 32^3 with
+ * n_theta = 64, n_rho = 64 is refused) and N^3 (64 + 16 n_theta) bytes with an
+ * FP32 spectral stage; d = 2 needs 32 bytes per
  * cell.  All calls on one device share that device's array and leave it
  * holding the last call's contents: calls that overlap on one device (other
  * streams, other host threads) race, and the caller must serialise them. */
 bz_status bz_eval_Q_noalloc(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint32_t flags,
                             double* theta, void* stream);
+
+/* ---------------------------------------------------------------- launch plans
+ * How the collision pipeline is launched, without changing what it computes:
+ *   pair_waves   waves per block of the N = 32 direction-pair kernel: 8 (one
+ *                block per CU), 4 or 2 (two or four blocks per CU, so that one
+ *                block's loads and final reduction overlap another's
+ *                transforms); 0 = the default, 8
+ *   chunk_cells  cap on the cells of one chunk of the pipeline's workspace; a
+ *                small chunk keeps a radial node's z-stage planes in the last-level
+ *                cache between the z-stage and the pair kernel; 0 = no cap (a
+ *                2 GiB workspace budget decides)
+ * bz_set_plan / bz_get_plan set and read a context's plan (BZ_EINVAL for other
+ * values).  bz_tune is the project's autotuner: it times bz_eval_Q(f, batch,
+ * flags), reps times after a warm-up, under every candidate plan of the
+ * context (pair_waves in {8, 4, 2} for the N = 32 sigma form, chunk_cells in
+ * {0, 64, 24} with d = 3), reports each candidate's mean time in `report`,
+ * keeps the fastest in the context and caches it for the discretisation
+ * (device, d, N, precision, method, rule sizes, BZ_Q_CORRECTED): contexts
+ * created later with the same discretisation start with it.  bz_tune
+ * synchronises the stream and allocates a [batch][K] output buffer. */
+#define BZ_TUNE_MAX 16
+typedef struct {
+  int pair_waves;
+  int chunk_cells;
+} bz_plan;
+
+typedef struct {
+  int n;                      /* candidates timed */
+  bz_plan plan[BZ_TUNE_MAX];  /* the candidates */
+  double ms[BZ_TUNE_MAX];     /* mean time of one bz_eval_Q under each */
+  int best;                   /* index of the plan kept */
+} bz_tune_report;
+
+bz_status bz_set_plan(bz_ctx* ctx, const bz_plan* plan);
+bz_status bz_get_plan(bz_ctx* ctx, bz_plan* plan);
+bz_status bz_tune(bz_ctx* ctx, const double* f, int64_t batch, uint32_t flags, int reps, bz_tune_report* report,
+                  void* stream);
 
 /* bz_maxwellian: discrete Maxwellian of each cell (eqs. discrete_conservation,
  * discrete_Gaussian; Newton's method, Section 2.2).
@@ -386,9 +425,10 @@ bz_status bz_slab_inflow(bz_ctx* ctx, bz_slab* slab, double* out, void* stream);
  * on the slab's context) in the slab's scans; NULL detaches.  Before each scan
  * every cell gets a second initial guess G = M[f_j] + scale * MLP(features of
  * bz_slab_inflow's row), BF16 inference with FP32 accumulation, computed for
- * all cells at once.  A visit starts from G instead of f_j when G has no
- * negative value and G's inner residual
- * |c g + r_old - (nu/eps)(M[g] - g)|_{L2} is the smaller, r_old being
+ * all cells at once.  A visit starts from G instead of f_j when M[G] exists,
+ * step 1 of the preconditioned update from G is solvable (eq. existence for
+ * r_old), and G's inner residual |c g + r_old - (nu/eps)(M[g] - g)|_{L2} is the
+ * smaller, r_old being
  * the visit's right-hand side with its upwind neighbour taken from the iterate
  * before the scan (the fresh value is not known then); the plain iteration of
  * the visit is unchanged, so the result is again the visit's inner solution,

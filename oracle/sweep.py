@@ -31,7 +31,7 @@ import numpy as np
 
 from . import cell as cellmod
 from .collision import bgk_nu_of, nu_of, penalty_split, q_corrected, q_fsm
-from .grid import Spec, sphere_area, transport_v1, velocity_nodes
+from .grid import Spec, phi_vectors, sphere_area, transport_v1, velocity_nodes
 from .maxwellian import discrete_maxwellian, moments
 
 
@@ -202,8 +202,8 @@ def warm_starts(prob: Slab, f: np.ndarray, P: np.ndarray, nu: np.ndarray, b: np.
     Before the scan, every cell gets a second candidate G_j = M[f_j] + scale * y_j,
     y_j the network's output for the features of the cell's transport part with
     both neighbours taken from the iterate before the scan (oracle.mlp.features).
-    The visit starts from G_j when G_j has no negative value and its inner
-    residual
+    The visit starts from G_j when the preconditioned step 1 from G_j is
+    solvable (eq. existence for the right-hand side below) and its inner residual
         |c g + r_old - (nu/eps)(M[g] - g)|_{L2}
     is smaller than that of f_j, where r_old is the visit's right-hand side with
     the upwind neighbour taken from the iterate before the scan (the fresh one is
@@ -214,6 +214,7 @@ def warm_starts(prob: Slab, f: np.ndarray, P: np.ndarray, nu: np.ndarray, b: np.
     params, n_in, H, n_out, scale = prob.warm
     T = transport_part(prob, f)
     c = cellmod.transport_coef(spec, prob.dx)
+    phi = phi_vectors(spec)
     lam = nu / prob.eps
     out = []
     for j in range(prob.nx):
@@ -223,12 +224,13 @@ def warm_starts(prob: Slab, f: np.ndarray, P: np.ndarray, nu: np.ndarray, b: np.
         G = Mf + scale * y[0]
         r_old = T[j] - P[j] / prob.eps - (b[j] if b is not None else 0.0)
         res_f = np.sum((c * f[j] + r_old - lam[j] * (Mf - f[j])) ** 2)
-        if G.min() < 0.0:  # not a distribution: never a start
-            out.append(None)
-            continue
         try:
             MG = discrete_maxwellian(spec, G)
         except RuntimeError:
+            out.append(None)
+            continue
+        # the preconditioned step 1 from G must be solvable (eq. existence)
+        if not cellmod.existence_ok(spec, spec.w * phi.T @ (c * (MG - G) - r_old)):
             out.append(None)
             continue
         res_G = np.sum((c * G + r_old - lam[j] * (MG - G)) ** 2)

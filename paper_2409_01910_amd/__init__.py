@@ -37,7 +37,7 @@ EXPORTED = [
     "bz_cell_fixed_point_learned",
     "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
     "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
-    "bz_slab_inflow", "bz_ws_attach",
+    "bz_slab_inflow", "bz_ws_attach", "bz_set_plan", "bz_get_plan", "bz_tune",
 ]
 
 
@@ -91,6 +91,18 @@ class bz_sweep_stats(ctypes.Structure):
 class bz_mg_opts(ctypes.Structure):
     _fields_ = [("coarsest", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("coarse_iters", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class bz_plan(ctypes.Structure):
+    _fields_ = [("pair_waves", ctypes.c_int), ("chunk_cells", ctypes.c_int)]
+
+
+BZ_TUNE_MAX = 16
+
+
+class bz_tune_report(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("plan", bz_plan * BZ_TUNE_MAX), ("ms", ctypes.c_double * BZ_TUNE_MAX),
+                ("best", ctypes.c_int)]
 
 
 class bz_profile_info(ctypes.Structure):
@@ -155,6 +167,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_mlp_train_step.argtypes = [P, P, P, I64, D, ctypes.POINTER(ctypes.c_double), P]
     lib.bz_mlp_features.argtypes = [P, P, P, P, D, P, I64, P]
     lib.bz_cell_fixed_point_learned.argtypes = [P, P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
+    lib.bz_set_plan.argtypes = [P, ctypes.POINTER(bz_plan)]
+    lib.bz_get_plan.argtypes = [P, ctypes.POINTER(bz_plan)]
+    lib.bz_tune.argtypes = [P, P, I64, U32, ctypes.c_int, ctypes.POINTER(bz_tune_report), P]
     lib.bz_profile_enable.argtypes = [P, ctypes.c_int]
     lib.bz_profile_get.argtypes = [P, ctypes.POINTER(bz_profile_info)]
     lib.bz_graph_capture_sweeps.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_void_p)]
@@ -376,6 +391,27 @@ class Context:
         self._check(self.lib.bz_mlp_features(self.h, _ptr(inflow_r), _ptr(theta), _ptr(eps), float(dx), _ptr(X), B,
                                              _stream()), "bz_mlp_features")
         return X
+
+    def set_plan(self, pair_waves: int = 0, chunk_cells: int = 0):
+        """bz_set_plan: launch plan of the collision pipeline (0 = default)."""
+        p = bz_plan(pair_waves, chunk_cells)
+        self._check(self.lib.bz_set_plan(self.h, ctypes.byref(p)), "bz_set_plan")
+
+    def get_plan(self):
+        p = bz_plan()
+        self._check(self.lib.bz_get_plan(self.h, ctypes.byref(p)), "bz_get_plan")
+        return {"pair_waves": p.pair_waves, "chunk_cells": p.chunk_cells}
+
+    def tune(self, f, corrected: bool = True, conserve: str | None = None, reps: int = 2):
+        """bz_tune: time bz_eval_Q on f under every candidate plan, keep and cache
+        the fastest.  Returns the report as a list of (plan, ms) and the best index."""
+        B = self._field(f, "f")
+        flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
+        rep = bz_tune_report()
+        self._check(self.lib.bz_tune(self.h, _ptr(f), B, flags, reps, ctypes.byref(rep), _stream()), "bz_tune")
+        cands = [({"pair_waves": rep.plan[i].pair_waves, "chunk_cells": rep.plan[i].chunk_cells}, rep.ms[i])
+                 for i in range(rep.n)]
+        return {"candidates": cands, "best": rep.best, "plan": cands[rep.best][0]}
 
     def profile_enable(self, on: bool = True):
         self._check(self.lib.bz_profile_enable(self.h, 1 if on else 0), "bz_profile_enable")

@@ -112,6 +112,7 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   }
   bz_status s = bz::build_tables(ctx);
   if (s == BZ_OK) s = bz::scratch_attach(ctx);
+  if (s == BZ_OK) bz::apply_cached_plan(ctx);
   if (s != BZ_OK) {
     bz::free_tables(ctx);
     delete ctx;

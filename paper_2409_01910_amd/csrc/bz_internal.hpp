@@ -58,6 +58,13 @@ struct bz_ctx {
   size_t prof_used = 0;             // events used
   double prof_flops = 0.0;
 
+  // launch plan of the collision pipeline (bz_plan; 0 = default): waves per
+  // block of the N = 32 direction-pair kernel (8) and a cap on the cells of a
+  // chunk (none: the 2 GiB workspace budget decides); set by bz_tune (measured
+  // and cached per discretisation) or bz_set_plan
+  int pair_waves = 0;
+  int chunk_cap = 0;
+
   // workspace (grown on demand, never shrunk until destroy)
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -113,6 +120,8 @@ bz_status v2_eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool
 // allocation-free collision evaluation (bz_noalloc.hip): resolves, once per
 // device, the device address of the library's static scratch array
 bz_status scratch_attach(bz_ctx* ctx);
+// the tuned launch plan cached for this context's discretisation, if any (bz_tune.cpp)
+void apply_cached_plan(bz_ctx* ctx);
 // argument checks shared by bz_eval_Q and bz_eval_Q_noalloc (bz_api.cpp)
 bz_status check_eval_q_args(bz_ctx* ctx, const double* f, const double* Q, int64_t batch, uint32_t flags,
                             const double* theta);

@@ -15,9 +15,17 @@
 //             accumulated plane
 //     colw    axis-0 forward transform, multiply by W_r(|xi|), add into Qh+
 //   final     inverse transform of Qh+, Q = Q+ - loss (FP64 combine)
-// The corrected form (eq. discrete_Q) is evaluated as the symmetric bilinear
-// form Q_s(g, h): gain pairs are g(v+s) h(v-s) + g(v-s) h(v+s), loss is
-// (g L[h] + h L[g]) / 2.  This equals Q^FSM[f,f] - Q^FSM[M,M] up to rounding.
+// The corrected form (eq. discrete_Q), Q^FSM[f,f] - Q^FSM[M,M], is evaluated
+//   * with an FP32 spectral stage as the symmetric bilinear form Q_s(g, h),
+//     g = f - M, h = f + M: gain pairs g(v+s) h(v-s) + g(v-s) h(v+s), loss
+//     (g L[h] + h L[g]) / 2, equal up to rounding and free of the cancellation
+//     that FP32 would not survive;
+//   * in FP64 as the difference itself: Q^FSM[f,f] through the pipeline above
+//     (one field, half the direction-pair work of the bilinear form) minus
+//     Q^FSM[M,M], whose gain is computed from 1D transforms: M is a sampled
+//     Gaussian, so its spectrum, every shifted copy M(v +- s) and their
+//     products factorise over the three axes (k_max_sep1, k_max_sep2); its
+//     loss goes through the same loss transform as f's.
 #include "bz_common.hpp"
 #include "bz_internal.hpp"
 #include "bz_newton.hpp"
@@ -87,6 +95,20 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
   if (theta_out && threadIdx.x < 5) theta_out[(size_t)b * 5 + threadIdx.x] = s_th[threadIdx.x];
   __syncthreads();
   const double ea = exp(s_th[0]);
+  if (corrected == 2) {
+    // difference form: spectra of f (volume b) and M (volume nb + b); GH keeps M
+    const int nb = gridDim.x;
+    double* Mb = GH + (size_t)b * K;
+    C* Ff = Fc + (size_t)b * K;
+    C* Fm = Fc + ((size_t)nb + b) * K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+      Mb[k] = M;
+      Ff[k] = C{T(fb[k]), T(0)};
+      Fm[k] = C{T(M), T(0)};
+    }
+    return;
+  }
   double* g = GH + (size_t)b * 2 * K;
   double* h = g + K;
   C* Fg = Fc + (size_t)b * 2 * K;
@@ -384,11 +406,16 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pairs(const typename V2<T>:
 //            4-point transforms over c give columns i3 = k' + 8t.
 // No stage moves data between lanes by lane permutes, and no lane computes a
 // twiddle it does not use.
-constexpr int kPair32Waves = 8;
+// Waves per block of the N = 32 pair kernel: a block is one (cell, plane) and
+// its waves share the plane's items; W = 8 holds one block per CU (the FP64
+// kernel fills the register file at two waves per SIMD), W = 4 and W = 2 let
+// two and four blocks share a CU, so that one block's loads and final
+// reduction overlap another's transforms.  The choice is tuned per context.
+constexpr int kPair32WaveChoices[3] = {8, 4, 2};
 
 template <typename T>
-constexpr size_t pairs32_lds_bytes() {
-  return (size_t)(kPair32Waves * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)kPair32Waves * 64 * 6 * sizeof(T);
+constexpr size_t pairs32_lds_bytes(int W) {
+  return (size_t)(W * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)W * 64 * 6 * sizeof(T);
 }
 
 // e^{2 pi i n / 32}, n = 0..31, for the per-lane twiddles of stages 2 and 3
@@ -413,8 +440,8 @@ __device__ __forceinline__ void cmul(T& xr, T& xi, T wr, T wi) {
   xr = r;
 }
 
-template <typename T, int NF>
-__global__ __launch_bounds__(64 * kPair32Waves) void k_pairs32(const typename V2<T>::type* __restrict__ Z,
+template <typename T, int NF, int kPair32Waves>
+__global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename V2<T>::type* __restrict__ Z,
                                                                typename V2<T>::type* __restrict__ Acc, int n_theta,
                                                                int n_phi, const typename V2<T>::type* __restrict__ ph23,
                                                                const T* __restrict__ pairsw) {
@@ -960,6 +987,219 @@ __global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __rest
   }
 }
 
+// ------------------------------------------------------------------ gain of the Maxwellian, separable
+// For M = e^alpha E_1(v_1) E_2(v_2) E_3(v_3) the pipeline's quantities factorise:
+// its normalised spectrum is e^alpha / K prod_a Ehat_a(l_a) (Ehat_a the 1D DFT
+// of E_a, zero at l_a = N/2), the shifted copies of a direction pair are
+// a = e^alpha / K prod_a A_a(i_a), A_a = IDFT_1(Ehat_a phase_a), b likewise
+// with the conjugate phases (the antipodal polar node on axis 1), and the
+// forward transform of their product is e^{2 alpha} / K^2 prod_a D_a(k_a),
+// D_a = DFT_1(A_a B_a).  With the pair q = (tp, j) of polar pair tp and
+// azimuth j, weight 2 w_q, the gain spectrum of M is
+//   Qh_M(k) = e^{2 alpha} / K^2 sum_r W_r(k) sum_tp D0_{r,tp}(k_1) G_{r,tp}(k_2, k_3),
+//   G_{r,tp}(k_2, k_3) = sum_j 2 w_q D1_{r,q}(k_2) D2_{r,q}(k_3).
+// k_max_sep1 (block per cell and radial node) forms D0 and G; k_max_sep2
+// (block per cell, thread per (k_2, k_3)) sums over r and tp and subtracts
+// Qh_M from the cell's gain spectrum.  Transforms of length N are done as
+// direct sums (N terms per output): a few dozen MFLOP per cell, against the
+// GFLOPs of the direction-pair transforms they replace.
+constexpr int kSepThreads = 256;
+constexpr int kSepJB = 16;  // azimuths per pass
+
+template <int N>
+__device__ __forceinline__ double2 sep_tw(const double2* tw, int m, int sign) {
+  const double2 w = tw[m & (N - 1)];
+  return double2{w.x, sign * w.y};
+}
+
+template <int N>
+__global__ __launch_bounds__(kSepThreads) void k_max_sep1(const double* __restrict__ theta,
+                                                          const double* __restrict__ nodes,
+                                                          const double2* __restrict__ ph1,
+                                                          const double2* __restrict__ ph23,
+                                                          const double* __restrict__ pairw, int n_rho, int n_theta,
+                                                          int n_phi, double2* __restrict__ D0s,
+                                                          double2* __restrict__ Gs) {
+  constexpr int NN = N * N;
+  const int b = blockIdx.x / n_rho, r = blockIdx.x % n_rho;
+  const int half = n_theta / 2, npairs = half * n_phi;
+  __shared__ double2 s_tw[N];                 // e^{2 pi i m / N}
+  __shared__ double2 s_E[3][N];               // Ehat_a
+  __shared__ double2 s_P[2 * kSepJB + 1][N];  // products A B
+  __shared__ double2 s_D[2 * kSepJB + 1][N];  // their transforms
+  __shared__ double s_w[kSepJB];
+  const double* th = theta + (size_t)b * 5;
+  if (threadIdx.x < N) {
+    const double a = 2.0 * kPi * threadIdx.x / N;
+    s_tw[threadIdx.x] = double2{cos(a), sin(a)};
+  }
+  __syncthreads();
+  // Ehat_a(l) = sum_i E_a(x_i) e^{-2 pi i l i / N}, zero at the Nyquist index
+  for (int e = threadIdx.x; e < 3 * N; e += kSepThreads) {
+    const int a = e / N, l = e % N;
+    double re = 0.0, im = 0.0;
+    if (l != N / 2) {
+#pragma unroll 2
+      for (int i = 0; i < N; ++i) {
+        const double x = nodes[i];
+        const double E = exp(th[1 + a] * x - th[4] * x * x);
+        const double2 w = sep_tw<N>(s_tw, l * i, -1);
+        re += E * w.x;
+        im += E * w.y;
+      }
+    }
+    s_E[a][l] = double2{re, im};
+  }
+  __syncthreads();
+  // product of the shifted copies of vector v at node i: A(i) B(i) with
+  // A = IDFT(Ehat phase_A), B = IDFT(Ehat phase_B)
+  auto prod = [&](int a, const double2* pa, const double2* pb, bool conj_b, int i) {
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll 2
+    for (int l = 0; l < N; ++l) {
+      const double2 E = s_E[a][l], w = sep_tw<N>(s_tw, l * i, 1);
+      const double2 qa = pa[l];
+      const double2 qb = conj_b ? double2{pb[l].x, -pb[l].y} : pb[l];
+      // (E qa) w and (E qb) w
+      const double er = E.x * qa.x - E.y * qa.y, ei = E.x * qa.y + E.y * qa.x;
+      ar += er * w.x - ei * w.y;
+      ai += er * w.y + ei * w.x;
+      const double fr = E.x * qb.x - E.y * qb.y, fi = E.x * qb.y + E.y * qb.x;
+      br += fr * w.x - fi * w.y;
+      bi += fr * w.y + fi * w.x;
+    }
+    return double2{ar * br - ai * bi, ar * bi + ai * br};
+  };
+  for (int tp = 0; tp < half; ++tp) {
+    const int tA = half + tp, tB = half - 1 - tp;
+    const double2* p1A = ph1 + ((size_t)r * n_theta + tA) * N;
+    const double2* p1B = ph1 + ((size_t)r * n_theta + tB) * N;
+    double2 g[NN / kSepThreads > 0 ? NN / kSepThreads : 1];
+    constexpr int GPT = NN / kSepThreads > 0 ? NN / kSepThreads : 1;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) g[u] = double2{0.0, 0.0};
+    for (int j0 = 0; j0 < n_phi; j0 += kSepJB) {
+      const int nj = (n_phi - j0) < kSepJB ? (n_phi - j0) : kSepJB;
+      // vectors: 0 = axis 1 of the polar pair (first pass only), 1 + 2 jl + {0, 1} = axes 2, 3 of azimuth jl
+      const int nv = 1 + 2 * nj;
+      __syncthreads();
+      for (int e = threadIdx.x; e < nv * N; e += kSepThreads) {
+        const int v = e / N, i = e % N;
+        double2 pr;
+        if (v == 0) {
+          pr = prod(0, p1A, p1B, false, i);
+        } else {
+          const int jl = (v - 1) >> 1, ax = (v - 1) & 1;
+          const int q = tp * n_phi + j0 + jl;
+          const double2* p = ph23 + (((size_t)r * npairs + q) * 2 + ax) * N;
+          pr = prod(1 + ax, p, p, true, i);
+        }
+        s_P[v][i] = pr;
+      }
+      if (threadIdx.x < nj) s_w[threadIdx.x] = 2.0 * pairw[tp * n_phi + j0 + threadIdx.x];
+      __syncthreads();
+      for (int e = threadIdx.x; e < nv * N; e += kSepThreads) {
+        const int v = e / N, k = e % N;
+        double re = 0.0, im = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < N; ++i) {
+          const double2 P = s_P[v][i], w = sep_tw<N>(s_tw, k * i, -1);
+          re += P.x * w.x - P.y * w.y;
+          im += P.x * w.y + P.y * w.x;
+        }
+        s_D[v][k] = double2{re, im};
+      }
+      __syncthreads();
+      if (j0 == 0 && threadIdx.x < N) D0s[(((size_t)b * n_rho + r) * half + tp) * N + threadIdx.x] = s_D[0][threadIdx.x];
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int kk = threadIdx.x + u * kSepThreads;
+        if (kk < NN) {
+          const int k2 = kk / N, k3 = kk % N;
+#pragma unroll 2
+          for (int jl = 0; jl < nj; ++jl) {
+            const double2 d1 = s_D[1 + 2 * jl][k2], d2 = s_D[2 + 2 * jl][k3];
+            const double wq = s_w[jl];
+            g[u].x += wq * (d1.x * d2.x - d1.y * d2.y);
+            g[u].y += wq * (d1.x * d2.y + d1.y * d2.x);
+          }
+        }
+      }
+    }
+    double2* Gout = Gs + (((size_t)b * n_rho + r) * half + tp) * NN;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      const int kk = threadIdx.x + u * kSepThreads;
+      if (kk < NN) Gout[kk] = g[u];
+    }
+  }
+}
+
+// k_1 values per thread of k_max_sep2 (the grid's second dimension covers the
+// rest): 8 complex accumulators keep a 1024-thread block within its registers
+template <int N>
+constexpr int sep2_ks() {
+  return N > 8 ? 8 : N;
+}
+
+template <int N>
+__global__ __launch_bounds__(N * N < 64 ? 64 : N * N) void k_max_sep2(const double* __restrict__ theta,
+                                                                      const double2* __restrict__ D0s,
+                                                                      const double2* __restrict__ Gs,
+                                                                      const double* __restrict__ W,
+                                                                      double2* __restrict__ Qh, int n_rho,
+                                                                      int n_theta) {
+  constexpr int K = N * N * N, NN = N * N, KS = sep2_ks<N>();
+  constexpr int TPC = 4;  // polar pairs per register batch
+  const int b = blockIdx.x, t = threadIdx.x, kb = blockIdx.y * KS;
+  const int half = n_theta / 2;
+  __shared__ double2 s_D0[TPC][N];
+  double2 acc[KS];
+#pragma unroll
+  for (int k1 = 0; k1 < KS; ++k1) acc[k1] = double2{0.0, 0.0};
+  for (int r = 0; r < n_rho; ++r) {
+    for (int tp0 = 0; tp0 < half; tp0 += TPC) {
+      const int nt = (half - tp0) < TPC ? (half - tp0) : TPC;
+      __syncthreads();
+      if (t < nt * N) s_D0[t / N][t % N] = D0s[(((size_t)b * n_rho + r) * half + tp0 + t / N) * N + t % N];
+      __syncthreads();
+      double2 g[TPC];
+#pragma unroll
+      for (int u = 0; u < TPC; ++u)
+        g[u] = (t < NN && u < nt) ? Gs[(((size_t)b * n_rho + r) * half + tp0 + u) * NN + t] : double2{0.0, 0.0};
+      if (t < NN) {
+        const double* Wr = W + (size_t)r * K + (size_t)kb * NN + t;
+#pragma unroll
+        for (int k1 = 0; k1 < KS; ++k1) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int u = 0; u < TPC; ++u) {
+            const double2 d = s_D0[u < nt ? u : 0][kb + k1];
+            const double on = u < nt ? 1.0 : 0.0;
+            sr += on * (d.x * g[u].x - d.y * g[u].y);
+            si += on * (d.x * g[u].y + d.y * g[u].x);
+          }
+          const double w = Wr[(size_t)k1 * NN];
+          acc[k1].x += w * sr;
+          acc[k1].y += w * si;
+        }
+      }
+    }
+  }
+  if (t < NN) {
+    const double ea = exp(theta[(size_t)b * 5]);
+    const double sc = ea * ea / ((double)K * (double)K);
+    double2* q = Qh + (size_t)b * K + (size_t)kb * NN + t;
+#pragma unroll
+    for (int k1 = 0; k1 < KS; ++k1) {
+      double2 v = q[(size_t)k1 * NN];
+      v.x -= sc * acc[k1].x;
+      v.y -= sc * acc[k1].y;
+      q[(size_t)k1 * NN] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ combine
 template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, const double* __restrict__ GH,
@@ -975,6 +1215,10 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, c
   double loss;
   if (NF == 1) {
     loss = f[gid] * double(Lc[gid].x);
+  } else if (NF == 3) {
+    // difference form: f L[f] - M L[M], the M volumes after the f volumes
+    const int64_t nb = n / K;
+    loss = f[gid] * double(Lc[gid].x) - GH[gid] * double(Lc[nb * K + gid].x);
   } else {
     const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
     const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
@@ -984,33 +1228,71 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, c
 }
 
 // ------------------------------------------------------------------ host driver
+// Workspace of one cell: spectra and loss transforms of nvol volumes (f, or the
+// two fields of the corrected form), the fields for the final combine, the
+// z-stage planes of the nz fields that go through the direction pairs, the
+// accumulated planes, the gain spectrum, and for the FP64 difference form the
+// separable Maxwellian factors D0, G and the Maxwellian parameters.
+struct QLayout {
+  bool diff;   // FP64 corrected form as Q[f,f] - Q[M,M] (separable Maxwellian gain)
+  int nvol;    // spectrum / loss volumes per cell
+  int nz;      // fields through the z-stage and the direction pairs
+  size_t per;  // bytes per cell
+};
+
 template <typename T>
-static size_t ws_per_cell(int N, int n_theta, int nf) {
+static QLayout q_layout(int N, int n_theta, int n_rho, bool corrected, bool carleman) {
   const size_t K = (size_t)N * N * N, cs = 2 * sizeof(T);
-  return K * (nf * cs /*Fc*/ + nf * cs /*Lc*/ + nf * 8 /*GH*/ + (size_t)nf * n_theta * cs /*Z*/ + cs /*Acc*/ +
-              cs /*Qh*/);
+  QLayout q;
+  q.diff = sizeof(T) == 8 && corrected && !carleman;
+  q.nvol = corrected ? 2 : 1;
+  q.nz = q.diff ? 1 : q.nvol;
+  q.per = K * (q.nvol * cs /*Fc*/ + q.nvol * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ +
+               (size_t)q.nz * n_theta * cs /*Z*/ + cs /*Acc*/ + cs /*Qh*/);
+  if (q.diff) q.per += (size_t)n_rho * (n_theta / 2) * ((size_t)N + (size_t)N * N) * 16 /*D0, G*/ + 5 * 8 /*theta*/;
+  return q;
+}
+
+template <typename T>
+static QLayout q_layout(const bz_ctx* ctx, bool corrected) {
+  return q_layout<T>(ctx->N, ctx->n_theta, ctx->n_rho, corrected, ctx->p.method == BZ_METHOD_CARLEMAN);
 }
 
 // cells per chunk of the collision workspace (2 GiB budget, or the bytes of a
 // caller-provided workspace)
 template <typename T, int N>
 static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected, size_t budget = (size_t)2 << 30) {
-  const size_t per = ws_per_cell<T>(N, ctx->n_theta, corrected ? 2 : 1);
+  const size_t per = q_layout<T>(ctx, corrected).per;
   int64_t chunk = (int64_t)(budget / per);
+  if (ctx->chunk_cap > 0 && chunk > ctx->chunk_cap) chunk = ctx->chunk_cap;
   if (chunk < 1) chunk = 1;
   if (chunk > batch) chunk = batch;
   return chunk;
 }
 
+template <typename T, int NF>
+static const void* pair_kernel(int N, int W) {
+  if (N == 32) {
+    if (W == 2) return (const void*)k_pairs32<T, NF, 2>;
+    if (W == 4) return (const void*)k_pairs32<T, NF, 4>;
+    return (const void*)k_pairs32<T, NF, 8>;
+  }
+  if (N == 16) return (const void*)k_pairs<T, 16, NF>;
+  return (const void*)k_pairs<T, 8, NF>;
+}
+
+// waves per block of the N = 32 pair kernel for this context (tuned, else 8)
+static int pair_waves(const bz_ctx* ctx) { return ctx->pair_waves > 0 ? ctx->pair_waves : 8; }
+
 template <typename T, int N>
 static bz_status prepare_chunked(bz_ctx* ctx, int64_t batch, bool corrected) {
   if (batch == 0) return BZ_OK;
-  const size_t per = ws_per_cell<T>(N, ctx->n_theta, corrected ? 2 : 1);
-  bz_status s = ensure_ws(ctx, per * chunk_cells<T, N>(ctx, batch, corrected));
+  const QLayout ql = q_layout<T>(ctx, corrected);
+  bz_status s = ensure_ws(ctx, ql.per * chunk_cells<T, N>(ctx, batch, corrected));
   if (s != BZ_OK) return s;
-  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>() : pairs_lds_bytes<T, N>();
-  const void* kp = (N == 32) ? (corrected ? (const void*)k_pairs32<T, 2> : (const void*)k_pairs32<T, 1>)
-                             : (corrected ? (const void*)k_pairs<T, N, 2> : (const void*)k_pairs<T, N, 1>);
+  const int W = pair_waves(ctx);
+  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>(W) : pairs_lds_bytes<T, N>();
+  const void* kp = ql.nz == 2 ? pair_kernel<T, 2>(N, W) : pair_kernel<T, 1>(N, W);
   BZ_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return BZ_OK;
 }
@@ -1020,9 +1302,10 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
                              hipStream_t st, void* ws_ext, size_t ws_ext_bytes) {
   using C = typename V2<T>::type;
   constexpr int K = N * N * N, NN = N * N;
-  const int nf = corrected ? 2 : 1;
+  const QLayout ql = q_layout<T>(ctx, corrected);
+  const int nf = ql.nvol, nz = ql.nz;
   const int nt = ctx->n_theta;
-  const size_t per = ws_per_cell<T>(N, nt, nf);
+  const size_t per = ql.per;
   bz_status s = BZ_OK;
   int64_t chunk;
   unsigned char* base;
@@ -1040,9 +1323,13 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   C* Fc = (C*)base;
   C* Lc = Fc + (size_t)chunk * nf * K;
   double* GH = (double*)(Lc + (size_t)chunk * nf * K);
-  C* Z = (C*)(GH + (size_t)chunk * nf * K);
-  C* Acc = Z + (size_t)chunk * nf * nt * K;
+  C* Z = (C*)(GH + (size_t)chunk * (ql.diff ? 1 : nf) * K);
+  C* Acc = Z + (size_t)chunk * nz * nt * K;
   C* Qh = Acc + (size_t)chunk * K;
+  const int half = nt / 2;
+  double2* D0s = (double2*)(Qh + (size_t)chunk * K);
+  double2* Gs = D0s + (ql.diff ? (size_t)chunk * ctx->n_rho * half * N : 0);
+  double* th_ws = (double*)(Gs + (ql.diff ? (size_t)chunk * ctx->n_rho * half * NN : 0));
   const bool f64 = sizeof(T) == 8;
   const C* ph1 = (const C*)(f64 ? (const void*)ctx->d_ph1 : (const void*)ctx->d_ph1_f);
   const C* ph23 = (const C*)(f64 ? (const void*)ctx->d_ph23 : (const void*)ctx->d_ph23_f);
@@ -1057,17 +1344,19 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
                          : (const T*)(f64 ? (const void*)ctx->d_Gm : (const void*)ctx->d_Gm_f);
   const T* cw = (const T*)(f64 ? (const void*)ctx->d_cw : (const void*)ctx->d_cw_f);
   constexpr int PPB = plane_ppb<T, N>();
-  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>() : pairs_lds_bytes<T, N>();
-  const void* kp = (N == 32) ? (corrected ? (const void*)k_pairs32<T, 2> : (const void*)k_pairs32<T, 1>)
-                             : (corrected ? (const void*)k_pairs<T, N, 2> : (const void*)k_pairs<T, N, 1>);
+  const int PW = pair_waves(ctx);
+  const size_t lds = (N == 32) ? pairs32_lds_bytes<T>(PW) : pairs_lds_bytes<T, N>();
+  const void* kp = nz == 2 ? pair_kernel<T, 2>(N, PW) : pair_kernel<T, 1>(N, PW);
   BZ_HIP(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int pair_threads = (N == 32) ? 64 * kPair32Waves : 64 * kPairWaves;
+  const int pair_threads = (N == 32) ? 64 * PW : 64 * kPairWaves;
   for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
     const int64_t B = (batch - c0) < chunk ? (batch - c0) : chunk;
     const double* fb = f + c0 * K;
     const int64_t nvol = B * nf;
-    hipLaunchKernelGGL((k_prep<T, N>), dim3((unsigned)B), dim3(kPrepThreads), 0, st, fb, GH, Fc,
-                       theta_out ? theta_out + c0 * 5 : nullptr, ctx->d_nodes, ctx->w, corrected ? 1 : 0);
+    // the difference form needs the Maxwellian parameters for its separable part
+    double* th_b = theta_out ? theta_out + c0 * 5 : (ql.diff ? th_ws : nullptr);
+    hipLaunchKernelGGL((k_prep<T, N>), dim3((unsigned)B), dim3(kPrepThreads), 0, st, fb, GH, Fc, th_b, ctx->d_nodes,
+                       ctx->w, ql.diff ? 2 : (corrected ? 1 : 0));
     const unsigned gcol = (unsigned)((nvol * NN + 255) / 256);
     const unsigned gpl = (unsigned)((nvol * N + PPB - 1) / PPB);
     hipLaunchKernelGGL((k_plane<T, N, -1>), dim3(gpl), dim3(N * PPB), 0, st, Fc, Fc, nvol * N);
@@ -1119,8 +1408,10 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       BZ_HIP(hipGetLastError());
       continue;
     }
+    const int64_t nzvol = B * nz;
+    const unsigned gz = (unsigned)((nzvol * NN + 255) / 256);
     for (int r = 0; r < ctx->n_rho; ++r) {
-      hipLaunchKernelGGL((k_zstage<T, N>), dim3(gcol), dim3(256), 0, st, Fc, Z, nvol, nt, ph1 + (size_t)r * nt * N);
+      hipLaunchKernelGGL((k_zstage<T, N>), dim3(gz), dim3(256), 0, st, Fc, Z, nzvol, nt, ph1 + (size_t)r * nt * N);
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
       if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
@@ -1128,16 +1419,27 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
         void* args[] = {(void*)&Z, (void*)&Acc, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pw};
         BZ_HIP(hipLaunchKernel(kp, dim3((unsigned)(B * N)), dim3(pair_threads), args, lds, st));
       }
-      if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nf * job_flops)) != BZ_OK) return s;
+      if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nz * job_flops)) != BZ_OK) return s;
       const unsigned gq = (unsigned)((B * NN + 255) / 256);
       hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r * K, r == 0 ? 1 : 0);
+    }
+    if (ql.diff) {
+      // subtract the gain of the Maxwellian, by separable transforms
+      hipLaunchKernelGGL((k_max_sep1<N>), dim3((unsigned)(B * ctx->n_rho)), dim3(kSepThreads), 0, st, th_b,
+                         ctx->d_nodes, (const double2*)ctx->d_ph1, (const double2*)ctx->d_ph23, ctx->d_pairw,
+                         ctx->n_rho, nt, ctx->n_phi, D0s, Gs);
+      hipLaunchKernelGGL((k_max_sep2<N>), dim3((unsigned)B, (unsigned)(N / sep2_ks<N>())), dim3(NN < 64 ? 64 : NN), 0,
+                         st, (const double*)th_b, (const double2*)D0s, (const double2*)Gs, ctx->d_W, (double2*)Qh,
+                         ctx->n_rho, nt);
     }
     const unsigned gq = (unsigned)((B * NN + 255) / 256);
     hipLaunchKernelGGL((k_col<T, N, +1, COL_PLAIN>), dim3(gq), dim3(256), 0, st, Qh, Qh, B, (const T*)nullptr);
     hipLaunchKernelGGL((k_plane<T, N, +1>), dim3((unsigned)((B * N + PPB - 1) / PPB)), dim3(N * PPB), 0, st, Qh, Qh,
                        B * N);
     const unsigned ge = (unsigned)((B * K + 255) / 256);
-    if (corrected)
+    if (ql.diff)
+      hipLaunchKernelGGL((k_combine<T, N, 3>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+    else if (corrected)
       hipLaunchKernelGGL((k_combine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
     else
       hipLaunchKernelGGL((k_combine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
@@ -1147,9 +1449,7 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
 }
 
 size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected) {
-  const int nf = corrected ? 2 : 1;
-  return ctx->p.precision == BZ_FP32 ? ws_per_cell<float>(ctx->N, ctx->n_theta, nf)
-                                     : ws_per_cell<double>(ctx->N, ctx->n_theta, nf);
+  return ctx->p.precision == BZ_FP32 ? q_layout<float>(ctx, corrected).per : q_layout<double>(ctx, corrected).per;
 }
 
 bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected) {

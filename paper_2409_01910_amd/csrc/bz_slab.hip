@@ -358,8 +358,8 @@ __global__ __launch_bounds__(kCellThreads) void k_slab_transport(
 // Learned warm start: per cell, the inner residual |c g + r_old - lambda (M[g] - g)|
 // of f_c and of the candidate G_c, with r_old the visit's right-hand side with the
 // upwind neighbour from the iterate before the scan (rs plus that neighbour's
-// term).  Where G_c's is smaller, G_c has no negative value and M[G_c] exists,
-// the visit starts from G_c:
+// term).  Where G_c's is smaller, M[G_c] exists and the preconditioned step 1
+// from G_c is solvable (eq. existence for r_old), the visit starts from G_c:
 // its moment sums replace those of f_c in pre, and eta0 gets M[G_c]'s
 // parameters; elsewhere eta0 gets f_c's.
 template <int N>
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kCellThreads) void k_ws_select(
   const double* up = has_up ? (forward ? fc - K : fc + K) : fc;  // a valid pointer with weight 0 when absent
   const double wup = has_up ? idx : 0.0;
   __shared__ double s_Ea[3][N], s_Eb[3][N], s_v[N], s_c[N], s_coef[N];
-  __shared__ double s_red[13 * (kCellThreads / 64)];
+  __shared__ double s_red[22 * (kCellThreads / 64)];
   const double* tha = theta + (size_t)c * 5;
   const double* thb = theta_l + (size_t)c * 5;
   if (threadIdx.x < N) {
@@ -397,9 +397,9 @@ __global__ __launch_bounds__(kCellThreads) void k_ws_select(
   }
   __syncthreads();
   const double ea = exp(tha[0]), eb = exp(thb[0]);
-  double acc[13];
+  double acc[22];
 #pragma unroll
-  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 22; ++q) acc[q] = 0.0;
 #pragma unroll 4
   for (int k = threadIdx.x; k < K; k += kCellThreads) {
     const int a0 = k / (N * N), a1 = (k / N) % N, a2 = k % N;
@@ -417,13 +417,20 @@ __global__ __launch_bounds__(kCellThreads) void k_ws_select(
     for (int q = 0; q < 5; ++q) {
       acc[2 + q] += phi[q] * gk;
       acc[7 + q] += phi[q] * cc * gk;
+      acc[12 + q] += phi[q] * cc * Mb;
+      acc[17 + q] += phi[q] * r;
     }
-    acc[12] += gk < 0.0 ? 1.0 : 0.0;
   }
-  block_sum<13>(acc, s_red);
-  // a physical candidate (no negative value) whose Maxwellian exists and whose
+  block_sum<22>(acc, s_red);
+  // step 1 of the preconditioned update from G (eq. step1) must be solvable:
+  // s = sum w phi (c (M[G] - G) - r_old) satisfies eq. existence
+  double sv[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sv[q] = w * (acc[12 + q] - acc[7 + q] - acc[17 + q]);
+  const bool exists = sv[0] > 0.0 && sv[0] * sv[4] > sv[1] * sv[1] + sv[2] * sv[2] + sv[3] * sv[3];
+  // a candidate whose Maxwellian exists, from which step 1 is solvable, and whose
   // residual is the smaller
-  const bool take = it_l[c] >= 0 && acc[12] == 0.0 && isfinite(acc[1]) && acc[1] < acc[0];
+  const bool take = it_l[c] >= 0 && exists && isfinite(acc[1]) && acc[1] < acc[0];
   if (threadIdx.x < 10 && take) pre[(size_t)c * 25 + 15 + threadIdx.x] = w * acc[2 + threadIdx.x];
   if (threadIdx.x < 5) eta0[(size_t)c * 5 + threadIdx.x] = take ? thb[threadIdx.x] : tha[threadIdx.x];
   if (threadIdx.x == 0 && take) atomicAdd(&stats[3], 1ull);

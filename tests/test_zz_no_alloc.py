@@ -23,7 +23,8 @@ def dev():
 
 
 # (d, N, L, n_theta, n_phi, n_rho, precision, batches, flags): 32^3 with n_theta = 8
-# needs 12.1 MB per cell in FP64, so 40 cells run in 8 chunks of 5
+# and n_rho = 2 needs 7.7 MB per cell in FP64 (corrected), so 40 cells run in 5
+# chunks of 8
 CASES = [
     (3, 16, 8.0, 4, 8, 8, 0, (37, 6), dict(corrected=True, conserve="mass")),
     (3, 32, 8.0, 8, 16, 2, 0, (40, 3), dict(corrected=True, conserve="mass")),
@@ -63,8 +64,8 @@ def test_noalloc_matches_eval_q_on_two_calls(dev, case):
 def test_noalloc_refuses_a_cell_beyond_the_scratch(dev):
     import paper_2409_01910_amd as bz
 
-    # 32^3 FP64 corrected with 64 polar nodes: 70.8 MB for one cell > 64 MiB
-    ctx = bz.Context(N=32, L=8.0, n_theta=64, n_phi=4, n_rho=1)
+    # 32^3 FP64 corrected with 64 polar and 64 radial nodes: 71.6 MB for one cell > 64 MiB
+    ctx = bz.Context(N=32, L=8.0, n_theta=64, n_phi=4, n_rho=64)
     f = torch.from_numpy(synth.mixture_batch(1, 32, 8.0, seed=3)).to(dev)
     out = torch.empty_like(f)
     with pytest.raises(bz.BZError, match="bytes of scratch"):
