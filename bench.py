@@ -237,6 +237,83 @@ def slab_workload(args, tol=1e-8):
                                             "eps": 0.1}, "runs": out}
 
 
+STUDY_EPS = (1.0, 1e-1, 1e-2, 1e-3, 1e-4)
+STUDY_ROWS = (("SI", 1), ("SGS-FP", 1), ("SGS-PFP", 1), ("MG-SGS-PFP", 1), ("SGS-FP", 2), ("SGS-PFP", 2),
+              ("MG-SGS-PFP", 2))
+
+
+def _bgk_study_run(ctx, row, order, eps, nx, cap_s, tol=1e-5):
+    """One run of the BGK heat-transfer study: x in (-1/2, 1/2), nx cells, walls
+    T = 1 and 2 at rest, mass 1, collision frequency nu = 1 (the model
+    v f_x = (M - f)/eps of Section 4.1), initial Maxwellian u = 0, T = 1.5; outer
+    tolerance 1e-5, inner 1e-8 (Section 4).  Stops at tol or after cap_s seconds
+    (checked between iterations)."""
+    import numpy as np
+    import torch
+
+    import paper_2409_01910_amd as bz
+    import synth
+
+    n, l = ctx.params.N, ctx.params.L
+    m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+    f0 = np.repeat(m[None], nx, axis=0)
+    f0 *= 1.0 / ((1.0 / nx) * (2.0 * l / n) ** 3 * f0.sum())
+    f = torch.from_numpy(f0).cuda().contiguous()
+    mode = {"SI": "si", "SGS-FP": "fp"}.get(row, "pfp")
+    slab = bz.Slab(ctx, [dict(xL=-0.5, xR=0.5, nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="bgk",
+                   bgk_nu=1.0, mode=mode, tol=1e-8, max_iter=10000, order=order)
+    res = slab.residual()[0]
+    its, inner, visits = 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while res >= tol and time.perf_counter() - t0 < cap_s and np.isfinite(res):
+        if row == "MG-SGS-PFP":
+            r, st = (slab.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=0.0) if order == 2
+                     else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=0.0))
+        else:
+            r, st = slab.sweep(1)
+        res = r[0]
+        its += 1
+        inner += st["inner_iters"]
+        visits += st["visits"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    slab.close()
+    return {"seconds": el, "iterations": its, "residual": res, "reached": bool(res < tol),
+            "inner_per_visit": inner / max(visits, 1), "ms_per_iteration": el / max(its, 1) * 1e3}
+
+
+def bgk_study_workload(args):
+    """Time to outer residual 1e-5 of SI, SGS-FP, SGS-PFP and MG-SGS-PFP (first
+    and second order) on the BGK heat-transfer slab for eps = 1 .. 1e-4, the
+    study of tab. time_1D1V, in three velocity dimensions (16^3 nodes on
+    [-6, 6]^3) with 256 cells.  Runs that do not reach 1e-5 within the cap are
+    reported with reached = False; once a method misses the cap at some eps its
+    runs at smaller eps are skipped (skipped = True), every method slowing down
+    as eps falls."""
+    import paper_2409_01910_amd as bz
+
+    ctx = bz.Context(N=args.study_n, L=6.0, n_theta=2, n_phi=4, n_rho=2)
+    table = {}
+    for row, order in STUDY_ROWS:
+        key = f"{row} order {order}"
+        table[key] = {}
+        missed = False
+        for eps in STUDY_EPS:
+            if missed:
+                table[key][f"{eps:g}"] = {"skipped": True, "reached": False}
+                continue
+            out = _bgk_study_run(ctx, row, order, eps, args.study_cells, args.study_cap)
+            missed = not out["reached"]
+            table[key][f"{eps:g}"] = out
+            print(f"# bgk study {key} eps {eps:g}: {out['seconds']:.2f} s, {out['iterations']} iterations, "
+                  f"residual {out['residual']:.2e}, inner/visit {out['inner_per_visit']:.2f}", file=sys.stderr,
+                  flush=True)
+    ctx.close()
+    return {"workload": "bgk-study", "cells": args.study_cells, "N": args.study_n, "L": 6.0, "tol": 1e-5,
+            "inner_tol": 1e-8, "cap_seconds": args.study_cap, "table": table}
+
+
 def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10):
     """BGK heat slab (x in [0, 1], walls T = 1 and 2 at rest, mass 1, n^3
     velocities on [-l, l]^3) driven by V-cycles (tab. mg's parameters for the
@@ -687,13 +764,18 @@ def main():
     ap.add_argument("--ws-snap", type=int, default=4, help="warmstart: V-cycle states per training instance")
     ap.add_argument("--ws-epochs", type=int, default=30, help="warmstart: training epochs")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-start time-to-residual runs")
-    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates"], default="batched-q",
+    ap.add_argument("--study-cells", type=int, default=256, help="bgk-study: cells of the slab")
+    ap.add_argument("--study-n", type=int, default=16, help="bgk-study: velocity nodes per axis")
+    ap.add_argument("--study-cap", type=float, default=20.0, help="bgk-study: seconds per run at most")
+    ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates",
+                                           "bgk-study"], default="batched-q",
                     help="batched-q: the headline; slab: 1D heat slab to outer residual 1e-8; "
                          "warmstart: learned+FP32 vs plain FP64 cell solves to inner residual 1e-8; "
                          "shock: normal shocks with inflow at both ends (single to 1e-8, 16-instance batch bounded); "
                          "order: first/second-order accuracy study on the BGK heat slab; "
                          "cavity: 2D2V lid-driven cavity and the batched 2D collision term; "
-                         "plates: 1D2V heat transfer between parallel plates")
+                         "plates: 1D2V heat transfer between parallel plates; "
+                         "bgk-study: SI / SGS-FP / SGS-PFP / MG-SGS-PFP times on the BGK heat slab")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
@@ -722,6 +804,9 @@ def main():
         return
     if args.workload == "plates":
         print(json.dumps(plates_workload(args)), flush=True)
+        return
+    if args.workload == "bgk-study":
+        print(json.dumps(bgk_study_workload(args)), flush=True)
         return
 
     if args.calibrate_copy:

@@ -239,11 +239,17 @@ bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
  *     existence test of eq. existence; on failure (or when the step-1 Newton
  *     does not converge) the visit continues with the plain iteration.
  * mode BZ_SOLVE_FP: plain fixed point, eq. fix_point.
+ * mode BZ_SOLVE_SI (slab scans with BGK collisions only): source iteration,
+ *     eq. SI.  The Maxwellian and nu of the iterate at the start of an SGS
+ *     iteration are kept through both of its scans, and each visit makes the
+ *     single update g = D^{-1}(nu/eps M^n_j - r); tol, max_iter and
+ *     fixed_iters are ignored.  The cell-solve calls, the cavity and a slab
+ *     with a learned start attached reject it (BZ_EINVAL / BZ_EUNSUPPORTED).
  * The residual |(|v_1|/dx) g + r - (nu/eps)(M[g] - g)|_{L2(R^3)} is evaluated
  * after every update; iteration stops when it is <= tol or after max_iter
  * updates.  fixed_iters > 0 makes exactly that many updates (for one-to-one
  * comparisons of iterates). */
-typedef enum { BZ_SOLVE_PFP = 0, BZ_SOLVE_FP = 1 } bz_solve_mode;
+typedef enum { BZ_SOLVE_PFP = 0, BZ_SOLVE_FP = 1, BZ_SOLVE_SI = 2 } bz_solve_mode;
 
 /* What a PFP update does when eq. existence fails for step 1's right-hand side s:
  * BZ_FALLBACK_FP continues the visit with the plain iteration (Section 3.2);

@@ -238,14 +238,23 @@ def warm_starts(prob: Slab, f: np.ndarray, P: np.ndarray, nu: np.ndarray, b: np.
     return out
 
 
-def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) -> np.ndarray:
+def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None, lagged=None) -> np.ndarray:
     """One SGS scan (the first or second line of eq. SGS): P and nu from the iterate
-    before the scan, slopes from the previous scan, cells visited in order."""
+    before the scan, slopes from the previous scan, cells visited in order.
+
+    With lagged = (M, nu) (source iteration, BGK only) each visit makes the single
+    update g = (|v_1|/dx + nu/eps)^{-1} ((nu/eps) M_j - r) with M and nu taken from
+    the iterate at the start of the iteration, eq. SI: the scan then solves the
+    transport equation of the velocities it sweeps along exactly."""
     spec = prob.spec
     v1 = transport_v1(spec)
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
     dx, eps = prob.dx, prob.eps
-    Q, M, nu = all_collision(prob, f)
+    if lagged is not None:
+        M, nu = lagged
+        Q = nu[:, None] * (M - f)  # BGK: P = 0
+    else:
+        Q, M, nu = all_collision(prob, f)
     P = penalty_split(Q, M, f, nu)
     s = slopes(prob, f)
     warm = warm_starts(prob, f, P, nu, b) if prob.warm is not None else [None] * prob.nx
@@ -262,6 +271,12 @@ def scan(prob: Slab, f: np.ndarray, forward: bool, b: np.ndarray | None = None) 
         r -= P[j] / eps
         if b is not None:
             r -= b[j]
+        if lagged is not None:
+            lam = nu[j] / eps
+            f[j] = (lam * M[j] - r) / (cellmod.transport_coef(spec, dx) + lam)
+            prob.stats["inner"] += 1
+            prob.stats["visits"] += 1
+            continue
         g0 = f[j] if warm[j] is None else warm[j]
         g, st = cellmod.solve(spec, r, nu[j], eps, dx, g0, mode=prob.inner, tol=prob.tol_inner,
                               max_iter=prob.max_inner, fixed_iters=prob.fixed_inner)
@@ -278,8 +293,18 @@ def total_mass(prob: Slab, f: np.ndarray) -> float:
 
 
 def sgs_iteration(prob: Slab, f: np.ndarray, b: np.ndarray | None = None, rescale: bool = True):
-    f = scan(prob, f, True, b)
-    f = scan(prob, f, False, b)
+    """One iteration: a forward and a backward scan (eq. SGS), then the mass rescale.
+    With inner = "si" it is the source iteration of eq. SI (BGK): M[f^n] and nu^n
+    are lagged over both scans, each visit one explicit update."""
+    if prob.inner == "si":
+        if prob.collision != "bgk":
+            raise ValueError("the source iteration is the BGK scheme of eq. SI")
+        _, M, nu = all_collision(prob, f)
+        f = scan(prob, f, True, b, lagged=(M, nu))
+        f = scan(prob, f, False, b, lagged=(M, nu))
+    else:
+        f = scan(prob, f, True, b)
+        f = scan(prob, f, False, b)
     if rescale:
         f = f * (prob.mass / total_mass(prob, f))
     return f

@@ -21,7 +21,7 @@ BZ_Q_CORRECTED = 1
 BZ_Q_MASS = 2
 BZ_Q_CONSERVE = 4
 BZ_BC_WALL, BZ_BC_INFLOW = 0, 1
-BZ_SOLVE_PFP, BZ_SOLVE_FP = 0, 1
+BZ_SOLVE_PFP, BZ_SOLVE_FP, BZ_SOLVE_SI = 0, 1, 2
 BZ_COLL_BINARY, BZ_COLL_BGK, BZ_COLL_BINARY_CONSERVE = 0, 1, 2
 _COLLISIONS = {"binary": BZ_COLL_BINARY, "bgk": BZ_COLL_BGK, "binary_conserve": BZ_COLL_BINARY_CONSERVE}
 _LIMITERS = {"none": 0, "minmod": 1}
@@ -318,8 +318,10 @@ class Context:
     @staticmethod
     def _opts(mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, fallback="fp"):
         """fallback: "fp" (the plain iteration) or "relax" (the relaxed step 1)."""
-        return bz_solve_opts(BZ_SOLVE_PFP if mode == "pfp" else BZ_SOLVE_FP, tol, max_iter, fixed_iters,
-                             {"fp": 0, "relax": 1}[fallback])
+        modes = {"pfp": BZ_SOLVE_PFP, "fp": BZ_SOLVE_FP, "si": BZ_SOLVE_SI}
+        if mode not in modes or fallback not in ("fp", "relax"):
+            raise ValueError(f"mode must be one of {sorted(modes)} and fallback 'fp' or 'relax'")
+        return bz_solve_opts(modes[mode], tol, max_iter, fixed_iters, {"fp": 0, "relax": 1}[fallback])
 
     @staticmethod
     def _stats_tensor(B, device):
@@ -428,7 +430,8 @@ class Slab:
     ``instances`` is a list of dicts with keys xL, xR, nx, eps, T_L, T_R, U_L, U_R,
     mass, and optionally bc_L / bc_R ("wall" or "inflow") with rho_L / rho_R.  ``f`` is a float64 device tensor [sum nx, K] that the slab reads and
     updates in place (borrowed for the slab's lifetime).  ``order`` is the
-    spatial order (1, or 2 for the linear reconstruction)."""
+    spatial order (1, or 2 for the linear reconstruction).  ``mode`` is the
+    visit's iteration: "pfp", "fp", or "si" (the source iteration, BGK only)."""
 
     def __init__(self, ctx: Context, instances, f, collision: str = "binary", bgk_nu: float = 0.0,
                  mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0, order: int = 1, limiter: str = "none",

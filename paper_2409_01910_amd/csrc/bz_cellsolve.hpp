@@ -147,9 +147,12 @@ __device__ __forceinline__ SolveOut solve_core(const RF& rf, const double* g0, d
   __syncthreads();
   // the update loop: wave 0 iterates in theta-space, the block joins only for a
   // pointwise residual when the separable one cannot decide
-  const int n_upd = opt.fixed_iters > 0 ? opt.fixed_iters : opt.max_iter;
-  int k_done = 0;
-  double res = INFINITY;
+  // the source iteration (mode 2) is the one plain update from the given eta
+  // and has no inner residual: it goes straight to the final write
+  const bool si = opt.mode == 2;
+  const int n_upd = si ? 0 : (opt.fixed_iters > 0 ? opt.fixed_iters : opt.max_iter);
+  int k_done = si ? 1 : 0;
+  double res = si ? 0.0 : INFINITY;
   double th[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) th[i] = eta[i];

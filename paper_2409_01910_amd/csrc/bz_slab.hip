@@ -488,17 +488,24 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(double* f, const double
         vm.mg[q] = p[15 + q];
         vm.cg[q] = p[20 + q];
       }
-      // eta0[c] holds the parameters of M[g0] known before the scan (of f_c,
-      // still unchanged, or of the learned start): Newton only confirms them
-      nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta, eta0 + (size_t)c * 5);
+      if (opt.mode == BZ_SOLVE_SI) {
+        // source iteration: eta0[c] holds the parameters of M[f^n_c] from the
+        // start of the iteration, which the one plain update takes as is
+#pragma unroll
+        for (int q = 0; q < 5; ++q) eta[q] = eta0[(size_t)c * 5 + q];
+      } else {
+        // eta0[c] holds the parameters of M[g0] known before the scan (of f_c,
+        // still unchanged, or of the learned start): Newton only confirms them
+        nfail = initial_eta<N>(s_nodes, w, vm.mg, inv_dx, lam, eta, eta0 + (size_t)c * 5);
+      }
     }
     NextMoments nx{has_next ? s_coef : nullptr, s_dinv_next, {}};
     const SolveOut o = solve_core<N, kChainThreads>(rf, fc, fc, lam, inv_dx, opt, s_nodes, s_c, s_dinv, w, vm, eta,
-                                                    nfail, opt.mode == 1, 0, &nx);
+                                                    nfail, opt.mode != BZ_SOLVE_PFP, 0, &nx);
 #pragma unroll
     for (int q = 0; q < 15; ++q) nb[q] = has_next ? nx.out[q] : 0.0;
     it_sum += o.iterations;
-    fb_sum += o.fallback;
+    fb_sum += opt.mode == BZ_SOLVE_PFP ? o.fallback : 0;
   }
   if (threadIdx.x == 0) {
     atomicAdd(&stats[0], it_sum);
@@ -721,7 +728,11 @@ static bz_status ghosts(bz_ctx* ctx, bz_slab* s, Level& L, hipStream_t st) {
   return BZ_OK;
 }
 
+// One scan.  With the source iteration the Maxwellian parameters and nu of the
+// iterate before the forward scan stay in force for the backward scan
+// (L.q_valid is kept), and each visit makes one plain update from them.
 static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream_t st) {
+  const bool si = s->inner.mode == BZ_SOLVE_SI;
   bz_status e = collide(ctx, s, L, st);
   if (e != BZ_OK) return e;
   if ((e = ghosts(ctx, s, L, st)) != BZ_OK) return e;
@@ -741,13 +752,13 @@ static bz_status scan(bz_ctx* ctx, bz_slab* s, Level& L, bool forward, hipStream
                                          L.theta, L.theta_l, L.it_l, L.nu, L.pre, L.eta0, L.d_inst, L.d_cell_inst,
                                          forward ? 1 : 0, ctx->d_nodes, ctx->w, ctx->p.v1_shift, s->d_stats));
   }
-  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, s->inner.fixed_iters, ctx->p.v1_shift,
+  SolveArgs a{s->inner.mode, s->inner.tol, s->inner.max_iter, si ? 1 : s->inner.fixed_iters, ctx->p.v1_shift,
               s->inner.fallback == BZ_FALLBACK_RELAX ? 1 : 0};
   BZ_SLAB_N(ctx->N, hipLaunchKernelGGL((k_chain<NN_>), dim3(s->n_inst), dim3(kChainThreads), 0, st, L.f, L.rs, L.pre,
                                        s->ws ? L.eta0 : L.theta, L.nu,
                                        L.d_inst, forward ? 1 : 0, a, s->d_stats, ctx->d_nodes, ctx->w));
   BZ_HIP(hipGetLastError());
-  L.q_valid = false;
+  L.q_valid = si && forward;
   return BZ_OK;
 }
 
@@ -935,9 +946,13 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (d->collision != BZ_COLL_BINARY && d->collision != BZ_COLL_BGK && d->collision != BZ_COLL_BINARY_CONSERVE)
     return set_err(ctx, BZ_EINVAL, "bad collision");
   const bz_solve_opts& o = d->inner;
-  if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP) return set_err(ctx, BZ_EINVAL, "bad inner mode");
+  if (o.mode != BZ_SOLVE_PFP && o.mode != BZ_SOLVE_FP && o.mode != BZ_SOLVE_SI)
+    return set_err(ctx, BZ_EINVAL, "bad inner mode");
+  if (o.mode == BZ_SOLVE_SI && d->collision != BZ_COLL_BGK)
+    return set_err(ctx, BZ_EINVAL, "the source iteration needs BGK collisions");
   if (o.fallback != BZ_FALLBACK_FP && o.fallback != BZ_FALLBACK_RELAX) return set_err(ctx, BZ_EINVAL, "bad fallback");
-  if (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0))
+  if (o.mode != BZ_SOLVE_SI &&
+      (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0)))
     return set_err(ctx, BZ_EINVAL, "bad inner options");
   int off = 0;
   std::vector<bz::InstDev> hi;
@@ -1065,6 +1080,8 @@ bz_status bz_ws_attach(bz_slab* s, bz_mlp* mlp) {
     s->ws = nullptr;
     return BZ_OK;
   }
+  if (s->inner.mode == BZ_SOLVE_SI)
+    return set_err(ctx, BZ_EUNSUPPORTED, "the source iteration has no inner iteration to start");
   if (bz::ws_ctx(mlp) != ctx) return set_err(ctx, BZ_EINVAL, "the network belongs to another context");
   if (bz::ws_n_in(mlp) != ctx->K + 6 || bz::ws_n_out(mlp) != ctx->K)
     return set_err(ctx, BZ_EINVAL, "the warm-start network must map K + 6 inputs to K outputs");
