@@ -381,14 +381,15 @@ def order_workload(args):
 
 
 def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5, order=1,
-                nu1=1, nu2=1, fp32=False, carleman=False):
+                nu1=1, nu2=1, fp32=False, carleman=False, mode="pfp"):
     """Lid-driven cavity on [0, 1]^2 (all walls T = 1, the lid y = 1 moving at
     (lid, 0)), n^2 velocities on [-l, l]^2, Maxwell molecules with M circle
     directions and nr radial nodes, first-order SGS-PFP FP64 (inner residual
     1e-8), from the uniform unit Maxwellian at rest (mass 1), until the outer
     residual is below tol or the iteration / time budget is spent.  method "mg":
     FAS V-cycles (levels down to min(nx, ny) <= coarsest, one pre- and one
-    post-smoothing iteration) instead of single SGS iterations."""
+    post-smoothing iteration) instead of single SGS iterations.  mode "fp":
+    SGS-FP (the plain inner iteration) instead of SGS-PFP."""
     import numpy as np
     import torch
 
@@ -404,7 +405,8 @@ def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, m
     ctx = bz.Context(N=n, L=l, n_phi=M, n_rho=nr, d=2, precision=bz.BZ_FP32 if fp32 else bz.BZ_FP64,
                      method=bz.BZ_METHOD_CARLEMAN if carleman else bz.BZ_METHOD_SIGMA)
     walls = ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
-    cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100, order=order)
+    cav = bz.Cavity(ctx, nx, nx, eps, walls, f, tol=1e-8, max_iter=100000 if mode == "fp" else 100, order=order,
+                    mode=mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist, inner, visits, last = [cav.residual()], 0, 0, t0
@@ -447,13 +449,26 @@ def cavity_workload(args):
             return "_o2" not in k and "_carl" not in k and k.startswith("paper")
         if args.cavity_case == "carleman":
             return "_carl" in k
+        if args.cavity_case == "fp":
+            return "_fp_" in k
         if args.cavity_case == "second_order":
             return "_o2" in k
         return args.cavity_case in ("all", k)
+    fp_missed = False
     for eps in (1.0, 0.1, 0.01, 0.001):
         key = f"paper_40x40_eps{eps:g}"
         if want(key):
             out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key)
+            print(f"# {key}: {json.dumps(out[key])}", flush=True)
+        key = f"paper_40x40_fp_eps{eps:g}"
+        if want(key) and args.cavity_case != "all":
+            # SGS-FP, first order (run on request: capped at 120 s per eps; once it
+            # misses the cap, smaller eps are not run)
+            if fp_missed:
+                out[key] = {"skipped": True, "reached": False}
+            else:
+                out[key] = _cavity_run(32, L40, 32, 16, 40, eps, 1.0, 1e-5, 3000, 120.0, key, mode="fp")
+                fp_missed = not out[key]["reached"]
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
         key = f"paper_40x40_mg_eps{eps:g}"
         if want(key):
@@ -526,7 +541,8 @@ def plates_workload(args):
     cells), 32^2 velocities, R = 3 and L = (3 sqrt 2 + 1) R / 2, plates at rest
     with T = 1 (x = 0) and T = 2 (x = 1), Maxwell molecules (M = 32 and
     n_rho = 16, which the paper does not state), from the uniform unit
-    Maxwellian (mass 1), to the outer residual 1e-5.  SGS-PFP and MG-SGS-PFP
+    Maxwellian (mass 1), to the outer residual 1e-5.  SGS-FP (first order; the
+    inner iteration capped at 10^5 updates per visit), SGS-PFP and MG-SGS-PFP
     (V-cycles to 4 cells, one pre- and one post-smoothing step at first order;
     to 8 cells with five pre- and one post-smoothing steps at second order, tab.
     mg), each case capped at 120 s; and MG-SGS-PFP at first order with the
@@ -546,21 +562,28 @@ def plates_workload(args):
     ctxs = {False: bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2),
             True: bz.Context(N=n, L=L, n_phi=32, n_rho=16, d=2, method=bz.BZ_METHOD_CARLEMAN)}
     out = {}
-    for order, method, carl in [(o, m, False) for o in (1, 2) for m in ("sgs", "mg")] + [(1, "mg", True)]:
+    for order, method, carl in ([(1, "fp", False)] + [(o, m, False) for o in (1, 2) for m in ("sgs", "mg")]
+                                + [(1, "mg", True)]):
         ctx = ctxs[carl]
+        missed = False
         for eps in (1.0, 0.1, 0.01, 0.001):
             key = f"order{order}_{method}{'_carleman' if carl else ''}_eps{eps:g}"
-            if args.plates_case not in ("all", key):
+            if args.plates_case not in ("all", key) and not (args.plates_case == "fp" and method == "fp"):
+                continue
+            if missed and method == "fp":
+                # SGS-FP slows down as eps falls: once it misses the cap, smaller eps are not run
+                out[key] = {"skipped": True, "reached": False}
                 continue
             f0 = np.repeat(m[None], nx, axis=0)
             f0 *= 1.0 / (dv * dv * f0.sum() / nx)
             f = torch.from_numpy(f0).cuda().contiguous()
-            cav = bz.Cavity(ctx, nx, 1, eps, walls, f, tol=1e-8, max_iter=100, order=order, uniform_y=True)
+            cav = bz.Cavity(ctx, nx, 1, eps, walls, f, tol=1e-8, max_iter=100000 if method == "fp" else 100,
+                            order=order, uniform_y=True, mode="fp" if method == "fp" else "pfp")
             torch.cuda.synchronize()
             t0 = last = time.perf_counter()
             hist, inner, visits = [cav.residual()], 0, 0
             while hist[-1] >= tol and len(hist) <= 20000 and time.perf_counter() - t0 < 120.0:
-                if method == "sgs":
+                if method in ("sgs", "fp"):
                     r, st = cav.sweep(1)
                 elif order == 1:
                     r, st = cav.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
@@ -576,6 +599,7 @@ def plates_workload(args):
             cav.close()
             out[key] = {"seconds": dt, "iterations": len(hist) - 1, "final_residual": hist[-1],
                         "reached": hist[-1] < tol, "mean_inner_iterations": inner / max(visits, 1)}
+            missed = not out[key]["reached"]
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
     return {"workload": "plates", "data": "synthetic", "dtype": "f64", "runs": out}
 
@@ -748,13 +772,13 @@ def main():
                              "n32_128cells_mg", "n32_order2", "n32_order2_mg", "n32_hs_sigma", "n32_hs_carleman"],
                     help="with --workload slab: run one case only")
     ap.add_argument("--cavity-case", default="all",
-                    choices=["all", "first_order", "second_order", "carleman"]
-                            + [f"paper_40x40{m}_eps{e}" for m in ("", "_mg", "_o2", "_o2mg", "_carl", "_carl_mg")
+                    choices=["all", "first_order", "second_order", "carleman", "fp"]
+                            + [f"paper_40x40{m}_eps{e}" for m in ("", "_fp", "_mg", "_o2", "_o2mg", "_carl", "_carl_mg")
                                for e in ("1", "0.1", "0.01", "0.001")]
                             + ["n48_64x64_mg_eps0.1", "n48_64x64_mg_eps0.1_fp32", "batched_q_48x48"],
                     help="with --workload cavity: run one case only")
     ap.add_argument("--plates-case", default="all",
-                    choices=["all"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("sgs", "mg", "mg_carleman")
+                    choices=["all", "fp"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("fp", "sgs", "mg", "mg_carleman")
                                        for e in ("1", "0.1", "0.01", "0.001")],
                     help="with --workload plates: run one case only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -870,6 +894,17 @@ def main():
         elapsed = time.perf_counter() - t0
         prof = ctx.profile_get()
         ctx.profile_enable(False)
+        relax = None
+        if not carl:
+            # the same step with the relaxed step 1 of Section 3.2's remark (one step, after the timed region)
+            t1 = time.perf_counter()
+            _, st_r = ctx.cell_fixed_point(f, inflow, eps, DX, mode="pfp", tol=1e-8, max_iter=100, out=g,
+                                           fallback="relax")
+            torch.cuda.synchronize()
+            d = ctx.decode_stats(st_r)
+            relax = {"ms_per_step": (time.perf_counter() - t1) * 1e3,
+                     "mean_iterations": float(d["iterations"].mean()), "max_iterations": int(d["iterations"].max()),
+                     "fallbacks": int(d["fallback"].sum()), "unconverged": int((d["status"] != 0).sum())}
         ctx.close()
         dt = "f64" if prec == bz.BZ_FP64 else "f32"
         if carl:
@@ -900,6 +935,7 @@ def main():
                     "avg_launch_ms": prof["total_ms"] / max(prof["launches"], 1),
                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
         roof["tuned_plan"] = tuned["plan"]
+        roof["relaxed_step1_step"] = relax
         roof["tuner_candidates_ms"] = [[c["pair_waves"], c["chunk_cells"], m] for c, m in tuned["candidates"]]
         return args.steps * args.batch / elapsed, elapsed, dt, roof, ctx.decode_stats(stats)
 

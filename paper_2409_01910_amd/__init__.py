@@ -352,7 +352,7 @@ class Context:
         return g, stats
 
     def cell_fixed_point(self, f_old, inflow_r, eps, dx, mode="pfp", tol=1e-8, max_iter=100, fixed_iters=0,
-                         out=None):
+                         out=None, fallback="fp"):
         import torch
 
         B = self._field(f_old, "f_old")
@@ -360,7 +360,7 @@ class Context:
         _arg(eps, "eps", B, device=f_old.device)
         g = torch.empty_like(f_old) if out is None else _arg(out, "out", f_old.numel(), device=f_old.device)
         stats = self._stats_tensor(B, f_old.device)
-        o = self._opts(mode, tol, max_iter, fixed_iters)
+        o = self._opts(mode, tol, max_iter, fixed_iters, fallback)
         st = self.lib.bz_cell_fixed_point(self.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx), _ptr(g), B,
                                           ctypes.byref(o), _ptr(stats), _stream())
         self._check(st, "bz_cell_fixed_point")
