@@ -520,12 +520,17 @@ bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cav, double* residual_out, 
  * coarsest level of `coarsest` cells smoothed until its residual falls 10x or
  * coarse_iters iterations pass, and a mass rescale after each cycle.  Every
  * instance's cell count must be coarsest * 2^k.  A cycle stops descending
- * once a level's residual is below `tol`. */
+ * once a level's residual is below `tol`.  With fixed_cycle != 0 the cycle has
+ * no data-dependent exit: every level descends (tol is not consulted) and the
+ * coarsest level runs exactly coarse_iters iterations, so the cycle makes no
+ * host synchronisation; this is the cycle bz_graph_capture_vcycles records
+ * (the cavity rejects it with BZ_EUNSUPPORTED). */
 typedef struct {
   int coarsest;
   int nu1, nu2;
   int coarse_iters;
   double tol;
+  int fixed_cycle;
 } bz_mg_opts;
 
 bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int n_cycles,
@@ -563,6 +568,13 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cav, const bz_mg_opts* opts, 
 typedef struct bz_graph bz_graph;
 bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* slab, int iters_per_replay, int with_residual,
                                   void* stream, bz_graph** out);
+/* bz_graph_capture_vcycles: the same for cycles_per_replay FAS V-cycles (eq.
+ * coarse) of bz_multigrid_vcycle with opts->fixed_cycle forced on (no early
+ * exit, so the replay is one fixed launch sequence), each followed by the mass
+ * rescale.  The coarse levels are allocated before the capture.  A slab with a
+ * learned start attached is refused (BZ_EUNSUPPORTED). */
+bz_status bz_graph_capture_vcycles(bz_ctx* ctx, bz_slab* slab, const bz_mg_opts* opts, int cycles_per_replay,
+                                   int with_residual, void* stream, bz_graph** out);
 bz_status bz_graph_launch(bz_graph* graph, double* residual_out, bz_sweep_stats* stats, void* stream);
 void bz_graph_destroy(bz_graph* graph);
 

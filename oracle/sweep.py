@@ -350,8 +350,12 @@ def level_R(prob: Slab, f: np.ndarray) -> np.ndarray:
 
 
 def vcycle(prob: Slab, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1: int, nu2: int,
-           tol: float, coarse_iters: int = 20):
-    """One FAS V-cycle for R_h(f) = b (eq. coarse)."""
+           tol: float, coarse_iters: int = 20, fixed: bool = False):
+    """One FAS V-cycle for R_h(f) = b (eq. coarse).  The coarsest level is
+    smoothed until its residual falls tenfold or coarse_iters iterations pass,
+    and a level whose residual is below tol does not descend; with fixed = True
+    neither exit is taken (every level descends, the coarsest level runs
+    exactly coarse_iters iterations)."""
     if b is None:
         b = np.zeros_like(f)
     for _ in range(nu1):
@@ -359,17 +363,17 @@ def vcycle(prob: Slab, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1: 
     if prob.nx <= coarsest:
         r0 = norm(prob, b - level_R(prob, f))
         for _ in range(coarse_iters):
-            if norm(prob, b - level_R(prob, f)) <= 0.1 * r0:
+            if not fixed and norm(prob, b - level_R(prob, f)) <= 0.1 * r0:
                 break
             f = sgs_iteration(prob, f, b, rescale=False)
         return f
     res = b - level_R(prob, f)
-    if norm(prob, res) < tol:
+    if not fixed and norm(prob, res) < tol:
         return f
     cp = prob.coarse()
     fc0 = restrict(f)
     bc = level_R(cp, fc0) + restrict(res)
-    fc = vcycle(cp, fc0.copy(), bc, coarsest, nu1, nu2, tol, coarse_iters)
+    fc = vcycle(cp, fc0.copy(), bc, coarsest, nu1, nu2, tol, coarse_iters, fixed)
     prob.stats["inner"] += cp.stats["inner"]
     prob.stats["visits"] += cp.stats["visits"]
     prob.stats["fallback"] += cp.stats["fallback"]

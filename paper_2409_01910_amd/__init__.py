@@ -35,7 +35,7 @@ EXPORTED = [
     "bz_mlp_create", "bz_mlp_destroy", "bz_mlp_num_params", "bz_mlp_get_params", "bz_mlp_set_params",
     "bz_mlp_set_output_scale", "bz_mlp_forward", "bz_mlp_grad", "bz_mlp_train_step", "bz_mlp_features",
     "bz_cell_fixed_point_learned",
-    "bz_graph_capture_sweeps", "bz_graph_launch", "bz_graph_destroy",
+    "bz_graph_capture_sweeps", "bz_graph_capture_vcycles", "bz_graph_launch", "bz_graph_destroy",
     "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
     "bz_slab_inflow", "bz_ws_attach", "bz_set_plan", "bz_get_plan", "bz_tune",
 ]
@@ -90,7 +90,7 @@ class bz_sweep_stats(ctypes.Structure):
 
 class bz_mg_opts(ctypes.Structure):
     _fields_ = [("coarsest", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
-                ("coarse_iters", ctypes.c_int), ("tol", ctypes.c_double)]
+                ("coarse_iters", ctypes.c_int), ("tol", ctypes.c_double), ("fixed_cycle", ctypes.c_int)]
 
 
 class bz_plan(ctypes.Structure):
@@ -173,6 +173,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_profile_enable.argtypes = [P, ctypes.c_int]
     lib.bz_profile_get.argtypes = [P, ctypes.POINTER(bz_profile_info)]
     lib.bz_graph_capture_sweeps.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(ctypes.c_void_p)]
+    lib.bz_graph_capture_vcycles.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, ctypes.c_int, P,
+                                             ctypes.POINTER(ctypes.c_void_p)]
     lib.bz_graph_launch.argtypes = [P, P, ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_graph_destroy.argtypes = [P]
     lib.bz_graph_destroy.restype = None
@@ -509,8 +511,10 @@ class Slab:
         return list(res)
 
     def vcycle(self, n_cycles: int = 1, coarsest: int = 4, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
-               tol: float = 1e-5):
-        o = bz_mg_opts(coarsest, nu1, nu2, coarse_iters, tol)
+               tol: float = 1e-5, fixed_cycle: bool = False):
+        """n_cycles FAS V-cycles; fixed_cycle: no residual-based exits (the
+        cycle capture_vcycles records)."""
+        o = bz_mg_opts(coarsest, nu1, nu2, coarse_iters, tol, 1 if fixed_cycle else 0)
         res = (ctypes.c_double * self.n)()
         st = bz_sweep_stats()
         self.ctx._check(self.ctx.lib.bz_multigrid_vcycle(self.ctx.h, self.h, ctypes.byref(o), n_cycles, res,
@@ -520,6 +524,12 @@ class Slab:
     def capture(self, iters: int, with_residual: bool = True) -> "SweepGraph":
         """Capture iters SGS iterations into a replayable HIP graph."""
         return SweepGraph(self, iters, with_residual)
+
+    def capture_vcycles(self, cycles: int, coarsest: int = 4, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
+                        with_residual: bool = True) -> "SweepGraph":
+        """Capture cycles fixed-structure FAS V-cycles (each with the mass
+        rescale) into a replayable HIP graph."""
+        return SweepGraph(self, cycles, with_residual, mg=bz_mg_opts(coarsest, nu1, nu2, coarse_iters, 0.0, 1))
 
 
 class Cavity:
@@ -589,11 +599,13 @@ class Cavity:
 
 
 class SweepGraph:
-    """iters SGS iterations (and optionally the outer residual) of a Slab captured
-    into a HIP graph (bz_graph_capture_sweeps), replayed on a dedicated stream of
-    default priority that is ordered after the caller's current stream."""
+    """iters SGS iterations, or iters fixed-structure V-cycles (mg given), and
+    optionally the outer residual, of a Slab captured into a HIP graph
+    (bz_graph_capture_sweeps / bz_graph_capture_vcycles), replayed on a
+    dedicated stream of default priority that is ordered after the caller's
+    current stream."""
 
-    def __init__(self, slab: "Slab", iters: int, with_residual: bool = True):
+    def __init__(self, slab: "Slab", iters: int, with_residual: bool = True, mg=None):
         import torch
 
         self.slab = slab
@@ -603,9 +615,15 @@ class SweepGraph:
         self.stream = torch.cuda.Stream()
         self.stream.wait_stream(torch.cuda.current_stream())
         h = ctypes.c_void_p()
-        self.ctx._check(self.ctx.lib.bz_graph_capture_sweeps(self.ctx.h, slab.h, iters, 1 if with_residual else 0,
-                                                             ctypes.c_void_p(self.stream.cuda_stream),
-                                                             ctypes.byref(h)), "bz_graph_capture_sweeps")
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        if mg is None:
+            self.ctx._check(self.ctx.lib.bz_graph_capture_sweeps(self.ctx.h, slab.h, iters, 1 if with_residual else 0,
+                                                                 sp, ctypes.byref(h)), "bz_graph_capture_sweeps")
+        else:
+            self._mg = mg
+            self.ctx._check(self.ctx.lib.bz_graph_capture_vcycles(self.ctx.h, slab.h, ctypes.byref(mg), iters,
+                                                                  1 if with_residual else 0, sp, ctypes.byref(h)),
+                            "bz_graph_capture_vcycles")
         self.h = h
 
     def launch(self):

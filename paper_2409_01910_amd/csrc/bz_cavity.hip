@@ -932,6 +932,7 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int 
   if (!ctx || !cv || cv->ctx != ctx || !o) return BZ_EINVAL;
   if (n_cycles < 0 || o->coarsest < 1 || o->nu1 < 0 || o->nu2 < 0 || o->coarse_iters < 0 || !(o->tol >= 0))
     return set_err(ctx, BZ_EINVAL, "bad multigrid options");
+  if (o->fixed_cycle) return set_err(ctx, BZ_EUNSUPPORTED, "the cavity cycle keeps its residual-based exits");
   {
     int nx = cv->lv[0].nx, ny = cv->lv[0].ny;
     while ((cv->uy ? nx : (nx < ny ? nx : ny)) > o->coarsest) {

@@ -859,13 +859,21 @@ static bz_status build_mg(bz_ctx* ctx, bz_slab* s, int coarsest) {
   return BZ_OK;
 }
 
+// One FAS V-cycle from level l.  With o->fixed_cycle the cycle reads nothing
+// back: every level descends and the coarsest runs coarse_iters iterations.
 static bz_status vcycle(bz_ctx* ctx, bz_slab* s, size_t l, const bz_mg_opts* o, hipStream_t st) {
   Level& L = s->levels[l];
   bz_status e;
   std::vector<double> rn;
+  const bool fixed = o->fixed_cycle != 0;
   for (int i = 0; i < o->nu1; ++i)
     if ((e = sgs_iter(ctx, s, L, false, st)) != BZ_OK) return e;
   if (l + 1 == s->levels.size()) {
+    if (fixed) {
+      for (int it = 0; it < o->coarse_iters; ++it)
+        if ((e = sgs_iter(ctx, s, L, false, st)) != BZ_OK) return e;
+      return BZ_OK;
+    }
     if ((e = residual(ctx, s, L, false, rn, st)) != BZ_OK) return e;
     const double r0 = vmax(rn);
     for (int it = 0; it < o->coarse_iters; ++it) {
@@ -877,20 +885,24 @@ static bz_status vcycle(bz_ctx* ctx, bz_slab* s, size_t l, const bz_mg_opts* o, 
     }
     return BZ_OK;
   }
-  if ((e = residual(ctx, s, L, true, rn, st)) != BZ_OK) return e;  // L.R = R_h(f)
-  if (vmax(rn) < o->tol) return BZ_OK;
+  if (fixed) {
+    if ((e = residual_launch(ctx, s, L, true, st)) != BZ_OK) return e;  // L.R = R_h(f)
+  } else {
+    if ((e = residual(ctx, s, L, true, rn, st)) != BZ_OK) return e;  // L.R = R_h(f)
+    if (vmax(rn) < o->tol) return BZ_OK;
+  }
   Level& C = s->levels[l + 1];
   const size_t K = ctx->K;
   const unsigned gc = (unsigned)(((int64_t)C.ncell * K + 255) / 256);
   // f_H = I f_h ; fc0 = f_H ; res_h = b_h - R_h(f_h) (b_h = 0 on the finest level)
   hipLaunchKernelGGL(k_restrict, dim3(gc), dim3(256), 0, st, L.f, (const double*)nullptr, C.f, (int64_t)C.ncell, (int)K);
-  BZ_HIP(hipMemcpyAsync(C.fc0, C.f, sizeof(double) * K * C.ncell, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_axpy, dim3(gc), dim3(256), 0, st, C.fc0, (const double*)C.f, (const double*)C.f, 0.0,
+                     (int64_t)C.ncell * K);
   C.q_valid = false;
   // b_H = R_H(f_H) + I (b_h - R_h(f_h)): first R_H(f_H) into C.R (C.b not yet used)
-  std::vector<double> tmp;
   double* saved_b = C.b;
   C.b = nullptr;
-  e = residual(ctx, s, C, true, tmp, st);
+  e = residual_launch(ctx, s, C, true, st);
   C.b = saved_b;
   if (e != BZ_OK) return e;
   // C.b = I(b_h - R_h) computed as I(b_h) - I(R_h), then += R_H(f_H)
@@ -1146,17 +1158,13 @@ struct bz_graph {
   bool with_residual = false;
 };
 
-extern "C" {
+namespace {
 
-bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay, int with_residual, void* stream,
-                                  bz_graph** out) {
-  if (!out) return BZ_EINVAL;
-  *out = nullptr;
-  if (!ctx || !s || s->ctx != ctx) return BZ_EINVAL;
-  if (iters_per_replay < 1) return set_err(ctx, BZ_EINVAL, "iters_per_replay < 1");
-  if (!stream) return set_err(ctx, BZ_EINVAL, "capture needs a non-default stream");
-  if (s->ws) return set_err(ctx, BZ_EUNSUPPORTED, "a slab with a warm-start network attached is not captured");
-  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+// Records body(stream) (plus a stats reset and, optionally, the outer
+// residual) into a graph; segments is what the statistics count per replay.
+template <typename Body>
+bz_status capture_graph(bz_ctx* ctx, bz_slab* s, int segments, int with_residual, void* stream, bz_graph** out,
+                        Body body) {
   hipStream_t st = (hipStream_t)stream;
   bz::Level& L = s->levels[0];
   // everything that allocates or sets attributes happens before the capture
@@ -1171,15 +1179,14 @@ bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay,
     ctx->prof = prof;
     return set_err(ctx, BZ_EHIP, "hipStreamBeginCapture");
   }
-  bz_status e = BZ_OK;
+  for (auto& lv : s->levels) lv.q_valid = false;
   hipLaunchKernelGGL(bz::k_zero_u64, dim3(1), dim3(64), 0, st, s->d_stats, 4);  // a kernel, not a memset node
-  L.q_valid = false;
-  for (int it = 0; it < iters_per_replay && e == BZ_OK; ++it) e = bz::sgs_iter(ctx, s, L, true, st);
+  bz_status e = body(st);
   if (e == BZ_OK && with_residual) e = bz::residual_launch(ctx, s, L, false, st);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(st, &g);
   ctx->prof = prof;
-  L.q_valid = false;
+  for (auto& lv : s->levels) lv.q_valid = false;
   if (e != BZ_OK || ce != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     return e != BZ_OK ? e : set_err(ctx, BZ_EHIP, "hipStreamEndCapture");
@@ -1188,7 +1195,7 @@ bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay,
   gr->ctx = ctx;
   gr->slab = s;
   gr->graph = g;
-  gr->iters = iters_per_replay;
+  gr->iters = segments;
   gr->with_residual = with_residual != 0;
   if (hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0) != hipSuccess) {
     bz_graph_destroy(gr);
@@ -1196,6 +1203,53 @@ bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay,
   }
   *out = gr;
   return BZ_OK;
+}
+
+bz_status capture_checks(bz_ctx* ctx, bz_slab* s, int n, void* stream, bz_graph** out) {
+  if (!out) return BZ_EINVAL;
+  *out = nullptr;
+  if (!ctx || !s || s->ctx != ctx) return BZ_EINVAL;
+  if (n < 1) return set_err(ctx, BZ_EINVAL, "at least one iteration or cycle per replay");
+  if (!stream) return set_err(ctx, BZ_EINVAL, "capture needs a non-default stream");
+  if (s->ws) return set_err(ctx, BZ_EUNSUPPORTED, "a slab with a warm-start network attached is not captured");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bz_status bz_graph_capture_sweeps(bz_ctx* ctx, bz_slab* s, int iters_per_replay, int with_residual, void* stream,
+                                  bz_graph** out) {
+  bz_status e = capture_checks(ctx, s, iters_per_replay, stream, out);
+  if (e != BZ_OK) return e;
+  bz::Level& L = s->levels[0];
+  return capture_graph(ctx, s, iters_per_replay, with_residual, stream, out, [&](hipStream_t st) {
+    bz_status r = BZ_OK;
+    for (int it = 0; it < iters_per_replay && r == BZ_OK; ++it) r = bz::sgs_iter(ctx, s, L, true, st);
+    return r;
+  });
+}
+
+bz_status bz_graph_capture_vcycles(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* opts, int cycles_per_replay,
+                                   int with_residual, void* stream, bz_graph** out) {
+  bz_status e = capture_checks(ctx, s, cycles_per_replay, stream, out);
+  if (e != BZ_OK) return e;
+  if (!opts || opts->coarsest < 1 || opts->nu1 < 0 || opts->nu2 < 0 || opts->coarse_iters < 0)
+    return set_err(ctx, BZ_EINVAL, "bad multigrid options");
+  if ((e = bz::build_mg(ctx, s, opts->coarsest)) != BZ_OK) return e;
+  bz_mg_opts o = *opts;
+  o.fixed_cycle = 1;
+  bz::Level& L = s->levels[0];
+  return capture_graph(ctx, s, cycles_per_replay, with_residual, stream, out, [&](hipStream_t st) {
+    bz_status r = BZ_OK;
+    for (int c = 0; c < cycles_per_replay && r == BZ_OK; ++c) {
+      r = bz::vcycle(ctx, s, 0, &o, st);
+      if (r == BZ_OK) r = bz::rescale(ctx, s, L, st);
+    }
+    return r;
+  });
 }
 
 bz_status bz_graph_launch(bz_graph* g, double* residual_out, bz_sweep_stats* stats, void* stream) {
