@@ -497,6 +497,8 @@ def cavity_workload(args):
             out[key] = _cavity_run(48, 8.0, 64, 24, 64, 0.1, 0.5, 1e-5, 40, 90.0, key, method="mg", coarsest=4,
                                    fp32=fp32)
             print(f"# {key}: {json.dumps(out[key])}", flush=True)
+    if args.cavity_case == "n48_64x64_learned":
+        out.update(cavity_learned_runs())
     if not want("batched_q_48x48"):
         return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
     # batched corrected, mass-projected 2D collision term: 4096 cells, 48^2, M = 64, n_rho = 24
@@ -534,6 +536,51 @@ def cavity_workload(args):
                                                    "algorithmic_tflops": 4096 * flop_c / dt / 1e12,
                                                    "frac_peak": 4096 * flop_c / dt / peak}
     return {"workload": "cavity", "data": "synthetic", "dtype": "f64", "runs": out}
+
+
+def cavity_learned_runs(n_train=8, hidden=256, epochs=20):
+    """The 64 x 64 cavity of 48^2 velocities on [-8, 8]^2 (M = 64, n_rho = 24,
+    lid 0.5, walls T = 1) at eps = 0.1 and 0.01, MG-SGS-PFP (V-cycles to 4 x 4)
+    to outer residual 1e-5: plain FP64, the FP32 spectral stage followed by FP64,
+    and each with the learned start.  The network (K + 5 -> hidden -> hidden -> K) is trained
+    first on the V-cycle iterates of n_train 16 x 16 cavities of the family of
+    paper_2409_01910_amd.warmstart (lid ~ U(0.3, 0.7), eps log-uniform in
+    [0.01, 0.3])."""
+    import paper_2409_01910_amd as bz
+    from paper_2409_01910_amd import warmstart as WS
+
+    c64 = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2)
+    c32 = bz.Context(N=48, L=8.0, n_phi=64, n_rho=24, d=2, precision=bz.BZ_FP32)
+    train = [WS.cavity_instance(11, i, 16) for i in range(n_train)]
+    X, Y, info = WS.cavity_dataset(c64, train, n_snap=3)
+    t0 = time.perf_counter()
+    mlp, hist, y_scale = WS.train(c64, X, Y, hidden=hidden, epochs=epochs, batch=256)
+    info["train_seconds"] = time.perf_counter() - t0
+    info["loss_first"], info["loss_last"] = hist[0], hist[-1]
+    mlp32 = WS.clone_network(mlp, c32, y_scale)
+    print(f"# cavity learned start: {info['samples']} samples, loss {hist[0]:.3e} -> {hist[-1]:.3e}",
+          file=sys.stderr, flush=True)
+    out = {"n48_64x64_learned_training": info}
+
+    def switch(inst):
+        # the FP32 stage's residual floor grows like 1/eps (measured: 5.6e-6 at
+        # eps = 0.1, 2.8e-5 at 0.01); hand over to FP64 ten times above it
+        return max(1e-5, 3e-6 / inst["eps"])
+
+    for eps in (0.1, 0.01):
+        inst = dict(nx=64, ny=64, eps=eps, lid=0.5)
+        runs = {}
+        for name, plan in (("plain_fp64", [(c64, None, 1e-5)]), ("learned_fp64", [(c64, mlp, 1e-5)]),
+                           ("plain_fp32_then_fp64", [(c32, None, switch), (c64, None, 1e-5)]),
+                           ("learned_fp32_then_fp64", [(c32, mlp32, switch), (c64, mlp, 1e-5)])):
+            r = WS.cavity_time_to_residual(plan, inst, tol=1e-5, max_seconds=120.0)
+            runs[name] = {k: r[k] for k in ("seconds", "vcycles", "final_residual", "reached", "inner_per_visit",
+                                            "visits", "learned_taken")}
+            print(f"# cavity 64x64 eps {eps} {name}: {r['seconds']:.2f} s, {r['vcycles']} V-cycles, residual "
+                  f"{r['final_residual']:.2e}, learned {r['learned_taken']} of {r['visits']}", file=sys.stderr,
+                  flush=True)
+        out[f"n48_64x64_learned_eps{eps:g}"] = runs
+    return out
 
 
 def plates_workload(args):
@@ -785,7 +832,8 @@ def main():
                     choices=["all", "first_order", "second_order", "carleman", "fp"]
                             + [f"paper_40x40{m}_eps{e}" for m in ("", "_fp", "_mg", "_o2", "_o2mg", "_carl", "_carl_mg")
                                for e in ("1", "0.1", "0.01", "0.001")]
-                            + ["n48_64x64_mg_eps0.1", "n48_64x64_mg_eps0.1_fp32", "batched_q_48x48"],
+                            + ["n48_64x64_mg_eps0.1", "n48_64x64_mg_eps0.1_fp32", "batched_q_48x48",
+                               "n48_64x64_learned"],
                     help="with --workload cavity: run one case only")
     ap.add_argument("--plates-case", default="all",
                     choices=["all", "fp"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("fp", "sgs", "mg", "mg_carleman")

@@ -312,7 +312,9 @@ bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* in
  *   which synchronises) and its gradient [num_params] FP32 device (nullable).
  * bz_mlp_train_step: one Adam step (beta 0.9 / 0.999, eps 1e-8) on that loss.
  * bz_mlp_features: the model input of each cell, width K + 6: inflow_r * dx
- *   (K values), rho, U_1..3, T of the Maxwellian theta, log10(eps).
+ *   (K values), rho, U_1..3, T of the Maxwellian theta, log10(eps); on a context
+ *   with d = 2, width K + 5: inflow_r * dx, rho, U_1, U_2, T of theta [batch][4],
+ *   log10(eps).
  * bz_mlp_set_output_scale: y is multiplied by this before it is added to
  *   M[f_old]. */
 typedef struct bz_mlp bz_mlp;
@@ -514,6 +516,29 @@ bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cav, int n_iters, double* resi
 /* bz_cavity_residual: sqrt(dx dy sum_ij sum_k w (v.grad f - Q/eps)^2), the
  * Section 4 stopping norm, into residual_out (host). */
 bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cav, double* residual_out, void* stream);
+
+/* bz_cavity_inflow: the transport part of every cell's visit right-hand side
+ * (eq. r in two space dimensions) with all four neighbours and the wall ghosts
+ * taken from the current field, plus the static reconstruction terms of its
+ * slopes at second order: what a visit's r would be, less -P/eps, if no
+ * neighbour had been updated yet.  out [nx * ny][K] device, cell (i, j) at row
+ * i * ny + j. */
+bz_status bz_cavity_inflow(bz_ctx* ctx, bz_cavity* cav, double* out, void* stream);
+
+/* bz_cavity_ws_attach: use a warm-start network (bz_mlp with n_in = K + 5,
+ * n_out = K, on the cavity's context) in the cavity's scans; NULL detaches.
+ * Before each scan every cell gets a candidate G = M[f_ij] + scale *
+ * MLP(features of bz_cavity_inflow's row, theta of f_ij, eps, dx), BF16
+ * inference with FP32 accumulation.  The visit itself knows its right-hand
+ * side r (the fresh neighbours of the wavefront included) and starts from G
+ * instead of f_ij when M[G] exists, step 1 of the preconditioned update from G
+ * satisfies eq. existence for r, and G's inner residual
+ * |c g + r - (nu/eps)(M[g] - g)|_{L2} is the smaller.  The visit's iteration is
+ * unchanged, so its result is again the inner solution to the inner tolerance.
+ * bz_sweep_stats.learned counts the visits that started from G.  The cavity
+ * borrows the network; it must outlive the attachment.  Not part of the
+ * paper's method. */
+bz_status bz_cavity_ws_attach(bz_cavity* cav, bz_mlp* mlp);
 
 /* bz_multigrid_vcycle: n_cycles nonlinear multigrid V-cycles (eq. coarse,
  * H = 2h) with SGS-PFP smoothing (nu1 pre-, nu2 post-steps, tab. mg), a

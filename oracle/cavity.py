@@ -36,7 +36,7 @@ import numpy as np
 
 from . import cell as cellmod
 from .collision import bgk_nu_of, nu_of, penalty_split, q_corrected, q_fsm
-from .grid import Spec, velocity_nodes
+from .grid import Spec, phi_vectors, velocity_nodes
 from .maxwellian import discrete_maxwellian
 
 SCANS = ((1, 1), (-1, -1), (-1, 1), (1, -1))
@@ -65,7 +65,10 @@ class Cavity:
     # y walls, two scans (+x, -x) per iteration, multigrid coarsens x only.  This
     # is the 1D slab between two plates with 2D velocities.
     uniform_y: bool = False
-    stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0})
+    # learned warm start: (flat parameters, n_in, hidden, n_out, output scale) of
+    # the network of oracle.mlp, or None for the plain start g0 = f_ij
+    warm: tuple | None = None
+    stats: dict = field(default_factory=lambda: {"inner": 0, "fallback": 0, "visits": 0, "learned": 0})
 
     @property
     def dx(self) -> float:
@@ -152,35 +155,102 @@ def all_collision(prob: Cavity, f: np.ndarray):
     return Q, M, nu
 
 
-def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = None) -> np.ndarray:
-    spec = prob.spec
-    v = velocity_nodes(spec)
+def transport_terms(prob: Cavity, f: np.ndarray, i: int, j: int, slx, sly) -> np.ndarray:
+    """The transport part of a visit's right-hand side for cell (i, j): the
+    upwind neighbour terms (cells or wall ghosts) of f and, at second order, the
+    static reconstruction terms of the slopes (slx, sly)."""
+    v = velocity_nodes(prob.spec)
     v1p, v1m = np.maximum(v[:, 0], 0.0), np.minimum(v[:, 0], 0.0)
     v2p, v2m = np.maximum(v[:, 1], 0.0), np.minimum(v[:, 1], 0.0)
+    zero = np.zeros(prob.spec.K)
+    W, E, S, N = neighbours(prob, f, i, j, slx, sly)
+    r = (-v1p * W + v1m * E) / prob.dx
+    if not prob.uniform_y:
+        r = r + (-v2p * S + v2m * N) / prob.dy
+    if prob.order == 2:
+        xw = slx[i - 1, j] if i > 0 else zero
+        xe = slx[i + 1, j] if i < prob.nx - 1 else zero
+        ys = sly[i, j - 1] if j > 0 else zero
+        yn = sly[i, j + 1] if j < prob.ny - 1 else zero
+        r -= (v1p * xw - v[:, 0] * slx[i, j] + v1m * xe) / (2.0 * prob.dx)
+        if not prob.uniform_y:
+            r -= (v2p * ys - v[:, 1] * sly[i, j] + v2m * yn) / (2.0 * prob.dy)
+    return r
+
+
+def transport_part(prob: Cavity, f: np.ndarray) -> np.ndarray:
+    """transport_terms of every cell with all neighbours (and the wall ghosts)
+    from f: what a visit's r would be, less -P/eps, if no neighbour had been
+    updated yet."""
+    slx, sly = slopes(prob, f)
+    T = np.empty_like(f)
+    for i in range(prob.nx):
+        for j in range(prob.ny):
+            T[i, j] = transport_terms(prob, f, i, j, slx, sly)
+    return T
+
+
+def warm_candidates(prob: Cavity, f: np.ndarray):
+    """Learned candidates of a scan (not part of the paper's method): before the
+    scan every cell gets G_ij = M[f_ij] + scale * y_ij, y_ij the network's output
+    for the features (oracle.mlp.features: the transport part of f times dx, the
+    moments of M[f_ij], log10 eps; K + 5 inputs with two velocity dimensions)."""
+    from . import mlp as mlpmod
+
+    spec = prob.spec
+    params, n_in, H, n_out, scale = prob.warm
+    T = transport_part(prob, f)
+    G = np.empty_like(f)
+    for i in range(prob.nx):
+        for j in range(prob.ny):
+            Mf, th = discrete_maxwellian(spec, f[i, j], return_theta=True)
+            x = mlpmod.features(spec, T[i, j], th, prob.eps, prob.dx)
+            y, _ = mlpmod.forward(params, x[None, :], n_in, H, n_out)
+            G[i, j] = Mf + scale * y[0]
+    return G
+
+
+def warm_choice(prob: Cavity, g: np.ndarray, G: np.ndarray, r: np.ndarray, nu: float) -> bool:
+    """The visit starts from G instead of g when M[G] exists, the preconditioned
+    step 1 from G is solvable (eq. existence) and G's inner residual
+    |c G + r - (nu/eps)(M[G] - G)| with the visit's own r (fresh neighbours
+    included) is below g's."""
+    spec = prob.spec
+    dxs = prob.dx if prob.uniform_y else (prob.dx, prob.dy)
+    c = cellmod.transport_coef(spec, dxs)
+    lam = nu / prob.eps
+    try:
+        MG = discrete_maxwellian(spec, G)
+    except RuntimeError:
+        return False
+    phi = phi_vectors(spec)
+    if not cellmod.existence_ok(spec, spec.w * phi.T @ (c * (MG - G) - r)):
+        return False
+    Mg = discrete_maxwellian(spec, g)
+    res_g = np.sum((c * g + r - lam * (Mg - g)) ** 2)
+    res_G = np.sum((c * G + r - lam * (MG - G)) ** 2)
+    return bool(res_G < res_g)
+
+
+def scan(prob: Cavity, f: np.ndarray, sx: int, sy: int, b: np.ndarray | None = None) -> np.ndarray:
+    spec = prob.spec
     Q, M, nu = all_collision(prob, f)
     P = penalty_split(Q, M, f, nu)
     slx, sly = slopes(prob, f)
-    zero = np.zeros(spec.K)
+    G = warm_candidates(prob, f) if prob.warm is not None else None
     f = f.copy()
     for i in (range(prob.nx) if sx > 0 else range(prob.nx - 1, -1, -1)):
         for j in (range(prob.ny) if sy > 0 else range(prob.ny - 1, -1, -1)):
-            W, E, S, N = neighbours(prob, f, i, j, slx, sly)
-            r = (-v1p * W + v1m * E) / prob.dx
-            if not prob.uniform_y:
-                r = r + (-v2p * S + v2m * N) / prob.dy
-            if prob.order == 2:
-                xw = slx[i - 1, j] if i > 0 else zero
-                xe = slx[i + 1, j] if i < prob.nx - 1 else zero
-                ys = sly[i, j - 1] if j > 0 else zero
-                yn = sly[i, j + 1] if j < prob.ny - 1 else zero
-                r -= (v1p * xw - v[:, 0] * slx[i, j] + v1m * xe) / (2.0 * prob.dx)
-                if not prob.uniform_y:
-                    r -= (v2p * ys - v[:, 1] * sly[i, j] + v2m * yn) / (2.0 * prob.dy)
+            r = transport_terms(prob, f, i, j, slx, sly)
             r -= P[i, j] / prob.eps
             if b is not None:
                 r -= b[i, j]
             dxs = prob.dx if prob.uniform_y else (prob.dx, prob.dy)
-            g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, dxs, f[i, j], mode=prob.inner,
+            g0 = f[i, j]
+            if G is not None and warm_choice(prob, f[i, j], G[i, j], r, nu[i, j]):
+                g0 = G[i, j]
+                prob.stats["learned"] = prob.stats.get("learned", 0) + 1
+            g, st = cellmod.solve(spec, r, nu[i, j], prob.eps, dxs, g0, mode=prob.inner,
                                   tol=prob.tol_inner, max_iter=prob.max_inner, fixed_iters=prob.fixed_inner,
                                   fallback=prob.fallback)
             prob.stats["relaxed"] = prob.stats.get("relaxed", 0) + st.relaxed
@@ -288,8 +358,8 @@ def vcycle(prob: Cavity, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1
     fc0 = restrict(f)
     bc = level_R(cp, fc0) + restrict(res)
     fc = vcycle(cp, fc0.copy(), bc, coarsest, nu1, nu2, tol, coarse_iters)
-    for k in ("inner", "visits", "fallback"):
-        prob.stats[k] += cp.stats[k]
+    for k in ("inner", "visits", "fallback", "learned"):
+        prob.stats[k] = prob.stats.get(k, 0) + cp.stats.get(k, 0)
     f = f + prolong(fc - fc0)
     for _ in range(nu2):
         f = sgs_iteration(prob, f, b, rescale=False)

@@ -38,6 +38,7 @@ EXPORTED = [
     "bz_graph_capture_sweeps", "bz_graph_capture_vcycles", "bz_graph_launch", "bz_graph_destroy",
     "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
     "bz_slab_inflow", "bz_ws_attach", "bz_set_plan", "bz_get_plan", "bz_tune",
+    "bz_cavity_inflow", "bz_cavity_ws_attach",
 ]
 
 
@@ -151,6 +152,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_outer_residual.argtypes = [P, P, P, P]
     lib.bz_slab_inflow.argtypes = [P, P, P, P]
     lib.bz_ws_attach.argtypes = [P, P]
+    lib.bz_cavity_inflow.argtypes = [P, P, P, P]
+    lib.bz_cavity_ws_attach.argtypes = [P, P]
     lib.bz_multigrid_vcycle.argtypes = [P, P, ctypes.POINTER(bz_mg_opts), ctypes.c_int, P,
                                         ctypes.POINTER(bz_sweep_stats), P]
     lib.bz_mlp_create.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
@@ -391,7 +394,7 @@ class Context:
         B = self._field(inflow_r, "inflow_r")
         _arg(theta, "theta", B * (self.d + 2), device=inflow_r.device)
         _arg(eps, "eps", B, device=inflow_r.device)
-        X = torch.empty((B, self.K + 6), dtype=torch.float32, device=inflow_r.device)
+        X = torch.empty((B, self.K + (6 if self.d == 3 else 5)), dtype=torch.float32, device=inflow_r.device)
         self._check(self.lib.bz_mlp_features(self.h, _ptr(inflow_r), _ptr(theta), _ptr(eps), float(dx), _ptr(X), B,
                                              _stream()), "bz_mlp_features")
         return X
@@ -596,6 +599,24 @@ class Cavity:
         self.ctx._check(self.ctx.lib.bz_cavity_residual(self.ctx.h, self.h, ctypes.byref(res), _stream()),
                         "bz_cavity_residual")
         return res.value
+
+    def inflow(self, out=None):
+        """bz_cavity_inflow: the transport part of every cell's right-hand side of
+        the current field, all neighbours (and wall ghosts) from that field; [nx * ny, K]."""
+        import torch
+
+        T = torch.empty_like(self.f) if out is None else _arg(out, "out", self.f.numel(), device=self.f.device)
+        self.ctx._check(self.ctx.lib.bz_cavity_inflow(self.ctx.h, self.h, _ptr(T), _stream()), "bz_cavity_inflow")
+        return T
+
+    def attach_warmstart(self, mlp):
+        """bz_cavity_ws_attach: start visits from the network's guess where its inner
+        residual is the smaller (None detaches).  Keeps a reference to mlp."""
+        if mlp is not None and (mlp.n_in != self.ctx.K + 5 or mlp.n_out != self.ctx.K):
+            raise BZError(f"the network must map K + 5 = {self.ctx.K + 5} inputs to K = {self.ctx.K} outputs")
+        self.ctx._check(self.ctx.lib.bz_cavity_ws_attach(self.h, mlp.h if mlp is not None else None),
+                        "bz_cavity_ws_attach")
+        self._ws = mlp
 
 
 class SweepGraph:

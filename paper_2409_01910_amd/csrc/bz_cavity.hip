@@ -41,6 +41,8 @@ struct CavLevel {
   double* part = nullptr;     // [ncell + 1] per-cell partial sums and their total
   double* sx = nullptr;       // [ncell][K] slopes along x and y (second order)
   double* sy = nullptr;
+  double* T = nullptr;        // [ncell][K] transport part of the scan's iterate (learned start)
+  double* G = nullptr;        // [ncell][K] learned candidates
 };
 
 struct bz_cavity {
@@ -54,7 +56,8 @@ struct bz_cavity {
   int uy = 0;  // uniform along y: no y transport or y walls, two scans, x-only coarsening
   int limiter = 0;  // second order: 0 none, 1 minmod
   std::vector<CavLevel> lv;
-  unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks
+  unsigned long long* d_stats = nullptr;  // inner updates, visits, fallbacks, learned starts taken
+  bz_mlp* ws = nullptr;                   // learned start (bz_cavity_ws_attach), or null
 };
 
 namespace bz {
@@ -267,7 +270,8 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
                                                            int sx, int sy, double dx, double dy, double eps,
                                                            CavWalls wl, const double* __restrict__ nodes, int N,
                                                            double w, int mode, double tol, int max_iter, int fixed,
-                                                           int relax, unsigned long long* __restrict__ stats) {
+                                                           int relax, unsigned long long* __restrict__ stats,
+                                                           const double* __restrict__ Gc) {
   __shared__ double red[14 * (kCavThreads / 64)];
   const int K = N * N;
   int i, j;
@@ -325,6 +329,47 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
   (void)newton4(th_g, t4, true, nodes, N, w, false, a0, a1);
 #pragma unroll
   for (int q = 0; q < OWN; ++q) Mg[q] = gauss2c(th_g, x[q], y[q]);
+  bool learned = false;
+  if (Gc) {
+    // learned candidate: taken when M[G] exists, step 1 from G satisfies eq.
+    // existence and G's inner residual (with this visit's r) is below g's
+    double gG[OWN], MG[OWN], th_G[4], tG[4];
+#pragma unroll
+    for (int q = 0; q < OWN; ++q) {
+      const int k = threadIdx.x + q * kCavThreads;
+      gG[q] = k < K ? Gc[cell * K + k] : 0.0;
+    }
+    moments_of(gG, tG);
+    bool ok = newton4(th_G, tG, true, nodes, N, w, false, a0, a1);
+    double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < OWN; ++q) {
+      const int k = threadIdx.x + q * kCavThreads;
+      MG[q] = ok ? gauss2c(th_G, x[q], y[q]) : 0.0;
+      if (k < K) {
+        const double eg = c[q] * g[q] + r[q] - lam * (Mg[q] - g[q]);
+        const double eG = c[q] * gG[q] + r[q] - lam * (MG[q] - gG[q]);
+        e[0] += eg * eg;
+        e[1] += eG * eG;
+        const double sv = w * (c[q] * (MG[q] - gG[q]) - r[q]);
+        e[2] += sv;
+        e[3] += x[q] * sv;
+        e[4] += y[q] * sv;
+        e[5] += (x[q] * x[q] + y[q] * y[q]) * sv;
+      }
+    }
+    block_sum<6>(e, red);
+    ok = ok && e[2] > 0.0 && e[2] * e[5] > e[3] * e[3] + e[4] * e[4] && e[1] < e[0];
+    if (ok) {
+      learned = true;
+      for (int a = 0; a < 4; ++a) th_g[a] = th_G[a];
+#pragma unroll
+      for (int q = 0; q < OWN; ++q) {
+        g[q] = gG[q];
+        Mg[q] = MG[q];
+      }
+    }
+  }
   double th_step[4] = {th_g[0], th_g[1], th_g[2], th_g[3]};
   bool fallback = mode == BZ_SOLVE_FP, fell = false;
   const int n = fixed > 0 ? fixed : max_iter;
@@ -425,6 +470,50 @@ __global__ void __launch_bounds__(kCavThreads) k_cav_visit(double* __restrict__ 
     atomicAdd(&stats[0], (unsigned long long)it);
     atomicAdd(&stats[1], 1ull);
     atomicAdd(&stats[2], fell ? 1ull : 0ull);
+    if (learned) atomicAdd(&stats[3], 1ull);
+  }
+}
+
+// transport part of a visit's right-hand side for every cell with all
+// neighbours (and wall ghosts) from the iterate f: the upwind neighbour terms
+// and, at second order, the static reconstruction terms of the slopes
+__global__ void __launch_bounds__(kCavThreads) k_cav_transport(const double* __restrict__ f,
+                                                               const double* __restrict__ slx,
+                                                               const double* __restrict__ sly, int nx, int ny, int uy,
+                                                               double dx, double dy, CavWalls wl,
+                                                               const double* __restrict__ nodes, int N,
+                                                               double* __restrict__ T) {
+  __shared__ double red[8 * (kCavThreads / 64)];
+  const int K = N * N;
+  const size_t cell = blockIdx.x;
+  const int i = (int)(cell / ny), j = (int)(cell - (size_t)i * ny);
+  const double* fc = f + cell * K;
+  double dens[4];
+  wall_densities(fc, slx ? slx + cell * K : nullptr, sly ? sly + cell * K : nullptr, i, j, nx, ny, uy, wl, nodes, N,
+                 red, dens);
+  const double* fW = i > 0 ? f + (cell - ny) * K : nullptr;
+  const double* fE = i < nx - 1 ? f + (cell + ny) * K : nullptr;
+  const double* fS = j > 0 ? f + (cell - 1) * K : nullptr;
+  const double* fN = j < ny - 1 ? f + (cell + 1) * K : nullptr;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N];
+    const double W = fW ? fW[k] : dens[0] * wall_m(wl, 0, x, y);
+    const double E = fE ? fE[k] : dens[1] * wall_m(wl, 1, x, y);
+    double t = (-fmax(x, 0.0) * W + fmin(x, 0.0) * E) / dx;
+    if (!uy) {
+      const double S = fS ? fS[k] : dens[2] * wall_m(wl, 2, x, y);
+      const double Nn = fN ? fN[k] : dens[3] * wall_m(wl, 3, x, y);
+      t += (-fmax(y, 0.0) * S + fmin(y, 0.0) * Nn) / dy;
+    }
+    if (slx) {
+      const double xw = i > 0 ? slx[(cell - ny) * K + k] : 0.0, xe = i < nx - 1 ? slx[(cell + ny) * K + k] : 0.0;
+      t -= (fmax(x, 0.0) * xw - x * slx[cell * K + k] + fmin(x, 0.0) * xe) / (2.0 * dx);
+      if (!uy) {
+        const double ys = j > 0 ? sly[(cell - 1) * K + k] : 0.0, yn = j < ny - 1 ? sly[(cell + 1) * K + k] : 0.0;
+        t -= (fmax(y, 0.0) * ys - y * sly[cell * K + k] + fmin(y, 0.0) * yn) / (2.0 * dy);
+      }
+    }
+    T[cell * K + k] = t;
   }
 }
 
@@ -672,7 +761,7 @@ bz_status alloc_level(bz_ctx* ctx, CavLevel& L, bool own, bool slopes) {
 }
 
 void free_level(CavLevel& L, bool own) {
-  void* ptrs[] = {L.Q, L.rs, L.theta, L.nu, L.part, L.res, own ? L.f : nullptr, L.b, L.f0, L.sx, L.sy};
+  void* ptrs[] = {L.Q, L.rs, L.theta, L.nu, L.part, L.res, own ? L.f : nullptr, L.b, L.f0, L.sx, L.sy, L.T, L.G};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   L = CavLevel{};
@@ -726,6 +815,34 @@ bz_status cav_residual(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* res, dou
   return BZ_OK;
 }
 
+// transport part of every cell of a level from its current iterate (slopes
+// recomputed at second order)
+bz_status cav_transport(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, double* T, hipStream_t st) {
+  bz_status s = cav_slopes(ctx, cv, L, st);
+  if (s != BZ_OK) return s;
+  hipLaunchKernelGGL(k_cav_transport, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, cv->order == 2 ? L.sx : nullptr,
+                     cv->order == 2 ? L.sy : nullptr, L.nx, L.ny, cv->uy, L.dx, L.dy, walls_of(cv), ctx->d_nodes,
+                     ctx->N, T);
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// the learned candidates of a scan (after cav_static, which leaves the slopes
+// of the iterate and, for binary collisions, its Maxwellian parameters)
+bz_status cav_candidates(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
+  const size_t bytes = (size_t)L.ncell * ctx->K * sizeof(double);
+  if (!L.T && hipMalloc((void**)&L.T, bytes) != hipSuccess) return set_err(ctx, BZ_ENOMEM, "learned-start field");
+  if (!L.G && hipMalloc((void**)&L.G, bytes) != hipSuccess) return set_err(ctx, BZ_ENOMEM, "learned-start field");
+  bz_status s;
+  if (cv->collision == BZ_COLL_BGK && (s = v2_maxwellian(ctx, L.f, L.theta, nullptr, nullptr, L.ncell, st)) != BZ_OK)
+    return s;
+  hipLaunchKernelGGL(k_cav_transport, dim3(L.ncell), dim3(kCavThreads), 0, st, L.f, cv->order == 2 ? L.sx : nullptr,
+                     cv->order == 2 ? L.sy : nullptr, L.nx, L.ny, cv->uy, L.dx, L.dy, walls_of(cv), ctx->d_nodes,
+                     ctx->N, L.T);
+  BZ_HIP(hipGetLastError());
+  return ws_candidates2(ctx, cv->ws, L.T, L.theta, cv->eps, L.dx, L.G, L.ncell, st);
+}
+
 // one SGS iteration of a level (four scans, FAS source b when the level has one), no rescale
 bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   static const int scans[4][2] = {{1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
@@ -734,6 +851,7 @@ bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
   const auto visit = ctx->K <= 4 * kCavThreads ? k_cav_visit<4> : k_cav_visit<kCavOwn>;
   for (int sc = 0; sc < (cv->uy ? 2 : 4); ++sc) {
     bz_status s = cav_static(ctx, cv, L, st);
+    if (s == BZ_OK && cv->ws) s = cav_candidates(ctx, cv, L, st);
     if (s != BZ_OK) return s;
     for (int dd = 0; dd <= L.nx + L.ny - 2; ++dd) {
       const int lo = dd - (L.ny - 1) > 0 ? dd - (L.ny - 1) : 0;
@@ -742,7 +860,8 @@ bz_status cav_sgs(bz_ctx* ctx, bz_cavity* cv, CavLevel& L, hipStream_t st) {
                          L.ny, cv->uy, dd,
                          scans[sc][0], scans[sc][1], L.dx, L.dy, cv->eps, wl, ctx->d_nodes, ctx->N, ctx->w,
                          cv->opts.mode, cv->opts.tol, cv->opts.max_iter, cv->opts.fixed_iters,
-                         cv->opts.fallback == BZ_FALLBACK_RELAX ? 1 : 0, cv->d_stats);
+                         cv->opts.fallback == BZ_FALLBACK_RELAX ? 1 : 0, cv->d_stats,
+                         cv->ws ? (const double*)L.G : nullptr);
       BZ_HIP(hipGetLastError());
     }
   }
@@ -823,7 +942,7 @@ bz_status cav_vcycle(bz_ctx* ctx, bz_cavity* cv, size_t l, const bz_mg_opts& o, 
 }
 
 bz_status read_stats(bz_ctx* ctx, bz_cavity* cv, bz_sweep_stats* stats, int n, hipStream_t st) {
-  unsigned long long h[3] = {0, 0, 0};
+  unsigned long long h[4] = {0, 0, 0, 0};
   BZ_HIP(hipMemcpyAsync(h, cv->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
   BZ_HIP(hipStreamSynchronize(st));
   if (stats) {
@@ -831,7 +950,7 @@ bz_status read_stats(bz_ctx* ctx, bz_cavity* cv, bz_sweep_stats* stats, int n, h
     stats->inner_iters = (int64_t)h[0];
     stats->visits = (int64_t)h[1];
     stats->fallbacks = (int64_t)h[2];
-    stats->learned = 0;
+    stats->learned = (int64_t)h[3];
   }
   return BZ_OK;
 }
@@ -890,7 +1009,7 @@ bz_status bz_cavity_create(bz_ctx* ctx, const bz_cavity_desc* d, bz_cavity** out
   L0.f = d->f;
   bz_status s = bz::alloc_level(ctx, L0, false, cv->order == 2);
   cv->lv.push_back(L0);
-  if (s == BZ_OK && hipMalloc((void**)&cv->d_stats, 3 * sizeof(unsigned long long)) != hipSuccess)
+  if (s == BZ_OK && hipMalloc((void**)&cv->d_stats, 4 * sizeof(unsigned long long)) != hipSuccess)
     s = set_err(ctx, BZ_ENOMEM, "cavity statistics");
   if (s != BZ_OK) {
     bz_cavity_destroy(cv);
@@ -914,7 +1033,7 @@ bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cv, int n_iters, double* resid
   if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 3 * sizeof(unsigned long long), st));
+  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 4 * sizeof(unsigned long long), st));
   for (int it = 0; it < n_iters; ++it) {
     bz_status s = bz::cav_sgs(ctx, cv, cv->lv[0], st);
     if (s == BZ_OK) s = bz::cav_rescale(ctx, cv, st);
@@ -944,7 +1063,7 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int 
   }
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 3 * sizeof(unsigned long long), st));
+  BZ_HIP(hipMemsetAsync(cv->d_stats, 0, 4 * sizeof(unsigned long long), st));
   for (int c = 0; c < n_cycles; ++c) {
     bz_status s = bz::cav_vcycle(ctx, cv, 0, *o, st);
     if (s == BZ_OK) s = bz::cav_rescale(ctx, cv, st);
@@ -955,6 +1074,30 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int 
     if (s != BZ_OK) return s;
   }
   return bz::read_stats(ctx, cv, stats, n_cycles, st);
+}
+
+bz_status bz_cavity_inflow(bz_ctx* ctx, bz_cavity* cv, double* T_out, void* stream) {
+  if (!ctx || !cv || cv->ctx != ctx || !T_out) return BZ_EINVAL;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  return bz::cav_transport(ctx, cv, cv->lv[0], T_out, (hipStream_t)stream);
+}
+
+bz_status bz_cavity_ws_attach(bz_cavity* cv, bz_mlp* mlp) {
+  if (!cv) return BZ_EINVAL;
+  bz_ctx* ctx = cv->ctx;
+  if (!mlp) {
+    cv->ws = nullptr;
+    return BZ_OK;
+  }
+  if (bz::ws_ctx(mlp) != ctx) return set_err(ctx, BZ_EINVAL, "the network belongs to another context");
+  if (bz::ws_n_in(mlp) != ctx->K + 5 || bz::ws_n_out(mlp) != ctx->K)
+    return set_err(ctx, BZ_EINVAL, "the 2D warm-start network must map K + 5 inputs to K outputs");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  bz_status e = bz::ws_prepare(mlp, cv->lv[0].ncell, nullptr);
+  if (e != BZ_OK) return e;
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(ctx, BZ_EHIP, "hipDeviceSynchronize");
+  cv->ws = mlp;
+  return BZ_OK;
 }
 
 bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cv, double* residual_out, void* stream) {

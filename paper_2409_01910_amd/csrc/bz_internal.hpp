@@ -140,6 +140,8 @@ bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const d
 // inference), and the sizing of the network's scratch and BF16 weights
 bz_status ws_candidates(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, const double* eps,
                         const double* dxs, double* G, int64_t batch, hipStream_t st);
+bz_status ws_candidates2(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, double eps, double dx,
+                         double* G, int64_t batch, hipStream_t st);
 bz_status ws_prepare(bz_mlp* mp, int64_t batch, hipStream_t st);
 bz_ctx* ws_ctx(bz_mlp* mp);
 int ws_n_in(bz_mlp* mp);

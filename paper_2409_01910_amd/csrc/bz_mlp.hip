@@ -229,6 +229,54 @@ __global__ __launch_bounds__(256) void k_warm_guess(const float* __restrict__ Y,
   }
 }
 
+// two-dimensional velocities (N x N grid, block per cell): rows of width K + 5,
+// the transport part times dx, then rho, U_1, U_2, T of the cell's discrete
+// Maxwellian exp(th0 + th1 x + th2 y - th3 (x^2 + y^2)), then log10(eps)
+__global__ __launch_bounds__(256) void k_features2(const double* __restrict__ inflow, const double* __restrict__ theta,
+                                                   const double* __restrict__ eps_c, double eps_all, double dx,
+                                                   float* __restrict__ Xf, unsigned short* __restrict__ Xb,
+                                                   const double* __restrict__ nodes, int N, double w) {
+  const int K = N * N, W = K + 5;
+  const int b = blockIdx.x;
+  const double* th = theta + (size_t)b * 4;
+  const double* in = inflow + (size_t)b * K;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const float x = (float)(in[k] * dx);
+    if (Xf) Xf[(size_t)b * W + k] = x;
+    if (Xb) Xb[(size_t)b * W + k] = f2bf(x);
+  }
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double x = nodes[i];
+      s0 += exp(th[1] * x - th[3] * x * x);
+      s1 += exp(th[2] * x - th[3] * x * x);
+    }
+    const double rho = w * exp(th[0]) * s0 * s1;
+    const double T = 0.5 / th[3];
+    const double e = eps_c ? eps_c[b] : eps_all;
+    const double f[5] = {rho, th[1] * T, th[2] * T, T, log10(e)};
+    for (int i = 0; i < 5; ++i) {
+      if (Xf) Xf[(size_t)b * W + K + i] = (float)f[i];
+      if (Xb) Xb[(size_t)b * W + K + i] = f2bf((float)f[i]);
+    }
+  }
+}
+
+// g0 = M_theta + y_scale * Y on the N x N grid
+__global__ __launch_bounds__(256) void k_warm_guess2(const float* __restrict__ Y, const double* __restrict__ theta,
+                                                     double y_scale, double* __restrict__ g0,
+                                                     const double* __restrict__ nodes, int N) {
+  const int K = N * N;
+  const int b = blockIdx.x;
+  const double* th = theta + (size_t)b * 4;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double x = nodes[k / N], y = nodes[k % N];
+    const double M = exp(th[0] + th[1] * x + th[2] * y - th[3] * (x * x + y * y));
+    g0[(size_t)b * K + k] = M + y_scale * (double)Y[(size_t)b * K + k];
+  }
+}
+
 }  // namespace bz
 
 struct bz_mlp {
@@ -543,12 +591,17 @@ bz_status bz_mlp_train_step(bz_mlp* mp, const float* X, const float* T, int64_t 
 bz_status bz_mlp_features(bz_ctx* ctx, const double* inflow_r, const double* theta, const double* eps, double dx,
                           float* X, int64_t batch, void* stream) {
   if (!ctx) return BZ_EINVAL;
-  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "features need d = 3");
   if (batch < 0 || (batch > 0 && (!inflow_r || !theta || !eps || !X)) || !(dx > 0))
     return set_err(ctx, BZ_EINVAL, "bad feature arguments");
   if (batch == 0) return BZ_OK;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  if (ctx->d == 2) {
+    hipLaunchKernelGGL(bz::k_features2, dim3((unsigned)batch), dim3(256), 0, st, inflow_r, theta, eps, 0.0, dx, X,
+                       (unsigned short*)nullptr, ctx->d_nodes, ctx->N, ctx->w);
+    BZ_HIP(hipGetLastError());
+    return BZ_OK;
+  }
   switch (ctx->N) {
     case 8: hipLaunchKernelGGL((bz::k_features<8>), dim3((unsigned)batch), dim3(256), 0, st, inflow_r, theta, eps, dx, X, (unsigned short*)nullptr, ctx->d_nodes, ctx->w); break;
     case 16: hipLaunchKernelGGL((bz::k_features<16>), dim3((unsigned)batch), dim3(256), 0, st, inflow_r, theta, eps, dx, X, (unsigned short*)nullptr, ctx->d_nodes, ctx->w); break;
@@ -604,6 +657,22 @@ bz_status ws_candidates(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const dou
     case 16: hipLaunchKernelGGL((k_warm_guess<16>), dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G, ctx->d_nodes); break;
     case 32: hipLaunchKernelGGL((k_warm_guess<32>), dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G, ctx->d_nodes); break;
   }
+  BZ_HIP(hipGetLastError());
+  return BZ_OK;
+}
+
+// the learned candidates of a batch of cells with two-dimensional velocities,
+// one eps and one dx: features (BF16) -> MLP (BF16 products) -> G = M_theta + scale y
+bz_status ws_candidates2(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, double eps, double dx,
+                         double* G, int64_t batch, hipStream_t st) {
+  if (mp->n_in != ctx->K + 5 || mp->n_out != ctx->K) return set_err(ctx, BZ_EINVAL, "MLP sizes do not match K");
+  bz_status s = ensure_cap(mp, batch);
+  if (s != BZ_OK) return s;
+  hipLaunchKernelGGL(k_features2, dim3((unsigned)batch), dim3(256), 0, st, inflow, theta, (const double*)nullptr, eps,
+                     dx, (float*)nullptr, mp->xb, ctx->d_nodes, ctx->N, ctx->w);
+  if ((s = forward(mp, mp->xb, batch, true, st)) != BZ_OK) return s;
+  hipLaunchKernelGGL(k_warm_guess2, dim3((unsigned)batch), dim3(256), 0, st, mp->y, theta, mp->y_scale, G,
+                     ctx->d_nodes, ctx->N);
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

@@ -14,7 +14,9 @@ mass 1, initial state the Maxwellian u = 0, T = 1.5; instance i draws from
 numpy.random.default_rng([seed, i]).
 
 Training pairs come from the solver's own iterates: the states after V-cycles
-0, 1, ..., n_snap - 1 of each training instance.  For each cell of a state the
+0, 1, ..., n_snap - 1 of each training instance.  (Two-dimensional cavities,
+below, take the state after the next V-cycle as the target, since the library
+has no single-cell solve with two-dimensional velocities.)  For each cell of a state the
 input is the network's feature row of the cell's transport part (both
 neighbours from that state) and the target is g* - M[f_j], g* the solution
 of the cell's inner problem with that transport part (the visit the learned
@@ -26,7 +28,7 @@ import time
 
 import numpy as np
 
-from . import Context, MLP, Slab
+from . import Cavity, Context, MLP, Slab
 
 
 def heat_slab_instance(seed: int, i: int, nx: int):
@@ -183,3 +185,101 @@ def time_to_residual(plan, inst, tol: float = 1e-8, max_cycles: int = 300, max_s
     if return_field:
         out["f"] = f
     return out
+
+
+# ------------------------------------------------------------------ 2D cavities
+# Family (lid-driven cavities on [0, 1]^2, walls T = 1 at rest except the lid
+# y = 1): lid speed ~ U(0.3, 0.7), eps log-uniform in [0.01, 0.3]; instance i
+# draws from numpy.random.default_rng([seed, i]); initial state the unit
+# Maxwellian at rest of total mass 1.
+
+MG2 = dict(coarsest=4, nu1=1, nu2=1, coarse_iters=20)
+
+
+def cavity_instance(seed: int, i: int, n: int):
+    rng = np.random.default_rng([seed, i])
+    lid = float(rng.uniform(0.3, 0.7))
+    eps = float(np.exp(rng.uniform(np.log(0.01), np.log(0.3))))
+    return dict(nx=n, ny=n, eps=eps, lid=lid)
+
+
+def cavity_walls(lid: float):
+    return ((1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (0.0, 0.0)), (1.0, (lid, 0.0)))
+
+
+def cavity_field(ctx: Context, nx: int, ny: int):
+    """Uniform unit Maxwellian at rest of total mass 1 on [0, 1]^2 (input data)."""
+    import torch
+
+    N, L = ctx.params.N, ctx.params.L
+    dv = 2.0 * L / N
+    x = (np.arange(N) - N // 2 + 1) * dv
+    V = np.stack(np.meshgrid(x, x, indexing="ij"), -1).reshape(-1, 2)
+    m = np.exp(-(V * V).sum(1) / 2.0) / (2.0 * np.pi)
+    f0 = np.repeat(m[None], nx * ny, axis=0)
+    f0 *= 1.0 / (dv * dv * f0.sum() / (nx * ny))
+    return torch.from_numpy(f0).to(f"cuda:{ctx.params.device}").contiguous()
+
+
+def cavity_dataset(ctx: Context, instances, n_snap: int = 3):
+    """Features X [n, K + 5] (float32) and targets f_next - M[f] [n, K] (float32):
+    for the states f after V-cycles 0 .. n_snap - 1 of every instance, the
+    features of f's transport part and Maxwellian, and the state after the next
+    V-cycle.  Returns (X, Y, info)."""
+    import torch
+
+    Xs, Ys, t0 = [], [], time.perf_counter()
+    for d in instances:
+        f = cavity_field(ctx, d["nx"], d["ny"])
+        cav = Cavity(ctx, d["nx"], d["ny"], d["eps"], cavity_walls(d["lid"]), f)
+        eps = torch.full((d["nx"] * d["ny"],), d["eps"], dtype=torch.float64, device=f.device)
+        for _ in range(n_snap):
+            T = cav.inflow()
+            theta, M, _ = ctx.maxwellian(f)
+            X = ctx.features(T, theta, eps, 1.0 / d["nx"])
+            cav.vcycle(1, tol=1e-8, **MG2)
+            ok = torch.isfinite(f).all(1)
+            Xs.append(X[ok])
+            Ys.append((f - M)[ok].to(torch.float32))
+        cav.close()
+    X, Y = torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous()
+    return X, Y, {"samples": int(X.shape[0]), "seconds": time.perf_counter() - t0}
+
+
+def cavity_time_to_residual(plan, inst, tol: float = 1e-5, max_cycles: int = 200, max_seconds: float = 120.0,
+                            coarsest: int = 4):
+    """MG-SGS-PFP V-cycles on one cavity from the uniform state until the outer
+    residual is below tol; plan as in time_to_residual.  Returns seconds,
+    V-cycles, inner updates per visit, learned starts taken and per-leg counts."""
+    import torch
+
+    f = cavity_field(plan[0][0], inst["nx"], inst["ny"])
+    hist, inner, visits, learned, legs = [], 0, 0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ctx, mlp, switch in plan:
+        if callable(switch):
+            switch = switch(inst)
+        cav = Cavity(ctx, inst["nx"], inst["ny"], inst["eps"], cavity_walls(inst["lid"]), f)
+        if mlp is not None:
+            cav.attach_warmstart(mlp)
+        if not hist:
+            hist.append(cav.residual())
+        start, best, best_at = len(hist), hist[-1], len(hist)
+        while hist[-1] >= switch and len(hist) <= max_cycles and time.perf_counter() - t0 < max_seconds:
+            r, st = cav.vcycle(1, tol=tol, coarsest=coarsest, nu1=1, nu2=1, coarse_iters=20)
+            hist.append(r)
+            inner += st["inner_iters"]
+            visits += st["visits"]
+            learned += st["learned"]
+            if r < 0.9 * best:
+                best, best_at = r, len(hist)
+            if not np.isfinite(r) or (switch > tol and len(hist) - best_at > 10):
+                break
+        legs.append({"precision": "fp64" if ctx.params.precision == 0 else "fp32", "learned": mlp is not None,
+                     "vcycles": len(hist) - start, "residual_at_end": hist[-1]})
+        cav.close()
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t0, "vcycles": len(hist) - 1, "final_residual": hist[-1],
+            "reached": hist[-1] < tol, "inner_per_visit": inner / max(visits, 1), "visits": visits,
+            "learned_taken": learned, "legs": legs}
