@@ -254,10 +254,14 @@ def _bgk_study_run(ctx, row, order, eps, nx, cap_s, tol=1e-5):
     import paper_2409_01910_amd as bz
     import synth
 
-    n, l = ctx.params.N, ctx.params.L
-    m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+    n, l, dim = ctx.params.N, ctx.params.L, ctx.params.d
+    if dim == 1:
+        v = (np.arange(n) - n // 2 + 1) * (2.0 * l / n)
+        m = np.exp(-v * v / 3.0) / np.sqrt(3.0 * np.pi)
+    else:
+        m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
     f0 = np.repeat(m[None], nx, axis=0)
-    f0 *= 1.0 / ((1.0 / nx) * (2.0 * l / n) ** 3 * f0.sum())
+    f0 *= 1.0 / ((1.0 / nx) * (2.0 * l / n) ** dim * f0.sum())
     f = torch.from_numpy(f0).cuda().contiguous()
     mode = {"SI": "si", "SGS-FP": "fp"}.get(row, "pfp")
     slab = bz.Slab(ctx, [dict(xL=-0.5, xR=0.5, nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="bgk",
@@ -265,8 +269,12 @@ def _bgk_study_run(ctx, row, order, eps, nx, cap_s, tol=1e-5):
     res = slab.residual()[0]
     its, inner, visits = 0, 0, 0
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    t0 = last = time.perf_counter()
     while res >= tol and time.perf_counter() - t0 < cap_s and np.isfinite(res):
+        if time.perf_counter() - last > 30.0:
+            last = time.perf_counter()
+            print(f"# bgk study {row} order {order} eps {eps:g}: iteration {its}, residual {res:.2e}",
+                  file=sys.stderr, flush=True)
         if row == "MG-SGS-PFP":
             r, st = (slab.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=0.0) if order == 2
                      else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=0.0))
@@ -286,14 +294,17 @@ def _bgk_study_run(ctx, row, order, eps, nx, cap_s, tol=1e-5):
 def bgk_study_workload(args):
     """Time to outer residual 1e-5 of SI, SGS-FP, SGS-PFP and MG-SGS-PFP (first
     and second order) on the BGK heat-transfer slab for eps = 1 .. 1e-4, the
-    study of tab. time_1D1V, in three velocity dimensions (16^3 nodes on
-    [-6, 6]^3) with 256 cells.  Runs that do not reach 1e-5 within the cap are
-    reported with reached = False; once a method misses the cap at some eps its
-    runs at smaller eps are skipped (skipped = True), every method slowing down
-    as eps falls."""
+    study of tab. time_1D1V: one velocity dimension with 50 nodes on [-6, 6]
+    and 256 cells (the paper's discretisation), or with --study-d 3 three
+    velocity dimensions (16^3 nodes on [-6, 6]^3).  Runs that do not reach
+    1e-5 within the cap are reported with reached = False; once a method
+    misses the cap at some eps its runs at smaller eps are skipped
+    (skipped = True), every method slowing down as eps falls."""
     import paper_2409_01910_amd as bz
 
-    ctx = bz.Context(N=args.study_n, L=6.0, n_theta=2, n_phi=4, n_rho=2)
+    n = args.study_n or (50 if args.study_d == 1 else 16)
+    ctx = (bz.Context(N=n, L=6.0, d=1) if args.study_d == 1
+           else bz.Context(N=n, L=6.0, n_theta=2, n_phi=4, n_rho=2))
     table = {}
     for row, order in STUDY_ROWS:
         key = f"{row} order {order}"
@@ -310,7 +321,8 @@ def bgk_study_workload(args):
                   f"residual {out['residual']:.2e}, inner/visit {out['inner_per_visit']:.2f}", file=sys.stderr,
                   flush=True)
     ctx.close()
-    return {"workload": "bgk-study", "cells": args.study_cells, "N": args.study_n, "L": 6.0, "tol": 1e-5,
+    return {"workload": "bgk-study", "cells": args.study_cells, "N": n, "velocity_dims": args.study_d, "L": 6.0,
+            "tol": 1e-5,
             "inner_tol": 1e-8, "cap_seconds": args.study_cap, "table": table}
 
 
@@ -849,7 +861,8 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=30, help="warmstart: training epochs")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-start time-to-residual runs")
     ap.add_argument("--study-cells", type=int, default=256, help="bgk-study: cells of the slab")
-    ap.add_argument("--study-n", type=int, default=16, help="bgk-study: velocity nodes per axis")
+    ap.add_argument("--study-d", type=int, default=1, choices=[1, 3], help="bgk-study: velocity dimensions")
+    ap.add_argument("--study-n", type=int, default=0, help="bgk-study: velocity nodes per axis (50 in 1D, 16 in 3D)")
     ap.add_argument("--study-cap", type=float, default=20.0, help="bgk-study: seconds per run at most")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates",
                                            "bgk-study"], default="batched-q",

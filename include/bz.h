@@ -104,7 +104,19 @@ typedef struct bz_ctx bz_ctx;
  *            BZ_METHOD_CARLEMAN (gamma = 0),
  *            v1_shift = 0, and the calls bz_eval_Q (flags BZ_Q_CORRECTED and
  *            BZ_Q_MASS), bz_maxwellian and the bz_cavity_* scans; the other calls
- *            return BZ_EUNSUPPORTED on such a context. */
+ *            return BZ_EUNSUPPORTED on such a context.
+ *            With d = 1 the grid is N nodes (N even, 2 <= N <= 64) and the
+ *            context serves the BGK slab of Section 4.1's 1D1V model only
+ *            (bz_slab_create with BZ_COLL_BGK and diffuse walls at rest, modes
+ *            PFP, FP and SI, first or second order; bz_sgs_sweep,
+ *            bz_multigrid_vcycle, bz_outer_residual): BZ_FP64, BZ_METHOD_SIGMA,
+ *            v1_shift = 0; the collision rule sizes are not used.  Moments and
+ *            Maxwellian parameters have 3 entries (1, v, v^2), the BGK
+ *            frequency is |S^0| rho = 2 rho unless bgk_nu is given, and one
+ *            wave runs each instance's whole call (iterations or V-cycles) in
+ *            one launch, with the V-cycle's exits decided per instance.  Graph
+ *            capture, the learned start and the other calls return
+ *            BZ_EUNSUPPORTED. */
 typedef enum { BZ_METHOD_SIGMA = 0, BZ_METHOD_CARLEMAN = 1 } bz_method;
 
 typedef struct {

@@ -123,8 +123,8 @@ def radial_rule(spec: Spec, n: int | None = None):
 
 
 def sphere_area(d: int) -> float:
-    """|S^{d-1}|: 2 pi (d=2), 4 pi (d=3)."""
-    return 2.0 * np.pi if d == 2 else 4.0 * np.pi
+    """|S^{d-1}|: 2 (d=1, the two points +-1), 2 pi (d=2), 4 pi (d=3)."""
+    return {1: 2.0, 2: 2.0 * np.pi, 3: 4.0 * np.pi}[d]
 
 
 def S_d(d: int, z):

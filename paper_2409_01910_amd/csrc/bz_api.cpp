@@ -74,14 +74,18 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   *out = nullptr;
   if (!p) return BZ_EINVAL;
   const int d = p->d == 0 ? 3 : p->d;
-  if (d != 2 && d != 3) return BZ_EINVAL;
+  if (d != 1 && d != 2 && d != 3) return BZ_EINVAL;
+  // one velocity dimension serves the BGK slab only: up to 64 nodes, FP64, no shift
+  if (d == 1 && (p->N < 2 || p->N > 64 || p->N % 2 || p->precision != BZ_FP64 || p->v1_shift != 0.0 ||
+                 p->method != BZ_METHOD_SIGMA))
+    return BZ_EINVAL;
   if (d == 3 && !(p->N == 8 || p->N == 16 || p->N == 32)) return BZ_EINVAL;
   if (d == 2 && !(p->N == 8 || p->N == 12 || p->N == 16 || p->N == 24 || p->N == 32 || p->N == 48))
     return BZ_EINVAL;
   if (!(p->L > 0) || !std::isfinite(p->L)) return BZ_EINVAL;
   if (d == 3 && (p->n_theta < 2 || p->n_theta % 2 || p->n_theta > 64)) return BZ_EINVAL;
-  if (p->n_phi < 2 || p->n_phi % 2 || p->n_phi > 256) return BZ_EINVAL;
-  if (p->n_rho < 1 || p->n_rho > 256) return BZ_EINVAL;
+  if (d > 1 && (p->n_phi < 2 || p->n_phi % 2 || p->n_phi > 256)) return BZ_EINVAL;
+  if (d > 1 && (p->n_rho < 1 || p->n_rho > 256)) return BZ_EINVAL;
   if (p->precision != BZ_FP64 && p->precision != BZ_FP32) return BZ_EINVAL;
   if (!(p->gamma > -3.0) || p->gamma > 2.0) return BZ_EINVAL;
   if (!std::isfinite(p->v1_shift) || std::fabs(p->v1_shift) > 1e6) return BZ_EINVAL;
@@ -95,12 +99,12 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   ctx->p.d = d;
   ctx->d = d;
   ctx->N = p->N;
-  ctx->K = d == 3 ? p->N * p->N * p->N : p->N * p->N;
+  ctx->K = d == 3 ? p->N * p->N * p->N : d == 2 ? p->N * p->N : p->N;
   ctx->n_theta = p->n_theta;
   ctx->n_phi = p->n_phi;
   ctx->n_rho = p->n_rho;
   ctx->dv = 2.0 * p->L / p->N;
-  ctx->w = d == 3 ? ctx->dv * ctx->dv * ctx->dv : ctx->dv * ctx->dv;
+  ctx->w = d == 3 ? ctx->dv * ctx->dv * ctx->dv : d == 2 ? ctx->dv * ctx->dv : ctx->dv;
   ctx->R = p->R > 0 ? p->R : 2.0 * p->L / (3.0 * std::sqrt(2.0) + 1.0);
   ctx->Rg = 2.0 * ctx->R;
   // <|g|^gamma> = (4T)^{gamma/2} Gamma((d + gamma)/2) / Gamma(d/2): the T-independent factor
@@ -173,6 +177,7 @@ bz_status check_eval_q_args(bz_ctx* ctx, const double* f, const double* Q, int64
   if (theta && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "theta requires BZ_Q_CORRECTED");
   if ((flags & BZ_Q_MASS) && !(flags & BZ_Q_CORRECTED)) return set_err(ctx, BZ_EINVAL, "BZ_Q_MASS requires BZ_Q_CORRECTED");
   if (ctx->d == 2 && (flags & BZ_Q_CONSERVE)) return set_err(ctx, BZ_EUNSUPPORTED, "BZ_Q_CONSERVE with d = 2");
+  if (ctx->d == 1) return set_err(ctx, BZ_EUNSUPPORTED, "a context with d = 1 serves the BGK slab only");
   return BZ_OK;
 }
 
@@ -207,6 +212,7 @@ bz_status bz_maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, 
   if (!ctx) return BZ_EINVAL;
   if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
   if (batch > 0 && (!f || !theta)) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (ctx->d == 1) return set_err(ctx, BZ_EUNSUPPORTED, "a context with d = 1 serves the BGK slab only");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   if (ctx->d == 2) return bz::v2_maxwellian(ctx, f, theta, M, newton_iters, batch, (hipStream_t)stream);
   return bz::maxwellian(ctx, f, theta, M, newton_iters, batch, (hipStream_t)stream);

@@ -143,6 +143,14 @@ bz_status ws_candidates(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const dou
 bz_status ws_candidates2(bz_ctx* ctx, bz_mlp* mp, const double* inflow, const double* theta, double eps, double dx,
                          double* G, int64_t batch, hipStream_t st);
 bz_status ws_prepare(bz_mlp* mp, int64_t batch, hipStream_t st);
+
+// the slab with one velocity dimension (csrc/bz_slab1v.hip); op 0: SGS
+// iterations, 1: V-cycles, 2: residual only
+struct Slab1V;
+bz_status slab1v_create(bz_ctx* ctx, const bz_slab_desc* d, Slab1V** out);
+void slab1v_destroy(Slab1V* s);
+bz_status slab1v_run(bz_ctx* ctx, Slab1V* s, double* f, int op, int n, const bz_mg_opts* mg, double* residual_out,
+                     bz_sweep_stats* stats, hipStream_t st);
 bz_ctx* ws_ctx(bz_mlp* mp);
 int ws_n_in(bz_mlp* mp);
 int ws_n_out(bz_mlp* mp);

@@ -593,6 +593,7 @@ bz_status bz_mlp_features(bz_ctx* ctx, const double* inflow_r, const double* the
   if (!ctx) return BZ_EINVAL;
   if (batch < 0 || (batch > 0 && (!inflow_r || !theta || !eps || !X)) || !(dx > 0))
     return set_err(ctx, BZ_EINVAL, "bad feature arguments");
+  if (ctx->d == 1) return set_err(ctx, BZ_EUNSUPPORTED, "a context with d = 1 serves the BGK slab only");
   if (batch == 0) return BZ_OK;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;

@@ -93,6 +93,8 @@ struct bz_slab {
   std::vector<bz::Level> levels;
   bool mg_built = false;
   bz_mlp* ws = nullptr;  // attached warm-start network (borrowed), or NULL
+  bz::Slab1V* v1 = nullptr;  // one velocity dimension: the whole slab lives there
+  double* f = nullptr;       // the caller's field (borrowed)
 };
 
 namespace bz {
@@ -951,7 +953,7 @@ extern "C" {
 bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (!ctx || !out) return BZ_EINVAL;
   *out = nullptr;
-  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "the 1D slab needs d = 3 (use the bz_cavity_* calls)");
+  if (ctx->d == 2) return set_err(ctx, BZ_EUNSUPPORTED, "the 1D slab needs d = 1 or 3 (use the bz_cavity_* calls)");
   if (!d || d->n_instances < 1 || !d->instances || !d->f) return set_err(ctx, BZ_EINVAL, "bad slab description");
   if (d->order < 0 || d->order > 2) return set_err(ctx, BZ_EINVAL, "order must be 1 or 2 (0 reads as 1)");
   if (d->limiter != BZ_LIMITER_NONE && d->limiter != BZ_LIMITER_MINMOD) return set_err(ctx, BZ_EINVAL, "bad limiter");
@@ -966,6 +968,27 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
   if (o.mode != BZ_SOLVE_SI &&
       (o.fixed_iters < 0 || (o.fixed_iters == 0 && (o.max_iter < 1 || o.max_iter > 100000)) || !(o.tol >= 0)))
     return set_err(ctx, BZ_EINVAL, "bad inner options");
+  if (ctx->d == 1) {
+    for (int i = 0; i < d->n_instances; ++i) {
+      const bz_slab_instance& in = d->instances[i];
+      if (in.nx < 1 || !(in.xR > in.xL) || !(in.eps > 0) || !(in.T_L > 0) || !(in.T_R > 0) || !(in.mass > 0))
+        return set_err(ctx, BZ_EINVAL, "bad slab instance");
+    }
+    if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+    bz::Slab1V* v1 = nullptr;
+    bz_status e = bz::slab1v_create(ctx, d, &v1);
+    if (e != BZ_OK) return e;
+    bz_slab* s = new bz_slab();
+    s->ctx = ctx;
+    s->n_inst = d->n_instances;
+    s->inst.assign(d->instances, d->instances + d->n_instances);
+    s->collision = d->collision;
+    s->inner = o;
+    s->v1 = v1;
+    s->f = d->f;
+    *out = s;
+    return BZ_OK;
+  }
   int off = 0;
   std::vector<bz::InstDev> hi;
   std::vector<bz::WallDev> walls;
@@ -1040,6 +1063,7 @@ bz_status bz_slab_create(bz_ctx* ctx, const bz_slab_desc* d, bz_slab** out) {
 void bz_slab_destroy(bz_slab* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
+  if (s->v1) bz::slab1v_destroy(s->v1);
   for (auto& L : s->levels) bz::level_free(L);
   if (s->wallM) (void)hipFree(s->wallM);
   if (s->wall_in) (void)hipFree(s->wall_in);
@@ -1054,6 +1078,7 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
   if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 0, n_iters, nullptr, residual_out, stats, st);
   if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
     return set_err(ctx, BZ_EHIP, "stats reset");
   bz::Level& L = s->levels[0];
@@ -1073,6 +1098,7 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
 
 bz_status bz_slab_inflow(bz_ctx* ctx, bz_slab* s, double* out, void* stream) {
   if (!ctx || !s || s->ctx != ctx || !out) return BZ_EINVAL;
+  if (s->v1) return set_err(ctx, BZ_EUNSUPPORTED, "one velocity dimension: no learned start");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   bz::Level& L = s->levels[0];
@@ -1092,6 +1118,7 @@ bz_status bz_ws_attach(bz_slab* s, bz_mlp* mlp) {
     s->ws = nullptr;
     return BZ_OK;
   }
+  if (s->v1) return set_err(ctx, BZ_EUNSUPPORTED, "one velocity dimension: no learned start");
   if (s->inner.mode == BZ_SOLVE_SI)
     return set_err(ctx, BZ_EUNSUPPORTED, "the source iteration has no inner iteration to start");
   if (bz::ws_ctx(mlp) != ctx) return set_err(ctx, BZ_EINVAL, "the network belongs to another context");
@@ -1112,6 +1139,7 @@ bz_status bz_ws_attach(bz_slab* s, bz_mlp* mlp) {
 bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* s, double* residual_out, void* stream) {
   if (!ctx || !s || s->ctx != ctx || !residual_out) return BZ_EINVAL;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 2, 0, nullptr, residual_out, nullptr, (hipStream_t)stream);
   bz::Level& L = s->levels[0];
   L.q_valid = false;
   std::vector<double> rn;
@@ -1128,6 +1156,7 @@ bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int 
     return set_err(ctx, BZ_EINVAL, "bad multigrid options");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 1, n_cycles, o, residual_out, stats, st);
   bz_status e = bz::build_mg(ctx, s, o->coarsest);
   if (e != BZ_OK) return e;
   if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
@@ -1212,6 +1241,8 @@ bz_status capture_checks(bz_ctx* ctx, bz_slab* s, int n, void* stream, bz_graph*
   if (n < 1) return set_err(ctx, BZ_EINVAL, "at least one iteration or cycle per replay");
   if (!stream) return set_err(ctx, BZ_EINVAL, "capture needs a non-default stream");
   if (s->ws) return set_err(ctx, BZ_EUNSUPPORTED, "a slab with a warm-start network attached is not captured");
+  if (s->v1)
+    return set_err(ctx, BZ_EUNSUPPORTED, "one velocity dimension: a call already runs whole iterations in one launch");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   return BZ_OK;
 }

@@ -144,6 +144,11 @@ static bz_status build_carleman_tables(bz_ctx* ctx, const std::vector<double>& c
 
 bz_status build_tables(bz_ctx* ctx) {
   if (ctx->d == 2) return build_tables_v2(ctx);
+  if (ctx->d == 1) {  // the BGK slab needs the nodes only
+    ctx->h_nodes.resize(ctx->N);
+    for (int i = 0; i < ctx->N; ++i) ctx->h_nodes[i] = (i - ctx->N / 2 + 1) * ctx->dv;
+    return upload(ctx, &ctx->d_nodes, ctx->h_nodes);
+  }
   const int N = ctx->N, K = ctx->K, nt = ctx->n_theta, np = ctx->n_phi, nr = ctx->n_rho;
   const double L = ctx->p.L, gam = ctx->p.gamma;
   std::vector<double> ct, wt, rr, wr;
