@@ -326,10 +326,11 @@ def bgk_study_workload(args):
             "inner_tol": 1e-8, "cap_seconds": args.study_cap, "table": table}
 
 
-def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10):
-    """BGK heat slab (x in [0, 1], walls T = 1 and 2 at rest, mass 1, n^3
-    velocities on [-l, l]^3) driven by V-cycles (tab. mg's parameters for the
-    order) to outer residual tol; cell averages of rho and T, V-cycles, seconds."""
+def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10, dim=3):
+    """BGK heat slab (x in [0, 1], walls T = 1 and 2 at rest, mass 1, n^dim
+    velocities on [-l, l]^dim; dim = 1 is the 1D1V model with nu = 1, dim = 3
+    uses 4 pi rho) driven by V-cycles (tab. mg's parameters for the order) to
+    outer residual tol; cell averages of rho and T, V-cycles, seconds."""
     import numpy as np
     import torch
 
@@ -337,13 +338,20 @@ def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10):
     import synth
 
     dv = 2.0 * l / n
-    m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+    x = (np.arange(n) - n // 2 + 1) * dv
+    if dim == 1:
+        m = np.exp(-x * x / 3.0) / np.sqrt(3.0 * np.pi)
+        ctx = bz.Context(N=n, L=l, d=1)
+        nu = 1.0
+    else:
+        m = synth.maxwellian_mixture([(1.0, np.zeros(3), 1.5)], n, l)
+        ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8)
+        nu = 0.0
     f0 = np.repeat(m[None], nx, axis=0)
-    f0 *= 1.0 / ((1.0 / nx) * dv ** 3 * f0.sum())
+    f0 *= 1.0 / ((1.0 / nx) * dv ** dim * f0.sum())
     f = torch.from_numpy(f0).cuda().contiguous()
-    ctx = bz.Context(N=n, L=l, n_theta=4, n_phi=8, n_rho=8)
-    slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="bgk", tol=1e-11,
-                   max_iter=200, order=order)
+    slab = bz.Slab(ctx, [dict(nx=nx, eps=eps, T_L=1.0, T_R=2.0, mass=1.0)], f, collision="bgk", bgk_nu=nu,
+                   tol=1e-11, max_iter=200, order=order)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r, cycles = slab.residual()[0], 0
@@ -354,30 +362,35 @@ def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10):
     dt = time.perf_counter() - t0
     F = f.cpu().numpy()
     slab.close()
-    x = (np.arange(n) - n // 2 + 1) * dv
-    V = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(-1, 3)
-    rho = F.sum(1) * dv ** 3
-    U = (F @ V) * dv ** 3 / rho[:, None]
-    T = ((F * (V * V).sum(1)).sum(1) * dv ** 3 / rho - (U * U).sum(1)) / 3.0
+    if dim == 1:
+        V = x[:, None]
+    else:
+        V = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(-1, 3)
+    rho = F.sum(1) * dv ** dim
+    U = (F @ V) * dv ** dim / rho[:, None]
+    T = ((F * (V * V).sum(1)).sum(1) * dv ** dim / rho - (U * U).sum(1)) / dim
     return rho, T, cycles, r, dt
 
 
 def order_workload(args):
-    """Section 4.1's order study on the BGK heat slab (16^3 velocities on
-    [-6, 6]^3): L2 errors err = sqrt(dx sum (m_j - m_ref_j)^2) of the cell
-    averages of rho and T for dx = 1/16 ... 1/128, first and second order,
-    against a 1024-cell second-order solution, at eps = 1 and 0.1."""
+    """Section 4.1's order study on the BGK heat slab: the 1D1V model (50
+    velocities on [-6, 6], nu = 1; --order-d 3: 16^3 velocities on [-6, 6]^3):
+    L2 errors err = sqrt(dx sum (m_j - m_ref_j)^2) of the cell averages of rho
+    and T for dx = 1/16 ... 1/128, first and second order, against a 1024-cell
+    second-order solution, at eps = 1 and 0.1."""
     import numpy as np
 
+    dim = args.order_d
+    n = 50 if dim == 1 else 16
     out = {}
     for eps in (1.0, 0.1):
-        rr, Tr, cyc, res, dt = _bgk_slab_averages(16, 6.0, 1024, eps, 2)
+        rr, Tr, cyc, res, dt = _bgk_slab_averages(n, 6.0, 1024, eps, 2, dim=dim)
         print(f"# order study eps {eps}: reference 1024 cells, {cyc} V-cycles, {dt:.1f} s", flush=True)
         runs = {"reference": {"cells": 1024, "vcycles": cyc, "residual": res, "seconds": dt}}
         for order in (1, 2):
             rows, prev = [], None
             for nx in (16, 32, 64, 128):
-                rho, T, cyc, res, dt = _bgk_slab_averages(16, 6.0, nx, eps, order)
+                rho, T, cyc, res, dt = _bgk_slab_averages(n, 6.0, nx, eps, order, dim=dim)
                 k = 1024 // nx
                 er = float(np.sqrt(np.sum((rho - rr.reshape(nx, k).mean(1)) ** 2) / nx))
                 eT = float(np.sqrt(np.sum((T - Tr.reshape(nx, k).mean(1)) ** 2) / nx))
@@ -389,7 +402,7 @@ def order_workload(args):
                 prev = (er, eT)
             runs[f"order{order}"] = rows
         out[f"eps={eps}"] = runs
-    return {"workload": "order", "data": "synthetic", "dtype": "f64", "runs": out}
+    return {"workload": "order", "velocity_dims": dim, "N": n, "data": "synthetic", "dtype": "f64", "runs": out}
 
 
 def _cavity_run(n, l, M, nr, nx, eps, lid, tol, max_iters, max_seconds, label, method="sgs", coarsest=5, order=1,
@@ -672,25 +685,26 @@ def shock_workload(args, tol=1e-8):
     residual tol.  batch16: 16 instances, Mach = linspace(1.5, 2.5), eps cycling
     1, 0.1, 0.01, M = 128, n_rho = 16, in one slab (one work-group per instance
     in each scan), for a bounded time, by SGS iterations and by replays of a
-    captured 3-level V-cycle."""
+    captured 3-level V-cycle; and the 16 instances at Mach = linspace(2, 4) on
+    the wider box [-16, 16]^3, by SGS iterations."""
     import numpy as np
     import torch
 
     import paper_2409_01910_amd as bz
     import synth
 
-    def build(machs_eps, nt, nph, nr):
+    def build(machs_eps, nt, nph, nr, L=8.0):
         ups = [synth.RH_states(m) for m, _ in machs_eps]
         shift = float(np.mean([0.5 * (u[1] + d[1]) for u, d in ups]))
-        ctx = bz.Context(N=32, L=8.0, n_theta=nt, n_phi=nph, n_rho=nr, v1_shift=shift)
+        ctx = bz.Context(N=32, L=L, n_theta=nt, n_phi=nph, n_rho=nr, v1_shift=shift)
         fs, inst = [], []
         dx = 40.0 / 128
         for (mach, eps) in machs_eps:
-            f0, up, down = synth.shock_step(mach, 128, 32, 8.0, v1_shift=shift)
+            f0, up, down = synth.shock_step(mach, 128, 32, L, v1_shift=shift)
             fs.append(f0)
             inst.append(dict(nx=128, eps=eps, xL=-20.0, xR=20.0, bc_L="inflow", bc_R="inflow", rho_L=up[0],
                              rho_R=down[0], T_L=up[2], T_R=down[2], U_L=(up[1], 0, 0), U_R=(down[1], 0, 0),
-                             mass=dx * 0.5 ** 3 * f0.sum()))
+                             mass=dx * (2.0 * L / 32) ** 3 * f0.sum()))
         f = torch.from_numpy(np.concatenate(fs)).cuda().contiguous()
         slab = bz.Slab(ctx, inst, f, collision="binary_conserve", tol=1e-8, max_iter=100)
         return ctx, slab, shift
@@ -738,6 +752,15 @@ def shock_workload(args, tol=1e-8):
     r = run(slab, 90.0, "batch16 mg graph", graph=graph)
     out["batch16_M128_mg_graph"] = dict(r, v1_shift=shift, levels=3)
     graph.close()
+    slab.close()
+    ctx.close()
+    # Mach 2 to 4 needs a wider box: 32^3 on [-16, 16]^3 (dv = 1) holds the
+    # Mach-4 downstream Maxwellian (T = 5.9) within the support radius
+    batch = synth.shock_instances(16, mach=(2.0, 4.0))
+    ctx, slab, shift = build(batch, 8, 16, 16, L=16.0)
+    r = run(slab, 90.0, "batch16 mach 2-4")
+    out["batch16_M128_mach2to4_L16"] = dict(r, v1_shift=shift, L=16.0,
+                                            instances=[{"mach": m, "eps": e} for m, e in batch])
     slab.close()
     ctx.close()
     return {"metric": "time to outer residual 1e-8, normal shock (128 cells, 32^3, inflow both ends), plain SGS-PFP",
@@ -862,6 +885,7 @@ def main():
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-start time-to-residual runs")
     ap.add_argument("--study-cells", type=int, default=256, help="bgk-study: cells of the slab")
     ap.add_argument("--study-d", type=int, default=1, choices=[1, 3], help="bgk-study: velocity dimensions")
+    ap.add_argument("--order-d", type=int, default=1, choices=[1, 3], help="order: velocity dimensions")
     ap.add_argument("--study-n", type=int, default=0, help="bgk-study: velocity nodes per axis (50 in 1D, 16 in 3D)")
     ap.add_argument("--study-cap", type=float, default=20.0, help="bgk-study: seconds per run at most")
     ap.add_argument("--workload", choices=["batched-q", "slab", "warmstart", "shock", "order", "cavity", "plates",
