@@ -38,7 +38,9 @@ typedef enum {
   BZ_EINVAL = 1,       /* bad argument or shape */
   BZ_ENOMEM = 2,       /* device allocation of workspace failed */
   BZ_EHIP = 3,         /* a HIP runtime call failed */
-  BZ_EUNSUPPORTED = 4  /* valid request this build does not implement */
+  BZ_EUNSUPPORTED = 4, /* valid request this build does not implement */
+  BZ_ENUMERIC = 5      /* strict mode (bz_set_strict): the call finished and filled its
+                          outputs, but a result it returns is not finite */
 } bz_status;
 
 typedef enum { BZ_FP64 = 0, BZ_FP32 = 1 } bz_precision;
@@ -236,6 +238,14 @@ bz_status bz_get_plan(bz_ctx* ctx, bz_plan* plan);
 bz_status bz_tune(bz_ctx* ctx, const double* f, int64_t batch, uint32_t flags, int reps, bz_tune_report* report,
                   void* stream);
 
+/* bz_eval_Q_strided: bz_eval_Q on fields whose rows are ldf (input) and ldq
+ * (output) doubles apart (ldf, ldq >= K; a row holds one cell's K values): a
+ * batch that is a view into a larger array.  Rows of other strides are packed
+ * into and unpacked from contiguous device buffers (stream-ordered
+ * allocations), one extra pass each way; with ldf = ldq = K it is bz_eval_Q. */
+bz_status bz_eval_Q_strided(bz_ctx* ctx, const double* f, int64_t ldf, double* Q, int64_t ldq, int64_t batch,
+                            uint32_t flags, double* theta, void* stream);
+
 /* bz_maxwellian: discrete Maxwellian of each cell (eqs. discrete_conservation,
  * discrete_Gaussian; Newton's method, Section 2.2).
  *   f [batch][K] in;  theta [batch][5] out (alpha, beta, gamma);
@@ -344,6 +354,29 @@ bz_status bz_mlp_train_step(bz_mlp* mlp, const float* X, const float* T, int64_t
                             void* stream);
 bz_status bz_mlp_features(bz_ctx* ctx, const double* inflow_r, const double* theta, const double* eps, double dx,
                           float* X, int64_t batch, void* stream);
+
+/* bz_cell_fixed_point_ex: bz_cell_fixed_point with the cell update's
+ * remaining inputs given per cell:
+ *   nu  [batch] device, nullable: the penalty frequency of eq. Pf used both in
+ *       P = Q - nu (M - f_old) and in the visit (NULL: the matched frequency of
+ *       the Maxwellian, as bz_cell_fixed_point);
+ *   dxs [batch] device, nullable: each cell's width (NULL: dx for every cell);
+ *   g0  [batch][K] device, nullable: the initial guesses (NULL: f_old); g may
+ *       alias g0 but not f_old. */
+bz_status bz_cell_fixed_point_ex(bz_ctx* ctx, const double* f_old, const double* inflow_r, const double* eps,
+                                 const double* nu, double dx, const double* dxs, const double* g0, double* g,
+                                 int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, void* stream);
+
+/* Strict mode (off by default).  Numerical events never fail a call by
+ * themselves; with strict != 0, a call that synchronises with the host and
+ * returns residuals (bz_sgs_sweep, bz_multigrid_vcycle, bz_outer_residual and
+ * the bz_cavity_* sweeps, V-cycles and residual) returns BZ_ENUMERIC after
+ * filling its outputs when one of them is not finite.  bz_cell_check
+ * synchronises on `stream`, counts the cells of a cell call's statistics
+ * (device [batch]) whose visit ended non-finite (status 2) into *n_bad (host,
+ * nullable), and in strict mode returns BZ_ENUMERIC when there is one. */
+bz_status bz_set_strict(bz_ctx* ctx, int strict);
+bz_status bz_cell_check(bz_ctx* ctx, const bz_cell_stats* stats, int64_t batch, int64_t* n_bad, void* stream);
 
 /* bz_cell_fixed_point_learned: bz_cell_fixed_point with a second candidate
  * initial guess g^0 = M[f_old] + scale * MLP(features) (BF16 inference); each

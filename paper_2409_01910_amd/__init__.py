@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbz.so")
 
 BZ_FP64, BZ_FP32 = 0, 1
+BZ_ENUMERIC = 5
 BZ_METHOD_SIGMA, BZ_METHOD_CARLEMAN = 0, 1
 BZ_Q_CORRECTED = 1
 BZ_Q_MASS = 2
@@ -38,7 +39,8 @@ EXPORTED = [
     "bz_graph_capture_sweeps", "bz_graph_capture_vcycles", "bz_graph_launch", "bz_graph_destroy",
     "bz_cavity_create", "bz_cavity_destroy", "bz_cavity_sweep", "bz_cavity_residual", "bz_cavity_vcycle",
     "bz_slab_inflow", "bz_ws_attach", "bz_set_plan", "bz_get_plan", "bz_tune",
-    "bz_cavity_inflow", "bz_cavity_ws_attach",
+    "bz_cavity_inflow", "bz_cavity_ws_attach", "bz_eval_Q_strided", "bz_cell_fixed_point_ex", "bz_set_strict",
+    "bz_cell_check",
 ]
 
 
@@ -135,6 +137,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bz_workspace_bytes.restype = ctypes.c_size_t
     lib.bz_eval_Q.argtypes = [P, P, P, I64, U32, P, P]
     lib.bz_eval_Q_noalloc.argtypes = [P, P, P, I64, U32, P, P]
+    lib.bz_eval_Q_strided.argtypes = [P, P, I64, P, I64, I64, U32, P, P]
+    lib.bz_cell_fixed_point_ex.argtypes = [P, P, P, P, P, D, P, P, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
+    lib.bz_set_strict.argtypes = [P, ctypes.c_int]
+    lib.bz_cell_check.argtypes = [P, P, I64, ctypes.POINTER(I64), P]
     lib.bz_maxwellian.argtypes = [P, P, P, P, P, I64, P]
     lib.bz_cell_solve.argtypes = [P, P, P, P, D, P, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
     lib.bz_cell_fixed_point.argtypes = [P, P, P, P, D, P, I64, ctypes.POINTER(bz_solve_opts), P, P]
@@ -192,6 +198,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 class BZError(RuntimeError):
     pass
+
+
+class BZNumericError(BZError):
+    """BZ_ENUMERIC: strict mode found a non-finite result (the call's outputs are filled)."""
 
 
 def _ptr(t):
@@ -273,7 +283,8 @@ class Context:
         if st != 0:
             buf = ctypes.create_string_buffer(512)
             self.lib.bz_last_error(self.h, buf, 512)
-            raise BZError(f"{what}: {self.lib.bz_status_str(st).decode()}: {buf.value.decode()}")
+            cls = BZNumericError if st == BZ_ENUMERIC else BZError
+            raise cls(f"{what}: {self.lib.bz_status_str(st).decode()}: {buf.value.decode()}")
 
     def _field(self, t, name):
         import torch
@@ -297,6 +308,40 @@ class Context:
         st = self.lib.bz_eval_Q(self.h, _ptr(f), _ptr(Q), B, flags, _ptr(theta), _stream())
         self._check(st, "bz_eval_Q")
         return Q
+
+    def eval_Q_strided(self, f, out, corrected: bool = True, theta=None, conserve: str | None = None):
+        """bz_eval_Q_strided: f and out are float64 device views [batch, K] with
+        unit stride along K and row strides >= K (e.g. every other row of a
+        larger array)."""
+        import torch
+
+        for t, n in ((f, "f"), (out, "out")):
+            if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2
+                    or t.shape[1] != self.K or t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < self.K)
+                    or t.device != f.device):
+                raise BZError(f"{n} must be a float64 device view [batch, K] with unit inner stride")
+        B = f.shape[0]
+        if out.shape[0] != B:
+            raise BZError("out must have the batch of f")
+        _arg(theta, "theta", B * (self.d + 2), device=f.device, optional=True)
+        flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
+        ldf = f.stride(0) if B > 1 else self.K
+        ldq = out.stride(0) if B > 1 else self.K
+        st = self.lib.bz_eval_Q_strided(self.h, _ptr(f), ldf, _ptr(out), ldq, B, flags, _ptr(theta), _stream())
+        self._check(st, "bz_eval_Q_strided")
+        return out
+
+    def set_strict(self, on: bool = True):
+        """bz_set_strict: calls that return residuals raise BZNumericError on a non-finite one."""
+        self._check(self.lib.bz_set_strict(self.h, 1 if on else 0), "bz_set_strict")
+
+    def cell_check(self, stats):
+        """bz_cell_check: cells of a cell call's statistics that ended non-finite
+        (synchronises; raises BZNumericError in strict mode when there is one)."""
+        n = ctypes.c_int64(0)
+        B = stats.numel() * stats.element_size() // ctypes.sizeof(bz_cell_stats)
+        self._check(self.lib.bz_cell_check(self.h, _ptr(stats), B, ctypes.byref(n), _stream()), "bz_cell_check")
+        return n.value
 
     def eval_Q_noalloc(self, f, out, corrected: bool = True, theta=None, conserve: str | None = None):
         """bz_eval_Q_noalloc: the collision term into the caller's ``out`` with no
@@ -369,6 +414,26 @@ class Context:
         st = self.lib.bz_cell_fixed_point(self.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), float(dx), _ptr(g), B,
                                           ctypes.byref(o), _ptr(stats), _stream())
         self._check(st, "bz_cell_fixed_point")
+        return g, stats
+
+    def cell_fixed_point_ex(self, f_old, inflow_r, eps, dx=0.0, nu=None, dxs=None, g0=None, mode="pfp", tol=1e-8,
+                            max_iter=100, fixed_iters=0, out=None, fallback="fp"):
+        """bz_cell_fixed_point_ex: the cell update with optional per-cell penalty
+        frequency nu [B], per-cell widths dxs [B] and initial guesses g0 [B, K]."""
+        import torch
+
+        B = self._field(f_old, "f_old")
+        _arg(inflow_r, "inflow_r", f_old.numel(), device=f_old.device)
+        _arg(eps, "eps", B, device=f_old.device)
+        _arg(nu, "nu", B, device=f_old.device, optional=True)
+        _arg(dxs, "dxs", B, device=f_old.device, optional=True)
+        _arg(g0, "g0", f_old.numel(), device=f_old.device, optional=True)
+        g = torch.empty_like(f_old) if out is None else _arg(out, "out", f_old.numel(), device=f_old.device)
+        stats = self._stats_tensor(B, f_old.device)
+        o = self._opts(mode, tol, max_iter, fixed_iters, fallback)
+        st = self.lib.bz_cell_fixed_point_ex(self.h, _ptr(f_old), _ptr(inflow_r), _ptr(eps), _ptr(nu), float(dx),
+                                             _ptr(dxs), _ptr(g0), _ptr(g), B, ctypes.byref(o), _ptr(stats), _stream())
+        self._check(st, "bz_cell_fixed_point_ex")
         return g, stats
 
     def cell_fixed_point_learned(self, mlp, f_old, inflow_r, eps, dx, mode="pfp", tol=1e-8, max_iter=100,

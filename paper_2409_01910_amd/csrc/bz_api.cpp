@@ -1,6 +1,7 @@
 // C ABI entry points: validation, context lifetime, workspace.
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <string>
 
 #include "bz_internal.hpp"
@@ -56,6 +57,7 @@ const char* bz_status_str(bz_status s) {
     case BZ_ENOMEM: return "out of device memory";
     case BZ_EHIP: return "HIP runtime error";
     case BZ_EUNSUPPORTED: return "unsupported";
+    case BZ_ENUMERIC: return "non-finite result (strict mode)";
   }
   return "unknown status";
 }
@@ -181,6 +183,13 @@ bz_status check_eval_q_args(bz_ctx* ctx, const double* f, const double* Q, int64
   return BZ_OK;
 }
 
+bz_status strict_check(bz_ctx* ctx, const double* vals, int64_t n) {
+  if (!ctx->strict || !vals) return BZ_OK;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(vals[i])) return set_err(ctx, BZ_ENUMERIC, "a returned residual is not finite");
+  return BZ_OK;
+}
+
 }  // namespace bz
 
 extern "C" {
@@ -204,6 +213,38 @@ bz_status bz_eval_Q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, uint
   if (s == BZ_OK)
     s = (flags & BZ_Q_CONSERVE) ? bz::conserve_project(ctx, Q, th, batch, st) : bz::mass_project(ctx, Q, th, batch, st);
   if (!theta) (void)hipFreeAsync(th, st);
+  return s;
+}
+
+bz_status bz_eval_Q_strided(bz_ctx* ctx, const double* f, int64_t ldf, double* Q, int64_t ldq, int64_t batch,
+                            uint32_t flags, double* theta, void* stream) {
+  bz_status cs = bz::check_eval_q_args(ctx, f, Q, batch, flags, theta);
+  if (cs != BZ_OK) return cs;
+  const int64_t K = ctx->K;
+  if (ldf < K || ldq < K) return set_err(ctx, BZ_EINVAL, "row strides must be >= K");
+  if (ldf == K && ldq == K) return bz_eval_Q(ctx, f, Q, batch, flags, theta, stream);
+  if (batch == 0) return BZ_OK;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t row = (size_t)K * sizeof(double), bytes = row * (size_t)batch;
+  double *fp = const_cast<double*>(f), *qp = Q;
+  hipError_t e = hipSuccess;
+  if (ldf != K && (e = hipMallocAsync((void**)&fp, bytes, st)) != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
+  if (ldq != K && (e = hipMallocAsync((void**)&qp, bytes, st)) != hipSuccess) {
+    if (fp != f) (void)hipFreeAsync(fp, st);
+    return bz::hip_err(ctx, e, "hipMallocAsync");
+  }
+  bz_status s = BZ_OK;
+  if (fp != f && (e = hipMemcpy2DAsync(fp, row, f, (size_t)ldf * sizeof(double), row, (size_t)batch,
+                                       hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    s = bz::hip_err(ctx, e, "pack f");
+  if (s == BZ_OK) s = bz_eval_Q(ctx, fp, qp, batch, flags, theta, stream);
+  if (s == BZ_OK && qp != Q &&
+      (e = hipMemcpy2DAsync(Q, (size_t)ldq * sizeof(double), qp, row, row, (size_t)batch, hipMemcpyDeviceToDevice,
+                            st)) != hipSuccess)
+    s = bz::hip_err(ctx, e, "unpack Q");
+  if (fp != f) (void)hipFreeAsync(fp, st);
+  if (qp != Q) (void)hipFreeAsync(qp, st);
   return s;
 }
 
@@ -273,6 +314,60 @@ bz_status bz_cell_fixed_point(bz_ctx* ctx, const double* f_old, const double* in
   if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, f_old, g, batch, opts, stats, st);
   (void)hipFreeAsync(buf, st);
   return s;
+}
+
+bz_status bz_cell_fixed_point_ex(bz_ctx* ctx, const double* f_old, const double* inflow_r, const double* eps,
+                                 const double* nu_in, double dx, const double* dxs, const double* g0, double* g,
+                                 int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, void* stream) {
+  if (!ctx) return BZ_EINVAL;
+  if (ctx->d != 3) return set_err(ctx, BZ_EUNSUPPORTED, "this call needs d = 3");
+  if (batch < 0) return set_err(ctx, BZ_EINVAL, "batch < 0");
+  bz_status s = check_opts(ctx, opts);
+  if (s != BZ_OK) return s;
+  if (!dxs && (!(dx > 0) || !std::isfinite(dx))) return set_err(ctx, BZ_EINVAL, "dx must be > 0");
+  if (batch == 0) return BZ_OK;
+  if (!f_old || !inflow_r || !eps || !g) return set_err(ctx, BZ_EINVAL, "NULL buffer");
+  if (g == f_old) return set_err(ctx, BZ_EINVAL, "g must not alias f_old");
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t K = (size_t)ctx->K;
+  double* buf = nullptr;
+  const size_t bytes = (size_t)batch * (2 * K + 6) * sizeof(double);
+  hipError_t e = hipMallocAsync((void**)&buf, bytes, st);
+  if (e != hipSuccess) return bz::hip_err(ctx, e, "hipMallocAsync");
+  double* Q = buf;
+  double* r = Q + batch * K;
+  double* theta = r + batch * K;
+  double* nu = theta + batch * 5;
+  s = bz::eval_q(ctx, f_old, Q, batch, true, theta, st);
+  if (s == BZ_OK) s = bz::mass_project(ctx, Q, theta, batch, st);
+  if (s == BZ_OK) s = bz::penalty_rhs(ctx, f_old, Q, theta, inflow_r, eps, r, nu, batch, st, nu_in);
+  if (s == BZ_OK) s = bz::cell_solve(ctx, r, nu, eps, dx, g0 ? g0 : f_old, g, batch, opts, stats, st, nullptr, dxs);
+  (void)hipFreeAsync(buf, st);
+  return s;
+}
+
+bz_status bz_set_strict(bz_ctx* ctx, int strict) {
+  if (!ctx) return BZ_EINVAL;
+  ctx->strict = strict != 0;
+  return BZ_OK;
+}
+
+bz_status bz_cell_check(bz_ctx* ctx, const bz_cell_stats* stats, int64_t batch, int64_t* n_bad, void* stream) {
+  if (!ctx || batch < 0 || (batch > 0 && !stats)) return BZ_EINVAL;
+  if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
+  std::vector<bz_cell_stats> h((size_t)batch);
+  if (batch > 0) {
+    hipError_t e = hipMemcpyAsync(h.data(), stats, sizeof(bz_cell_stats) * (size_t)batch, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return bz::hip_err(ctx, e, "reading cell statistics");
+  }
+  int64_t bad = 0;
+  for (const bz_cell_stats& c : h) bad += c.status == 2 ? 1 : 0;
+  if (n_bad) *n_bad = bad;
+  if (ctx->strict && bad > 0) return set_err(ctx, BZ_ENUMERIC, std::to_string(bad) + " cells ended non-finite");
+  return BZ_OK;
 }
 
 bz_status bz_cell_fixed_point_learned(bz_ctx* ctx, bz_mlp* mlp, const double* f_old, const double* inflow_r,

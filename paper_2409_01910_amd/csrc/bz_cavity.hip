@@ -1043,7 +1043,8 @@ bz_status bz_cavity_sweep(bz_ctx* ctx, bz_cavity* cv, int n_iters, double* resid
     bz_status s = bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, st);
     if (s != BZ_OK) return s;
   }
-  return bz::read_stats(ctx, cv, stats, n_iters, st);
+  bz_status s = bz::read_stats(ctx, cv, stats, n_iters, st);
+  return s != BZ_OK ? s : bz::strict_check(ctx, residual_out, residual_out ? 1 : 0);
 }
 
 bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int n_cycles, double* residual_out,
@@ -1073,7 +1074,8 @@ bz_status bz_cavity_vcycle(bz_ctx* ctx, bz_cavity* cv, const bz_mg_opts* o, int 
     bz_status s = bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, st);
     if (s != BZ_OK) return s;
   }
-  return bz::read_stats(ctx, cv, stats, n_cycles, st);
+  bz_status s = bz::read_stats(ctx, cv, stats, n_cycles, st);
+  return s != BZ_OK ? s : bz::strict_check(ctx, residual_out, residual_out ? 1 : 0);
 }
 
 bz_status bz_cavity_inflow(bz_ctx* ctx, bz_cavity* cv, double* T_out, void* stream) {
@@ -1103,7 +1105,8 @@ bz_status bz_cavity_ws_attach(bz_cavity* cv, bz_mlp* mlp) {
 bz_status bz_cavity_residual(bz_ctx* ctx, bz_cavity* cv, double* residual_out, void* stream) {
   if (!ctx || !cv || cv->ctx != ctx || !residual_out) return BZ_EINVAL;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
-  return bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, (hipStream_t)stream);
+  bz_status s = bz::cav_residual(ctx, cv, cv->lv[0], nullptr, residual_out, (hipStream_t)stream);
+  return s != BZ_OK ? s : bz::strict_check(ctx, residual_out, 1);
 }
 
 }  // extern "C"

@@ -78,11 +78,13 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_solve(const double* __res
                                                              const double* g0, double* g, SolveArgs opt,
                                                              bz_cell_stats* __restrict__ stats,
                                                              const double* __restrict__ nodes, double w,
-                                                             const double* __restrict__ g0b) {
+                                                             const double* __restrict__ g0b,
+                                                             const double* __restrict__ dxs) {
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
   RPlain rf{r + (size_t)b * K};
-  const SolveOut o = solve_cell_block<N, kCellThreads>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dx, opt, nodes, w,
+  const double dxb = dxs ? dxs[b] : dx;
+  const SolveOut o = solve_cell_block<N, kCellThreads>(rf, g0 + (size_t)b * K, g + (size_t)b * K, nu[b] / eps[b], dxb, opt, nodes, w,
                                          g0b ? g0b + (size_t)b * K : nullptr);
   if (stats && threadIdx.x == 0) {
     bz_cell_stats st;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(kCellThreads) void k_penalty_rhs(const double* __re
                                                               const double* __restrict__ eps, double* __restrict__ r,
                                                               double* __restrict__ nu_out,
                                                               const double* __restrict__ nodes, double w, double gam,
-                                                              double gfac) {
+                                                              double gfac, const double* __restrict__ nu_in) {
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
   __shared__ double s_E[3][N];
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(kCellThreads) void k_penalty_rhs(const double* __re
     double s[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a)
       for (int i = 0; i < N; ++i) s[a] += s_E[a][i];
-    s_nu = penalty_nu(w * exp(th[0]) * s[0] * s[1] * s[2], th[4], gam, gfac);
+    s_nu = nu_in ? nu_in[b] : penalty_nu(w * exp(th[0]) * s[0] * s[1] * s[2], th[4], gam, gfac);
     nu_out[b] = s_nu;
   }
   __syncthreads();
@@ -255,12 +257,12 @@ bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int
 
 bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
                      double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
-                     const double* g0b) {
+                     const double* g0b, const double* dxs) {
   if (batch == 0) return BZ_OK;
   SolveArgs a{opts->mode, opts->tol, opts->max_iter, opts->fixed_iters, ctx->p.v1_shift,
               opts->fallback == BZ_FALLBACK_RELAX ? 1 : 0};
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_cell_solve<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, r,
-                                           nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b));
+                                           nu, eps, dx, g0, g, a, stats, ctx->d_nodes, ctx->w, g0b, dxs));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }
@@ -282,11 +284,11 @@ bz_status conserve_project(bz_ctx* ctx, double* Q, const double* theta, int64_t 
 }
 
 bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const double* theta, const double* inflow,
-                      const double* eps, double* r, double* nu, int64_t batch, hipStream_t st) {
+                      const double* eps, double* r, double* nu, int64_t batch, hipStream_t st, const double* nu_in) {
   if (batch == 0) return BZ_OK;
   BZ_DISPATCH_N(ctx->N, hipLaunchKernelGGL((k_penalty_rhs<NN_>), dim3((unsigned)batch), dim3(kCellThreads), 0, st, f,
                                            Q, theta, inflow, eps, r, nu, ctx->d_nodes, ctx->w, ctx->p.gamma,
-                                           ctx->nu_gfac));
+                                           ctx->nu_gfac, nu_in));
   BZ_HIP(hipGetLastError());
   return BZ_OK;
 }

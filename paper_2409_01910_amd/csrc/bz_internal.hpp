@@ -16,7 +16,8 @@ struct bz_ctx {
   int n_theta = 0, n_phi = 0, n_rho = 0, n_pairs = 0;
   double dv = 0, w = 0, R = 0, Rg = 0;
   double nu_gfac = 1.0;  // 4^{gamma/2} Gamma((3 + gamma)/2) / Gamma(3/2), for the penalty frequency
-  int d = 3;             // velocity dimension (2 or 3)
+  int d = 3;             // velocity dimension (1, 2 or 3)
+  bool strict = false;   // bz_set_strict
   std::string err;
 
   // host copies of the tables (FP64)
@@ -131,7 +132,7 @@ bz_status maxwellian(bz_ctx* ctx, const double* f, double* theta, double* M, int
                      hipStream_t st);
 bz_status cell_solve(bz_ctx* ctx, const double* r, const double* nu, const double* eps, double dx, const double* g0,
                      double* g, int64_t batch, const bz_solve_opts* opts, bz_cell_stats* stats, hipStream_t st,
-                     const double* g0b = nullptr);
+                     const double* g0b = nullptr, const double* dxs = nullptr);
 // learned initial guesses g0 [batch][K] (bz_mlp.hip)
 bz_status learned_guess(bz_ctx* ctx, bz_mlp* mp, const double* inflow_r, const double* theta, const double* eps,
                         double dx, double* g0, int64_t batch, hipStream_t st);
@@ -160,6 +161,9 @@ bz_status mass_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batc
 bz_status conserve_project(bz_ctx* ctx, double* Q, const double* theta, int64_t batch, hipStream_t st);
 // r = inflow - (Q - nu (M_theta - f)) / eps, nu = 4 pi rho(theta); writes nu
 bz_status penalty_rhs(bz_ctx* ctx, const double* f, const double* Q, const double* theta, const double* inflow,
-                      const double* eps, double* r, double* nu, int64_t batch, hipStream_t st);
+                      const double* eps, double* r, double* nu, int64_t batch, hipStream_t st,
+                      const double* nu_in = nullptr);
+// strict mode: BZ_ENUMERIC when one of the n returned values is not finite
+bz_status strict_check(bz_ctx* ctx, const double* vals, int64_t n);
 
 }  // namespace bz

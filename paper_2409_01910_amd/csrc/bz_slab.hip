@@ -1078,7 +1078,10 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
   if (n_iters < 0) return set_err(ctx, BZ_EINVAL, "n_iters < 0");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 0, n_iters, nullptr, residual_out, stats, st);
+  if (s->v1) {
+    bz_status e = bz::slab1v_run(ctx, s->v1, s->f, 0, n_iters, nullptr, residual_out, stats, st);
+    return e != BZ_OK ? e : bz::strict_check(ctx, residual_out, s->n_inst);
+  }
   if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
     return set_err(ctx, BZ_EHIP, "stats reset");
   bz::Level& L = s->levels[0];
@@ -1093,7 +1096,8 @@ bz_status bz_sgs_sweep(bz_ctx* ctx, bz_slab* s, int n_iters, double* residual_ou
     if (e != BZ_OK) return e;
     for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
   }
-  return bz::read_stats(ctx, s, stats, n_iters, st);
+  bz_status e = bz::read_stats(ctx, s, stats, n_iters, st);
+  return e != BZ_OK ? e : bz::strict_check(ctx, residual_out, s->n_inst);
 }
 
 bz_status bz_slab_inflow(bz_ctx* ctx, bz_slab* s, double* out, void* stream) {
@@ -1139,14 +1143,17 @@ bz_status bz_ws_attach(bz_slab* s, bz_mlp* mlp) {
 bz_status bz_outer_residual(bz_ctx* ctx, bz_slab* s, double* residual_out, void* stream) {
   if (!ctx || !s || s->ctx != ctx || !residual_out) return BZ_EINVAL;
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
-  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 2, 0, nullptr, residual_out, nullptr, (hipStream_t)stream);
+  if (s->v1) {
+    bz_status e = bz::slab1v_run(ctx, s->v1, s->f, 2, 0, nullptr, residual_out, nullptr, (hipStream_t)stream);
+    return e != BZ_OK ? e : bz::strict_check(ctx, residual_out, s->n_inst);
+  }
   bz::Level& L = s->levels[0];
   L.q_valid = false;
   std::vector<double> rn;
   bz_status e = bz::residual(ctx, s, L, false, rn, (hipStream_t)stream);
   if (e != BZ_OK) return e;
   for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
-  return BZ_OK;
+  return bz::strict_check(ctx, residual_out, s->n_inst);
 }
 
 bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int n_cycles, double* residual_out,
@@ -1156,7 +1163,10 @@ bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int 
     return set_err(ctx, BZ_EINVAL, "bad multigrid options");
   if (hipSetDevice(ctx->p.device) != hipSuccess) return set_err(ctx, BZ_EHIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  if (s->v1) return bz::slab1v_run(ctx, s->v1, s->f, 1, n_cycles, o, residual_out, stats, st);
+  if (s->v1) {
+    bz_status e1 = bz::slab1v_run(ctx, s->v1, s->f, 1, n_cycles, o, residual_out, stats, st);
+    return e1 != BZ_OK ? e1 : bz::strict_check(ctx, residual_out, s->n_inst);
+  }
   bz_status e = bz::build_mg(ctx, s, o->coarsest);
   if (e != BZ_OK) return e;
   if (hipMemsetAsync(s->d_stats, 0, sizeof(unsigned long long) * 4, st) != hipSuccess)
@@ -1172,7 +1182,8 @@ bz_status bz_multigrid_vcycle(bz_ctx* ctx, bz_slab* s, const bz_mg_opts* o, int 
     if ((e = bz::residual(ctx, s, L, false, rn, st)) != BZ_OK) return e;
     for (int i = 0; i < s->n_inst; ++i) residual_out[i] = rn[i];
   }
-  return bz::read_stats(ctx, s, stats, n_cycles, st);
+  e = bz::read_stats(ctx, s, stats, n_cycles, st);
+  return e != BZ_OK ? e : bz::strict_check(ctx, residual_out, s->n_inst);
 }
 
 }  // extern "C"
