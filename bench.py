@@ -874,8 +874,9 @@ def main():
                     choices=["all", "fp"] + [f"order{o}_{m}_eps{e}" for o in (1, 2) for m in ("fp", "sgs", "mg", "mg_carleman")
                                        for e in ("1", "0.1", "0.01", "0.001")],
                     help="with --workload plates: run one case only")
-    ap.add_argument("--plan", default="", metavar="W,C",
-                    help="fix the collision launch plan (pair waves, chunk cells) instead of tuning it")
+    ap.add_argument("--plan", default="", metavar="W,C[,A]",
+                    help="fix the collision launch plan (pair waves, chunk cells, held radial nodes) "
+                         "instead of tuning it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     ap.add_argument("--ws-train", type=int, default=24, help="warmstart: training instances")
@@ -972,13 +973,14 @@ def main():
         # launch plan of the collision pipeline, tuned on a sample of the batch
         # (or given: profiler runs fix it so that every traced launch is a timed one)
         if args.plan:
-            w, c = (int(x) for x in args.plan.split(","))
-            ctx.set_plan(w if not carl else 0, c)
+            w, c, a = ([int(x) for x in args.plan.split(",")] + [0])[:3]
+            ctx.set_plan(w if not carl else 0, c, a)
             tuned = {"plan": ctx.get_plan(), "candidates": []}
         else:
             tuned = ctx.tune(f[:min(512, args.batch)].contiguous(), corrected=True, conserve="mass")
         print(f"# {precision} {method} tuned plan {tuned['plan']}: " +
-              ", ".join(f"{c['pair_waves']}/{c['chunk_cells']} {m:.1f} ms" for c, m in tuned["candidates"]),
+              ", ".join(f"{c['pair_waves']}/{c['chunk_cells']}/{c['acc_nodes']} {m:.1f} ms"
+                        for c, m in tuned["candidates"]),
               file=sys.stderr, flush=True)
 
         for i in range(args.warmup):
@@ -1044,7 +1046,8 @@ def main():
                     "kernel_share_of_step": prof["total_ms"] * 1e-3 / elapsed}
         roof["tuned_plan"] = tuned["plan"]
         roof["relaxed_step1_step"] = relax
-        roof["tuner_candidates_ms"] = [[c["pair_waves"], c["chunk_cells"], m] for c, m in tuned["candidates"]]
+        roof["tuner_candidates_ms"] = [[c["pair_waves"], c["chunk_cells"], c["acc_nodes"], m]
+                                       for c, m in tuned["candidates"]]
         return args.steps * args.batch / elapsed, elapsed, dt, roof, ctx.decode_stats(stats)
 
     value, elapsed, dt, roof, st = measure(args.precision, args.method)

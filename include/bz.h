@@ -207,10 +207,18 @@ bz_status bz_eval_Q_noalloc(bz_ctx* ctx, const double* f, double* Q, int64_t bat
  *                block per CU), 4 or 2 (two or four blocks per CU, so that one
  *                block's loads and final reduction overlap another's
  *                transforms); 0 = the default, 8
- *   chunk_cells  cap on the cells of one chunk of the pipeline's workspace; a
- *                small chunk keeps a radial node's z-stage planes in the last-level
- *                cache between the z-stage and the pair kernel; 0 = no cap (a
- *                2 GiB workspace budget decides)
+ *   chunk_cells  cells of one chunk of the pipeline's workspace (fewer when a
+ *                caller-provided workspace holds fewer); a small chunk keeps a
+ *                radial node's z-stage planes in the last-level cache between
+ *                the z-stage and the pair kernel, a large one fills the GPU with
+ *                fewer launches; 0 = as many as an 8 GiB workspace budget holds
+ *   acc_nodes    radial nodes whose accumulated direction-pair planes are held
+ *                in the workspace before one pass applies their axis-0
+ *                transforms and radial weights to the gain spectrum (the sum
+ *                runs in node order either way, so the result does not
+ *                change); more nodes read and write the gain spectrum fewer
+ *                times and take 16 bytes per cell and velocity each; 0 = all
+ *                n_rho nodes (at most n_rho are used)
  * bz_set_plan / bz_get_plan set and read a context's plan (BZ_EINVAL for other
  * values).  bz_tune is the project's autotuner: it times bz_eval_Q(f, batch,
  * flags), reps times after a warm-up, under every candidate plan of the
@@ -224,6 +232,7 @@ bz_status bz_eval_Q_noalloc(bz_ctx* ctx, const double* f, double* Q, int64_t bat
 typedef struct {
   int pair_waves;
   int chunk_cells;
+  int acc_nodes;
 } bz_plan;
 
 typedef struct {

@@ -97,7 +97,7 @@ class bz_mg_opts(ctypes.Structure):
 
 
 class bz_plan(ctypes.Structure):
-    _fields_ = [("pair_waves", ctypes.c_int), ("chunk_cells", ctypes.c_int)]
+    _fields_ = [("pair_waves", ctypes.c_int), ("chunk_cells", ctypes.c_int), ("acc_nodes", ctypes.c_int)]
 
 
 BZ_TUNE_MAX = 16
@@ -125,6 +125,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libbz.so not built at {path}: run __graft_entry__.build()")
+    # torch first (when installed), so that the library binds to the HIP
+    # runtime torch loads and the process holds one runtime, whichever of the
+    # two the caller imports first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I64, D, U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.bz_create.argtypes = [ctypes.POINTER(bz_params), ctypes.POINTER(ctypes.c_void_p)]
@@ -464,15 +471,15 @@ class Context:
                                              _stream()), "bz_mlp_features")
         return X
 
-    def set_plan(self, pair_waves: int = 0, chunk_cells: int = 0):
+    def set_plan(self, pair_waves: int = 0, chunk_cells: int = 0, acc_nodes: int = 0):
         """bz_set_plan: launch plan of the collision pipeline (0 = default)."""
-        p = bz_plan(pair_waves, chunk_cells)
+        p = bz_plan(pair_waves, chunk_cells, acc_nodes)
         self._check(self.lib.bz_set_plan(self.h, ctypes.byref(p)), "bz_set_plan")
 
     def get_plan(self):
         p = bz_plan()
         self._check(self.lib.bz_get_plan(self.h, ctypes.byref(p)), "bz_get_plan")
-        return {"pair_waves": p.pair_waves, "chunk_cells": p.chunk_cells}
+        return {"pair_waves": p.pair_waves, "chunk_cells": p.chunk_cells, "acc_nodes": p.acc_nodes}
 
     def tune(self, f, corrected: bool = True, conserve: str | None = None, reps: int = 2):
         """bz_tune: time bz_eval_Q on f under every candidate plan, keep and cache
@@ -481,8 +488,8 @@ class Context:
         flags = (BZ_Q_CORRECTED if corrected else 0) | {None: 0, "mass": BZ_Q_MASS, "all": BZ_Q_CONSERVE}[conserve]
         rep = bz_tune_report()
         self._check(self.lib.bz_tune(self.h, _ptr(f), B, flags, reps, ctypes.byref(rep), _stream()), "bz_tune")
-        cands = [({"pair_waves": rep.plan[i].pair_waves, "chunk_cells": rep.plan[i].chunk_cells}, rep.ms[i])
-                 for i in range(rep.n)]
+        cands = [({"pair_waves": rep.plan[i].pair_waves, "chunk_cells": rep.plan[i].chunk_cells,
+                   "acc_nodes": rep.plan[i].acc_nodes}, rep.ms[i]) for i in range(rep.n)]
         return {"candidates": cands, "best": rep.best, "plan": cands[rep.best][0]}
 
     def profile_enable(self, on: bool = True):

@@ -60,11 +60,13 @@ struct bz_ctx {
   double prof_flops = 0.0;
 
   // launch plan of the collision pipeline (bz_plan; 0 = default): waves per
-  // block of the N = 32 direction-pair kernel (8) and a cap on the cells of a
-  // chunk (none: the 2 GiB workspace budget decides); set by bz_tune (measured
-  // and cached per discretisation) or bz_set_plan
+  // block of the N = 32 direction-pair kernel (8), the cells of a chunk (as
+  // many as the 8 GiB workspace budget holds) and the radial nodes whose
+  // accumulated planes are held for one column pass (all); set by bz_tune
+  // (measured and cached per discretisation) or bz_set_plan
   int pair_waves = 0;
   int chunk_cap = 0;
+  int acc_nodes = 0;
 
   // workspace (grown on demand, never shrunk until destroy)
   void* ws = nullptr;

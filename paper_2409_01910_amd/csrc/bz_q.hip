@@ -454,7 +454,7 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
   // register left for them): [wave][u1 u2 (m = 15) | u3 u4 (m = 15) | u1 u2
   // (m = 14)][lane], 16-byte pairs
   C* ulast = twl + 32;
-  // the accumulated plane reuses the wave tiles once every wave is done
+  // the waves' partial planes reuse the wave tiles once every wave is done
   T* red = reinterpret_cast<T*>(tiles);
   const int b = blockIdx.x / N, i1 = blockIdx.x % N;
   // wave index made uniform, so that per-item and per-azimuth values load once
@@ -630,48 +630,55 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
       wave_sync();
     }
   }
-  __syncthreads();  // every wave is done with its tile before red overwrites them
-  for (int w2 = 0; w2 < kPair32Waves; ++w2) {
-    if (wv == w2) {
+  // The block's plane is the sum of its waves' partial planes, then a forward
+  // 2D transform (axes 1 and 2).  Each wave stores its partial plane (rows
+  // padded to LD entries) over the tiles, and one wave does each transform
+  // pass with two lanes per row (then per column): lane half h forms
+  // u(n) = x(n) + (-1)^h x(n + 16), times w^n for h = 1, whose 16-point
+  // transform is entries 2j + h.  The transposed plane sits after the partials.
+  __syncthreads();  // every wave is done with its tile before the partials overwrite them
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+  for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          T* dst = red + (rg + 8 * g) * N + kp + 8 * t;
-          *dst = (w2 == 0 ? T(0) : *dst) + acc[4 * g + t];
-        }
+    for (int t = 0; t < 4; ++t) red[wv * (N * LD) + (rg + 8 * g) * LD + kp + 8 * t] = acc[4 * g + t];
+  __syncthreads();
+  C* trans = tiles + kPair32Waves * (N * LD) / 2;
+  const int hh = ln >> 5, lq = ln & 31;
+  const T sg = hh ? T(-1) : T(1);
+  if (wv == 0) {
+    // rows: real input, summed over the waves in wave order
+    T re[16], im[16];
+#pragma unroll
+    for (int n = 0; n < 16; ++n) {
+      T x0 = T(0), x1 = T(0);
+      for (int w = 0; w < kPair32Waves; ++w) {
+        x0 += red[w * (N * LD) + lq * LD + n];
+        x1 += red[w * (N * LD) + lq * LD + n + 16];
+      }
+      const T u = x0 + sg * x1;
+      re[n] = hh ? u * T(kTw32.c[n]) : u;
+      im[n] = hh ? -u * T(kTw32.s[n]) : T(0);
     }
-    __syncthreads();
-  }
-  // forward 2D transform of the accumulated real plane (axes 1 and 2), through
-  // a transpose buffer placed after red
-  C* trans = tiles + NN / 2;
-  if (threadIdx.x < N) {
-    const int row = threadIdx.x;
-    T re[N], im[N];
+    fft_reg<T, 16, -1>(re, im);
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
-      re[l] = red[row * N + l];
-      im[l] = T(0);
-    }
-    fft_reg<T, N, -1>(re, im);
-#pragma unroll
-    for (int l = 0; l < N; ++l) trans[row * LD + l] = C{re[l], im[l]};
+    for (int j = 0; j < 16; ++j) trans[lq * LD + 2 * j + hh] = C{re[j], im[j]};
   }
   __syncthreads();
-  if (threadIdx.x < N) {
-    const int col = threadIdx.x;
-    T re[N], im[N];
+  if (wv == 0) {
+    // columns
+    T re[16], im[16];
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
-      const C x = trans[l * LD + col];
-      re[l] = x.x;
-      im[l] = x.y;
+    for (int n = 0; n < 16; ++n) {
+      const C x0 = trans[n * LD + lq], x1 = trans[(n + 16) * LD + lq];
+      const T ur = x0.x + sg * x1.x, ui = x0.y + sg * x1.y;
+      const T wr = hh ? T(kTw32.c[n]) : T(1), wi = hh ? -T(kTw32.s[n]) : T(0);
+      re[n] = ur * wr - ui * wi;
+      im[n] = ur * wi + ui * wr;
     }
-    fft_reg<T, N, -1>(re, im);
-    C* dst = Acc + (size_t)b * K + (size_t)i1 * NN + col;
+    fft_reg<T, 16, -1>(re, im);
+    C* dst = Acc + (size_t)b * K + (size_t)i1 * NN + (size_t)hh * N + lq;
 #pragma unroll
-    for (int l = 0; l < N; ++l) dst[(size_t)l * N] = C{re[l], im[l]};
+    for (int j = 0; j < 16; ++j) dst[(size_t)(2 * j) * N] = C{re[j], im[j]};
   }
 }
 
@@ -957,34 +964,62 @@ __global__ __launch_bounds__(256) void k_ccombine(const double* __restrict__ f, 
 }
 
 // ------------------------------------------------------------------ axis-0 forward + radial weight
+// Qh (+)= sum over the nslot held radial nodes s of W_s * DFT_axis0(Acc_s), in
+// node order, so the sum is the same as one launch per node; the accumulator
+// of a column is read and written once per launch instead of once per node.
+// Two lanes share a column (lanes q and q + 32 of a wave, 32 columns per
+// wave), splitting the length-N transform by decimation in frequency: lane
+// half h forms u(n) = x(n) + (-1)^h x(n + N/2), times w^n for h = 1, whose
+// N/2-point transform is X(2j + h).  Both halves load the same addresses in
+// the same instruction, so the HBM traffic is that of one lane per column.
+// At N = 32 in FP64 a lane holds its 16 accumulators and all 32 loads of a
+// node in flight (one wave per SIMD); bounding it to two waves spills and
+// measured no faster.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __restrict__ Acc,
                                               typename V2<T>::type* __restrict__ Qh, int64_t nvol,
-                                              const T* __restrict__ Wr, int first) {
+                                              const T* __restrict__ Wr, int nslot, int64_t slot_stride, int first) {
   using C = typename V2<T>::type;
-  constexpr int K = N * N * N, NN = N * N;
+  constexpr int K = N * N * N, NN = N * N, H = N / 2;
+  constexpr Twiddle<N> tw{};
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nvol * NN) return;
-  const int64_t vol = gid / NN;
-  const int c = (int)(gid % NN);
-  T re[N], im[N];
-  const C* src = Acc + vol * K + c;
+  const int ln = (int)(gid & 63), h = ln >> 5;
+  const int64_t col = (gid >> 6) * 32 + (ln & 31);
+  if (col >= nvol * NN) return;
+  const int64_t vol = col / NN;
+  const int c = (int)(col % NN);
+  const T sg = h ? T(-1) : T(1);
+  C* dst = Qh + vol * K + (size_t)h * NN + c;  // outputs k = 2j + h
+  T oR[H], oI[H];
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    const C v = src[(size_t)l * NN];
-    re[l] = v.x;
-    im[l] = v.y;
+  for (int j = 0; j < H; ++j) {
+    const C o = first ? C{T(0), T(0)} : dst[(size_t)(2 * j) * NN];
+    oR[j] = o.x;
+    oI[j] = o.y;
   }
-  fft_reg<T, N, -1>(re, im);
-  C* dst = Qh + vol * K + c;
+  for (int s = 0; s < nslot; ++s) {
+    T re[H], im[H];
+    const C* src = Acc + s * slot_stride + vol * K + c;
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    const T g = Wr[(size_t)l * NN + c];
-    C o = first ? C{T(0), T(0)} : dst[(size_t)l * NN];
-    o.x += g * re[l];
-    o.y += g * im[l];
-    dst[(size_t)l * NN] = o;
+    for (int n = 0; n < H; ++n) {
+      const C x0 = src[(size_t)n * NN], x1 = src[(size_t)(n + H) * NN];
+      const T ur = x0.x + sg * x1.x, ui = x0.y + sg * x1.y;
+      // w^n = e^{-2 pi i n / N} on the odd half, 1 (exactly) on the even half
+      const T wr = h ? T(tw.c[n]) : T(1), wi = h ? -T(tw.s[n]) : T(0);
+      re[n] = ur * wr - ui * wi;
+      im[n] = ur * wi + ui * wr;
+    }
+    fft_reg<T, H, -1>(re, im);
+    const T* w = Wr + (size_t)s * K + (size_t)h * NN + c;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const T g = w[(size_t)(2 * j) * NN];
+      oR[j] += g * re[j];
+      oI[j] += g * im[j];
+    }
   }
+#pragma unroll
+  for (int j = 0; j < H; ++j) dst[(size_t)(2 * j) * NN] = C{oR[j], oI[j]};
 }
 
 // ------------------------------------------------------------------ gain of the Maxwellian, separable
@@ -1000,137 +1035,136 @@ __global__ __launch_bounds__(256) void k_colw(const typename V2<T>::type* __rest
 //   G_{r,tp}(k_2, k_3) = sum_j 2 w_q D1_{r,q}(k_2) D2_{r,q}(k_3).
 // k_max_sep1 (block per cell and radial node) forms D0 and G; k_max_sep2
 // (block per cell, thread per (k_2, k_3)) sums over r and tp and subtracts
-// Qh_M from the cell's gain spectrum.  Transforms of length N are done as
-// direct sums (N terms per output): a few dozen MFLOP per cell, against the
-// GFLOPs of the direction-pair transforms they replace.
+// Qh_M from the cell's gain spectrum.  The length-N transforms are register
+// FFTs: a wave takes one polar pair and a lane one factor vector (axis 1 of
+// the polar pair, or axis 2 or 3 of one azimuth), forming A and B by one
+// transform, then the transform D of their product; the G sums then use every
+// thread.  A few MFLOP per cell, against the GFLOPs of the direction-pair
+// transforms they replace.
 constexpr int kSepThreads = 256;
-constexpr int kSepJB = 16;  // azimuths per pass
+constexpr int kSepWaves = kSepThreads / 64;  // polar pairs per round
+constexpr int kSepJB = 16;                   // azimuths per pass
 
 template <int N>
-__device__ __forceinline__ double2 sep_tw(const double2* tw, int m, int sign) {
-  const double2 w = tw[m & (N - 1)];
-  return double2{w.x, sign * w.y};
-}
-
-template <int N>
-__global__ __launch_bounds__(kSepThreads) void k_max_sep1(const double* __restrict__ theta,
+__global__ __launch_bounds__(kSepThreads, 2) void k_max_sep1(const double* __restrict__ theta,
                                                           const double* __restrict__ nodes,
                                                           const double2* __restrict__ ph1,
                                                           const double2* __restrict__ ph23,
                                                           const double* __restrict__ pairw, int n_rho, int n_theta,
                                                           int n_phi, double2* __restrict__ D0s,
                                                           double2* __restrict__ Gs) {
-  constexpr int NN = N * N;
+  constexpr int NN = N * N, NV = 2 * kSepJB + 1;
+  constexpr int GPT = NN / kSepThreads > 0 ? NN / kSepThreads : 1;
   const int b = blockIdx.x / n_rho, r = blockIdx.x % n_rho;
   const int half = n_theta / 2, npairs = half * n_phi;
-  __shared__ double2 s_tw[N];                 // e^{2 pi i m / N}
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   __shared__ double2 s_E[3][N];               // Ehat_a
-  __shared__ double2 s_P[2 * kSepJB + 1][N];  // products A B
-  __shared__ double2 s_D[2 * kSepJB + 1][N];  // their transforms
-  __shared__ double s_w[kSepJB];
+  __shared__ double2 s_D[kSepWaves][NV][N];   // the transforms D, per wave and vector
+  __shared__ double s_w[kSepWaves][kSepJB];
   const double* th = theta + (size_t)b * 5;
-  if (threadIdx.x < N) {
-    const double a = 2.0 * kPi * threadIdx.x / N;
-    s_tw[threadIdx.x] = double2{cos(a), sin(a)};
-  }
-  __syncthreads();
-  // Ehat_a(l) = sum_i E_a(x_i) e^{-2 pi i l i / N}, zero at the Nyquist index
-  for (int e = threadIdx.x; e < 3 * N; e += kSepThreads) {
-    const int a = e / N, l = e % N;
-    double re = 0.0, im = 0.0;
-    if (l != N / 2) {
-#pragma unroll 2
-      for (int i = 0; i < N; ++i) {
-        const double x = nodes[i];
-        const double E = exp(th[1 + a] * x - th[4] * x * x);
-        const double2 w = sep_tw<N>(s_tw, l * i, -1);
-        re += E * w.x;
-        im += E * w.y;
-      }
-    }
-    s_E[a][l] = double2{re, im};
-  }
-  __syncthreads();
-  // product of the shifted copies of vector v at node i: A(i) B(i) with
-  // A = IDFT(Ehat phase_A), B = IDFT(Ehat phase_B)
-  auto prod = [&](int a, const double2* pa, const double2* pb, bool conj_b, int i) {
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-#pragma unroll 2
-    for (int l = 0; l < N; ++l) {
-      const double2 E = s_E[a][l], w = sep_tw<N>(s_tw, l * i, 1);
-      const double2 qa = pa[l];
-      const double2 qb = conj_b ? double2{pb[l].x, -pb[l].y} : pb[l];
-      // (E qa) w and (E qb) w
-      const double er = E.x * qa.x - E.y * qa.y, ei = E.x * qa.y + E.y * qa.x;
-      ar += er * w.x - ei * w.y;
-      ai += er * w.y + ei * w.x;
-      const double fr = E.x * qb.x - E.y * qb.y, fi = E.x * qb.y + E.y * qb.x;
-      br += fr * w.x - fi * w.y;
-      bi += fr * w.y + fi * w.x;
-    }
-    return double2{ar * br - ai * bi, ar * bi + ai * br};
-  };
-  for (int tp = 0; tp < half; ++tp) {
-    const int tA = half + tp, tB = half - 1 - tp;
-    const double2* p1A = ph1 + ((size_t)r * n_theta + tA) * N;
-    const double2* p1B = ph1 + ((size_t)r * n_theta + tB) * N;
-    double2 g[NN / kSepThreads > 0 ? NN / kSepThreads : 1];
-    constexpr int GPT = NN / kSepThreads > 0 ? NN / kSepThreads : 1;
+  // Ehat_a = DFT(E_a), zero at the Nyquist index
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    double re[N], im[N];
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) g[u] = double2{0.0, 0.0};
+    for (int i = 0; i < N; ++i) {
+      const double x = nodes[i];
+      re[i] = exp(th[1 + a] * x - th[4] * x * x);
+      im[i] = 0.0;
+    }
+    fft_reg<double, N, -1>(re, im);
+    re[N / 2] = 0.0;
+    im[N / 2] = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) s_E[a][l] = double2{re[l], im[l]};
+  }
+  __syncthreads();
+  for (int tp0 = 0; tp0 < half; tp0 += kSepWaves) {
+    const int ntp = (half - tp0) < kSepWaves ? (half - tp0) : kSepWaves;
     for (int j0 = 0; j0 < n_phi; j0 += kSepJB) {
       const int nj = (n_phi - j0) < kSepJB ? (n_phi - j0) : kSepJB;
-      // vectors: 0 = axis 1 of the polar pair (first pass only), 1 + 2 jl + {0, 1} = axes 2, 3 of azimuth jl
+      // vectors: 0 = axis 1 of the polar pair, 1 + 2 jl + {0, 1} = axes 2, 3 of azimuth jl
       const int nv = 1 + 2 * nj;
+      const int tp = tp0 + wv;
       __syncthreads();
-      for (int e = threadIdx.x; e < nv * N; e += kSepThreads) {
-        const int v = e / N, i = e % N;
-        double2 pr;
+      if (wv < ntp && ln < nv) {
+        const int v = ln;
+        int a;
+        const double2 *pa, *pb;
+        bool conj_b;
         if (v == 0) {
-          pr = prod(0, p1A, p1B, false, i);
+          a = 0;
+          pa = ph1 + ((size_t)r * n_theta + half + tp) * N;
+          pb = ph1 + ((size_t)r * n_theta + half - 1 - tp) * N;
+          conj_b = false;
         } else {
           const int jl = (v - 1) >> 1, ax = (v - 1) & 1;
           const int q = tp * n_phi + j0 + jl;
-          const double2* p = ph23 + (((size_t)r * npairs + q) * 2 + ax) * N;
-          pr = prod(1 + ax, p, p, true, i);
+          a = 1 + ax;
+          pa = pb = ph23 + (((size_t)r * npairs + q) * 2 + ax) * N;
+          conj_b = true;
         }
-        s_P[v][i] = pr;
-      }
-      if (threadIdx.x < nj) s_w[threadIdx.x] = 2.0 * pairw[tp * n_phi + j0 + threadIdx.x];
-      __syncthreads();
-      for (int e = threadIdx.x; e < nv * N; e += kSepThreads) {
-        const int v = e / N, k = e % N;
-        double re = 0.0, im = 0.0;
-#pragma unroll 4
-        for (int i = 0; i < N; ++i) {
-          const double2 P = s_P[v][i], w = sep_tw<N>(s_tw, k * i, -1);
-          re += P.x * w.x - P.y * w.y;
-          im += P.x * w.y + P.y * w.x;
-        }
-        s_D[v][k] = double2{re, im};
-      }
-      __syncthreads();
-      if (j0 == 0 && threadIdx.x < N) D0s[(((size_t)b * n_rho + r) * half + tp) * N + threadIdx.x] = s_D[0][threadIdx.x];
+        double2* row = &s_D[wv][v][0];
+        // A and B are real up to rounding (Ehat_a phase is Hermitian: E_a is
+        // real, a phase e^{i xi_l s} has xi_{-l} = -xi_l, and Ehat_a is zero at
+        // N/2), so one transform of Ehat_a (phase_A + i phase_B) gives A + i B
+        double re[N], im[N];
 #pragma unroll
-      for (int u = 0; u < GPT; ++u) {
-        const int kk = threadIdx.x + u * kSepThreads;
-        if (kk < NN) {
-          const int k2 = kk / N, k3 = kk % N;
-#pragma unroll 2
-          for (int jl = 0; jl < nj; ++jl) {
-            const double2 d1 = s_D[1 + 2 * jl][k2], d2 = s_D[2 + 2 * jl][k3];
-            const double wq = s_w[jl];
-            g[u].x += wq * (d1.x * d2.x - d1.y * d2.y);
-            g[u].y += wq * (d1.x * d2.y + d1.y * d2.x);
+        for (int l = 0; l < N; ++l) {
+          const double2 E = s_E[a][l], qa = pa[l], q0 = pb[l];
+          const double qby = conj_b ? -q0.y : q0.y;
+          const double ar = E.x * qa.x - E.y * qa.y, ai = E.x * qa.y + E.y * qa.x;
+          const double br = E.x * q0.x - E.y * qby, bi = E.x * qby + E.y * q0.x;
+          re[l] = ar - bi;
+          im[l] = ai + br;
+        }
+        fft_reg<double, N, +1>(re, im);
+        // D = DFT(A B)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          re[i] = re[i] * im[i];
+          im[i] = 0.0;
+        }
+        fft_reg<double, N, -1>(re, im);
+#pragma unroll
+        for (int k = 0; k < N; ++k) row[k] = double2{re[k], im[k]};
+      }
+      if (wv < ntp && ln < nj) s_w[wv][ln] = 2.0 * pairw[tp * n_phi + j0 + ln];
+      __syncthreads();
+      if (j0 == 0 && threadIdx.x < ntp * N) {
+        const int w = threadIdx.x / N, k = threadIdx.x % N;
+        D0s[(((size_t)b * n_rho + r) * half + tp0 + w) * N + k] = s_D[w][0][k];
+      }
+      // G of each polar pair of the round, entries kk = t + u * kSepThreads:
+      // one k_3 = t mod N per thread, so its factor loads once per azimuth;
+      // the sums of later azimuth passes add to what the first one stored
+      const int k3 = threadIdx.x % N;
+      for (int w = 0; w < ntp; ++w) {
+        double2* Gout = Gs + (((size_t)b * n_rho + r) * half + tp0 + w) * NN;
+        double2 g[GPT];
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+          const int kk = threadIdx.x + u * kSepThreads;
+          g[u] = (j0 == 0 || kk >= NN) ? double2{0.0, 0.0} : Gout[kk];
+        }
+        for (int jl = 0; jl < nj; ++jl) {
+          const double2 d2 = s_D[w][2 + 2 * jl][k3];
+          const double wq = s_w[w][jl];
+          const double e2r = wq * d2.x, e2i = wq * d2.y;
+#pragma unroll
+          for (int u = 0; u < GPT; ++u) {
+            const int kk = threadIdx.x + u * kSepThreads;
+            const double2 d1 = s_D[w][1 + 2 * jl][(kk < NN ? kk : 0) / N];
+            g[u].x += d1.x * e2r - d1.y * e2i;
+            g[u].y += d1.x * e2i + d1.y * e2r;
           }
         }
-      }
-    }
-    double2* Gout = Gs + (((size_t)b * n_rho + r) * half + tp) * NN;
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) {
-      const int kk = threadIdx.x + u * kSepThreads;
-      if (kk < NN) Gout[kk] = g[u];
+        for (int u = 0; u < GPT; ++u) {
+          const int kk = threadIdx.x + u * kSepThreads;
+          if (kk < NN) Gout[kk] = g[u];
+        }
+      }
     }
   }
 }
@@ -1231,40 +1265,58 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, c
 // Workspace of one cell: spectra and loss transforms of nvol volumes (f, or the
 // two fields of the corrected form), the fields for the final combine, the
 // z-stage planes of the nz fields that go through the direction pairs, the
-// accumulated planes, the gain spectrum, and for the FP64 difference form the
+// accumulated planes of nacc radial nodes (folded into the gain spectrum by
+// one column pass), the gain spectrum, and for the FP64 difference form the
 // separable Maxwellian factors D0, G and the Maxwellian parameters.
 struct QLayout {
   bool diff;   // FP64 corrected form as Q[f,f] - Q[M,M] (separable Maxwellian gain)
   int nvol;    // spectrum / loss volumes per cell
   int nz;      // fields through the z-stage and the direction pairs
+  int nacc;    // radial nodes whose accumulated planes are held at once
   size_t per;  // bytes per cell
 };
 
+// radial nodes held per column pass: the plan's value (0: all of them, the
+// accumulator then being written once), at most n_rho; 1 for the Carleman
+// form, which has no radial loop
+static int acc_nodes(const bz_ctx* ctx) {
+  if (ctx->p.method == BZ_METHOD_CARLEMAN) return 1;
+  const int a = ctx->acc_nodes > 0 ? ctx->acc_nodes : ctx->n_rho;
+  return a < ctx->n_rho ? a : ctx->n_rho;
+}
+
 template <typename T>
-static QLayout q_layout(int N, int n_theta, int n_rho, bool corrected, bool carleman) {
+static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected, bool carleman) {
   const size_t K = (size_t)N * N * N, cs = 2 * sizeof(T);
   QLayout q;
   q.diff = sizeof(T) == 8 && corrected && !carleman;
   q.nvol = corrected ? 2 : 1;
   q.nz = q.diff ? 1 : q.nvol;
+  q.nacc = nacc;
   q.per = K * (q.nvol * cs /*Fc*/ + q.nvol * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ +
-               (size_t)q.nz * n_theta * cs /*Z*/ + cs /*Acc*/ + cs /*Qh*/);
+               (size_t)q.nz * n_theta * cs /*Z*/ + (size_t)nacc * cs /*Acc*/ + cs /*Qh*/);
   if (q.diff) q.per += (size_t)n_rho * (n_theta / 2) * ((size_t)N + (size_t)N * N) * 16 /*D0, G*/ + 5 * 8 /*theta*/;
   return q;
 }
 
 template <typename T>
 static QLayout q_layout(const bz_ctx* ctx, bool corrected) {
-  return q_layout<T>(ctx->N, ctx->n_theta, ctx->n_rho, corrected, ctx->p.method == BZ_METHOD_CARLEMAN);
+  return q_layout<T>(ctx->N, ctx->n_theta, ctx->n_rho, acc_nodes(ctx), corrected,
+                     ctx->p.method == BZ_METHOD_CARLEMAN);
 }
 
-// cells per chunk of the collision workspace (2 GiB budget, or the bytes of a
-// caller-provided workspace)
+// cells per chunk of the collision workspace: the plan's chunk size if it
+// sets one, else as many as an 8 GiB budget holds (about 3% of the device's
+// HBM; 517 cells of the FP64 corrected form at 32^3, M = 128, n_rho = 16 with
+// every radial node held); never more than the bytes of a caller-provided
+// workspace hold
+constexpr size_t kWsBudget = (size_t)8 << 30;
+
 template <typename T, int N>
-static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected, size_t budget = (size_t)2 << 30) {
+static int64_t chunk_cells(const bz_ctx* ctx, int64_t batch, bool corrected, size_t ws_ext_bytes = 0) {
   const size_t per = q_layout<T>(ctx, corrected).per;
-  int64_t chunk = (int64_t)(budget / per);
-  if (ctx->chunk_cap > 0 && chunk > ctx->chunk_cap) chunk = ctx->chunk_cap;
+  int64_t chunk = ctx->chunk_cap > 0 ? ctx->chunk_cap : (int64_t)(kWsBudget / per);
+  if (ws_ext_bytes > 0 && chunk > (int64_t)(ws_ext_bytes / per)) chunk = (int64_t)(ws_ext_bytes / per);
   if (chunk < 1) chunk = 1;
   if (chunk > batch) chunk = batch;
   return chunk;
@@ -1325,7 +1377,9 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   double* GH = (double*)(Lc + (size_t)chunk * nf * K);
   C* Z = (C*)(GH + (size_t)chunk * (ql.diff ? 1 : nf) * K);
   C* Acc = Z + (size_t)chunk * nz * nt * K;
-  C* Qh = Acc + (size_t)chunk * K;
+  const int nacc = ql.nacc;
+  const int64_t slot = (int64_t)chunk * K;  // one radial node's accumulated planes
+  C* Qh = Acc + (size_t)nacc * slot;
   const int half = nt / 2;
   double2* D0s = (double2*)(Qh + (size_t)chunk * K);
   double2* Gs = D0s + (ql.diff ? (size_t)chunk * ctx->n_rho * half * N : 0);
@@ -1416,12 +1470,18 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
       if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
       {
-        void* args[] = {(void*)&Z, (void*)&Acc, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pw};
+        C* acc_r = Acc + (size_t)(r % nacc) * slot;
+        void* args[] = {(void*)&Z, (void*)&acc_r, (void*)&nt, (void*)&ctx->n_phi, (void*)&ph23r, (void*)&pw};
         BZ_HIP(hipLaunchKernel(kp, dim3((unsigned)(B * N)), dim3(pair_threads), args, lds, st));
       }
       if ((s = prof_mark(ctx, st, true, (double)B * N * ctx->n_pairs * nz * job_flops)) != BZ_OK) return s;
-      const unsigned gq = (unsigned)((B * NN + 255) / 256);
-      hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r * K, r == 0 ? 1 : 0);
+      // fold the held nodes into the gain spectrum once the slots are full
+      if (r % nacc == nacc - 1 || r == ctx->n_rho - 1) {
+        const int r0 = r - r % nacc, ns = r - r0 + 1;
+        const unsigned gq = (unsigned)((2 * B * NN + 255) / 256);  // two lanes per column
+        hipLaunchKernelGGL((k_colw<T, N>), dim3(gq), dim3(256), 0, st, Acc, Qh, B, W + (size_t)r0 * K, ns, slot,
+                           r0 == 0 ? 1 : 0);
+      }
     }
     if (ql.diff) {
       // subtract the gain of the Maxwellian, by separable transforms
