@@ -218,16 +218,26 @@ __global__ __launch_bounds__(256) void k_col(const typename V2<T>::type* __restr
 
 // ------------------------------------------------------------------ z-stage
 // Z[b][fld][t][i1][l2][l3] = sum_l1 F[b][fld][l1][l2][l3] exp(i xi_l1 s1_t) e^{2 pi i l1 i1 / N}
-template <typename T, int N>
+// A plane (b, fld, t, i1) is Hermitian in (l2, l3): the fields are real, their
+// spectra zero at every Nyquist index, and xi_{-l} = -xi_l, so
+// Z(l2, l3) = conj Z(-l2, -l3) and the row l2 = N/2 is zero.  With HALF the
+// z-stage computes and stores rows l2 < N/2 only ([b][fld][t][i1][N/2][N]),
+// and the pair kernel reads the other rows as mirrored conjugates.
+template <int N, bool HALF>
+constexpr int zplane() {
+  return HALF ? N * N / 2 : N * N;
+}
+
+template <typename T, int N, bool HALF>
 __global__ __launch_bounds__(256) void k_zstage(const typename V2<T>::type* __restrict__ F,
                                                 typename V2<T>::type* __restrict__ Z, int64_t nvol, int n_theta,
                                                 const typename V2<T>::type* __restrict__ ph1) {
   using C = typename V2<T>::type;
-  constexpr int K = N * N * N, NN = N * N;
+  constexpr int K = N * N * N, NN = N * N, PL = zplane<N, HALF>();
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nvol * NN) return;
-  const int64_t vol = gid / NN;  // vol = b * nf + fld
-  const int c = (int)(gid % NN);
+  if (gid >= nvol * PL) return;
+  const int64_t vol = gid / PL;  // vol = b * nf + fld
+  const int c = (int)(gid % PL);  // (l2, l3), l2 < N/2 with HALF
   T xr[N], xi[N];
   const C* src = F + vol * K + c;
 #pragma unroll
@@ -246,9 +256,9 @@ __global__ __launch_bounds__(256) void k_zstage(const typename V2<T>::type* __re
       im[l] = xr[l] * p.y + xi[l] * p.x;
     }
     fft_reg<T, N, +1>(re, im);
-    C* dst = Z + (vol * n_theta + t) * K + c;
+    C* dst = Z + (vol * n_theta + t) * (N * PL) + c;
 #pragma unroll
-    for (int l = 0; l < N; ++l) dst[(size_t)l * NN] = C{re[l], im[l]};
+    for (int l = 0; l < N; ++l) dst[(size_t)l * PL] = C{re[l], im[l]};
   }
 }
 
@@ -479,8 +489,27 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     const int tp = it >> 1, v = (NF == 2) ? (it & 1) : 0;
     const int tA = half + tp, tB = half - 1 - tp;
     const int thA = (v == 0) ? tA : tB, thB = (v == 0) ? tB : tA;
-    const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * K + (size_t)i1 * NN + (size_t)h * N + q;
-    const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * K + (size_t)i1 * NN + (size_t)h * N + q;
+    // half planes (rows l2 < 16): row 2m + h above 16 is the conjugate of row
+    // 32 - 2m - h at column -q, row 16 is zero
+    constexpr int PL = zplane<32, true>();
+    const C* za = Z + (((size_t)b * NF + 0) * n_theta + thA) * (N * PL) + (size_t)i1 * PL;
+    const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * (N * PL) + (size_t)i1 * PL;
+    // (m < 8: row 2m + h direct; m > 8: row 32 - h - 2m at column -q; m = 8:
+    // row 15 mirrored for h = 1, row 0 read and zeroed for h = 0)
+    const int qm = (N - q) & (N - 1);
+    const C* za_d = za + (size_t)h * N + q;
+    const C* za_m = za + (size_t)(N - h) * N + qm;
+    const C* zb_d = zb + (size_t)h * N + q;
+    const C* zb_m = zb + (size_t)(N - h) * N + qm;
+    auto zrow = [&](const C* zd, const C* zm, int m) -> C {
+      if (m < 8) return zd[(size_t)(2 * m) * N];
+      if (m > 8) {
+        const C x = zm[-(ptrdiff_t)(2 * m) * N];
+        return C{x.x, -x.y};
+      }
+      const C x = h ? zm[-(ptrdiff_t)16 * N] : zd[0];
+      return h ? C{x.x, -x.y} : C{T(0), T(0)};
+    };
     // with the phase P = Pr + i Pi, the sign sA of the item, a = A P' and
     // b = B conj(P'), P' = Pr + i sA Pi, the combined field a + i b is
     //   Re = Pr (Ar - Bi) + Pi sA (Br - Ai),   Im = Pr (Ai + Br) + Pi sA (Ar + Bi),
@@ -490,7 +519,7 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     T u1[16], u2[16], u3[16], u4[16];  // entries 14 (u1, u2) and 15 unused
 #pragma unroll
     for (int m = 0; m < 15; ++m) {
-      const C x = za[(size_t)(2 * m) * N], y = zb[(size_t)(2 * m) * N];
+      const C x = zrow(za_d, za_m, m), y = zrow(zb_d, zb_m, m);
       if (m < 14) {
         u1[m] = x.x - y.y;
         u2[m] = sA * (y.x - x.y);
@@ -500,10 +529,10 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     }
     C* ul = ulast + (size_t)wv * 192 + ln;
     {
-      const C x = za[(size_t)30 * N], y = zb[(size_t)30 * N];
+      const C x = zrow(za_d, za_m, 15), y = zrow(zb_d, zb_m, 15);
       ul[0] = C{x.x - y.y, sA * (y.x - x.y)};
       ul[64] = C{x.y + y.x, sA * (x.x + y.y)};
-      const C x14 = za[(size_t)28 * N], y14 = zb[(size_t)28 * N];
+      const C x14 = zrow(za_d, za_m, 14), y14 = zrow(zb_d, zb_m, 14);
       ul[128] = C{x14.x - y14.y, sA * (y14.x - x14.y)};
     }
     const int phi_step = (NF == 2) ? 1 : 2;
@@ -1293,8 +1322,12 @@ static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected,
   q.nvol = corrected ? 2 : 1;
   q.nz = q.diff ? 1 : q.nvol;
   q.nacc = nacc;
-  q.per = K * (q.nvol * cs /*Fc*/ + q.nvol * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ +
-               (size_t)q.nz * n_theta * cs /*Z*/ + (size_t)nacc * cs /*Acc*/ + cs /*Qh*/);
+  // Z: half planes for the N = 32 pair kernel; the Carleman form keeps the
+  // full region for its direction fields
+  const size_t zk = (N == 32 && !carleman) ? K / 2 : K;
+  q.per = K * (q.nvol * cs /*Fc*/ + q.nvol * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ + (size_t)nacc * cs /*Acc*/ +
+               cs /*Qh*/) +
+          zk * (size_t)q.nz * n_theta * cs /*Z*/;
   if (q.diff) q.per += (size_t)n_rho * (n_theta / 2) * ((size_t)N + (size_t)N * N) * 16 /*D0, G*/ + 5 * 8 /*theta*/;
   return q;
 }
@@ -1376,7 +1409,9 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   C* Lc = Fc + (size_t)chunk * nf * K;
   double* GH = (double*)(Lc + (size_t)chunk * nf * K);
   C* Z = (C*)(GH + (size_t)chunk * (ql.diff ? 1 : nf) * K);
-  C* Acc = Z + (size_t)chunk * nz * nt * K;
+  constexpr bool zhalf = N == 32;
+  const bool zfull = !zhalf || ctx->p.method == BZ_METHOD_CARLEMAN;
+  C* Acc = Z + (size_t)chunk * nz * nt * (zfull ? K : K / 2);
   const int nacc = ql.nacc;
   const int64_t slot = (int64_t)chunk * K;  // one radial node's accumulated planes
   C* Qh = Acc + (size_t)nacc * slot;
@@ -1463,9 +1498,10 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       continue;
     }
     const int64_t nzvol = B * nz;
-    const unsigned gz = (unsigned)((nzvol * NN + 255) / 256);
+    const unsigned gz = (unsigned)((nzvol * zplane<N, zhalf>() + 255) / 256);
     for (int r = 0; r < ctx->n_rho; ++r) {
-      hipLaunchKernelGGL((k_zstage<T, N>), dim3(gz), dim3(256), 0, st, Fc, Z, nzvol, nt, ph1 + (size_t)r * nt * N);
+      hipLaunchKernelGGL((k_zstage<T, N, zhalf>), dim3(gz), dim3(256), 0, st, Fc, Z, nzvol, nt,
+                         ph1 + (size_t)r * nt * N);
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
       if ((s = prof_mark(ctx, st, false, 0.0)) != BZ_OK) return s;
