@@ -52,10 +52,10 @@ def traffic_per_launch(precision, total_units, launches, method="sigma"):
     Carleman form."""
     import hashlib
 
-    if precision != "fp64" or launches == 0:
+    if launches == 0 or (method == "carleman" and precision != "fp64"):
         return None
     name, prefix = (("carleman_hs_fp64_batched_q_4096.md", "carleman") if method == "carleman"
-                    else ("k_pairs32_zstage_traffic_fp64.md", "pairs"))
+                    else (f"k_pairs32_zstage_traffic_{precision}.md", "pairs"))
     unit = "dir" if method == "carleman" else "node"
     path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2409_01910_amd", "csrc", "bz_q.hip")

@@ -496,18 +496,18 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     const C* zb = Z + (((size_t)b * NF + (NF - 1)) * n_theta + thB) * (N * PL) + (size_t)i1 * PL;
     // (m < 8: row 2m + h direct; m > 8: row 32 - h - 2m at column -q; m = 8:
     // row 15 mirrored for h = 1, row 0 read and zeroed for h = 0)
-    const int qm = (N - q) & (N - 1);
+    // (the mirrored entry of row 32 - h - 2m is moff - 2mN entries from the
+    // direct entry of row h, for both fields)
     const C* za_d = za + (size_t)h * N + q;
-    const C* za_m = za + (size_t)(N - h) * N + qm;
     const C* zb_d = zb + (size_t)h * N + q;
-    const C* zb_m = zb + (size_t)(N - h) * N + qm;
-    auto zrow = [&](const C* zd, const C* zm, int m) -> C {
+    const int moff = (N - 2 * h) * N + ((N - q) & (N - 1)) - q;
+    auto zrow = [&](const C* zd, int m) -> C {
       if (m < 8) return zd[(size_t)(2 * m) * N];
       if (m > 8) {
-        const C x = zm[-(ptrdiff_t)(2 * m) * N];
+        const C x = zd[moff - 2 * m * N];
         return C{x.x, -x.y};
       }
-      const C x = h ? zm[-(ptrdiff_t)16 * N] : zd[0];
+      const C x = zd[h ? moff - 16 * N : 0];
       return h ? C{x.x, -x.y} : C{T(0), T(0)};
     };
     // with the phase P = Pr + i Pi, the sign sA of the item, a = A P' and
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     T u1[16], u2[16], u3[16], u4[16];  // entries 14 (u1, u2) and 15 unused
 #pragma unroll
     for (int m = 0; m < 15; ++m) {
-      const C x = zrow(za_d, za_m, m), y = zrow(zb_d, zb_m, m);
+      const C x = zrow(za_d, m), y = zrow(zb_d, m);
       if (m < 14) {
         u1[m] = x.x - y.y;
         u2[m] = sA * (y.x - x.y);
@@ -529,10 +529,10 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     }
     C* ul = ulast + (size_t)wv * 192 + ln;
     {
-      const C x = zrow(za_d, za_m, 15), y = zrow(zb_d, zb_m, 15);
+      const C x = zrow(za_d, 15), y = zrow(zb_d, 15);
       ul[0] = C{x.x - y.y, sA * (y.x - x.y)};
       ul[64] = C{x.y + y.x, sA * (x.x + y.y)};
-      const C x14 = zrow(za_d, za_m, 14), y14 = zrow(zb_d, zb_m, 14);
+      const C x14 = zrow(za_d, 14), y14 = zrow(zb_d, 14);
       ul[128] = C{x14.x - y14.y, sA * (y14.x - x14.y)};
     }
     const int phi_step = (NF == 2) ? 1 : 2;
@@ -1198,46 +1198,43 @@ __global__ __launch_bounds__(kSepThreads, 2) void k_max_sep1(const double* __res
   }
 }
 
-// k_1 values per thread of k_max_sep2 (the grid's second dimension covers the
-// rest): 8 complex accumulators keep a 1024-thread block within its registers
-template <int N>
-constexpr int sep2_ks() {
-  return N > 8 ? 8 : N;
-}
+// k_max_sep2: a thread owns one (k_2, k_3) column of a cell and all N of its
+// k_1 sums, so each G entry is read once; 256 columns per block
+constexpr int kSep2Threads = 256;
 
 template <int N>
-__global__ __launch_bounds__(N * N < 64 ? 64 : N * N) void k_max_sep2(const double* __restrict__ theta,
-                                                                      const double2* __restrict__ D0s,
-                                                                      const double2* __restrict__ Gs,
-                                                                      const double* __restrict__ W,
-                                                                      double2* __restrict__ Qh, int n_rho,
-                                                                      int n_theta) {
-  constexpr int K = N * N * N, NN = N * N, KS = sep2_ks<N>();
+__global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restrict__ theta,
+                                                           const double2* __restrict__ D0s,
+                                                           const double2* __restrict__ Gs,
+                                                           const double* __restrict__ W,
+                                                           double2* __restrict__ Qh, int n_rho, int n_theta) {
+  constexpr int K = N * N * N, NN = N * N;
   constexpr int TPC = 4;  // polar pairs per register batch
-  const int b = blockIdx.x, t = threadIdx.x, kb = blockIdx.y * KS;
+  const int b = blockIdx.x, t = blockIdx.y * kSep2Threads + threadIdx.x;
   const int half = n_theta / 2;
   __shared__ double2 s_D0[TPC][N];
-  double2 acc[KS];
+  double2 acc[N];
 #pragma unroll
-  for (int k1 = 0; k1 < KS; ++k1) acc[k1] = double2{0.0, 0.0};
+  for (int k1 = 0; k1 < N; ++k1) acc[k1] = double2{0.0, 0.0};
   for (int r = 0; r < n_rho; ++r) {
     for (int tp0 = 0; tp0 < half; tp0 += TPC) {
       const int nt = (half - tp0) < TPC ? (half - tp0) : TPC;
       __syncthreads();
-      if (t < nt * N) s_D0[t / N][t % N] = D0s[(((size_t)b * n_rho + r) * half + tp0 + t / N) * N + t % N];
+      for (int e = threadIdx.x; e < nt * N; e += kSep2Threads)
+        s_D0[e / N][e % N] = D0s[(((size_t)b * n_rho + r) * half + tp0 + e / N) * N + e % N];
       __syncthreads();
       double2 g[TPC];
 #pragma unroll
       for (int u = 0; u < TPC; ++u)
         g[u] = (t < NN && u < nt) ? Gs[(((size_t)b * n_rho + r) * half + tp0 + u) * NN + t] : double2{0.0, 0.0};
       if (t < NN) {
-        const double* Wr = W + (size_t)r * K + (size_t)kb * NN + t;
+        const double* Wr = W + (size_t)r * K + t;
 #pragma unroll
-        for (int k1 = 0; k1 < KS; ++k1) {
+        for (int k1 = 0; k1 < N; ++k1) {
           double sr = 0.0, si = 0.0;
 #pragma unroll
           for (int u = 0; u < TPC; ++u) {
-            const double2 d = s_D0[u < nt ? u : 0][kb + k1];
+            const double2 d = s_D0[u < nt ? u : 0][k1];
             const double on = u < nt ? 1.0 : 0.0;
             sr += on * (d.x * g[u].x - d.y * g[u].y);
             si += on * (d.x * g[u].y + d.y * g[u].x);
@@ -1252,9 +1249,9 @@ __global__ __launch_bounds__(N * N < 64 ? 64 : N * N) void k_max_sep2(const doub
   if (t < NN) {
     const double ea = exp(theta[(size_t)b * 5]);
     const double sc = ea * ea / ((double)K * (double)K);
-    double2* q = Qh + (size_t)b * K + (size_t)kb * NN + t;
+    double2* q = Qh + (size_t)b * K + t;
 #pragma unroll
-    for (int k1 = 0; k1 < KS; ++k1) {
+    for (int k1 = 0; k1 < N; ++k1) {
       double2 v = q[(size_t)k1 * NN];
       v.x -= sc * acc[k1].x;
       v.y -= sc * acc[k1].y;
@@ -1524,9 +1521,9 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       hipLaunchKernelGGL((k_max_sep1<N>), dim3((unsigned)(B * ctx->n_rho)), dim3(kSepThreads), 0, st, th_b,
                          ctx->d_nodes, (const double2*)ctx->d_ph1, (const double2*)ctx->d_ph23, ctx->d_pairw,
                          ctx->n_rho, nt, ctx->n_phi, D0s, Gs);
-      hipLaunchKernelGGL((k_max_sep2<N>), dim3((unsigned)B, (unsigned)(N / sep2_ks<N>())), dim3(NN < 64 ? 64 : NN), 0,
-                         st, (const double*)th_b, (const double2*)D0s, (const double2*)Gs, ctx->d_W, (double2*)Qh,
-                         ctx->n_rho, nt);
+      hipLaunchKernelGGL((k_max_sep2<N>), dim3((unsigned)B, (unsigned)((NN + kSep2Threads - 1) / kSep2Threads)),
+                         dim3(kSep2Threads), 0, st, (const double*)th_b, (const double2*)D0s, (const double2*)Gs,
+                         ctx->d_W, (double2*)Qh, ctx->n_rho, nt);
     }
     const unsigned gq = (unsigned)((B * NN + 255) / 256);
     hipLaunchKernelGGL((k_col<T, N, +1, COL_PLAIN>), dim3(gq), dim3(256), 0, st, Qh, Qh, B, (const T*)nullptr);
