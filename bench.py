@@ -179,10 +179,8 @@ def _slab_run(n, l, plan, tol, max_iters, max_seconds, nx=32, eps=0.1, method="s
             else:
                 if method == "sgs":
                     r, st = slab.sweep(1)
-                elif order == 2:
-                    r, st = slab.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
                 else:
-                    r, st = slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
+                    r, st = slab.vcycle(1, tol=tol, **bz.mg_params(1, order))
             hist.append(r[0])
             inner += st["inner_iters"]
             visits += st["visits"]
@@ -276,8 +274,7 @@ def _bgk_study_run(ctx, row, order, eps, nx, cap_s, tol=1e-5):
             print(f"# bgk study {row} order {order} eps {eps:g}: iteration {its}, residual {res:.2e}",
                   file=sys.stderr, flush=True)
         if row == "MG-SGS-PFP":
-            r, st = (slab.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=0.0) if order == 2
-                     else slab.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=0.0))
+            r, st = slab.vcycle(1, tol=0.0, **bz.mg_params(1, order))
         else:
             r, st = slab.sweep(1)
         res = r[0]
@@ -355,7 +352,7 @@ def _bgk_slab_averages(n, l, nx, eps, order, tol=1e-10, dim=3):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r, cycles = slab.residual()[0], 0
-    mg = dict(coarsest=8, nu1=5, nu2=1) if order == 2 else dict(coarsest=4, nu1=1, nu2=1)
+    mg = bz.mg_params(1, order)
     while r > tol and cycles < 400:
         r = slab.vcycle(1, tol=tol, **mg)[0][0]
         cycles += 1
@@ -657,10 +654,9 @@ def plates_workload(args):
             while hist[-1] >= tol and len(hist) <= 20000 and time.perf_counter() - t0 < 120.0:
                 if method in ("sgs", "fp"):
                     r, st = cav.sweep(1)
-                elif order == 1:
-                    r, st = cav.vcycle(1, coarsest=4, nu1=1, nu2=1, tol=tol)
                 else:
-                    r, st = cav.vcycle(1, coarsest=8, nu1=5, nu2=1, tol=tol)
+                    # one spatial dimension: the 1D rows of tab. mg
+                    r, st = cav.vcycle(1, tol=tol, **bz.mg_params(1, order))
                 hist.append(r)
                 inner += st["inner_iters"]
                 visits += st["visits"]

@@ -366,9 +366,11 @@ def vcycle(prob: Cavity, f: np.ndarray, b: np.ndarray | None, coarsest: int, nu1
     return f
 
 
-def mg_iteration(prob: Cavity, f: np.ndarray, coarsest: int = 4, nu1: int = 1, nu2: int = 1,
+def mg_iteration(prob: Cavity, f: np.ndarray, coarsest: int = 5, nu1: int = 1, nu2: int = 1,
                  tol: float = 1e-5) -> np.ndarray:
-    """One V-cycle followed by the mass rescale (MG-SGS-PFP)."""
+    """One V-cycle followed by the mass rescale (MG-SGS-PFP).  The defaults are
+    the first-order 2D parameters of tab. mg (coarsest grid 5 x 5, one pre- and
+    one post-smoothing step)."""
     f = vcycle(prob, f, None, coarsest, nu1, nu2, tol)
     return f * (prob.mass / total_mass(prob, f))
 

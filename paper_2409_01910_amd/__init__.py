@@ -501,6 +501,19 @@ class Context:
         return {"launches": info.launches, "total_ms": info.total_ms, "flops": info.flops}
 
 
+# Multigrid parameters of tab. mg (Section 3.4): (spatial dimension, order of
+# the scheme) -> (coarsest grid in cells per direction, pre-smoothing steps,
+# post-smoothing steps) of the FAS V-cycle.
+MG_PARAMS = {(1, 1): (4, 1, 1), (1, 2): (8, 5, 1), (2, 1): (5, 1, 1), (2, 2): (5, 5, 1)}
+
+
+def mg_params(dim: int, order: int) -> dict:
+    """The V-cycle keywords (coarsest, nu1, nu2) of tab. mg for a 1D (slab) or
+    2D (cavity) problem with a first- or second-order scheme."""
+    c, n1, n2 = MG_PARAMS[(dim, order)]
+    return {"coarsest": c, "nu1": n1, "nu2": n2}
+
+
 class Slab:
     """A set of 1D slab instances sharing one context (bz_slab).
 
@@ -656,9 +669,10 @@ class Cavity:
                                                      _stream()), "bz_cavity_sweep")
         return (res.value if residual else None), Slab._stats(st)
 
-    def vcycle(self, n_cycles: int = 1, coarsest: int = 4, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
+    def vcycle(self, n_cycles: int = 1, coarsest: int = 5, nu1: int = 1, nu2: int = 1, coarse_iters: int = 20,
                tol: float = 1e-5):
-        """n_cycles FAS V-cycles (each followed by the mass rescale); returns (residual, stats)."""
+        """n_cycles FAS V-cycles (each followed by the mass rescale); returns (residual, stats).
+        The defaults are tab. mg's for a first-order 2D scheme (coarsest 5 x 5)."""
         o = bz_mg_opts(coarsest, nu1, nu2, coarse_iters, tol)
         res = ctypes.c_double(0.0)
         st = bz_sweep_stats()
