@@ -61,6 +61,24 @@ def test_eval_q_fp64_matches_oracle(dev, case, corrected, gamma):
         assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
 
 
+@pytest.mark.parametrize("N", [8, 16])
+def test_eval_q_corrected_with_many_polar_pairs_and_azimuths(dev, N):
+    # the separable gain of the Maxwellian (FP64 difference form) takes four
+    # polar pairs per round and 16 azimuths per pass: 5 polar pairs (a second,
+    # ragged round) and 20 azimuths (a second pass that adds to the stored G)
+    L, nt, nph, nr, B = 6.0, 10, 20, 2, 3
+    print(f"eval_Q corrected N={N} M={nt}x{nph} n_rho={nr} B={B}", flush=True)
+    sp = _spec(N, L, nt, nph, nr)
+    f = synth.mixture_batch(B, N, L, seed=25)
+    ctx = _ctx(N, L, nt, nph, nr)
+    Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True).cpu().numpy()
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i])
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qg[i], ref, scale) < 1e-12, (i, _rel(Qg[i], ref, scale))
+
+
 @pytest.mark.parametrize("case", [(8, 6.0, 4, 8, 4, 5), (16, 8.0, 4, 8, 8, 3)])
 def test_eval_q_conservation_projection_matches_oracle(dev, case):
     import paper_2409_01910_amd as bz
