@@ -7,13 +7,15 @@
 //   loss      L[u] = IDFT(Gm * DFT u)                   (loss term of the operator)
 //   per radial node r:
 //     zstage  axis-0 inverse transform with the phase exp(i xi_1 s_1) for every
-//             polar node: shared by all azimuths of that node
+//             polar node: shared by all azimuths of that node (at N = 32 only
+//             the half of each Hermitian plane with l2 < N/2 is stored)
 //     pairs   for every antipodal direction pair (sigma, -sigma): axis-1/axis-2
 //             inverse transforms with the remaining phases, giving
 //             c = A(v + s) + i B(v - s) in one complex transform; accumulate
 //             w Re(c) Im(c) in physical space; then 2D forward transform of the
-//             accumulated plane
-//     colw    axis-0 forward transform, multiply by W_r(|xi|), add into Qh+
+//             accumulated plane, held with those of the other radial nodes
+//   colw      per group of held radial nodes: axis-0 forward transform of each
+//             node's planes, multiply by W_r(|xi|), add into Qh+
 //   final     inverse transform of Qh+, Q = Q+ - loss (FP64 combine)
 // The corrected form (eq. discrete_Q), Q^FSM[f,f] - Q^FSM[M,M], is evaluated
 //   * with an FP32 spectral stage as the symmetric bilinear form Q_s(g, h),
@@ -1337,7 +1339,7 @@ static QLayout q_layout(const bz_ctx* ctx, bool corrected) {
 
 // cells per chunk of the collision workspace: the plan's chunk size if it
 // sets one, else as many as an 8 GiB budget holds (about 3% of the device's
-// HBM; 517 cells of the FP64 corrected form at 32^3, M = 128, n_rho = 16 with
+// HBM; 594 cells of the FP64 corrected form at 32^3, M = 128, n_rho = 16 with
 // every radial node held); never more than the bytes of a caller-provided
 // workspace hold
 constexpr size_t kWsBudget = (size_t)8 << 30;
