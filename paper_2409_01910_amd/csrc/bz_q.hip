@@ -98,16 +98,14 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
   __syncthreads();
   const double ea = exp(s_th[0]);
   if (corrected == 2) {
-    // difference form: spectra of f (volume b) and M (volume nb + b); GH keeps M
-    const int nb = gridDim.x;
+    // difference form: f and M packed as f + i M in volume b (both real, so one
+    // complex transform carries both spectra); GH keeps M
     double* Mb = GH + (size_t)b * K;
     C* Ff = Fc + (size_t)b * K;
-    C* Fm = Fc + ((size_t)nb + b) * K;
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
       const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
       Mb[k] = M;
-      Ff[k] = C{T(fb[k]), T(0)};
-      Fm[k] = C{T(M), T(0)};
+      Ff[k] = C{T(fb[k]), T(M)};
     }
     return;
   }
@@ -262,6 +260,24 @@ __global__ __launch_bounds__(256) void k_zstage(const typename V2<T>::type* __re
 #pragma unroll
     for (int l = 0; l < N; ++l) dst[(size_t)l * PL] = C{re[l], im[l]};
   }
+}
+
+// f's spectrum from the packed spectrum Z = fhat + i Mhat of the difference
+// form (both Hermitian): fhat(l) = (Z(l) + conj Z(-l)) / 2, for the columns
+// the z-stage reads (rows l2 < N/2 with HALF); volumes [b][K] in and out
+template <typename T, int N, bool HALF>
+__global__ __launch_bounds__(256) void k_unpack(const typename V2<T>::type* __restrict__ Zp,
+                                                typename V2<T>::type* __restrict__ Fu, int64_t nb) {
+  using C = typename V2<T>::type;
+  constexpr int K = N * N * N, NN = N * N, PL = zplane<N, HALF>();
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nb * N * PL) return;
+  const int64_t b = gid / (N * PL);
+  const int rem = (int)(gid % (N * PL)), l1 = rem / PL, c = rem % PL, l2 = c / N, l3 = c % N;
+  const int k = l1 * NN + c;
+  const int km = ((N - l1) & (N - 1)) * NN + ((N - l2) & (N - 1)) * N + ((N - l3) & (N - 1));
+  const C a = Zp[b * K + k], m = Zp[b * K + km];
+  Fu[b * K + k] = C{T(0.5) * (a.x + m.x), T(0.5) * (a.y - m.y)};
 }
 
 // ------------------------------------------------------------------ direction pairs (hot loop)
@@ -1278,9 +1294,8 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, c
   if (NF == 1) {
     loss = f[gid] * double(Lc[gid].x);
   } else if (NF == 3) {
-    // difference form: f L[f] - M L[M], the M volumes after the f volumes
-    const int64_t nb = n / K;
-    loss = f[gid] * double(Lc[gid].x) - GH[gid] * double(Lc[nb * K + gid].x);
+    // difference form: f L[f] - M L[M], the packed loss transform L[f] + i L[M]
+    loss = f[gid] * double(Lc[gid].x) - GH[gid] * double(Lc[gid].y);
   } else {
     const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
     const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
@@ -1324,8 +1339,10 @@ static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected,
   // Z: half planes for the N = 32 pair kernel; the Carleman form keeps the
   // full region for its direction fields
   const size_t zk = (N == 32 && !carleman) ? K / 2 : K;
-  q.per = K * (q.nvol * cs /*Fc*/ + q.nvol * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ + (size_t)nacc * cs /*Acc*/ +
-               cs /*Qh*/) +
+  // the difference form transforms f + i M as one volume: Fc holds it and the
+  // unpacked spectrum of f, Lc one packed loss volume
+  q.per = K * (q.nvol * cs /*Fc*/ + (q.diff ? 1 : q.nvol) * cs /*Lc*/ + (q.diff ? 8 : q.nvol * 8) /*GH*/ +
+               (size_t)nacc * cs /*Acc*/ + cs /*Qh*/) +
           zk * (size_t)q.nz * n_theta * cs /*Z*/;
   if (q.diff) q.per += (size_t)n_rho * (n_theta / 2) * ((size_t)N + (size_t)N * N) * 16 /*D0, G*/ + 5 * 8 /*theta*/;
   return q;
@@ -1406,10 +1423,11 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   }
   C* Fc = (C*)base;
   C* Lc = Fc + (size_t)chunk * nf * K;
-  double* GH = (double*)(Lc + (size_t)chunk * nf * K);
+  double* GH = (double*)(Lc + (size_t)chunk * (ql.diff ? 1 : nf) * K);
+  // the difference form's unpacked spectrum of f: the second Fc slot
+  C* Fu = Fc + (size_t)chunk * K;
   C* Z = (C*)(GH + (size_t)chunk * (ql.diff ? 1 : nf) * K);
-  constexpr bool zhalf = N == 32;
-  const bool zfull = !zhalf || ctx->p.method == BZ_METHOD_CARLEMAN;
+  const bool zfull = N != 32 || ctx->p.method == BZ_METHOD_CARLEMAN;
   C* Acc = Z + (size_t)chunk * nz * nt * (zfull ? K : K / 2);
   const int nacc = ql.nacc;
   const int64_t slot = (int64_t)chunk * K;  // one radial node's accumulated planes
@@ -1440,7 +1458,8 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
   for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
     const int64_t B = (batch - c0) < chunk ? (batch - c0) : chunk;
     const double* fb = f + c0 * K;
-    const int64_t nvol = B * nf;
+    // transformed volumes: f + i M packed in one in the difference form
+    const int64_t nvol = ql.diff ? B : B * nf;
     // the difference form needs the Maxwellian parameters for its separable part
     double* th_b = theta_out ? theta_out + c0 * 5 : (ql.diff ? th_ws : nullptr);
     hipLaunchKernelGGL((k_prep<T, N>), dim3((unsigned)B), dim3(kPrepThreads), 0, st, fb, GH, Fc, th_b, ctx->d_nodes,
@@ -1452,6 +1471,13 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
     // loss: L[u] = IDFT(Gm * uhat)
     hipLaunchKernelGGL((k_col<T, N, +1, COL_PREMUL>), dim3(gcol), dim3(256), 0, st, Fc, Lc, nvol, Gm);
     hipLaunchKernelGGL((k_plane<T, N, +1>), dim3(gpl), dim3(N * PPB), 0, st, Lc, Lc, nvol * N);
+    constexpr bool zhalf = N == 32;
+    if (ql.diff) {
+      const unsigned gu = (unsigned)((B * N * zplane<N, zhalf>() + 255) / 256);
+      hipLaunchKernelGGL((k_unpack<T, N, zhalf>), dim3(gu), dim3(256), 0, st, Fc, Fu, B);
+    }
+    // the fields through the z-stage: the unpacked spectrum of f, or the spectra
+    const C* Fz = ql.diff ? Fu : Fc;
     if (carleman) {
       // gain accumulated in physical space in the Qh region (B*K reals); the
       // direction fields use the Z region ([B][N][nf][N][N] complex)
@@ -1499,7 +1525,7 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
     const int64_t nzvol = B * nz;
     const unsigned gz = (unsigned)((nzvol * zplane<N, zhalf>() + 255) / 256);
     for (int r = 0; r < ctx->n_rho; ++r) {
-      hipLaunchKernelGGL((k_zstage<T, N, zhalf>), dim3(gz), dim3(256), 0, st, Fc, Z, nzvol, nt,
+      hipLaunchKernelGGL((k_zstage<T, N, zhalf>), dim3(gz), dim3(256), 0, st, Fz, Z, nzvol, nt,
                          ph1 + (size_t)r * nt * N);
       const C* ph23r = ph23 + (size_t)r * ctx->n_pairs * 2 * N;
       const double job_flops = 10.0 * NN * __builtin_ctz(N) + 17.0 * NN;
