@@ -516,9 +516,15 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
     // row 15 mirrored for h = 1, row 0 read and zeroed for h = 0)
     // (the mirrored entry of row 32 - h - 2m is moff - 2mN entries from the
     // direct entry of row h, for both fields)
-    const C* za_d = za + (size_t)h * N + q;
-    const C* zb_d = zb + (size_t)h * N + q;
-    const int moff = (N - 2 * h) * N + ((N - q) & (N - 1)) - q;
+    // the lane roles re-derived here and after the item loop from the work-item
+    // id (kept opaque, so that they are not hoisted): held live across the
+    // loops they cost the FP64 kernel 56 bytes of spill per lane
+    int tid_i = (int)__builtin_amdgcn_workitem_id_x();
+    asm volatile("" : "+v"(tid_i));
+    const int hi = (tid_i >> 5) & 1, qi = tid_i & 31;
+    const C* za_d = za + (hi * N + qi);
+    const C* zb_d = zb + (hi * N + qi);
+    const int moff = (N - 2 * hi) * N + ((N - qi) & (N - 1)) - qi;
     auto zrow = [&](const C* zd, int m) -> C {
       if (m < 8) return zd[(size_t)(2 * m) * N];
       if (m > 8) {
@@ -684,13 +690,17 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
   // u(n) = x(n) + (-1)^h x(n + 16), times w^n for h = 1, whose 16-point
   // transform is entries 2j + h.  The transposed plane sits after the partials.
   __syncthreads();  // every wave is done with its tile before the partials overwrite them
+  int tid_t = (int)__builtin_amdgcn_workitem_id_x();
+  asm volatile("" : "+v"(tid_t));
+  const int lnt = tid_t & 63;
+  const int kpt = (lnt & 1) | ((lnt >> 2) & 6), rgt = ((lnt >> 1) & 3) | ((lnt >> 3) & 4);
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) red[wv * (N * LD) + (rg + 8 * g) * LD + kp + 8 * t] = acc[4 * g + t];
+    for (int t = 0; t < 4; ++t) red[wv * (N * LD) + (rgt + 8 * g) * LD + kpt + 8 * t] = acc[4 * g + t];
   __syncthreads();
   C* trans = tiles + kPair32Waves * (N * LD) / 2;
-  const int hh = ln >> 5, lq = ln & 31;
+  const int hh = lnt >> 5, lq = lnt & 31;
   const T sg = hh ? T(-1) : T(1);
   if (wv == 0) {
     // rows: real input, summed over the waves in wave order

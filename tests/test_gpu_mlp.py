@@ -110,7 +110,12 @@ def test_trained_network_gain_in_the_scans(dev):
     ctx = bz.Context(N=16, L=8.0, n_theta=4, n_phi=8, n_rho=4)
     train = [WS.heat_slab_instance(5, i, 16) for i in range(8)]
     X, Y, info = WS.sweep_dataset(ctx, train, n_snap=3)
-    mlp, hist, _ = WS.train(ctx, X, Y, hidden=64, epochs=40, batch=64, lr=2e-3)
+    # 120 epochs (600 Adam steps): the dataset is the solver's own iterates less
+    # the cells whose inner solve misses 1e-10, and which borderline cells miss
+    # it moves with rounding-level changes of the collision term (361 to 372
+    # samples seen), which after only 40 epochs left the loss at 0.45 to 0.58 of
+    # its start
+    mlp, hist, _ = WS.train(ctx, X, Y, hidden=64, epochs=120, batch=64, lr=2e-3)
     print(f"samples {info['samples']}, loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
     assert hist[-1] < 0.5 * hist[0]
     plain_inner, learned_inner, taken = 0.0, 0.0, 0
