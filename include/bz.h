@@ -43,7 +43,7 @@ typedef enum {
                           outputs, but a result it returns is not finite */
 } bz_status;
 
-typedef enum { BZ_FP64 = 0, BZ_FP32 = 1 } bz_precision;
+typedef enum { BZ_FP64 = 0, BZ_FP32 = 1, BZ_FP32_DIFF = 2 } bz_precision;
 
 typedef struct bz_ctx bz_ctx;
 
@@ -59,6 +59,18 @@ typedef struct bz_ctx bz_ctx;
  *   precision  arithmetic of the spectral stage (FFTs, shifted products and
  *            their accumulation).  Moments, Newton solves, the steady-state
  *            correction, the cell solve and residuals are always FP64.
+ *            BZ_FP64 evaluates the corrected form (eq. discrete_Q) of the 3D
+ *            sigma form as the difference Q[f,f] - Q[M,M] (one field through
+ *            the direction pairs, the Maxwellian's gain from separable FP64 1D
+ *            transforms); BZ_FP32, and the 2D and Carleman forms in either
+ *            precision, as the symmetric bilinear form Q_s(f - M, f + M) (two
+ *            fields through the pairs, f - M scaled by a power of two to the
+ *            magnitude of f + M), whose FP32 rounding error scales with
+ *            |f - M|, so it stays small against Q near equilibrium;
+ *            BZ_FP32_DIFF as the difference with an FP32 stage (d = 3, sigma
+ *            form): half the pair work of BZ_FP32, but its rounding error
+ *            scales with the loss term Q^- itself, so near equilibrium it
+ *            bounds the residual an FP32 stage can reach.
  *   device   HIP device ordinal the context works on.
  *   v1_shift physical v_1 of the grid origin: the nodes sample v' = v - v1_shift e_1.
  *            Fields, moments, Maxwellian parameters (theta) and the collision

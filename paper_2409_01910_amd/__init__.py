@@ -15,7 +15,7 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbz.so")
 
-BZ_FP64, BZ_FP32 = 0, 1
+BZ_FP64, BZ_FP32, BZ_FP32_DIFF = 0, 1, 2
 BZ_ENUMERIC = 5
 BZ_METHOD_SIGMA, BZ_METHOD_CARLEMAN = 0, 1
 BZ_Q_CORRECTED = 1

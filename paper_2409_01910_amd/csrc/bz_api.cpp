@@ -88,7 +88,9 @@ bz_status bz_create(const bz_params* p, bz_ctx** out) {
   if (d == 3 && (p->n_theta < 2 || p->n_theta % 2 || p->n_theta > 64)) return BZ_EINVAL;
   if (d > 1 && (p->n_phi < 2 || p->n_phi % 2 || p->n_phi > 256)) return BZ_EINVAL;
   if (d > 1 && (p->n_rho < 1 || p->n_rho > 256)) return BZ_EINVAL;
-  if (p->precision != BZ_FP64 && p->precision != BZ_FP32) return BZ_EINVAL;
+  if (p->precision != BZ_FP64 && p->precision != BZ_FP32 && p->precision != BZ_FP32_DIFF) return BZ_EINVAL;
+  // the FP32 difference form: 3D velocities, sigma form (its Maxwellian part is separable)
+  if (p->precision == BZ_FP32_DIFF && (d != 3 || p->method != BZ_METHOD_SIGMA)) return BZ_EUNSUPPORTED;
   if (!(p->gamma > -3.0) || p->gamma > 2.0) return BZ_EINVAL;
   if (!std::isfinite(p->v1_shift) || std::fabs(p->v1_shift) > 1e6) return BZ_EINVAL;
   if (p->method != BZ_METHOD_SIGMA && p->method != BZ_METHOD_CARLEMAN) return BZ_EINVAL;

@@ -52,7 +52,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict__ f, double* __restrict__ GH,
                                                        typename V2<T>::type* __restrict__ Fc,
                                                        double* __restrict__ theta_out, const double* __restrict__ nodes,
-                                                       double w, int corrected) {
+                                                       double w, int corrected, double* __restrict__ scale) {
   using C = typename V2<T>::type;
   constexpr int K = N * N * N;
   const int b = blockIdx.x;
@@ -109,17 +109,48 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
     }
     return;
   }
+  // bilinear form: g = f - M and h = f + M.  The direction stage carries g and h
+  // as the two parts of one complex transform, whose rounding is relative to
+  // the larger part; g enters the transforms scaled by the power of two that
+  // brings it to h's magnitude (exact in any precision), so that its rounding
+  // error scales with g itself.  The combine divides the scale out again.
   double* g = GH + (size_t)b * 2 * K;
   double* h = g + K;
   C* Fg = Fc + (size_t)b * 2 * K;
   C* Fh = Fg + K;
+  double gm = 0.0, hm = 0.0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
     const double gk = fb[k] - M, hk = fb[k] + M;
     g[k] = gk;
     h[k] = hk;
-    Fg[k] = C{T(gk), T(0)};
-    Fh[k] = C{T(hk), T(0)};
+    gm = fmax(gm, fabs(gk));
+    hm = fmax(hm, fabs(hk));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    gm = fmax(gm, __shfl_xor(gm, off, 64));
+    hm = fmax(hm, __shfl_xor(hm, off, 64));
+  }
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_red[wid] = gm;
+    s_red[nw + wid] = hm;
+  }
+  __syncthreads();
+  gm = 0.0;
+  hm = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    gm = fmax(gm, s_red[i]);
+    hm = fmax(hm, s_red[nw + i]);
+  }
+  int e = (gm > 0.0 && hm > gm) ? ilogb(hm) - ilogb(gm) : 0;
+  e = e < 60 ? e : 60;
+  const double sc = ldexp(1.0, e);
+  if (threadIdx.x == 0) scale[b] = sc;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    Fg[k] = C{T(sc * g[k]), T(0)};
+    Fh[k] = C{T(h[k]), T(0)};
   }
 }
 
@@ -1003,21 +1034,23 @@ template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_ccombine(const double* __restrict__ f, const double* __restrict__ GH,
                                                   const T* __restrict__ gain,
                                                   const typename V2<T>::type* __restrict__ Lc, double* __restrict__ Q,
-                                                  int64_t n) {
+                                                  int64_t n, const double* __restrict__ scale) {
   constexpr int K = N * N * N;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= n) return;
   const int64_t b = gid / K;
   const int k = (int)(gid % K);
-  double loss;
+  double loss, is = 1.0;
   if (NF == 1) {
     loss = f[gid] * double(Lc[gid].x);
   } else {
+    // bilinear form: the gain and L[g] carry the power-of-two scale of g
+    is = 1.0 / scale[b];
     const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
-    const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
+    const double Lg = double(Lc[b * 2 * K + k].x) * is, Lh = double(Lc[b * 2 * K + K + k].x);
     loss = 0.5 * (g * Lh + h * Lg);
   }
-  Q[gid] = double(gain[gid]) - loss;
+  Q[gid] = double(gain[gid]) * is - loss;
 }
 
 // ------------------------------------------------------------------ axis-0 forward + radial weight
@@ -1227,15 +1260,18 @@ __global__ __launch_bounds__(kSepThreads, 2) void k_max_sep1(const double* __res
 }
 
 // k_max_sep2: a thread owns one (k_2, k_3) column of a cell and all N of its
-// k_1 sums, so each G entry is read once; 256 columns per block
+// k_1 sums, so each G entry is read once; 256 columns per block.  The sums are
+// FP64; the gain spectrum Qh is that of the spectral stage (T).
 constexpr int kSep2Threads = 256;
 
-template <int N>
+template <int N, typename T>
 __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restrict__ theta,
                                                            const double2* __restrict__ D0s,
                                                            const double2* __restrict__ Gs,
                                                            const double* __restrict__ W,
-                                                           double2* __restrict__ Qh, int n_rho, int n_theta) {
+                                                           typename V2<T>::type* __restrict__ Qh, int n_rho,
+                                                           int n_theta) {
+  using C = typename V2<T>::type;
   constexpr int K = N * N * N, NN = N * N;
   constexpr int TPC = 4;  // polar pairs per register batch
   const int b = blockIdx.x, t = blockIdx.y * kSep2Threads + threadIdx.x;
@@ -1277,13 +1313,11 @@ __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restr
   if (t < NN) {
     const double ea = exp(theta[(size_t)b * 5]);
     const double sc = ea * ea / ((double)K * (double)K);
-    double2* q = Qh + (size_t)b * K + t;
+    C* q = Qh + (size_t)b * K + t;
 #pragma unroll
     for (int k1 = 0; k1 < N; ++k1) {
-      double2 v = q[(size_t)k1 * NN];
-      v.x -= sc * acc[k1].x;
-      v.y -= sc * acc[k1].y;
-      q[(size_t)k1 * NN] = v;
+      const C v = q[(size_t)k1 * NN];
+      q[(size_t)k1 * NN] = C{T(double(v.x) - sc * acc[k1].x), T(double(v.y) - sc * acc[k1].y)};
     }
   }
 }
@@ -1293,13 +1327,13 @@ template <typename T, int N, int NF>
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, const double* __restrict__ GH,
                                                  const typename V2<T>::type* __restrict__ Qp,
                                                  const typename V2<T>::type* __restrict__ Lc, double* __restrict__ Q,
-                                                 int64_t n) {
+                                                 int64_t n, const double* __restrict__ scale) {
   constexpr int K = N * N * N;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= n) return;
   const int64_t b = gid / K;
   const int k = (int)(gid % K);
-  const double gain = double(Qp[gid].x);
+  double gain = double(Qp[gid].x);
   double loss;
   if (NF == 1) {
     loss = f[gid] * double(Lc[gid].x);
@@ -1307,9 +1341,12 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ f, c
     // difference form: f L[f] - M L[M], the packed loss transform L[f] + i L[M]
     loss = f[gid] * double(Lc[gid].x) - GH[gid] * double(Lc[gid].y);
   } else {
+    // bilinear form: the gain and L[g] carry the power-of-two scale of g
+    const double is = 1.0 / scale[b];
     const double g = GH[b * 2 * K + k], h = GH[b * 2 * K + K + k];
-    const double Lg = double(Lc[b * 2 * K + k].x), Lh = double(Lc[b * 2 * K + K + k].x);
+    const double Lg = double(Lc[b * 2 * K + k].x) * is, Lh = double(Lc[b * 2 * K + K + k].x);
     loss = 0.5 * (g * Lh + h * Lg);
+    gain *= is;
   }
   Q[gid] = gain - loss;
 }
@@ -1338,11 +1375,12 @@ static int acc_nodes(const bz_ctx* ctx) {
   return a < ctx->n_rho ? a : ctx->n_rho;
 }
 
+// diff32: the FP32 stage in the difference form (BZ_FP32_DIFF)
 template <typename T>
-static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected, bool carleman) {
+static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected, bool carleman, bool diff32) {
   const size_t K = (size_t)N * N * N, cs = 2 * sizeof(T);
   QLayout q;
-  q.diff = sizeof(T) == 8 && corrected && !carleman;
+  q.diff = (sizeof(T) == 8 || diff32) && corrected && !carleman;
   q.nvol = corrected ? 2 : 1;
   q.nz = q.diff ? 1 : q.nvol;
   q.nacc = nacc;
@@ -1355,13 +1393,14 @@ static QLayout q_layout(int N, int n_theta, int n_rho, int nacc, bool corrected,
                (size_t)nacc * cs /*Acc*/ + cs /*Qh*/) +
           zk * (size_t)q.nz * n_theta * cs /*Z*/;
   if (q.diff) q.per += (size_t)n_rho * (n_theta / 2) * ((size_t)N + (size_t)N * N) * 16 /*D0, G*/ + 5 * 8 /*theta*/;
+  else if (corrected) q.per += 8 /*scale of g*/;
   return q;
 }
 
 template <typename T>
 static QLayout q_layout(const bz_ctx* ctx, bool corrected) {
   return q_layout<T>(ctx->N, ctx->n_theta, ctx->n_rho, acc_nodes(ctx), corrected,
-                     ctx->p.method == BZ_METHOD_CARLEMAN);
+                     ctx->p.method == BZ_METHOD_CARLEMAN, ctx->p.precision == BZ_FP32_DIFF);
 }
 
 // cells per chunk of the collision workspace: the plan's chunk size if it
@@ -1472,8 +1511,11 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
     const int64_t nvol = ql.diff ? B : B * nf;
     // the difference form needs the Maxwellian parameters for its separable part
     double* th_b = theta_out ? theta_out + c0 * 5 : (ql.diff ? th_ws : nullptr);
+    // the bilinear form's per-cell scale of g (the region the difference form
+    // keeps its parameters in)
+    double* sc_b = (corrected && !ql.diff) ? th_ws : nullptr;
     hipLaunchKernelGGL((k_prep<T, N>), dim3((unsigned)B), dim3(kPrepThreads), 0, st, fb, GH, Fc, th_b, ctx->d_nodes,
-                       ctx->w, ql.diff ? 2 : (corrected ? 1 : 0));
+                       ctx->w, ql.diff ? 2 : (corrected ? 1 : 0), sc_b);
     const unsigned gcol = (unsigned)((nvol * NN + 255) / 256);
     const unsigned gpl = (unsigned)((nvol * N + PPB - 1) / PPB);
     hipLaunchKernelGGL((k_plane<T, N, -1>), dim3(gpl), dim3(N * PPB), 0, st, Fc, Fc, nvol * N);
@@ -1526,9 +1568,11 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       }
       const unsigned ge = (unsigned)((B * K + 255) / 256);
       if (corrected)
-        hipLaunchKernelGGL((k_ccombine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K);
+        hipLaunchKernelGGL((k_ccombine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K,
+                           sc_b);
       else
-        hipLaunchKernelGGL((k_ccombine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K);
+        hipLaunchKernelGGL((k_ccombine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, gain, Lc, Q + c0 * K, B * K,
+                           sc_b);
       BZ_HIP(hipGetLastError());
       continue;
     }
@@ -1559,9 +1603,9 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       hipLaunchKernelGGL((k_max_sep1<N>), dim3((unsigned)(B * ctx->n_rho)), dim3(kSepThreads), 0, st, th_b,
                          ctx->d_nodes, (const double2*)ctx->d_ph1, (const double2*)ctx->d_ph23, ctx->d_pairw,
                          ctx->n_rho, nt, ctx->n_phi, D0s, Gs);
-      hipLaunchKernelGGL((k_max_sep2<N>), dim3((unsigned)B, (unsigned)((NN + kSep2Threads - 1) / kSep2Threads)),
+      hipLaunchKernelGGL((k_max_sep2<N, T>), dim3((unsigned)B, (unsigned)((NN + kSep2Threads - 1) / kSep2Threads)),
                          dim3(kSep2Threads), 0, st, (const double*)th_b, (const double2*)D0s, (const double2*)Gs,
-                         ctx->d_W, (double2*)Qh, ctx->n_rho, nt);
+                         ctx->d_W, Qh, ctx->n_rho, nt);
     }
     const unsigned gq = (unsigned)((B * NN + 255) / 256);
     hipLaunchKernelGGL((k_col<T, N, +1, COL_PLAIN>), dim3(gq), dim3(256), 0, st, Qh, Qh, B, (const T*)nullptr);
@@ -1569,22 +1613,25 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
                        B * N);
     const unsigned ge = (unsigned)((B * K + 255) / 256);
     if (ql.diff)
-      hipLaunchKernelGGL((k_combine<T, N, 3>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+      hipLaunchKernelGGL((k_combine<T, N, 3>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K,
+                         sc_b);
     else if (corrected)
-      hipLaunchKernelGGL((k_combine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+      hipLaunchKernelGGL((k_combine<T, N, 2>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K,
+                         sc_b);
     else
-      hipLaunchKernelGGL((k_combine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K);
+      hipLaunchKernelGGL((k_combine<T, N, 1>), dim3(ge), dim3(256), 0, st, fb, GH, Qh, Lc, Q + c0 * K, B * K,
+                         sc_b);
     BZ_HIP(hipGetLastError());
   }
   return BZ_OK;
 }
 
 size_t eval_q_ws_per_cell(const bz_ctx* ctx, bool corrected) {
-  return ctx->p.precision == BZ_FP32 ? q_layout<float>(ctx, corrected).per : q_layout<double>(ctx, corrected).per;
+  return ctx->p.precision != BZ_FP64 ? q_layout<float>(ctx, corrected).per : q_layout<double>(ctx, corrected).per;
 }
 
 bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected) {
-  const bool fp32 = ctx->p.precision == BZ_FP32;
+  const bool fp32 = ctx->p.precision != BZ_FP64;
   switch (ctx->N) {
     case 8:
       return fp32 ? prepare_chunked<float, 8>(ctx, batch, corrected) : prepare_chunked<double, 8>(ctx, batch, corrected);
@@ -1601,7 +1648,7 @@ bz_status eval_q_prepare(bz_ctx* ctx, int64_t batch, bool corrected) {
 bz_status eval_q(bz_ctx* ctx, const double* f, double* Q, int64_t batch, bool corrected, double* theta_out,
                  hipStream_t st, void* ws_ext, size_t ws_ext_bytes) {
   if (batch == 0) return BZ_OK;
-  const bool fp32 = ctx->p.precision == BZ_FP32;
+  const bool fp32 = ctx->p.precision != BZ_FP64;
   switch (ctx->N) {
     case 8:
       return fp32 ? run_chunked<float, 8>(ctx, f, Q, batch, corrected, theta_out, st, ws_ext, ws_ext_bytes)

@@ -317,6 +317,44 @@ __device__ __forceinline__ void load_spec(const cx_t<T>* SG, const cx_t<T>* SH, 
 // position of grid point k = i_1 N + i_2 in a transform tile (row pitch N + 1)
 __device__ __forceinline__ int tix(int k, int N) { return k + k / N; }
 
+// The corrected form carries g = f - M and h = f + M as the two parts of one
+// complex transform, whose rounding is relative to the larger part.  g enters
+// the transforms scaled by the power of two that brings max|g| to max|h|
+// (exact in any precision), so that its rounding error scales with g itself;
+// the gain and L_g carry that scale and are divided by it.  Returns the
+// exponent, uniform over the block (a scalar register); every thread of the
+// block must take part.
+template <int NOWN>
+__device__ __forceinline__ int g_scale(const double (&g)[NOWN], const double (&h)[NOWN], double* red) {
+  double gm = 0.0, hm = 0.0;
+#pragma unroll
+  for (int i = 0; i < NOWN; ++i) {
+    gm = fmax(gm, fabs(g[i]));
+    hm = fmax(hm, fabs(h[i]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    gm = fmax(gm, __shfl_xor(gm, off, 64));
+    hm = fmax(hm, __shfl_xor(hm, off, 64));
+  }
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[wid] = gm;
+    red[nw + wid] = hm;
+  }
+  __syncthreads();
+  gm = 0.0;
+  hm = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    gm = fmax(gm, red[w]);
+    hm = fmax(hm, red[nw + w]);
+  }
+  __syncthreads();
+  int e = (gm > 0.0 && hm > gm) ? ilogb(hm) - ilogb(gm) : 0;
+  e = e < 60 ? e : 60;
+  return __builtin_amdgcn_readfirstlane(e);
+}
+
 __device__ __forceinline__ double gauss2(const double* th, double x, double y) {
   return exp(th[0] + th[1] * x + th[2] * y - th[3] * (x * x + y * y));
 }
@@ -370,8 +408,13 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
       } else {
         g[i] = h[i] = fv;
       }
-      B0[tix(k, N)] = X::make(T(g[i]), T(h[i]));
     }
+  }
+  const int ge = corrected ? g_scale<kV2Own>(g, h, red) : 0;
+#pragma unroll
+  for (int i = 0; i < kV2Own; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < K) B0[tix(k, N)] = X::make(T(ldexp(g[i], ge)), T(h[i]));
   }
   __syncthreads();
   // spectra: Z = DFT(g + i h); gh_l = (Z_l + conj Z_-l) / 2K, hh_l = (Z_l - conj Z_-l) / 2iK,
@@ -503,7 +546,7 @@ k_q2(const double* __restrict__ f, const double* __restrict__ theta,
     q[i] = 0.0;
     if (k < K) {
       const C l = Lx[tix(k, N)];
-      q[i] = gain[i] - 0.5 * (g[i] * double(l.x) + h[i] * double(l.y));
+      q[i] = ldexp(gain[i], -ge) - 0.5 * (g[i] * double(l.x) + h[i] * ldexp(double(l.y), -ge));
       sq += q[i];
       sm += Mk[i];
     }
@@ -567,8 +610,13 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
       } else {
         g[i] = h[i] = fv;
       }
-      B0[tix(k, N)] = X::make(T(g[i]), T(h[i]));
     }
+  }
+  const int ge = corrected ? g_scale<kOwn>(g, h, red) : 0;
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < K) B0[tix(k, N)] = X::make(T(ldexp(g[i], ge)), T(h[i]));
   }
   __syncthreads();
   {
@@ -659,7 +707,7 @@ k_c2(const double* __restrict__ f, const double* __restrict__ theta, double* __r
     q[i] = 0.0;
     if (k < K) {
       const C l = Lx[tix(k, N)];
-      q[i] = double(gain[i]) - 0.5 * (g[i] * double(l.x) + h[i] * double(l.y));
+      q[i] = ldexp(double(gain[i]), -ge) - 0.5 * (g[i] * double(l.x) + h[i] * ldexp(double(l.y), -ge));
       sq += q[i];
       sm += Mk[i];
     }

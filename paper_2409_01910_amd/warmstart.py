@@ -133,11 +133,13 @@ def clone_network(mlp: MLP, ctx: Context, y_scale: float) -> MLP:
 
 
 def fp32_switch(inst) -> float:
-    """Residual at which a run leaves the FP32 spectral stage for FP64.  The outer
-    residual holds Q/eps, and the FP32 stage carries an error of about 1e-6 of
-    the loss term, so its floor grows like 1/eps (measured: about 2e-6/eps on
-    the heat slab at 32^3); the switch is ten times that floor, and 1e-5 at
-    the least."""
+    """Residual at which a run leaves the FP32 spectral stage for FP64:
+    max(1e-5, 2e-5/eps), far above the FP32 stage's own floor (measured 1e-7 to
+    7e-7 on the heat slab at 32^3 for eps from 0.49 down to 0.0072; the outer
+    residual holds Q/eps).  At this size, one cell per visit, a V-cycle costs
+    about as much in FP32 as in FP64 and more near the floor, where the inner
+    solves run to their cap, so the FP32 stage takes only the first, large
+    reductions."""
     return max(1e-5, 2e-5 / inst["eps"])
 
 

@@ -124,11 +124,13 @@ def test_eval_q_mass_projection_matches_oracle(dev, case):
         ctx.eval_Q(fd, corrected=False, conserve="mass")
 
 
-def test_eval_q_fp32_error_bound(dev):
+@pytest.mark.parametrize("prec", [1, 2])
+def test_eval_q_fp32_error_bound(dev, prec):
+    # prec 1: the bilinear form; 2: the difference form with an FP32 stage
     N, L, nt, nph, nr, B = 16, 8.0, 4, 8, 8, 3
     sp = _spec(N, L, nt, nph, nr)
     f = synth.mixture_batch(B, N, L, seed=22)
-    ctx = _ctx(N, L, nt, nph, nr, prec=1)
+    ctx = _ctx(N, L, nt, nph, nr, prec=prec)
     Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True).cpu().numpy()
     for i in range(B):
         ref = OQ.q_corrected(sp, f[i])
@@ -137,6 +139,59 @@ def test_eval_q_fp32_error_bound(dev):
         err = _rel(Qg[i], ref, scale)
         print("fp32 rel err", err)
         assert err < 2e-6
+
+
+# near-equilibrium cases: (form, d, N, L, rule, gamma)
+NEAR_EQ = [("sigma", 3, 16, 8.0, dict(n_theta=4, n_phi=8, n_rho=8), 0.0),
+           ("carleman", 3, 16, 8.0, dict(n_theta=4, n_phi=8, n_rho=2), 1.0),
+           ("sigma", 2, 32, 8.0, dict(n_phi=16, n_rho=8), 0.0),
+           ("carleman", 2, 32, 8.0, dict(n_phi=16, n_rho=8), 0.0)]
+
+
+@pytest.mark.parametrize("case", NEAR_EQ)
+def test_fp32_error_near_equilibrium(dev, case):
+    # f = M + delta (f0 - M) with the discrete Maxwellian M of f0: Q[f] is of order
+    # delta while the loss term stays of order one (|Q| / |Q-| down to 1e-4 here).
+    # The bilinear form's FP32 error scales with f - M (g enters the transforms
+    # scaled to h's magnitude), so it holds against |Q| itself; the difference
+    # form's scales with the loss term, so only that bound holds for it.
+    import paper_2409_01910_amd as bz
+    from oracle import carleman as CA
+    from oracle.maxwellian import discrete_maxwellian
+
+    form, d, N, L, rule, gamma = case
+    delta = 1e-3
+    print(f"near equilibrium: {form} d={d} N={N}", flush=True)
+    sp = Spec(d=d, N=N, L=L, gamma=gamma, **rule)
+    op = OQ.q_fsm if form == "sigma" else (CA.q_carleman if d == 3 else CA.q_carleman_2d)
+    f0 = synth.mixture_batch(2, N, L, d=d, seed=23)
+    M = np.stack([discrete_maxwellian(sp, g) for g in f0])
+    f = M + delta * (f0 - M)
+    refs = [OQ.q_corrected(sp, g, op=op) for g in f]
+    losses = [op(sp, g, parts=True)[1] for g in f]
+    method = bz.BZ_METHOD_SIGMA if form == "sigma" else bz.BZ_METHOD_CARLEMAN
+    precs = (1, 2) if (form, d) == ("sigma", 3) else (1,)
+    for prec in precs:
+        ctx = bz.Context(N=N, L=L, gamma=gamma, d=d, method=method, precision=prec, **rule)
+        Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True).cpu().numpy()
+        for i in range(2):
+            e_q = _rel(Qg[i], refs[i], np.abs(refs[i]).max())
+            e_l = _rel(Qg[i], refs[i], np.abs(losses[i]).max())
+            print(f"precision {prec} cell {i}: |Q|/|Q-| {np.abs(refs[i]).max() / np.abs(losses[i]).max():.1e} "
+                  f"err/|Q| {e_q:.3e} err/|Q-| {e_l:.3e}", flush=True)
+            assert e_l < 2e-6
+            if prec == 1:
+                assert e_q < 5e-6
+
+
+def test_fp32_difference_form_is_3d_sigma_only(dev):
+    import paper_2409_01910_amd as bz
+
+    with pytest.raises(bz.BZError):
+        bz.Context(N=16, L=8.0, n_phi=8, n_rho=4, d=2, precision=bz.BZ_FP32_DIFF)
+    with pytest.raises(bz.BZError):
+        bz.Context(N=8, L=6.0, gamma=1.0, n_theta=2, n_phi=4, n_rho=2, precision=bz.BZ_FP32_DIFF,
+                   method=bz.BZ_METHOD_CARLEMAN)
 
 
 def test_eval_q_empty_batch(dev):
@@ -268,15 +323,16 @@ def test_eval_q_n32_matches_oracle(dev, rule, corrected):
 
 
 @pytest.mark.parametrize("rule", N32_CASES)
-@pytest.mark.parametrize("corrected", [False, True])
-def test_eval_q_n32_fp32_error_bound(dev, rule, corrected):
-    # the FP32 build of the same kernel reads its row phases from the table
+@pytest.mark.parametrize("corrected,prec", [(False, 1), (True, 1), (True, 2)])
+def test_eval_q_n32_fp32_error_bound(dev, rule, corrected, prec):
+    # the FP32 build of the same kernel reads its row phases from the table;
+    # prec 2 is the difference form with an FP32 stage
     nt, nph, nr = rule
     N, L, B = 32, 8.0, 2
-    print(f"eval_Q FP32 N=32 M={nt}x{nph} n_rho={nr} corrected={corrected}", flush=True)
+    print(f"eval_Q FP32 N=32 M={nt}x{nph} n_rho={nr} corrected={corrected} prec={prec}", flush=True)
     sp = _spec(N, L, nt, nph, nr)
     f = synth.mixture_batch(B, N, L, seed=25)
-    ctx = _ctx(N, L, nt, nph, nr, prec=1)
+    ctx = _ctx(N, L, nt, nph, nr, prec=prec)
     Qg = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=corrected).cpu().numpy()
     for i in range(B):
         gain, loss = OQ.q_fsm(sp, f[i], parts=True)
@@ -287,7 +343,7 @@ def test_eval_q_n32_fp32_error_bound(dev, rule, corrected):
         assert err < 2e-6
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6), (2, 2e-6)])
 def test_eval_q_full_workload_sampled(dev, prec, tol):
     # the benchmark's workload and launch configuration: 4096 cells, 32^3,
     # M = 128 (8 x 16), 16 radial nodes, the launch plan tuned on the first 512
