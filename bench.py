@@ -45,24 +45,35 @@ def make_inputs(batch, seed=0):
     return f, eps
 
 
+# the collision kernels' source: bz_q.hip and the headers it includes
+Q_SOURCES = ("bz_q.hip", "bz_common.hpp", "bz_internal.hpp", "bz_newton.hpp")
+
+
+def q_source_sha256():
+    """sha256 over the collision kernels' source files, in Q_SOURCES order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in Q_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_01910_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_per_launch(precision, total_units, launches, method="sigma"):
     """HBM bytes per marked launch from the committed counter profile, or None
     when that profile was taken on a different kernel source or precision.
     Units: (cell, radial node) for the sigma form, (cell, direction) for the
     Carleman form."""
-    import hashlib
-
     if launches == 0 or (method == "carleman" and precision != "fp64"):
         return None
     name, prefix = (("carleman_hs_fp64_batched_q_4096.md", "carleman") if method == "carleman"
                     else (f"k_pairs32_zstage_traffic_{precision}.md", "pairs"))
     unit = "dir" if method == "carleman" else "node"
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2409_01910_amd", "csrc", "bz_q.hip")
     try:
         kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("source_sha256", "").strip() != sha:
+        if kv.get("source_sha256", "").strip() != q_source_sha256():
             return None
         per = (float(kv[f"{prefix}_fetch_bytes_per_cell_{unit}"]) +
                float(kv[f"{prefix}_write_bytes_per_cell_{unit}"]))

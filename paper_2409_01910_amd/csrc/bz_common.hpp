@@ -71,7 +71,11 @@ constexpr int bitrev(int i) {
 //   X_l = sum_j x_j exp(SIGN * 2 pi i l j / N)   (SIGN = -1 forward, +1 inverse,
 // no normalisation).  Radix-2 decimation in time; all indices are compile-time
 // constants after unrolling, so re[] / im[] stay in VGPRs and twiddles fold
-// into immediates.
+// into immediates.  A general twiddle w = c + i s enters its butterfly as a
+// scaled rotation: x w = c (x + i t x) with t = s / c when |s| <= |c|, else
+// x w = s (u x + i x) with u = c / s, so that the scale folds into the
+// butterfly's fused multiply-adds (6 instructions per butterfly instead of 8;
+// the ratio is at most 1 in magnitude).
 template <typename T, int N, int SIGN>
 __device__ __forceinline__ void fft_reg(T* re, T* im) {
   constexpr Twiddle<N> tw{};
@@ -97,16 +101,33 @@ __device__ __forceinline__ void fft_reg(T* re, T* im) {
 #pragma unroll
       for (int i = k; i < N; i += 2 * half) {
         const int j = i + half;
+        if (k != 0 && 4 * k != 2 * half) {
+          const double cd = tw.c[idx], sd = SIGN * tw.s[idx];
+          T yr, yi, m;
+          if (cd * cd >= sd * sd) {
+            const T t = T(sd / cd);
+            yr = re[j] - t * im[j];
+            yi = im[j] + t * re[j];
+            m = c;
+          } else {
+            const T u = T(cd / sd);
+            yr = re[j] * u - im[j];
+            yi = re[j] + im[j] * u;
+            m = s;
+          }
+          re[j] = re[i] - m * yr;
+          im[j] = im[i] - m * yi;
+          re[i] = re[i] + m * yr;
+          im[i] = im[i] + m * yi;
+          continue;
+        }
         T xr, xi;
         if (k == 0) {
           xr = re[j];
           xi = im[j];
-        } else if (4 * k == 2 * half) {  // w = SIGN * i
+        } else {  // w = SIGN * i
           xr = -T(SIGN) * im[j];
           xi = T(SIGN) * re[j];
-        } else {
-          xr = re[j] * c - im[j] * s;
-          xi = re[j] * s + im[j] * c;
         }
         re[j] = re[i] - xr;
         im[j] = im[i] - xi;

@@ -474,11 +474,32 @@ constexpr int kPair32WaveChoices[3] = {8, 4, 2};
 
 template <typename T>
 constexpr size_t pairs32_lds_bytes(int W) {
-  return (size_t)(W * 1056 + 32) * sizeof(typename V2<T>::type) + (size_t)W * 64 * 6 * sizeof(T);
+  return (size_t)(W * 1056 + 64) * sizeof(typename V2<T>::type) + (size_t)W * 64 * 6 * sizeof(T);
 }
 
 // e^{2 pi i n / 32}, n = 0..31, for the per-lane twiddles of stages 2 and 3
 constexpr Twiddle<32> kTw32{};
+
+// The same twiddles as three-shear rotations: x e^{i a} is
+//   x1 = x_r - t x_i,  im = x_i + s x1,  re = x1 - t im
+// with t = tan(a / 2) = s / (1 + c) and s = sin a: three fused multiply-adds
+// instead of four, as accurate as the product while |t| <= 1 (|a| <= pi / 2;
+// near a = pi the intermediate x1 grows like t and the error with it).
+// n = 16 (a = pi) has no finite t and is never used.
+struct Shear32 {
+  double t[32];
+  constexpr Shear32() : t() {
+    for (int n = 0; n < 32; ++n) t[n] = n == 16 ? 0.0 : kTw32.s[n] / (1.0 + kTw32.c[n]);
+  }
+};
+constexpr Shear32 kSh32{};
+
+template <typename T>
+__device__ __forceinline__ void srot(T& xr, T& xi, T t, T s) {
+  const T x1 = xr - t * xi;
+  xi = xi + s * x1;
+  xr = x1 - t * xi;
+}
 
 // Slots of the wave's tile, 33 slots per row.  Every slot is a lane base plus
 // a compile-time offset, so a stage's 16 accesses share one address register.
@@ -509,10 +530,11 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
   extern __shared__ __align__(16) unsigned char smem[];
   C* tiles = reinterpret_cast<C*>(smem);
   C* twl = tiles + (size_t)kPair32Waves * kPair32Tile;  // e^{2 pi i n / 32}
+  C* tsh = twl + 32;                                     // (t, s) of the same as shears
   // part of the per-item sums live in LDS instead of registers (FP64 has no
   // register left for them): [wave][u1 u2 (m = 15) | u3 u4 (m = 15) | u1 u2
   // (m = 14)][lane], 16-byte pairs
-  C* ulast = twl + 32;
+  C* ulast = tsh + 32;
   // the waves' partial planes reuse the wave tiles once every wave is done
   T* red = reinterpret_cast<T*>(tiles);
   const int b = blockIdx.x / N, i1 = blockIdx.x % N;
@@ -523,7 +545,10 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
   const int k2 = ln & 15, c2 = ln >> 4;   // stage 2
   const int kp = (ln & 1) | ((ln >> 2) & 6), rg = ((ln >> 1) & 3) | ((ln >> 3) & 4);  // stage 3
   C* tile = tiles + (size_t)wv * kPair32Tile;
-  if (threadIdx.x < 32) twl[threadIdx.x] = C{T(kTw32.c[threadIdx.x]), T(kTw32.s[threadIdx.x])};
+  if (threadIdx.x < 32) {
+    twl[threadIdx.x] = C{T(kTw32.c[threadIdx.x]), T(kTw32.s[threadIdx.x])};
+    tsh[threadIdx.x] = C{T(kSh32.t[threadIdx.x]), T(kTw32.s[threadIdx.x])};
+  }
   __syncthreads();
   T acc[16];
 #pragma unroll
@@ -664,15 +689,25 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
 #pragma unroll
       for (int k = 0; k < 16; ++k) tile[s1_slot(h, k, q)] = C{re[k], im[k]};
       wave_sync();
-      // stage 2: re/im[j] row k2, re/im[8 + j] row k2 + 16, column c2 + 4j
-      // (the per-lane twiddles are read from LDS each time: kept in registers
-      // across the loop they would cost spills in FP64)
-      const C wk = twl[k2];
+      // stage 2: re/im[j] row ra, re/im[8 + j] row rb, column c2 + 4j, with
+      // (ra, rb) = (k2, k2 + 16).  FP64 takes the twiddle W^k2 as a shear
+      // rotation; for k2 > 8 the rotation is by W^(k2 + 16) = -W^k2 instead
+      // (its shear ratio stays within 1) and the two rows trade places.  FP32
+      // keeps the products: there the exchanged rows cost paired LDS stores.
+      // (The per-lane twiddles are read from LDS each time: kept in registers
+      // across the loop they would cost spills in FP64.)
+      constexpr bool kShear = sizeof(T) == 8;
+      const bool swap = kShear && k2 > 8;
+      const int ra = swap ? k2 + 16 : k2, rb = swap ? k2 : k2 + 16;
+      const C wk = kShear ? tsh[ra] : twl[k2];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const C e = tile[s1_slot(0, k2, c2 + 4 * j)], o = tile[s1_slot(1, k2, c2 + 4 * j)];
         T tr = o.x, ti = o.y;
-        cmul(tr, ti, wk.x, wk.y);
+        if (kShear)
+          srot(tr, ti, wk.x, wk.y);
+        else
+          cmul(tr, ti, wk.x, wk.y);
         re[j] = e.x + tr;
         im[j] = e.y + ti;
         re[8 + j] = e.x - tr;
@@ -683,23 +718,29 @@ __global__ __launch_bounds__(64 * kPair32Waves, 2) void k_pairs32(const typename
       wave_sync();
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        tile[s2_slot(k2, c2, j)] = C{re[j], im[j]};
-        tile[s2_slot(k2 + 16, c2, j)] = C{re[8 + j], im[8 + j]};
+        tile[s2_slot(ra, c2, j)] = C{re[j], im[j]};
+        tile[s2_slot(rb, c2, j)] = C{re[8 + j], im[8 + j]};
       }
       wave_sync();
-      // stage 3: row rg + 8g, column kp + 8t in entry 4g + t
-      const C w1 = twl[kp], w2 = twl[2 * kp], w3 = twl[3 * kp];
+      // stage 3: row rg + 8g, column kp + 8t in entry 4g + t.  The twiddles
+      // W^n (n = kp, 2kp, 3kp) are shear rotations within pi / 2: for
+      // 8 < n < 24 the rotation by W^(n + 16) = -W^n, with the sign (sg2,
+      // sg3) moved into the 4-point sums (W^kp needs none, kp < 8)
+      const int n2 = 2 * kp, n3 = 3 * kp;
+      const bool f2 = n2 > 8, f3 = n3 > 8;
+      const T sg2 = f2 ? T(-1) : T(1), sg3 = f3 ? T(-1) : T(1);
+      const C w1 = tsh[kp], w2 = tsh[f2 ? n2 + 16 : n2], w3 = tsh[f3 ? (n3 + 16) & 31 : n3];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int r = rg + 8 * g;
         const C z0 = tile[s2_slot(r, 0, kp)], z1 = tile[s2_slot(r, 1, kp)];
         const C z2 = tile[s2_slot(r, 2, kp)], z3 = tile[s2_slot(r, 3, kp)];
         T x1r = z1.x, x1i = z1.y, x2r = z2.x, x2i = z2.y, x3r = z3.x, x3i = z3.y;
-        cmul(x1r, x1i, w1.x, w1.y);
-        cmul(x2r, x2i, w2.x, w2.y);
-        cmul(x3r, x3i, w3.x, w3.y);
-        const T ar = z0.x + x2r, ai = z0.y + x2i, br = z0.x - x2r, bi = z0.y - x2i;
-        const T cr = x1r + x3r, ci = x1i + x3i, dr = x1r - x3r, di = x1i - x3i;
+        srot(x1r, x1i, w1.x, w1.y);
+        srot(x2r, x2i, w2.x, w2.y);
+        srot(x3r, x3i, w3.x, w3.y);
+        const T ar = z0.x + sg2 * x2r, ai = z0.y + sg2 * x2i, br = z0.x - sg2 * x2r, bi = z0.y - sg2 * x2i;
+        const T cr = x1r + sg3 * x3r, ci = x1i + sg3 * x3i, dr = x1r - sg3 * x3r, di = x1i - sg3 * x3i;
         re[4 * g + 0] = ar + cr;
         im[4 * g + 0] = ai + ci;
         re[4 * g + 2] = ar - cr;
