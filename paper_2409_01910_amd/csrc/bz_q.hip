@@ -118,14 +118,13 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
   double* h = g + K;
   C* Fg = Fc + (size_t)b * 2 * K;
   C* Fh = Fg + K;
+  // (the first pass only finds the maxima; the second recomputes M, which
+  // costs less than reading back stored fields)
   double gm = 0.0, hm = 0.0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
-    const double gk = fb[k] - M, hk = fb[k] + M;
-    g[k] = gk;
-    h[k] = hk;
-    gm = fmax(gm, fabs(gk));
-    hm = fmax(hm, fabs(hk));
+    gm = fmax(gm, fabs(fb[k] - M));
+    hm = fmax(hm, fabs(fb[k] + M));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -149,8 +148,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const double* __restrict_
   const double sc = ldexp(1.0, e);
   if (threadIdx.x == 0) scale[b] = sc;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    Fg[k] = C{T(sc * g[k]), T(0)};
-    Fh[k] = C{T(h[k]), T(0)};
+    const double M = ea * s_E[0][k / (N * N)] * s_E[1][(k / N) % N] * s_E[2][k % N];
+    const double gk = fb[k] - M, hk = fb[k] + M;
+    g[k] = gk;
+    h[k] = hk;
+    Fg[k] = C{T(sc * gk), T(0)};
+    Fh[k] = C{T(hk), T(0)};
   }
 }
 
