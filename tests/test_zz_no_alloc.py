@@ -29,6 +29,7 @@ CASES = [
     (3, 16, 8.0, 4, 8, 8, 0, (37, 6), dict(corrected=True, conserve="mass")),
     (3, 32, 8.0, 8, 16, 2, 0, (40, 3), dict(corrected=True, conserve="mass")),
     (3, 32, 8.0, 2, 4, 2, 1, (23, 4), dict(corrected=True, conserve="all")),
+    (3, 32, 8.0, 2, 4, 2, 2, (21, 5), dict(corrected=True, conserve="mass")),
     (3, 8, 6.0, 2, 4, 3, 0, (9, 2), dict(corrected=False)),
     (2, 48, 8.0, 0, 16, 6, 0, (30, 7), dict(corrected=True, conserve="mass")),
     (2, 32, 8.0, 0, 16, 6, 1, (12, 5), dict(corrected=True)),
