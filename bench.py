@@ -918,6 +918,10 @@ def main():
         print(f"bench.py runs on one GPU only (the hot path is measured on a single MI355X); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.precision == "fp32d" and args.method != "sigma":
+        print("--precision fp32d (the difference form with an FP32 stage) exists for the sigma form only",
+              file=sys.stderr)
+        sys.exit(2)
 
     import numpy as np
     import torch
