@@ -72,10 +72,11 @@ constexpr int bitrev(int i) {
 // no normalisation).  Radix-2 decimation in time; all indices are compile-time
 // constants after unrolling, so re[] / im[] stay in VGPRs and twiddles fold
 // into immediates.  A general twiddle w = c + i s enters its butterfly as a
-// scaled rotation: x w = c (x + i t x) with t = s / c when |s| <= |c|, else
-// x w = s (u x + i x) with u = c / s, so that the scale folds into the
-// butterfly's fused multiply-adds (6 instructions per butterfly instead of 8;
-// the ratio is at most 1 in magnitude).
+// scaled rotation: for x = a + i b, x w = c ((a - t b) + i (b + t a)) with
+// t = s / c when |s| <= |c|, else x w = s ((u a - b) + i (a + u b)) with
+// u = c / s, so that the scale c or s folds into the butterfly's fused
+// multiply-adds (6 instructions per butterfly instead of 8; the ratio is at
+// most 1 in magnitude).
 template <typename T, int N, int SIGN>
 __device__ __forceinline__ void fft_reg(T* re, T* im) {
   constexpr Twiddle<N> tw{};
