@@ -139,6 +139,18 @@ def test_eval_q_fp32_error_bound(dev, prec):
         err = _rel(Qg[i], ref, scale)
         print("fp32 rel err", err)
         assert err < 2e-6
+    # the conservation projection on the FP32 stage: against the oracle's
+    # projected form, and the five moments of the result at rounding level
+    from oracle import maxwellian as MXo
+
+    Qp = ctx.eval_Q(torch.from_numpy(f).to(dev), corrected=True, conserve="all").cpu().numpy()
+    for i in range(B):
+        ref = OQ.q_corrected(sp, f[i], conserve="all")
+        _, loss = OQ.q_fsm(sp, f[i], parts=True)
+        scale = max(np.abs(ref).max(), np.abs(loss).max())
+        assert _rel(Qp[i], ref, scale) < 2e-6
+        m = MXo.moments(sp, Qp[i])
+        assert np.all(np.abs(m) < 1e-13 * sp.w * np.abs(loss).sum() * np.array([1, L, L, L, L * L])), m
 
 
 # near-equilibrium cases: (form, d, N, L, rule, gamma)
@@ -323,7 +335,7 @@ def test_eval_q_n32_matches_oracle(dev, rule, corrected):
 
 
 @pytest.mark.parametrize("rule", N32_CASES)
-@pytest.mark.parametrize("corrected,prec", [(False, 1), (True, 1), (True, 2)])
+@pytest.mark.parametrize("corrected,prec", [(False, 1), (True, 1), (False, 2), (True, 2)])
 def test_eval_q_n32_fp32_error_bound(dev, rule, corrected, prec):
     # the FP32 build of the same kernel reads its row phases from the table;
     # prec 2 is the difference form with an FP32 stage
