@@ -1303,10 +1303,14 @@ __global__ __launch_bounds__(kSepThreads, 2) void k_max_sep1(const double* __res
   }
 }
 
-// k_max_sep2: a thread owns one (k_2, k_3) column of a cell and all N of its
-// k_1 sums, so each G entry is read once; 256 columns per block.  The sums are
-// FP64; the gain spectrum Qh is that of the spectral stage (T).
+// k_max_sep2: two threads own one (k_2, k_3) column of a cell, each with half
+// of its N k_1 sums (the halves are the block's two half-blocks, so that a
+// wave's columns stay contiguous); each G entry is read by both from the same
+// cache line; 128 columns per block.  With all N sums in one thread the FP64
+// kernel held 266 registers, one wave per SIMD.  The sums are FP64; the gain
+// spectrum Qh is that of the spectral stage (T).
 constexpr int kSep2Threads = 256;
+constexpr int kSep2Cols = kSep2Threads / 2;
 
 template <int N, typename T>
 __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restrict__ theta,
@@ -1318,12 +1322,14 @@ __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restr
   using C = typename V2<T>::type;
   constexpr int K = N * N * N, NN = N * N;
   constexpr int TPC = 4;  // polar pairs per register batch
-  const int b = blockIdx.x, t = blockIdx.y * kSep2Threads + threadIdx.x;
+  constexpr int KH = N / 2;
+  const int hk = threadIdx.x / kSep2Cols;  // which half of the k_1 sums
+  const int b = blockIdx.x, t = blockIdx.y * kSep2Cols + threadIdx.x % kSep2Cols;
   const int half = n_theta / 2;
   __shared__ double2 s_D0[TPC][N];
-  double2 acc[N];
+  double2 acc[KH];
 #pragma unroll
-  for (int k1 = 0; k1 < N; ++k1) acc[k1] = double2{0.0, 0.0};
+  for (int k = 0; k < KH; ++k) acc[k] = double2{0.0, 0.0};
   for (int r = 0; r < n_rho; ++r) {
     for (int tp0 = 0; tp0 < half; tp0 += TPC) {
       const int nt = (half - tp0) < TPC ? (half - tp0) : TPC;
@@ -1338,7 +1344,8 @@ __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restr
       if (t < NN) {
         const double* Wr = W + (size_t)r * K + t;
 #pragma unroll
-        for (int k1 = 0; k1 < N; ++k1) {
+        for (int k = 0; k < KH; ++k) {
+          const int k1 = hk * KH + k;
           double sr = 0.0, si = 0.0;
 #pragma unroll
           for (int u = 0; u < TPC; ++u) {
@@ -1348,8 +1355,8 @@ __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restr
             si += on * (d.x * g[u].y + d.y * g[u].x);
           }
           const double w = Wr[(size_t)k1 * NN];
-          acc[k1].x += w * sr;
-          acc[k1].y += w * si;
+          acc[k].x += w * sr;
+          acc[k].y += w * si;
         }
       }
     }
@@ -1359,9 +1366,10 @@ __global__ __launch_bounds__(kSep2Threads) void k_max_sep2(const double* __restr
     const double sc = ea * ea / ((double)K * (double)K);
     C* q = Qh + (size_t)b * K + t;
 #pragma unroll
-    for (int k1 = 0; k1 < N; ++k1) {
+    for (int k = 0; k < KH; ++k) {
+      const int k1 = hk * KH + k;
       const C v = q[(size_t)k1 * NN];
-      q[(size_t)k1 * NN] = C{T(double(v.x) - sc * acc[k1].x), T(double(v.y) - sc * acc[k1].y)};
+      q[(size_t)k1 * NN] = C{T(double(v.x) - sc * acc[k].x), T(double(v.y) - sc * acc[k].y)};
     }
   }
 }
@@ -1647,7 +1655,7 @@ static bz_status run_chunked(bz_ctx* ctx, const double* f, double* Q, int64_t ba
       hipLaunchKernelGGL((k_max_sep1<N>), dim3((unsigned)(B * ctx->n_rho)), dim3(kSepThreads), 0, st, th_b,
                          ctx->d_nodes, (const double2*)ctx->d_ph1, (const double2*)ctx->d_ph23, ctx->d_pairw,
                          ctx->n_rho, nt, ctx->n_phi, D0s, Gs);
-      hipLaunchKernelGGL((k_max_sep2<N, T>), dim3((unsigned)B, (unsigned)((NN + kSep2Threads - 1) / kSep2Threads)),
+      hipLaunchKernelGGL((k_max_sep2<N, T>), dim3((unsigned)B, (unsigned)((NN + kSep2Cols - 1) / kSep2Cols)),
                          dim3(kSep2Threads), 0, st, (const double*)th_b, (const double2*)D0s, (const double2*)Gs,
                          ctx->d_W, Qh, ctx->n_rho, nt);
     }
